@@ -1,0 +1,61 @@
+"""The whole decode of a batch of syndromes (Sec. IV.A), composed from the
+oracle's steps: representatives per class -> Metropolis chains per
+(class, temperature, chain) -> estimator and decision -> correction.
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).
+
+The correction is the final configuration of chain 0 of the chosen class at
+the highest inverse temperature (any member of a class is an equally valid
+correction, Sec. II).
+"""
+
+import numpy as np
+
+from . import chains, estimator, geometry, init, tables
+
+
+def decode(L, syndromes, p, sweeps, seed, chains_per_class=1, n_temps=1, burn=0,
+           syndrome_ids=None, trace=False, check_invariants=False):
+    lat = geometry.Lattice(L)
+    syn = np.asarray(syndromes, dtype=np.uint8).reshape(-1, lat.n_stab)
+    syn = (syn != 0).astype(np.uint8)
+    n = syn.shape[0]
+    ids = np.arange(n, dtype=np.uint64) if syndrome_ids is None else \
+        np.asarray(syndrome_ids, dtype=np.uint64)
+    K, C = int(n_temps), int(chains_per_class)
+    if K != 1 and K % 2 != 0:
+        raise ValueError("n_temps must be 1 or even")
+    tab = tables.tables(p, K)                                  # [K, 4]
+    reps = np.stack([init.representatives(lat, syn[i]) for i in range(n)]) \
+        if n else np.zeros((0, 4, lat.n_qubits), np.uint8)
+
+    # task order: ((syndrome * 4 + class) * K + (k - 1)) * chains + chain
+    si, ci, ki, hi = np.meshgrid(np.arange(n), np.arange(4), np.arange(K), np.arange(C),
+                                 indexing="ij")
+    si, ci, ki, hi = (a.reshape(-1) for a in (si, ci, ki, hi))
+    state0 = reps[si, ci] if n else np.zeros((0, lat.n_qubits), np.uint8)
+    res = chains.run(lat, state0, ids[si] if n else ids, ci, ki + 1, hi, tab[ki], seed,
+                     0, burn + sweeps, burn, trace=trace,
+                     check_invariants=check_invariants,
+                     syndromes=syn[si] if n else None)
+
+    shape = (n, 4, K, C)
+    S = res["S"].reshape(shape)
+    A = res["A"].reshape(shape)
+    nf = res["n"].reshape(shape)
+    states = res["state"].reshape(shape + (lat.n_qubits,))
+    bb = tables.beta_bar(p)
+    prob = np.zeros((n, 4))
+    mean = np.zeros((n, 4))
+    key = np.zeros((n, 4), dtype=np.int64)
+    chosen = np.zeros(n, dtype=np.int64)
+    for i in range(n):
+        prob[i], mean[i], key[i], chosen[i] = estimator.estimate(
+            S[i], nf[i], C, sweeps, bb, lat.n_qubits, lat.n_stab)
+    correction = states[np.arange(n), chosen, K - 1, 0] if n else \
+        np.zeros((0, lat.n_qubits), np.uint8)
+    out = dict(class_prob=prob, mean_n=mean, sum_n=S, accepts=A, n_final=nf, key=key,
+               chosen=chosen, correction=correction, states=states, init=reps)
+    if trace:
+        out["trace"] = res["trace"].reshape(shape + (-1,))
+    return out

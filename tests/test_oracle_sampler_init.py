@@ -1,0 +1,62 @@
+"""Pins for the depolarizing sampler (Eq. pauliChannel with p/3 each) and the
+class representatives."""
+
+import numpy as np
+import pytest
+
+from oracle import geometry, init, sampler
+
+
+def test_sampler_rates():
+    lat = geometry.Lattice(9)
+    p = 0.15
+    e = sampler.sample_errors(lat, p, 0xABCDEF, np.arange(4000))
+    n = e.size
+    hit = (e != 0).mean()
+    assert abs(hit - p) < 5 * np.sqrt(p * (1 - p) / n)
+    for code in (1, 2, 3):
+        frac = (e == code).mean()
+        assert abs(frac - p / 3) < 5 * np.sqrt(p / 3 * (1 - p / 3) / n)
+    # distinct ids give distinct errors; same id reproduces
+    e2 = sampler.sample_errors(lat, p, 0xABCDEF, np.array([3, 0]))
+    assert np.array_equal(e2[0], e[3]) and np.array_equal(e2[1], e[0])
+
+
+def test_syndrome_is_linear():
+    lat = geometry.Lattice(5)
+    e = sampler.sample_errors(lat, 0.3, 7, np.arange(50))
+    syn = geometry.syndrome(lat, e)
+    acc = np.zeros_like(syn)
+    for q in range(lat.n_qubits):
+        single = np.zeros_like(e); single[:, q] = e[:, q]
+        acc ^= geometry.syndrome(lat, single)
+    assert np.array_equal(acc, syn)
+
+
+@pytest.mark.parametrize("L", [2, 3, 4, 6, 9, 13])
+def test_representatives(L):
+    lat = geometry.Lattice(L)
+    rng = np.random.default_rng(L)
+    syns = rng.integers(0, 2, size=(30, lat.n_stab)).astype(np.uint8)
+    for syn in syns:
+        reps = init.representatives(lat, syn)
+        assert np.array_equal(geometry.syndrome(lat, reps), np.broadcast_to(syn, (4, lat.n_stab)))
+        assert geometry.class_index(lat, reps).tolist() == [0, 1, 2, 3]
+
+
+@pytest.mark.parametrize("L", [2, 3, 5, 13, 25])
+def test_empty_syndrome_representatives(L):
+    """No anyons: the class representatives are I, Xbar, Zbar and Xbar*Zbar,
+    of weights 0, L, L and 2L - 1 (Xbar and Zbar overlap in one qubit, which
+    carries Y)."""
+    lat = geometry.Lattice(L)
+    reps = init.representatives(lat, np.zeros(lat.n_stab, dtype=np.uint8))
+    assert geometry.weight(reps).tolist() == [0, L, L, 2 * L - 1]
+
+
+def test_all_syndromes_small():
+    lat = geometry.Lattice(3)
+    for v in range(1 << lat.n_stab):
+        syn = np.array([(v >> b) & 1 for b in range(lat.n_stab)], dtype=np.uint8)
+        reps = init.representatives(lat, syn)
+        assert np.array_equal(geometry.syndrome(lat, reps)[0], syn)
