@@ -1,0 +1,172 @@
+#!/usr/bin/env python3
+"""Throughput of the MCMC surface-code decoder on one MI355X.
+
+Workload (the metric point): distance L = 13 planar code, depolarizing
+p = 0.15, 4 classes x 4 chains, 169 = L^2 counted sweeps, single temperature
+(beta* = beta_bar), decided per syndrome.  A step decodes one batch of
+syndromes that is already resident in device memory: class starts, the
+colour-phased Metropolis chains, the estimator and the decision, all in the
+library's kernels.  Batches are sampled on the device before timing (distinct
+sample ids per step) with the library's depolarizing sampler.
+
+Printed: one JSON line with syndromes/s (value), stabilizer updates/s, the
+logical error rate of the decoded batches, the integer-ALU roofline of the
+chain kernel (its duration measured with events on the launch stream as the
+difference between a full step and a step with no sweeps) and the CPU oracle
+timed on a bounded sample of the same workload.
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+L, P, CHAINS, SWEEPS, BURN, K = 13, 0.15, 4, 169, 0, 1
+SEED = 0x1302266900000013
+BATCH = 65536
+# integer operations per stabilizer update in the minimal formulation
+# (Philox4x32-10 share 20, weight change 8-12, accept 4, flip 4, accumulate 3)
+OPS_PER_UPDATE = 40
+# MI355X: 256 CUs x 64 int32 lanes per clock x 2.4 GHz
+PEAK_INT_OPS = 256 * 64 * 2.4e9
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--batch", type=int, default=BATCH)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=256)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the decoder "
+              "shards by syndrome with no exchange, so a multi-GPU figure is not produced.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1302_2669_amd as mc
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    n = args.batch
+    nq, ns = mc.geometry(L)
+    steps, warm = args.steps, args.warmup
+
+    # resident inputs: one distinct batch per step
+    batches, truth = [], []
+    for b in range(warm + steps):
+        syn, cls, _ = mc.sample_errors(L, P, SEED, n, device=dev, id_base=b * n)
+        batches.append(syn)
+        truth.append(cls)
+    prm = mc.make_params(L, P, SWEEPS, SEED, chains=CHAINS, n_temps=K, burn=BURN)
+    ws = torch.empty((mc.workspace_size(prm, n),), dtype=torch.uint8, device=dev)
+    ids = [torch.arange(b * n, (b + 1) * n, dtype=torch.int32, device=dev)
+           for b in range(warm + steps)]
+    torch.cuda.synchronize()
+
+    def step(b, sweeps=SWEEPS):
+        return mc.decode_batch(batches[b], L, P, sweeps, SEED, chains=CHAINS, n_temps=K,
+                               burn=BURN, syndrome_ids=ids[b], want_correction=True, workspace=ws)
+
+    for b in range(warm):
+        step(b)
+    torch.cuda.synchronize()
+
+    stream = torch.cuda.current_stream(dev)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    chosen = []
+    t0 = time.perf_counter()
+    ev[0].record(stream)
+    for i in range(steps):
+        out = step(warm + i)
+        ev[i + 1].record(stream)
+        chosen.append(out["chosen"])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    per_step_ms = [ev[i].elapsed_time(ev[i + 1]) for i in range(steps)]
+    ms_per_step = wall * 1e3 / steps
+
+    # same launches with no sweep: class starts + estimator only
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for i in range(steps):
+        step(warm + i, sweeps=0)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    overhead_ms = e0.elapsed_time(e1) / steps
+    chain_ms = float(np.mean(per_step_ms)) - overhead_ms
+
+    updates_per_syndrome = 4 * CHAINS * K * (BURN + SWEEPS) * ns
+    syn_per_s = n * steps / wall
+    upd_per_s = syn_per_s * updates_per_syndrome
+    fails = sum(int((c != t).sum().item()) for c, t in zip(chosen, truth[warm:]))
+    total = n * steps
+    p_l = fails / total
+    z = 1.96
+    den = 1 + z * z / total
+    centre = (p_l + z * z / (2 * total)) / den
+    half = z * np.sqrt(p_l * (1 - p_l) / total + z * z / (4 * total * total)) / den
+
+    chain_updates = n * updates_per_syndrome
+    achieved = chain_updates * OPS_PER_UPDATE / (chain_ms * 1e-3) / 1e12
+    peak = PEAK_INT_OPS / 1e12
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(args.cpu_sample, ns)
+
+    line = {
+        "metric": "decoded syndromes/sec + stabilizer updates/sec at L=13 p=0.15, matched logical error",
+        "value": syn_per_s,
+        "unit": "syndromes/s",
+        "stabilizer_updates_per_s": upd_per_s,
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": warm,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic: i.i.d. depolarizing samples from the library's Philox sampler",
+        "config": {"workload": "planar code L=13, depolarizing p=0.15, 4 classes x 4 chains, "
+                               "169 sweeps (L^2), single temperature, batch of "
+                               f"{n} syndromes per step",
+                   "L": L, "p": P, "chains_per_class": CHAINS, "sweeps": SWEEPS, "burn": BURN,
+                   "n_temps": K, "batch": n, "updates_per_syndrome": updates_per_syndrome},
+        "logical_error": {"rate": p_l, "wilson95": [centre - half, centre + half],
+                          "samples": total},
+        "roofline": {"bound": "alu", "kernel": "chain_kernel<13>", "achieved": achieved,
+                     "peak": peak, "unit": "Tops/s", "frac": achieved / peak, "traffic": None,
+                     "chain_ms_per_launch": chain_ms, "ops_per_update": OPS_PER_UPDATE,
+                     "updates_per_launch": chain_updates},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def cpu_baseline(n_sample, ns):
+    """The oracle, as written, on a bounded sample of the same workload."""
+    here = os.path.dirname(os.path.abspath(__file__))
+    if here not in sys.path:
+        sys.path.insert(0, here)
+    from oracle import decoder, geometry, sampler
+    lat = geometry.Lattice(L)
+    syn, _, _ = sampler.sample(lat, P, SEED, np.arange(n_sample))
+    t0 = time.perf_counter()
+    decoder.decode(L, syn, P, SWEEPS, SEED, chains_per_class=CHAINS, n_temps=K, burn=BURN)
+    dt = time.perf_counter() - t0
+    return {"value": n_sample / dt, "unit": "syndromes/s", "cores": 1, "kind": "oracle",
+            "sample": f"{n_sample} syndromes of the same workload (L=13, p=0.15, 4x4 chains, "
+                      f"169 sweeps), NumPy oracle in one process, {dt:.1f} s",
+            "stabilizer_updates_per_s": n_sample * 4 * CHAINS * K * (BURN + SWEEPS) * ns / dt}
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,190 @@
+/*
+ * mcmcdec — single-temperature MCMC decoder for the planar surface code on
+ * AMD Instinct MI355X (gfx950).
+ *
+ * Method: A. Hutter, J. R. Wootton, D. Loss, "An efficient Markov chain Monte
+ * Carlo algorithm for the surface code", arXiv:1302.2669.  Given the anyon
+ * configuration (syndrome) of a distance-L planar code under depolarizing
+ * noise, the decoder runs Metropolis chains over the stabilizer-equivalent
+ * error configurations of each of the four logical classes (Sec. IV), turns
+ * the chain averages of the error count n into class probabilities with the
+ * thermodynamic-integration identity (Eq. main), and picks the most likely
+ * class (Sec. IV.A).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  Lattice   (2L-1)x(2L-1) grid; data qubits on cells (r,c) with r+c even,
+ *            numbered row-major: n_q = 2L^2-2L+1.  Stars (sigma^x stabilizers)
+ *            on (r odd, c even), plaquettes (sigma^z) on (r even, c odd);
+ *            n_stab = 2L(L-1) (Sec. II).  Sites: stars row-major, then
+ *            plaquettes row-major.
+ *  Pauli     one byte per qubit: bit 0 = x part, bit 1 = z part
+ *            (0=I, 1=X, 2=Z, 3=Y).
+ *  Syndrome  one byte per site, 0 = unlit, nonzero = lit.  A star is lit by an
+ *            odd number of z parts on its qubits, a plaquette by x parts.
+ *            Every syndrome is valid.
+ *  Class     bx + 2*bz, bx = parity of x parts on grid column 0, bz = parity
+ *            of z parts on grid row 0 (0=I, 1=X-bar, 2=Z-bar, 3=Y-bar).
+ *  Colours   a sweep applies colour 0 (stars, i+j even), 1 (stars, odd),
+ *            2 (plaquettes, even), 3 (plaquettes, odd); sites of one colour
+ *            share no qubit (Sec. V's four groups).
+ *  Random    Philox4x32-10, key = (seed lo, seed hi).  Draw d of a sweep
+ *            (d = colour*L(L-1)/2 + rank of the site in its colour) is word
+ *            d&3 at counter (d>>2, sweep, syndrome_id,
+ *            cls<<28 | temp<<20 | chain); temp runs 1..K.
+ *  Accept    Delta n <= 0, or u < A_k[Delta n] with
+ *            A_k[D] = floor(2^32 exp(-beta_k D)), beta_k = k*beta_bar/K,
+ *            beta_bar = -log((p/3)/(1-p)) (Eq. betaBar, Sec. IV).
+ *
+ * Pointers
+ * --------
+ *  Arguments named d_* are DEVICE pointers owned by the caller; h_* are host
+ *  pointers.  `stream` is a hipStream_t (NULL = the default stream).  Calls
+ *  that take a stream are asynchronous: they validate, enqueue kernels and
+ *  return; results are ready after the stream is synchronised.  No entry point
+ *  allocates device memory: scratch space comes in through `d_workspace`,
+ *  sized by mcmc_workspace_size().
+ *
+ * Errors
+ * ------
+ *  Every entry point returns MCMC_OK (0) or a negative mcmc_status and never
+ *  throws.  Invalid arguments are rejected before anything is enqueued.  A
+ *  failed kernel launch returns MCMC_EDEVICE; faults inside kernels surface at
+ *  the caller's next stream synchronisation.
+ */
+#ifndef MCMCDEC_H
+#define MCMCDEC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum mcmc_status {
+  MCMC_OK = 0,
+  MCMC_EINVAL = -1,     /* malformed argument (NULL where required, bad flag) */
+  MCMC_ERANGE = -2,     /* argument outside the supported range               */
+  MCMC_ENOMEM = -3,     /* host allocation failed                              */
+  MCMC_EDEVICE = -4,    /* HIP runtime error (launch failure, bad device ptr)  */
+  MCMC_EWORKSPACE = -5  /* workspace pointer NULL or smaller than required     */
+};
+
+#define MCMC_L_MIN 2
+#define MCMC_L_MAX 25
+#define MCMC_TEMPS_MAX 64
+#define MCMC_CHAINS_MAX (1 << 20)
+#define MCMC_SWEEPS_MAX (1 << 28)
+
+/* flags */
+#define MCMC_TRACE 1u  /* write n after every colour phase to d_trace          */
+#define MCMC_RESUME 2u /* start from d_chain_state instead of the class starts */
+
+typedef struct mcmc_params {
+  int32_t L;           /* code distance, MCMC_L_MIN..MCMC_L_MAX                  */
+  int32_t n_temps;     /* K: 1 (beta* = beta_bar, Sec. IV.A) or even 2..64
+                          (beta_k = k beta_bar/K, Simpson's rule, Sec. IV.A)    */
+  int32_t chains;      /* independent chains per class and temperature, >= 1   */
+  int32_t burn;        /* uncounted sweeps at the start, >= 0                   */
+  int32_t sweeps;      /* counted sweeps, >= 0: the chain covers absolute sweeps
+                          [0, burn + sweeps)                                    */
+  int32_t sweep_begin; /* with MCMC_RESUME: first absolute sweep of this call
+                          (the state in d_chain_state is the one after sweep
+                          sweep_begin-1); must be 0 otherwise                   */
+  double p;            /* depolarizing rate, 0 < p < 0.75 (beta_bar > 0)        */
+  uint64_t seed;       /* Philox key                                            */
+  uint32_t flags;      /* MCMC_TRACE | MCMC_RESUME                              */
+  uint32_t reserved;   /* must be 0                                             */
+} mcmc_params;
+
+/* Human-readable name of a status code (static string). */
+const char* mcmc_strerror(int status);
+
+/* ABI version of this header: 0x00010000 for 1.0. */
+int32_t mcmc_abi_version(void);
+
+/* n_q and n_stab of a distance-L code (Sec. II: n_stab = 2L(L-1),
+ * Sec. IV.A: n_q = n_stab + 1).  Host only.  ERANGE outside L_MIN..L_MAX. */
+int mcmc_geometry(int32_t L, int32_t* h_n_qubits, int32_t* h_n_stab);
+
+/* Host export of the lattice tables, for checking against other
+ * implementations.  h_supports [n_stab][4] qubit indices, -1 padded
+ * (weight-3 boundary stabilizers); h_colour [n_stab] 0..3; h_draw [n_stab]
+ * the draw number d of each site within a sweep.  Any pointer may be NULL. */
+int mcmc_lattice(int32_t L, int32_t* h_supports, int32_t* h_colour, int32_t* h_draw);
+
+/* The uint32 acceptance thresholds A_k[1..4] for k = 1..n_temps, row-major
+ * [n_temps][4], computed in double precision on the host (Eq. betaBar,
+ * Sec. IV).  ERANGE if p is outside (0, 0.75) or n_temps outside 1..64. */
+int mcmc_acceptance_table(double p, int32_t n_temps, uint32_t* h_table);
+
+/* Bytes of device workspace mcmc_decode_batch needs for n syndromes. */
+int mcmc_workspace_size(const mcmc_params* h_prm, int64_t n, size_t* h_bytes);
+
+/* Bytes of a chain-state buffer for n syndromes (every chain's packed
+ * configuration, weight, energy sum and accept count). */
+int mcmc_chain_state_size(const mcmc_params* h_prm, int64_t n, size_t* h_bytes);
+
+/*
+ * Decode n syndromes of one (L, p) with the same sweep budget.
+ *
+ *  d_syndromes   [n][n_stab] uint8                       (required)
+ *  d_syndrome_ids[n] uint32 Philox counter word 2, NULL => i (required to be
+ *                distinct for independent chains across calls)
+ *  d_class_prob  [n][4] double   estimated P(E) (Eq. main with the closed-form
+ *                beta=0 endpoint; trapezoid for K=1, Simpson for even K)
+ *  d_mean_n      [n][4] double   pooled <n> at beta_bar (k = K)
+ *  d_sum_n       [n][4][K][chains] int64  sum of n after every counted colour
+ *                phase, or NULL
+ *  d_accepts     [n][4][K][chains] int64  accepted moves (burn-in included), or NULL
+ *  d_chosen      [n] uint8       the decided class: the one with the largest
+ *                estimated Z_E, i.e. the smallest integer key
+ *                sum_{k<K} w_k S_{E,k} + S_{E,K} (w_k = 4 odd k, 2 even k);
+ *                ties to the lowest class.  For K=1 this is argmin <n>
+ *                (Sec. IV.A).                                       (required)
+ *  d_correction  [n][n_q] uint8  final configuration of chain 0 of the chosen
+ *                class at k = K, or NULL
+ *  d_chain_state chain-state buffer (mcmc_chain_state_size) or NULL: read at
+ *                start with MCMC_RESUME, written at the end when non-NULL
+ *  d_trace       [n][4][K][chains][4*(burn+sweeps-sweep_begin)] int16, n after
+ *                every colour phase, required iff MCMC_TRACE
+ *  d_workspace   >= mcmc_workspace_size() bytes, 256-byte aligned
+ *
+ * Output per syndrome depends only on its bytes, its id and *h_prm; never on
+ * n, batch order or the launch configuration.
+ */
+int mcmc_decode_batch(const uint8_t* d_syndromes, const uint32_t* d_syndrome_ids, int64_t n,
+                      const mcmc_params* h_prm, double* d_class_prob, double* d_mean_n,
+                      int64_t* d_sum_n, int64_t* d_accepts, uint8_t* d_chosen,
+                      uint8_t* d_correction, void* d_chain_state, int16_t* d_trace,
+                      void* d_workspace, size_t workspace_bytes, void* stream);
+
+/* The four class starting configurations (Sec. IV: one chain start per
+ * class, consistent with the syndrome) of n syndromes: d_reps [n][4][n_q]
+ * uint8, row k of class k.  Asynchronous; needs no workspace. */
+int mcmc_init_representatives(int32_t L, const uint8_t* d_syndromes, int64_t n,
+                              uint8_t* d_reps, void* stream);
+
+/* Unpack a chain-state buffer into d_states [n][4][K][chains][n_q] uint8 and
+ * d_weights [n][4][K][chains] int32 (either may be NULL). */
+int mcmc_unpack_chain_state(const mcmc_params* h_prm, int64_t n, const void* d_chain_state,
+                            uint8_t* d_states, int32_t* d_weights, void* stream);
+
+/*
+ * Depolarizing errors (Eq. pauliChannel, X/Y/Z with p/3 each) for sample ids
+ * d_sample_ids[i] (NULL => id_base + i).  Qubit q of sample s draws
+ * Philox(ctr = (q>>1, 0, s, 1<<30), key = seed) words 2(q&1), 2(q&1)+1 =
+ * (u0, u1): hit iff u0 < floor(p 2^32); type (u1*3)>>32 -> X, Y, Z.
+ *  d_syndromes [n][n_stab] uint8, d_true_class [n] uint8 (required),
+ *  d_errors    [n][n_q] uint8 or NULL.
+ */
+int mcmc_sample_errors(int32_t L, double p, uint64_t seed, const uint32_t* d_sample_ids,
+                       uint32_t id_base, int64_t n, uint8_t* d_syndromes, uint8_t* d_true_class,
+                       uint8_t* d_errors, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MCMCDEC_H */

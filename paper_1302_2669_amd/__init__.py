@@ -1,0 +1,170 @@
+"""MI355X-native single-temperature MCMC decoder for the planar surface code
+(Hutter, Wootton, Loss, arXiv:1302.2669).
+
+Python face of libmcmcdec.so.  Functions take and return torch tensors on a
+HIP device and run on the current torch stream; they only marshal arguments.
+"""
+
+import ctypes
+
+import numpy as np
+
+from . import _lib
+from ._lib import MCMC_L_MAX, MCMC_L_MIN, MCMC_RESUME, MCMC_TRACE, McmcError, Params
+
+__all__ = ["Params", "McmcError", "geometry", "lattice", "acceptance_table", "workspace_size",
+           "chain_state_size", "decode_batch", "sample_errors", "init_representatives",
+           "unpack_chain_state", "MCMC_TRACE", "MCMC_RESUME", "MCMC_L_MIN", "MCMC_L_MAX"]
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(device=None):
+    torch = _torch()
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def geometry(L):
+    """(n_qubits, n_stab) of a distance-L code."""
+    nq, ns = ctypes.c_int32(), ctypes.c_int32()
+    _lib.check(_lib._lib().mcmc_geometry(L, ctypes.byref(nq), ctypes.byref(ns)), "mcmc_geometry")
+    return nq.value, ns.value
+
+
+def lattice(L):
+    """(supports [n_stab, 4] (-1 padded), colour [n_stab], draw [n_stab]) as numpy."""
+    _, ns = geometry(L)
+    sup = np.zeros((ns, 4), dtype=np.int32)
+    col = np.zeros(ns, dtype=np.int32)
+    drw = np.zeros(ns, dtype=np.int32)
+    _lib.check(_lib._lib().mcmc_lattice(L, sup.ctypes.data, col.ctypes.data, drw.ctypes.data),
+               "mcmc_lattice")
+    return sup, col, drw
+
+
+def acceptance_table(p, n_temps=1):
+    out = np.zeros((n_temps, 4), dtype=np.uint32)
+    _lib.check(_lib._lib().mcmc_acceptance_table(float(p), int(n_temps), out.ctypes.data),
+               "mcmc_acceptance_table")
+    return out
+
+
+def make_params(L, p, sweeps, seed, chains=1, n_temps=1, burn=0, sweep_begin=0, flags=0):
+    return Params(L=int(L), n_temps=int(n_temps), chains=int(chains), burn=int(burn),
+                  sweeps=int(sweeps), sweep_begin=int(sweep_begin), p=float(p),
+                  seed=int(seed) & ((1 << 64) - 1), flags=int(flags), reserved=0)
+
+
+def workspace_size(prm, n):
+    b = ctypes.c_size_t()
+    _lib.check(_lib._lib().mcmc_workspace_size(ctypes.byref(prm), int(n), ctypes.byref(b)),
+               "mcmc_workspace_size")
+    return b.value
+
+
+def chain_state_size(prm, n):
+    b = ctypes.c_size_t()
+    _lib.check(_lib._lib().mcmc_chain_state_size(ctypes.byref(prm), int(n), ctypes.byref(b)),
+               "mcmc_chain_state_size")
+    return b.value
+
+
+def decode_batch(syndromes, L, p, sweeps, seed, chains=1, n_temps=1, burn=0, syndrome_ids=None,
+                 want_sums=False, want_correction=True, trace=False, chain_state=None,
+                 resume_from=None, workspace=None):
+    """Decode a [n, n_stab] uint8 device tensor of syndromes.
+
+    Returns a dict of device tensors: class_prob [n,4] f64, mean_n [n,4] f64,
+    chosen [n] u8, and when requested correction [n,n_q] u8, sum_n/accepts
+    [n,4,K,chains] i64, trace [n,4,K,chains,4*(burn+sweeps-begin)] i16,
+    chain_state (uint8 buffer).  `resume_from=(state_buffer, sweep_begin)`
+    continues earlier chains (MCMC_RESUME).
+    """
+    torch = _torch()
+    dev = syndromes.device
+    n = int(syndromes.shape[0])
+    nq, ns = geometry(L)
+    if syndromes.dtype != torch.uint8 or syndromes.dim() != 2 or syndromes.shape[1] != ns:
+        raise ValueError(f"syndromes must be uint8 [n, {ns}]")
+    syndromes = syndromes.contiguous()
+    flags = (_lib.MCMC_TRACE if trace else 0) | (_lib.MCMC_RESUME if resume_from is not None else 0)
+    begin = 0 if resume_from is None else int(resume_from[1])
+    prm = make_params(L, p, sweeps, seed, chains, n_temps, burn, begin, flags)
+    out = {
+        "class_prob": torch.empty((n, 4), dtype=torch.float64, device=dev),
+        "mean_n": torch.empty((n, 4), dtype=torch.float64, device=dev),
+        "chosen": torch.empty((n,), dtype=torch.uint8, device=dev),
+    }
+    if want_correction:
+        out["correction"] = torch.empty((n, nq), dtype=torch.uint8, device=dev)
+    if want_sums:
+        out["sum_n"] = torch.empty((n, 4, n_temps, chains), dtype=torch.int64, device=dev)
+        out["accepts"] = torch.empty((n, 4, n_temps, chains), dtype=torch.int64, device=dev)
+    if trace:
+        out["trace"] = torch.empty((n, 4, n_temps, chains, 4 * (burn + sweeps - begin)),
+                                   dtype=torch.int16, device=dev)
+    cs = None
+    if resume_from is not None:
+        cs = resume_from[0]
+    elif chain_state:
+        cs = torch.empty((chain_state_size(prm, n),), dtype=torch.uint8, device=dev)
+    if cs is not None:
+        out["chain_state"] = cs
+    if workspace is None:
+        workspace = torch.empty((max(workspace_size(prm, n), 1),), dtype=torch.uint8, device=dev)
+    ids = None
+    if syndrome_ids is not None:
+        ids = syndrome_ids.to(device=dev, dtype=torch.int32).contiguous()
+    st = _lib._lib().mcmc_decode_batch(
+        _ptr(syndromes), _ptr(ids), n, ctypes.byref(prm), _ptr(out["class_prob"]),
+        _ptr(out["mean_n"]), _ptr(out.get("sum_n")), _ptr(out.get("accepts")), _ptr(out["chosen"]),
+        _ptr(out.get("correction")), _ptr(cs), _ptr(out.get("trace")), _ptr(workspace),
+        workspace.numel(), _stream(dev))
+    _lib.check(st, "mcmc_decode_batch")
+    return out
+
+
+def sample_errors(L, p, seed, n, device="cuda", id_base=0, sample_ids=None, want_errors=False):
+    """Depolarizing samples: (syndromes [n,n_stab] u8, true_class [n] u8, errors or None)."""
+    torch = _torch()
+    nq, ns = geometry(L)
+    syn = torch.empty((n, ns), dtype=torch.uint8, device=device)
+    cls = torch.empty((n,), dtype=torch.uint8, device=device)
+    err = torch.empty((n, nq), dtype=torch.uint8, device=device) if want_errors else None
+    ids = None if sample_ids is None else sample_ids.to(device=device, dtype=torch.int32).contiguous()
+    st = _lib._lib().mcmc_sample_errors(int(L), float(p), int(seed) & ((1 << 64) - 1), _ptr(ids),
+                                        int(id_base), int(n), _ptr(syn), _ptr(cls), _ptr(err),
+                                        _stream(syn.device))
+    _lib.check(st, "mcmc_sample_errors")
+    return syn, cls, err
+
+
+def init_representatives(syndromes, L):
+    torch = _torch()
+    nq, ns = geometry(L)
+    n = int(syndromes.shape[0])
+    reps = torch.empty((n, 4, nq), dtype=torch.uint8, device=syndromes.device)
+    st = _lib._lib().mcmc_init_representatives(int(L), _ptr(syndromes.contiguous()), n, _ptr(reps),
+                                               _stream(syndromes.device))
+    _lib.check(st, "mcmc_init_representatives")
+    return reps
+
+
+def unpack_chain_state(chain_state, n, L, p, sweeps, seed, chains=1, n_temps=1, burn=0):
+    torch = _torch()
+    nq, _ = geometry(L)
+    prm = make_params(L, p, sweeps, seed, chains, n_temps, burn)
+    states = torch.empty((n, 4, n_temps, chains, nq), dtype=torch.uint8, device=chain_state.device)
+    weights = torch.empty((n, 4, n_temps, chains), dtype=torch.int32, device=chain_state.device)
+    st = _lib._lib().mcmc_unpack_chain_state(ctypes.byref(prm), int(n), _ptr(chain_state),
+                                             _ptr(states), _ptr(weights),
+                                             _stream(chain_state.device))
+    _lib.check(st, "mcmc_unpack_chain_state")
+    return states, weights

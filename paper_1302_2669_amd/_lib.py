@@ -1,0 +1,90 @@
+"""ctypes binding of libmcmcdec.so (C-ABI in include/mcmcdec.h).
+
+Argument marshalling only: every step of the decode runs in the library's HIP
+kernels.  torch is used for device memory and streams.  If the shared library
+is missing this module raises; there is no fallback path.
+"""
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmcmcdec.so")
+
+MCMC_OK = 0
+STATUS = {0: "MCMC_OK", -1: "MCMC_EINVAL", -2: "MCMC_ERANGE", -3: "MCMC_ENOMEM",
+          -4: "MCMC_EDEVICE", -5: "MCMC_EWORKSPACE"}
+MCMC_L_MIN, MCMC_L_MAX = 2, 25
+MCMC_TEMPS_MAX = 64
+MCMC_TRACE, MCMC_RESUME = 1, 2
+
+
+class McmcError(RuntimeError):
+    def __init__(self, status, where):
+        self.status = status
+        super().__init__(f"{where}: {STATUS.get(status, status)} ({_lib().mcmc_strerror(status).decode()})")
+
+
+class Params(ctypes.Structure):
+    _fields_ = [
+        ("L", ctypes.c_int32),
+        ("n_temps", ctypes.c_int32),
+        ("chains", ctypes.c_int32),
+        ("burn", ctypes.c_int32),
+        ("sweeps", ctypes.c_int32),
+        ("sweep_begin", ctypes.c_int32),
+        ("p", ctypes.c_double),
+        ("seed", ctypes.c_uint64),
+        ("flags", ctypes.c_uint32),
+        ("reserved", ctypes.c_uint32),
+    ]
+
+
+_P = ctypes.c_void_p
+_I32, _I64, _U32, _U64, _D, _SZ = (ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32,
+                                   ctypes.c_uint64, ctypes.c_double, ctypes.c_size_t)
+_PI32 = ctypes.POINTER(ctypes.c_int32)
+_PSZ = ctypes.POINTER(ctypes.c_size_t)
+_PPRM = ctypes.POINTER(Params)
+
+_SIGNATURES = {
+    "mcmc_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+    "mcmc_abi_version": (_I32, []),
+    "mcmc_geometry": (ctypes.c_int, [_I32, _PI32, _PI32]),
+    "mcmc_lattice": (ctypes.c_int, [_I32, _P, _P, _P]),
+    "mcmc_acceptance_table": (ctypes.c_int, [_D, _I32, _P]),
+    "mcmc_workspace_size": (ctypes.c_int, [_PPRM, _I64, _PSZ]),
+    "mcmc_chain_state_size": (ctypes.c_int, [_PPRM, _I64, _PSZ]),
+    "mcmc_decode_batch": (ctypes.c_int, [_P, _P, _I64, _PPRM, _P, _P, _P, _P, _P, _P, _P, _P,
+                                         _P, _SZ, _P]),
+    "mcmc_init_representatives": (ctypes.c_int, [_I32, _P, _I64, _P, _P]),
+    "mcmc_unpack_chain_state": (ctypes.c_int, [_PPRM, _I64, _P, _P, _P, _P]),
+    "mcmc_sample_errors": (ctypes.c_int, [_I32, _D, _U64, _P, _U32, _I64, _P, _P, _P, _P]),
+}
+
+_handle = None
+
+
+def _lib():
+    global _handle
+    if _handle is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(
+                f"{LIB_PATH} is missing: build it with `python -m paper_1302_2669_amd.build` "
+                "(the decoder has no CPU fallback)")
+        h = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGNATURES.items():
+            fn = getattr(h, name)
+            fn.restype = res
+            fn.argtypes = args
+        _handle = h
+    return _handle
+
+
+def exported_symbols():
+    return sorted(_SIGNATURES)
+
+
+def check(status, where):
+    if status != MCMC_OK:
+        raise McmcError(status, where)

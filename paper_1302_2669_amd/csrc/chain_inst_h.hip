@@ -1,0 +1,6 @@
+// Explicit instantiations of the chain kernel for L = 23.
+#include "chain_kernel.h"
+
+namespace mcmc {
+template hipError_t launch_chain_L<23>(const ChainArgs&, hipStream_t, bool, bool);
+}  // namespace mcmc

@@ -1,0 +1,297 @@
+// Colour-phased Metropolis chains, one chain per lane (Sec. IV, Sec. IV.A,
+// Sec. V of arXiv:1302.2669).
+//
+// Mapping.  Every lane owns one chain (syndrome, class, temperature, replica)
+// and keeps its whole configuration in VGPRs as packed 2-bit Pauli fields
+// (device_common.h): 2L-1 row words for L <= 16, twice that up to L = 25.
+// The code distance is a template parameter, so every row, word, field and
+// Philox block index below is a compile-time constant and the state never
+// leaves registers; the kernel has no barrier and no shared state between
+// lanes.  The only LDS use is a per-lane copy of the acceptance thresholds.
+//
+// One sweep = the four colour phases of Sec. V's grouping in order.  Within a
+// phase the sites share no qubit, so a whole grid row of same-coloured sites
+// is evaluated at once with word-parallel (SWAR) arithmetic:
+//   per neighbour direction, a star qubit contributes c = 2[I] + [z] and a
+//   plaquette qubit c = 2[I] + [x] (so c - 1 = its change of weight), summed
+//   over the four neighbour words into one 4-bit nibble per site:
+//   t = Delta n + 4 in [0, 8];
+// then per site: the Philox word u, accept = t <= 4 || u < A[t-4], and the
+// accepted sites' masks flip the x (star) or z (plaquette) bits of the three
+// touched rows with a handful of XORs.  The weight change of the row is the
+// sum of accepted nibbles minus 4 per accepted site.
+//
+// Accumulation: n after every colour phase of a counted sweep is added to S
+// (int64); A counts accepted moves.  No cross-lane reduction is needed.
+#pragma once
+
+#include "device_common.h"
+#include "internal.h"
+
+namespace mcmc {
+
+__device__ __forceinline__ uint32_t c_star(uint32_t v) {
+  const uint32_t z = (v >> 1) & 0x55555555u;
+  const uint32_t id = ~(v | (v >> 1)) & 0x55555555u;
+  return (id << 1) | z;
+}
+__device__ __forceinline__ uint32_t c_plaq(uint32_t v) {
+  const uint32_t x = v & 0x55555555u;
+  const uint32_t id = ~(v | (v >> 1)) & 0x55555555u;
+  return (id << 1) | x;
+}
+
+// Sum of the eight nibbles of v.
+__device__ __forceinline__ uint32_t nibble_sum(uint32_t v, uint32_t acc) {
+  const uint32_t b = (v & 0x0F0F0F0Fu) + ((v >> 4) & 0x0F0F0F0Fu);
+  return __builtin_amdgcn_sad_u8(b, 0u, acc);
+}
+
+// Rank (position within its colour, row-major) of the first site of row i.
+template <int L>
+__host__ __device__ constexpr int star_row_rank(int i, int par_of_row0) {
+  // stars of colour with (i' + j) & 1 == phi: row i' holds (L - par + 1) / 2
+  // of them, par = (i' + phi) & 1
+  int r = 0;
+  for (int ii = 0; ii < i; ++ii) r += (L - ((ii + par_of_row0) & 1) + 1) / 2;
+  return r;
+}
+template <int L>
+__host__ __device__ constexpr int plaq_row_rank(int i, int par_of_row0) {
+  int r = 0;
+  for (int ii = 0; ii < i; ++ii) r += (L - 1 - ((ii + par_of_row0) & 1) + 1) / 2;
+  return r;
+}
+
+// Row fence: every state word is passed through an empty asm statement, so no
+// computation of a later row can be hoisted above this point.  Without it the
+// compiler precomputes partial neighbour sums of many rows ahead and keeps
+// them live, which costs far more occupancy than the latency it hides.
+// The row's weight change and accept count are fenced too, so that their
+// computation is not sunk to the end of the phase.
+template <int R, int W>
+__device__ __forceinline__ void row_fence(uint32_t (&st)[R][W], int32_t& dn, int32_t& acc) {
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+#pragma unroll
+    for (int w = 0; w < W; ++w) asm volatile("" : "+v"(st[r][w]));
+  asm volatile("" : "+v"(dn), "+v"(acc));
+}
+#ifndef MCMC_ROW_FENCE
+#define MCMC_ROW_FENCE() row_fence(st, dn, acc_total)
+#endif
+
+#ifndef MCMC_CHAIN_WAVES_PER_EU
+#define MCMC_CHAIN_WAVES_PER_EU 5
+#endif
+
+template <int L, bool TRACE>
+__global__ void __launch_bounds__(256)
+__attribute__((amdgpu_waves_per_eu(MCMC_CHAIN_WAVES_PER_EU)))
+chain_kernel(const ChainArgs a, const int64_t T) {
+  using G = Geo<L>;
+  constexpr int R = G::R, W = G::W, S = G::S;
+  __shared__ uint32_t lds_tbl[9][256];
+
+  const int lane = threadIdx.x;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + lane;
+  if (t >= T) return;
+
+  // task -> (syndrome, class, temperature, replica)
+  const int chain = (int)(t % a.C);
+  int64_t rest = t / a.C;
+  const int kt = (int)(rest % a.K);
+  rest /= a.K;
+  const int cls = (int)(rest & 3);
+  const int64_t syn = rest >> 2;
+  const int64_t sc = syn * 4 + cls;
+  const int64_t n4 = a.n * 4;
+
+  // this lane's thresholds: entry t = Delta + 4; t <= 4 is never read
+#pragma unroll
+  for (int e = 0; e < 9; ++e) lds_tbl[e][lane] = e <= 4 ? 0xFFFFFFFFu : a.table[kt][e - 5];
+
+  uint32_t st[R][W];
+  int32_t n;
+  int64_t Ssum = 0, Acnt = 0;
+  if (a.resume_rows) {
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+      for (int w = 0; w < W; ++w) st[r][w] = a.resume_rows[(int64_t)(r * W + w) * T + t];
+    n = a.resume_n[t];
+    Ssum = a.resume_S[t];
+    Acnt = a.resume_A[t];
+  } else {
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+      for (int w = 0; w < W; ++w) st[r][w] = a.init_rows[(int64_t)(r * W + w) * n4 + sc];
+    n = a.init_n[sc];
+  }
+
+  ChainRng rng;
+  const uint32_t sid = a.syndrome_ids ? a.syndrome_ids[syn] : (uint32_t)syn;
+  rng.init(a.k0, a.k1, sid, ((uint32_t)cls << 28) | ((uint32_t)(kt + 1) << 20) | (uint32_t)chain);
+
+  int16_t* trace = TRACE ? a.trace + t * a.trace_len : nullptr;
+  int64_t tpos = 0;
+
+  for (int sweep = a.sweep_begin; sweep < a.sweep_end; ++sweep) {
+    rng.begin_sweep((uint32_t)sweep);
+    uint4 blk = make_uint4(0, 0, 0, 0);
+    int32_t dn = 0;     // weight change of the current phase
+    int32_t acc_total = 0;
+
+    auto end_phase = [&]() {
+      n += dn;
+      dn = 0;
+      if (sweep >= a.burn) Ssum += n;
+      if constexpr (TRACE) trace[tpos++] = (int16_t)n;
+    };
+
+    // ---------------- stars: colours 0 and 1 ----------------
+    static_for<2>([&](auto PH) {
+      constexpr int phi = decltype(PH)::value;
+      static_for<L - 1>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        constexpr int par = (i + phi) & 1;
+        constexpr int nsite = (L - par + 1) / 2;
+        constexpr int rank0 = star_row_rank<L>(i, phi);
+        uint32_t cO[W], sum[W], acc[W];
+        static_for<W>([&](auto WW) { cO[decltype(WW)::value] = c_star(st[2 * i + 1][decltype(WW)::value]); });
+        static_for<W>([&](auto WW) {
+          constexpr int w = decltype(WW)::value;
+          const uint32_t cN = c_star(st[2 * i][w]);
+          const uint32_t cS = c_star(st[2 * i + 2][w]);
+          uint32_t cWest;
+          if constexpr (w == 0) cWest = (cO[0] << 2) | 1u;
+          else cWest = (cO[w] << 2) | (cO[w - 1] >> 30);
+          constexpr uint32_t M = 0x33333333u;
+          sum[w] = ((cN >> (2 * par)) & M) + ((cS >> (2 * par)) & M) +
+                   ((cO[w] >> (2 * par)) & M) + ((cWest >> (2 * par)) & M);
+          acc[w] = 0;
+        });
+        static_for<nsite>([&](auto MM) {
+          constexpr int m = decltype(MM)::value;
+          constexpr int j = par + 2 * m;
+          constexpr int w = j / 16, nib = (j % 16) / 2;
+          constexpr int d = phi * S + rank0 + m;
+          if constexpr ((d & 3) == 0) blk = rng.template block<d / 4>();
+          const uint32_t u = word_of(blk, d & 3);
+          const uint32_t tt = (sum[w] >> (4 * nib)) & 15u;
+          const uint32_t thr = lds_tbl[tt][lane];
+          const bool ok = (tt <= 4u) | (u < thr);
+          acc[w] |= (uint32_t)ok << (4 * nib);
+        });
+        static_for<W>([&](auto WW) {
+          constexpr int w = decltype(WW)::value;
+          const uint32_t nm = (acc[w] << 4) - acc[w];
+          dn += (int32_t)nibble_sum(sum[w] & nm, 0u) - 4 * (int32_t)__builtin_popcount(acc[w]);
+          acc_total += __builtin_popcount(acc[w]);
+        });
+        uint32_t ax[W];
+        static_for<W>([&](auto WW) { ax[decltype(WW)::value] = acc[decltype(WW)::value] << (2 * par); });
+        static_for<W>([&](auto WW) {
+          constexpr int w = decltype(WW)::value;
+          st[2 * i][w] ^= ax[w];
+          st[2 * i + 2][w] ^= ax[w];
+          uint32_t westward = ax[w] >> 2;
+          if constexpr (w + 1 < W) westward |= ax[w + 1] << 30;
+          st[2 * i + 1][w] ^= (ax[w] | westward) & field_mask(L - 1, w) & 0x55555555u;
+        });
+        MCMC_ROW_FENCE();
+      });
+      end_phase();
+    });
+
+    // ---------------- plaquettes: colours 2 and 3 ----------------
+    static_for<2>([&](auto PH) {
+      constexpr int phi = 2 + decltype(PH)::value;
+      static_for<L>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        constexpr int par = (i + phi - 2) & 1;
+        constexpr int nsite = (L - par) / 2;
+        constexpr int rank0 = plaq_row_rank<L>(i, phi - 2);
+        if constexpr (nsite > 0) {
+          uint32_t cE[W], sum[W], acc[W];
+          static_for<W>([&](auto WW) { cE[decltype(WW)::value] = c_plaq(st[2 * i][decltype(WW)::value]); });
+          static_for<W>([&](auto WW) {
+            constexpr int w = decltype(WW)::value;
+            uint32_t cN = 0x55555555u, cS = 0x55555555u;
+            if constexpr (i > 0) cN = c_plaq(st[2 * i - 1][w]);
+            if constexpr (i < L - 1) cS = c_plaq(st[2 * i + 1][w]);
+            uint32_t cEast = cE[w] >> 2;
+            if constexpr (w + 1 < W) cEast |= cE[w + 1] << 30;
+            constexpr uint32_t M = 0x33333333u;
+            sum[w] = ((cN >> (2 * par)) & M) + ((cS >> (2 * par)) & M) +
+                     ((cE[w] >> (2 * par)) & M) + ((cEast >> (2 * par)) & M);
+            acc[w] = 0;
+          });
+          static_for<nsite>([&](auto MM) {
+            constexpr int m = decltype(MM)::value;
+            constexpr int j = par + 2 * m;
+            constexpr int w = j / 16, nib = (j % 16) / 2;
+            constexpr int d = phi * S + rank0 + m;
+            if constexpr ((d & 3) == 0) blk = rng.template block<d / 4>();
+            const uint32_t u = word_of(blk, d & 3);
+            const uint32_t tt = (sum[w] >> (4 * nib)) & 15u;
+            const uint32_t thr = lds_tbl[tt][lane];
+            const bool ok = (tt <= 4u) | (u < thr);
+            acc[w] |= (uint32_t)ok << (4 * nib);
+          });
+          static_for<W>([&](auto WW) {
+            constexpr int w = decltype(WW)::value;
+            const uint32_t nm = (acc[w] << 4) - acc[w];
+            dn += (int32_t)nibble_sum(sum[w] & nm, 0u) - 4 * (int32_t)__builtin_popcount(acc[w]);
+            acc_total += __builtin_popcount(acc[w]);
+          });
+          uint32_t az[W];
+          static_for<W>([&](auto WW) { az[decltype(WW)::value] = acc[decltype(WW)::value] << (2 * par + 1); });
+          static_for<W>([&](auto WW) {
+            constexpr int w = decltype(WW)::value;
+            if constexpr (i > 0) st[2 * i - 1][w] ^= az[w];
+            if constexpr (i < L - 1) st[2 * i + 1][w] ^= az[w];
+            uint32_t eastward = az[w] << 2;
+            if constexpr (w > 0) eastward |= az[w - 1] >> 30;
+            st[2 * i][w] ^= az[w] | eastward;
+          });
+          MCMC_ROW_FENCE();
+        }
+      });
+      end_phase();
+    });
+    Acnt += acc_total;
+  }
+
+  a.S_out[t] = Ssum;
+  a.A_out[t] = Acnt;
+  a.n_out[t] = n;
+  if (a.state_rows) {
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+      for (int w = 0; w < W; ++w) a.state_rows[(int64_t)(r * W + w) * T + t] = st[r][w];
+  }
+  if (a.corr_rows && chain == 0 && kt == a.K - 1) {
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+      for (int w = 0; w < W; ++w) a.corr_rows[(int64_t)(r * W + w) * n4 + sc] = st[r][w];
+  }
+}
+
+template <int L>
+hipError_t launch_chain_L(const ChainArgs& a, hipStream_t s, bool trace, bool /*resume*/) {
+  const int64_t T = a.n * 4 * a.K * a.C;
+  if (T == 0) return hipSuccess;
+  const dim3 block(256);
+  const dim3 grid((unsigned)((T + 255) / 256));
+  if (trace)
+    hipLaunchKernelGGL((chain_kernel<L, true>), grid, block, 0, s, a, T);
+  else
+    hipLaunchKernelGGL((chain_kernel<L, false>), grid, block, 0, s, a, T);
+  return hipGetLastError();
+}
+
+}  // namespace mcmc

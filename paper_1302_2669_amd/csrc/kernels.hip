@@ -1,0 +1,282 @@
+// Kernels around the chain kernel: class starts, unpacking, the estimator and
+// the error sampler (arXiv:1302.2669, Sec. II-IV).
+#include <math.h>
+
+#include "device_common.h"
+#include "internal.h"
+
+namespace mcmc {
+
+// ---------------------------------------------------------------------------
+// Class starts (Sec. IV: every class needs a starting configuration consistent
+// with the syndrome).  E0 explains each lit plaquette (2i, 2j+1) by X on
+// (2i, 0), (2i, 2), ..., (2i, 2j) and each lit star (2i+1, 2j) by Z on
+// (0, 2j), (2, 2j), ..., (2i, 2j); so on even row 2i the x part of field k is
+// the parity of lit plaquettes (i, j >= k) and the z part of field k the
+// parity of lit stars (i' >= i, k).  Odd rows stay empty.  E0 lies in class
+// (bx, bz) = (parity of all lit plaquettes, parity of all lit stars);
+// class c multiplies it by X-bar (X on row 0) if bx != c&1 and by Z-bar
+// (Z on column 0) if bz != c>>1.  One thread per (syndrome, class).
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) init_kernel(int L, const uint8_t* __restrict__ syn,
+                                                   int64_t n, uint32_t* __restrict__ rows,
+                                                   int32_t* __restrict__ weights,
+                                                   uint8_t* __restrict__ bytes) {
+  const int64_t sc = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (sc >= n * 4) return;
+  const int64_t s = sc >> 2;
+  const int cls = (int)(sc & 3);
+  const int nstab = 2 * L * (L - 1);
+  const int nstar = L * (L - 1);
+  const uint8_t* sy = syn + s * nstab;
+  const int W = words_per_row(L);
+  const int64_t n4 = n * 4;
+
+  int bx = 0, bz = 0;
+  for (int k = 0; k < nstab; ++k) {
+    const int lit = sy[k] != 0;
+    if (k < nstar) bz ^= lit; else bx ^= lit;
+  }
+  const int xbar = bx ^ (cls & 1);
+  const int zbar = bz ^ (cls >> 1);
+
+  int weight = 0;
+  uint32_t colpar = 0;  // bit k: parity of lit stars (i' >= i, k)
+  for (int i = L - 1; i >= 0; --i) {
+    if (i <= L - 2)
+      for (int k = 0; k < L; ++k) colpar ^= (uint32_t)(sy[i * L + k] != 0) << k;
+    // x parts of even row 2i: suffix parity of plaquettes (i, j >= k)
+    uint32_t xbits = 0, p = 0;
+    for (int j = L - 2; j >= 0; --j) {
+      p ^= (uint32_t)(sy[nstar + i * (L - 1) + j] != 0);
+      xbits |= p << j;
+    }
+    uint32_t zbits = colpar;
+    if (i == 0 && xbar) xbits ^= (1u << L) - 1u;
+    if (zbar) zbits ^= 1u;
+    weight += __builtin_popcount(xbits | zbits);
+    if (bytes) {  // qubit (2i, 2k) is number i*side + k; odd-row qubits are I
+      const int side = 2 * L - 1, nq = 2 * L * L - 2 * L + 1;
+      uint8_t* out = bytes + sc * nq;
+      for (int k = 0; k < L; ++k)
+        out[i * side + k] = (uint8_t)(((xbits >> k) & 1u) | (((zbits >> k) & 1u) << 1));
+      if (i >= 1)
+        for (int f = 0; f < L - 1; ++f) out[(i - 1) * side + L + f] = 0;
+    }
+    if (!rows) continue;
+    for (int w = 0; w < W; ++w) {
+      uint32_t word = 0;
+      for (int f = 0; f < 16; ++f) {
+        const int k = 16 * w + f;
+        uint32_t code = 3u;  // padding
+        if (k < L) code = ((xbits >> k) & 1u) | (((zbits >> k) & 1u) << 1);
+        word |= code << (2 * f);
+      }
+      rows[(int64_t)((2 * i) * W + w) * n4 + sc] = word;
+    }
+    if (i >= 1) {  // odd row 2i-1: empty, padding beyond L-1 fields
+      for (int w = 0; w < W; ++w)
+        rows[(int64_t)((2 * i - 1) * W + w) * n4 + sc] = ~field_mask(L - 1, w);
+    }
+  }
+  if (weights) weights[sc] = weight;
+}
+
+hipError_t launch_init(int L, const uint8_t* syn, int64_t n, uint32_t* rows, int32_t* weights,
+                       uint8_t* bytes, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  const int64_t work = n * 4;
+  hipLaunchKernelGGL(init_kernel, dim3((unsigned)((work + 255) / 256)), dim3(256), 0, s, L, syn, n,
+                     rows, weights, bytes);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Unpack `count` packed configurations (word-major, element stride `stride`)
+// into one byte per qubit (row-major over the grid) and/or their weights.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) unpack_kernel(int L, const uint32_t* __restrict__ rows,
+                                                     int64_t count, int64_t stride,
+                                                     uint8_t* __restrict__ out,
+                                                     int32_t* __restrict__ weights) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= count) return;
+  const int W = words_per_row(L);
+  const int nq = 2 * L * L - 2 * L + 1;
+  int q = 0, weight = 0;
+  for (int r = 0; r < 2 * L - 1; ++r) {
+    const int fields = (r & 1) ? L - 1 : L;
+    for (int f = 0; f < fields; ++f) {
+      const uint32_t word = rows[(int64_t)(r * W + f / 16) * stride + e];
+      const uint8_t code = (uint8_t)((word >> (2 * (f % 16))) & 3u);
+      weight += code != 0;
+      if (out) out[e * nq + q] = code;
+      ++q;
+    }
+  }
+  if (weights) weights[e] = weight;
+}
+
+hipError_t launch_unpack(int L, const uint32_t* rows, int64_t count, int64_t stride, uint8_t* out,
+                         int32_t* weights, hipStream_t s) {
+  if (count == 0) return hipSuccess;
+  hipLaunchKernelGGL(unpack_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, L,
+                     rows, count, stride, out, weights);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Estimator and decision (Eq. main, Sec. IV.A), one thread per syndrome, FP64
+// in a fixed order with no contraction:
+//   mean_{E,k} = (sum_c S) / (C * 4 * sweeps)   (mean final weight if sweeps = 0)
+//   K = 1 : I_E = (beta_bar / 2) (f0 + mean_{E,1})                (trapezoid)
+//   K even: I_E = (h / 3)(f0 + 4 f1 + 2 f2 + ... + f_K), h = beta_bar / K
+//   log Z_E = n_stab log 2 - I_E,  P_E = softmax(log Z)
+// Decision by the integer key sum_{k<K} w_k S_{E,k} + S_{E,K} (all I_E share
+// f0 and the denominator), ties to the lowest class.
+// ---------------------------------------------------------------------------
+#pragma clang fp contract(off)
+__global__ void __launch_bounds__(128) decide_kernel(const DecideArgs a) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= a.n) return;
+  const int K = a.K, C = a.C;
+  const bool counted = a.sweeps > 0;
+  const double denom = counted ? (double)((int64_t)C * 4 * a.sweeps) : (double)C;
+  double logz[4];
+  int64_t key[4];
+  for (int e = 0; e < 4; ++e) {
+    const int64_t base = ((s * 4 + e) * K) * C;
+    double acc = a.f0;
+    int64_t kk = 0;
+    double mean_last = 0.0, mean_first = 0.0;
+    for (int k = 0; k < K; ++k) {
+      int64_t sum = 0;
+      for (int c = 0; c < C; ++c)
+        sum += counted ? a.S[base + (int64_t)k * C + c] : (int64_t)a.n_final[base + (int64_t)k * C + c];
+      const double mean = (double)sum / denom;
+      if (k == 0) mean_first = mean;
+      if (k + 1 < K) {
+        acc = acc + ((k + 1) % 2 == 1 ? 4.0 : 2.0) * mean;
+        kk += ((k + 1) % 2 == 1 ? 4 : 2) * sum;
+      } else {
+        acc = acc + mean;
+        kk += sum;
+        mean_last = mean;
+      }
+    }
+    double integral;
+    if (K == 1) {
+      integral = (a.beta_bar / 2.0) * (a.f0 + mean_first);
+    } else {
+      const double h = a.beta_bar / (double)K;
+      integral = (acc * h) / 3.0;
+    }
+    logz[e] = a.log_z0 - integral;
+    key[e] = kk;
+    if (a.mean_n) a.mean_n[s * 4 + e] = mean_last;
+  }
+  double m = logz[0];
+  for (int e = 1; e < 4; ++e) m = logz[e] > m ? logz[e] : m;
+  double ex[4];
+  for (int e = 0; e < 4; ++e) ex[e] = exp(logz[e] - m);
+  const double tot = ((ex[0] + ex[1]) + ex[2]) + ex[3];
+  for (int e = 0; e < 4; ++e) a.class_prob[s * 4 + e] = ex[e] / tot;
+  int best = 0;
+  for (int e = 1; e < 4; ++e)
+    if (key[e] < key[best]) best = e;
+  a.chosen[s] = (uint8_t)best;
+
+  if (a.correction && a.corr_rows) {
+    const int L = a.L;
+    const int W = words_per_row(L);
+    const int nq = 2 * L * L - 2 * L + 1;
+    const int64_t n4 = a.n * 4;
+    const int64_t sc = s * 4 + best;
+    int q = 0;
+    for (int r = 0; r < 2 * L - 1; ++r) {
+      const int fields = (r & 1) ? L - 1 : L;
+      for (int f = 0; f < fields; ++f) {
+        const uint32_t word = a.corr_rows[(int64_t)(r * W + f / 16) * n4 + sc];
+        a.correction[s * nq + q++] = (uint8_t)((word >> (2 * (f % 16))) & 3u);
+      }
+    }
+  }
+}
+#pragma clang fp contract(on)
+
+hipError_t launch_decide(const DecideArgs& a, hipStream_t s) {
+  if (a.n == 0) return hipSuccess;
+  hipLaunchKernelGGL(decide_kernel, dim3((unsigned)((a.n + 127) / 128)), dim3(128), 0, s, a);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Depolarizing errors (Eq. pauliChannel with p/3 each), their syndrome and
+// class.  One workgroup per sample: the errors are drawn into LDS (one Philox
+// block serves two qubits), then every site takes its parity.
+// ---------------------------------------------------------------------------
+constexpr int SAMPLE_MAX_NQ = 2 * MCMC_L_MAX * MCMC_L_MAX - 2 * MCMC_L_MAX + 1;
+
+__global__ void __launch_bounds__(256) sample_kernel(int L, uint32_t threshold, uint32_t k0,
+                                                     uint32_t k1, const uint32_t* __restrict__ ids,
+                                                     uint32_t id_base, int64_t n,
+                                                     uint8_t* __restrict__ syn,
+                                                     uint8_t* __restrict__ true_class,
+                                                     uint8_t* __restrict__ errors) {
+  __shared__ uint8_t err[SAMPLE_MAX_NQ + 1];
+  const int64_t smp = blockIdx.x;
+  if (smp >= n) return;
+  const uint32_t sid = ids ? ids[smp] : id_base + (uint32_t)smp;
+  const int side = 2 * L - 1;
+  const int nq = 2 * L * L - 2 * L + 1;
+  const int nstab = 2 * L * (L - 1);
+  const int nstar = L * (L - 1);
+  for (int pr = threadIdx.x; pr < (nq + 1) / 2; pr += blockDim.x) {
+    const uint4 w = philox4x32_10(make_uint4((uint32_t)pr, 0u, sid, 1u << 30), k0, k1);
+    for (int h = 0; h < 2; ++h) {
+      const int q = 2 * pr + h;
+      if (q >= nq) break;
+      const uint32_t u0 = h ? w.z : w.x;
+      const uint32_t u1 = h ? w.w : w.y;
+      const uint32_t type = (uint32_t)(((uint64_t)u1 * 3u) >> 32);  // 0 X, 1 Y, 2 Z
+      const uint8_t code = (uint8_t)(type == 0 ? 1 : (type == 1 ? 3 : 2));
+      err[q] = u0 < threshold ? code : (uint8_t)0;
+    }
+  }
+  __syncthreads();
+  auto qidx = [side](int r, int c) { return (r * side + c) >> 1; };
+  for (int site = threadIdx.x; site < nstab; site += blockDim.x) {
+    int r, c, bit;
+    if (site < nstar) {
+      r = 2 * (site / L) + 1; c = 2 * (site % L); bit = 2;      // stars see z parts
+    } else {
+      const int k = site - nstar;
+      r = 2 * (k / (L - 1)); c = 2 * (k % (L - 1)) + 1; bit = 1;  // plaquettes see x parts
+    }
+    int par = 0;
+    if (r > 0) par ^= (err[qidx(r - 1, c)] & bit) != 0;
+    if (r < side - 1) par ^= (err[qidx(r + 1, c)] & bit) != 0;
+    if (c > 0) par ^= (err[qidx(r, c - 1)] & bit) != 0;
+    if (c < side - 1) par ^= (err[qidx(r, c + 1)] & bit) != 0;
+    syn[smp * nstab + site] = (uint8_t)par;
+  }
+  if (threadIdx.x == 0) {
+    int bx = 0, bz = 0;
+    for (int r = 0; r < side; r += 2) bx ^= err[qidx(r, 0)] & 1;
+    for (int c = 0; c < side; c += 2) bz ^= (err[qidx(0, c)] >> 1) & 1;
+    true_class[smp] = (uint8_t)(bx + 2 * bz);
+  }
+  if (errors)
+    for (int q = threadIdx.x; q < nq; q += blockDim.x) errors[smp * nq + q] = err[q];
+}
+
+hipError_t launch_sample(int L, uint32_t threshold, uint32_t k0, uint32_t k1, const uint32_t* ids,
+                         uint32_t id_base, int64_t n, uint8_t* syn, uint8_t* true_class,
+                         uint8_t* errors, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(sample_kernel, dim3((unsigned)n), dim3(256), 0, s, L, threshold, k0, k1, ids,
+                     id_base, n, syn, true_class, errors);
+  return hipGetLastError();
+}
+
+}  // namespace mcmc

@@ -1,0 +1,32 @@
+"""Seeded synthetic inputs shared by the oracle and the HIP path.
+
+Holds none of the decoder's arithmetic: only numpy's own generator (PCG64)
+for uniformly random syndrome bits (every bit string is a valid planar-code
+syndrome), the fixed seeds of the workloads, and the mixed-size workload
+descriptor.  Depolarizing samples themselves come from each side's own
+sampler, keyed by (seed, sample id).
+"""
+
+import numpy as np
+
+# 64-bit Philox keys of the workloads (decode and sampling use the same seed)
+SEED_SMALL = 0x1302266900000001      # L = 3, p = 0.10, 1000 samples, 4 x 1 chains, 2000 sweeps
+SEED_L9 = 0x1302266900000002         # L = 9, p in {0.05, 0.10, 0.15}, 4 x 4 chains, 81 sweeps
+SEED_METRIC = 0x1302266900000013     # L = 13, p = 0.15, 4 x 4 chains, 169 sweeps
+
+
+def n_stab(L):
+    return 2 * L * (L - 1)
+
+
+def uniform_syndromes(L, n, seed, density=0.5):
+    rng = np.random.default_rng(seed)
+    return (rng.random((n, n_stab(L))) < density).astype(np.uint8)
+
+
+def mixed_workload(n, seed, Ls=(5, 7, 9, 11, 13, 15, 17, 19, 21, 23, 25), p_lo=0.05, p_hi=0.18):
+    """(L [n], p [n], sweeps [n] = L^2) for the mixed-size batch."""
+    rng = np.random.default_rng(seed)
+    L = rng.choice(np.asarray(Ls), size=n)
+    p = p_lo + (p_hi - p_lo) * rng.random(n)
+    return L.astype(np.int32), p, (L * L).astype(np.int32)
