@@ -81,6 +81,14 @@ enum mcmc_status {
 #define MCMC_TRACE 1u  /* write n after every colour phase to d_trace          */
 #define MCMC_RESUME 2u /* start from d_chain_state instead of the class starts */
 
+/* class starts (Sec. IV: one starting configuration per class, consistent
+ * with the syndrome) */
+#define MCMC_INIT_CANONICAL 0u /* every anyon's string to the left (plaquettes) or
+                                  top (stars) boundary, times the logicals     */
+#define MCMC_INIT_MATCHING 1u  /* greedy matching per anyon type plus the
+                                  cheapest parity change per class (an
+                                  approximation of Sec. III's enhanced matching) */
+
 typedef struct mcmc_params {
   int32_t L;           /* code distance, MCMC_L_MIN..MCMC_L_MAX                  */
   int32_t n_temps;     /* K: 1 (beta* = beta_bar, Sec. IV.A) or even 2..64
@@ -95,7 +103,7 @@ typedef struct mcmc_params {
   double p;            /* depolarizing rate, 0 < p < 0.75 (beta_bar > 0)        */
   uint64_t seed;       /* Philox key                                            */
   uint32_t flags;      /* MCMC_TRACE | MCMC_RESUME                              */
-  uint32_t reserved;   /* must be 0                                             */
+  uint32_t init;       /* MCMC_INIT_CANONICAL or MCMC_INIT_MATCHING             */
 } mcmc_params;
 
 /* Human-readable name of a status code (static string). */
@@ -148,7 +156,8 @@ int mcmc_chain_state_size(const mcmc_params* h_prm, int64_t n, size_t* h_bytes);
  *  d_chain_state chain-state buffer (mcmc_chain_state_size) or NULL: read at
  *                start with MCMC_RESUME, written at the end when non-NULL
  *  d_trace       [n][4][K][chains][4*(burn+sweeps-sweep_begin)] int16, n after
- *                every colour phase, required iff MCMC_TRACE
+ *                every colour phase; required with MCMC_TRACE (may be NULL when
+ *                that length is 0), must be NULL without it
  *  d_workspace   >= mcmc_workspace_size() bytes, 256-byte aligned
  *
  * Output per syndrome depends only on its bytes, its id and *h_prm; never on
@@ -162,8 +171,9 @@ int mcmc_decode_batch(const uint8_t* d_syndromes, const uint32_t* d_syndrome_ids
 
 /* The four class starting configurations (Sec. IV: one chain start per
  * class, consistent with the syndrome) of n syndromes: d_reps [n][4][n_q]
- * uint8, row k of class k.  Asynchronous; needs no workspace. */
-int mcmc_init_representatives(int32_t L, const uint8_t* d_syndromes, int64_t n,
+ * uint8, row k of class k; `init` is MCMC_INIT_CANONICAL or
+ * MCMC_INIT_MATCHING.  Asynchronous; needs no workspace. */
+int mcmc_init_representatives(int32_t L, uint32_t init, const uint8_t* d_syndromes, int64_t n,
                               uint8_t* d_reps, void* stream);
 
 /* Unpack a chain-state buffer into d_states [n][4][K][chains][n_q] uint8 and

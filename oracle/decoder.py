@@ -14,8 +14,12 @@ import numpy as np
 from . import chains, estimator, geometry, init, tables
 
 
+INIT_CANONICAL = 0
+INIT_MATCHING = 1
+
+
 def decode(L, syndromes, p, sweeps, seed, chains_per_class=1, n_temps=1, burn=0,
-           syndrome_ids=None, trace=False, check_invariants=False):
+           syndrome_ids=None, trace=False, check_invariants=False, init_mode=INIT_MATCHING):
     lat = geometry.Lattice(L)
     syn = np.asarray(syndromes, dtype=np.uint8).reshape(-1, lat.n_stab)
     syn = (syn != 0).astype(np.uint8)
@@ -26,7 +30,8 @@ def decode(L, syndromes, p, sweeps, seed, chains_per_class=1, n_temps=1, burn=0,
     if K != 1 and K % 2 != 0:
         raise ValueError("n_temps must be 1 or even")
     tab = tables.tables(p, K)                                  # [K, 4]
-    reps = np.stack([init.representatives(lat, syn[i]) for i in range(n)]) \
+    start = init.matching_representatives if init_mode == INIT_MATCHING else init.representatives
+    reps = np.stack([start(lat, syn[i]) for i in range(n)]) \
         if n else np.zeros((0, 4, lat.n_qubits), np.uint8)
 
     # task order: ((syndrome * 4 + class) * K + (k - 1)) * chains + chain

@@ -10,11 +10,13 @@ import ctypes
 import numpy as np
 
 from . import _lib
-from ._lib import MCMC_L_MAX, MCMC_L_MIN, MCMC_RESUME, MCMC_TRACE, McmcError, Params
+from ._lib import (MCMC_INIT_CANONICAL, MCMC_INIT_MATCHING, MCMC_L_MAX, MCMC_L_MIN, MCMC_RESUME,
+                   MCMC_TRACE, McmcError, Params)
 
 __all__ = ["Params", "McmcError", "geometry", "lattice", "acceptance_table", "workspace_size",
            "chain_state_size", "decode_batch", "sample_errors", "init_representatives",
-           "unpack_chain_state", "MCMC_TRACE", "MCMC_RESUME", "MCMC_L_MIN", "MCMC_L_MAX"]
+           "unpack_chain_state", "MCMC_TRACE", "MCMC_RESUME", "MCMC_L_MIN", "MCMC_L_MAX",
+           "MCMC_INIT_CANONICAL", "MCMC_INIT_MATCHING"]
 
 
 def _torch():
@@ -56,10 +58,11 @@ def acceptance_table(p, n_temps=1):
     return out
 
 
-def make_params(L, p, sweeps, seed, chains=1, n_temps=1, burn=0, sweep_begin=0, flags=0):
+def make_params(L, p, sweeps, seed, chains=1, n_temps=1, burn=0, sweep_begin=0, flags=0,
+                init=MCMC_INIT_MATCHING):
     return Params(L=int(L), n_temps=int(n_temps), chains=int(chains), burn=int(burn),
                   sweeps=int(sweeps), sweep_begin=int(sweep_begin), p=float(p),
-                  seed=int(seed) & ((1 << 64) - 1), flags=int(flags), reserved=0)
+                  seed=int(seed) & ((1 << 64) - 1), flags=int(flags), init=int(init))
 
 
 def workspace_size(prm, n):
@@ -78,7 +81,7 @@ def chain_state_size(prm, n):
 
 def decode_batch(syndromes, L, p, sweeps, seed, chains=1, n_temps=1, burn=0, syndrome_ids=None,
                  want_sums=False, want_correction=True, trace=False, chain_state=None,
-                 resume_from=None, workspace=None):
+                 resume_from=None, workspace=None, init=MCMC_INIT_MATCHING):
     """Decode a [n, n_stab] uint8 device tensor of syndromes.
 
     Returns a dict of device tensors: class_prob [n,4] f64, mean_n [n,4] f64,
@@ -96,7 +99,7 @@ def decode_batch(syndromes, L, p, sweeps, seed, chains=1, n_temps=1, burn=0, syn
     syndromes = syndromes.contiguous()
     flags = (_lib.MCMC_TRACE if trace else 0) | (_lib.MCMC_RESUME if resume_from is not None else 0)
     begin = 0 if resume_from is None else int(resume_from[1])
-    prm = make_params(L, p, sweeps, seed, chains, n_temps, burn, begin, flags)
+    prm = make_params(L, p, sweeps, seed, chains, n_temps, burn, begin, flags, init)
     out = {
         "class_prob": torch.empty((n, 4), dtype=torch.float64, device=dev),
         "mean_n": torch.empty((n, 4), dtype=torch.float64, device=dev),
@@ -146,13 +149,13 @@ def sample_errors(L, p, seed, n, device="cuda", id_base=0, sample_ids=None, want
     return syn, cls, err
 
 
-def init_representatives(syndromes, L):
+def init_representatives(syndromes, L, init=MCMC_INIT_MATCHING):
     torch = _torch()
     nq, ns = geometry(L)
     n = int(syndromes.shape[0])
     reps = torch.empty((n, 4, nq), dtype=torch.uint8, device=syndromes.device)
-    st = _lib._lib().mcmc_init_representatives(int(L), _ptr(syndromes.contiguous()), n, _ptr(reps),
-                                               _stream(syndromes.device))
+    st = _lib._lib().mcmc_init_representatives(int(L), int(init), _ptr(syndromes.contiguous()), n,
+                                               _ptr(reps), _stream(syndromes.device))
     _lib.check(st, "mcmc_init_representatives")
     return reps
 

@@ -17,6 +17,7 @@ STATUS = {0: "MCMC_OK", -1: "MCMC_EINVAL", -2: "MCMC_ERANGE", -3: "MCMC_ENOMEM",
 MCMC_L_MIN, MCMC_L_MAX = 2, 25
 MCMC_TEMPS_MAX = 64
 MCMC_TRACE, MCMC_RESUME = 1, 2
+MCMC_INIT_CANONICAL, MCMC_INIT_MATCHING = 0, 1
 
 
 class McmcError(RuntimeError):
@@ -36,7 +37,7 @@ class Params(ctypes.Structure):
         ("p", ctypes.c_double),
         ("seed", ctypes.c_uint64),
         ("flags", ctypes.c_uint32),
-        ("reserved", ctypes.c_uint32),
+        ("init", ctypes.c_uint32),
     ]
 
 
@@ -57,7 +58,7 @@ _SIGNATURES = {
     "mcmc_chain_state_size": (ctypes.c_int, [_PPRM, _I64, _PSZ]),
     "mcmc_decode_batch": (ctypes.c_int, [_P, _P, _I64, _PPRM, _P, _P, _P, _P, _P, _P, _P, _P,
                                          _P, _SZ, _P]),
-    "mcmc_init_representatives": (ctypes.c_int, [_I32, _P, _I64, _P, _P]),
+    "mcmc_init_representatives": (ctypes.c_int, [_I32, _U32, _P, _I64, _P, _P]),
     "mcmc_unpack_chain_state": (ctypes.c_int, [_PPRM, _I64, _P, _P, _P, _P]),
     "mcmc_sample_errors": (ctypes.c_int, [_I32, _D, _U64, _P, _U32, _I64, _P, _P, _P, _P]),
 }

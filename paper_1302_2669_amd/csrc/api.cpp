@@ -34,7 +34,7 @@ int check_params(const mcmc_params* prm, int64_t n) {
   if (prm->burn < 0 || prm->sweeps < 0) return MCMC_ERANGE;
   if ((int64_t)prm->burn + prm->sweeps > MCMC_SWEEPS_MAX) return MCMC_ERANGE;
   if (prm->flags & ~(MCMC_TRACE | MCMC_RESUME)) return MCMC_EINVAL;
-  if (prm->reserved != 0) return MCMC_EINVAL;
+  if (prm->init != MCMC_INIT_CANONICAL && prm->init != MCMC_INIT_MATCHING) return MCMC_EINVAL;
   if (prm->flags & MCMC_RESUME) {
     if (prm->sweep_begin < 0 || prm->sweep_begin > prm->burn + prm->sweeps) return MCMC_ERANGE;
   } else if (prm->sweep_begin != 0) {
@@ -185,7 +185,9 @@ int mcmc_decode_batch(const uint8_t* syndromes, const uint32_t* syndrome_ids, in
   if (!syndromes || !class_prob || !chosen) return MCMC_EINVAL;
   const bool do_trace = (prm->flags & MCMC_TRACE) != 0;
   const bool resume = (prm->flags & MCMC_RESUME) != 0;
-  if (do_trace != (trace != nullptr)) return MCMC_EINVAL;
+  const int64_t trace_len = 4 * (int64_t)(prm->burn + prm->sweeps - prm->sweep_begin);
+  if (!do_trace && trace) return MCMC_EINVAL;
+  if (do_trace && !trace && trace_len > 0) return MCMC_EINVAL;
   if (resume && !chain_state) return MCMC_EINVAL;
   const WorkspaceLayout wl = workspace_layout(prm, n);
   if (!workspace || workspace_bytes < wl.bytes) return MCMC_EWORKSPACE;
@@ -204,7 +206,9 @@ int mcmc_decode_batch(const uint8_t* syndromes, const uint32_t* syndrome_ids, in
   uint32_t* corr_rows = correction ? (uint32_t*)(ws + wl.corr_rows) : nullptr;
 
   if (!resume) {
-    st = hip_status(mcmc::launch_init(L, syndromes, n, init_rows, init_n, nullptr, s));
+    st = hip_status(prm->init == MCMC_INIT_MATCHING
+                        ? mcmc::launch_init_matching(L, syndromes, n, init_rows, init_n, nullptr, s)
+                        : mcmc::launch_init(L, syndromes, n, init_rows, init_n, nullptr, s));
     if (st != MCMC_OK) return st;
   }
 
@@ -225,8 +229,8 @@ int mcmc_decode_batch(const uint8_t* syndromes, const uint32_t* syndrome_ids, in
   a.A_out = A;
   a.n_out = nf;
   a.corr_rows = corr_rows;
-  a.trace = trace;
-  a.trace_len = 4 * (int64_t)(a.sweep_end - a.sweep_begin);
+  a.trace = trace_len > 0 ? trace : nullptr;
+  a.trace_len = trace_len;
   if (chain_state) {
     const mcmc::ChainStateLayout cl = mcmc::chain_state_layout(L, T);
     char* cs = (char*)chain_state;
@@ -238,7 +242,7 @@ int mcmc_decode_batch(const uint8_t* syndromes, const uint32_t* syndrome_ids, in
       a.resume_A = (const int64_t*)(cs + cl.A);
     }
   }
-  st = hip_status(mcmc::launch_chain(L, a, s, do_trace, resume));
+  st = hip_status(mcmc::launch_chain(L, a, s, do_trace && trace_len > 0, resume));
   if (st != MCMC_OK) return st;
 
   if (chain_state) {  // n, S, A of every chain next to the rows
@@ -276,14 +280,17 @@ int mcmc_decode_batch(const uint8_t* syndromes, const uint32_t* syndrome_ids, in
   return hip_status(mcmc::launch_decide(d, s));
 }
 
-int mcmc_init_representatives(int32_t L, const uint8_t* syndromes, int64_t n, uint8_t* reps,
-                              void* stream) {
+int mcmc_init_representatives(int32_t L, uint32_t init, const uint8_t* syndromes, int64_t n,
+                              uint8_t* reps, void* stream) {
   if (!valid_L(L)) return MCMC_ERANGE;
+  if (init != MCMC_INIT_CANONICAL && init != MCMC_INIT_MATCHING) return MCMC_EINVAL;
   if (n < 0) return MCMC_ERANGE;
   if (n == 0) return MCMC_OK;
   if (!syndromes || !reps) return MCMC_EINVAL;
-  return hip_status(
-      mcmc::launch_init(L, syndromes, n, nullptr, nullptr, reps, (hipStream_t)stream));
+  hipStream_t s = (hipStream_t)stream;
+  return hip_status(init == MCMC_INIT_MATCHING
+                        ? mcmc::launch_init_matching(L, syndromes, n, nullptr, nullptr, reps, s)
+                        : mcmc::launch_init(L, syndromes, n, nullptr, nullptr, reps, s));
 }
 
 int mcmc_unpack_chain_state(const mcmc_params* prm, int64_t n, const void* chain_state,

@@ -45,6 +45,9 @@ hipError_t launch_chain(int L, const ChainArgs& a, hipStream_t s, bool trace, bo
 // rows ([RW][n*4] word-major), weights ([n*4]) and bytes ([n*4][n_q]) may each be nullptr.
 hipError_t launch_init(int L, const uint8_t* syn, int64_t n, uint32_t* rows, int32_t* weights,
                        uint8_t* bytes, hipStream_t s);
+// Greedy-matching class starts, same outputs as launch_init.
+hipError_t launch_init_matching(int L, const uint8_t* syn, int64_t n, uint32_t* rows,
+                                int32_t* weights, uint8_t* bytes, hipStream_t s);
 hipError_t launch_unpack(int L, const uint32_t* rows, int64_t count, int64_t stride,
                          uint8_t* out, int32_t* weights, hipStream_t s);
 

@@ -280,3 +280,210 @@ hipError_t launch_sample(int L, uint32_t threshold, uint32_t k0, uint32_t k1, co
 }
 
 }  // namespace mcmc
+
+namespace mcmc {
+
+// ---------------------------------------------------------------------------
+// Matching start (Sec. III, Sec. IV): each class's chain starts from a low-
+// weight configuration of that class, built per anyon type by a greedy
+// matching and a cheapest parity change ("enhanced" matching).
+//
+// Per type: distances are Manhattan |di| + |dj|; boundary distance j+1 or
+// L-1-j (plaquettes, left/right), i+1 or L-1-i (stars, top/bottom), nearer
+// side first, ties to left/top.  For d = 1, 2, ...: each free anyon a in
+// row-major order takes the first free b > a (row-major) at distance d, else
+// its boundary if that is at distance d.  The class parity of the type is
+// the number of left/top boundary matches mod 2; the other parity comes from
+// the cheapest single change, searched over boundary matches (switch side)
+// and then pairs (split into one left/top and one right/bottom match), first
+// minimum winning; with no anyon it is the logical string.  Paths: plaquette
+// pair: X on (2i1, 2j+2) for j between j1 and j2, then (2i+1, 2j2+1) for
+// i1 <= i < i2; star pair: Z on (2i+2, 2j1) for i1 <= i < i2, then
+// (2i2+1, 2j+1) for j between j1 and j2.
+//
+// One thread per syndrome; working bit-rows (one bit per qubit of a grid row)
+// live in LDS, [row][thread] so that lanes hit distinct banks.
+// ---------------------------------------------------------------------------
+constexpr int MATCH_THREADS = 64;
+constexpr int MATCH_R = 2 * MCMC_L_MAX - 1;
+
+struct MatchLds {
+  uint32_t plane[4][MATCH_R][MATCH_THREADS];  // x base, x flipped, z base, z flipped
+  uint32_t freem[MCMC_L_MAX][MATCH_THREADS];
+};
+
+__device__ __forceinline__ void toggle_bits(uint32_t (*pl)[MATCH_THREADS], int row, int lo, int hi,
+                                            int tid) {
+  // toggle fields lo..hi-1 of grid row `row`
+  if (hi > lo) pl[row][tid] ^= ((hi >= 32 ? 0u : (1u << hi)) - 1u) ^ ((1u << lo) - 1u);
+}
+
+// XOR the boundary string of anyon (i, j) on `side` into plane pl.
+__device__ __forceinline__ void paint_boundary(uint32_t (*pl)[MATCH_THREADS], int L, bool star,
+                                               int i, int j, int side, int tid) {
+  if (!star) {
+    if (side == 0) toggle_bits(pl, 2 * i, 0, j + 1, tid);
+    else toggle_bits(pl, 2 * i, j + 1, L, tid);
+  } else {
+    const int r0 = side == 0 ? 0 : i + 1, r1 = side == 0 ? i + 1 : L;
+    for (int k = r0; k < r1; ++k) pl[2 * k][tid] ^= 1u << j;
+  }
+}
+
+__device__ __forceinline__ void paint_pair(uint32_t (*pl)[MATCH_THREADS], bool star, int i1, int j1,
+                                           int i2, int j2, int tid) {
+  const int jl = j1 < j2 ? j1 : j2, jh = j1 < j2 ? j2 : j1;
+  if (!star) {
+    toggle_bits(pl, 2 * i1, jl + 1, jh + 1, tid);             // (2i1, 2j+2), jl <= j < jh
+    for (int i = i1; i < i2; ++i) pl[2 * i + 1][tid] ^= 1u << j2;  // (2i+1, 2j2+1)
+  } else {
+    for (int i = i1; i < i2; ++i) pl[2 * i + 2][tid] ^= 1u << j1;  // (2i+2, 2j1)
+    toggle_bits(pl, 2 * i2 + 1, jl, jh, tid);                 // (2i2+1, 2j+1), jl <= j < jh
+  }
+}
+
+__global__ void __launch_bounds__(MATCH_THREADS) init_matching_kernel(
+    int L, const uint8_t* __restrict__ syn, int64_t n, uint32_t* __restrict__ rows,
+    int32_t* __restrict__ weights, uint8_t* __restrict__ bytes) {
+  __shared__ MatchLds sh;
+  const int tid = threadIdx.x;
+  const int64_t s = (int64_t)blockIdx.x * MATCH_THREADS + tid;
+  if (s >= n) return;
+  const int R = 2 * L - 1;
+  const int nstab = 2 * L * (L - 1), nstar = L * (L - 1);
+  const uint8_t* sy = syn + s * nstab;
+  for (int p = 0; p < 4; ++p)
+    for (int r = 0; r < R; ++r) sh.plane[p][r][tid] = 0u;
+
+  int base_par[2];
+  for (int t = 0; t < 2; ++t) {  // t = 0: plaquettes (x parts), t = 1: stars (z parts)
+    const bool star = t == 1;
+    const int nr = star ? L - 1 : L, nc = star ? L : L - 1;
+    const int off = star ? 0 : nstar;
+    uint32_t (*base)[MATCH_THREADS] = sh.plane[2 * t];
+    uint32_t (*flip)[MATCH_THREADS] = sh.plane[2 * t + 1];
+    bool any_free = false;
+    for (int i = 0; i < nr; ++i) {
+      uint32_t m = 0;
+      for (int j = 0; j < nc; ++j) m |= (uint32_t)(sy[off + i * nc + j] != 0) << j;
+      sh.freem[i][tid] = m;
+      any_free |= m != 0;
+    }
+    auto sd = [&](int i, int j, int side) {
+      return star ? (side == 0 ? i + 1 : L - 1 - i) : (side == 0 ? j + 1 : L - 1 - j);
+    };
+    int left = 0;
+    // best parity change: boundary kind (a, side) and pair kind (a, b, option)
+    int bb_delta = 1 << 30, bb_i = -1, bb_j = 0, bb_side = 0;
+    int bp_delta = 1 << 30, bp_i1 = -1, bp_j1 = 0, bp_i2 = 0, bp_j2 = 0, bp_opt = 0;
+    for (int d = 1; any_free; ++d) {
+      for (int i = 0; i < nr; ++i) {
+        int j = -1;
+        while (true) {
+          const uint32_t cur = sh.freem[i][tid];
+          const uint32_t m = (j + 1 >= 32) ? 0u : (cur & (~0u << (j + 1)));
+          if (!m) break;
+          j = __builtin_ctz(m);
+          // first free partner b > a at distance d
+          int bi = -1, bj = -1;
+          if (j + d < nc && ((cur >> (j + d)) & 1u)) {
+            bi = i; bj = j + d;
+          } else {
+            for (int di = 1; di <= d && i + di < nr; ++di) {
+              const uint32_t rm = sh.freem[i + di][tid];
+              const int dj = d - di;
+              if (dj > 0) {
+                if (j - dj >= 0 && ((rm >> (j - dj)) & 1u)) { bi = i + di; bj = j - dj; break; }
+                if (j + dj < nc && ((rm >> (j + dj)) & 1u)) { bi = i + di; bj = j + dj; break; }
+              } else if ((rm >> j) & 1u) {
+                bi = i + di; bj = j; break;
+              }
+            }
+          }
+          if (bi >= 0) {
+            sh.freem[i][tid] &= ~(1u << j);
+            sh.freem[bi][tid] &= ~(1u << bj);
+            paint_pair(base, star, i, j, bi, bj, tid);
+            for (int opt = 0; opt < 2; ++opt) {
+              const int delta = sd(i, j, opt) + sd(bi, bj, 1 - opt) - d;
+              if (delta < bp_delta) {
+                bp_delta = delta; bp_i1 = i; bp_j1 = j; bp_i2 = bi; bp_j2 = bj; bp_opt = opt;
+              }
+            }
+          } else {
+            const int dn0 = sd(i, j, 0), dn1 = sd(i, j, 1);
+            const int side = dn0 <= dn1 ? 0 : 1;
+            if ((side == 0 ? dn0 : dn1) == d) {
+              sh.freem[i][tid] &= ~(1u << j);
+              paint_boundary(base, L, star, i, j, side, tid);
+              left += side == 0;
+              const int delta = (side == 0 ? dn1 - dn0 : dn0 - dn1);
+              if (delta < bb_delta) { bb_delta = delta; bb_i = i; bb_j = j; bb_side = side; }
+            }
+          }
+        }
+      }
+      any_free = false;
+      for (int i = 0; i < nr; ++i) any_free |= sh.freem[i][tid] != 0;
+    }
+    base_par[t] = left & 1;
+    // flipped parity = base xor the cheapest change
+    for (int r = 0; r < R; ++r) flip[r][tid] = base[r][tid];
+    if (bb_i >= 0 && (bp_i1 < 0 || bb_delta <= bp_delta)) {
+      paint_boundary(flip, L, star, bb_i, bb_j, bb_side, tid);
+      paint_boundary(flip, L, star, bb_i, bb_j, 1 - bb_side, tid);
+    } else if (bp_i1 >= 0) {
+      paint_pair(flip, star, bp_i1, bp_j1, bp_i2, bp_j2, tid);
+      paint_boundary(flip, L, star, bp_i1, bp_j1, bp_opt, tid);
+      paint_boundary(flip, L, star, bp_i2, bp_j2, 1 - bp_opt, tid);
+    } else if (!star) {
+      toggle_bits(flip, 0, 0, L, tid);                          // X-bar: row 0
+    } else {
+      for (int k = 0; k < L; ++k) flip[2 * k][tid] ^= 1u;       // Z-bar: column 0
+    }
+  }
+
+  const int W = words_per_row(L);
+  const int64_t n4 = n * 4;
+  const int nq = 2 * L * L - 2 * L + 1, side_len = 2 * L - 1;
+  for (int cls = 0; cls < 4; ++cls) {
+    uint32_t (*xp)[MATCH_THREADS] = sh.plane[((cls & 1) == base_par[0]) ? 0 : 1];
+    uint32_t (*zp)[MATCH_THREADS] = sh.plane[((cls >> 1) == base_par[1]) ? 2 : 3];
+    const int64_t sc = s * 4 + cls;
+    int weight = 0;
+    for (int r = 0; r < R; ++r) {
+      const int fields = (r & 1) ? L - 1 : L;
+      const uint32_t xb = xp[r][tid], zb = zp[r][tid];
+      const uint32_t valid = fields >= 32 ? ~0u : ((1u << fields) - 1u);
+      weight += __builtin_popcount((xb | zb) & valid);
+      if (rows) {
+        for (int w = 0; w < W; ++w) {
+          uint32_t word = 0;
+          for (int f = 0; f < 16; ++f) {
+            const int k = 16 * w + f;
+            const uint32_t code = k < fields ? (((xb >> k) & 1u) | (((zb >> k) & 1u) << 1)) : 3u;
+            word |= code << (2 * f);
+          }
+          rows[(int64_t)(r * W + w) * n4 + sc] = word;
+        }
+      }
+      if (bytes) {
+        // first qubit of row r: (r * side_len + (r & 1)) / 2
+        uint8_t* out = bytes + sc * nq + (r * side_len + (r & 1)) / 2;
+        for (int k = 0; k < fields; ++k)
+          out[k] = (uint8_t)(((xb >> k) & 1u) | (((zb >> k) & 1u) << 1));
+      }
+    }
+    if (weights) weights[sc] = weight;
+  }
+}
+
+hipError_t launch_init_matching(int L, const uint8_t* syn, int64_t n, uint32_t* rows,
+                                int32_t* weights, uint8_t* bytes, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(init_matching_kernel, dim3((unsigned)((n + MATCH_THREADS - 1) / MATCH_THREADS)),
+                     dim3(MATCH_THREADS), 0, s, L, syn, n, rows, weights, bytes);
+  return hipGetLastError();
+}
+
+}  // namespace mcmc

@@ -67,6 +67,7 @@ def _ws(**kw):
     (dict(n_temps=3), -1), (dict(n_temps=0), -2), (dict(n_temps=66), -2),
     (dict(chains=0), -2), (dict(sweeps=-1), -2), (dict(burn=-2), -2),
     (dict(L=30), -2), (dict(p=0.8), -2), (dict(flags=8), -1), (dict(sweep_begin=3), -1),
+    (dict(init=2), -1),
 ])
 def test_param_validation(kw, status):
     with pytest.raises(mc.McmcError) as e:

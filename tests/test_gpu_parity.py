@@ -39,11 +39,12 @@ def to_np(d):
 
 
 def gpu_decode(L, syn, p, sweeps, seed, chains=1, K=1, burn=0, ids=None, trace=True,
-               chain_state=True):
+               chain_state=True, init=mc.MCMC_INIT_MATCHING):
     s = torch.from_numpy(np.ascontiguousarray(syn, dtype=np.uint8)).to(DEV)
     tid = None if ids is None else torch.from_numpy(np.asarray(ids, dtype=np.int64))
     out = mc.decode_batch(s, L, p, sweeps, seed, chains=chains, n_temps=K, burn=burn,
-                          syndrome_ids=tid, want_sums=True, trace=trace, chain_state=chain_state)
+                          syndrome_ids=tid, want_sums=True, trace=trace, chain_state=chain_state,
+                          init=init)
     res = to_np({k: v for k, v in out.items() if k != "chain_state"})
     if chain_state:
         st, w = mc.unpack_chain_state(out["chain_state"], syn.shape[0], L, p, sweeps, seed, chains,
@@ -83,16 +84,19 @@ def test_sampler_parity(L, p):
 
 
 # ---------------------------------------------------------------- class starts
+@pytest.mark.parametrize("mode", [mc.MCMC_INIT_CANONICAL, mc.MCMC_INIT_MATCHING])
 @pytest.mark.parametrize("L", [2, 3, 4, 5, 9, 13, 15, 16, 17, 24, 25])
-def test_init_parity(L):
-    say(f"init L={L}")
+def test_init_parity(L, mode):
+    say(f"init L={L} mode={mode}")
     lat = geometry.Lattice(L)
-    syn = uniform_syndromes(L, 40, seed=L)
+    start = init.matching_representatives if mode == mc.MCMC_INIT_MATCHING else init.representatives
+    syn = np.concatenate([uniform_syndromes(L, 30, seed=L),
+                          uniform_syndromes(L, 30, seed=L + 100, density=0.08)])
     syn[0] = 0
     syn[1] = 1
-    reps = mc.init_representatives(torch.from_numpy(syn).to(DEV), L).cpu().numpy()
+    reps = mc.init_representatives(torch.from_numpy(syn).to(DEV), L, init=mode).cpu().numpy()
     for i in range(syn.shape[0]):
-        assert np.array_equal(reps[i], init.representatives(lat, syn[i])), i
+        assert np.array_equal(reps[i], start(lat, syn[i])), i
 
 
 # ---------------------------------------------------------------- chains
@@ -114,14 +118,15 @@ CASES = [
 
 
 @pytest.mark.parametrize("L,p,sweeps,burn,chains,K,n", CASES)
-def test_chain_parity(L, p, sweeps, burn, chains, K, n):
-    say(f"chains L={L} p={p} sweeps={sweeps} burn={burn} chains={chains} K={K} n={n}")
+@pytest.mark.parametrize("mode", [mc.MCMC_INIT_MATCHING, mc.MCMC_INIT_CANONICAL])
+def test_chain_parity(L, p, sweeps, burn, chains, K, n, mode):
+    say(f"chains L={L} p={p} sweeps={sweeps} burn={burn} chains={chains} K={K} n={n} init={mode}")
     lat = geometry.Lattice(L)
     syn, _, _ = sampler.sample(lat, p, SEED_L9 + L, np.arange(n))
     ids = np.arange(n) * 7 + 3
-    g = gpu_decode(L, syn, p, sweeps, SEED_L9, chains, K, burn, ids=ids)
+    g = gpu_decode(L, syn, p, sweeps, SEED_L9, chains, K, burn, ids=ids, init=mode)
     o = decoder.decode(L, syn, p, sweeps, SEED_L9, chains_per_class=chains, n_temps=K, burn=burn,
-                       syndrome_ids=ids, trace=True)
+                       syndrome_ids=ids, trace=True, init_mode=mode)
     o["n_final"] = o["n_final"].astype(np.int32)
     assert_parity(g, o)
 

@@ -171,12 +171,16 @@ def test_decision_rules():
     assert chosen == 1 and mean.tolist() == [7.0, 5.0, 9.0, 6.0]
 
 
-def test_decoder_zero_sweeps_is_min_weight_of_starts():
+@pytest.mark.parametrize("mode", [decoder.INIT_CANONICAL, decoder.INIT_MATCHING])
+def test_decoder_zero_sweeps_is_min_weight_of_starts(mode):
+    """With no sweep the decision compares the class starts' weights, which
+    for the matching start is Sec. III's enhanced-matching rule."""
     lat = geometry.Lattice(5)
     syn, _, _ = sampler.sample(lat, 0.1, 3, np.arange(20))
-    out = decoder.decode(5, syn, 0.1, 0, 1, chains_per_class=1)
+    out = decoder.decode(5, syn, 0.1, 0, 1, chains_per_class=1, init_mode=mode)
+    start = init.matching_representatives if mode == decoder.INIT_MATCHING else init.representatives
     for i in range(20):
-        w = geometry.weight(init.representatives(lat, syn[i]))
+        w = geometry.weight(start(lat, syn[i]))
         assert out["chosen"][i] == int(np.argmin(w))
 
 

@@ -60,3 +60,60 @@ def test_all_syndromes_small():
         syn = np.array([(v >> b) & 1 for b in range(lat.n_stab)], dtype=np.uint8)
         reps = init.representatives(lat, syn)
         assert np.array_equal(geometry.syndrome(lat, reps)[0], syn)
+
+
+@pytest.mark.parametrize("L", [2, 3, 4, 5, 8, 13, 25])
+def test_matching_representatives_valid(L):
+    lat = geometry.Lattice(L)
+    rng = np.random.default_rng(100 + L)
+    for density in (0.05, 0.3, 0.7):
+        syns = (rng.random((10, lat.n_stab)) < density).astype(np.uint8)
+        for syn in syns:
+            reps = init.matching_representatives(lat, syn)
+            assert np.array_equal(geometry.syndrome(lat, reps), np.broadcast_to(syn, (4, lat.n_stab)))
+            assert geometry.class_index(lat, reps).tolist() == [0, 1, 2, 3]
+
+
+@pytest.mark.parametrize("L", [3, 5, 9])
+def test_matching_recovers_single_errors(L):
+    """Any single-qubit error is matched back exactly: its anyons are adjacent
+    (or next to a boundary), so the start of the error's own class is the
+    error itself, of weight 1."""
+    lat = geometry.Lattice(L)
+    for q in range(lat.n_qubits):
+        for code in (1, 2, 3):
+            e = np.zeros(lat.n_qubits, dtype=np.uint8)
+            e[q] = code
+            syn = geometry.syndrome(lat, e)
+            reps = init.matching_representatives(lat, syn)
+            c = int(geometry.class_index(lat, e))
+            assert np.array_equal(reps[c], e), (q, code)
+
+
+@pytest.mark.parametrize("L", [2, 3, 5, 13])
+def test_matching_empty_syndrome(L):
+    lat = geometry.Lattice(L)
+    reps = init.matching_representatives(lat, np.zeros(lat.n_stab, dtype=np.uint8))
+    assert geometry.weight(reps).tolist() == [0, L, L, 2 * L - 1]
+
+
+def test_matching_is_minimum_weight_for_sparse_syndromes():
+    """At low density the greedy start of every class reaches the exact
+    minimum weight of its class (L = 3, exhaustive over two-error syndromes)."""
+    from oracle import enumerate as en
+    lat = geometry.Lattice(3)
+    hits = total = 0
+    for q1 in range(lat.n_qubits):
+        for q2 in range(q1 + 1, lat.n_qubits):
+            e = np.zeros(lat.n_qubits, dtype=np.uint8)
+            e[q1], e[q2] = 1, 2
+            syn = geometry.syndrome(lat, e)
+            h = en.class_histograms(lat, syn)
+            reps = init.matching_representatives(lat, syn)
+            w = geometry.weight(reps)
+            c = int(geometry.class_index(lat, e))
+            exact_min = int(np.nonzero(h[c])[0][0])
+            assert w[c] >= exact_min
+            hits += int(w[c] == exact_min)
+            total += 1
+    assert hits == total
