@@ -27,11 +27,16 @@ import numpy as np
 L, P, CHAINS, SWEEPS, BURN, K = 13, 0.15, 4, 169, 0, 1
 SEED = 0x1302266900000013
 BATCH = 65536
-# integer operations per stabilizer update in the minimal formulation
-# (Philox4x32-10 share 20, weight change 8-12, accept 4, flip 4, accumulate 3)
+# integer operations per stabilizer update in the minimal scalar formulation:
+# Philox4x32-10 share 20 (5 mul_lo + 5 mul_hi + 10 xor), weight change 8-12,
+# accept 4, flip 4, accumulate 3 -> 40 at the low end
 OPS_PER_UPDATE = 40
-# MI355X: 256 CUs x 64 int32 lanes per clock x 2.4 GHz
-PEAK_INT_OPS = 256 * 64 * 2.4e9
+# MI355X vector ALU: 256 CUs x 128 lanes per clock x 2.4 GHz = 78.6 T lane
+# slots/s (the FP32 vector peak of 157.3 TFLOP/s counts an FMA as two flops);
+# three-operand integer instructions (v_mad_u64_u32: mul_lo + mul_hi,
+# v_bitop3: two XORs, v_add3: two adds) retire two operations per slot, so the
+# integer-operation peak is 157.3 T ops/s
+PEAK_INT_OPS = 256 * 128 * 2.4e9 * 2
 
 
 def main():
@@ -42,6 +47,8 @@ def main():
     ap.add_argument("--batch", type=int, default=BATCH)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=256)
+    ap.add_argument("--copy-probe-mb", type=int, default=0,
+                    help="also run one device copy of this size (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the decoder "
@@ -116,6 +123,12 @@ def main():
     chain_updates = n * updates_per_syndrome
     achieved = chain_updates * OPS_PER_UPDATE / (chain_ms * 1e-3) / 1e12
     peak = PEAK_INT_OPS / 1e12
+
+    if args.copy_probe_mb:
+        src = torch.ones((args.copy_probe_mb << 20,), dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -47,6 +47,32 @@ __device__ __forceinline__ uint32_t nibble_sum(uint32_t v, uint32_t acc) {
   return __builtin_amdgcn_sad_u8(b, 0u, acc);
 }
 
+// acc = 2 * acc + (u < thr): the comparison's borrow lands directly in the
+// running bit mask (site order is reversed by the caller).
+__device__ __forceinline__ uint32_t push_accept(uint32_t acc, uint32_t u, uint32_t thr) {
+  asm("v_cmp_lt_u32 vcc, %1, %2\n\tv_addc_co_u32 %0, vcc, %0, %0, vcc"
+      : "+v"(acc)
+      : "v"(u), "v"(thr)
+      : "vcc");
+  return acc;
+}
+
+// Bits 0..7 of x moved to bits 0, 4, ..., 28 (one per nibble).
+__device__ __forceinline__ uint32_t spread_nibbles(uint32_t x) {
+  x = (x | (x << 12)) & 0x000F000Fu;
+  x = (x | (x << 6)) & 0x03030303u;
+  return (x | (x << 3)) & 0x11111111u;
+}
+
+// Nibble-LSB mask of the sites of one row in word w: sites j = par, par+2, ...
+// below `limit` fields, at nibble (j % 16) / 2 of word j / 16.
+__host__ __device__ constexpr uint32_t site_nibbles(int par, int limit, int w) {
+  uint32_t m = 0;
+  for (int j = par; j < limit; j += 2)
+    if (j / 16 == w) m |= 1u << (4 * ((j % 16) / 2));
+  return m;
+}
+
 // Rank (position within its colour, row-major) of the first site of row i.
 template <int L>
 __host__ __device__ constexpr int star_row_rank(int i, int par_of_row0) {
@@ -150,6 +176,42 @@ chain_kernel(const ChainArgs a, const int64_t T) {
       if constexpr (TRACE) trace[tpos++] = (int16_t)n;
     };
 
+    // Accept decisions of one row's sites (nibble m of `sum` holds Delta n + 4
+    // of site m): Philox words in draw order, thresholds from LDS, then
+    // u < A[Delta] folded into a bit mask, OR the sites with Delta n <= 0
+    // (t + 3 < 8).  Leaves the nibble-LSB accept masks in acc and adds the
+    // row's weight change and accept count.
+    auto decide_row = [&](auto PAR, auto NSITE, auto D0, auto LIMIT, const uint32_t (&sum)[W],
+                          uint32_t (&acc)[W]) {
+      constexpr int par = decltype(PAR)::value, nsite = decltype(NSITE)::value;
+      constexpr int d0 = decltype(D0)::value, limit = decltype(LIMIT)::value;
+      uint32_t uu[nsite], th[nsite];
+      static_for<nsite>([&](auto MM) {
+        constexpr int m = decltype(MM)::value;
+        constexpr int j = par + 2 * m;
+        constexpr int w = j / 16, nib = (j % 16) / 2;
+        constexpr int d = d0 + m;
+        if constexpr ((d & 3) == 0) blk = rng.template block<d / 4>();
+        uu[m] = word_of(blk, d & 3);
+        th[m] = lds_tbl[(sum[w] >> (4 * nib)) & 15u][lane];
+      });
+      uint32_t bits = 0;  // bit m: u_m < A[Delta_m]
+      static_for<nsite>([&](auto MM) {
+        constexpr int m = nsite - 1 - decltype(MM)::value;
+        bits = push_accept(bits, uu[m], th[m]);
+      });
+      static_for<W>([&](auto WW) {
+        constexpr int w = decltype(WW)::value;
+        constexpr uint32_t sites = site_nibbles(par, limit, w);
+        const uint32_t low = ~(sum[w] + 0x33333333u) >> 3;  // nibble LSB: t <= 4
+        acc[w] = (spread_nibbles((bits >> (8 * w)) & 0xFFu) | low) & sites;
+        const uint32_t nm = (acc[w] << 4) - acc[w];
+        const int32_t cnt = (int32_t)__builtin_popcount(acc[w]);
+        dn += (int32_t)nibble_sum(sum[w] & nm, 0u) - 4 * cnt;
+        acc_total += cnt;
+      });
+    };
+
     // ---------------- stars: colours 0 and 1 ----------------
     static_for<2>([&](auto PH) {
       constexpr int phi = decltype(PH)::value;
@@ -170,26 +232,10 @@ chain_kernel(const ChainArgs a, const int64_t T) {
           constexpr uint32_t M = 0x33333333u;
           sum[w] = ((cN >> (2 * par)) & M) + ((cS >> (2 * par)) & M) +
                    ((cO[w] >> (2 * par)) & M) + ((cWest >> (2 * par)) & M);
-          acc[w] = 0;
         });
-        static_for<nsite>([&](auto MM) {
-          constexpr int m = decltype(MM)::value;
-          constexpr int j = par + 2 * m;
-          constexpr int w = j / 16, nib = (j % 16) / 2;
-          constexpr int d = phi * S + rank0 + m;
-          if constexpr ((d & 3) == 0) blk = rng.template block<d / 4>();
-          const uint32_t u = word_of(blk, d & 3);
-          const uint32_t tt = (sum[w] >> (4 * nib)) & 15u;
-          const uint32_t thr = lds_tbl[tt][lane];
-          const bool ok = (tt <= 4u) | (u < thr);
-          acc[w] |= (uint32_t)ok << (4 * nib);
-        });
-        static_for<W>([&](auto WW) {
-          constexpr int w = decltype(WW)::value;
-          const uint32_t nm = (acc[w] << 4) - acc[w];
-          dn += (int32_t)nibble_sum(sum[w] & nm, 0u) - 4 * (int32_t)__builtin_popcount(acc[w]);
-          acc_total += __builtin_popcount(acc[w]);
-        });
+        decide_row(std::integral_constant<int, par>{}, std::integral_constant<int, nsite>{},
+                   std::integral_constant<int, phi * S + rank0>{},
+                   std::integral_constant<int, L>{}, sum, acc);
         uint32_t ax[W];
         static_for<W>([&](auto WW) { ax[decltype(WW)::value] = acc[decltype(WW)::value] << (2 * par); });
         static_for<W>([&](auto WW) {
@@ -226,26 +272,10 @@ chain_kernel(const ChainArgs a, const int64_t T) {
             constexpr uint32_t M = 0x33333333u;
             sum[w] = ((cN >> (2 * par)) & M) + ((cS >> (2 * par)) & M) +
                      ((cE[w] >> (2 * par)) & M) + ((cEast >> (2 * par)) & M);
-            acc[w] = 0;
           });
-          static_for<nsite>([&](auto MM) {
-            constexpr int m = decltype(MM)::value;
-            constexpr int j = par + 2 * m;
-            constexpr int w = j / 16, nib = (j % 16) / 2;
-            constexpr int d = phi * S + rank0 + m;
-            if constexpr ((d & 3) == 0) blk = rng.template block<d / 4>();
-            const uint32_t u = word_of(blk, d & 3);
-            const uint32_t tt = (sum[w] >> (4 * nib)) & 15u;
-            const uint32_t thr = lds_tbl[tt][lane];
-            const bool ok = (tt <= 4u) | (u < thr);
-            acc[w] |= (uint32_t)ok << (4 * nib);
-          });
-          static_for<W>([&](auto WW) {
-            constexpr int w = decltype(WW)::value;
-            const uint32_t nm = (acc[w] << 4) - acc[w];
-            dn += (int32_t)nibble_sum(sum[w] & nm, 0u) - 4 * (int32_t)__builtin_popcount(acc[w]);
-            acc_total += __builtin_popcount(acc[w]);
-          });
+          decide_row(std::integral_constant<int, par>{}, std::integral_constant<int, nsite>{},
+                     std::integral_constant<int, phi * S + rank0>{},
+                     std::integral_constant<int, L - 1>{}, sum, acc);
           uint32_t az[W];
           static_for<W>([&](auto WW) { az[decltype(WW)::value] = acc[decltype(WW)::value] << (2 * par + 1); });
           static_for<W>([&](auto WW) {

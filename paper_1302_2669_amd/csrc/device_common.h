@@ -65,19 +65,41 @@ __device__ __forceinline__ void mulhilo(uint32_t a, uint32_t b, uint32_t& hi, ui
   lo = (uint32_t)p;
 }
 
+// a ^ b ^ k in one three-input bit operation (truth table 0x96); k is
+// wave-uniform (the Philox round key) and sits in an SGPR.
+__device__ __forceinline__ uint32_t xor3_key(uint32_t a, uint32_t b, uint32_t k) {
+  uint32_t r;
+  asm("v_bitop3_b32 %0, %1, %2, %3 bitop3:0x96" : "=v"(r) : "v"(a), "v"(b), "s"(k));
+  return r;
+}
+
+__device__ __forceinline__ uint4 philox_round(uint4 c, uint32_t k0, uint32_t k1) {
+  uint32_t h0, l0, h1, l1;
+  mulhilo(PHILOX_M0, c.x, h0, l0);
+  mulhilo(PHILOX_M1, c.z, h1, l1);
+  return make_uint4(xor3_key(h1, c.y, k0), l1, xor3_key(h0, c.w, k1), l0);
+}
+
 // Rounds first..9 of Philox4x32-10 on counter c; key (k0, k1) is the ORIGINAL
-// key (round r uses k + r*W).
+// key (round r uses k + r*W).  The loop body holds two rounds, so the word
+// rotation of a round costs no register moves; the loop itself is kept rolled
+// because the chain kernel inlines one copy per block of draws.
 __device__ __forceinline__ uint4 philox_rounds(uint4 c, uint32_t k0, uint32_t k1, int first) {
   k0 += (uint32_t)first * PHILOX_W0;
   k1 += (uint32_t)first * PHILOX_W1;
-#pragma unroll 1
-  for (int r = first; r < 10; ++r) {
-    uint32_t h0, l0, h1, l1;
-    mulhilo(PHILOX_M0, c.x, h0, l0);
-    mulhilo(PHILOX_M1, c.z, h1, l1);
-    c = make_uint4(h1 ^ c.y ^ k0, l1, h0 ^ c.w ^ k1, l0);
+  int r = first;
+  if ((10 - first) & 1) {
+    c = philox_round(c, k0, k1);
     k0 += PHILOX_W0;
     k1 += PHILOX_W1;
+    ++r;
+  }
+#pragma unroll 1
+  for (; r < 10; r += 2) {
+    c = philox_round(c, k0, k1);
+    c = philox_round(c, k0 + PHILOX_W0, k1 + PHILOX_W1);
+    k0 += 2 * PHILOX_W0;
+    k1 += 2 * PHILOX_W1;
   }
   return c;
 }
