@@ -193,6 +193,87 @@ int mcmc_sample_errors(int32_t L, double p, uint64_t seed, const uint32_t* d_sam
                        uint32_t id_base, int64_t n, uint8_t* d_syndromes, uint8_t* d_true_class,
                        uint8_t* d_errors, void* stream);
 
+/*
+ * Mixed batches (syndromes of different L, p, sweep budget, chains and
+ * temperature count in one decode).  A plan is built once on the host from an
+ * array of items; executing it enqueues the class starts, the persistent
+ * chain kernels (one per L range its syndromes fall in: 2-13, 14-16, and on a
+ * second stream 17-19, 20-22, 23-25; waves take 64-chain tiles from an atomic
+ * queue, longest tiles first) and the estimator, with no host
+ * synchronisation.  The same sequence can be recorded into a HIP graph once
+ * and replayed (mcmc_plan_graph_launch).  Per-syndrome results are identical
+ * to mcmc_decode_batch with that syndrome's parameters and id, whatever the
+ * batch composition or launch shape.
+ */
+typedef struct mcmc_item {
+  int32_t L;            /* MCMC_L_MIN..MCMC_L_MAX                                  */
+  int32_t sweeps;       /* counted sweeps, >= 0                                    */
+  int32_t burn;         /* uncounted sweeps, >= 0                                  */
+  int32_t chains;       /* chains per class and temperature, >= 1                  */
+  int32_t n_temps;      /* 1 or even 2..64                                         */
+  uint32_t syndrome_id; /* Philox counter word 2 of this syndrome's chains         */
+  double p;             /* depolarizing rate, 0 < p < 0.75                         */
+  int64_t syn_offset;   /* byte offset of its n_stab(L) syndrome bytes in the input */
+  int64_t corr_offset;  /* byte offset of its n_q(L) correction bytes in the output */
+} mcmc_item;
+
+/* Launch shape of a plan: workgroup size (64, 128 or 256) of the L <= 16
+ * kernels (narrow) and of the L >= 17 kernels (wide); the persistent grid of
+ * each kernel in waves per SIMD, as an offset (narrow -4..8, wide -2..8)
+ * from the occupancy its register budget allows; and whether the two groups
+ * run on two streams at once (1) or one after the other (0).  Never changes
+ * results. */
+typedef struct mcmc_tuning {
+  int32_t wg_narrow, occ_narrow;
+  int32_t wg_wide, occ_wide;
+  int32_t concurrent;
+} mcmc_tuning;
+
+typedef struct mcmc_plan mcmc_plan; /* opaque */
+
+/* Build a plan for n items (host array, copied).  Allocates the plan's device
+ * tables (hipMalloc) and two streams; *plan receives the handle.  ERANGE /
+ * EINVAL for an invalid item (checked before anything is allocated). */
+int mcmc_plan_create(const mcmc_item* h_items, int64_t n, uint64_t seed, uint32_t init,
+                     mcmc_plan** plan);
+int mcmc_plan_destroy(mcmc_plan* plan);
+
+/* Total chains (length of the per-chain outputs), workspace bytes, and the
+ * number of stabilizer updates one execution performs.  Any pointer may be NULL. */
+int mcmc_plan_info(const mcmc_plan* plan, int64_t* h_total_chains, size_t* h_workspace_bytes,
+                   int64_t* h_total_updates);
+int mcmc_plan_get_tuning(const mcmc_plan* plan, mcmc_tuning* h_tuning);
+int mcmc_plan_set_tuning(mcmc_plan* plan, const mcmc_tuning* h_tuning);
+
+/*
+ * Decode the plan's syndromes.  Outputs are indexed by the item's position in
+ * the array given to mcmc_plan_create:
+ *  d_class_prob [n][4] f64, d_mean_n [n][4] f64 or NULL, d_chosen [n] u8;
+ *  d_sum_n / d_accepts: per chain, item i's [4][K][chains] block after those
+ *  of items 0..i-1 (or NULL); d_correction: at each item's corr_offset (or NULL).
+ */
+int mcmc_plan_execute(mcmc_plan* plan, const uint8_t* d_syndromes, double* d_class_prob,
+                      double* d_mean_n, int64_t* d_sum_n, int64_t* d_accepts, uint8_t* d_chosen,
+                      uint8_t* d_correction, void* d_workspace, size_t workspace_bytes,
+                      void* stream);
+
+/* Same, through a HIP graph recorded on first use for this set of pointers
+ * and replayed afterwards (the plan keeps the instantiated graphs). */
+int mcmc_plan_graph_launch(mcmc_plan* plan, const uint8_t* d_syndromes, double* d_class_prob,
+                           double* d_mean_n, int64_t* d_sum_n, int64_t* d_accepts,
+                           uint8_t* d_chosen, uint8_t* d_correction, void* d_workspace,
+                           size_t workspace_bytes, void* stream);
+
+/* Pick the launch shape by timing whole executions of the plan (coordinate
+ * search over workgroup size, grid sizes and stream overlap), synchronising
+ * `stream`.  With cache_path, a stored shape for the same workload signature
+ * (device CU count and the plan's groups) is reused, and a new one appended.
+ * The chosen shape is written to *h_result when non-NULL. */
+int mcmc_plan_autotune(mcmc_plan* plan, const uint8_t* d_syndromes, double* d_class_prob,
+                       double* d_mean_n, int64_t* d_sum_n, int64_t* d_accepts, uint8_t* d_chosen,
+                       uint8_t* d_correction, void* d_workspace, size_t workspace_bytes,
+                       void* stream, const char* cache_path, mcmc_tuning* h_result);
+
 #ifdef __cplusplus
 }
 #endif

@@ -16,7 +16,7 @@ from ._lib import (MCMC_INIT_CANONICAL, MCMC_INIT_MATCHING, MCMC_L_MAX, MCMC_L_M
 __all__ = ["Params", "McmcError", "geometry", "lattice", "acceptance_table", "workspace_size",
            "chain_state_size", "decode_batch", "sample_errors", "init_representatives",
            "unpack_chain_state", "MCMC_TRACE", "MCMC_RESUME", "MCMC_L_MIN", "MCMC_L_MAX",
-           "MCMC_INIT_CANONICAL", "MCMC_INIT_MATCHING"]
+           "MCMC_INIT_CANONICAL", "MCMC_INIT_MATCHING", "MixedPlan"]
 
 
 def _torch():
@@ -171,3 +171,123 @@ def unpack_chain_state(chain_state, n, L, p, sweeps, seed, chains=1, n_temps=1, 
                                              _stream(chain_state.device))
     _lib.check(st, "mcmc_unpack_chain_state")
     return states, weights
+
+
+class MixedPlan:
+    """A mixed batch: syndromes of different L, p, budgets and chain counts
+    decoded by one plan (see mcmc_plan_* in the C header).
+
+    `items` is a sequence of dicts with keys L, p, sweeps and optionally burn
+    (0), chains (1), n_temps (1), syndrome_id (position).  Syndromes are passed
+    as one flat uint8 device tensor: item i's n_stab(L_i) bytes after those of
+    items 0..i-1; corrections come back the same way (n_q(L_i) bytes each).
+    """
+
+    def __init__(self, items, seed, init=MCMC_INIT_MATCHING):
+        n = len(items)
+        arr = (_lib.Item * max(n, 1))()
+        syn_off = corr_off = 0
+        self.L = np.zeros(n, dtype=np.int32)
+        self.syn_offsets = np.zeros(n + 1, dtype=np.int64)
+        self.corr_offsets = np.zeros(n + 1, dtype=np.int64)
+        self.chain_offsets = np.zeros(n + 1, dtype=np.int64)
+        for i, it in enumerate(items):
+            L = int(it["L"])
+            nq, ns = geometry(L)
+            arr[i].L = L
+            arr[i].sweeps = int(it["sweeps"])
+            arr[i].burn = int(it.get("burn", 0))
+            arr[i].chains = int(it.get("chains", 1))
+            arr[i].n_temps = int(it.get("n_temps", 1))
+            arr[i].syndrome_id = int(it.get("syndrome_id", i)) & 0xFFFFFFFF
+            arr[i].p = float(it["p"])
+            arr[i].syn_offset = syn_off
+            arr[i].corr_offset = corr_off
+            self.L[i] = L
+            syn_off += ns
+            corr_off += nq
+            self.syn_offsets[i + 1] = syn_off
+            self.corr_offsets[i + 1] = corr_off
+            self.chain_offsets[i + 1] = self.chain_offsets[i] + 4 * arr[i].n_temps * arr[i].chains
+        self.n = n
+        self.syn_bytes, self.corr_bytes = syn_off, corr_off
+        h = ctypes.c_void_p()
+        _lib.check(_lib._lib().mcmc_plan_create(arr, n, int(seed) & ((1 << 64) - 1), int(init),
+                                                ctypes.byref(h)), "mcmc_plan_create")
+        self._h = h
+        tc, wb, tu = ctypes.c_int64(), ctypes.c_size_t(), ctypes.c_int64()
+        _lib.check(_lib._lib().mcmc_plan_info(h, ctypes.byref(tc), ctypes.byref(wb),
+                                              ctypes.byref(tu)), "mcmc_plan_info")
+        self.total_chains, self.workspace_bytes, self.total_updates = tc.value, wb.value, tu.value
+        self._ws = None
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib._lib().mcmc_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _outputs(self, dev, want_sums, want_correction):
+        torch = _torch()
+        out = {
+            "class_prob": torch.empty((self.n, 4), dtype=torch.float64, device=dev),
+            "mean_n": torch.empty((self.n, 4), dtype=torch.float64, device=dev),
+            "chosen": torch.empty((self.n,), dtype=torch.uint8, device=dev),
+        }
+        if want_correction:
+            out["correction"] = torch.empty((max(self.corr_bytes, 1),), dtype=torch.uint8, device=dev)
+        if want_sums:
+            out["sum_n"] = torch.empty((max(self.total_chains, 1),), dtype=torch.int64, device=dev)
+            out["accepts"] = torch.empty((max(self.total_chains, 1),), dtype=torch.int64, device=dev)
+        return out
+
+    def _args(self, syndromes, out):
+        torch = _torch()
+        if self._ws is None or self._ws.device != syndromes.device:
+            self._ws = torch.empty((max(self.workspace_bytes, 1),), dtype=torch.uint8,
+                                   device=syndromes.device)
+        return (self._h, _ptr(syndromes), _ptr(out["class_prob"]), _ptr(out["mean_n"]),
+                _ptr(out.get("sum_n")), _ptr(out.get("accepts")), _ptr(out["chosen"]),
+                _ptr(out.get("correction")), _ptr(self._ws), self._ws.numel(),
+                _stream(syndromes.device))
+
+    def _check_input(self, syndromes):
+        torch = _torch()
+        if syndromes.dtype != torch.uint8 or syndromes.dim() != 1 or \
+                syndromes.numel() < self.syn_bytes:
+            raise ValueError(f"syndromes must be a flat uint8 tensor of {self.syn_bytes} bytes")
+        return syndromes.contiguous()
+
+    def execute(self, syndromes, want_sums=False, want_correction=True, graph=False, out=None):
+        syndromes = self._check_input(syndromes)
+        if out is None:
+            out = self._outputs(syndromes.device, want_sums, want_correction)
+        fn = _lib._lib().mcmc_plan_graph_launch if graph else _lib._lib().mcmc_plan_execute
+        _lib.check(fn(*self._args(syndromes, out)),
+                   "mcmc_plan_graph_launch" if graph else "mcmc_plan_execute")
+        return out
+
+    def autotune(self, syndromes, cache_path=None):
+        syndromes = self._check_input(syndromes)
+        out = self._outputs(syndromes.device, False, True)
+        res = _lib.Tuning()
+        path = None if cache_path is None else str(cache_path).encode()
+        _lib.check(_lib._lib().mcmc_plan_autotune(*self._args(syndromes, out), path,
+                                                  ctypes.byref(res)), "mcmc_plan_autotune")
+        return {k: getattr(res, k) for k, _ in _lib.Tuning._fields_}
+
+    @property
+    def tuning(self):
+        t = _lib.Tuning()
+        _lib.check(_lib._lib().mcmc_plan_get_tuning(self._h, ctypes.byref(t)), "mcmc_plan_get_tuning")
+        return {k: getattr(t, k) for k, _ in _lib.Tuning._fields_}
+
+    @tuning.setter
+    def tuning(self, values):
+        t = _lib.Tuning(**values)
+        _lib.check(_lib._lib().mcmc_plan_set_tuning(self._h, ctypes.byref(t)), "mcmc_plan_set_tuning")

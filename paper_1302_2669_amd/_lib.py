@@ -41,6 +41,30 @@ class Params(ctypes.Structure):
     ]
 
 
+class Item(ctypes.Structure):
+    _fields_ = [
+        ("L", ctypes.c_int32),
+        ("sweeps", ctypes.c_int32),
+        ("burn", ctypes.c_int32),
+        ("chains", ctypes.c_int32),
+        ("n_temps", ctypes.c_int32),
+        ("syndrome_id", ctypes.c_uint32),
+        ("p", ctypes.c_double),
+        ("syn_offset", ctypes.c_int64),
+        ("corr_offset", ctypes.c_int64),
+    ]
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [
+        ("wg_narrow", ctypes.c_int32),
+        ("occ_narrow", ctypes.c_int32),
+        ("wg_wide", ctypes.c_int32),
+        ("occ_wide", ctypes.c_int32),
+        ("concurrent", ctypes.c_int32),
+    ]
+
+
 _P = ctypes.c_void_p
 _I32, _I64, _U32, _U64, _D, _SZ = (ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32,
                                    ctypes.c_uint64, ctypes.c_double, ctypes.c_size_t)
@@ -61,6 +85,16 @@ _SIGNATURES = {
     "mcmc_init_representatives": (ctypes.c_int, [_I32, _U32, _P, _I64, _P, _P]),
     "mcmc_unpack_chain_state": (ctypes.c_int, [_PPRM, _I64, _P, _P, _P, _P]),
     "mcmc_sample_errors": (ctypes.c_int, [_I32, _D, _U64, _P, _U32, _I64, _P, _P, _P, _P]),
+    "mcmc_plan_create": (ctypes.c_int, [ctypes.POINTER(Item), _I64, _U64, _U32,
+                                        ctypes.POINTER(_P)]),
+    "mcmc_plan_destroy": (ctypes.c_int, [_P]),
+    "mcmc_plan_info": (ctypes.c_int, [_P, ctypes.POINTER(_I64), _PSZ, ctypes.POINTER(_I64)]),
+    "mcmc_plan_get_tuning": (ctypes.c_int, [_P, ctypes.POINTER(Tuning)]),
+    "mcmc_plan_set_tuning": (ctypes.c_int, [_P, ctypes.POINTER(Tuning)]),
+    "mcmc_plan_execute": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P, _P, _P, _SZ, _P]),
+    "mcmc_plan_graph_launch": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P, _P, _P, _SZ, _P]),
+    "mcmc_plan_autotune": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P, _P, _P, _SZ, _P,
+                                          ctypes.c_char_p, ctypes.POINTER(Tuning)]),
 }
 
 _handle = None

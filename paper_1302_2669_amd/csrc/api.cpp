@@ -4,24 +4,58 @@
 #include <math.h>
 #include <string.h>
 
-#include <vector>
 
 #include "../../include/mcmcdec.h"
 #include "device_common.h"
+#include "host_common.h"
 #include "internal.h"
+
+#include <algorithm>
+
+namespace mcmc {
+
+int device_cus() {
+  static int cached[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0) dev = 0;
+  if (dev >= 64) dev = 63;
+  if (cached[dev] == 0) {
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        cus <= 0)
+      cus = 256;
+    cached[dev] = cus;
+  }
+  return cached[dev];
+}
+
+ChainStateLayout chain_state_layout(int L, int64_t T) {
+  ChainStateLayout c{};
+  size_t off = 0;
+  c.rows = off; off = align_up(off + (size_t)words_per_config(L) * T * sizeof(uint32_t));
+  c.n = off;    off = align_up(off + (size_t)T * sizeof(int32_t));
+  c.S = off;    off = align_up(off + (size_t)T * sizeof(int64_t));
+  c.A = off;    off = align_up(off + (size_t)T * sizeof(int64_t));
+  c.bytes = off;
+  return c;
+}
+
+hipError_t launch_chains(int range, const RunArgs& a, int waves, int wg, hipStream_t s) {
+  switch (range) {
+    case 0: return launch_chains_range<0>(a, waves, wg, s);
+    case 1: return launch_chains_range<1>(a, waves, wg, s);
+    case 2: return launch_chains_range<2>(a, waves, wg, s);
+    case 3: return launch_chains_range<3>(a, waves, wg, s);
+    case 4: return launch_chains_range<4>(a, waves, wg, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace mcmc
 
 namespace {
 
-constexpr size_t kAlign = 256;
-
-size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
-
-bool valid_L(int32_t L) { return L >= MCMC_L_MIN && L <= MCMC_L_MAX; }
-
-// beta_bar = -log((p/3)/(1-p))  (Eq. betaBar)
-double beta_bar(double p) { return -log((p / 3.0) / (1.0 - p)); }
-
-bool valid_p(double p) { return p > 0.0 && p < 0.75; }  // false for NaN
+using namespace mcmc;
 
 int check_params(const mcmc_params* prm, int64_t n) {
   if (!prm) return MCMC_EINVAL;
@@ -40,7 +74,7 @@ int check_params(const mcmc_params* prm, int64_t n) {
   } else if (prm->sweep_begin != 0) {
     return MCMC_EINVAL;
   }
-  // task count must fit the 1-D grid (blocks of 256 lanes, 32-bit block index)
+  // chains and tiles must fit the counters (tile index is 32-bit)
   const int64_t T = n * 4 * (int64_t)prm->n_temps * prm->chains;
   if (n > 0 && (T / n / 4 / prm->n_temps != prm->chains || T > ((int64_t)1 << 38)))
     return MCMC_ERANGE;
@@ -48,53 +82,26 @@ int check_params(const mcmc_params* prm, int64_t n) {
 }
 
 struct WorkspaceLayout {
-  size_t init_rows, init_n, S, A, n_final, corr_rows, bytes;
+  size_t queue, init_rows, init_n, S, A, n_final, final_rows, bytes;
 };
 
 WorkspaceLayout workspace_layout(const mcmc_params* prm, int64_t n) {
-  const int RW = mcmc::words_per_config(prm->L);
+  const int RW = words_per_config(prm->L);
   const int64_t T = n * 4 * (int64_t)prm->n_temps * prm->chains;
   WorkspaceLayout w{};
   size_t off = 0;
-  w.init_rows = off; off = align_up(off + (size_t)RW * n * 4 * sizeof(uint32_t));
-  w.init_n = off;    off = align_up(off + (size_t)n * 4 * sizeof(int32_t));
-  w.S = off;         off = align_up(off + (size_t)T * sizeof(int64_t));
-  w.A = off;         off = align_up(off + (size_t)T * sizeof(int64_t));
-  w.n_final = off;   off = align_up(off + (size_t)T * sizeof(int32_t));
-  w.corr_rows = off; off = align_up(off + (size_t)RW * n * 4 * sizeof(uint32_t));
+  w.queue = off;      off = align_up(off + 4 * sizeof(uint32_t));
+  w.init_rows = off;  off = align_up(off + (size_t)RW * n * 4 * sizeof(uint32_t));
+  w.init_n = off;     off = align_up(off + (size_t)n * 4 * sizeof(int32_t));
+  w.S = off;          off = align_up(off + (size_t)T * sizeof(int64_t));
+  w.A = off;          off = align_up(off + (size_t)T * sizeof(int64_t));
+  w.n_final = off;    off = align_up(off + (size_t)T * sizeof(int32_t));
+  w.final_rows = off; off = align_up(off + (size_t)RW * n * 4 * sizeof(uint32_t));
   w.bytes = off;
   return w;
 }
 
-void fill_table(double p, int32_t K, uint32_t* out) {
-  const double bb = beta_bar(p);
-  for (int k = 1; k <= K; ++k) {
-    const double beta = ((double)k * bb) / (double)K;
-    for (int d = 1; d <= 4; ++d) {
-      const double w = exp(-(beta * (double)d));
-      out[(k - 1) * 4 + (d - 1)] = (uint32_t)floor(ldexp(w, 32));
-    }
-  }
-}
-
-int hip_status(hipError_t e) { return e == hipSuccess ? MCMC_OK : MCMC_EDEVICE; }
-
 }  // namespace
-
-namespace mcmc {
-
-ChainStateLayout chain_state_layout(int L, int64_t T) {
-  ChainStateLayout c{};
-  size_t off = 0;
-  c.rows = off; off = align_up(off + (size_t)words_per_config(L) * T * sizeof(uint32_t));
-  c.n = off;    off = align_up(off + (size_t)T * sizeof(int32_t));
-  c.S = off;    off = align_up(off + (size_t)T * sizeof(int64_t));
-  c.A = off;    off = align_up(off + (size_t)T * sizeof(int64_t));
-  c.bytes = off;
-  return c;
-}
-
-}  // namespace mcmc
 
 extern "C" {
 
@@ -171,7 +178,7 @@ int mcmc_chain_state_size(const mcmc_params* prm, int64_t n, size_t* bytes) {
   const int st = check_params(prm, n);
   if (st != MCMC_OK) return st;
   const int64_t T = n * 4 * (int64_t)prm->n_temps * prm->chains;
-  *bytes = mcmc::chain_state_layout(prm->L, T).bytes;
+  *bytes = chain_state_layout(prm->L, T).bytes;
   return MCMC_OK;
 }
 
@@ -198,41 +205,56 @@ int mcmc_decode_batch(const uint8_t* syndromes, const uint32_t* syndrome_ids, in
   char* ws = (char*)workspace;
   const int L = prm->L;
   const int64_t T = n * 4 * (int64_t)prm->n_temps * prm->chains;
+  uint32_t* queue = (uint32_t*)(ws + wl.queue);
   uint32_t* init_rows = (uint32_t*)(ws + wl.init_rows);
   int32_t* init_n = (int32_t*)(ws + wl.init_n);
   int64_t* S = sum_n ? sum_n : (int64_t*)(ws + wl.S);
   int64_t* A = accepts ? accepts : (int64_t*)(ws + wl.A);
   int32_t* nf = (int32_t*)(ws + wl.n_final);
-  uint32_t* corr_rows = correction ? (uint32_t*)(ws + wl.corr_rows) : nullptr;
+  uint32_t* final_rows = correction ? (uint32_t*)(ws + wl.final_rows) : nullptr;
 
+  st = hip_status(launch_zero(queue, 4, s));
+  if (st != MCMC_OK) return st;
   if (!resume) {
-    st = hip_status(prm->init == MCMC_INIT_MATCHING
-                        ? mcmc::launch_init_matching(L, syndromes, n, init_rows, init_n, nullptr, s)
-                        : mcmc::launch_init(L, syndromes, n, init_rows, init_n, nullptr, s));
+    StartArgs sa{};
+    sa.syn = syndromes;
+    sa.n = n;
+    sa.L = L;
+    sa.rows = init_rows;
+    sa.weights = init_n;
+    st = hip_status(prm->init == MCMC_INIT_MATCHING ? launch_init_matching(sa, s)
+                                                    : launch_init(sa, s));
     if (st != MCMC_OK) return st;
   }
 
-  mcmc::ChainArgs a{};
-  a.init_rows = init_rows;
-  a.init_n = init_n;
+  RunArgs a{};
+  a.g0.L = L;
+  a.g0.K = prm->n_temps;
+  a.g0.C = prm->chains;
+  a.g0.burn = prm->burn;
+  a.g0.sweep_begin = prm->sweep_begin;
+  a.g0.sweep_end = prm->burn + prm->sweeps;
+  a.g0.first_item = 0;
+  a.g0.n_items = (int32_t)n;
+  a.g0.n_tasks = T;
   a.syndrome_ids = syndrome_ids;
-  a.n = n;
-  a.K = prm->n_temps;
-  a.C = prm->chains;
-  a.burn = prm->burn;
-  a.sweep_begin = prm->sweep_begin;
-  a.sweep_end = prm->burn + prm->sweeps;
+  fill_table(prm->p, prm->n_temps, &a.table0[0][0]);
+  a.n_tiles = (T + TILE - 1) / TILE;
+  a.queue = queue;
+  a.lmin = a.lmax = L;
   a.k0 = (uint32_t)(prm->seed & 0xFFFFFFFFull);
   a.k1 = (uint32_t)(prm->seed >> 32);
-  fill_table(prm->p, prm->n_temps, &a.table[0][0]);
+  a.init_rows = init_rows;
+  a.init_n = init_n;
   a.S_out = S;
   a.A_out = A;
   a.n_out = nf;
-  a.corr_rows = corr_rows;
-  a.trace = trace_len > 0 ? trace : nullptr;
+  a.final_rows = final_rows;
+  a.total_chains = T;
+  a.trace = (do_trace && trace_len > 0) ? trace : nullptr;
   a.trace_len = trace_len;
   if (chain_state) {
-    const mcmc::ChainStateLayout cl = mcmc::chain_state_layout(L, T);
+    const ChainStateLayout cl = chain_state_layout(L, T);
     char* cs = (char*)chain_state;
     a.state_rows = (uint32_t*)(cs + cl.rows);
     if (resume) {
@@ -242,11 +264,13 @@ int mcmc_decode_batch(const uint8_t* syndromes, const uint32_t* syndrome_ids, in
       a.resume_A = (const int64_t*)(cs + cl.A);
     }
   }
-  st = hip_status(mcmc::launch_chain(L, a, s, do_trace && trace_len > 0, resume));
+  const int range = range_of(L);
+  const int64_t waves = std::min<int64_t>(a.n_tiles, default_waves(range, device_cus()));
+  st = hip_status(launch_chains(range, a, (int)waves, 256, s));
   if (st != MCMC_OK) return st;
 
   if (chain_state) {  // n, S, A of every chain next to the rows
-    const mcmc::ChainStateLayout cl = mcmc::chain_state_layout(L, T);
+    const ChainStateLayout cl = chain_state_layout(L, T);
     char* cs = (char*)chain_state;
     st = hip_status(hipMemcpyAsync(cs + cl.n, nf, (size_t)T * sizeof(int32_t),
                                    hipMemcpyDeviceToDevice, s));
@@ -259,25 +283,19 @@ int mcmc_decode_batch(const uint8_t* syndromes, const uint32_t* syndrome_ids, in
     if (st != MCMC_OK) return st;
   }
 
-  mcmc::DecideArgs d{};
+  DecideArgs d{};
+  d.g0 = a.g0;
+  d.beta_bar = beta_bar(prm->p);
+  d.ln2 = log(2.0);
+  d.n = n;
   d.S = S;
   d.n_final = nf;
-  d.corr_rows = corr_rows;
-  d.n = n;
-  d.K = prm->n_temps;
-  d.C = prm->chains;
-  d.L = L;
-  d.sweeps = prm->sweeps;
-  d.beta_bar = beta_bar(prm->p);
-  const int nq = 2 * L * L - 2 * L + 1;
-  const int nstab = 2 * L * (L - 1);
-  d.f0 = 0.75 * (double)nq;
-  d.log_z0 = (double)nstab * log(2.0);
+  d.final_rows = final_rows;
   d.class_prob = class_prob;
   d.mean_n = mean_n;
   d.chosen = chosen;
   d.correction = correction;
-  return hip_status(mcmc::launch_decide(d, s));
+  return hip_status(launch_decide(d, s));
 }
 
 int mcmc_init_representatives(int32_t L, uint32_t init, const uint8_t* syndromes, int64_t n,
@@ -288,9 +306,12 @@ int mcmc_init_representatives(int32_t L, uint32_t init, const uint8_t* syndromes
   if (n == 0) return MCMC_OK;
   if (!syndromes || !reps) return MCMC_EINVAL;
   hipStream_t s = (hipStream_t)stream;
-  return hip_status(init == MCMC_INIT_MATCHING
-                        ? mcmc::launch_init_matching(L, syndromes, n, nullptr, nullptr, reps, s)
-                        : mcmc::launch_init(L, syndromes, n, nullptr, nullptr, reps, s));
+  StartArgs sa{};
+  sa.syn = syndromes;
+  sa.n = n;
+  sa.L = L;
+  sa.bytes = reps;
+  return hip_status(init == MCMC_INIT_MATCHING ? launch_init_matching(sa, s) : launch_init(sa, s));
 }
 
 int mcmc_unpack_chain_state(const mcmc_params* prm, int64_t n, const void* chain_state,
@@ -300,8 +321,8 @@ int mcmc_unpack_chain_state(const mcmc_params* prm, int64_t n, const void* chain
   if (n == 0) return MCMC_OK;
   if (!chain_state) return MCMC_EINVAL;
   const int64_t T = n * 4 * (int64_t)prm->n_temps * prm->chains;
-  const mcmc::ChainStateLayout cl = mcmc::chain_state_layout(prm->L, T);
-  return hip_status(mcmc::launch_unpack(prm->L, (const uint32_t*)((const char*)chain_state + cl.rows),
+  const ChainStateLayout cl = chain_state_layout(prm->L, T);
+  return hip_status(launch_unpack(prm->L, (const uint32_t*)((const char*)chain_state + cl.rows),
                                         T, T, states, weights, (hipStream_t)stream));
 }
 
@@ -313,7 +334,7 @@ int mcmc_sample_errors(int32_t L, double p, uint64_t seed, const uint32_t* sampl
   if (!syndromes || !true_class) return MCMC_EINVAL;
   if (n > 0x7FFFFFFF) return MCMC_ERANGE;
   const uint32_t thr = (uint32_t)floor(ldexp(p, 32));
-  return hip_status(mcmc::launch_sample(L, thr, (uint32_t)(seed & 0xFFFFFFFFull),
+  return hip_status(launch_sample(L, thr, (uint32_t)(seed & 0xFFFFFFFFull),
                                         (uint32_t)(seed >> 32), sample_ids, id_base, n, syndromes,
                                         true_class, errors, (hipStream_t)stream));
 }

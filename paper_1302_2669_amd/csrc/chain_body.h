@@ -47,8 +47,8 @@ __device__ __forceinline__ uint32_t nibble_sum(uint32_t v, uint32_t acc) {
   return __builtin_amdgcn_sad_u8(b, 0u, acc);
 }
 
-// acc = 2 * acc + (u < thr): the comparison's borrow lands directly in the
-// running bit mask (site order is reversed by the caller).
+// acc = 2 * acc + (u < thr): the comparison result lands directly in the
+// running bit mask (the first site pushed ends in the highest bit).
 __device__ __forceinline__ uint32_t push_accept(uint32_t acc, uint32_t u, uint32_t thr) {
   asm("v_cmp_lt_u32 vcc, %1, %2\n\tv_addc_co_u32 %0, vcc, %0, %0, vcc"
       : "+v"(acc)
@@ -107,35 +107,50 @@ __device__ __forceinline__ void row_fence(uint32_t (&st)[R][W], int32_t& dn, int
 #define MCMC_ROW_FENCE() row_fence(st, dn, acc_total)
 #endif
 
-#ifndef MCMC_CHAIN_WAVES_PER_EU
-#define MCMC_CHAIN_WAVES_PER_EU 5
-#endif
+// The item (syndrome) behind index `idx` of a group: from the plan's table, or
+// implicit for a uniform batch.
+__device__ __forceinline__ ItemDesc item_of(const RunArgs& a, int64_t idx, int RW) {
+  if (a.items) return a.items[idx];
+  ItemDesc it;
+  it.orig = idx;
+  it.syn_off = 0;
+  it.rows_off = idx * RW * 4;
+  it.chain_off = idx * 4 * (int64_t)a.g0.K * a.g0.C;
+  it.corr_off = 0;
+  it.table_off = 0;
+  it.beta_bar = 0.0;
+  it.sid = a.syndrome_ids ? a.syndrome_ids[idx] : (uint32_t)idx;
+  it.group = 0;
+  return it;
+}
 
-template <int L, bool TRACE>
-__global__ void __launch_bounds__(256)
-__attribute__((amdgpu_waves_per_eu(MCMC_CHAIN_WAVES_PER_EU)))
-chain_kernel(const ChainArgs a, const int64_t T) {
+// One chain (lane) of group g: task t of the group.  lds_tbl is this
+// workgroup's threshold table, column `col` belongs to this lane.
+template <int L>
+__device__ __forceinline__ void run_chain(const RunArgs& a, const GroupDesc& g, int64_t t,
+                                          uint32_t (*lds_tbl)[256], const int col) {
   using G = Geo<L>;
   constexpr int R = G::R, W = G::W, S = G::S;
-  __shared__ uint32_t lds_tbl[9][256];
+  const int lane = col;
+  const int K = g.K, C = g.C;
 
-  const int lane = threadIdx.x;
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + lane;
-  if (t >= T) return;
-
-  // task -> (syndrome, class, temperature, replica)
-  const int chain = (int)(t % a.C);
-  int64_t rest = t / a.C;
-  const int kt = (int)(rest % a.K);
-  rest /= a.K;
-  const int cls = (int)(rest & 3);
-  const int64_t syn = rest >> 2;
-  const int64_t sc = syn * 4 + cls;
-  const int64_t n4 = a.n * 4;
+  // task -> (item, class, temperature, replica)
+  const int64_t per_item = 4 * (int64_t)K * C;
+  const int64_t item_local = t / per_item;
+  const int rem = (int)(t - item_local * per_item);
+  const int chain = rem % C;
+  const int kt = (rem / C) % K;
+  const int cls = rem / (C * K);
+  const ItemDesc it = item_of(a, g.first_item + item_local, G::RW);
+  const int64_t out = it.chain_off + rem;   // per-chain output slot
 
   // this lane's thresholds: entry t = Delta + 4; t <= 4 is never read
 #pragma unroll
-  for (int e = 0; e < 9; ++e) lds_tbl[e][lane] = e <= 4 ? 0xFFFFFFFFu : a.table[kt][e - 5];
+  for (int e = 0; e < 9; ++e) {
+    uint32_t v = 0xFFFFFFFFu;
+    if (e > 4) v = a.tables ? a.tables[it.table_off + kt * 4 + (e - 5)] : a.table0[kt][e - 5];
+    lds_tbl[e][lane] = v;
+  }
 
   uint32_t st[R][W];
   int32_t n;
@@ -144,26 +159,26 @@ chain_kernel(const ChainArgs a, const int64_t T) {
 #pragma unroll
     for (int r = 0; r < R; ++r)
 #pragma unroll
-      for (int w = 0; w < W; ++w) st[r][w] = a.resume_rows[(int64_t)(r * W + w) * T + t];
-    n = a.resume_n[t];
-    Ssum = a.resume_S[t];
-    Acnt = a.resume_A[t];
+      for (int w = 0; w < W; ++w)
+        st[r][w] = a.resume_rows[(int64_t)(r * W + w) * a.total_chains + out];
+    n = a.resume_n[out];
+    Ssum = a.resume_S[out];
+    Acnt = a.resume_A[out];
   } else {
 #pragma unroll
     for (int r = 0; r < R; ++r)
 #pragma unroll
-      for (int w = 0; w < W; ++w) st[r][w] = a.init_rows[(int64_t)(r * W + w) * n4 + sc];
-    n = a.init_n[sc];
+      for (int w = 0; w < W; ++w) st[r][w] = a.init_rows[it.rows_off + (r * W + w) * 4 + cls];
+    n = a.init_n[it.orig * 4 + cls];
   }
 
   ChainRng rng;
-  const uint32_t sid = a.syndrome_ids ? a.syndrome_ids[syn] : (uint32_t)syn;
-  rng.init(a.k0, a.k1, sid, ((uint32_t)cls << 28) | ((uint32_t)(kt + 1) << 20) | (uint32_t)chain);
+  rng.init(a.k0, a.k1, it.sid, ((uint32_t)cls << 28) | ((uint32_t)(kt + 1) << 20) | (uint32_t)chain);
 
-  int16_t* trace = TRACE ? a.trace + t * a.trace_len : nullptr;
+  int16_t* trace = a.trace ? a.trace + out * a.trace_len : nullptr;
   int64_t tpos = 0;
 
-  for (int sweep = a.sweep_begin; sweep < a.sweep_end; ++sweep) {
+  for (int sweep = g.sweep_begin; sweep < g.sweep_end; ++sweep) {
     rng.begin_sweep((uint32_t)sweep);
     uint4 blk = make_uint4(0, 0, 0, 0);
     int32_t dn = 0;     // weight change of the current phase
@@ -172,8 +187,8 @@ chain_kernel(const ChainArgs a, const int64_t T) {
     auto end_phase = [&]() {
       n += dn;
       dn = 0;
-      if (sweep >= a.burn) Ssum += n;
-      if constexpr (TRACE) trace[tpos++] = (int16_t)n;
+      if (sweep >= g.burn) Ssum += n;
+      if (trace) trace[tpos++] = (int16_t)n;
     };
 
     // Accept decisions of one row's sites (nibble m of `sum` holds Delta n + 4
@@ -185,21 +200,19 @@ chain_kernel(const ChainArgs a, const int64_t T) {
                           uint32_t (&acc)[W]) {
       constexpr int par = decltype(PAR)::value, nsite = decltype(NSITE)::value;
       constexpr int d0 = decltype(D0)::value, limit = decltype(LIMIT)::value;
-      uint32_t uu[nsite], th[nsite];
+      // bit (nsite-1-m) of `rbits`: u_m < A[Delta_m], pushed in site order so
+      // that only one draw and one threshold are live at a time
+      uint32_t rbits = 0;
       static_for<nsite>([&](auto MM) {
         constexpr int m = decltype(MM)::value;
         constexpr int j = par + 2 * m;
         constexpr int w = j / 16, nib = (j % 16) / 2;
         constexpr int d = d0 + m;
         if constexpr ((d & 3) == 0) blk = rng.template block<d / 4>();
-        uu[m] = word_of(blk, d & 3);
-        th[m] = lds_tbl[(sum[w] >> (4 * nib)) & 15u][lane];
+        const uint32_t thr = lds_tbl[(sum[w] >> (4 * nib)) & 15u][lane];
+        rbits = push_accept(rbits, word_of(blk, d & 3), thr);
       });
-      uint32_t bits = 0;  // bit m: u_m < A[Delta_m]
-      static_for<nsite>([&](auto MM) {
-        constexpr int m = nsite - 1 - decltype(MM)::value;
-        bits = push_accept(bits, uu[m], th[m]);
-      });
+      const uint32_t bits = __builtin_bitreverse32(rbits) >> (32 - nsite);  // bit m: site m
       static_for<W>([&](auto WW) {
         constexpr int w = decltype(WW)::value;
         constexpr uint32_t sites = site_nibbles(par, limit, w);
@@ -294,34 +307,67 @@ chain_kernel(const ChainArgs a, const int64_t T) {
     Acnt += acc_total;
   }
 
-  a.S_out[t] = Ssum;
-  a.A_out[t] = Acnt;
-  a.n_out[t] = n;
+  a.S_out[out] = Ssum;
+  a.A_out[out] = Acnt;
+  a.n_out[out] = n;
   if (a.state_rows) {
 #pragma unroll
     for (int r = 0; r < R; ++r)
 #pragma unroll
-      for (int w = 0; w < W; ++w) a.state_rows[(int64_t)(r * W + w) * T + t] = st[r][w];
+      for (int w = 0; w < W; ++w) a.state_rows[(int64_t)(r * W + w) * a.total_chains + out] = st[r][w];
   }
-  if (a.corr_rows && chain == 0 && kt == a.K - 1) {
+  if (a.final_rows && chain == 0 && kt == K - 1) {
 #pragma unroll
     for (int r = 0; r < R; ++r)
 #pragma unroll
-      for (int w = 0; w < W; ++w) a.corr_rows[(int64_t)(r * W + w) * n4 + sc] = st[r][w];
+      for (int w = 0; w < W; ++w) a.final_rows[it.rows_off + (r * W + w) * 4 + cls] = st[r][w];
   }
 }
 
-template <int L>
-hipError_t launch_chain_L(const ChainArgs& a, hipStream_t s, bool trace, bool /*resume*/) {
-  const int64_t T = a.n * 4 * a.K * a.C;
-  if (T == 0) return hipSuccess;
-  const dim3 block(256);
-  const dim3 grid((unsigned)((T + 255) / 256));
-  if (trace)
-    hipLaunchKernelGGL((chain_kernel<L, true>), grid, block, 0, s, a, T);
-  else
-    hipLaunchKernelGGL((chain_kernel<L, false>), grid, block, 0, s, a, T);
-  return hipGetLastError();
+
+// Persistent tile loop over the L range [LMIN, LMAX]: every wave takes the
+// next tile from the launch's queue (tiles are ordered longest first by the
+// planner) and runs the code of that tile's L; tiles of another L range are
+// skipped.  Every wave leaves once the queue is exhausted.
+template <int LMIN, int LMAX>
+__device__ __forceinline__ void dispatch_tile(const RunArgs& a, const GroupDesc& g, int L, int64_t t,
+                                              uint32_t (*lds_tbl)[256], int col) {
+  if constexpr (LMIN <= LMAX) {
+    if (L == LMIN) {
+      run_chain<LMIN>(a, g, t, lds_tbl, col);
+      return;
+    }
+    dispatch_tile<LMIN + 1, LMAX>(a, g, L, t, lds_tbl, col);
+  }
+}
+
+template <int LMIN, int LMAX>
+__device__ __forceinline__ void chains_persistent(const RunArgs& a) {
+  __shared__ uint32_t lds_tbl[9][256];
+  const int col = threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  while (true) {
+    uint32_t tile = 0;
+    if (lane == 0) tile = atomicAdd(a.queue, 1u);
+    tile = __builtin_amdgcn_readfirstlane(tile);  // lane 0 is active: the loop is wave-uniform
+    if ((int64_t)tile >= a.n_tiles) break;
+    GroupDesc g;
+    int L;
+    int64_t first;
+    if (a.tiles) {
+      const TileDesc td = a.tiles[tile];
+      g = a.groups[td.group];
+      L = td.L;
+      first = td.first_task;
+    } else {
+      g = a.g0;
+      L = a.g0.L;
+      first = (int64_t)tile * TILE;
+    }
+    if (L < LMIN || L > LMAX) continue;
+    const int64_t t = first + lane;
+    if (t < g.n_tasks) dispatch_tile<LMIN, LMAX>(a, g, L, t, lds_tbl, col);
+  }
 }
 
 }  // namespace mcmc

@@ -16,52 +16,122 @@ struct ChainStateLayout {
 };
 ChainStateLayout chain_state_layout(int L, int64_t T);
 
-struct ChainArgs {
-  const uint32_t* init_rows;   // [RW][n*4] word-major class starts
-  const int32_t* init_n;       // [n*4] their weights
-  const uint32_t* syndrome_ids;// [n] or nullptr (=> index)
-  int64_t n;                   // syndromes
-  int32_t K, C;                // temperatures, chains per class and temperature
-  int32_t burn, sweep_begin, sweep_end;
-  uint32_t k0, k1;             // Philox key
-  uint32_t table[MCMC_TEMPS_MAX][4];  // acceptance thresholds A_k[1..4], row k-1
-  int64_t* S_out;              // [T]
-  int64_t* A_out;              // [T]
-  int32_t* n_out;              // [T]
-  uint32_t* state_rows;        // [RW][T] final configurations, or nullptr
-  const uint32_t* resume_rows; // [RW][T] with resume
+// ---------------------------------------------------------------------------
+// Work description of a chain launch.  Chains are grouped by everything that
+// shapes the kernel's code and loop (L, temperatures, chains per class, sweep
+// range); a group's chains are numbered item-major:
+//   task = item_local * (4*K*C) + (cls*K + k)*C + chain.
+// A wave takes a tile of 64 consecutive tasks of one group.  Uniform batches
+// (mcmc_decode_batch) describe one group implicitly; mixed batches carry
+// explicit group, item and tile tables built by the host planner.
+// ---------------------------------------------------------------------------
+struct GroupDesc {
+  int32_t L, K, C, burn, sweep_begin, sweep_end;
+  int32_t first_item, n_items;  // items of the group in plan order
+  int64_t n_tasks;              // n_items * 4 * K * C
+};
+
+struct ItemDesc {               // one syndrome, plan order
+  int64_t orig;                 // caller's index (outputs indexed by it)
+  int64_t syn_off;              // byte offset of its syndrome in the input
+  int64_t rows_off;             // word offset of its [RW][4] start / final-row block
+  int64_t chain_off;            // first per-chain output slot
+  int64_t corr_off;             // byte offset of its correction output
+  int64_t table_off;            // uint32 offset of its [K][4] thresholds
+  double beta_bar;
+  uint32_t sid;                 // Philox counter word 2
+  int32_t group;
+};
+
+struct TileDesc {
+  int32_t group;
+  int32_t L;
+  int64_t first_task;           // within the group
+};
+
+constexpr int TILE = 64;        // tasks per tile (one wave)
+
+struct RunArgs {
+  // explicit plan, or all nullptr for a uniform batch
+  const GroupDesc* groups;
+  const ItemDesc* items;
+  const TileDesc* tiles;
+  const uint32_t* tables;
+  // uniform batch: group g0 with items s = 0..n-1
+  GroupDesc g0;
+  const uint32_t* syndrome_ids;  // [n] or nullptr (=> s)
+  uint32_t table0[MCMC_TEMPS_MAX][4];
+  int64_t n_tiles;
+  uint32_t* queue;               // tile counter of this launch, zero at start
+  int32_t lmin, lmax;            // L range compiled into the launched kernel
+  uint32_t k0, k1;               // Philox key
+  const uint32_t* init_rows;     // class starts, [RW][4] block per item
+  const int32_t* init_n;         // [orig*4 + cls]
+  int64_t* S_out;                // per chain (chain_off + rem)
+  int64_t* A_out;
+  int32_t* n_out;
+  uint32_t* final_rows;          // chain 0 at k = K of every class, [RW][4] per item, or nullptr
+  int64_t total_chains;          // uniform batch: chain-state stride
+  uint32_t* state_rows;          // uniform batch only: [RW][total_chains] final states, or nullptr
+  const uint32_t* resume_rows;   // uniform batch only
   const int32_t* resume_n;
   const int64_t* resume_S;
   const int64_t* resume_A;
-  uint32_t* corr_rows;         // [RW][n*4]: chain 0 at k = K of every class, or nullptr
-  int16_t* trace;              // [T][trace_len] or nullptr
+  int16_t* trace;                // [chain][trace_len] or nullptr
   int64_t trace_len;
 };
 
-template <int L>
-hipError_t launch_chain_L(const ChainArgs& a, hipStream_t s, bool trace, bool resume);
-hipError_t launch_chain(int L, const ChainArgs& a, hipStream_t s, bool trace, bool resume);
+// Persistent chain kernels, one per L range, each with the register budget
+// of its largest code: L 2..13 (6 waves per SIMD), 14..16 (5), and the
+// two-word-row ranges 17..19, 20..22, 23..25 (3).  `waves` is the persistent
+// grid in waves, `wg` the workgroup size (64, 128 or 256).
+constexpr int N_RANGES = 5;
+constexpr int RANGE_LO[N_RANGES] = {2, 14, 17, 20, 23};
+constexpr int RANGE_HI[N_RANGES] = {13, 16, 19, 22, 25};
+constexpr int RANGE_WAVES[N_RANGES] = {6, 5, 3, 3, 3};
+inline int range_of(int L) {
+  for (int r = 0; r < N_RANGES; ++r)
+    if (L >= RANGE_LO[r] && L <= RANGE_HI[r]) return r;
+  return -1;
+}
+inline bool range_is_wide(int r) { return RANGE_LO[r] > 16; }
+template <int R>
+hipError_t launch_chains_range(const RunArgs& a, int waves, int wg, hipStream_t s);
+hipError_t launch_chains(int range, const RunArgs& a, int waves, int wg, hipStream_t s);
+hipError_t launch_zero(uint32_t* p, int64_t n, hipStream_t s);
 
-// rows ([RW][n*4] word-major), weights ([n*4]) and bytes ([n*4][n_q]) may each be nullptr.
-hipError_t launch_init(int L, const uint8_t* syn, int64_t n, uint32_t* rows, int32_t* weights,
-                       uint8_t* bytes, hipStream_t s);
-// Greedy-matching class starts, same outputs as launch_init.
-hipError_t launch_init_matching(int L, const uint8_t* syn, int64_t n, uint32_t* rows,
-                                int32_t* weights, uint8_t* bytes, hipStream_t s);
+// Class starts of syndromes given either implicitly (L, n: syndrome s at
+// s*n_stab, block at s*RW*4) or by the plan's item table.
+struct StartArgs {
+  const uint8_t* syn;
+  const ItemDesc* items;         // nullptr => implicit
+  const GroupDesc* groups;
+  int64_t n;
+  int32_t L;                     // implicit only
+  uint32_t* rows;                // [RW][4] per item, or nullptr
+  int32_t* weights;              // [orig*4 + cls], or nullptr
+  uint8_t* bytes;                // [orig][4][n_q] (implicit only), or nullptr
+};
+hipError_t launch_init(const StartArgs& a, hipStream_t s);
+hipError_t launch_init_matching(const StartArgs& a, hipStream_t s);
+
 hipError_t launch_unpack(int L, const uint32_t* rows, int64_t count, int64_t stride,
                          uint8_t* out, int32_t* weights, hipStream_t s);
 
 struct DecideArgs {
-  const int64_t* S;            // [n][4][K][C]
-  const int32_t* n_final;      // [n][4][K][C]
-  const uint32_t* corr_rows;   // [RW][n*4] or nullptr
+  const ItemDesc* items;       // nullptr => uniform batch (g0, beta_bar)
+  const GroupDesc* groups;
+  GroupDesc g0;
+  double beta_bar;             // uniform batch
+  double ln2;                  // log 2 from the host's libm
   int64_t n;
-  int32_t K, C, L, sweeps;
-  double beta_bar, f0, log_z0; // f0 = 3/4 n_q, log_z0 = n_stab log 2
-  double* class_prob;          // [n][4]
+  const int64_t* S;            // per chain
+  const int32_t* n_final;      // per chain
+  const uint32_t* final_rows;  // [RW][4] per item, or nullptr
+  double* class_prob;          // [n][4] (caller's index)
   double* mean_n;              // [n][4] or nullptr
   uint8_t* chosen;             // [n]
-  uint8_t* correction;         // [n][n_q] or nullptr
+  uint8_t* correction;         // uniform: [n][n_q]; plan: at item corr_off; or nullptr
 };
 hipError_t launch_decide(const DecideArgs& a, hipStream_t s);
 

@@ -18,19 +18,39 @@ namespace mcmc {
 // class c multiplies it by X-bar (X on row 0) if bx != c&1 and by Z-bar
 // (Z on column 0) if bz != c>>1.  One thread per (syndrome, class).
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) init_kernel(int L, const uint8_t* __restrict__ syn,
-                                                   int64_t n, uint32_t* __restrict__ rows,
-                                                   int32_t* __restrict__ weights,
-                                                   uint8_t* __restrict__ bytes) {
+// Syndrome s of a start launch: its L, input bytes, start block and caller index.
+struct StartItem {
+  int L;
+  const uint8_t* sy;
+  int64_t rows_off, orig;
+};
+__device__ __forceinline__ StartItem start_item(const StartArgs& a, int64_t s) {
+  StartItem r;
+  if (a.items) {
+    const ItemDesc it = a.items[s];
+    r.L = a.groups[it.group].L;
+    r.sy = a.syn + it.syn_off;
+    r.rows_off = it.rows_off;
+    r.orig = it.orig;
+  } else {
+    r.L = a.L;
+    r.sy = a.syn + s * (int64_t)(2 * a.L * (a.L - 1));
+    r.rows_off = s * (int64_t)words_per_config(a.L) * 4;
+    r.orig = s;
+  }
+  return r;
+}
+
+__global__ void __launch_bounds__(256) init_kernel(const StartArgs a) {
   const int64_t sc = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (sc >= n * 4) return;
-  const int64_t s = sc >> 2;
+  if (sc >= a.n * 4) return;
   const int cls = (int)(sc & 3);
+  const StartItem si = start_item(a, sc >> 2);
+  const int L = si.L;
   const int nstab = 2 * L * (L - 1);
   const int nstar = L * (L - 1);
-  const uint8_t* sy = syn + s * nstab;
+  const uint8_t* sy = si.sy;
   const int W = words_per_row(L);
-  const int64_t n4 = n * 4;
 
   int bx = 0, bz = 0;
   for (int k = 0; k < nstab; ++k) {
@@ -55,15 +75,15 @@ __global__ void __launch_bounds__(256) init_kernel(int L, const uint8_t* __restr
     if (i == 0 && xbar) xbits ^= (1u << L) - 1u;
     if (zbar) zbits ^= 1u;
     weight += __builtin_popcount(xbits | zbits);
-    if (bytes) {  // qubit (2i, 2k) is number i*side + k; odd-row qubits are I
+    if (a.bytes) {  // qubit (2i, 2k) is number i*side + k; odd-row qubits are I
       const int side = 2 * L - 1, nq = 2 * L * L - 2 * L + 1;
-      uint8_t* out = bytes + sc * nq;
+      uint8_t* out = a.bytes + (si.orig * 4 + cls) * nq;
       for (int k = 0; k < L; ++k)
         out[i * side + k] = (uint8_t)(((xbits >> k) & 1u) | (((zbits >> k) & 1u) << 1));
       if (i >= 1)
         for (int f = 0; f < L - 1; ++f) out[(i - 1) * side + L + f] = 0;
     }
-    if (!rows) continue;
+    if (!a.rows) continue;
     for (int w = 0; w < W; ++w) {
       uint32_t word = 0;
       for (int f = 0; f < 16; ++f) {
@@ -72,22 +92,33 @@ __global__ void __launch_bounds__(256) init_kernel(int L, const uint8_t* __restr
         if (k < L) code = ((xbits >> k) & 1u) | (((zbits >> k) & 1u) << 1);
         word |= code << (2 * f);
       }
-      rows[(int64_t)((2 * i) * W + w) * n4 + sc] = word;
+      a.rows[si.rows_off + ((2 * i) * W + w) * 4 + cls] = word;
     }
     if (i >= 1) {  // odd row 2i-1: empty, padding beyond L-1 fields
       for (int w = 0; w < W; ++w)
-        rows[(int64_t)((2 * i - 1) * W + w) * n4 + sc] = ~field_mask(L - 1, w);
+        a.rows[si.rows_off + ((2 * i - 1) * W + w) * 4 + cls] = ~field_mask(L - 1, w);
     }
   }
-  if (weights) weights[sc] = weight;
+  if (a.weights) a.weights[si.orig * 4 + cls] = weight;
 }
 
-hipError_t launch_init(int L, const uint8_t* syn, int64_t n, uint32_t* rows, int32_t* weights,
-                       uint8_t* bytes, hipStream_t s) {
+hipError_t launch_init(const StartArgs& a, hipStream_t s) {
+  if (a.n == 0) return hipSuccess;
+  const int64_t work = a.n * 4;
+  hipLaunchKernelGGL(init_kernel, dim3((unsigned)((work + 255) / 256)), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+__global__ void __launch_bounds__(256) zero_kernel(uint32_t* p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0u;
+}
+
+// Clears a small device buffer with a kernel (no memset node, so that the
+// sequence can be captured into a graph and replayed).
+hipError_t launch_zero(uint32_t* p, int64_t n, hipStream_t s) {
   if (n == 0) return hipSuccess;
-  const int64_t work = n * 4;
-  hipLaunchKernelGGL(init_kernel, dim3((unsigned)((work + 255) / 256)), dim3(256), 0, s, L, syn, n,
-                     rows, weights, bytes);
+  hipLaunchKernelGGL(zero_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n);
   return hipGetLastError();
 }
 
@@ -139,14 +170,36 @@ hipError_t launch_unpack(int L, const uint32_t* rows, int64_t count, int64_t str
 __global__ void __launch_bounds__(128) decide_kernel(const DecideArgs a) {
   const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= a.n) return;
-  const int K = a.K, C = a.C;
-  const bool counted = a.sweeps > 0;
-  const double denom = counted ? (double)((int64_t)C * 4 * a.sweeps) : (double)C;
+  GroupDesc g;
+  int64_t orig, chain_off, rows_off, corr_off;
+  double beta_bar;
+  if (a.items) {
+    const ItemDesc it = a.items[s];
+    g = a.groups[it.group];
+    orig = it.orig;
+    chain_off = it.chain_off;
+    rows_off = it.rows_off;
+    corr_off = it.corr_off;
+    beta_bar = it.beta_bar;
+  } else {
+    g = a.g0;
+    orig = s;
+    chain_off = s * 4 * (int64_t)g.K * g.C;
+    rows_off = s * (int64_t)words_per_config(g.L) * 4;
+    corr_off = s * (int64_t)(2 * g.L * g.L - 2 * g.L + 1);
+    beta_bar = a.beta_bar;
+  }
+  const int K = g.K, C = g.C, L = g.L;
+  const int sweeps = g.sweep_end - g.burn;
+  const bool counted = sweeps > 0;
+  const double denom = counted ? (double)((int64_t)C * 4 * sweeps) : (double)C;
+  const double f0 = 0.75 * (double)(2 * L * L - 2 * L + 1);
+  const double log_z0 = (double)(2 * L * (L - 1)) * a.ln2;
   double logz[4];
   int64_t key[4];
   for (int e = 0; e < 4; ++e) {
-    const int64_t base = ((s * 4 + e) * K) * C;
-    double acc = a.f0;
+    const int64_t base = chain_off + (int64_t)e * K * C;
+    double acc = f0;
     int64_t kk = 0;
     double mean_last = 0.0, mean_first = 0.0;
     for (int k = 0; k < K; ++k) {
@@ -166,38 +219,35 @@ __global__ void __launch_bounds__(128) decide_kernel(const DecideArgs a) {
     }
     double integral;
     if (K == 1) {
-      integral = (a.beta_bar / 2.0) * (a.f0 + mean_first);
+      integral = (beta_bar / 2.0) * (f0 + mean_first);
     } else {
-      const double h = a.beta_bar / (double)K;
+      const double h = beta_bar / (double)K;
       integral = (acc * h) / 3.0;
     }
-    logz[e] = a.log_z0 - integral;
+    logz[e] = log_z0 - integral;
     key[e] = kk;
-    if (a.mean_n) a.mean_n[s * 4 + e] = mean_last;
+    if (a.mean_n) a.mean_n[orig * 4 + e] = mean_last;
   }
   double m = logz[0];
   for (int e = 1; e < 4; ++e) m = logz[e] > m ? logz[e] : m;
   double ex[4];
   for (int e = 0; e < 4; ++e) ex[e] = exp(logz[e] - m);
   const double tot = ((ex[0] + ex[1]) + ex[2]) + ex[3];
-  for (int e = 0; e < 4; ++e) a.class_prob[s * 4 + e] = ex[e] / tot;
+  for (int e = 0; e < 4; ++e) a.class_prob[orig * 4 + e] = ex[e] / tot;
   int best = 0;
   for (int e = 1; e < 4; ++e)
     if (key[e] < key[best]) best = e;
-  a.chosen[s] = (uint8_t)best;
+  a.chosen[orig] = (uint8_t)best;
 
-  if (a.correction && a.corr_rows) {
-    const int L = a.L;
+  if (a.correction && a.final_rows) {
     const int W = words_per_row(L);
-    const int nq = 2 * L * L - 2 * L + 1;
-    const int64_t n4 = a.n * 4;
-    const int64_t sc = s * 4 + best;
+    uint8_t* out = a.correction + corr_off;
     int q = 0;
     for (int r = 0; r < 2 * L - 1; ++r) {
       const int fields = (r & 1) ? L - 1 : L;
       for (int f = 0; f < fields; ++f) {
-        const uint32_t word = a.corr_rows[(int64_t)(r * W + f / 16) * n4 + sc];
-        a.correction[s * nq + q++] = (uint8_t)((word >> (2 * (f % 16))) & 3u);
+        const uint32_t word = a.final_rows[rows_off + (r * W + f / 16) * 4 + best];
+        out[q++] = (uint8_t)((word >> (2 * (f % 16))) & 3u);
       }
     }
   }
@@ -342,16 +392,16 @@ __device__ __forceinline__ void paint_pair(uint32_t (*pl)[MATCH_THREADS], bool s
   }
 }
 
-__global__ void __launch_bounds__(MATCH_THREADS) init_matching_kernel(
-    int L, const uint8_t* __restrict__ syn, int64_t n, uint32_t* __restrict__ rows,
-    int32_t* __restrict__ weights, uint8_t* __restrict__ bytes) {
+__global__ void __launch_bounds__(MATCH_THREADS) init_matching_kernel(const StartArgs a) {
   __shared__ MatchLds sh;
   const int tid = threadIdx.x;
   const int64_t s = (int64_t)blockIdx.x * MATCH_THREADS + tid;
-  if (s >= n) return;
+  if (s >= a.n) return;
+  const StartItem si = start_item(a, s);
+  const int L = si.L;
   const int R = 2 * L - 1;
-  const int nstab = 2 * L * (L - 1), nstar = L * (L - 1);
-  const uint8_t* sy = syn + s * nstab;
+  const int nstar = L * (L - 1);
+  const uint8_t* sy = si.sy;
   for (int p = 0; p < 4; ++p)
     for (int r = 0; r < R; ++r) sh.plane[p][r][tid] = 0u;
 
@@ -444,19 +494,18 @@ __global__ void __launch_bounds__(MATCH_THREADS) init_matching_kernel(
   }
 
   const int W = words_per_row(L);
-  const int64_t n4 = n * 4;
   const int nq = 2 * L * L - 2 * L + 1, side_len = 2 * L - 1;
   for (int cls = 0; cls < 4; ++cls) {
     uint32_t (*xp)[MATCH_THREADS] = sh.plane[((cls & 1) == base_par[0]) ? 0 : 1];
     uint32_t (*zp)[MATCH_THREADS] = sh.plane[((cls >> 1) == base_par[1]) ? 2 : 3];
-    const int64_t sc = s * 4 + cls;
+    const int64_t sc = si.orig * 4 + cls;
     int weight = 0;
     for (int r = 0; r < R; ++r) {
       const int fields = (r & 1) ? L - 1 : L;
       const uint32_t xb = xp[r][tid], zb = zp[r][tid];
       const uint32_t valid = fields >= 32 ? ~0u : ((1u << fields) - 1u);
       weight += __builtin_popcount((xb | zb) & valid);
-      if (rows) {
+      if (a.rows) {
         for (int w = 0; w < W; ++w) {
           uint32_t word = 0;
           for (int f = 0; f < 16; ++f) {
@@ -464,25 +513,25 @@ __global__ void __launch_bounds__(MATCH_THREADS) init_matching_kernel(
             const uint32_t code = k < fields ? (((xb >> k) & 1u) | (((zb >> k) & 1u) << 1)) : 3u;
             word |= code << (2 * f);
           }
-          rows[(int64_t)(r * W + w) * n4 + sc] = word;
+          a.rows[si.rows_off + (r * W + w) * 4 + cls] = word;
         }
       }
-      if (bytes) {
+      if (a.bytes) {
         // first qubit of row r: (r * side_len + (r & 1)) / 2
-        uint8_t* out = bytes + sc * nq + (r * side_len + (r & 1)) / 2;
+        uint8_t* out = a.bytes + sc * nq + (r * side_len + (r & 1)) / 2;
         for (int k = 0; k < fields; ++k)
           out[k] = (uint8_t)(((xb >> k) & 1u) | (((zb >> k) & 1u) << 1));
       }
     }
-    if (weights) weights[sc] = weight;
+    if (a.weights) a.weights[sc] = weight;
   }
 }
 
-hipError_t launch_init_matching(int L, const uint8_t* syn, int64_t n, uint32_t* rows,
-                                int32_t* weights, uint8_t* bytes, hipStream_t s) {
-  if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(init_matching_kernel, dim3((unsigned)((n + MATCH_THREADS - 1) / MATCH_THREADS)),
-                     dim3(MATCH_THREADS), 0, s, L, syn, n, rows, weights, bytes);
+hipError_t launch_init_matching(const StartArgs& a, hipStream_t s) {
+  if (a.n == 0) return hipSuccess;
+  hipLaunchKernelGGL(init_matching_kernel,
+                     dim3((unsigned)((a.n + MATCH_THREADS - 1) / MATCH_THREADS)),
+                     dim3(MATCH_THREADS), 0, s, a);
   return hipGetLastError();
 }
 

@@ -1,0 +1,532 @@
+// Mixed batches: syndromes of different L, p, sweep budget and chain count
+// decoded together (the batched-launch pattern).  A plan is built once on the
+// host: items are grouped by (L, K, chains, burn, sweeps); groups get 64-chain
+// tiles; tiles of each row width are ordered longest first (LPT) so that the
+// persistent kernels' atomic queues hand out long tiles before short ones;
+// per-syndrome acceptance tables are computed in FP64 on the host exactly as
+// for a uniform batch.  Execution enqueues queue reset -> class starts ->
+// persistent chain kernels (one per row width, on two streams joined again) ->
+// estimator; the same sequence can be captured once into a HIP graph and
+// replayed.  Outputs depend only on each syndrome's bytes, id and parameters,
+// never on the plan's grouping, order or launch shape.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <functional>
+#include <map>
+#include <new>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/mcmcdec.h"
+#include "device_common.h"
+#include "host_common.h"
+#include "internal.h"
+
+using namespace mcmc;
+
+struct GraphEntry {
+  std::vector<const void*> key;
+  hipGraphExec_t exec = nullptr;
+};
+
+struct mcmc_plan {
+  int64_t n = 0;
+  uint64_t seed = 0;
+  uint32_t init = MCMC_INIT_MATCHING;
+  int device = 0;
+  std::vector<GroupDesc> groups;
+  std::vector<ItemDesc> items;       // plan order
+  std::vector<TileDesc> tiles;       // by kernel range, each longest first
+  std::vector<uint32_t> tables;
+  int64_t range_first[N_RANGES] = {0}, range_tiles[N_RANGES] = {0};
+  int64_t total_chains = 0, total_rows = 0, total_updates = 0;
+  size_t corr_bytes = 0;
+  // device copies
+  void* dev = nullptr;
+  GroupDesc* d_groups = nullptr;
+  ItemDesc* d_items = nullptr;
+  TileDesc* d_tiles = nullptr;
+  uint32_t* d_tables = nullptr;
+  // launch shape
+  mcmc_tuning tuning{};
+  hipStream_t side = nullptr;        // second stream for the two-word-row kernels
+  hipStream_t capture = nullptr;     // stream used to record graphs
+  hipEvent_t fork = nullptr, join = nullptr;
+  std::vector<GraphEntry> graphs;
+};
+
+namespace {
+
+struct PlanWorkspace {
+  size_t queue, init_rows, init_n, S, A, n_final, final_rows, bytes;
+};
+
+PlanWorkspace plan_workspace(const mcmc_plan* p) {
+  PlanWorkspace w{};
+  size_t off = 0;
+  w.queue = off;      off = align_up(off + 4 * sizeof(uint32_t));
+  w.init_rows = off;  off = align_up(off + (size_t)p->total_rows * sizeof(uint32_t));
+  w.init_n = off;     off = align_up(off + (size_t)p->n * 4 * sizeof(int32_t));
+  w.S = off;          off = align_up(off + (size_t)p->total_chains * sizeof(int64_t));
+  w.A = off;          off = align_up(off + (size_t)p->total_chains * sizeof(int64_t));
+  w.n_final = off;    off = align_up(off + (size_t)p->total_chains * sizeof(int32_t));
+  w.final_rows = off; off = align_up(off + (size_t)p->total_rows * sizeof(uint32_t));
+  w.bytes = off;
+  return w;
+}
+
+int check_item(const mcmc_item& it) {
+  if (!valid_L(it.L) || !valid_p(it.p)) return MCMC_ERANGE;
+  if (it.n_temps < 1 || it.n_temps > MCMC_TEMPS_MAX) return MCMC_ERANGE;
+  if (it.n_temps != 1 && (it.n_temps % 2) != 0) return MCMC_EINVAL;
+  if (it.chains < 1 || it.chains > MCMC_CHAINS_MAX) return MCMC_ERANGE;
+  if (it.burn < 0 || it.sweeps < 0 || (int64_t)it.burn + it.sweeps > MCMC_SWEEPS_MAX)
+    return MCMC_ERANGE;
+  if (it.syn_offset < 0 || it.corr_offset < 0) return MCMC_ERANGE;
+  return MCMC_OK;
+}
+
+void release_graphs(mcmc_plan* p) {
+  for (auto& g : p->graphs)
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+  p->graphs.clear();
+}
+
+int enqueue(mcmc_plan* p, const uint8_t* syn, double* prob, double* mean_n, int64_t* sum_n,
+            int64_t* accepts, uint8_t* chosen, uint8_t* correction, void* workspace,
+            hipStream_t s) {
+  const PlanWorkspace wl = plan_workspace(p);
+  char* ws = (char*)workspace;
+  uint32_t* queue = (uint32_t*)(ws + wl.queue);
+  uint32_t* init_rows = (uint32_t*)(ws + wl.init_rows);
+  int32_t* init_n = (int32_t*)(ws + wl.init_n);
+  int64_t* S = sum_n ? sum_n : (int64_t*)(ws + wl.S);
+  int64_t* A = accepts ? accepts : (int64_t*)(ws + wl.A);
+  int32_t* nf = (int32_t*)(ws + wl.n_final);
+  uint32_t* final_rows = correction ? (uint32_t*)(ws + wl.final_rows) : nullptr;
+
+  int st = hip_status(launch_zero(queue, 4, s));
+  if (st != MCMC_OK) return st;
+  StartArgs sa{};
+  sa.syn = syn;
+  sa.items = p->d_items;
+  sa.groups = p->d_groups;
+  sa.n = p->n;
+  sa.rows = init_rows;
+  sa.weights = init_n;
+  st = hip_status(p->init == MCMC_INIT_MATCHING ? launch_init_matching(sa, s) : launch_init(sa, s));
+  if (st != MCMC_OK) return st;
+
+  RunArgs a{};
+  a.groups = p->d_groups;
+  a.items = p->d_items;
+  a.tables = p->d_tables;
+  a.k0 = (uint32_t)(p->seed & 0xFFFFFFFFull);
+  a.k1 = (uint32_t)(p->seed >> 32);
+  a.init_rows = init_rows;
+  a.init_n = init_n;
+  a.S_out = S;
+  a.A_out = A;
+  a.n_out = nf;
+  a.final_rows = final_rows;
+  a.total_chains = p->total_chains;
+
+  const mcmc_tuning& tu = p->tuning;
+  const int cus = device_cus();
+  auto run_range = [&](int r, hipStream_t on) -> int {
+    if (p->range_tiles[r] == 0) return MCMC_OK;
+    RunArgs ra = a;
+    ra.tiles = p->d_tiles + p->range_first[r];
+    ra.n_tiles = p->range_tiles[r];
+    ra.queue = queue + r;
+    ra.lmin = RANGE_LO[r];
+    ra.lmax = RANGE_HI[r];
+    const bool wide = range_is_wide(r);
+    // occupancy offset from the kernel's own register-limited occupancy
+    const int per_simd = std::max(1, RANGE_WAVES[r] + (wide ? tu.occ_wide : tu.occ_narrow));
+    const int wg = wide ? tu.wg_wide : tu.wg_narrow;
+    const int64_t waves = std::min<int64_t>(p->range_tiles[r], (int64_t)cus * 4 * per_simd);
+    return hip_status(launch_chains(r, ra, (int)waves, wg, on));
+  };
+  bool narrow = false, wide = false;
+  for (int r = 0; r < N_RANGES; ++r) {
+    if (p->range_tiles[r] == 0) continue;
+    (range_is_wide(r) ? wide : narrow) = true;
+  }
+  hipStream_t wide_stream = s;
+  if (narrow && wide && tu.concurrent) {
+    // two-word-row kernels on the side stream, joined again below
+    if (hipEventRecord(p->fork, s) != hipSuccess) return MCMC_EDEVICE;
+    if (hipStreamWaitEvent(p->side, p->fork, 0) != hipSuccess) return MCMC_EDEVICE;
+    wide_stream = p->side;
+  }
+  for (int r = N_RANGES - 1; r >= 0; --r) {   // longest tiles first
+    st = run_range(r, range_is_wide(r) ? wide_stream : s);
+    if (st != MCMC_OK) return st;
+  }
+  if (wide_stream != s) {
+    if (hipEventRecord(p->join, p->side) != hipSuccess) return MCMC_EDEVICE;
+    if (hipStreamWaitEvent(s, p->join, 0) != hipSuccess) return MCMC_EDEVICE;
+  }
+
+  DecideArgs d{};
+  d.items = p->d_items;
+  d.groups = p->d_groups;
+  d.ln2 = log(2.0);
+  d.n = p->n;
+  d.S = S;
+  d.n_final = nf;
+  d.final_rows = final_rows;
+  d.class_prob = prob;
+  d.mean_n = mean_n;
+  d.chosen = chosen;
+  d.correction = correction;
+  return hip_status(launch_decide(d, s));
+}
+
+int check_exec(const mcmc_plan* p, const uint8_t* syn, const double* prob, const uint8_t* chosen,
+               const void* workspace, size_t workspace_bytes) {
+  if (!p) return MCMC_EINVAL;
+  if (p->n == 0) return MCMC_OK;
+  if (!syn || !prob || !chosen) return MCMC_EINVAL;
+  const PlanWorkspace wl = plan_workspace(p);
+  if (!workspace || workspace_bytes < wl.bytes || ((uintptr_t)workspace % kAlign) != 0)
+    return MCMC_EWORKSPACE;
+  return MCMC_OK;
+}
+
+// Workload signature for the tuning cache: device CU count and the multiset
+// of (L, K, chains, burn, sweeps, items) groups.
+std::string plan_signature(const mcmc_plan* p) {
+  std::string s = "cus=" + std::to_string(device_cus());
+  for (const GroupDesc& g : p->groups) {
+    s += ";" + std::to_string(g.L) + "," + std::to_string(g.K) + "," + std::to_string(g.C) + "," +
+         std::to_string(g.burn) + "," + std::to_string(g.sweep_end - g.burn) + "," +
+         std::to_string(g.n_items);
+  }
+  return s;
+}
+
+bool read_cache(const char* path, const std::string& sig, mcmc_tuning* t) {
+  FILE* f = fopen(path, "r");
+  if (!f) return false;
+  char line[1 << 16];
+  bool found = false;
+  while (fgets(line, sizeof(line), f)) {
+    char* tab = strchr(line, '\t');
+    if (!tab) continue;
+    *tab = 0;
+    if (sig != line) continue;
+    mcmc_tuning v{};
+    if (sscanf(tab + 1, "%d %d %d %d %d", &v.wg_narrow, &v.occ_narrow, &v.wg_wide, &v.occ_wide,
+               &v.concurrent) == 5) {
+      *t = v;
+      found = true;
+    }
+  }
+  fclose(f);
+  return found;
+}
+
+void write_cache(const char* path, const std::string& sig, const mcmc_tuning& t) {
+  FILE* f = fopen(path, "a");
+  if (!f) return;
+  fprintf(f, "%s\t%d %d %d %d %d\n", sig.c_str(), t.wg_narrow, t.occ_narrow, t.wg_wide,
+          t.occ_wide, t.concurrent);
+  fclose(f);
+}
+
+}  // namespace
+
+extern "C" {
+
+int mcmc_plan_create(const mcmc_item* items, int64_t n, uint64_t seed, uint32_t init,
+                     mcmc_plan** out) {
+  if (!out) return MCMC_EINVAL;
+  *out = nullptr;
+  if (n < 0 || n > ((int64_t)1 << 31)) return MCMC_ERANGE;
+  if (n > 0 && !items) return MCMC_EINVAL;
+  if (init != MCMC_INIT_CANONICAL && init != MCMC_INIT_MATCHING) return MCMC_EINVAL;
+  for (int64_t i = 0; i < n; ++i) {
+    const int st = check_item(items[i]);
+    if (st != MCMC_OK) return st;
+  }
+  mcmc_plan* p = new (std::nothrow) mcmc_plan();
+  if (!p) return MCMC_ENOMEM;
+  p->n = n;
+  p->seed = seed;
+  p->init = init;
+  (void)hipGetDevice(&p->device);
+
+  // groups: (L, K, C, burn, sweeps) -> items
+  std::map<std::tuple<int, int, int, int, int>, std::vector<int64_t>> by_key;
+  for (int64_t i = 0; i < n; ++i) {
+    const mcmc_item& it = items[i];
+    by_key[{it.L, it.n_temps, it.chains, it.burn, it.sweeps}].push_back(i);
+  }
+  // per-chain cost of a group: (burn + sweeps) * n_stab
+  std::vector<std::pair<int64_t, std::tuple<int, int, int, int, int>>> order;
+  for (auto& kv : by_key) {
+    const auto& k = kv.first;
+    const int64_t cost = ((int64_t)std::get<3>(k) + std::get<4>(k)) * n_stab(std::get<0>(k));
+    order.push_back({cost, k});
+  }
+  std::stable_sort(order.begin(), order.end(),
+                   [](const auto& a, const auto& b) { return a.first > b.first; });
+
+  // per-chain outputs and start blocks in the caller's order
+  std::vector<int64_t> chain_off(n), rows_off(n);
+  int64_t c_acc = 0, r_acc = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    chain_off[i] = c_acc;
+    rows_off[i] = r_acc;
+    c_acc += 4 * (int64_t)items[i].n_temps * items[i].chains;
+    r_acc += (int64_t)words_per_config(items[i].L) * 4;
+  }
+  p->total_chains = c_acc;
+  p->total_rows = r_acc;
+
+  for (auto& o : order) {
+    const auto& k = o.second;
+    const std::vector<int64_t>& members = by_key[k];
+    GroupDesc g{};
+    g.L = std::get<0>(k);
+    g.K = std::get<1>(k);
+    g.C = std::get<2>(k);
+    g.burn = std::get<3>(k);
+    g.sweep_begin = 0;
+    g.sweep_end = std::get<3>(k) + std::get<4>(k);
+    g.first_item = (int32_t)p->items.size();
+    g.n_items = (int32_t)members.size();
+    g.n_tasks = (int64_t)members.size() * 4 * g.K * g.C;
+    const int gid = (int)p->groups.size();
+    for (int64_t i : members) {
+      const mcmc_item& src = items[i];
+      ItemDesc it{};
+      it.orig = i;
+      it.syn_off = src.syn_offset;
+      it.rows_off = rows_off[i];
+      it.chain_off = chain_off[i];
+      it.corr_off = src.corr_offset;
+      it.table_off = (int64_t)p->tables.size();
+      it.beta_bar = beta_bar(src.p);
+      it.sid = src.syndrome_id;
+      it.group = gid;
+      p->tables.resize(p->tables.size() + 4 * (size_t)src.n_temps);
+      fill_table(src.p, src.n_temps, p->tables.data() + it.table_off);
+      p->items.push_back(it);
+      p->total_updates += 4 * (int64_t)src.n_temps * src.chains *
+                          ((int64_t)src.burn + src.sweeps) * n_stab(src.L);
+    }
+    p->groups.push_back(g);
+  }
+  // tiles per kernel range, each range longest first (groups are already in
+  // descending cost order)
+  for (int r = 0; r < N_RANGES; ++r) {
+    p->range_first[r] = (int64_t)p->tiles.size();
+    for (size_t gi = 0; gi < p->groups.size(); ++gi) {
+      const GroupDesc& g = p->groups[gi];
+      if (range_of(g.L) != r) continue;
+      for (int64_t f = 0; f < g.n_tasks; f += TILE) p->tiles.push_back(TileDesc{(int32_t)gi, g.L, f});
+    }
+    p->range_tiles[r] = (int64_t)p->tiles.size() - p->range_first[r];
+  }
+  if ((int64_t)p->tiles.size() > 0xFFFFFFFFll) {
+    delete p;
+    return MCMC_ERANGE;
+  }
+
+  // device copies in one allocation
+  const size_t gsz = align_up(p->groups.size() * sizeof(GroupDesc) + 1);
+  const size_t isz = align_up(p->items.size() * sizeof(ItemDesc) + 1);
+  const size_t tsz = align_up(p->tiles.size() * sizeof(TileDesc) + 1);
+  const size_t bsz = align_up(p->tables.size() * sizeof(uint32_t) + 1);
+  if (hipMalloc(&p->dev, gsz + isz + tsz + bsz) != hipSuccess) {
+    delete p;
+    return MCMC_EDEVICE;
+  }
+  char* base = (char*)p->dev;
+  p->d_groups = (GroupDesc*)base;
+  p->d_items = (ItemDesc*)(base + gsz);
+  p->d_tiles = (TileDesc*)(base + gsz + isz);
+  p->d_tables = (uint32_t*)(base + gsz + isz + tsz);
+  bool ok = true;
+  if (!p->groups.empty())
+    ok &= hipMemcpy(p->d_groups, p->groups.data(), p->groups.size() * sizeof(GroupDesc),
+                    hipMemcpyHostToDevice) == hipSuccess;
+  if (!p->items.empty())
+    ok &= hipMemcpy(p->d_items, p->items.data(), p->items.size() * sizeof(ItemDesc),
+                    hipMemcpyHostToDevice) == hipSuccess;
+  if (!p->tiles.empty())
+    ok &= hipMemcpy(p->d_tiles, p->tiles.data(), p->tiles.size() * sizeof(TileDesc),
+                    hipMemcpyHostToDevice) == hipSuccess;
+  if (!p->tables.empty())
+    ok &= hipMemcpy(p->d_tables, p->tables.data(), p->tables.size() * sizeof(uint32_t),
+                    hipMemcpyHostToDevice) == hipSuccess;
+  ok &= hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking) == hipSuccess;
+  ok &= hipStreamCreateWithFlags(&p->capture, hipStreamNonBlocking) == hipSuccess;
+  ok &= hipEventCreateWithFlags(&p->fork, hipEventDisableTiming) == hipSuccess;
+  ok &= hipEventCreateWithFlags(&p->join, hipEventDisableTiming) == hipSuccess;
+  if (!ok) {
+    mcmc_plan_destroy(p);
+    return MCMC_EDEVICE;
+  }
+  p->tuning.wg_narrow = 256;
+  p->tuning.wg_wide = 256;
+  p->tuning.occ_narrow = 0;
+  p->tuning.occ_wide = 0;
+  p->tuning.concurrent = 1;
+  *out = p;
+  return MCMC_OK;
+}
+
+int mcmc_plan_destroy(mcmc_plan* p) {
+  if (!p) return MCMC_OK;
+  release_graphs(p);
+  if (p->fork) (void)hipEventDestroy(p->fork);
+  if (p->join) (void)hipEventDestroy(p->join);
+  if (p->side) (void)hipStreamDestroy(p->side);
+  if (p->capture) (void)hipStreamDestroy(p->capture);
+  if (p->dev) (void)hipFree(p->dev);
+  delete p;
+  return MCMC_OK;
+}
+
+int mcmc_plan_info(const mcmc_plan* p, int64_t* total_chains, size_t* workspace_bytes,
+                   int64_t* total_updates) {
+  if (!p) return MCMC_EINVAL;
+  if (total_chains) *total_chains = p->total_chains;
+  if (workspace_bytes) *workspace_bytes = plan_workspace(p).bytes;
+  if (total_updates) *total_updates = p->total_updates;
+  return MCMC_OK;
+}
+
+int mcmc_plan_get_tuning(const mcmc_plan* p, mcmc_tuning* t) {
+  if (!p || !t) return MCMC_EINVAL;
+  *t = p->tuning;
+  return MCMC_OK;
+}
+
+int mcmc_plan_set_tuning(mcmc_plan* p, const mcmc_tuning* t) {
+  if (!p || !t) return MCMC_EINVAL;
+  auto wg_ok = [](int wg) { return wg == 64 || wg == 128 || wg == 256; };
+  if (!wg_ok(t->wg_narrow) || !wg_ok(t->wg_wide)) return MCMC_EINVAL;
+  if (t->occ_narrow < -4 || t->occ_narrow > 8 || t->occ_wide < -2 || t->occ_wide > 8)
+    return MCMC_ERANGE;
+  if (t->concurrent != 0 && t->concurrent != 1) return MCMC_EINVAL;
+  p->tuning = *t;
+  release_graphs(p);  // captured graphs hold the old launch shape
+  return MCMC_OK;
+}
+
+int mcmc_plan_execute(mcmc_plan* p, const uint8_t* syndromes, double* class_prob,
+                      double* mean_n, int64_t* sum_n, int64_t* accepts, uint8_t* chosen,
+                      uint8_t* correction, void* workspace, size_t workspace_bytes,
+                      void* stream) {
+  int st = check_exec(p, syndromes, class_prob, chosen, workspace, workspace_bytes);
+  if (st != MCMC_OK || p->n == 0) return st;
+  return enqueue(p, syndromes, class_prob, mean_n, sum_n, accepts, chosen, correction, workspace,
+                 (hipStream_t)stream);
+}
+
+int mcmc_plan_graph_launch(mcmc_plan* p, const uint8_t* syndromes, double* class_prob,
+                           double* mean_n, int64_t* sum_n, int64_t* accepts, uint8_t* chosen,
+                           uint8_t* correction, void* workspace, size_t workspace_bytes,
+                           void* stream) {
+  int st = check_exec(p, syndromes, class_prob, chosen, workspace, workspace_bytes);
+  if (st != MCMC_OK || p->n == 0) return st;
+  const std::vector<const void*> key = {syndromes, class_prob, mean_n, sum_n, accepts,
+                                        chosen, correction, workspace};
+  hipGraphExec_t exec = nullptr;
+  for (auto& g : p->graphs)
+    if (g.key == key) exec = g.exec;
+  if (!exec) {
+    if (hipStreamBeginCapture(p->capture, hipStreamCaptureModeThreadLocal) != hipSuccess)
+      return MCMC_EDEVICE;
+    st = enqueue(p, syndromes, class_prob, mean_n, sum_n, accepts, chosen, correction, workspace,
+                 p->capture);
+    hipGraph_t graph = nullptr;
+    const hipError_t e = hipStreamEndCapture(p->capture, &graph);
+    if (st != MCMC_OK || e != hipSuccess || !graph) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return st != MCMC_OK ? st : MCMC_EDEVICE;
+    }
+    const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ie != hipSuccess) return MCMC_EDEVICE;
+    p->graphs.push_back(GraphEntry{key, exec});
+  }
+  return hip_status(hipGraphLaunch(exec, (hipStream_t)stream));
+}
+
+int mcmc_plan_autotune(mcmc_plan* p, const uint8_t* syndromes, double* class_prob,
+                       double* mean_n, int64_t* sum_n, int64_t* accepts, uint8_t* chosen,
+                       uint8_t* correction, void* workspace, size_t workspace_bytes, void* stream,
+                       const char* cache_path, mcmc_tuning* result) {
+  int st = check_exec(p, syndromes, class_prob, chosen, workspace, workspace_bytes);
+  if (st != MCMC_OK) return st;
+  const std::string sig = plan_signature(p);
+  mcmc_tuning best = p->tuning;
+  if (cache_path && read_cache(cache_path, sig, &best)) {
+    st = mcmc_plan_set_tuning(p, &best);
+    if (st == MCMC_OK && result) *result = p->tuning;
+    return st;
+  }
+  if (p->n == 0) {
+    if (result) *result = p->tuning;
+    return MCMC_OK;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return MCMC_EDEVICE;
+  auto time_of = [&](const mcmc_tuning& t, float* ms) -> int {
+    p->tuning = t;
+    if (hipEventRecord(e0, s) != hipSuccess) return MCMC_EDEVICE;
+    int r = enqueue(p, syndromes, class_prob, mean_n, sum_n, accepts, chosen, correction,
+                    workspace, s);
+    if (r != MCMC_OK) return r;
+    if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess)
+      return MCMC_EDEVICE;
+    return hip_status(hipEventElapsedTime(ms, e0, e1));
+  };
+  // coordinate search from the default shape; every candidate decodes the
+  // whole batch, and all candidates give identical outputs
+  float best_ms = 0.0f;
+  st = time_of(best, &best_ms);  // also warms up the code objects
+  if (st == MCMC_OK) st = time_of(best, &best_ms);
+  // each move is applied to the best shape found so far
+  const std::vector<std::function<void(mcmc_tuning&)>> moves = {
+      [](mcmc_tuning& t) { t.wg_narrow = t.wg_wide = 64; },
+      [](mcmc_tuning& t) { t.wg_narrow = t.wg_wide = 128; },
+      [](mcmc_tuning& t) { t.occ_narrow = -1; },
+      [](mcmc_tuning& t) { t.occ_narrow = 1; },
+      [](mcmc_tuning& t) { t.occ_wide = -1; },
+      [](mcmc_tuning& t) { t.occ_wide = 1; },
+      [](mcmc_tuning& t) { t.concurrent = 1 - t.concurrent; },
+  };
+  for (size_t i = 0; st == MCMC_OK && i < moves.size(); ++i) {
+    mcmc_tuning cand = best;
+    moves[i](cand);
+    float ms = 0.0f;
+    st = time_of(cand, &ms);
+    if (st == MCMC_OK && ms < best_ms * 0.98f) {
+      best_ms = ms;
+      best = cand;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  p->tuning = best;
+  release_graphs(p);
+  if (st != MCMC_OK) return st;
+  if (cache_path) write_cache(cache_path, sig, best);
+  if (result) *result = best;
+  return MCMC_OK;
+}
+
+}  // extern "C"

@@ -94,3 +94,22 @@ def test_decode_rejects_before_launch():
     assert lib.mcmc_decode_batch(*args(prm=bad)) == -1      # trace requested, no buffer
     assert lib.mcmc_sample_errors(9, 0.1, 1, None, 0, 4, None, dummy, None, None) == -1
     assert lib.mcmc_sample_errors(9, 0.9, 1, None, 0, 4, dummy, dummy, None, None) == -2
+
+
+def test_plan_rejects_invalid_items_before_allocating():
+    lib = _lib._lib()
+    h = ctypes.c_void_p()
+    good = dict(L=9, sweeps=10, burn=0, chains=2, n_temps=1, syndrome_id=0, p=0.1,
+                syn_offset=0, corr_offset=0)
+    for bad, status in ((dict(L=1), -2), (dict(L=26), -2), (dict(p=0.9), -2), (dict(n_temps=3), -1),
+                        (dict(chains=0), -2), (dict(sweeps=-1), -2), (dict(syn_offset=-4), -2)):
+        arr = (_lib.Item * 2)()
+        for i in range(2):
+            for k, v in good.items():
+                setattr(arr[i], k, v)
+        for k, v in bad.items():
+            setattr(arr[1], k, v)
+        assert lib.mcmc_plan_create(arr, 2, 1, 1, ctypes.byref(h)) == status
+    assert lib.mcmc_plan_create(None, 3, 1, 1, ctypes.byref(h)) == -1
+    assert lib.mcmc_plan_create(None, 0, 1, 5, ctypes.byref(h)) == -1
+    assert lib.mcmc_plan_destroy(None) == 0

@@ -1,0 +1,158 @@
+"""Mixed batches through the plan API: every syndrome's results equal the
+uniform decode of that syndrome alone (same id and parameters), bit for bit,
+whatever the batch composition, launch shape or graph replay; sampled
+syndromes are also replayed on the oracle."""
+
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+import paper_1302_2669_amd as mc  # noqa: E402
+from oracle import decoder, geometry, sampler  # noqa: E402
+
+from inputs import mixed_workload  # noqa: E402
+
+DEV = "cuda"
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def make_batch(Ls, ps, sweeps, seed, chains=None, n_temps=None, burns=None):
+    items, syns = [], []
+    for i, (L, p, sw) in enumerate(zip(Ls, ps, sweeps)):
+        lat = geometry.Lattice(int(L))
+        syn, _, _ = sampler.sample(lat, float(p), seed, [1000 + i])
+        syns.append(syn[0])
+        items.append(dict(L=int(L), p=float(p), sweeps=int(sw),
+                          burn=int(burns[i]) if burns is not None else 0,
+                          chains=int(chains[i]) if chains is not None else 2,
+                          n_temps=int(n_temps[i]) if n_temps is not None else 1,
+                          syndrome_id=7 * i + 1))
+    flat = torch.from_numpy(np.concatenate(syns)).to(DEV)
+    return items, syns, flat
+
+
+def per_item(plan, out, i):
+    a, b = plan.chain_offsets[i], plan.chain_offsets[i + 1]
+    c0, c1 = plan.corr_offsets[i], plan.corr_offsets[i + 1]
+    return dict(sum_n=out["sum_n"][a:b].cpu().numpy(), accepts=out["accepts"][a:b].cpu().numpy(),
+                chosen=int(out["chosen"][i]), correction=out["correction"][c0:c1].cpu().numpy(),
+                class_prob=out["class_prob"][i].cpu().numpy(), mean_n=out["mean_n"][i].cpu().numpy())
+
+
+def uniform(item, syn, seed):
+    s = torch.from_numpy(syn[None]).to(DEV)
+    o = mc.decode_batch(s, item["L"], item["p"], item["sweeps"], seed, chains=item["chains"],
+                        n_temps=item["n_temps"], burn=item["burn"],
+                        syndrome_ids=torch.tensor([item["syndrome_id"]]), want_sums=True)
+    torch.cuda.synchronize()
+    return dict(sum_n=o["sum_n"].reshape(-1).cpu().numpy(),
+                accepts=o["accepts"].reshape(-1).cpu().numpy(), chosen=int(o["chosen"][0]),
+                correction=o["correction"][0].cpu().numpy(),
+                class_prob=o["class_prob"][0].cpu().numpy(), mean_n=o["mean_n"][0].cpu().numpy())
+
+
+def same(a, b):
+    for k in ("sum_n", "accepts", "correction", "class_prob", "mean_n"):
+        assert np.array_equal(a[k], b[k]), k
+    assert a["chosen"] == b["chosen"]
+
+
+def test_mixed_plan_equals_uniform_decodes():
+    say("mixed plan vs uniform decodes")
+    rng = np.random.default_rng(3)
+    Ls = [3, 25, 5, 17, 9, 13, 2, 20, 16, 23, 7, 11, 19, 22, 24, 21, 18, 4]
+    ps = rng.uniform(0.05, 0.18, len(Ls))
+    sweeps = [min(L * L, 40) for L in Ls]
+    chains = rng.integers(1, 4, len(Ls))
+    n_temps = [1 if i % 3 else 2 for i in range(len(Ls))]
+    burns = [i % 3 for i in range(len(Ls))]
+    items, syns, flat = make_batch(Ls, ps, sweeps, 11, chains, n_temps, burns)
+    plan = mc.MixedPlan(items, seed=0xABCD)
+    out = plan.execute(flat, want_sums=True)
+    torch.cuda.synchronize()
+    for i, it in enumerate(items):
+        same(per_item(plan, out, i), uniform(it, syns[i], 0xABCD))
+    # every launch shape gives the same bits
+    base = {k: v.clone() for k, v in out.items()}
+    for tun in (dict(wg_narrow=64, occ_narrow=-4, wg_wide=128, occ_wide=-2, concurrent=0),
+                dict(wg_narrow=128, occ_narrow=3, wg_wide=64, occ_wide=2, concurrent=1)):
+        plan.tuning = tun
+        o2 = plan.execute(flat, want_sums=True)
+        torch.cuda.synchronize()
+        for k in base:
+            assert torch.equal(base[k], o2[k]), (tun, k)
+    plan.close()
+
+
+def test_mixed_plan_against_oracle():
+    say("mixed plan vs oracle")
+    Ls, ps, sweeps = [5, 9, 13, 17], [0.07, 0.12, 0.15, 0.17], [6, 5, 4, 2]
+    items, syns, flat = make_batch(Ls, ps, sweeps, 5)
+    plan = mc.MixedPlan(items, seed=99)
+    out = plan.execute(flat, want_sums=True)
+    torch.cuda.synchronize()
+    for i, it in enumerate(items):
+        g = per_item(plan, out, i)
+        o = decoder.decode(it["L"], syns[i][None], it["p"], it["sweeps"], 99,
+                           chains_per_class=it["chains"], syndrome_ids=[it["syndrome_id"]])
+        assert np.array_equal(g["sum_n"], o["sum_n"].reshape(-1))
+        assert np.array_equal(g["accepts"], o["accepts"].reshape(-1))
+        assert g["chosen"] == int(o["chosen"][0])
+        assert np.array_equal(g["correction"], o["correction"][0])
+        np.testing.assert_allclose(g["class_prob"], o["class_prob"][0], rtol=1e-12, atol=0)
+    plan.close()
+
+
+def test_graph_replays_match_eager():
+    """The captured graph is replayed several times with eager work and
+    synchronisations in between; every replay equals the eager execution."""
+    say("graph replays")
+    L, p, sw = mixed_workload(200, seed=21)
+    sw = np.minimum(sw, 30)
+    items, syns, flat = make_batch(L, p, sw, 8)
+    plan = mc.MixedPlan(items, seed=5)
+    eager = plan.execute(flat, want_sums=True)
+    torch.cuda.synchronize()
+    eager = {k: v.clone() for k, v in eager.items()}
+    out = plan._outputs(flat.device, True, True)
+    for rep in range(4):
+        for v in out.values():
+            v.fill_(0)
+        plan.execute(flat, want_sums=True, graph=True, out=out)
+        torch.cuda.synchronize()
+        for k in eager:
+            assert torch.equal(eager[k], out[k]), (rep, k)
+        junk = torch.randn(1 << 20, device=DEV).sum()   # eager work between replays
+        torch.cuda.synchronize()
+        del junk
+    plan.close()
+
+
+def test_autotune_keeps_results(tmp_path):
+    say("autotune")
+    L, p, sw = mixed_workload(300, seed=4)
+    sw = np.minimum(sw, 12)
+    items, syns, flat = make_batch(L, p, sw, 9)
+    plan = mc.MixedPlan(items, seed=77)
+    ref = plan.execute(flat, want_sums=True)
+    torch.cuda.synchronize()
+    ref = {k: v.clone() for k, v in ref.items()}
+    cache = tmp_path / "tune.txt"
+    t1 = plan.autotune(flat, cache_path=cache)
+    assert cache.exists() and cache.read_text().strip()
+    t2 = plan.autotune(flat, cache_path=cache)      # served from the cache
+    assert t1 == t2 == plan.tuning
+    o = plan.execute(flat, want_sums=True)
+    torch.cuda.synchronize()
+    for k in ref:
+        assert torch.equal(ref[k], o[k]), k
+    plan.close()
