@@ -47,6 +47,9 @@ def main():
     ap.add_argument("--batch", type=int, default=BATCH)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=256)
+    ap.add_argument("--workload", choices=["metric", "mixed"], default="metric",
+                    help="metric: L=13 p=0.15 (default); mixed: L in 5..25, p in [0.05,0.18]")
+    ap.add_argument("--mixed-n", type=int, default=100000)
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="also run one device copy of this size (HBM counter calibration)")
     args = ap.parse_args()
@@ -61,6 +64,8 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.workload == "mixed":
+        return bench_mixed(args, mc, torch, dev)
     n = args.batch
     nq, ns = mc.geometry(L)
     steps, warm = args.steps, args.warmup
@@ -160,6 +165,46 @@ def main():
                      "chain_ms_per_launch": chain_ms, "ops_per_update": OPS_PER_UPDATE,
                      "updates_per_launch": chain_updates},
         "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def bench_mixed(args, mc, torch, dev):
+    """Mixed sizes in one plan: L uniform in {5, 7, ..., 25}, p uniform in
+    [0.05, 0.18], budget L^2 sweeps, 4 chains per class; autotuned launch
+    shape, graph-captured execution."""
+    from paper_1302_2669_amd.inputs import mixed_workload
+    n = args.mixed_n
+    Ls, ps, sweeps = mixed_workload(n, seed=SEED ^ 0x3)
+    items = [dict(L=int(l), p=float(q), sweeps=int(s), chains=4, syndrome_id=i)
+             for i, (l, q, s) in enumerate(zip(Ls, ps, sweeps))]
+    plan = mc.MixedPlan(items, seed=SEED)
+    syn, cls = plan.sample(SEED, device=dev)
+    tuning = plan.autotune(syn)
+    out = plan.execute(syn, graph=True)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream(dev)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(args.steps):
+        plan.execute(syn, graph=True, out=out)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1) / args.steps
+    fail = float((out["chosen"] != cls).float().mean())
+    line = {
+        "metric": "decoded syndromes/sec, mixed L 5..25 in one plan",
+        "value": n * args.steps / wall, "unit": "syndromes/s",
+        "stabilizer_updates_per_s": plan.total_updates * args.steps / wall,
+        "n_gpus": 1, "steps": args.steps, "warmup": 1, "ms_per_step": ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32",
+        "data": "synthetic: i.i.d. depolarizing samples per item",
+        "config": {"workload": f"{n} syndromes, L uniform in {{5,...,25}}, p uniform in "
+                               "[0.05,0.18], L^2 sweeps, 4 chains per class, one plan",
+                   "tuning": tuning, "updates_per_step": plan.total_updates},
+        "logical_error": {"rate": fail, "samples": n},
     }
     print(json.dumps(line), flush=True)
 

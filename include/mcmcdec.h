@@ -264,6 +264,12 @@ int mcmc_plan_graph_launch(mcmc_plan* plan, const uint8_t* d_syndromes, double* 
                            uint8_t* d_chosen, uint8_t* d_correction, void* d_workspace,
                            size_t workspace_bytes, void* stream);
 
+/* Depolarizing samples for the plan's items (the rule of mcmc_sample_errors
+ * with each item's L and p, sample id = its syndrome_id): syndromes written at
+ * the items' syn_offset in d_syndromes, classes to d_true_class [n]. */
+int mcmc_plan_sample(const mcmc_plan* plan, uint64_t seed, uint8_t* d_syndromes,
+                     uint8_t* d_true_class, void* stream);
+
 /* Pick the launch shape by timing whole executions of the plan (coordinate
  * search over workgroup size, grid sizes and stream overlap), synchronising
  * `stream`.  With cache_path, a stored shape for the same workload signature

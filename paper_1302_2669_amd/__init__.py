@@ -272,6 +272,15 @@ class MixedPlan:
                    "mcmc_plan_graph_launch" if graph else "mcmc_plan_execute")
         return out
 
+    def sample(self, seed, device="cuda"):
+        """Depolarizing samples of every item: (flat syndromes, true classes)."""
+        torch = _torch()
+        syn = torch.empty((max(self.syn_bytes, 1),), dtype=torch.uint8, device=device)
+        cls = torch.empty((max(self.n, 1),), dtype=torch.uint8, device=device)
+        _lib.check(_lib._lib().mcmc_plan_sample(self._h, int(seed) & ((1 << 64) - 1), _ptr(syn),
+                                                _ptr(cls), _stream(syn.device)), "mcmc_plan_sample")
+        return syn[:self.syn_bytes], cls[:self.n]
+
     def autotune(self, syndromes, cache_path=None):
         syndromes = self._check_input(syndromes)
         out = self._outputs(syndromes.device, False, True)

@@ -93,6 +93,7 @@ _SIGNATURES = {
     "mcmc_plan_set_tuning": (ctypes.c_int, [_P, ctypes.POINTER(Tuning)]),
     "mcmc_plan_execute": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P, _P, _P, _SZ, _P]),
     "mcmc_plan_graph_launch": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P, _P, _P, _SZ, _P]),
+    "mcmc_plan_sample": (ctypes.c_int, [_P, _U64, _P, _P, _P]),
     "mcmc_plan_autotune": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P, _P, _P, _SZ, _P,
                                           ctypes.c_char_p, ctypes.POINTER(Tuning)]),
 }

@@ -90,7 +90,7 @@ WorkspaceLayout workspace_layout(const mcmc_params* prm, int64_t n) {
   const int64_t T = n * 4 * (int64_t)prm->n_temps * prm->chains;
   WorkspaceLayout w{};
   size_t off = 0;
-  w.queue = off;      off = align_up(off + 4 * sizeof(uint32_t));
+  w.queue = off;      off = align_up(off + kQueueSlots * sizeof(uint32_t));
   w.init_rows = off;  off = align_up(off + (size_t)RW * n * 4 * sizeof(uint32_t));
   w.init_n = off;     off = align_up(off + (size_t)n * 4 * sizeof(int32_t));
   w.S = off;          off = align_up(off + (size_t)T * sizeof(int64_t));
@@ -213,7 +213,7 @@ int mcmc_decode_batch(const uint8_t* syndromes, const uint32_t* syndrome_ids, in
   int32_t* nf = (int32_t*)(ws + wl.n_final);
   uint32_t* final_rows = correction ? (uint32_t*)(ws + wl.final_rows) : nullptr;
 
-  st = hip_status(launch_zero(queue, 4, s));
+  st = hip_status(launch_zero(queue, kQueueSlots, s));
   if (st != MCMC_OK) return st;
   if (!resume) {
     StartArgs sa{};

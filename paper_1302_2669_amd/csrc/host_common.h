@@ -12,6 +12,11 @@ namespace mcmc {
 
 constexpr size_t kAlign = 256;
 
+// Tile-queue counters at the head of every workspace, one per chain kernel
+// range; all of them are zeroed before each launch sequence.
+constexpr int kQueueSlots = 8;
+static_assert(kQueueSlots >= N_RANGES, "one queue counter per kernel range");
+
 inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 inline bool valid_L(int32_t L) { return L >= MCMC_L_MIN && L <= MCMC_L_MAX; }

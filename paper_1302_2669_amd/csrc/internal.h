@@ -39,8 +39,10 @@ struct ItemDesc {               // one syndrome, plan order
   int64_t corr_off;             // byte offset of its correction output
   int64_t table_off;            // uint32 offset of its [K][4] thresholds
   double beta_bar;
-  uint32_t sid;                 // Philox counter word 2
+  uint32_t sid;                 // Philox counter word 2 (also the sample id)
   int32_t group;
+  uint32_t err_thr;             // floor(p 2^32), for sampling this item's errors
+  uint32_t pad;
 };
 
 struct TileDesc {
@@ -138,5 +140,9 @@ hipError_t launch_decide(const DecideArgs& a, hipStream_t s);
 hipError_t launch_sample(int L, uint32_t threshold, uint32_t k0, uint32_t k1, const uint32_t* ids,
                          uint32_t id_base, int64_t n, uint8_t* syn, uint8_t* true_class,
                          uint8_t* errors, hipStream_t s);
+// One sample per plan item (its L, p, id; syndrome written at syn_off, class at orig).
+hipError_t launch_sample_items(const ItemDesc* items, const GroupDesc* groups, int64_t n,
+                               uint32_t k0, uint32_t k1, uint8_t* syn, uint8_t* true_class,
+                               hipStream_t s);
 
 }  // namespace mcmc

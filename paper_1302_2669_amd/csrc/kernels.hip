@@ -267,16 +267,10 @@ hipError_t launch_decide(const DecideArgs& a, hipStream_t s) {
 // ---------------------------------------------------------------------------
 constexpr int SAMPLE_MAX_NQ = 2 * MCMC_L_MAX * MCMC_L_MAX - 2 * MCMC_L_MAX + 1;
 
-__global__ void __launch_bounds__(256) sample_kernel(int L, uint32_t threshold, uint32_t k0,
-                                                     uint32_t k1, const uint32_t* __restrict__ ids,
-                                                     uint32_t id_base, int64_t n,
-                                                     uint8_t* __restrict__ syn,
-                                                     uint8_t* __restrict__ true_class,
-                                                     uint8_t* __restrict__ errors) {
-  __shared__ uint8_t err[SAMPLE_MAX_NQ + 1];
-  const int64_t smp = blockIdx.x;
-  if (smp >= n) return;
-  const uint32_t sid = ids ? ids[smp] : id_base + (uint32_t)smp;
+__device__ __forceinline__ void sample_one(int L, uint32_t threshold, uint32_t k0, uint32_t k1,
+                                           uint32_t sid, uint8_t* err, uint8_t* __restrict__ syn,
+                                           uint8_t* __restrict__ true_class,
+                                           uint8_t* __restrict__ errors) {
   const int side = 2 * L - 1;
   const int nq = 2 * L * L - 2 * L + 1;
   const int nstab = 2 * L * (L - 1);
@@ -308,16 +302,54 @@ __global__ void __launch_bounds__(256) sample_kernel(int L, uint32_t threshold, 
     if (r < side - 1) par ^= (err[qidx(r + 1, c)] & bit) != 0;
     if (c > 0) par ^= (err[qidx(r, c - 1)] & bit) != 0;
     if (c < side - 1) par ^= (err[qidx(r, c + 1)] & bit) != 0;
-    syn[smp * nstab + site] = (uint8_t)par;
+    syn[site] = (uint8_t)par;
   }
   if (threadIdx.x == 0) {
     int bx = 0, bz = 0;
     for (int r = 0; r < side; r += 2) bx ^= err[qidx(r, 0)] & 1;
     for (int c = 0; c < side; c += 2) bz ^= (err[qidx(0, c)] >> 1) & 1;
-    true_class[smp] = (uint8_t)(bx + 2 * bz);
+    *true_class = (uint8_t)(bx + 2 * bz);
   }
   if (errors)
-    for (int q = threadIdx.x; q < nq; q += blockDim.x) errors[smp * nq + q] = err[q];
+    for (int q = threadIdx.x; q < nq; q += blockDim.x) errors[q] = err[q];
+}
+
+__global__ void __launch_bounds__(256) sample_kernel(int L, uint32_t threshold, uint32_t k0,
+                                                     uint32_t k1, const uint32_t* __restrict__ ids,
+                                                     uint32_t id_base, int64_t n,
+                                                     uint8_t* __restrict__ syn,
+                                                     uint8_t* __restrict__ true_class,
+                                                     uint8_t* __restrict__ errors) {
+  __shared__ uint8_t err[SAMPLE_MAX_NQ + 1];
+  const int64_t smp = blockIdx.x;
+  if (smp >= n) return;
+  const uint32_t sid = ids ? ids[smp] : id_base + (uint32_t)smp;
+  const int nq = 2 * L * L - 2 * L + 1;
+  const int nstab = 2 * L * (L - 1);
+  sample_one(L, threshold, k0, k1, sid, err, syn + smp * nstab, true_class + smp,
+             errors ? errors + smp * nq : nullptr);
+}
+
+__global__ void __launch_bounds__(256) sample_items_kernel(const ItemDesc* __restrict__ items,
+                                                           const GroupDesc* __restrict__ groups,
+                                                           int64_t n, uint32_t k0, uint32_t k1,
+                                                           uint8_t* __restrict__ syn,
+                                                           uint8_t* __restrict__ true_class) {
+  __shared__ uint8_t err[SAMPLE_MAX_NQ + 1];
+  const int64_t smp = blockIdx.x;
+  if (smp >= n) return;
+  const ItemDesc it = items[smp];
+  sample_one(groups[it.group].L, it.err_thr, k0, k1, it.sid, err, syn + it.syn_off,
+             true_class + it.orig, nullptr);
+}
+
+hipError_t launch_sample_items(const ItemDesc* items, const GroupDesc* groups, int64_t n,
+                               uint32_t k0, uint32_t k1, uint8_t* syn, uint8_t* true_class,
+                               hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(sample_items_kernel, dim3((unsigned)n), dim3(256), 0, s, items, groups, n, k0,
+                     k1, syn, true_class);
+  return hipGetLastError();
 }
 
 hipError_t launch_sample(int L, uint32_t threshold, uint32_t k0, uint32_t k1, const uint32_t* ids,

@@ -69,7 +69,7 @@ struct PlanWorkspace {
 PlanWorkspace plan_workspace(const mcmc_plan* p) {
   PlanWorkspace w{};
   size_t off = 0;
-  w.queue = off;      off = align_up(off + 4 * sizeof(uint32_t));
+  w.queue = off;      off = align_up(off + kQueueSlots * sizeof(uint32_t));
   w.init_rows = off;  off = align_up(off + (size_t)p->total_rows * sizeof(uint32_t));
   w.init_n = off;     off = align_up(off + (size_t)p->n * 4 * sizeof(int32_t));
   w.S = off;          off = align_up(off + (size_t)p->total_chains * sizeof(int64_t));
@@ -110,7 +110,7 @@ int enqueue(mcmc_plan* p, const uint8_t* syn, double* prob, double* mean_n, int6
   int32_t* nf = (int32_t*)(ws + wl.n_final);
   uint32_t* final_rows = correction ? (uint32_t*)(ws + wl.final_rows) : nullptr;
 
-  int st = hip_status(launch_zero(queue, 4, s));
+  int st = hip_status(launch_zero(queue, kQueueSlots, s));
   if (st != MCMC_OK) return st;
   StartArgs sa{};
   sa.syn = syn;
@@ -317,6 +317,7 @@ int mcmc_plan_create(const mcmc_item* items, int64_t n, uint64_t seed, uint32_t 
       it.beta_bar = beta_bar(src.p);
       it.sid = src.syndrome_id;
       it.group = gid;
+      it.err_thr = (uint32_t)floor(ldexp(src.p, 32));
       p->tables.resize(p->tables.size() + 4 * (size_t)src.n_temps);
       fill_table(src.p, src.n_temps, p->tables.data() + it.table_off);
       p->items.push_back(it);
@@ -462,6 +463,16 @@ int mcmc_plan_graph_launch(mcmc_plan* p, const uint8_t* syndromes, double* class
     p->graphs.push_back(GraphEntry{key, exec});
   }
   return hip_status(hipGraphLaunch(exec, (hipStream_t)stream));
+}
+
+int mcmc_plan_sample(const mcmc_plan* p, uint64_t seed, uint8_t* syndromes, uint8_t* true_class,
+                     void* stream) {
+  if (!p) return MCMC_EINVAL;
+  if (p->n == 0) return MCMC_OK;
+  if (!syndromes || !true_class) return MCMC_EINVAL;
+  return hip_status(launch_sample_items(p->d_items, p->d_groups, p->n,
+                                        (uint32_t)(seed & 0xFFFFFFFFull), (uint32_t)(seed >> 32),
+                                        syndromes, true_class, (hipStream_t)stream));
 }
 
 int mcmc_plan_autotune(mcmc_plan* p, const uint8_t* syndromes, double* class_prob,

@@ -1,4 +1,5 @@
-"""Seeded synthetic inputs shared by the oracle and the HIP path.
+"""Seeded synthetic inputs shared by the tests (oracle and HIP path alike)
+and the benchmark.
 
 Holds none of the decoder's arithmetic: only numpy's own generator (PCG64)
 for uniformly random syndrome bits (every bit string is a valid planar-code

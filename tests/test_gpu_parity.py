@@ -17,7 +17,7 @@ torch = pytest.importorskip("torch")
 import paper_1302_2669_amd as mc  # noqa: E402
 from oracle import decoder, geometry, init, sampler  # noqa: E402
 
-from inputs import uniform_syndromes, SEED_SMALL, SEED_L9, SEED_METRIC  # noqa: E402
+from paper_1302_2669_amd.inputs import uniform_syndromes, SEED_SMALL, SEED_L9, SEED_METRIC  # noqa: E402
 
 DEV = "cuda"
 RTOL = 1e-12
