@@ -1,0 +1,169 @@
+"""Float64 reference of the gate network (not part of the paper: the learned
+budget gate grown on the decoder), forward and backward.
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).
+
+Network over an L x L grid, channels last:
+  input  3 planes: lit stars (i, j) at (y, x) = (i, j) (row L-1 empty), lit
+         plaquettes (i, j) at (i, j) (column L-1 empty), and p everywhere
+  conv1  3 -> 32, 3x3, zero padding, bias, ReLU
+  conv2  32 -> 32, same
+  conv3  32 -> 32, same
+  head   linear over the flattened conv3 output (feature f = pixel*32 + c)
+         -> 7 logits: 4 class logits, 3 budget logits ({0, L, L^2} sweeps)
+Tap t = (dy+1)*3 + (dx+1).  Weights: W[c_out][tap][c_in].
+
+Loss per sample: soft cross-entropy of the class logits against the MCMC
+class probabilities, plus w_b times the cross-entropy of the budget logits
+against the budget label; averaged over the batch.
+
+`bf16=True` reproduces the rounding points of the GPU kernels (operands of
+every matrix product in bfloat16, round-to-nearest-even; accumulation exact
+here): input p, all weights used in products, the ReLU outputs, and the
+back-propagated pre-activation gradients of the three convolutions.  With
+bf16=False everything is plain float64 (used for the finite-difference pin).
+"""
+
+import numpy as np
+
+C = 32
+TAPS = [(dy, dx) for dy in (-1, 0, 1) for dx in (-1, 0, 1)]
+
+
+def to_bf16(x):
+    """Round float64 values to the nearest bfloat16 (8 significant bits, ties
+    to even) and return them as float64."""
+    x = np.asarray(x, dtype=np.float64)
+    m, e = np.frexp(x)                       # x = m 2^e, 0.5 <= |m| < 1
+    return np.ldexp(np.rint(np.ldexp(m, 8)), e - 8)
+
+
+def param_shapes(L):
+    return [("W1", (C, 9, 3)), ("b1", (C,)), ("W2", (C, 9, C)), ("b2", (C,)),
+            ("W3", (C, 9, C)), ("b3", (C,)), ("Wh", (7, L * L * C)), ("bh", (7,))]
+
+
+def unflatten(L, flat):
+    out, off = {}, 0
+    for name, shape in param_shapes(L):
+        size = int(np.prod(shape))
+        out[name] = np.asarray(flat[off:off + size], dtype=np.float64).reshape(shape)
+        off += size
+    return out
+
+
+def flatten(L, params):
+    return np.concatenate([np.asarray(params[n], dtype=np.float64).reshape(-1)
+                           for n, _ in param_shapes(L)])
+
+
+def encode(L, syndromes, p):
+    """[B, L, L, 3] float64 input planes (before any rounding)."""
+    syn = np.asarray(syndromes, dtype=np.float64)
+    B = syn.shape[0]
+    ns = L * (L - 1)
+    x = np.zeros((B, L, L, 3))
+    x[:, :L - 1, :, 0] = syn[:, :ns].reshape(B, L - 1, L)
+    x[:, :, :L - 1, 1] = syn[:, ns:].reshape(B, L, L - 1)
+    x[:, :, :, 2] = np.asarray(p, dtype=np.float64)[:, None, None]
+    return x
+
+
+def _shift(x, dy, dx):
+    """out[b, y, x] = x[b, y+dy, x+dx] with zeros outside."""
+    B, H, W, Cc = x.shape
+    out = np.zeros_like(x)
+    ys, ye = max(0, -dy), min(H, H - dy)
+    xs, xe = max(0, -dx), min(W, W - dx)
+    out[:, ys:ye, xs:xe] = x[:, ys + dy:ye + dy, xs + dx:xe + dx]
+    return out
+
+
+def conv(x, W, b):
+    """y[b,y,x,co] = sum_{tap,ci} x[b, y+dy, x+dx, ci] W[co, tap, ci] + b[co]."""
+    y = np.zeros(x.shape[:3] + (W.shape[0],))
+    for t, (dy, dx) in enumerate(TAPS):
+        y += _shift(x, dy, dx) @ W[:, t, :].T
+    return y + b
+
+
+def forward(L, params, syndromes, p, bf16=True):
+    r = to_bf16 if bf16 else (lambda v: np.asarray(v, dtype=np.float64))
+    P = {k: (r(v) if k.startswith("W") else np.asarray(v, dtype=np.float64))
+         for k, v in params.items()}
+    x0 = r(encode(L, syndromes, p))
+    a1 = r(np.maximum(conv(x0, P["W1"], P["b1"]), 0.0))
+    a2 = r(np.maximum(conv(a1, P["W2"], P["b2"]), 0.0))
+    a3 = r(np.maximum(conv(a2, P["W3"], P["b3"]), 0.0))
+    B = x0.shape[0]
+    flat = a3.reshape(B, -1)
+    logits = flat @ P["Wh"].T + P["bh"]
+    return logits, dict(x0=x0, a1=a1, a2=a2, a3=a3, P=P)
+
+
+def _softmax(z):
+    z = z - z.max(axis=1, keepdims=True)
+    e = np.exp(z)
+    return e / e.sum(axis=1, keepdims=True)
+
+
+def loss_and_dlogits(logits, class_target, budget_target, budget_weight):
+    B = logits.shape[0]
+    pc = _softmax(logits[:, :4])
+    pb = _softmax(logits[:, 4:7])
+    t = np.asarray(class_target, dtype=np.float64)
+    y = np.asarray(budget_target, dtype=np.int64)
+    lc = -(t * np.log(pc)).sum(axis=1)
+    lb = -np.log(pb[np.arange(B), y])
+    loss = (lc + budget_weight * lb).mean()
+    dz = np.zeros_like(logits)
+    dz[:, :4] = (pc - t) / B
+    onehot = np.zeros((B, 3))
+    onehot[np.arange(B), y] = 1.0
+    dz[:, 4:7] = budget_weight * (pb - onehot) / B
+    return loss, dz, lc + budget_weight * lb
+
+
+def _conv_backward(x, dpre, W):
+    """Gradients of conv(x, W, b) given dL/d(pre-activation)."""
+    dW = np.zeros_like(W)
+    for t, (dy, dx) in enumerate(TAPS):
+        xs = _shift(x, dy, dx)
+        dW[:, t, :] = np.einsum("byxo,byxi->oi", dpre, xs)
+    db = dpre.sum(axis=(0, 1, 2))
+    dx_ = np.zeros(x.shape)
+    for t, (dy, dx) in enumerate(TAPS):
+        dx_ += _shift(dpre, -dy, -dx) @ W[:, t, :]
+    return dW, db, dx_
+
+
+def backward(L, params, syndromes, p, class_target, budget_target, budget_weight=0.5, bf16=True):
+    """(loss, per-sample losses, grads dict, logits)."""
+    r = to_bf16 if bf16 else (lambda v: np.asarray(v, dtype=np.float64))
+    logits, st = forward(L, params, syndromes, p, bf16)
+    loss, dz, per = loss_and_dlogits(logits, class_target, budget_target, budget_weight)
+    P = st["P"]
+    B = logits.shape[0]
+    a3f = st["a3"].reshape(B, -1)
+    g = {"Wh": dz.T @ a3f, "bh": dz.sum(axis=0)}
+    da3 = (dz @ P["Wh"]).reshape(st["a3"].shape)
+    dpre3 = r(da3 * (st["a3"] > 0))
+    g["W3"], g["b3"], da2 = _conv_backward(st["a2"], dpre3, P["W3"])
+    dpre2 = r(da2 * (st["a2"] > 0))
+    g["W2"], g["b2"], da1 = _conv_backward(st["a1"], dpre2, P["W2"])
+    dpre1 = r(da1 * (st["a1"] > 0))
+    g["W1"], g["b1"], _ = _conv_backward(st["x0"], dpre1, P["W1"])
+    return loss, per, g, logits
+
+
+def adam(params, grads, m, v, lr, beta1, beta2, eps, step):
+    """One Adam step (bias-corrected), element by element, float64."""
+    out_p, out_m, out_v = {}, {}, {}
+    for k in params:
+        mm = beta1 * m[k] + (1 - beta1) * grads[k]
+        vv = beta2 * v[k] + (1 - beta2) * grads[k] ** 2
+        mh = mm / (1 - beta1 ** step)
+        vh = vv / (1 - beta2 ** step)
+        out_p[k] = params[k] - lr * mh / (np.sqrt(vh) + eps)
+        out_m[k], out_v[k] = mm, vv
+    return out_p, out_m, out_v

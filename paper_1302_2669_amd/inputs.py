@@ -31,3 +31,20 @@ def mixed_workload(n, seed, Ls=(5, 7, 9, 11, 13, 15, 17, 19, 21, 23, 25), p_lo=0
     L = rng.choice(np.asarray(Ls), size=n)
     p = p_lo + (p_hi - p_lo) * rng.random(n)
     return L.astype(np.int32), p, (L * L).astype(np.int32)
+
+
+def cnn_init(L, seed, channels=32):
+    """Initial gate-network parameters as one float32 vector, in the order
+    W1 [32][9][3], b1 [32], W2 [32][9][32], b2, W3 [32][9][32], b3,
+    Wh [7][L*L*32], bh [7]: He-normal weights, zero biases."""
+    rng = np.random.default_rng(seed)
+    shapes = [(channels, 9, 3), (channels,), (channels, 9, channels), (channels,),
+              (channels, 9, channels), (channels,), (7, L * L * channels), (7,)]
+    parts = []
+    for k, shape in enumerate(shapes):
+        if k % 2 == 1:
+            parts.append(np.zeros(shape, dtype=np.float32).reshape(-1))
+        else:
+            fan_in = int(np.prod(shape[1:]))
+            parts.append(rng.normal(0.0, np.sqrt(2.0 / fan_in), size=shape).astype(np.float32).reshape(-1))
+    return np.concatenate(parts)

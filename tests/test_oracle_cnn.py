@@ -1,0 +1,86 @@
+"""Pins for the gate network's float64 reference: analytic gradients against
+central finite differences, the bf16 rounding helper against its definition,
+Adam against a closed-form first step, and the layout against the shapes."""
+
+import numpy as np
+import pytest
+
+from oracle import cnn
+from paper_1302_2669_amd.inputs import cnn_init, uniform_syndromes
+
+
+def test_bf16_rounding():
+    """bfloat16 keeps 8 significant bits: the spacing above 1 is 2^-7."""
+    u = 2.0 ** -7
+    cases = [(1.0, 1.0), (1 + u, 1 + u), (1 + u / 2, 1.0),            # tie -> even
+             (1 + 3 * u / 2, 1 + 2 * u),                                # tie -> even
+             (1 + u / 2 + 1e-9, 1 + u), (-(1 + 0.7 * u), -(1 + u)),
+             (3.0, 3.0), (0.0, 0.0), (2.0 ** -20 * (1 + u / 4), 2.0 ** -20)]
+    for x, want in cases:
+        assert cnn.to_bf16(x) == want, x
+    # agrees with truncating the float32 bit pattern when the dropped bits are 0
+    rng = np.random.default_rng(3)
+    v = rng.standard_normal(1000).astype(np.float32)
+    exact = (v.view(np.uint32) & 0xFFFF0000).view(np.float32).astype(np.float64)
+    assert np.array_equal(cnn.to_bf16(exact), exact)
+
+
+def test_layout_matches_init():
+    L = 5
+    flat = cnn_init(L, 1)
+    n = sum(int(np.prod(s)) for _, s in cnn.param_shapes(L))
+    assert flat.size == n
+    P = cnn.unflatten(L, flat)
+    assert np.array_equal(cnn.flatten(L, P), flat.astype(np.float64))
+    assert not P["b1"].any() and P["W2"].std() > 0
+
+
+@pytest.mark.parametrize("L", [3, 4])
+def test_gradients_against_finite_differences(L):
+    B = 3
+    flat = cnn_init(L, 7).astype(np.float64)
+    syn = uniform_syndromes(L, B, seed=L, density=0.4)
+    p = np.array([0.05, 0.11, 0.17])
+    rng = np.random.default_rng(0)
+    t = rng.dirichlet(np.ones(4), size=B)
+    y = rng.integers(0, 3, size=B)
+    # move biases off zero so that every ReLU is away from its kink
+    flat = flat + 0.01 * rng.standard_normal(flat.size)
+    P = cnn.unflatten(L, flat)
+    loss, _, g, _ = cnn.backward(L, P, syn, p, t, y, 0.7, bf16=False)
+    gflat = cnn.flatten(L, g)
+
+    def f(v):
+        return cnn.backward(L, cnn.unflatten(L, v), syn, p, t, y, 0.7, bf16=False)[0]
+
+    eps = 1e-6
+    idx = np.concatenate([rng.choice(flat.size, 40, replace=False),
+                          [0, 864 + 3, flat.size - 1, flat.size - 8]])
+    for i in idx:
+        e = np.zeros_like(flat)
+        e[i] = eps
+        fd = (f(flat + e) - f(flat - e)) / (2 * eps)
+        assert abs(fd - gflat[i]) <= 1e-6 * max(1.0, abs(fd)), (i, fd, gflat[i])
+    d = rng.standard_normal(flat.size)
+    d /= np.linalg.norm(d)
+    fd = (f(flat + eps * d) - f(flat - eps * d)) / (2 * eps)
+    assert abs(fd - gflat @ d) <= 1e-6 * max(1.0, abs(fd))
+
+
+def test_loss_closed_form():
+    """Uniform logits: loss = log 4 + w log 3 for any targets."""
+    z = np.zeros((5, 7))
+    t = np.random.default_rng(1).dirichlet(np.ones(4), size=5)
+    loss, dz, _ = cnn.loss_and_dlogits(z, t, np.array([0, 1, 2, 0, 1]), 0.5)
+    assert loss == pytest.approx(np.log(4) + 0.5 * np.log(3), rel=1e-14)
+    assert np.allclose(dz[:, :4].sum(axis=1), 0) and np.allclose(dz[:, 4:].sum(axis=1), 0)
+
+
+def test_adam_first_step():
+    """With bias correction the first step moves every weight by lr*sign(g)
+    (up to eps)."""
+    p = {"w": np.array([1.0, -2.0, 3.0])}
+    g = {"w": np.array([0.5, -1e-3, 2.0])}
+    z = {"w": np.zeros(3)}
+    out, m, v = cnn.adam(p, g, z, z, 0.01, 0.9, 0.999, 1e-12, 1)
+    assert np.allclose(out["w"], p["w"] - 0.01 * np.sign(g["w"]), atol=1e-9)
