@@ -237,6 +237,10 @@ typedef struct mcmc_plan mcmc_plan; /* opaque */
 int mcmc_plan_create(const mcmc_item* h_items, int64_t n, uint64_t seed, uint32_t init,
                      mcmc_plan** plan);
 int mcmc_plan_destroy(mcmc_plan* plan);
+/* Replace the plan's items (same rules as mcmc_plan_create; seed, init and
+ * tuning kept).  Reuses the plan's device tables when they are large enough,
+ * else reallocates them; recorded graphs are dropped.  Synchronous copies. */
+int mcmc_plan_rebuild(mcmc_plan* plan, const mcmc_item* h_items, int64_t n);
 
 /* Total chains (length of the per-chain outputs), workspace bytes, and the
  * number of stabilizer updates one execution performs.  Any pointer may be NULL. */
@@ -279,6 +283,128 @@ int mcmc_plan_autotune(mcmc_plan* plan, const uint8_t* d_syndromes, double* d_cl
                        double* d_mean_n, int64_t* d_sum_n, int64_t* d_accepts, uint8_t* d_chosen,
                        uint8_t* d_correction, void* d_workspace, size_t workspace_bytes,
                        void* stream, const char* cache_path, mcmc_tuning* h_result);
+
+/*
+ * Gate network.  Not part of the paper's method: a small convolutional
+ * network over the syndrome of one code size, trained on the decoder's own
+ * class probabilities, that predicts the four class log-probabilities and a
+ * sweep budget (0, short, full) so that easy syndromes skip most or all of
+ * the Metropolis sweeps.  The chains themselves are unchanged.
+ *
+ *  Input    [L][L][3] planes per syndrome: lit star (i, j) at (i, j) (row L-1
+ *           empty), lit plaquette (i, j) at (i, j) (column L-1 empty), and
+ *           the syndrome's depolarizing rate p in every cell.
+ *  Body     three 3x3 convolutions with 32 channels, zero padding, bias and
+ *           ReLU; tap t = 3(dy+1) + (dx+1), weights W[c_out][t][c_in].
+ *  Head     linear map of the flattened last activation (feature =
+ *           (y L + x) 32 + c) to 7 logits: classes 0..3, budgets 0..2.
+ *  Params   one fp32 vector in the order W1 [32][9][3], b1 [32], W2
+ *           [32][9][32], b2, W3 [32][9][32], b3, Wh [7][32 L^2], bh [7]
+ *           (mcmc_cnn_param_count floats).
+ *  Numerics every matrix product takes bfloat16 operands (weights, input
+ *           planes, ReLU outputs and back-propagated pre-activation
+ *           gradients rounded to nearest even) with fp32 accumulation on the
+ *           matrix cores; biases, logits, loss, gradients and the optimizer
+ *           are fp32.  Every reduction has a fixed order: results do not
+ *           depend on the launch or on timing.
+ */
+#define MCMC_CNN_BATCH_MAX (1 << 24)
+
+/* Number of fp32 parameters for distance L. */
+int mcmc_cnn_param_count(int32_t L, int64_t* h_count);
+/* Device workspace bytes of mcmc_cnn_forward / mcmc_cnn_backward for a batch. */
+int mcmc_cnn_workspace_size(int32_t L, int64_t batch, size_t* h_bytes);
+/* Byte offsets in that workspace of the bfloat16 [batch L^2][channels]
+ * tensors x0 (8 channels, 3 used), a1, a2, a3 (the three ReLU outputs) and
+ * the pre-activation gradients of conv3, conv2, conv1 (32 channels), in that
+ * order, h_offsets[7].  For inspection in tests. */
+int mcmc_cnn_workspace_offsets(int32_t L, int64_t batch, int64_t* h_offsets);
+
+/*
+ * Forward pass: d_syndromes [batch][n_stab] uint8, d_p [batch] fp32,
+ * d_params as above, d_logits [batch][8] fp32 (entries 0..6 written; 7 is
+ * left as is).  The workspace keeps the activations for mcmc_cnn_backward.
+ */
+int mcmc_cnn_forward(int32_t L, int64_t batch, const float* d_params, const uint8_t* d_syndromes,
+                     const float* d_p, float* d_logits, void* d_workspace, size_t workspace_bytes,
+                     void* stream);
+
+/*
+ * Loss and gradients of the batch just run forward (same L, batch, params,
+ * inputs and workspace, in stream order).  Loss per sample: soft
+ * cross-entropy of the class logits against d_class_target [batch][4] fp32
+ * plus budget_weight times the cross-entropy of the budget logits against
+ * d_budget [batch] int32 in 0..2 (values outside are clamped); the objective
+ * is the batch mean.  d_grads [param_count] fp32 receives its gradient;
+ * d_loss [batch] fp32 the per-sample losses, or NULL.
+ */
+int mcmc_cnn_backward(int32_t L, int64_t batch, const float* d_params, const float* d_logits,
+                      const float* d_class_target, const int32_t* d_budget, float budget_weight,
+                      float* d_grads, float* d_loss, void* d_workspace, size_t workspace_bytes,
+                      void* stream);
+
+/* One Adam step number `step` (>= 1) over n_params floats, in place on
+ * d_params, d_m, d_v: m = b1 m + (1-b1) g, v = b2 v + (1-b2) g^2,
+ * w -= lr (m / (1-b1^step)) / (sqrt(v / (1-b2^step)) + eps). */
+int mcmc_cnn_step(int64_t n_params, int64_t step, float lr, float beta1, float beta2, float eps,
+                  float* d_params, const float* d_grads, float* d_m, float* d_v, void* stream);
+
+/*
+ * Gate from logits [batch][8]: d_class = argmax of the class logits (ties to
+ * the lowest), d_confidence = its softmax probability (or NULL), budget =
+ * argmax of the budget logits; d_route = budget when the confidence is at
+ * least `threshold`, else 2 (full budget).
+ */
+int mcmc_cnn_gate(int64_t batch, const float* d_logits, float threshold, uint8_t* d_route,
+                  uint8_t* d_class, float* d_confidence, void* stream);
+
+/*
+ * Gated decoder for one code size: the network runs on the whole batch, then
+ * each syndrome takes its route: 0 = the network's class (correction: that
+ * class's start configuration), 1 = the Metropolis decoder with sweeps_short
+ * counted sweeps, 2 = with sweeps_full.  Routes 1 and 2 run as one mixed plan
+ * (one persistent launch of both budgets); their results are exactly those
+ * of mcmc_decode_batch with the syndrome's p, id and budget.
+ */
+typedef struct mcmc_gate_config {
+  int32_t L;            /* code distance                                           */
+  int32_t n_temps;      /* K of the Metropolis routes (1 or even)                  */
+  int32_t chains;       /* chains per class and temperature                        */
+  int32_t burn;         /* uncounted sweeps                                        */
+  int32_t sweeps_short; /* counted sweeps of route 1                               */
+  int32_t sweeps_full;  /* counted sweeps of route 2                               */
+  double p;             /* rate used when no per-syndrome rates are given          */
+  uint64_t seed;        /* Philox key of the chains                                */
+  uint32_t init;        /* MCMC_INIT_CANONICAL or MCMC_INIT_MATCHING                */
+  float threshold;      /* minimum class confidence for routes 0 and 1            */
+  int64_t max_batch;    /* largest batch a call may pass                           */
+} mcmc_gate_config;
+
+typedef struct mcmc_gated mcmc_gated; /* opaque */
+
+/* Build a gated decoder; allocates its plan's device tables (sized for
+ * max_batch syndromes) and pinned host staging buffers. */
+int mcmc_gated_create(const mcmc_gate_config* h_cfg, mcmc_gated** gated);
+int mcmc_gated_destroy(mcmc_gated* gated);
+/* Device workspace bytes of mcmc_gated_decode (any batch up to max_batch). */
+int mcmc_gated_workspace_size(const mcmc_gated* gated, size_t* h_bytes);
+/* The decoder's internal plan (for mcmc_plan_set_tuning / get_tuning). */
+int mcmc_gated_plan(mcmc_gated* gated, mcmc_plan** h_plan);
+
+/*
+ * Decode n <= max_batch syndromes d_syndromes [n][n_stab] with network
+ * parameters d_params.  h_ids [n] host syndrome ids (NULL => i), h_p [n] host
+ * rates (NULL => the configured p).  Outputs: d_chosen [n] (required),
+ * d_route [n] and d_logits [n][8] (or NULL), d_correction [n][n_q] (or NULL),
+ * h_counts [3] syndromes per route (or NULL).  Synchronous: it waits for the
+ * gate before building the Metropolis plan, and returns with the stream
+ * drained.
+ */
+int mcmc_gated_decode(mcmc_gated* gated, const float* d_params, const uint8_t* d_syndromes,
+                      const uint32_t* h_ids, const double* h_p, int64_t n, uint8_t* d_chosen,
+                      uint8_t* d_route, float* d_logits, uint8_t* d_correction,
+                      int64_t* h_counts, void* d_workspace, size_t workspace_bytes,
+                      void* stream);
 
 #ifdef __cplusplus
 }

@@ -33,11 +33,18 @@ def _stream(device=None):
     return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
 
 
+_GEOMETRY = {}
+
+
 def geometry(L):
     """(n_qubits, n_stab) of a distance-L code."""
-    nq, ns = ctypes.c_int32(), ctypes.c_int32()
-    _lib.check(_lib._lib().mcmc_geometry(L, ctypes.byref(nq), ctypes.byref(ns)), "mcmc_geometry")
-    return nq.value, ns.value
+    L = int(L)
+    if L not in _GEOMETRY:
+        nq, ns = ctypes.c_int32(), ctypes.c_int32()
+        _lib.check(_lib._lib().mcmc_geometry(L, ctypes.byref(nq), ctypes.byref(ns)),
+                   "mcmc_geometry")
+        _GEOMETRY[L] = (nq.value, ns.value)
+    return _GEOMETRY[L]
 
 
 def lattice(L):

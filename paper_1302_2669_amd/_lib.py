@@ -18,6 +18,7 @@ MCMC_L_MIN, MCMC_L_MAX = 2, 25
 MCMC_TEMPS_MAX = 64
 MCMC_TRACE, MCMC_RESUME = 1, 2
 MCMC_INIT_CANONICAL, MCMC_INIT_MATCHING = 0, 1
+MCMC_CNN_BATCH_MAX = 1 << 24
 
 
 class McmcError(RuntimeError):
@@ -65,6 +66,22 @@ class Tuning(ctypes.Structure):
     ]
 
 
+class GateConfig(ctypes.Structure):
+    _fields_ = [
+        ("L", ctypes.c_int32),
+        ("n_temps", ctypes.c_int32),
+        ("chains", ctypes.c_int32),
+        ("burn", ctypes.c_int32),
+        ("sweeps_short", ctypes.c_int32),
+        ("sweeps_full", ctypes.c_int32),
+        ("p", ctypes.c_double),
+        ("seed", ctypes.c_uint64),
+        ("init", ctypes.c_uint32),
+        ("threshold", ctypes.c_float),
+        ("max_batch", ctypes.c_int64),
+    ]
+
+
 _P = ctypes.c_void_p
 _I32, _I64, _U32, _U64, _D, _SZ = (ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32,
                                    ctypes.c_uint64, ctypes.c_double, ctypes.c_size_t)
@@ -88,6 +105,7 @@ _SIGNATURES = {
     "mcmc_plan_create": (ctypes.c_int, [ctypes.POINTER(Item), _I64, _U64, _U32,
                                         ctypes.POINTER(_P)]),
     "mcmc_plan_destroy": (ctypes.c_int, [_P]),
+    "mcmc_plan_rebuild": (ctypes.c_int, [_P, ctypes.POINTER(Item), _I64]),
     "mcmc_plan_info": (ctypes.c_int, [_P, ctypes.POINTER(_I64), _PSZ, ctypes.POINTER(_I64)]),
     "mcmc_plan_get_tuning": (ctypes.c_int, [_P, ctypes.POINTER(Tuning)]),
     "mcmc_plan_set_tuning": (ctypes.c_int, [_P, ctypes.POINTER(Tuning)]),
@@ -96,6 +114,21 @@ _SIGNATURES = {
     "mcmc_plan_sample": (ctypes.c_int, [_P, _U64, _P, _P, _P]),
     "mcmc_plan_autotune": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P, _P, _P, _SZ, _P,
                                           ctypes.c_char_p, ctypes.POINTER(Tuning)]),
+    "mcmc_cnn_param_count": (ctypes.c_int, [_I32, ctypes.POINTER(_I64)]),
+    "mcmc_cnn_workspace_size": (ctypes.c_int, [_I32, _I64, _PSZ]),
+    "mcmc_cnn_workspace_offsets": (ctypes.c_int, [_I32, _I64, ctypes.POINTER(_I64)]),
+    "mcmc_cnn_forward": (ctypes.c_int, [_I32, _I64, _P, _P, _P, _P, _P, _SZ, _P]),
+    "mcmc_cnn_backward": (ctypes.c_int, [_I32, _I64, _P, _P, _P, _P, ctypes.c_float, _P, _P, _P,
+                                         _SZ, _P]),
+    "mcmc_cnn_step": (ctypes.c_int, [_I64, _I64, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                     ctypes.c_float, _P, _P, _P, _P, _P]),
+    "mcmc_cnn_gate": (ctypes.c_int, [_I64, _P, ctypes.c_float, _P, _P, _P, _P]),
+    "mcmc_gated_create": (ctypes.c_int, [ctypes.POINTER(GateConfig), ctypes.POINTER(_P)]),
+    "mcmc_gated_destroy": (ctypes.c_int, [_P]),
+    "mcmc_gated_workspace_size": (ctypes.c_int, [_P, _PSZ]),
+    "mcmc_gated_plan": (ctypes.c_int, [_P, ctypes.POINTER(_P)]),
+    "mcmc_gated_decode": (ctypes.c_int, [_P, _P, _P, _P, _P, _I64, _P, _P, _P, _P,
+                                         ctypes.POINTER(_I64), _P, _SZ, _P]),
 }
 
 _handle = None

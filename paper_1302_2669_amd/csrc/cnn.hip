@@ -1,0 +1,546 @@
+// Gate network kernels: a small convolutional network over the syndrome
+// planes of one code size, trained on the decoder's own class probabilities
+// to predict the class and a sweep budget (the learned-gate pattern grown on
+// the decoder; not part of the paper's method).
+//
+// Layout: activations channels-last [pixel][channel] in bfloat16 (pixel =
+// sample*L*L + y*L + x); master parameters fp32 in the order W1 [32][9][3],
+// b1, W2 [32][9][32], b2, W3 [32][9][32], b3, Wh [7][L*L*32], bh [7].
+// Convolutions are implicit GEMMs on v_mfma_f32_16x16x32_bf16 (bf16 operands,
+// fp32 accumulation): forward M = pixels, N = 32 output channels,
+// K = 9 taps x input channels; backward-data the same with the taps mirrored
+// and the weight roles transposed; weight gradients M = 32, N = taps x input
+// channels, K = pixels, split over pixel chunks and reduced in a fixed order.
+// Lane layout of the 16x16x32 MFMA: lane l holds A[l%16][8(l/16)..+7],
+// B[8(l/16)..+7][l%16] and D[4(l/16)+i][l%16], i = 0..3.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "internal.h"
+
+namespace mcmc {
+namespace {
+
+typedef __bf16 bf16;
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int CH = 32;
+
+__device__ __forceinline__ bf16x8 load8(const bf16* p) {
+  const uint4 v = *reinterpret_cast<const uint4*>(p);
+  return __builtin_bit_cast(bf16x8, v);
+}
+__device__ __forceinline__ bf16x8 zero8() { return __builtin_bit_cast(bf16x8, make_uint4(0, 0, 0, 0)); }
+
+__device__ __forceinline__ f32x4 mfma(bf16x8 a, bf16x8 b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ int tap_dy(int t) { return t / 3 - 1; }
+__device__ __forceinline__ int tap_dx(int t) { return t % 3 - 1; }
+
+// ---- input planes ----------------------------------------------------------
+// x0[pixel][8]: 0 lit star (i, j) at (i, j), 1 lit plaquette (i, j) at (i, j),
+// 2 the sample's p, 3..7 zero.
+__global__ void encode_kernel(int L, int64_t B, const uint8_t* __restrict__ syn,
+                              const float* __restrict__ p, bf16* __restrict__ x0) {
+  const int64_t pix = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t P = B * L * L;
+  if (pix >= P) return;
+  const int64_t b = pix / (L * L);
+  const int r = (int)(pix - b * L * L), y = r / L, x = r % L;
+  const uint8_t* s = syn + b * (int64_t)(2 * L * (L - 1));
+  const int ns = L * (L - 1);
+  const float star = (y < L - 1 && s[y * L + x]) ? 1.0f : 0.0f;
+  const float plaq = (x < L - 1 && s[ns + y * (L - 1) + x]) ? 1.0f : 0.0f;
+  bf16* o = x0 + pix * 8;
+  o[0] = (bf16)star;
+  o[1] = (bf16)plaq;
+  o[2] = (bf16)p[b];
+  for (int c = 3; c < 8; ++c) o[c] = (bf16)0.0f;
+}
+
+// ---- parameter casts -------------------------------------------------------
+// wb1 [32][96] (k = tap*8 + ci, ci < 3), wb2/wb3 [32][288] (k = tap*32 + ci),
+// wt2/wt3 [32 ci][288 (tap*32 + co)] = W[co][tap][ci], whb [16][L*L*32].
+__global__ void cast_kernel(int L, const float* __restrict__ prm, const CnnOffsets off,
+                            bf16* __restrict__ wb1, bf16* __restrict__ wb2, bf16* __restrict__ wb3,
+                            bf16* __restrict__ wt2, bf16* __restrict__ wt3, bf16* __restrict__ whb) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t kh = (int64_t)L * L * CH;
+  if (i < 32 * 96) {
+    const int co = (int)(i / 96), k = (int)(i % 96), tap = k / 8, ci = k % 8;
+    wb1[i] = (bf16)((tap < 9 && ci < 3) ? prm[off.W1 + (co * 9 + tap) * 3 + ci] : 0.0f);
+  }
+  if (i < 32 * 288) {
+    wb2[i] = (bf16)prm[off.W2 + i];
+    wb3[i] = (bf16)prm[off.W3 + i];
+    const int ci = (int)(i / 288), k = (int)(i % 288), tap = k / 32, co = k % 32;
+    wt2[i] = (bf16)prm[off.W2 + (co * 9 + tap) * 32 + ci];
+    wt3[i] = (bf16)prm[off.W3 + (co * 9 + tap) * 32 + ci];
+  }
+  if (i < 16 * kh) {
+    const int o = (int)(i / kh);
+    whb[i] = (bf16)(o < 7 ? prm[off.Wh + i] : 0.0f);
+  }
+}
+
+// ---- convolution as implicit GEMM -------------------------------------------
+// Forward (MIRROR = false): out[p][n] = relu(sum_{tap,ci} in[p + tap][ci] *
+// w[n][tap*CIN + ci] + bias[n]).  Backward data (MIRROR = true): out[p][n] =
+// (sum_{tap,c} in[p - tap][c] * w[n][tap*CIN + c]) * (mask[p][n] > 0).
+// One wave computes 16 pixels x 32 channels; 4 waves per workgroup.
+template <int CIN, bool MIRROR>
+__global__ void __launch_bounds__(256) conv_kernel(int L, int64_t P, const bf16* __restrict__ in,
+                                                   const bf16* __restrict__ w,
+                                                   const float* __restrict__ bias,
+                                                   const bf16* __restrict__ mask,
+                                                   bf16* __restrict__ out) {
+  constexpr int KP = (9 * CIN + 31) / 32 * 32;
+  constexpr int CHUNKS = CIN / 8;
+  const int lane = threadIdx.x & 63;
+  const int64_t tile = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int64_t pm = tile * 16 + (lane & 15);
+  const int LL = L * L;
+  int64_t b = 0;
+  int y = 0, x = 0;
+  if (pm < P) {
+    b = pm / LL;
+    const int r = (int)(pm - b * LL);
+    y = r / L;
+    x = r % L;
+  }
+  f32x4 acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
+  const int grp = lane >> 4;
+  const int n = lane & 15;
+#pragma unroll
+  for (int s = 0; s < KP / 32; ++s) {
+    const int g = 4 * s + grp;
+    const int tap = g / CHUNKS, cc = g % CHUNKS;
+    bf16x8 a = zero8();
+    if (tap < 9 && pm < P) {
+      int dy = tap_dy(tap), dx = tap_dx(tap);
+      if (MIRROR) { dy = -dy; dx = -dx; }
+      const int yy = y + dy, xx = x + dx;
+      if (yy >= 0 && yy < L && xx >= 0 && xx < L)
+        a = load8(in + ((b * LL + yy * L + xx) * CIN + cc * 8));
+    }
+    const bf16x8 b0 = load8(w + (int64_t)n * KP + s * 32 + 8 * grp);
+    const bf16x8 b1 = load8(w + (int64_t)(n + 16) * KP + s * 32 + 8 * grp);
+    acc0 = mfma(a, b0, acc0);
+    acc1 = mfma(a, b1, acc1);
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int64_t po = tile * 16 + 4 * grp + i;
+    if (po >= P) continue;
+    float v0 = acc0[i], v1 = acc1[i];
+    if (!MIRROR) {
+      v0 = fmaxf(v0 + bias[n], 0.0f);
+      v1 = fmaxf(v1 + bias[n + 16], 0.0f);
+    } else {
+      v0 = (float)mask[po * CH + n] > 0.0f ? v0 : 0.0f;
+      v1 = (float)mask[po * CH + n + 16] > 0.0f ? v1 : 0.0f;
+    }
+    out[po * CH + n] = (bf16)v0;
+    out[po * CH + n + 16] = (bf16)v1;
+  }
+}
+
+// ---- weight gradients: partial sums over one chunk of 256 pixels ----------
+// part[chunk][co][c] = sum_{p in chunk} dpre[p][co] * in[p + tap(c)][ci(c)],
+// c = tap*CIN + ci < 9*CIN (columns up to KP are zero).
+constexpr int WG_CHUNK = 256;
+
+template <int CIN>
+__global__ void __launch_bounds__(256) conv_wgrad_kernel(int L, int64_t P,
+                                                         const bf16* __restrict__ dpre,
+                                                         const bf16* __restrict__ in,
+                                                         float* __restrict__ part,
+                                                         float* __restrict__ partb) {
+  constexpr int KP = (9 * CIN + 31) / 32 * 32;
+  constexpr int NT = KP / 16;          // column tiles
+  constexpr int TILES = 2 * NT;        // x 2 row tiles of 16 output channels
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int grp = lane >> 4, n = lane & 15;
+  const int64_t chunk = blockIdx.x;
+  const int64_t p0 = chunk * WG_CHUNK;
+  const int LL = L * L;
+  for (int t = wave; t < TILES; t += 4) {
+    const int mt = t / NT, nt = t % NT;
+    const int co = mt * 16 + n;                  // A row of this lane
+    const int c = nt * 16 + n;                   // B column of this lane
+    const int tap = c / CIN, ci = c % CIN;
+    const bool col_ok = c < 9 * CIN;
+    const int dy = col_ok ? tap_dy(tap) : 0, dx = col_ok ? tap_dx(tap) : 0;
+    f32x4 acc = {0, 0, 0, 0};
+#pragma unroll 1
+    for (int s = 0; s < WG_CHUNK / 32; ++s) {
+      bf16x8 a, bb;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int64_t p = p0 + s * 32 + 8 * grp + j;
+        bf16 av = (bf16)0.0f, bv = (bf16)0.0f;
+        if (p < P) {
+          av = dpre[p * CH + co];
+          if (col_ok) {
+            const int64_t b = p / LL;
+            const int r = (int)(p - b * LL), y = r / L + dy, x = r % L + dx;
+            if (y >= 0 && y < L && x >= 0 && x < L) bv = in[(b * LL + y * L + x) * CIN + ci];
+          }
+        }
+        a[j] = av;
+        bb[j] = bv;
+      }
+      acc = mfma(a, bb, acc);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int orow = mt * 16 + 4 * grp + i;
+      part[(chunk * CH + orow) * KP + nt * 16 + n] = acc[i];
+    }
+  }
+  // bias partials: 8 runs of 32 pixels per channel, then summed in run order
+  __shared__ float runs[8][CH];
+  {
+    const int co = threadIdx.x & 31, run = threadIdx.x >> 5;
+    float s = 0.0f;
+    for (int j = 0; j < 32; ++j) {
+      const int64_t p = p0 + run * 32 + j;
+      if (p < P) s += (float)dpre[p * CH + co];
+    }
+    runs[run][co] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x < CH) {
+    float s = 0.0f;
+    for (int r = 0; r < 8; ++r) s += runs[r][threadIdx.x];
+    partb[chunk * CH + threadIdx.x] = s;
+  }
+}
+
+// grad W[co][tap][ci] (ci < cin_real) and grad b[co]: sums of the chunk
+// partials in chunk order.
+template <int CIN>
+__global__ void wgrad_reduce_kernel(int64_t chunks, int cin_real, const float* __restrict__ part,
+                                    const float* __restrict__ partb, float* __restrict__ gW,
+                                    float* __restrict__ gb) {
+  constexpr int KP = (9 * CIN + 31) / 32 * 32;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < CH * 9 * cin_real) {
+    const int co = i / (9 * cin_real), rem = i % (9 * cin_real);
+    const int tap = rem / cin_real, ci = rem % cin_real;
+    const int c = tap * CIN + ci;
+    float s = 0.0f;
+    for (int64_t k = 0; k < chunks; ++k) s += part[(k * CH + co) * KP + c];
+    gW[i] = s;
+  }
+  if (i < CH) {
+    float s = 0.0f;
+    for (int64_t k = 0; k < chunks; ++k) s += partb[k * CH + i];
+    gb[i] = s;
+  }
+}
+
+// ---- head ----------------------------------------------------------------
+// logits[b][o] = sum_f a3[b][f] * whb[o][f] + bh[o], o < 7; 16 samples per wave.
+__global__ void __launch_bounds__(256) head_fwd_kernel(int L, int64_t B, const bf16* __restrict__ a3,
+                                                       const bf16* __restrict__ whb,
+                                                       const float* __restrict__ bh,
+                                                       float* __restrict__ logits) {
+  const int lane = threadIdx.x & 63, grp = lane >> 4, n = lane & 15;
+  const int64_t tile = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int64_t bm = tile * 16 + n;
+  const int64_t kh = (int64_t)L * L * CH;
+  f32x4 acc = {0, 0, 0, 0};
+#pragma unroll 1
+  for (int64_t k = 0; k < kh; k += 32) {
+    const bf16x8 a = bm < B ? load8(a3 + bm * kh + k + 8 * grp) : zero8();
+    const bf16x8 b = load8(whb + (int64_t)n * kh + k + 8 * grp);
+    acc = mfma(a, b, acc);
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int64_t bo = tile * 16 + 4 * grp + i;
+    if (bo < B && n < 7) logits[bo * 8 + n] = acc[i] + bh[n];
+  }
+}
+
+// Loss and dL/dlogits per sample (soft cross-entropy on the 4 class logits,
+// weighted cross-entropy on the 3 budget logits), averaged over the batch.
+__global__ void loss_kernel(int64_t B, const float* __restrict__ logits,
+                            const float* __restrict__ tgt, const int32_t* __restrict__ budget,
+                            float wb, float* __restrict__ dz, float* __restrict__ loss) {
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= B) return;
+  const float* z = logits + b * 8;
+  float m = fmaxf(fmaxf(z[0], z[1]), fmaxf(z[2], z[3]));
+  float e[4], se = 0.0f;
+  for (int k = 0; k < 4; ++k) { e[k] = expf(z[k] - m); se += e[k]; }
+  float lc = 0.0f;
+  for (int k = 0; k < 4; ++k) {
+    const float pk = e[k] / se;
+    lc -= tgt[b * 4 + k] * ((z[k] - m) - logf(se));
+    dz[b * 8 + k] = (pk - tgt[b * 4 + k]) / (float)B;
+  }
+  const float mb = fmaxf(fmaxf(z[4], z[5]), z[6]);
+  float eb[3], sb = 0.0f;
+  for (int k = 0; k < 3; ++k) { eb[k] = expf(z[4 + k] - mb); sb += eb[k]; }
+  const int y = min(max(budget[b], 0), 2);
+  const float lb = -((z[4 + y] - mb) - logf(sb));
+  for (int k = 0; k < 3; ++k)
+    dz[b * 8 + 4 + k] = wb * (eb[k] / sb - (k == y ? 1.0f : 0.0f)) / (float)B;
+  dz[b * 8 + 7] = 0.0f;
+  loss[b] = lc + wb * lb;
+}
+
+// grad Wh[o][f] = sum_b dz[b][o] a3[b][f]; grad bh[o] = sum_b dz[b][o].
+__global__ void head_wgrad_kernel(int L, int64_t B, const float* __restrict__ dz,
+                                  const bf16* __restrict__ a3, float* __restrict__ gWh,
+                                  float* __restrict__ gbh) {
+  const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t kh = (int64_t)L * L * CH;
+  if (f < kh) {
+    float s[7] = {0, 0, 0, 0, 0, 0, 0};
+    for (int64_t b = 0; b < B; ++b) {
+      const float a = (float)a3[b * kh + f];
+      for (int o = 0; o < 7; ++o) s[o] += dz[b * 8 + o] * a;
+    }
+    for (int o = 0; o < 7; ++o) gWh[o * kh + f] = s[o];
+  }
+  if (f < 7) {
+    float s = 0.0f;
+    for (int64_t b = 0; b < B; ++b) s += dz[b * 8 + f];
+    gbh[f] = s;
+  }
+}
+
+// dpre3[b][f] = (sum_o dz[b][o] whb[o][f]) * (a3[b][f] > 0), rounded to bf16.
+__global__ void head_dgrad_kernel(int L, int64_t B, const float* __restrict__ dz,
+                                  const bf16* __restrict__ whb, const bf16* __restrict__ a3,
+                                  bf16* __restrict__ dpre) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t kh = (int64_t)L * L * CH;
+  if (i >= B * kh) return;
+  const int64_t b = i / kh, f = i - b * kh;
+  float s = 0.0f;
+  for (int o = 0; o < 7; ++o) s += dz[b * 8 + o] * (float)whb[o * kh + f];
+  dpre[i] = (bf16)((float)a3[i] > 0.0f ? s : 0.0f);
+}
+
+__global__ void adam_kernel(int64_t n, float* __restrict__ prm, const float* __restrict__ g,
+                            float* __restrict__ m, float* __restrict__ v, float lr, float b1,
+                            float b2, float eps, float c1, float c2) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float mm = b1 * m[i] + (1.0f - b1) * g[i];
+  const float vv = b2 * v[i] + (1.0f - b2) * g[i] * g[i];
+  m[i] = mm;
+  v[i] = vv;
+  prm[i] -= lr * (mm / c1) / (sqrtf(vv / c2) + eps);
+}
+
+// Gate: class = argmax of the class logits, confidence = its softmax
+// probability, budget = argmax of the budget logits.  route 0: take the
+// network's class; 1: decide by MCMC with the short budget; 2: full budget.
+__global__ void gate_kernel(int64_t B, const float* __restrict__ logits, float thr,
+                            uint8_t* __restrict__ route, uint8_t* __restrict__ cls,
+                            float* __restrict__ conf) {
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= B) return;
+  const float* z = logits + b * 8;
+  int best = 0;
+  for (int k = 1; k < 4; ++k)
+    if (z[k] > z[best]) best = k;
+  float se = 0.0f;
+  for (int k = 0; k < 4; ++k) se += expf(z[k] - z[best]);
+  const float c = 1.0f / se;
+  int bud = 0;
+  for (int k = 1; k < 3; ++k)
+    if (z[4 + k] > z[4 + bud]) bud = k;
+  const bool sure = c >= thr;
+  route[b] = (uint8_t)(sure ? (bud == 0 ? 0 : (bud == 1 ? 1 : 2)) : 2);
+  cls[b] = (uint8_t)best;
+  if (conf) conf[b] = c;
+}
+
+__global__ void gather_kernel(int64_t n, int row, const int32_t* __restrict__ idx,
+                              const uint8_t* __restrict__ src, uint8_t* __restrict__ dst) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n * row) return;
+  const int64_t k = i / row;
+  dst[i] = src[(int64_t)idx[k] * row + (i - k * row)];
+}
+
+__global__ void scatter_kernel(int64_t n, const int32_t* __restrict__ idx,
+                               const uint8_t* __restrict__ src, uint8_t* __restrict__ dst) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[idx[i]] = src[i];
+}
+
+__global__ void pick_kernel(int64_t n, int nq, const int32_t* __restrict__ idx,
+                            const uint8_t* __restrict__ cls, const uint8_t* __restrict__ reps,
+                            uint8_t* __restrict__ corr) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n * nq) return;
+  const int64_t k = i / nq;
+  const int q = (int)(i - k * nq);
+  const int64_t o = idx[k];
+  corr[o * nq + q] = reps[(k * 4 + cls[o]) * nq + q];
+}
+
+unsigned blocks_for(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
+
+}  // namespace
+
+CnnOffsets cnn_offsets(int L) {
+  CnnOffsets o{};
+  const int64_t kh = (int64_t)L * L * CH;
+  o.W1 = 0;
+  o.b1 = o.W1 + CH * 9 * 3;
+  o.W2 = o.b1 + CH;
+  o.b2 = o.W2 + CH * 9 * CH;
+  o.W3 = o.b2 + CH;
+  o.b3 = o.W3 + CH * 9 * CH;
+  o.Wh = o.b3 + CH;
+  o.bh = o.Wh + 7 * kh;
+  o.total = o.bh + 7;
+  return o;
+}
+
+CnnWorkspace cnn_workspace(int L, int64_t B) {
+  CnnWorkspace w{};
+  const int64_t P = B * L * L, kh = (int64_t)L * L * CH;
+  const int64_t chunks = (P + WG_CHUNK - 1) / WG_CHUNK;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = off;
+    off = (off + bytes + 255) / 256 * 256;
+    return at;
+  };
+  w.x0 = take((size_t)P * 8 * 2);
+  w.a1 = take((size_t)P * CH * 2);
+  w.a2 = take((size_t)P * CH * 2);
+  w.a3 = take((size_t)P * CH * 2);
+  w.wb1 = take(32 * 96 * 2);
+  w.wb2 = take(32 * 288 * 2);
+  w.wb3 = take(32 * 288 * 2);
+  w.wt2 = take(32 * 288 * 2);
+  w.wt3 = take(32 * 288 * 2);
+  w.whb = take((size_t)16 * kh * 2);
+  w.dz = take((size_t)B * 8 * 4);
+  w.dp3 = take((size_t)P * CH * 2);
+  w.dp2 = take((size_t)P * CH * 2);
+  w.dp1 = take((size_t)P * CH * 2);
+  w.part = take((size_t)chunks * CH * 288 * 4);
+  w.partb = take((size_t)chunks * CH * 4);
+  w.loss = take((size_t)B * 4);
+  w.bytes = off;
+  return w;
+}
+
+#define WSP(T, name) reinterpret_cast<T*>(ws + wl.name)
+
+hipError_t cnn_forward(int L, int64_t B, const float* prm, const uint8_t* syn, const float* p,
+                       float* logits, char* ws, hipStream_t s) {
+  const CnnWorkspace wl = cnn_workspace(L, B);
+  const CnnOffsets off = cnn_offsets(L);
+  const int64_t P = B * L * L, kh = (int64_t)L * L * CH;
+  hipLaunchKernelGGL(encode_kernel, dim3(blocks_for(P, 256)), dim3(256), 0, s, L, B, syn, p,
+                     WSP(bf16, x0));
+  // one thread per entry of the largest of the cast arrays
+  const int64_t n_cast = 16 * kh > 32 * 288 ? 16 * kh : 32 * 288;
+  hipLaunchKernelGGL(cast_kernel, dim3(blocks_for(n_cast, 256)), dim3(256), 0, s, L, prm, off,
+                     WSP(bf16, wb1), WSP(bf16, wb2), WSP(bf16, wb3), WSP(bf16, wt2),
+                     WSP(bf16, wt3), WSP(bf16, whb));
+  const unsigned g = blocks_for((P + 15) / 16, 4);
+  hipLaunchKernelGGL((conv_kernel<8, false>), dim3(g), dim3(256), 0, s, L, P, WSP(bf16, x0),
+                     WSP(bf16, wb1), prm + off.b1, nullptr, WSP(bf16, a1));
+  hipLaunchKernelGGL((conv_kernel<32, false>), dim3(g), dim3(256), 0, s, L, P, WSP(bf16, a1),
+                     WSP(bf16, wb2), prm + off.b2, nullptr, WSP(bf16, a2));
+  hipLaunchKernelGGL((conv_kernel<32, false>), dim3(g), dim3(256), 0, s, L, P, WSP(bf16, a2),
+                     WSP(bf16, wb3), prm + off.b3, nullptr, WSP(bf16, a3));
+  hipLaunchKernelGGL(head_fwd_kernel, dim3(blocks_for((B + 15) / 16, 4)), dim3(256), 0, s, L, B,
+                     WSP(bf16, a3), WSP(bf16, whb), prm + off.bh, logits);
+  return hipGetLastError();
+}
+
+hipError_t cnn_backward(int L, int64_t B, const float* prm, const float* logits, const float* tgt,
+                        const int32_t* budget, float wb, float* grads, float* loss, char* ws,
+                        hipStream_t s) {
+  const CnnWorkspace wl = cnn_workspace(L, B);
+  const CnnOffsets off = cnn_offsets(L);
+  const int64_t P = B * L * L, kh = (int64_t)L * L * CH;
+  const int64_t chunks = (P + WG_CHUNK - 1) / WG_CHUNK;
+  float* lossv = loss ? loss : WSP(float, loss);
+  hipLaunchKernelGGL(loss_kernel, dim3(blocks_for(B, 256)), dim3(256), 0, s, B, logits, tgt,
+                     budget, wb, WSP(float, dz), lossv);
+  hipLaunchKernelGGL(head_wgrad_kernel, dim3(blocks_for(kh, 256)), dim3(256), 0, s, L, B,
+                     WSP(float, dz), WSP(bf16, a3), grads + off.Wh, grads + off.bh);
+  hipLaunchKernelGGL(head_dgrad_kernel, dim3(blocks_for(B * kh, 256)), dim3(256), 0, s, L, B,
+                     WSP(float, dz), WSP(bf16, whb), WSP(bf16, a3), WSP(bf16, dp3));
+  const unsigned g = blocks_for((P + 15) / 16, 4);
+  // conv3: weights, then data back into a2's gradient
+  hipLaunchKernelGGL((conv_wgrad_kernel<32>), dim3((unsigned)chunks), dim3(256), 0, s, L, P,
+                     WSP(bf16, dp3), WSP(bf16, a2), WSP(float, part), WSP(float, partb));
+  hipLaunchKernelGGL((wgrad_reduce_kernel<32>), dim3(blocks_for(CH * 9 * CH, 256)), dim3(256), 0,
+                     s, chunks, CH, WSP(float, part), WSP(float, partb), grads + off.W3,
+                     grads + off.b3);
+  hipLaunchKernelGGL((conv_kernel<32, true>), dim3(g), dim3(256), 0, s, L, P, WSP(bf16, dp3),
+                     WSP(bf16, wt3), nullptr, WSP(bf16, a2), WSP(bf16, dp2));
+  // conv2
+  hipLaunchKernelGGL((conv_wgrad_kernel<32>), dim3((unsigned)chunks), dim3(256), 0, s, L, P,
+                     WSP(bf16, dp2), WSP(bf16, a1), WSP(float, part), WSP(float, partb));
+  hipLaunchKernelGGL((wgrad_reduce_kernel<32>), dim3(blocks_for(CH * 9 * CH, 256)), dim3(256), 0,
+                     s, chunks, CH, WSP(float, part), WSP(float, partb), grads + off.W2,
+                     grads + off.b2);
+  hipLaunchKernelGGL((conv_kernel<32, true>), dim3(g), dim3(256), 0, s, L, P, WSP(bf16, dp2),
+                     WSP(bf16, wt2), nullptr, WSP(bf16, a1), WSP(bf16, dp1));
+  // conv1: weights only
+  hipLaunchKernelGGL((conv_wgrad_kernel<8>), dim3((unsigned)chunks), dim3(256), 0, s, L, P,
+                     WSP(bf16, dp1), WSP(bf16, x0), WSP(float, part), WSP(float, partb));
+  hipLaunchKernelGGL((wgrad_reduce_kernel<8>), dim3(blocks_for(CH * 9 * 3, 256)), dim3(256), 0, s,
+                     chunks, 3, WSP(float, part), WSP(float, partb), grads + off.W1,
+                     grads + off.b1);
+  return hipGetLastError();
+}
+
+hipError_t cnn_adam(int64_t n, float* prm, const float* g, float* m, float* v, float lr, float b1,
+                    float b2, float eps, float c1, float c2, hipStream_t s) {
+  hipLaunchKernelGGL(adam_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, prm, g, m, v, lr,
+                     b1, b2, eps, c1, c2);
+  return hipGetLastError();
+}
+
+hipError_t cnn_gate(int64_t B, const float* logits, float thr, uint8_t* route, uint8_t* cls,
+                    float* conf, hipStream_t s) {
+  hipLaunchKernelGGL(gate_kernel, dim3(blocks_for(B, 256)), dim3(256), 0, s, B, logits, thr, route,
+                     cls, conf);
+  return hipGetLastError();
+}
+
+hipError_t cnn_gather(int64_t n, int row, const int32_t* idx, const uint8_t* src, uint8_t* dst,
+                      hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(gather_kernel, dim3(blocks_for(n * row, 256)), dim3(256), 0, s, n, row, idx,
+                     src, dst);
+  return hipGetLastError();
+}
+
+hipError_t cnn_scatter(int64_t n, const int32_t* idx, const uint8_t* src, uint8_t* dst,
+                       hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(scatter_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, idx, src, dst);
+  return hipGetLastError();
+}
+
+hipError_t cnn_pick(int64_t n, int nq, const int32_t* idx, const uint8_t* cls,
+                    const uint8_t* reps, uint8_t* corr, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(pick_kernel, dim3(blocks_for(n * nq, 256)), dim3(256), 0, s, n, nq, idx, cls,
+                     reps, corr);
+  return hipGetLastError();
+}
+
+}  // namespace mcmc

@@ -1,0 +1,333 @@
+// C-ABI of the gate network and of the gated decoder.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <new>
+#include <vector>
+
+#include "host_common.h"
+
+using namespace mcmc;
+
+namespace {
+
+bool cnn_batch_ok(int64_t batch) { return batch >= 0 && batch <= MCMC_CNN_BATCH_MAX; }
+
+int check_ws(const void* ws, size_t have, size_t need) {
+  if (need == 0) return MCMC_OK;
+  if (!ws || have < need || ((uintptr_t)ws % kAlign) != 0) return MCMC_EWORKSPACE;
+  return MCMC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mcmc_cnn_param_count(int32_t L, int64_t* h_count) {
+  if (!valid_L(L)) return MCMC_ERANGE;
+  if (!h_count) return MCMC_EINVAL;
+  *h_count = cnn_offsets(L).total;
+  return MCMC_OK;
+}
+
+int mcmc_cnn_workspace_size(int32_t L, int64_t batch, size_t* h_bytes) {
+  if (!valid_L(L) || !cnn_batch_ok(batch)) return MCMC_ERANGE;
+  if (!h_bytes) return MCMC_EINVAL;
+  *h_bytes = batch == 0 ? 0 : cnn_workspace(L, batch).bytes;
+  return MCMC_OK;
+}
+
+int mcmc_cnn_workspace_offsets(int32_t L, int64_t batch, int64_t* h_offsets) {
+  if (!valid_L(L) || !cnn_batch_ok(batch)) return MCMC_ERANGE;
+  if (!h_offsets) return MCMC_EINVAL;
+  const CnnWorkspace w = cnn_workspace(L, batch);
+  const size_t o[7] = {w.x0, w.a1, w.a2, w.a3, w.dp3, w.dp2, w.dp1};
+  for (int i = 0; i < 7; ++i) h_offsets[i] = (int64_t)o[i];
+  return MCMC_OK;
+}
+
+int mcmc_cnn_forward(int32_t L, int64_t batch, const float* d_params, const uint8_t* d_syndromes,
+                     const float* d_p, float* d_logits, void* d_workspace, size_t workspace_bytes,
+                     void* stream) {
+  if (!valid_L(L) || !cnn_batch_ok(batch)) return MCMC_ERANGE;
+  if (batch == 0) return MCMC_OK;
+  if (!d_params || !d_syndromes || !d_p || !d_logits) return MCMC_EINVAL;
+  const int st = check_ws(d_workspace, workspace_bytes, cnn_workspace(L, batch).bytes);
+  if (st != MCMC_OK) return st;
+  return hip_status(cnn_forward(L, batch, d_params, d_syndromes, d_p, d_logits,
+                                (char*)d_workspace, (hipStream_t)stream));
+}
+
+int mcmc_cnn_backward(int32_t L, int64_t batch, const float* d_params, const float* d_logits,
+                      const float* d_class_target, const int32_t* d_budget, float budget_weight,
+                      float* d_grads, float* d_loss, void* d_workspace, size_t workspace_bytes,
+                      void* stream) {
+  if (!valid_L(L) || !cnn_batch_ok(batch)) return MCMC_ERANGE;
+  if (batch == 0) return MCMC_OK;
+  if (!d_params || !d_logits || !d_class_target || !d_budget || !d_grads) return MCMC_EINVAL;
+  if (!(budget_weight >= 0.0f) || !isfinite(budget_weight)) return MCMC_ERANGE;
+  const int st = check_ws(d_workspace, workspace_bytes, cnn_workspace(L, batch).bytes);
+  if (st != MCMC_OK) return st;
+  return hip_status(cnn_backward(L, batch, d_params, d_logits, d_class_target, d_budget,
+                                 budget_weight, d_grads, d_loss, (char*)d_workspace,
+                                 (hipStream_t)stream));
+}
+
+int mcmc_cnn_step(int64_t n_params, int64_t step, float lr, float beta1, float beta2, float eps,
+                  float* d_params, const float* d_grads, float* d_m, float* d_v, void* stream) {
+  if (n_params < 0 || step < 1) return MCMC_ERANGE;
+  if (!(lr >= 0.0f) || !(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f) ||
+      !(eps > 0.0f))
+    return MCMC_ERANGE;
+  if (n_params == 0) return MCMC_OK;
+  if (!d_params || !d_grads || !d_m || !d_v) return MCMC_EINVAL;
+  // bias corrections 1 - beta^t in double on the host
+  const float c1 = (float)(1.0 - pow((double)beta1, (double)step));
+  const float c2 = (float)(1.0 - pow((double)beta2, (double)step));
+  return hip_status(cnn_adam(n_params, d_params, d_grads, d_m, d_v, lr, beta1, beta2, eps, c1, c2,
+                             (hipStream_t)stream));
+}
+
+int mcmc_cnn_gate(int64_t batch, const float* d_logits, float threshold, uint8_t* d_route,
+                  uint8_t* d_class, float* d_confidence, void* stream) {
+  if (!cnn_batch_ok(batch)) return MCMC_ERANGE;
+  if (!(threshold >= 0.0f && threshold <= 1.0f)) return MCMC_ERANGE;
+  if (batch == 0) return MCMC_OK;
+  if (!d_logits || !d_route || !d_class) return MCMC_EINVAL;
+  return hip_status(
+      cnn_gate(batch, d_logits, threshold, d_route, d_class, d_confidence, (hipStream_t)stream));
+}
+
+}  // extern "C"
+
+// ---- gated decoder ------------------------------------------------------------
+
+struct mcmc_gated {
+  mcmc_gate_config cfg{};
+  mcmc_plan* plan = nullptr;
+  size_t plan_ws = 0;
+  int nq = 0, ns = 0;
+  // pinned host staging
+  uint8_t* h_route = nullptr;
+  int32_t* h_idx = nullptr;   // plan item -> batch index (routes 1 and 2)
+  int32_t* h_idx0 = nullptr;  // route-0 batch indices
+  float* h_pf = nullptr;
+  std::vector<mcmc_item> items;
+};
+
+namespace {
+
+struct GatedWorkspace {
+  size_t cnn, logits, pf, route, cls, conf, idx, idx0, prob, chosen, syn0, reps, plan, bytes;
+};
+
+GatedWorkspace gated_workspace(const mcmc_gated* g) {
+  const int64_t n = g->cfg.max_batch;
+  GatedWorkspace w{};
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = off;
+    off = align_up(off + bytes);
+    return at;
+  };
+  w.cnn = take(cnn_workspace(g->cfg.L, n).bytes);
+  w.logits = take((size_t)n * 8 * sizeof(float));
+  w.pf = take((size_t)n * sizeof(float));
+  w.route = take((size_t)n);
+  w.cls = take((size_t)n);
+  w.conf = take((size_t)n * sizeof(float));
+  w.idx = take((size_t)n * sizeof(int32_t));
+  w.idx0 = take((size_t)n * sizeof(int32_t));
+  w.prob = take((size_t)n * 4 * sizeof(double));
+  w.chosen = take((size_t)n);
+  w.syn0 = take((size_t)n * g->ns);
+  w.reps = take((size_t)n * 4 * g->nq);
+  w.plan = take(g->plan_ws);
+  w.bytes = off;
+  return w;
+}
+
+void free_gated(mcmc_gated* g) {
+  if (!g) return;
+  if (g->plan) mcmc_plan_destroy(g->plan);
+  if (g->h_route) (void)hipHostFree(g->h_route);
+  if (g->h_idx) (void)hipHostFree(g->h_idx);
+  if (g->h_idx0) (void)hipHostFree(g->h_idx0);
+  if (g->h_pf) (void)hipHostFree(g->h_pf);
+  delete g;
+}
+
+mcmc_item make_item(const mcmc_gate_config& c, int32_t sweeps, uint32_t id, double p, int64_t i,
+                    int ns, int nq) {
+  mcmc_item it{};
+  it.L = c.L;
+  it.sweeps = sweeps;
+  it.burn = c.burn;
+  it.chains = c.chains;
+  it.n_temps = c.n_temps;
+  it.syndrome_id = id;
+  it.p = p;
+  it.syn_offset = i * ns;
+  it.corr_offset = i * nq;
+  return it;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mcmc_gated_create(const mcmc_gate_config* h_cfg, mcmc_gated** out) {
+  if (!out || !h_cfg) return MCMC_EINVAL;
+  *out = nullptr;
+  const mcmc_gate_config& c = *h_cfg;
+  if (!valid_L(c.L) || !valid_p(c.p)) return MCMC_ERANGE;
+  if (c.max_batch < 1 || c.max_batch > MCMC_CNN_BATCH_MAX) return MCMC_ERANGE;
+  if (!(c.threshold >= 0.0f && c.threshold <= 1.0f)) return MCMC_ERANGE;
+  if (c.sweeps_short < 0 || c.sweeps_full < 0) return MCMC_ERANGE;
+  if (c.init != MCMC_INIT_CANONICAL && c.init != MCMC_INIT_MATCHING) return MCMC_EINVAL;
+  mcmc_gated* g = new (std::nothrow) mcmc_gated();
+  if (!g) return MCMC_ENOMEM;
+  g->cfg = c;
+  mcmc_geometry(c.L, &g->nq, &g->ns);
+  // reserve the plan's device block for a whole batch at the full budget
+  // (both budgets have the same number of chains and tiles)
+  try {
+    g->items.resize((size_t)c.max_batch);
+  } catch (...) {
+    free_gated(g);
+    return MCMC_ENOMEM;
+  }
+  for (int64_t i = 0; i < c.max_batch; ++i)
+    g->items[i] = make_item(c, c.sweeps_full, (uint32_t)i, c.p, i, g->ns, g->nq);
+  int st = mcmc_plan_create(g->items.data(), c.max_batch, c.seed, c.init, &g->plan);
+  if (st != MCMC_OK) {
+    free_gated(g);
+    return st;
+  }
+  st = mcmc_plan_info(g->plan, nullptr, &g->plan_ws, nullptr);
+  const size_t n = (size_t)c.max_batch;
+  bool ok = st == MCMC_OK;
+  ok = ok && hipHostMalloc((void**)&g->h_route, n, hipHostMallocDefault) == hipSuccess;
+  ok = ok && hipHostMalloc((void**)&g->h_idx, n * 4, hipHostMallocDefault) == hipSuccess;
+  ok = ok && hipHostMalloc((void**)&g->h_idx0, n * 4, hipHostMallocDefault) == hipSuccess;
+  ok = ok && hipHostMalloc((void**)&g->h_pf, n * 4, hipHostMallocDefault) == hipSuccess;
+  if (!ok) {
+    free_gated(g);
+    return st != MCMC_OK ? st : MCMC_EDEVICE;
+  }
+  *out = g;
+  return MCMC_OK;
+}
+
+int mcmc_gated_destroy(mcmc_gated* g) {
+  free_gated(g);
+  return MCMC_OK;
+}
+
+int mcmc_gated_workspace_size(const mcmc_gated* g, size_t* h_bytes) {
+  if (!g || !h_bytes) return MCMC_EINVAL;
+  *h_bytes = gated_workspace(g).bytes;
+  return MCMC_OK;
+}
+
+int mcmc_gated_plan(mcmc_gated* g, mcmc_plan** h_plan) {
+  if (!g || !h_plan) return MCMC_EINVAL;
+  *h_plan = g->plan;
+  return MCMC_OK;
+}
+
+int mcmc_gated_decode(mcmc_gated* g, const float* d_params, const uint8_t* d_syndromes,
+                      const uint32_t* h_ids, const double* h_p, int64_t n, uint8_t* d_chosen,
+                      uint8_t* d_route, float* d_logits, uint8_t* d_correction,
+                      int64_t* h_counts, void* d_workspace, size_t workspace_bytes,
+                      void* stream) {
+  if (!g) return MCMC_EINVAL;
+  const mcmc_gate_config& c = g->cfg;
+  if (n < 0 || n > c.max_batch) return MCMC_ERANGE;
+  if (h_counts) h_counts[0] = h_counts[1] = h_counts[2] = 0;
+  if (n == 0) return MCMC_OK;
+  if (!d_params || !d_syndromes || !d_chosen) return MCMC_EINVAL;
+  if (h_p)
+    for (int64_t i = 0; i < n; ++i)
+      if (!valid_p(h_p[i])) return MCMC_ERANGE;
+  const GatedWorkspace wl = gated_workspace(g);
+  int st = check_ws(d_workspace, workspace_bytes, wl.bytes);
+  if (st != MCMC_OK) return st;
+  const hipStream_t s = (hipStream_t)stream;
+  char* ws = (char*)d_workspace;
+  float* logits = d_logits ? d_logits : (float*)(ws + wl.logits);
+  uint8_t* route = d_route ? d_route : (uint8_t*)(ws + wl.route);
+  float* pf = (float*)(ws + wl.pf);
+  int32_t* idx = (int32_t*)(ws + wl.idx);
+  int32_t* idx0 = (int32_t*)(ws + wl.idx0);
+
+  // network pass and gate; route-0 classes go straight to d_chosen
+  for (int64_t i = 0; i < n; ++i) g->h_pf[i] = (float)(h_p ? h_p[i] : c.p);
+  if (hipMemcpyAsync(pf, g->h_pf, (size_t)n * sizeof(float), hipMemcpyHostToDevice, s) !=
+      hipSuccess)
+    return MCMC_EDEVICE;
+  st = hip_status(cnn_forward(c.L, n, d_params, d_syndromes, pf, logits, ws + wl.cnn, s));
+  if (st != MCMC_OK) return st;
+  st = hip_status(cnn_gate(n, logits, c.threshold, route, d_chosen, (float*)(ws + wl.conf), s));
+  if (st != MCMC_OK) return st;
+  if (hipMemcpyAsync(g->h_route, route, (size_t)n, hipMemcpyDeviceToHost, s) != hipSuccess)
+    return MCMC_EDEVICE;
+  if (hipStreamSynchronize(s) != hipSuccess) return MCMC_EDEVICE;
+
+  // budgets per syndrome: the short ones first in the item list, then the
+  // full ones (the plan orders its tiles by cost anyway)
+  int64_t m = 0, n0 = 0, n1 = 0;
+  for (int pass = 1; pass <= 2; ++pass)
+    for (int64_t i = 0; i < n; ++i) {
+      const uint8_t r = g->h_route[i];
+      if (r != pass) continue;
+      const int32_t sweeps = r == 1 ? c.sweeps_short : c.sweeps_full;
+      const uint32_t id = h_ids ? h_ids[i] : (uint32_t)i;
+      g->items[m] = make_item(c, sweeps, id, h_p ? h_p[i] : c.p, i, g->ns, g->nq);
+      g->h_idx[m++] = (int32_t)i;
+      if (r == 1) ++n1;
+    }
+  for (int64_t i = 0; i < n; ++i)
+    if (g->h_route[i] == 0) g->h_idx0[n0++] = (int32_t)i;
+  if (h_counts) {
+    h_counts[0] = n0;
+    h_counts[1] = n1;
+    h_counts[2] = m - n1;
+  }
+
+  if (m > 0) {
+    if (hipMemcpyAsync(idx, g->h_idx, (size_t)m * 4, hipMemcpyHostToDevice, s) != hipSuccess)
+      return MCMC_EDEVICE;
+    st = mcmc_plan_rebuild(g->plan, g->items.data(), m);
+    if (st != MCMC_OK) return st;
+    size_t need = 0;
+    mcmc_plan_info(g->plan, nullptr, &need, nullptr);
+    if (need > g->plan_ws) return MCMC_EWORKSPACE;
+    uint8_t* chosen_sub = (uint8_t*)(ws + wl.chosen);
+    st = mcmc_plan_execute(g->plan, d_syndromes, (double*)(ws + wl.prob), nullptr, nullptr,
+                           nullptr, chosen_sub, d_correction, ws + wl.plan, g->plan_ws, stream);
+    if (st != MCMC_OK) return st;
+    st = hip_status(cnn_scatter(m, idx, chosen_sub, d_chosen, s));
+    if (st != MCMC_OK) return st;
+  }
+  if (d_correction && n0 > 0) {
+    // route 0: the class start of the network's class
+    if (hipMemcpyAsync(idx0, g->h_idx0, (size_t)n0 * 4, hipMemcpyHostToDevice, s) != hipSuccess)
+      return MCMC_EDEVICE;
+    uint8_t* syn0 = (uint8_t*)(ws + wl.syn0);
+    uint8_t* reps = (uint8_t*)(ws + wl.reps);
+    st = hip_status(cnn_gather(n0, g->ns, idx0, d_syndromes, syn0, s));
+    if (st != MCMC_OK) return st;
+    st = mcmc_init_representatives(c.L, c.init, syn0, n0, reps, stream);
+    if (st != MCMC_OK) return st;
+    st = hip_status(cnn_pick(n0, g->nq, idx0, d_chosen, reps, d_correction, s));
+    if (st != MCMC_OK) return st;
+  }
+  // the staging buffers are reused by the next call
+  if (hipStreamSynchronize(s) != hipSuccess) return MCMC_EDEVICE;
+  return MCMC_OK;
+}
+
+}  // extern "C"

@@ -145,4 +145,35 @@ hipError_t launch_sample_items(const ItemDesc* items, const GroupDesc* groups, i
                                uint32_t k0, uint32_t k1, uint8_t* syn, uint8_t* true_class,
                                hipStream_t s);
 
+// ---- gate network -----------------------------------------------------------
+// Offsets (in floats) of the parameter blocks in the flat fp32 vector.
+struct CnnOffsets {
+  int64_t W1, b1, W2, b2, W3, b3, Wh, bh, total;
+};
+// Byte offsets of the buffers in a gate-network workspace for L and batch B.
+struct CnnWorkspace {
+  size_t x0, a1, a2, a3, wb1, wb2, wb3, wt2, wt3, whb, dz, dp3, dp2, dp1, part, partb, loss,
+      bytes;
+};
+CnnOffsets cnn_offsets(int L);
+CnnWorkspace cnn_workspace(int L, int64_t B);
+hipError_t cnn_forward(int L, int64_t B, const float* prm, const uint8_t* syn, const float* p,
+                       float* logits, char* ws, hipStream_t s);
+hipError_t cnn_backward(int L, int64_t B, const float* prm, const float* logits, const float* tgt,
+                        const int32_t* budget, float wb, float* grads, float* loss, char* ws,
+                        hipStream_t s);
+hipError_t cnn_adam(int64_t n, float* prm, const float* g, float* m, float* v, float lr, float b1,
+                    float b2, float eps, float c1, float c2, hipStream_t s);
+hipError_t cnn_gate(int64_t B, const float* logits, float thr, uint8_t* route, uint8_t* cls,
+                    float* conf, hipStream_t s);
+// dst[k][0..row) = src[idx[k]][0..row), k < n
+hipError_t cnn_gather(int64_t n, int row, const int32_t* idx, const uint8_t* src, uint8_t* dst,
+                      hipStream_t s);
+// dst[idx[k]] = src[k], k < n
+hipError_t cnn_scatter(int64_t n, const int32_t* idx, const uint8_t* src, uint8_t* dst,
+                       hipStream_t s);
+// corr[idx[k]][..] = reps[k][cls[idx[k]]][..], rows of n_q bytes
+hipError_t cnn_pick(int64_t n, int nq, const int32_t* idx, const uint8_t* cls,
+                    const uint8_t* reps, uint8_t* corr, hipStream_t s);
+
 }  // namespace mcmc

@@ -48,6 +48,7 @@ struct mcmc_plan {
   size_t corr_bytes = 0;
   // device copies
   void* dev = nullptr;
+  size_t dev_bytes = 0;
   GroupDesc* d_groups = nullptr;
   ItemDesc* d_items = nullptr;
   TileDesc* d_tiles = nullptr;
@@ -245,23 +246,20 @@ void write_cache(const char* path, const std::string& sig, const mcmc_tuning& t)
 
 extern "C" {
 
-int mcmc_plan_create(const mcmc_item* items, int64_t n, uint64_t seed, uint32_t init,
-                     mcmc_plan** out) {
-  if (!out) return MCMC_EINVAL;
-  *out = nullptr;
-  if (n < 0 || n > ((int64_t)1 << 31)) return MCMC_ERANGE;
-  if (n > 0 && !items) return MCMC_EINVAL;
-  if (init != MCMC_INIT_CANONICAL && init != MCMC_INIT_MATCHING) return MCMC_EINVAL;
-  for (int64_t i = 0; i < n; ++i) {
-    const int st = check_item(items[i]);
-    if (st != MCMC_OK) return st;
-  }
-  mcmc_plan* p = new (std::nothrow) mcmc_plan();
-  if (!p) return MCMC_ENOMEM;
+namespace {
+
+// (Re)build the plan's groups, items, tiles and tables from an item array
+// (already validated) and copy them to the device, growing the plan's device
+// block only when it is too small.
+int build_plan(mcmc_plan* p, const mcmc_item* items, int64_t n) {
+  release_graphs(p);
   p->n = n;
-  p->seed = seed;
-  p->init = init;
-  (void)hipGetDevice(&p->device);
+  p->groups.clear();
+  p->items.clear();
+  p->tiles.clear();
+  p->tables.clear();
+  p->total_chains = p->total_rows = p->total_updates = 0;
+  for (int r = 0; r < N_RANGES; ++r) p->range_first[r] = p->range_tiles[r] = 0;
 
   // groups: (L, K, C, burn, sweeps) -> items
   std::map<std::tuple<int, int, int, int, int>, std::vector<int64_t>> by_key;
@@ -291,6 +289,10 @@ int mcmc_plan_create(const mcmc_item* items, int64_t n, uint64_t seed, uint32_t 
   p->total_chains = c_acc;
   p->total_rows = r_acc;
 
+  p->items.reserve(n);
+  double last_p = -1.0;
+  int32_t last_K = 0;
+  int64_t last_table = -1;
   for (auto& o : order) {
     const auto& k = o.second;
     const std::vector<int64_t>& members = by_key[k];
@@ -313,13 +315,20 @@ int mcmc_plan_create(const mcmc_item* items, int64_t n, uint64_t seed, uint32_t 
       it.rows_off = rows_off[i];
       it.chain_off = chain_off[i];
       it.corr_off = src.corr_offset;
-      it.table_off = (int64_t)p->tables.size();
       it.beta_bar = beta_bar(src.p);
       it.sid = src.syndrome_id;
       it.group = gid;
       it.err_thr = (uint32_t)floor(ldexp(src.p, 32));
-      p->tables.resize(p->tables.size() + 4 * (size_t)src.n_temps);
-      fill_table(src.p, src.n_temps, p->tables.data() + it.table_off);
+      if (src.p == last_p && src.n_temps == last_K) {
+        it.table_off = last_table;   // same rate and ladder: share the rows
+      } else {
+        it.table_off = (int64_t)p->tables.size();
+        p->tables.resize(p->tables.size() + 4 * (size_t)src.n_temps);
+        fill_table(src.p, src.n_temps, p->tables.data() + it.table_off);
+        last_p = src.p;
+        last_K = src.n_temps;
+        last_table = it.table_off;
+      }
       p->items.push_back(it);
       p->total_updates += 4 * (int64_t)src.n_temps * src.chains *
                           ((int64_t)src.burn + src.sweeps) * n_stab(src.L);
@@ -337,19 +346,20 @@ int mcmc_plan_create(const mcmc_item* items, int64_t n, uint64_t seed, uint32_t 
     }
     p->range_tiles[r] = (int64_t)p->tiles.size() - p->range_first[r];
   }
-  if ((int64_t)p->tiles.size() > 0xFFFFFFFFll) {
-    delete p;
-    return MCMC_ERANGE;
-  }
+  if ((int64_t)p->tiles.size() > 0xFFFFFFFFll) return MCMC_ERANGE;
 
-  // device copies in one allocation
+  // device copies in one block
   const size_t gsz = align_up(p->groups.size() * sizeof(GroupDesc) + 1);
   const size_t isz = align_up(p->items.size() * sizeof(ItemDesc) + 1);
   const size_t tsz = align_up(p->tiles.size() * sizeof(TileDesc) + 1);
   const size_t bsz = align_up(p->tables.size() * sizeof(uint32_t) + 1);
-  if (hipMalloc(&p->dev, gsz + isz + tsz + bsz) != hipSuccess) {
-    delete p;
-    return MCMC_EDEVICE;
+  const size_t need = gsz + isz + tsz + bsz;
+  if (need > p->dev_bytes) {
+    if (p->dev) (void)hipFree(p->dev);
+    p->dev = nullptr;
+    p->dev_bytes = 0;
+    if (hipMalloc(&p->dev, need) != hipSuccess) return MCMC_EDEVICE;
+    p->dev_bytes = need;
   }
   char* base = (char*)p->dev;
   p->d_groups = (GroupDesc*)base;
@@ -369,6 +379,39 @@ int mcmc_plan_create(const mcmc_item* items, int64_t n, uint64_t seed, uint32_t 
   if (!p->tables.empty())
     ok &= hipMemcpy(p->d_tables, p->tables.data(), p->tables.size() * sizeof(uint32_t),
                     hipMemcpyHostToDevice) == hipSuccess;
+  return ok ? MCMC_OK : MCMC_EDEVICE;
+}
+
+int check_items(const mcmc_item* items, int64_t n) {
+  if (n < 0 || n > ((int64_t)1 << 31)) return MCMC_ERANGE;
+  if (n > 0 && !items) return MCMC_EINVAL;
+  for (int64_t i = 0; i < n; ++i) {
+    const int st = check_item(items[i]);
+    if (st != MCMC_OK) return st;
+  }
+  return MCMC_OK;
+}
+
+}  // namespace
+
+int mcmc_plan_create(const mcmc_item* items, int64_t n, uint64_t seed, uint32_t init,
+                     mcmc_plan** out) {
+  if (!out) return MCMC_EINVAL;
+  *out = nullptr;
+  if (init != MCMC_INIT_CANONICAL && init != MCMC_INIT_MATCHING) return MCMC_EINVAL;
+  int st = check_items(items, n);
+  if (st != MCMC_OK) return st;
+  mcmc_plan* p = new (std::nothrow) mcmc_plan();
+  if (!p) return MCMC_ENOMEM;
+  p->seed = seed;
+  p->init = init;
+  (void)hipGetDevice(&p->device);
+  st = build_plan(p, items, n);
+  if (st != MCMC_OK) {
+    mcmc_plan_destroy(p);
+    return st;
+  }
+  bool ok = true;
   ok &= hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking) == hipSuccess;
   ok &= hipStreamCreateWithFlags(&p->capture, hipStreamNonBlocking) == hipSuccess;
   ok &= hipEventCreateWithFlags(&p->fork, hipEventDisableTiming) == hipSuccess;
@@ -384,6 +427,13 @@ int mcmc_plan_create(const mcmc_item* items, int64_t n, uint64_t seed, uint32_t 
   p->tuning.concurrent = 1;
   *out = p;
   return MCMC_OK;
+}
+
+int mcmc_plan_rebuild(mcmc_plan* p, const mcmc_item* items, int64_t n) {
+  if (!p) return MCMC_EINVAL;
+  const int st = check_items(items, n);
+  if (st != MCMC_OK) return st;
+  return build_plan(p, items, n);
 }
 
 int mcmc_plan_destroy(mcmc_plan* p) {

@@ -1,0 +1,250 @@
+"""Learned gate in front of the Metropolis decoder (not part of the paper's
+method): a small convolutional network over the syndrome planes that predicts
+the four class probabilities and a sweep budget, trained by the library's own
+forward/backward kernels on class probabilities the decoder itself produces.
+
+Argument marshalling only: the network, its gradients, the optimizer, the
+gate and the decodes run in libmcmcdec.so.  See the gate-network section of
+include/mcmcdec.h for the layouts.
+"""
+
+import ctypes
+
+import numpy as np
+
+from . import _lib
+from . import MCMC_INIT_MATCHING, MixedPlan, geometry, _ptr, _stream, _torch
+
+BUDGET_NAMES = ("none", "short", "full")
+
+
+def param_count(L):
+    n = ctypes.c_int64()
+    _lib.check(_lib._lib().mcmc_cnn_param_count(int(L), ctypes.byref(n)), "mcmc_cnn_param_count")
+    return n.value
+
+
+def workspace_size(L, batch):
+    b = ctypes.c_size_t()
+    _lib.check(_lib._lib().mcmc_cnn_workspace_size(int(L), int(batch), ctypes.byref(b)),
+               "mcmc_cnn_workspace_size")
+    return b.value
+
+
+def workspace_offsets(L, batch):
+    """Byte offsets of x0, a1, a2, a3, dpre3, dpre2, dpre1 in the workspace."""
+    arr = (ctypes.c_int64 * 7)()
+    _lib.check(_lib._lib().mcmc_cnn_workspace_offsets(int(L), int(batch), arr),
+               "mcmc_cnn_workspace_offsets")
+    return dict(zip(("x0", "a1", "a2", "a3", "dp3", "dp2", "dp1"), list(arr)))
+
+
+def forward(L, params, syndromes, p, workspace=None):
+    """logits [B][8] fp32 (entries 0..6 meaningful) and the workspace holding
+    the activations."""
+    torch = _torch()
+    B = syndromes.shape[0]
+    dev = syndromes.device
+    if workspace is None:
+        workspace = torch.empty((max(workspace_size(L, B), 1),), dtype=torch.uint8, device=dev)
+    logits = torch.zeros((B, 8), dtype=torch.float32, device=dev)
+    syndromes = syndromes.contiguous()
+    p = p.to(dtype=torch.float32).contiguous()
+    _lib.check(_lib._lib().mcmc_cnn_forward(int(L), B, _ptr(params), _ptr(syndromes), _ptr(p),
+                                            _ptr(logits), _ptr(workspace), workspace.numel(),
+                                            _stream(dev)), "mcmc_cnn_forward")
+    return logits, workspace
+
+
+def backward(L, params, logits, class_target, budget, workspace, budget_weight=0.5,
+             want_loss=True):
+    """(grads [param_count] fp32, per-sample loss [B] or None) of the batch
+    whose forward pass left its activations in `workspace`."""
+    torch = _torch()
+    B = logits.shape[0]
+    dev = logits.device
+    grads = torch.empty_like(params)
+    loss = torch.empty((B,), dtype=torch.float32, device=dev) if want_loss else None
+    tgt = class_target.to(dtype=torch.float32).contiguous()
+    bud = budget.to(dtype=torch.int32).contiguous()
+    _lib.check(_lib._lib().mcmc_cnn_backward(int(L), B, _ptr(params), _ptr(logits), _ptr(tgt),
+                                             _ptr(bud), float(budget_weight), _ptr(grads),
+                                             _ptr(loss), _ptr(workspace), workspace.numel(),
+                                             _stream(dev)), "mcmc_cnn_backward")
+    return grads, loss
+
+
+def adam_step(params, grads, m, v, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+    _lib.check(_lib._lib().mcmc_cnn_step(params.numel(), int(step), float(lr), float(beta1),
+                                         float(beta2), float(eps), _ptr(params), _ptr(grads),
+                                         _ptr(m), _ptr(v), _stream(params.device)),
+               "mcmc_cnn_step")
+
+
+def gate(logits, threshold=0.99):
+    """(route [B] u8, class [B] u8, confidence [B] fp32)."""
+    torch = _torch()
+    B = logits.shape[0]
+    dev = logits.device
+    route = torch.empty((B,), dtype=torch.uint8, device=dev)
+    cls = torch.empty((B,), dtype=torch.uint8, device=dev)
+    conf = torch.empty((B,), dtype=torch.float32, device=dev)
+    _lib.check(_lib._lib().mcmc_cnn_gate(B, _ptr(logits.contiguous()), float(threshold),
+                                         _ptr(route), _ptr(cls), _ptr(conf), _stream(dev)),
+               "mcmc_cnn_gate")
+    return route, cls, conf
+
+
+class GateNet:
+    """Parameters and Adam state of one network on the device."""
+
+    def __init__(self, L, init_params, device="cuda"):
+        torch = _torch()
+        self.L = int(L)
+        init = np.asarray(init_params, dtype=np.float32)
+        if init.size != param_count(L):
+            raise ValueError(f"expected {param_count(L)} parameters, got {init.size}")
+        self.params = torch.from_numpy(init.copy()).to(device)
+        self.m = torch.zeros_like(self.params)
+        self.v = torch.zeros_like(self.params)
+        self.step_count = 0
+        self._ws = None
+        self._ws_batch = -1
+
+    def _workspace(self, B, dev):
+        torch = _torch()
+        if self._ws is None or self._ws_batch < B or self._ws.device != dev:
+            self._ws = torch.empty((max(workspace_size(self.L, B), 1),), dtype=torch.uint8,
+                                   device=dev)
+            self._ws_batch = B
+        return self._ws
+
+    def forward(self, syndromes, p):
+        B = syndromes.shape[0]
+        ws = self._workspace(B, syndromes.device)[:max(workspace_size(self.L, B), 1)]
+        return forward(self.L, self.params, syndromes, p, ws)
+
+    def train_step(self, syndromes, p, class_target, budget, lr=1e-3, budget_weight=0.5):
+        logits, ws = self.forward(syndromes, p)
+        grads, loss = backward(self.L, self.params, logits, class_target, budget, ws,
+                               budget_weight)
+        self.step_count += 1
+        adam_step(self.params, grads, self.m, self.v, self.step_count, lr)
+        return loss
+
+    def predict(self, syndromes, p, threshold=0.99, batch=65536):
+        """(class_prob [B][4] fp32 from the class logits, route, class)."""
+        torch = _torch()
+        outs = []
+        for s in range(0, syndromes.shape[0], batch):
+            logits, _ = self.forward(syndromes[s:s + batch], p[s:s + batch])
+            route, cls, _ = gate(logits, threshold)
+            outs.append((torch.softmax(logits[:, :4], dim=1), route, cls))
+        return tuple(torch.cat([o[i] for o in outs]) for i in range(3))
+
+
+def mcmc_labels(L, syndromes, p, ids, seed, sweeps_short=None, sweeps_full=None, chains=4,
+                label_temps=20, label_chains=1, init=MCMC_INIT_MATCHING):
+    """Training targets made by the decoder itself, for n syndromes of
+    distance L (flat [n][n_stab] device tensor), rates p (host float array)
+    and ids (host int array):
+
+    * class_target [n][4]: the class probabilities of thermodynamic
+      integration over `label_temps` temperatures (Simpson's rule),
+      `sweeps_full` sweeps, `label_chains` chains;
+    * budget [n]: the smallest of (0, sweeps_short, sweeps_full) counted
+      sweeps whose decision (the plain decoder: one temperature, `chains`
+      chains) equals the one at sweeps_full (0 sweeps: the decision from the
+      class starts alone);
+    * decision [n]: that full-budget decision.
+    """
+    torch = _torch()
+    n = len(p)
+    sweeps_short = L if sweeps_short is None else sweeps_short
+    sweeps_full = L * L if sweeps_full is None else sweeps_full
+    flat = syndromes.reshape(-1).contiguous()
+
+    def run(sweeps, K, C):
+        items = [dict(L=L, p=float(p[i]), sweeps=sweeps, chains=C, n_temps=K,
+                      syndrome_id=int(ids[i])) for i in range(n)]
+        plan = MixedPlan(items, seed, init)
+        out = plan.execute(flat, want_correction=False)
+        plan.close()
+        return out
+
+    soft = run(sweeps_full, label_temps, label_chains)["class_prob"].to(torch.float32)
+    d_full = run(sweeps_full, 1, chains)["chosen"]
+    d_short = run(sweeps_short, 1, chains)["chosen"]
+    d_zero = run(0, 1, chains)["chosen"]
+    budget = torch.full((n,), 2, dtype=torch.int32, device=syndromes.device)
+    budget[d_short == d_full] = 1
+    budget[d_zero == d_full] = 0
+    return soft, budget, d_full
+
+
+class GatedDecoder:
+    """The gated decoder of include/mcmcdec.h (mcmc_gated_*)."""
+
+    def __init__(self, L, p, seed, max_batch, sweeps_short=None, sweeps_full=None, chains=4,
+                 n_temps=1, burn=0, threshold=0.99, init=MCMC_INIT_MATCHING, device="cuda"):
+        torch = _torch()
+        cfg = _lib.GateConfig()
+        cfg.L = int(L)
+        cfg.n_temps = int(n_temps)
+        cfg.chains = int(chains)
+        cfg.burn = int(burn)
+        cfg.sweeps_short = int(L if sweeps_short is None else sweeps_short)
+        cfg.sweeps_full = int(L * L if sweeps_full is None else sweeps_full)
+        cfg.p = float(p)
+        cfg.seed = int(seed) & ((1 << 64) - 1)
+        cfg.init = int(init)
+        cfg.threshold = float(threshold)
+        cfg.max_batch = int(max_batch)
+        self.cfg = cfg
+        self.L = int(L)
+        self.nq, self.ns = geometry(L)
+        h = ctypes.c_void_p()
+        _lib.check(_lib._lib().mcmc_gated_create(ctypes.byref(cfg), ctypes.byref(h)),
+                   "mcmc_gated_create")
+        self._h = h
+        b = ctypes.c_size_t()
+        _lib.check(_lib._lib().mcmc_gated_workspace_size(h, ctypes.byref(b)),
+                   "mcmc_gated_workspace_size")
+        self.workspace = torch.empty((max(b.value, 1),), dtype=torch.uint8, device=device)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib._lib().mcmc_gated_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def decode(self, params, syndromes, p=None, ids=None, want_correction=False):
+        """dict with chosen [n], route [n], logits [n][8], counts (3 ints) and
+        optionally correction [n][n_q]."""
+        torch = _torch()
+        n = syndromes.shape[0]
+        dev = syndromes.device
+        syndromes = syndromes.contiguous()
+        chosen = torch.empty((n,), dtype=torch.uint8, device=dev)
+        route = torch.empty((n,), dtype=torch.uint8, device=dev)
+        logits = torch.zeros((n, 8), dtype=torch.float32, device=dev)
+        corr = torch.empty((n, self.nq), dtype=torch.uint8, device=dev) if want_correction \
+            else None
+        h_p = None if p is None else np.ascontiguousarray(p, dtype=np.float64)
+        h_ids = None if ids is None else np.ascontiguousarray(ids, dtype=np.uint32)
+        counts = (ctypes.c_int64 * 3)()
+        _lib.check(_lib._lib().mcmc_gated_decode(
+            self._h, _ptr(params), _ptr(syndromes),
+            None if h_ids is None else h_ids.ctypes.data_as(ctypes.c_void_p),
+            None if h_p is None else h_p.ctypes.data_as(ctypes.c_void_p), n, _ptr(chosen),
+            _ptr(route), _ptr(logits), _ptr(corr), counts, _ptr(self.workspace),
+            self.workspace.numel(), _stream(dev)), "mcmc_gated_decode")
+        out = dict(chosen=chosen, route=route, logits=logits, counts=list(counts))
+        if corr is not None:
+            out["correction"] = corr
+        return out

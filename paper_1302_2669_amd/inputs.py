@@ -48,3 +48,19 @@ def cnn_init(L, seed, channels=32):
             fan_in = int(np.prod(shape[1:]))
             parts.append(rng.normal(0.0, np.sqrt(2.0 / fan_in), size=shape).astype(np.float32).reshape(-1))
     return np.concatenate(parts)
+
+
+def uniform_rates(n, seed, lo=0.05, hi=0.18):
+    """n depolarizing rates uniform in [lo, hi), float32 (the network's input
+    precision; the same values, widened, serve the float64 decoder)."""
+    rng = np.random.default_rng(seed)
+    return (lo + (hi - lo) * rng.random(n)).astype(np.float32)
+
+
+def cnn_targets(n, seed):
+    """Synthetic training targets: class distributions [n][4] (Dirichlet(1))
+    and budget labels [n] in 0..2."""
+    rng = np.random.default_rng(seed)
+    t = rng.dirichlet(np.ones(4), size=n).astype(np.float32)
+    b = rng.integers(0, 3, size=n).astype(np.int32)
+    return t, b
