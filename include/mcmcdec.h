@@ -351,20 +351,25 @@ int mcmc_cnn_step(int64_t n_params, int64_t step, float lr, float beta1, float b
 
 /*
  * Gate from logits [batch][8]: d_class = argmax of the class logits (ties to
- * the lowest), d_confidence = its softmax probability (or NULL), budget =
- * argmax of the budget logits; d_route = budget when the confidence is at
- * least `threshold`, else 2 (full budget).
+ * the lowest); with q = softmax of the budget logits, d_confidence
+ * [batch][2] = (q0, q0 + q1) (or NULL): the predicted probabilities that no
+ * sweep, and that at most the short budget, already give the full-budget
+ * decision.  d_route = 0 if q0 >= threshold, else 1 if q0 + q1 >= threshold,
+ * else 2.
  */
 int mcmc_cnn_gate(int64_t batch, const float* d_logits, float threshold, uint8_t* d_route,
                   uint8_t* d_class, float* d_confidence, void* stream);
 
 /*
- * Gated decoder for one code size: the network runs on the whole batch, then
- * each syndrome takes its route: 0 = the network's class (correction: that
- * class's start configuration), 1 = the Metropolis decoder with sweeps_short
- * counted sweeps, 2 = with sweeps_full.  Routes 1 and 2 run as one mixed plan
- * (one persistent launch of both budgets); their results are exactly those
- * of mcmc_decode_batch with the syndrome's p, id and budget.
+ * Gated decoder for one code size.  The network runs on the whole batch and
+ * its gate sets each syndrome's sweep budget: route 0 = no counted sweep (the
+ * decision from the class starts alone), 1 = sweeps_short, 2 = sweeps_full.
+ * All syndromes then run as one mixed plan (one persistent launch of every
+ * budget).  With escalate > 0, a route-1 syndrome whose largest estimated
+ * class probability is below `escalate` is decoded again with sweeps_full
+ * (route 3): its chains are keyed by sweep, so this extends the same chains.
+ * Every output is exactly that of mcmc_decode_batch with the syndrome's p,
+ * id and final budget; the network only chooses the budget.
  */
 typedef struct mcmc_gate_config {
   int32_t L;            /* code distance                                           */
@@ -376,7 +381,9 @@ typedef struct mcmc_gate_config {
   double p;             /* rate used when no per-syndrome rates are given          */
   uint64_t seed;        /* Philox key of the chains                                */
   uint32_t init;        /* MCMC_INIT_CANONICAL or MCMC_INIT_MATCHING                */
-  float threshold;      /* minimum class confidence for routes 0 and 1            */
+  float threshold;      /* minimum gate confidence for routes 0 and 1             */
+  float escalate;       /* route-1 syndromes below this class probability take
+                           the full budget; 0 = never                             */
   int64_t max_batch;    /* largest batch a call may pass                           */
 } mcmc_gate_config;
 
@@ -395,10 +402,10 @@ int mcmc_gated_plan(mcmc_gated* gated, mcmc_plan** h_plan);
  * Decode n <= max_batch syndromes d_syndromes [n][n_stab] with network
  * parameters d_params.  h_ids [n] host syndrome ids (NULL => i), h_p [n] host
  * rates (NULL => the configured p).  Outputs: d_chosen [n] (required),
- * d_route [n] and d_logits [n][8] (or NULL), d_correction [n][n_q] (or NULL),
- * h_counts [3] syndromes per route (or NULL).  Synchronous: it waits for the
- * gate before building the Metropolis plan, and returns with the stream
- * drained.
+ * d_route [n] (0..3) and d_logits [n][8] (or NULL), d_correction [n][n_q]
+ * (or NULL), h_counts [4] syndromes per final route (or NULL).  Synchronous:
+ * it waits for the gate (and for the short-budget estimates when escalating)
+ * before building each Metropolis plan, and returns with the stream drained.
  */
 int mcmc_gated_decode(mcmc_gated* gated, const float* d_params, const uint8_t* d_syndromes,
                       const uint32_t* h_ids, const double* h_p, int64_t n, uint8_t* d_chosen,

@@ -180,6 +180,13 @@ def unpack_chain_state(chain_state, n, L, p, sweeps, seed, chains=1, n_temps=1, 
     return states, weights
 
 
+# numpy twin of the C mcmc_item struct (natural alignment, 48 bytes)
+_ITEM_DTYPE = np.dtype([("L", "<i4"), ("sweeps", "<i4"), ("burn", "<i4"), ("chains", "<i4"),
+                        ("n_temps", "<i4"), ("syndrome_id", "<u4"), ("p", "<f8"),
+                        ("syn_offset", "<i8"), ("corr_offset", "<i8")], align=True)
+assert _ITEM_DTYPE.itemsize == ctypes.sizeof(_lib.Item)
+
+
 class MixedPlan:
     """A mixed batch: syndromes of different L, p, budgets and chain counts
     decoded by one plan (see mcmc_plan_* in the C header).
@@ -192,34 +199,57 @@ class MixedPlan:
 
     def __init__(self, items, seed, init=MCMC_INIT_MATCHING):
         n = len(items)
-        arr = (_lib.Item * max(n, 1))()
-        syn_off = corr_off = 0
+        cols = {k: np.asarray([it.get(k, d) if k != "syndrome_id" else it.get(k, i)
+                               for i, it in enumerate(items)])
+                for k, d in (("L", 0), ("p", 0.0), ("sweeps", 0), ("burn", 0), ("chains", 1),
+                             ("n_temps", 1), ("syndrome_id", 0))} if n else {}
+        self._build(n, cols, seed, init)
+
+    @classmethod
+    def from_arrays(cls, L, p, sweeps, seed, chains=1, n_temps=1, burn=0, syndrome_ids=None,
+                    init=MCMC_INIT_MATCHING):
+        """Same as the constructor, from per-item arrays (scalars broadcast)."""
+        p = np.asarray(p, dtype=np.float64).reshape(-1)
+        n = p.size
+        bc = lambda v: np.broadcast_to(np.asarray(v), (n,))  # noqa: E731
+        cols = dict(L=bc(L), p=p, sweeps=bc(sweeps), burn=bc(burn), chains=bc(chains),
+                    n_temps=bc(n_temps),
+                    syndrome_id=np.arange(n) if syndrome_ids is None else bc(syndrome_ids))
+        self = cls.__new__(cls)
+        self._build(n, cols, seed, init)
+        return self
+
+    def _build(self, n, cols, seed, init):
+        arr = np.zeros(max(n, 1), dtype=_ITEM_DTYPE)
         self.L = np.zeros(n, dtype=np.int32)
         self.syn_offsets = np.zeros(n + 1, dtype=np.int64)
         self.corr_offsets = np.zeros(n + 1, dtype=np.int64)
         self.chain_offsets = np.zeros(n + 1, dtype=np.int64)
-        for i, it in enumerate(items):
-            L = int(it["L"])
-            nq, ns = geometry(L)
-            arr[i].L = L
-            arr[i].sweeps = int(it["sweeps"])
-            arr[i].burn = int(it.get("burn", 0))
-            arr[i].chains = int(it.get("chains", 1))
-            arr[i].n_temps = int(it.get("n_temps", 1))
-            arr[i].syndrome_id = int(it.get("syndrome_id", i)) & 0xFFFFFFFF
-            arr[i].p = float(it["p"])
-            arr[i].syn_offset = syn_off
-            arr[i].corr_offset = corr_off
-            self.L[i] = L
-            syn_off += ns
-            corr_off += nq
-            self.syn_offsets[i + 1] = syn_off
-            self.corr_offsets[i + 1] = corr_off
-            self.chain_offsets[i + 1] = self.chain_offsets[i] + 4 * arr[i].n_temps * arr[i].chains
+        if n:
+            L = cols["L"].astype(np.int32)
+            geo = {int(v): geometry(int(v)) for v in np.unique(L)}
+            nq = np.asarray([geo[int(v)][0] for v in L], dtype=np.int64)
+            ns = np.asarray([geo[int(v)][1] for v in L], dtype=np.int64)
+            np.cumsum(ns, out=self.syn_offsets[1:])
+            np.cumsum(nq, out=self.corr_offsets[1:])
+            arr = arr[:n]
+            arr["L"] = L
+            arr["sweeps"] = cols["sweeps"]
+            arr["burn"] = cols["burn"]
+            arr["chains"] = cols["chains"]
+            arr["n_temps"] = cols["n_temps"]
+            arr["syndrome_id"] = cols["syndrome_id"].astype(np.int64) & 0xFFFFFFFF
+            arr["p"] = cols["p"]
+            arr["syn_offset"] = self.syn_offsets[:-1]
+            arr["corr_offset"] = self.corr_offsets[:-1]
+            self.L[:] = L
+            np.cumsum(4 * arr["n_temps"].astype(np.int64) * arr["chains"],
+                      out=self.chain_offsets[1:])
         self.n = n
-        self.syn_bytes, self.corr_bytes = syn_off, corr_off
+        self.syn_bytes, self.corr_bytes = int(self.syn_offsets[-1]), int(self.corr_offsets[-1])
         h = ctypes.c_void_p()
-        _lib.check(_lib._lib().mcmc_plan_create(arr, n, int(seed) & ((1 << 64) - 1), int(init),
+        _lib.check(_lib._lib().mcmc_plan_create(arr.ctypes.data_as(ctypes.POINTER(_lib.Item)), n,
+                                                int(seed) & ((1 << 64) - 1), int(init),
                                                 ctypes.byref(h)), "mcmc_plan_create")
         self._h = h
         tc, wb, tu = ctypes.c_int64(), ctypes.c_size_t(), ctypes.c_int64()

@@ -78,6 +78,7 @@ class GateConfig(ctypes.Structure):
         ("seed", ctypes.c_uint64),
         ("init", ctypes.c_uint32),
         ("threshold", ctypes.c_float),
+        ("escalate", ctypes.c_float),
         ("max_batch", ctypes.c_int64),
     ]
 

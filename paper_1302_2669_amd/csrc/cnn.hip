@@ -341,9 +341,11 @@ __global__ void adam_kernel(int64_t n, float* __restrict__ prm, const float* __r
   prm[i] -= lr * (mm / c1) / (sqrtf(vv / c2) + eps);
 }
 
-// Gate: class = argmax of the class logits, confidence = its softmax
-// probability, budget = argmax of the budget logits.  route 0: take the
-// network's class; 1: decide by MCMC with the short budget; 2: full budget.
+// Gate: class = argmax of the class logits (ties to the lowest); budget
+// probabilities q = softmax of the budget logits; conf = (q0, q0 + q1), the
+// probabilities that 0 and that at most the short budget reach the
+// full-budget decision.  route = 0 if q0 >= thr, else 1 if q0 + q1 >= thr,
+// else 2.
 __global__ void gate_kernel(int64_t B, const float* __restrict__ logits, float thr,
                             uint8_t* __restrict__ route, uint8_t* __restrict__ cls,
                             float* __restrict__ conf) {
@@ -353,16 +355,28 @@ __global__ void gate_kernel(int64_t B, const float* __restrict__ logits, float t
   int best = 0;
   for (int k = 1; k < 4; ++k)
     if (z[k] > z[best]) best = k;
-  float se = 0.0f;
-  for (int k = 0; k < 4; ++k) se += expf(z[k] - z[best]);
-  const float c = 1.0f / se;
-  int bud = 0;
-  for (int k = 1; k < 3; ++k)
-    if (z[4 + k] > z[4 + bud]) bud = k;
-  const bool sure = c >= thr;
-  route[b] = (uint8_t)(sure ? (bud == 0 ? 0 : (bud == 1 ? 1 : 2)) : 2);
+  const float m = fmaxf(fmaxf(z[4], z[5]), z[6]);
+  const float e0 = expf(z[4] - m), e1 = expf(z[5] - m), e2 = expf(z[6] - m);
+  const float sum = (e0 + e1) + e2;
+  const float q0 = e0 / sum, q01 = (e0 + e1) / sum;
+  route[b] = (uint8_t)(q0 >= thr ? 0 : (q01 >= thr ? 1 : 2));
   cls[b] = (uint8_t)best;
-  if (conf) conf[b] = c;
+  if (conf) {
+    conf[2 * b] = q0;
+    conf[2 * b + 1] = q01;
+  }
+}
+
+// flag[i] = 1 when syndrome i took the short budget and the largest of its
+// estimated class probabilities is below thr.
+__global__ void escalate_kernel(int64_t n, const uint8_t* __restrict__ route,
+                                const double* __restrict__ prob, double thr,
+                                uint8_t* __restrict__ flag) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double* q = prob + i * 4;
+  const double m = fmax(fmax(q[0], q[1]), fmax(q[2], q[3]));
+  flag[i] = (uint8_t)(route[i] == 1 && m < thr);
 }
 
 __global__ void gather_kernel(int64_t n, int row, const int32_t* __restrict__ idx,
@@ -517,6 +531,14 @@ hipError_t cnn_gate(int64_t B, const float* logits, float thr, uint8_t* route, u
                     float* conf, hipStream_t s) {
   hipLaunchKernelGGL(gate_kernel, dim3(blocks_for(B, 256)), dim3(256), 0, s, B, logits, thr, route,
                      cls, conf);
+  return hipGetLastError();
+}
+
+hipError_t cnn_escalate_flags(int64_t n, const uint8_t* route, const double* prob, double thr,
+                              uint8_t* flag, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(escalate_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, route, prob,
+                     thr, flag);
   return hipGetLastError();
 }
 

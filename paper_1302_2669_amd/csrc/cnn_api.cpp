@@ -111,8 +111,8 @@ struct mcmc_gated {
   int nq = 0, ns = 0;
   // pinned host staging
   uint8_t* h_route = nullptr;
-  int32_t* h_idx = nullptr;   // plan item -> batch index (routes 1 and 2)
-  int32_t* h_idx0 = nullptr;  // route-0 batch indices
+  uint8_t* h_flag = nullptr;
+  int32_t* h_idx = nullptr;   // escalated batch indices
   float* h_pf = nullptr;
   std::vector<mcmc_item> items;
 };
@@ -120,7 +120,7 @@ struct mcmc_gated {
 namespace {
 
 struct GatedWorkspace {
-  size_t cnn, logits, pf, route, cls, conf, idx, idx0, prob, chosen, syn0, reps, plan, bytes;
+  size_t cnn, logits, pf, route, cls, conf, flag, idx, prob, chosen, plan, bytes;
 };
 
 GatedWorkspace gated_workspace(const mcmc_gated* g) {
@@ -137,13 +137,11 @@ GatedWorkspace gated_workspace(const mcmc_gated* g) {
   w.pf = take((size_t)n * sizeof(float));
   w.route = take((size_t)n);
   w.cls = take((size_t)n);
-  w.conf = take((size_t)n * sizeof(float));
+  w.conf = take((size_t)n * 2 * sizeof(float));
+  w.flag = take((size_t)n);
   w.idx = take((size_t)n * sizeof(int32_t));
-  w.idx0 = take((size_t)n * sizeof(int32_t));
   w.prob = take((size_t)n * 4 * sizeof(double));
   w.chosen = take((size_t)n);
-  w.syn0 = take((size_t)n * g->ns);
-  w.reps = take((size_t)n * 4 * g->nq);
   w.plan = take(g->plan_ws);
   w.bytes = off;
   return w;
@@ -153,8 +151,8 @@ void free_gated(mcmc_gated* g) {
   if (!g) return;
   if (g->plan) mcmc_plan_destroy(g->plan);
   if (g->h_route) (void)hipHostFree(g->h_route);
+  if (g->h_flag) (void)hipHostFree(g->h_flag);
   if (g->h_idx) (void)hipHostFree(g->h_idx);
-  if (g->h_idx0) (void)hipHostFree(g->h_idx0);
   if (g->h_pf) (void)hipHostFree(g->h_pf);
   delete g;
 }
@@ -185,14 +183,15 @@ int mcmc_gated_create(const mcmc_gate_config* h_cfg, mcmc_gated** out) {
   if (!valid_L(c.L) || !valid_p(c.p)) return MCMC_ERANGE;
   if (c.max_batch < 1 || c.max_batch > MCMC_CNN_BATCH_MAX) return MCMC_ERANGE;
   if (!(c.threshold >= 0.0f && c.threshold <= 1.0f)) return MCMC_ERANGE;
+  if (!(c.escalate >= 0.0f && c.escalate <= 1.0f)) return MCMC_ERANGE;
   if (c.sweeps_short < 0 || c.sweeps_full < 0) return MCMC_ERANGE;
   if (c.init != MCMC_INIT_CANONICAL && c.init != MCMC_INIT_MATCHING) return MCMC_EINVAL;
   mcmc_gated* g = new (std::nothrow) mcmc_gated();
   if (!g) return MCMC_ENOMEM;
   g->cfg = c;
   mcmc_geometry(c.L, &g->nq, &g->ns);
-  // reserve the plan's device block for a whole batch at the full budget
-  // (both budgets have the same number of chains and tiles)
+  // reserve the plan's device block for a whole batch (every budget has the
+  // same number of chains and tiles per syndrome)
   try {
     g->items.resize((size_t)c.max_batch);
   } catch (...) {
@@ -210,8 +209,8 @@ int mcmc_gated_create(const mcmc_gate_config* h_cfg, mcmc_gated** out) {
   const size_t n = (size_t)c.max_batch;
   bool ok = st == MCMC_OK;
   ok = ok && hipHostMalloc((void**)&g->h_route, n, hipHostMallocDefault) == hipSuccess;
+  ok = ok && hipHostMalloc((void**)&g->h_flag, n, hipHostMallocDefault) == hipSuccess;
   ok = ok && hipHostMalloc((void**)&g->h_idx, n * 4, hipHostMallocDefault) == hipSuccess;
-  ok = ok && hipHostMalloc((void**)&g->h_idx0, n * 4, hipHostMallocDefault) == hipSuccess;
   ok = ok && hipHostMalloc((void**)&g->h_pf, n * 4, hipHostMallocDefault) == hipSuccess;
   if (!ok) {
     free_gated(g);
@@ -246,7 +245,7 @@ int mcmc_gated_decode(mcmc_gated* g, const float* d_params, const uint8_t* d_syn
   if (!g) return MCMC_EINVAL;
   const mcmc_gate_config& c = g->cfg;
   if (n < 0 || n > c.max_batch) return MCMC_ERANGE;
-  if (h_counts) h_counts[0] = h_counts[1] = h_counts[2] = 0;
+  if (h_counts) h_counts[0] = h_counts[1] = h_counts[2] = h_counts[3] = 0;
   if (n == 0) return MCMC_OK;
   if (!d_params || !d_syndromes || !d_chosen) return MCMC_EINVAL;
   if (h_p)
@@ -260,70 +259,78 @@ int mcmc_gated_decode(mcmc_gated* g, const float* d_params, const uint8_t* d_syn
   float* logits = d_logits ? d_logits : (float*)(ws + wl.logits);
   uint8_t* route = d_route ? d_route : (uint8_t*)(ws + wl.route);
   float* pf = (float*)(ws + wl.pf);
-  int32_t* idx = (int32_t*)(ws + wl.idx);
-  int32_t* idx0 = (int32_t*)(ws + wl.idx0);
+  double* prob = (double*)(ws + wl.prob);
 
-  // network pass and gate; route-0 classes go straight to d_chosen
+  // network pass and gate
   for (int64_t i = 0; i < n; ++i) g->h_pf[i] = (float)(h_p ? h_p[i] : c.p);
   if (hipMemcpyAsync(pf, g->h_pf, (size_t)n * sizeof(float), hipMemcpyHostToDevice, s) !=
       hipSuccess)
     return MCMC_EDEVICE;
   st = hip_status(cnn_forward(c.L, n, d_params, d_syndromes, pf, logits, ws + wl.cnn, s));
   if (st != MCMC_OK) return st;
-  st = hip_status(cnn_gate(n, logits, c.threshold, route, d_chosen, (float*)(ws + wl.conf), s));
+  st = hip_status(cnn_gate(n, logits, c.threshold, route, (uint8_t*)(ws + wl.cls),
+                           (float*)(ws + wl.conf), s));
   if (st != MCMC_OK) return st;
   if (hipMemcpyAsync(g->h_route, route, (size_t)n, hipMemcpyDeviceToHost, s) != hipSuccess)
     return MCMC_EDEVICE;
   if (hipStreamSynchronize(s) != hipSuccess) return MCMC_EDEVICE;
 
-  // budgets per syndrome: the short ones first in the item list, then the
-  // full ones (the plan orders its tiles by cost anyway)
-  int64_t m = 0, n0 = 0, n1 = 0;
-  for (int pass = 1; pass <= 2; ++pass)
-    for (int64_t i = 0; i < n; ++i) {
-      const uint8_t r = g->h_route[i];
-      if (r != pass) continue;
-      const int32_t sweeps = r == 1 ? c.sweeps_short : c.sweeps_full;
-      const uint32_t id = h_ids ? h_ids[i] : (uint32_t)i;
-      g->items[m] = make_item(c, sweeps, id, h_p ? h_p[i] : c.p, i, g->ns, g->nq);
-      g->h_idx[m++] = (int32_t)i;
-      if (r == 1) ++n1;
-    }
-  for (int64_t i = 0; i < n; ++i)
-    if (g->h_route[i] == 0) g->h_idx0[n0++] = (int32_t)i;
-  if (h_counts) {
-    h_counts[0] = n0;
-    h_counts[1] = n1;
-    h_counts[2] = m - n1;
+  // one plan, item i = syndrome i with the sweep budget of its route
+  const int32_t budget[3] = {0, c.sweeps_short, c.sweeps_full};
+  int64_t cnt[3] = {0, 0, 0};
+  for (int64_t i = 0; i < n; ++i) {
+    const uint8_t r = g->h_route[i] > 2 ? 2 : g->h_route[i];
+    ++cnt[r];
+    const uint32_t id = h_ids ? h_ids[i] : (uint32_t)i;
+    g->items[i] = make_item(c, budget[r], id, h_p ? h_p[i] : c.p, i, g->ns, g->nq);
   }
+  st = mcmc_plan_rebuild(g->plan, g->items.data(), n);
+  if (st != MCMC_OK) return st;
+  size_t need = 0;
+  mcmc_plan_info(g->plan, nullptr, &need, nullptr);
+  if (need > g->plan_ws) return MCMC_EWORKSPACE;
+  st = mcmc_plan_execute(g->plan, d_syndromes, prob, nullptr, nullptr, nullptr, d_chosen,
+                         d_correction, ws + wl.plan, g->plan_ws, stream);
+  if (st != MCMC_OK) return st;
 
-  if (m > 0) {
-    if (hipMemcpyAsync(idx, g->h_idx, (size_t)m * 4, hipMemcpyHostToDevice, s) != hipSuccess)
+  // short-budget syndromes whose own estimate is not confident: full budget
+  // (the chains are keyed by sweep, so this continues the same chains)
+  int64_t m = 0;
+  if (c.escalate > 0.0f && cnt[1] > 0) {
+    uint8_t* flag = (uint8_t*)(ws + wl.flag);
+    st = hip_status(cnn_escalate_flags(n, route, prob, (double)c.escalate, flag, s));
+    if (st != MCMC_OK) return st;
+    if (hipMemcpyAsync(g->h_flag, flag, (size_t)n, hipMemcpyDeviceToHost, s) != hipSuccess)
       return MCMC_EDEVICE;
-    st = mcmc_plan_rebuild(g->plan, g->items.data(), m);
-    if (st != MCMC_OK) return st;
-    size_t need = 0;
-    mcmc_plan_info(g->plan, nullptr, &need, nullptr);
-    if (need > g->plan_ws) return MCMC_EWORKSPACE;
-    uint8_t* chosen_sub = (uint8_t*)(ws + wl.chosen);
-    st = mcmc_plan_execute(g->plan, d_syndromes, (double*)(ws + wl.prob), nullptr, nullptr,
-                           nullptr, chosen_sub, d_correction, ws + wl.plan, g->plan_ws, stream);
-    if (st != MCMC_OK) return st;
-    st = hip_status(cnn_scatter(m, idx, chosen_sub, d_chosen, s));
-    if (st != MCMC_OK) return st;
+    if (hipStreamSynchronize(s) != hipSuccess) return MCMC_EDEVICE;
+    for (int64_t i = 0; i < n; ++i) {
+      if (!g->h_flag[i]) continue;
+      const uint32_t id = h_ids ? h_ids[i] : (uint32_t)i;
+      g->items[m] = make_item(c, c.sweeps_full, id, h_p ? h_p[i] : c.p, i, g->ns, g->nq);
+      g->h_idx[m++] = (int32_t)i;
+      g->h_route[i] = 3;
+    }
+    if (m > 0) {
+      int32_t* idx = (int32_t*)(ws + wl.idx);
+      uint8_t* chosen_sub = (uint8_t*)(ws + wl.chosen);
+      if (hipMemcpyAsync(idx, g->h_idx, (size_t)m * 4, hipMemcpyHostToDevice, s) != hipSuccess)
+        return MCMC_EDEVICE;
+      st = mcmc_plan_rebuild(g->plan, g->items.data(), m);
+      if (st != MCMC_OK) return st;
+      st = mcmc_plan_execute(g->plan, d_syndromes, prob, nullptr, nullptr, nullptr, chosen_sub,
+                             d_correction, ws + wl.plan, g->plan_ws, stream);
+      if (st != MCMC_OK) return st;
+      st = hip_status(cnn_scatter(m, idx, chosen_sub, d_chosen, s));
+      if (st != MCMC_OK) return st;
+      if (hipMemcpyAsync(route, g->h_route, (size_t)n, hipMemcpyHostToDevice, s) != hipSuccess)
+        return MCMC_EDEVICE;
+    }
   }
-  if (d_correction && n0 > 0) {
-    // route 0: the class start of the network's class
-    if (hipMemcpyAsync(idx0, g->h_idx0, (size_t)n0 * 4, hipMemcpyHostToDevice, s) != hipSuccess)
-      return MCMC_EDEVICE;
-    uint8_t* syn0 = (uint8_t*)(ws + wl.syn0);
-    uint8_t* reps = (uint8_t*)(ws + wl.reps);
-    st = hip_status(cnn_gather(n0, g->ns, idx0, d_syndromes, syn0, s));
-    if (st != MCMC_OK) return st;
-    st = mcmc_init_representatives(c.L, c.init, syn0, n0, reps, stream);
-    if (st != MCMC_OK) return st;
-    st = hip_status(cnn_pick(n0, g->nq, idx0, d_chosen, reps, d_correction, s));
-    if (st != MCMC_OK) return st;
+  if (h_counts) {
+    h_counts[0] = cnt[0];
+    h_counts[1] = cnt[1] - m;
+    h_counts[2] = cnt[2];
+    h_counts[3] = m;
   }
   // the staging buffers are reused by the next call
   if (hipStreamSynchronize(s) != hipSuccess) return MCMC_EDEVICE;

@@ -166,6 +166,9 @@ hipError_t cnn_adam(int64_t n, float* prm, const float* g, float* m, float* v, f
                     float b2, float eps, float c1, float c2, hipStream_t s);
 hipError_t cnn_gate(int64_t B, const float* logits, float thr, uint8_t* route, uint8_t* cls,
                     float* conf, hipStream_t s);
+// flag[i] = route[i] == 1 && max_k prob[i][k] < thr
+hipError_t cnn_escalate_flags(int64_t n, const uint8_t* route, const double* prob, double thr,
+                              uint8_t* flag, hipStream_t s);
 // dst[k][0..row) = src[idx[k]][0..row), k < n
 hipError_t cnn_gather(int64_t n, int row, const int32_t* idx, const uint8_t* src, uint8_t* dst,
                       hipStream_t s);

@@ -352,7 +352,11 @@ int build_plan(mcmc_plan* p, const mcmc_item* items, int64_t n) {
   const size_t gsz = align_up(p->groups.size() * sizeof(GroupDesc) + 1);
   const size_t isz = align_up(p->items.size() * sizeof(ItemDesc) + 1);
   const size_t tsz = align_up(p->tiles.size() * sizeof(TileDesc) + 1);
-  const size_t bsz = align_up(p->tables.size() * sizeof(uint32_t) + 1);
+  // table rows are shared by consecutive items of one rate; the block is
+  // sized for none shared so that a rebuild with other rates fits
+  size_t table_cap = 0;
+  for (int64_t i = 0; i < n; ++i) table_cap += 4 * (size_t)items[i].n_temps;
+  const size_t bsz = align_up(std::max(p->tables.size(), table_cap) * sizeof(uint32_t) + 1);
   const size_t need = gsz + isz + tsz + bsz;
   if (need > p->dev_bytes) {
     if (p->dev) (void)hipFree(p->dev);

@@ -82,13 +82,16 @@ def adam_step(params, grads, m, v, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e
 
 
 def gate(logits, threshold=0.99):
-    """(route [B] u8, class [B] u8, confidence [B] fp32)."""
+    """(route [B] u8, class [B] u8, confidence [B][2] fp32): the budget
+    route, the argmax class, and the predicted probabilities (q0, q0 + q1)
+    that no sweep / at most the short budget reaches the full-budget
+    decision."""
     torch = _torch()
     B = logits.shape[0]
     dev = logits.device
     route = torch.empty((B,), dtype=torch.uint8, device=dev)
     cls = torch.empty((B,), dtype=torch.uint8, device=dev)
-    conf = torch.empty((B,), dtype=torch.float32, device=dev)
+    conf = torch.empty((B, 2), dtype=torch.float32, device=dev)
     _lib.check(_lib._lib().mcmc_cnn_gate(B, _ptr(logits.contiguous()), float(threshold),
                                          _ptr(route), _ptr(cls), _ptr(conf), _stream(dev)),
                "mcmc_cnn_gate")
@@ -143,11 +146,23 @@ class GateNet:
         return tuple(torch.cat([o[i] for o in outs]) for i in range(3))
 
 
+def sample_dataset(L, p, seed, id_base=0, device="cuda"):
+    """Depolarizing samples of distance L with per-sample rates p (host
+    array): (syndromes [n][n_stab] u8, true classes [n] u8, ids [n]) on the
+    device, sample ids id_base + i."""
+    n = len(p)
+    ids = (id_base + np.arange(n, dtype=np.int64)) & 0xFFFFFFFF
+    plan = MixedPlan.from_arrays(L, p, 0, seed, syndrome_ids=ids)
+    syn, cls = plan.sample(seed, device)
+    plan.close()
+    return syn.reshape(n, -1), cls, ids
+
+
 def mcmc_labels(L, syndromes, p, ids, seed, sweeps_short=None, sweeps_full=None, chains=4,
                 label_temps=20, label_chains=1, init=MCMC_INIT_MATCHING):
     """Training targets made by the decoder itself, for n syndromes of
-    distance L (flat [n][n_stab] device tensor), rates p (host float array)
-    and ids (host int array):
+    distance L ([n][n_stab] device tensor), rates p (host float array) and ids
+    (host int array):
 
     * class_target [n][4]: the class probabilities of thermodynamic
       integration over `label_temps` temperatures (Simpson's rule),
@@ -165,9 +180,8 @@ def mcmc_labels(L, syndromes, p, ids, seed, sweeps_short=None, sweeps_full=None,
     flat = syndromes.reshape(-1).contiguous()
 
     def run(sweeps, K, C):
-        items = [dict(L=L, p=float(p[i]), sweeps=sweeps, chains=C, n_temps=K,
-                      syndrome_id=int(ids[i])) for i in range(n)]
-        plan = MixedPlan(items, seed, init)
+        plan = MixedPlan.from_arrays(L, p, sweeps, seed, chains=C, n_temps=K, syndrome_ids=ids,
+                                     init=init)
         out = plan.execute(flat, want_correction=False)
         plan.close()
         return out
@@ -182,11 +196,42 @@ def mcmc_labels(L, syndromes, p, ids, seed, sweeps_short=None, sweeps_full=None,
     return soft, budget, d_full
 
 
+def train(net, syndromes, p, class_target, budget, epochs=2, batch=512, lr=1e-3, seed=0,
+          budget_weight=0.5, lr_final=None, log=None):
+    """Adam over shuffled mini-batches (the last partial batch of an epoch is
+    dropped); the learning rate falls linearly from lr to lr_final (lr/10 by
+    default) over the run.  Returns the mean loss of each epoch."""
+    torch = _torch()
+    n = syndromes.shape[0]
+    dev = syndromes.device
+    p = p.to(dtype=torch.float32)
+    gen = torch.Generator().manual_seed(int(seed))
+    lr_final = lr / 10.0 if lr_final is None else lr_final
+    steps = max(1, epochs * (n // batch))
+    t = 0
+    history = []
+    for e in range(epochs):
+        perm = torch.randperm(n, generator=gen).to(dev)
+        total = torch.zeros((), dtype=torch.float64, device=dev)
+        for s in range(0, n - batch + 1, batch):
+            idx = perm[s:s + batch]
+            rate = lr + (lr_final - lr) * (t / max(1, steps - 1))
+            loss = net.train_step(syndromes[idx], p[idx], class_target[idx], budget[idx], rate,
+                                  budget_weight)
+            total += loss.double().sum()
+            t += 1
+        history.append(float(total) / max(1, (n // batch) * batch))
+        if log:
+            log(f"epoch {e}: mean loss {history[-1]:.4f}")
+    return history
+
+
 class GatedDecoder:
     """The gated decoder of include/mcmcdec.h (mcmc_gated_*)."""
 
     def __init__(self, L, p, seed, max_batch, sweeps_short=None, sweeps_full=None, chains=4,
-                 n_temps=1, burn=0, threshold=0.99, init=MCMC_INIT_MATCHING, device="cuda"):
+                 n_temps=1, burn=0, threshold=0.99, escalate=0.0, init=MCMC_INIT_MATCHING,
+                 device="cuda"):
         torch = _torch()
         cfg = _lib.GateConfig()
         cfg.L = int(L)
@@ -199,6 +244,7 @@ class GatedDecoder:
         cfg.seed = int(seed) & ((1 << 64) - 1)
         cfg.init = int(init)
         cfg.threshold = float(threshold)
+        cfg.escalate = float(escalate)
         cfg.max_batch = int(max_batch)
         self.cfg = cfg
         self.L = int(L)
@@ -224,8 +270,9 @@ class GatedDecoder:
             pass
 
     def decode(self, params, syndromes, p=None, ids=None, want_correction=False):
-        """dict with chosen [n], route [n], logits [n][8], counts (3 ints) and
-        optionally correction [n][n_q]."""
+        """dict with chosen [n], route [n] (0 none, 1 short, 2 full, 3 short
+        then full), logits [n][8], counts (4 ints, per route) and optionally
+        correction [n][n_q]."""
         torch = _torch()
         n = syndromes.shape[0]
         dev = syndromes.device
@@ -237,7 +284,7 @@ class GatedDecoder:
             else None
         h_p = None if p is None else np.ascontiguousarray(p, dtype=np.float64)
         h_ids = None if ids is None else np.ascontiguousarray(ids, dtype=np.uint32)
-        counts = (ctypes.c_int64 * 3)()
+        counts = (ctypes.c_int64 * 4)()
         _lib.check(_lib._lib().mcmc_gated_decode(
             self._h, _ptr(params), _ptr(syndromes),
             None if h_ids is None else h_ids.ctypes.data_as(ctypes.c_void_p),

@@ -1,10 +1,6 @@
-"""The gated decoder through the C-ABI: every route's output against the
-entry point it stands for, bit for bit.
-
-* route 2 (full budget) and route 1 (short budget): exactly mcmc_decode_batch
-  with that budget, the syndrome's rate and id (class and correction);
-* route 0: the network's class (argmax of its class logits, recomputed here
-  from the logits it returned) and that class's start configuration.
+"""The gated decoder through the C-ABI: every syndrome's output against
+mcmc_decode_batch with the same rate, id and the sweep budget of its route
+(0: none, 1: short, 2 and 3: full), bit for bit (class and correction).
 """
 
 import sys
@@ -48,16 +44,16 @@ def spread_params(L, seed):
 def check_routes(L, syn, p_host, ids, out, chains, sweeps_short, sweeps_full, seed):
     chosen = out["chosen"].cpu().numpy()
     route = out["route"].cpu().numpy()
-    logits = out["logits"].cpu().numpy()
     corr = out["correction"].cpu().numpy()
-    n = syn.shape[0]
-    counts = [int((route == r).sum()) for r in range(3)]
+    counts = [int((route == r).sum()) for r in range(4)]
     assert counts == list(out["counts"])
-    for r, sweeps in ((1, sweeps_short), (2, sweeps_full)):
+    budget = {0: 0, 1: sweeps_short, 2: sweeps_full, 3: sweeps_full}
+    probs = {}
+    for r, sweeps in budget.items():
         sel = np.nonzero(route == r)[0]
         if sel.size == 0:
             continue
-        # per rate value (uniform-rate entry point): one decode per distinct p
+        # the uniform-rate entry point: one decode per distinct rate
         for pv in np.unique(p_host[sel]):
             sub = sel[p_host[sel] == pv]
             ref = mc.decode_batch(syn[torch.from_numpy(sub).to(DEV)], L, float(pv), sweeps, seed,
@@ -65,13 +61,12 @@ def check_routes(L, syn, p_host, ids, out, chains, sweeps_short, sweeps_full, se
             torch.cuda.synchronize()
             assert np.array_equal(chosen[sub], ref["chosen"].cpu().numpy()), f"route {r}"
             assert np.array_equal(corr[sub], ref["correction"].cpu().numpy()), f"route {r}"
-    sel = np.nonzero(route == 0)[0]
-    if sel.size:
-        cls = np.argmax(logits[sel, :4], axis=1)
-        assert np.array_equal(chosen[sel], cls)
-        reps = mc.init_representatives(syn[torch.from_numpy(sel).to(DEV)], L).cpu().numpy()
-        assert np.array_equal(corr[sel], reps[np.arange(sel.size), cls])
-    return counts
+            if r in (1, 3):
+                short = ref if r == 1 else mc.decode_batch(
+                    syn[torch.from_numpy(sub).to(DEV)], L, float(pv), sweeps_short, seed,
+                    chains=chains, syndrome_ids=torch.from_numpy(ids[sub]))
+                probs.setdefault(r, []).append(short["class_prob"].max(dim=1).values.cpu().numpy())
+    return counts, {r: np.concatenate(v) for r, v in probs.items()}
 
 
 @pytest.mark.parametrize("L", [5, 13])
@@ -81,12 +76,13 @@ def test_gated_routes_match_plain_entry_points(L):
     syn = torch.from_numpy(uniform_syndromes(L, n, seed, density=0.08)).to(DEV)
     prm = torch.from_numpy(spread_params(L, seed + 1)).to(DEV)
     g = gate.GatedDecoder(L, 0.1, seed, max_batch=n, sweeps_short=3, sweeps_full=9,
-                          chains=chains, threshold=0.0)
+                          chains=chains, threshold=0.5)
     ids = (np.arange(n, dtype=np.int64) * 7 + 11).astype(np.uint32)
     out = g.decode(prm, syn, ids=ids, want_correction=True)
-    counts = check_routes(L, syn, np.full(n, 0.1), ids.astype(np.int64), out, chains, 3, 9, seed)
+    counts, _ = check_routes(L, syn, np.full(n, 0.1), ids.astype(np.int64), out, chains, 3, 9,
+                             seed)
     say(f"routes {counts}")
-    assert all(c > 0 for c in counts), counts
+    assert all(c > 0 for c in counts[:3]) and counts[3] == 0, counts
     # a second, smaller call on the same decoder (plan storage reused)
     m = 97
     syn2 = torch.from_numpy(uniform_syndromes(L, m, seed + 5, density=0.12)).to(DEV)
@@ -102,7 +98,7 @@ def test_gated_per_syndrome_rates():
     p = np.asarray([0.05, 0.09, 0.13, 0.17], dtype=np.float32)[np.arange(n) % 4].astype(np.float64)
     prm = torch.from_numpy(spread_params(L, seed + 1)).to(DEV)
     g = gate.GatedDecoder(L, 0.1, seed, max_batch=256, sweeps_short=4, sweeps_full=12,
-                          chains=chains, threshold=0.0)
+                          chains=chains, threshold=0.5)
     out = g.decode(prm, syn, p=p, want_correction=True)
     check_routes(L, syn, p, np.arange(n, dtype=np.int64), out, chains, 4, 12, seed)
     # the network saw the per-syndrome rates: same logits as a direct pass
@@ -123,9 +119,27 @@ def test_gated_threshold_one_is_plain_decoder():
     out = g.decode(prm, syn, want_correction=True)
     ref = mc.decode_batch(syn, L, 0.12, 25, seed, chains=2)
     torch.cuda.synchronize()
-    assert out["counts"] == [0, 0, n]
+    assert out["counts"] == [0, 0, n, 0]
     assert torch.equal(out["chosen"], ref["chosen"])
     assert torch.equal(out["correction"], ref["correction"])
+    g.close()
+
+
+def test_gated_escalation():
+    """Short-budget syndromes whose own class estimate is below the
+    escalation level take the full budget; the others keep the short one."""
+    L, n, chains, seed = 9, 400, 2, SEED + 9
+    syn = torch.from_numpy(uniform_syndromes(L, n, seed, density=0.06)).to(DEV)
+    prm = torch.from_numpy(spread_params(L, seed + 1)).to(DEV)
+    esc = 0.9
+    g = gate.GatedDecoder(L, 0.08, seed, max_batch=n, sweeps_short=9, sweeps_full=30,
+                          chains=chains, threshold=0.5, escalate=esc)
+    out = g.decode(prm, syn, want_correction=True)
+    counts, probs = check_routes(L, syn, np.full(n, 0.08), np.arange(n, dtype=np.int64), out,
+                                 chains, 9, 30, seed)
+    say(f"routes {counts}")
+    assert counts[1] > 0 and counts[3] > 0, counts
+    assert (probs[1] >= esc).all() and (probs[3] < esc).all()
     g.close()
 
 
