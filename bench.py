@@ -37,6 +37,9 @@ OPS_PER_UPDATE = 40
 # v_bitop3: two XORs, v_add3: two adds) retire two operations per slot, so the
 # integer-operation peak is 157.3 T ops/s
 PEAK_INT_OPS = 256 * 128 * 2.4e9 * 2
+# gate network at L=13: 2 flops per multiply-add over the three 3x3 convolutions
+# (3->32, 32->32, 32->32 on 169 pixels) and the 5408x7 head
+CNN_FLOPS_PER_SAMPLE = 2 * (169 * 32 * 27 + 2 * 169 * 32 * 288 + 7 * 5408)
 
 
 def main():
@@ -47,8 +50,12 @@ def main():
     ap.add_argument("--batch", type=int, default=BATCH)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=256)
-    ap.add_argument("--workload", choices=["metric", "mixed"], default="metric",
-                    help="metric: L=13 p=0.15 (default); mixed: L in 5..25, p in [0.05,0.18]")
+    ap.add_argument("--workload", choices=["metric", "mixed", "gated"], default="metric",
+                    help="metric: L=13 p=0.15 (default); mixed: L in 5..25, p in [0.05,0.18]; "
+                         "gated: gate network trained and timed against the plain decoder")
+    ap.add_argument("--gate-train", type=int, default=1_000_000)
+    ap.add_argument("--gate-epochs", type=int, default=4)
+    ap.add_argument("--gate-eval", type=int, default=100_000)
     ap.add_argument("--mixed-n", type=int, default=100000)
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="also run one device copy of this size (HBM counter calibration)")
@@ -66,6 +73,8 @@ def main():
     torch.cuda.set_device(dev)
     if args.workload == "mixed":
         return bench_mixed(args, mc, torch, dev)
+    if args.workload == "gated":
+        return bench_gated(args, mc, torch, dev)
     n = args.batch
     nq, ns = mc.geometry(L)
     steps, warm = args.steps, args.warmup
@@ -205,6 +214,107 @@ def bench_mixed(args, mc, torch, dev):
                                "[0.05,0.18], L^2 sweeps, 4 chains per class, one plan",
                    "tuning": tuning, "updates_per_step": plan.total_updates},
         "logical_error": {"rate": fail, "samples": n},
+    }
+    print(json.dumps(line), flush=True)
+
+
+def bench_gated(args, mc, torch, dev):
+    """The gate network at L=13: trained on the GPU on decoder-made labels for
+    syndromes with p uniform in [0.05, 0.18], then the gated decoder and the
+    plain decoder (every syndrome at L^2 sweeps, one graph-captured plan)
+    decode the same fresh syndromes with the same chains.  Reported at the
+    confidence level 0.99 with escalation (the matched-error operating
+    point), with the rest of the trade-off beside it."""
+    from paper_1302_2669_amd import gate
+    from paper_1302_2669_amd.inputs import cnn_init, uniform_rates
+    seed = SEED ^ 0x5
+    n_tr, n_ev = args.gate_train, args.gate_eval
+
+    def now():
+        torch.cuda.synchronize()
+        return time.perf_counter()
+
+    t0 = now()
+    p_tr = uniform_rates(n_tr, seed).astype(np.float64)
+    syn, _, ids = gate.sample_dataset(L, p_tr, seed, id_base=0)
+    soft, bud, _ = gate.mcmc_labels(L, syn, p_tr, ids, seed)
+    t1 = now()
+    net = gate.GateNet(L, cnn_init(L, seed), device=dev)
+    hist = gate.train(net, syn, torch.from_numpy(p_tr.astype(np.float32)).to(dev), soft, bud,
+                      epochs=args.gate_epochs, batch=512, lr=3e-3, seed=seed)
+    t2 = now()
+    del syn, soft, bud
+
+    def measure(p_ev, tag):
+        syn_e, cls_e, ids_e = gate.sample_dataset(L, p_ev, seed + 7, id_base=1 << 30)
+        plan = mc.MixedPlan.from_arrays(L, p_ev, SWEEPS, seed, chains=CHAINS, syndrome_ids=ids_e)
+        flat = syn_e.reshape(-1)
+        out = plan.execute(flat, want_correction=True, graph=True)
+        reps = max(1, args.steps // 2)
+        ta = now()
+        for _ in range(reps):
+            out = plan.execute(flat, want_correction=True, graph=True, out=out)
+        t_plain = (now() - ta) / reps
+        plan.close()
+        pr = out["chosen"] == cls_e
+        err_plain = float((~pr).float().mean())
+        points = []
+        for thr, esc in ((0.99, 0.99), (0.99, 0.0), (0.95, 0.99), (0.9, 0.99), (0.9, 0.0)):
+            g = gate.GatedDecoder(L, P, seed, max_batch=n_ev, chains=CHAINS, threshold=thr,
+                                  escalate=esc)
+            res = g.decode(net.params, syn_e, p=p_ev, ids=ids_e, want_correction=True)
+            ta = now()
+            for _ in range(reps):
+                res = g.decode(net.params, syn_e, p=p_ev, ids=ids_e, want_correction=True)
+            t_g = (now() - ta) / reps
+            g.close()
+            gr = res["chosen"] == cls_e
+            c = res["counts"]
+            work = c[1] * L + (c[2] + c[3]) * SWEEPS + c[3] * L
+            err = float((~gr).float().mean())
+            points.append({"threshold": thr, "escalate": esc, "syndromes_per_s": n_ev / t_g,
+                           "speedup": t_plain / t_g, "work_saving": n_ev * SWEEPS / work,
+                           "logical_error": err, "rel_error_change": (err - err_plain) / err_plain,
+                           "plain_right_gated_wrong": int((pr & ~gr).sum()),
+                           "plain_wrong_gated_right": int((~pr & gr).sum()), "routes": c})
+        # the network's forward pass alone over the evaluation batch
+        pe = torch.from_numpy(p_ev.astype(np.float32)).to(dev)
+        _, ws = gate.forward(L, net.params, syn_e, pe)
+        stream = torch.cuda.current_stream(dev)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            gate.forward(L, net.params, syn_e, pe, ws)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        fwd_ms = e0.elapsed_time(e1) / reps
+        return {"workload": tag, "plain_syndromes_per_s": n_ev / t_plain,
+                "plain_logical_error": err_plain, "points": points, "cnn_forward_ms": fwd_ms}
+
+    uni = measure(uniform_rates(n_ev, seed + 1).astype(np.float64),
+                  "L=13, p uniform in [0.05,0.18]")
+    fix = measure(np.full(n_ev, P), "L=13, p=0.15")
+    head = uni["points"][0]
+    flops_fwd = n_ev * CNN_FLOPS_PER_SAMPLE
+    line = {
+        "metric": "decoded syndromes/sec, gated decoder (trained gate network) vs plain MCMC",
+        "value": head["syndromes_per_s"], "unit": "syndromes/s",
+        "n_gpus": 1, "steps": max(1, args.steps // 2), "warmup": 1,
+        "ms_per_step": 1e3 * n_ev / head["syndromes_per_s"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16+u32",
+        "data": "synthetic: i.i.d. depolarizing samples; labels from the decoder itself",
+        "config": {"workload": f"L=13, p uniform in [0.05,0.18]: gate network trained on {n_tr} "
+                               f"decoder-labelled syndromes ({args.gate_epochs} epochs), "
+                               f"{n_ev} evaluation syndromes, budgets 0 / L / L^2, "
+                               "4 classes x 4 chains",
+                   "labels_s": t1 - t0, "train_s": t2 - t1, "final_train_loss": hist[-1]},
+        "speedup_vs_plain": head["speedup"],
+        "results": [uni, fix],
+        "roofline": {"bound": "mfma", "kernel": "gate network forward (three conv layers + head)",
+                     "achieved": flops_fwd / (uni["cnn_forward_ms"] * 1e-3) / 1e12,
+                     "peak": 2500.0, "unit": "TFLOP/s",
+                     "frac": flops_fwd / (uni["cnn_forward_ms"] * 1e-3) / 1e12 / 2500.0,
+                     "traffic": None, "flops_per_sample": CNN_FLOPS_PER_SAMPLE},
     }
     print(json.dumps(line), flush=True)
 
