@@ -330,6 +330,18 @@ int mcmc_cnn_forward(int32_t L, int64_t batch, const float* d_params, const uint
                      void* stream);
 
 /*
+ * Inference only: the same logits as mcmc_cnn_forward, bit for bit, from one
+ * fused kernel that keeps a group of samples' activations in LDS through all
+ * layers (nothing kept for a backward pass).  The workspace holds bf16 copies
+ * of the weights (mcmc_cnn_infer_workspace_size bytes).  EDEVICE if the
+ * device's LDS per workgroup cannot hold one sample.
+ */
+int mcmc_cnn_infer_workspace_size(int32_t L, size_t* h_bytes);
+int mcmc_cnn_infer(int32_t L, int64_t batch, const float* d_params, const uint8_t* d_syndromes,
+                   const float* d_p, float* d_logits, void* d_workspace, size_t workspace_bytes,
+                   void* stream);
+
+/*
  * Loss and gradients of the batch just run forward (same L, batch, params,
  * inputs and workspace, in stream order).  Loss per sample: soft
  * cross-entropy of the class logits against d_class_target [batch][4] fp32
@@ -361,7 +373,8 @@ int mcmc_cnn_gate(int64_t batch, const float* d_logits, float threshold, uint8_t
                   uint8_t* d_class, float* d_confidence, void* stream);
 
 /*
- * Gated decoder for one code size.  The network runs on the whole batch and
+ * Gated decoder for one code size.  The network (mcmc_cnn_infer) runs on the
+ * whole batch and
  * its gate sets each syndrome's sweep budget: route 0 = no counted sweep (the
  * decision from the class starts alone), 1 = sweeps_short, 2 = sweeps_full.
  * All syndromes then run as one mixed plan (one persistent launch of every

@@ -119,6 +119,8 @@ _SIGNATURES = {
     "mcmc_cnn_workspace_size": (ctypes.c_int, [_I32, _I64, _PSZ]),
     "mcmc_cnn_workspace_offsets": (ctypes.c_int, [_I32, _I64, ctypes.POINTER(_I64)]),
     "mcmc_cnn_forward": (ctypes.c_int, [_I32, _I64, _P, _P, _P, _P, _P, _SZ, _P]),
+    "mcmc_cnn_infer_workspace_size": (ctypes.c_int, [_I32, _PSZ]),
+    "mcmc_cnn_infer": (ctypes.c_int, [_I32, _I64, _P, _P, _P, _P, _P, _SZ, _P]),
     "mcmc_cnn_backward": (ctypes.c_int, [_I32, _I64, _P, _P, _P, _P, ctypes.c_float, _P, _P, _P,
                                          _SZ, _P]),
     "mcmc_cnn_step": (ctypes.c_int, [_I64, _I64, ctypes.c_float, ctypes.c_float, ctypes.c_float,

@@ -244,7 +244,13 @@ __global__ void wgrad_reduce_kernel(int64_t chunks, int cin_real, const float* _
 }
 
 // ---- head ----------------------------------------------------------------
-// logits[b][o] = sum_f a3[b][f] * whb[o][f] + bh[o], o < 7; 16 samples per wave.
+// logits[b][o] = sum_f a3[b][f] * whb[o][f] + bh[o], o < 7; 16 samples per
+// wave.  The sum over the L*L pixel steps (32 features each) runs as 8
+// interleaved MFMA chains, chain j taking steps j, j+8, ..., added in chain
+// order at the end; the fused inference kernel uses the same order, so both
+// give the same bits.
+constexpr int HEAD_CHAINS = 8;
+
 __global__ void __launch_bounds__(256) head_fwd_kernel(int L, int64_t B, const bf16* __restrict__ a3,
                                                        const bf16* __restrict__ whb,
                                                        const float* __restrict__ bh,
@@ -252,18 +258,171 @@ __global__ void __launch_bounds__(256) head_fwd_kernel(int L, int64_t B, const b
   const int lane = threadIdx.x & 63, grp = lane >> 4, n = lane & 15;
   const int64_t tile = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   const int64_t bm = tile * 16 + n;
-  const int64_t kh = (int64_t)L * L * CH;
-  f32x4 acc = {0, 0, 0, 0};
+  const int LL = L * L;
+  const int64_t kh = (int64_t)LL * CH;
+  f32x4 acc[HEAD_CHAINS];
+#pragma unroll
+  for (int j = 0; j < HEAD_CHAINS; ++j) acc[j] = f32x4{0, 0, 0, 0};
 #pragma unroll 1
-  for (int64_t k = 0; k < kh; k += 32) {
-    const bf16x8 a = bm < B ? load8(a3 + bm * kh + k + 8 * grp) : zero8();
-    const bf16x8 b = load8(whb + (int64_t)n * kh + k + 8 * grp);
-    acc = mfma(a, b, acc);
+  for (int st0 = 0; st0 < LL; st0 += HEAD_CHAINS) {
+#pragma unroll
+    for (int j = 0; j < HEAD_CHAINS; ++j) {
+      const int st = st0 + j;
+      if (st < LL) {
+        const bf16x8 a = bm < B ? load8(a3 + bm * kh + st * 32 + 8 * grp) : zero8();
+        const bf16x8 b = load8(whb + (int64_t)n * kh + st * 32 + 8 * grp);
+        acc[j] = mfma(a, b, acc[j]);
+      }
+    }
   }
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     const int64_t bo = tile * 16 + 4 * grp + i;
-    if (bo < B && n < 7) logits[bo * 8 + n] = acc[i] + bh[n];
+    float t = acc[0][i];
+#pragma unroll
+    for (int j = 1; j < HEAD_CHAINS; ++j) t = t + acc[j][i];
+    if (bo < B && n < 7) logits[bo * 8 + n] = t + bh[n];
+  }
+}
+
+// ---- fused inference -----------------------------------------------------
+// One workgroup (8 waves) runs S samples through the three convolutions and
+// the head with every activation in LDS; only the syndromes, rates, weights
+// and logits touch global memory.  Same operations in the same order as the
+// layered kernels above (conv: per-pixel tap/chunk k-steps on MFMA, bias,
+// ReLU, bf16; head: 8 interleaved chains), so the logits are identical.
+constexpr int INFER_THREADS = 512;
+constexpr int INFER_WAVES = INFER_THREADS / 64;
+constexpr int ASTR = 40;      // bf16 per pixel of a 32-channel activation (80 B: 16 lanes
+                              // reading 16 B each at this stride hit disjoint banks)
+constexpr int W1STR = 104;    // bf16 per row of conv1 weights (96 used)
+constexpr int W23STR = 296;   // bf16 per row of conv2/conv3 weights (288 used)
+constexpr int INFER_WEIGHT_BYTES = 32 * W1STR * 2 + 2 * 32 * W23STR * 2;
+constexpr int INFER_PART_BYTES = INFER_WAVES * 256 * 4;
+
+__device__ __forceinline__ bf16x8 lds8(const bf16* p) {
+  return __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(p));
+}
+
+template <int CIN, int WSTR, int INSTR>
+__device__ __forceinline__ void conv_lds(int L, int LL, int npix, const bf16* in, const bf16* w,
+                                         const float* __restrict__ bias, bf16* out) {
+  constexpr int KP = (9 * CIN + 31) / 32 * 32;
+  constexpr int STEPS = KP / 32;
+  constexpr int CHUNKS = CIN / 8;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, grp = lane >> 4, n = lane & 15;
+  bf16x8 bw0[STEPS], bw1[STEPS];
+#pragma unroll
+  for (int st = 0; st < STEPS; ++st) {
+    bw0[st] = lds8(w + n * WSTR + st * 32 + 8 * grp);
+    bw1[st] = lds8(w + (n + 16) * WSTR + st * 32 + 8 * grp);
+  }
+  const float bias0 = bias[n], bias1 = bias[n + 16];
+  const int ntiles = (npix + 15) / 16;
+  for (int t = wave; t < ntiles; t += INFER_WAVES) {
+    const int q = t * 16 + n;
+    const bool ok = q < npix;
+    int sm = 0, y = 0, x = 0;
+    if (ok) {
+      sm = q / LL;
+      const int r = q - sm * LL;
+      y = r / L;
+      x = r - y * L;
+    }
+    f32x4 acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
+#pragma unroll
+    for (int st = 0; st < STEPS; ++st) {
+      const int g = 4 * st + grp;
+      const int tap = g / CHUNKS, cc = g % CHUNKS;
+      bf16x8 a = zero8();
+      if (tap < 9 && ok) {
+        const int yy = y + tap_dy(tap), xx = x + tap_dx(tap);
+        if (yy >= 0 && yy < L && xx >= 0 && xx < L)
+          a = lds8(in + (sm * LL + yy * L + xx) * INSTR + cc * 8);
+      }
+      acc0 = mfma(a, bw0[st], acc0);
+      acc1 = mfma(a, bw1[st], acc1);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int po = t * 16 + 4 * grp + i;
+      if (po >= npix) continue;
+      out[po * ASTR + n] = (bf16)fmaxf(acc0[i] + bias0, 0.0f);
+      out[po * ASTR + n + 16] = (bf16)fmaxf(acc1[i] + bias1, 0.0f);
+    }
+  }
+}
+
+__global__ void __launch_bounds__(INFER_THREADS) infer_kernel(
+    int L, int S, int64_t B, const uint8_t* __restrict__ syn, const float* __restrict__ p,
+    const bf16* __restrict__ wb1, const bf16* __restrict__ wb2, const bf16* __restrict__ wb3,
+    const bf16* __restrict__ whb, const float* __restrict__ b1, const float* __restrict__ b2,
+    const float* __restrict__ b3, const float* __restrict__ bh, float* __restrict__ logits) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int LL = L * L, npix = S * LL, nst = 2 * L * (L - 1), ns = L * (L - 1);
+  bf16* w1s = reinterpret_cast<bf16*>(smem);
+  bf16* w2s = w1s + 32 * W1STR;
+  bf16* w3s = w2s + 32 * W23STR;
+  float* part = reinterpret_cast<float*>(w3s + 32 * W23STR);     // [waves][16][16]
+  bf16* bufA = reinterpret_cast<bf16*>(part + INFER_WAVES * 256);
+  bf16* bufB = bufA + npix * ASTR;
+  const int64_t s0 = (int64_t)blockIdx.x * S;
+  const int nsm = (int)min((int64_t)S, B - s0);
+  const int tid = threadIdx.x;
+
+  for (int i = tid; i < 32 * 12; i += INFER_THREADS) {
+    const int r = i / 12, c = i % 12;
+    *reinterpret_cast<uint4*>(w1s + r * W1STR + c * 8) =
+        *reinterpret_cast<const uint4*>(wb1 + r * 96 + c * 8);
+  }
+  for (int i = tid; i < 32 * 36; i += INFER_THREADS) {
+    const int r = i / 36, c = i % 36;
+    *reinterpret_cast<uint4*>(w2s + r * W23STR + c * 8) =
+        *reinterpret_cast<const uint4*>(wb2 + r * 288 + c * 8);
+    *reinterpret_cast<uint4*>(w3s + r * W23STR + c * 8) =
+        *reinterpret_cast<const uint4*>(wb3 + r * 288 + c * 8);
+  }
+  // input planes, 8 channels per pixel (the layout of the layered x0)
+  for (int q = tid; q < npix; q += INFER_THREADS) {
+    const int sm = q / LL, r = q - sm * LL, y = r / L, x = r - (r / L) * L;
+    bf16x8 v = zero8();
+    if (sm < nsm) {
+      const uint8_t* sy = syn + (s0 + sm) * nst;
+      v[0] = (bf16)((y < L - 1 && sy[y * L + x]) ? 1.0f : 0.0f);
+      v[1] = (bf16)((x < L - 1 && sy[ns + y * (L - 1) + x]) ? 1.0f : 0.0f);
+      v[2] = (bf16)p[s0 + sm];
+    }
+    *reinterpret_cast<uint4*>(bufA + q * 8) = __builtin_bit_cast(uint4, v);
+  }
+  __syncthreads();
+  conv_lds<8, W1STR, 8>(L, LL, npix, bufA, w1s, b1, bufB);
+  __syncthreads();
+  conv_lds<32, W23STR, ASTR>(L, LL, npix, bufB, w2s, b2, bufA);
+  __syncthreads();
+  conv_lds<32, W23STR, ASTR>(L, LL, npix, bufA, w3s, b3, bufB);
+  __syncthreads();
+
+  // head: wave j runs chain j over pixel steps j, j+8, ...
+  {
+    const int lane = tid & 63, wave = tid >> 6, grp = lane >> 4, n = lane & 15;
+    const int64_t kh = (int64_t)LL * CH;
+    f32x4 acc = {0, 0, 0, 0};
+    for (int st = wave; st < LL; st += INFER_WAVES) {
+      const bf16x8 a = n < nsm ? lds8(bufB + (n * LL + st) * ASTR + 8 * grp) : zero8();
+      const bf16x8 b = load8(whb + (int64_t)n * kh + st * 32 + 8 * grp);
+      acc = mfma(a, b, acc);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) part[wave * 256 + (4 * grp + i) * 16 + n] = acc[i];
+  }
+  __syncthreads();
+  if (tid < 16 * 8) {
+    const int row = tid >> 3, o = tid & 7;
+    if (row < nsm && o < 7) {
+      float t = part[row * 16 + o];
+      for (int j = 1; j < INFER_WAVES; ++j) t = t + part[j * 256 + row * 16 + o];
+      logits[(s0 + row) * 8 + o] = t + bh[o];
+    }
   }
 }
 
@@ -452,6 +611,62 @@ CnnWorkspace cnn_workspace(int L, int64_t B) {
   w.loss = take((size_t)B * 4);
   w.bytes = off;
   return w;
+}
+
+CnnWeights cnn_weights(int L) {
+  CnnWeights w{};
+  const int64_t kh = (int64_t)L * L * CH;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = off;
+    off = (off + bytes + 255) / 256 * 256;
+    return at;
+  };
+  w.wb1 = take(32 * 96 * 2);
+  w.wb2 = take(32 * 288 * 2);
+  w.wb3 = take(32 * 288 * 2);
+  w.wt2 = take(32 * 288 * 2);
+  w.wt3 = take(32 * 288 * 2);
+  w.whb = take((size_t)16 * kh * 2);
+  w.bytes = off;
+  return w;
+}
+
+int cnn_infer_group(int L) {
+  int dev = 0, maxlds = 0;
+  (void)hipGetDevice(&dev);
+  if (hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) !=
+      hipSuccess)
+    return 0;
+  const int per = 2 * L * L * ASTR * 2;
+  const int S = (maxlds - INFER_WEIGHT_BYTES - INFER_PART_BYTES) / per;
+  return S < 1 ? 0 : (S > 16 ? 16 : S);
+}
+
+hipError_t cnn_infer(int L, int64_t B, const float* prm, const uint8_t* syn, const float* p,
+                     float* logits, char* ws, hipStream_t s) {
+  const CnnWeights wl = cnn_weights(L);
+  const CnnOffsets off = cnn_offsets(L);
+  const int64_t kh = (int64_t)L * L * CH;
+  const int S = cnn_infer_group(L);
+  if (S < 1) return hipErrorInvalidConfiguration;
+  const int64_t n_cast = 16 * kh > 32 * 288 ? 16 * kh : 32 * 288;
+  bf16* wb1 = reinterpret_cast<bf16*>(ws + wl.wb1);
+  bf16* wb2 = reinterpret_cast<bf16*>(ws + wl.wb2);
+  bf16* wb3 = reinterpret_cast<bf16*>(ws + wl.wb3);
+  bf16* whb = reinterpret_cast<bf16*>(ws + wl.whb);
+  hipLaunchKernelGGL(cast_kernel, dim3(blocks_for(n_cast, 256)), dim3(256), 0, s, L, prm, off, wb1,
+                     wb2, wb3, reinterpret_cast<bf16*>(ws + wl.wt2),
+                     reinterpret_cast<bf16*>(ws + wl.wt3), whb);
+  const size_t lds = (size_t)INFER_WEIGHT_BYTES + INFER_PART_BYTES +
+                     (size_t)2 * S * L * L * ASTR * 2;
+  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&infer_kernel),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  const int64_t groups = (B + S - 1) / S;
+  hipLaunchKernelGGL(infer_kernel, dim3((unsigned)groups), dim3(INFER_THREADS), lds, s, L, S, B,
+                     syn, p, wb1, wb2, wb3, whb, prm + off.b1, prm + off.b2, prm + off.b3,
+                     prm + off.bh, logits);
+  return hipGetLastError();
 }
 
 #define WSP(T, name) reinterpret_cast<T*>(ws + wl.name)

@@ -60,6 +60,26 @@ int mcmc_cnn_forward(int32_t L, int64_t batch, const float* d_params, const uint
                                 (char*)d_workspace, (hipStream_t)stream));
 }
 
+int mcmc_cnn_infer_workspace_size(int32_t L, size_t* h_bytes) {
+  if (!valid_L(L)) return MCMC_ERANGE;
+  if (!h_bytes) return MCMC_EINVAL;
+  *h_bytes = cnn_weights(L).bytes;
+  return MCMC_OK;
+}
+
+int mcmc_cnn_infer(int32_t L, int64_t batch, const float* d_params, const uint8_t* d_syndromes,
+                   const float* d_p, float* d_logits, void* d_workspace, size_t workspace_bytes,
+                   void* stream) {
+  if (!valid_L(L) || !cnn_batch_ok(batch)) return MCMC_ERANGE;
+  if (batch == 0) return MCMC_OK;
+  if (!d_params || !d_syndromes || !d_p || !d_logits) return MCMC_EINVAL;
+  const int st = check_ws(d_workspace, workspace_bytes, cnn_weights(L).bytes);
+  if (st != MCMC_OK) return st;
+  if (cnn_infer_group(L) < 1) return MCMC_EDEVICE;
+  return hip_status(cnn_infer(L, batch, d_params, d_syndromes, d_p, d_logits, (char*)d_workspace,
+                              (hipStream_t)stream));
+}
+
 int mcmc_cnn_backward(int32_t L, int64_t batch, const float* d_params, const float* d_logits,
                       const float* d_class_target, const int32_t* d_budget, float budget_weight,
                       float* d_grads, float* d_loss, void* d_workspace, size_t workspace_bytes,
@@ -132,7 +152,7 @@ GatedWorkspace gated_workspace(const mcmc_gated* g) {
     off = align_up(off + bytes);
     return at;
   };
-  w.cnn = take(cnn_workspace(g->cfg.L, n).bytes);
+  w.cnn = take(cnn_weights(g->cfg.L).bytes);
   w.logits = take((size_t)n * 8 * sizeof(float));
   w.pf = take((size_t)n * sizeof(float));
   w.route = take((size_t)n);
@@ -186,6 +206,7 @@ int mcmc_gated_create(const mcmc_gate_config* h_cfg, mcmc_gated** out) {
   if (!(c.escalate >= 0.0f && c.escalate <= 1.0f)) return MCMC_ERANGE;
   if (c.sweeps_short < 0 || c.sweeps_full < 0) return MCMC_ERANGE;
   if (c.init != MCMC_INIT_CANONICAL && c.init != MCMC_INIT_MATCHING) return MCMC_EINVAL;
+  if (cnn_infer_group(c.L) < 1) return MCMC_EDEVICE;
   mcmc_gated* g = new (std::nothrow) mcmc_gated();
   if (!g) return MCMC_ENOMEM;
   g->cfg = c;
@@ -266,7 +287,7 @@ int mcmc_gated_decode(mcmc_gated* g, const float* d_params, const uint8_t* d_syn
   if (hipMemcpyAsync(pf, g->h_pf, (size_t)n * sizeof(float), hipMemcpyHostToDevice, s) !=
       hipSuccess)
     return MCMC_EDEVICE;
-  st = hip_status(cnn_forward(c.L, n, d_params, d_syndromes, pf, logits, ws + wl.cnn, s));
+  st = hip_status(cnn_infer(c.L, n, d_params, d_syndromes, pf, logits, ws + wl.cnn, s));
   if (st != MCMC_OK) return st;
   st = hip_status(cnn_gate(n, logits, c.threshold, route, (uint8_t*)(ws + wl.cls),
                            (float*)(ws + wl.conf), s));

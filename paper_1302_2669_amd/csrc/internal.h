@@ -155,7 +155,19 @@ struct CnnWorkspace {
   size_t x0, a1, a2, a3, wb1, wb2, wb3, wt2, wt3, whb, dz, dp3, dp2, dp1, part, partb, loss,
       bytes;
 };
+// Byte offsets of the bf16 weight copies (the workspace of cnn_infer).
+struct CnnWeights {
+  size_t wb1, wb2, wb3, wt2, wt3, whb, bytes;
+};
 CnnOffsets cnn_offsets(int L);
+CnnWeights cnn_weights(int L);
+// Samples per workgroup of the fused inference kernel on the current device
+// (0 if one sample does not fit in its LDS).
+int cnn_infer_group(int L);
+// Logits of the forward pass with every activation kept on chip; identical
+// to cnn_forward's.
+hipError_t cnn_infer(int L, int64_t B, const float* prm, const uint8_t* syn, const float* p,
+                     float* logits, char* ws, hipStream_t s);
 CnnWorkspace cnn_workspace(int L, int64_t B);
 hipError_t cnn_forward(int L, int64_t B, const float* prm, const uint8_t* syn, const float* p,
                        float* logits, char* ws, hipStream_t s);

@@ -15,6 +15,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <thread>
 #include <functional>
 #include <map>
 #include <new>
@@ -261,41 +262,88 @@ int build_plan(mcmc_plan* p, const mcmc_item* items, int64_t n) {
   p->total_chains = p->total_rows = p->total_updates = 0;
   for (int r = 0; r < N_RANGES; ++r) p->range_first[r] = p->range_tiles[r] = 0;
 
-  // groups: (L, K, C, burn, sweeps) -> items
-  std::map<std::tuple<int, int, int, int, int>, std::vector<int64_t>> by_key;
+  // groups: (L, K, C, burn, sweeps) -> items, in order of first appearance
+  // (a batch has few distinct keys: linear search with a last-hit cache)
+  using Key = std::tuple<int, int, int, int, int>;
+  std::vector<std::pair<Key, std::vector<int64_t>>> by_key;
+  size_t last = 0;
   for (int64_t i = 0; i < n; ++i) {
     const mcmc_item& it = items[i];
-    by_key[{it.L, it.n_temps, it.chains, it.burn, it.sweeps}].push_back(i);
+    const Key k{it.L, it.n_temps, it.chains, it.burn, it.sweeps};
+    if (by_key.empty() || by_key[last].first != k) {
+      last = by_key.size();
+      for (size_t j = 0; j < by_key.size(); ++j)
+        if (by_key[j].first == k) {
+          last = j;
+          break;
+        }
+      if (last == by_key.size()) by_key.push_back({k, {}});
+    }
+    by_key[last].second.push_back(i);
   }
-  // per-chain cost of a group: (burn + sweeps) * n_stab
-  std::vector<std::pair<int64_t, std::tuple<int, int, int, int, int>>> order;
-  for (auto& kv : by_key) {
-    const auto& k = kv.first;
-    const int64_t cost = ((int64_t)std::get<3>(k) + std::get<4>(k)) * n_stab(std::get<0>(k));
-    order.push_back({cost, k});
-  }
-  std::stable_sort(order.begin(), order.end(),
-                   [](const auto& a, const auto& b) { return a.first > b.first; });
+  // per-chain cost of a group: (burn + sweeps) * n_stab; most costly first,
+  // equal costs in key order
+  std::vector<size_t> order(by_key.size());
+  for (size_t j = 0; j < order.size(); ++j) order[j] = j;
+  auto cost = [&](size_t j) {
+    const Key& k = by_key[j].first;
+    return ((int64_t)std::get<3>(k) + std::get<4>(k)) * n_stab(std::get<0>(k));
+  };
+  std::sort(order.begin(), order.end(), [&](size_t a, size_t b) {
+    const int64_t ca = cost(a), cb = cost(b);
+    return ca != cb ? ca > cb : by_key[a].first < by_key[b].first;
+  });
 
-  // per-chain outputs and start blocks in the caller's order
-  std::vector<int64_t> chain_off(n), rows_off(n);
-  int64_t c_acc = 0, r_acc = 0;
+  // per-chain outputs, start blocks and table rows in the caller's order
+  std::vector<int64_t> chain_off(n), rows_off(n), table_off(n);
+  int64_t c_acc = 0, r_acc = 0, t_acc = 0;
   for (int64_t i = 0; i < n; ++i) {
     chain_off[i] = c_acc;
     rows_off[i] = r_acc;
+    table_off[i] = t_acc;
     c_acc += 4 * (int64_t)items[i].n_temps * items[i].chains;
     r_acc += (int64_t)words_per_config(items[i].L) * 4;
+    t_acc += 4 * (int64_t)items[i].n_temps;
   }
   p->total_chains = c_acc;
   p->total_rows = r_acc;
 
+  // acceptance tables and beta_bar per item, in parallel over contiguous
+  // chunks (an item with the rate and ladder of the one before copies its rows)
+  p->tables.resize((size_t)t_acc);
+  std::vector<double> bbar(n);
+  auto fill = [&](int64_t lo, int64_t hi) {
+    for (int64_t i = lo; i < hi; ++i) {
+      const mcmc_item& it = items[i];
+      uint32_t* dst = p->tables.data() + table_off[i];
+      if (i > lo && it.p == items[i - 1].p && it.n_temps == items[i - 1].n_temps) {
+        std::copy(dst - 4 * it.n_temps, dst, dst);
+        bbar[i] = bbar[i - 1];
+      } else {
+        fill_table(it.p, it.n_temps, dst);
+        bbar[i] = beta_bar(it.p);
+      }
+    }
+  };
+  const int64_t kChunk = 4096;
+  const int workers = (int)std::min<int64_t>(
+      std::max(1u, std::min(16u, std::thread::hardware_concurrency())), (n + kChunk - 1) / kChunk);
+  if (workers <= 1) {
+    fill(0, n);
+  } else {
+    std::vector<std::thread> pool;
+    const int64_t per = (n + workers - 1) / workers;
+    for (int w = 0; w < workers; ++w) {
+      const int64_t lo = w * per, hi = std::min(n, lo + per);
+      if (lo < hi) pool.emplace_back(fill, lo, hi);
+    }
+    for (auto& t : pool) t.join();
+  }
+
   p->items.reserve(n);
-  double last_p = -1.0;
-  int32_t last_K = 0;
-  int64_t last_table = -1;
-  for (auto& o : order) {
-    const auto& k = o.second;
-    const std::vector<int64_t>& members = by_key[k];
+  for (size_t j : order) {
+    const Key& k = by_key[j].first;
+    const std::vector<int64_t>& members = by_key[j].second;
     GroupDesc g{};
     g.L = std::get<0>(k);
     g.K = std::get<1>(k);
@@ -315,20 +363,11 @@ int build_plan(mcmc_plan* p, const mcmc_item* items, int64_t n) {
       it.rows_off = rows_off[i];
       it.chain_off = chain_off[i];
       it.corr_off = src.corr_offset;
-      it.beta_bar = beta_bar(src.p);
+      it.table_off = table_off[i];
+      it.beta_bar = bbar[i];
       it.sid = src.syndrome_id;
       it.group = gid;
       it.err_thr = (uint32_t)floor(ldexp(src.p, 32));
-      if (src.p == last_p && src.n_temps == last_K) {
-        it.table_off = last_table;   // same rate and ladder: share the rows
-      } else {
-        it.table_off = (int64_t)p->tables.size();
-        p->tables.resize(p->tables.size() + 4 * (size_t)src.n_temps);
-        fill_table(src.p, src.n_temps, p->tables.data() + it.table_off);
-        last_p = src.p;
-        last_K = src.n_temps;
-        last_table = it.table_off;
-      }
       p->items.push_back(it);
       p->total_updates += 4 * (int64_t)src.n_temps * src.chains *
                           ((int64_t)src.burn + src.sweeps) * n_stab(src.L);
@@ -352,11 +391,7 @@ int build_plan(mcmc_plan* p, const mcmc_item* items, int64_t n) {
   const size_t gsz = align_up(p->groups.size() * sizeof(GroupDesc) + 1);
   const size_t isz = align_up(p->items.size() * sizeof(ItemDesc) + 1);
   const size_t tsz = align_up(p->tiles.size() * sizeof(TileDesc) + 1);
-  // table rows are shared by consecutive items of one rate; the block is
-  // sized for none shared so that a rebuild with other rates fits
-  size_t table_cap = 0;
-  for (int64_t i = 0; i < n; ++i) table_cap += 4 * (size_t)items[i].n_temps;
-  const size_t bsz = align_up(std::max(p->tables.size(), table_cap) * sizeof(uint32_t) + 1);
+  const size_t bsz = align_up(p->tables.size() * sizeof(uint32_t) + 1);
   const size_t need = gsz + isz + tsz + bsz;
   if (need > p->dev_bytes) {
     if (p->dev) (void)hipFree(p->dev);

@@ -56,6 +56,25 @@ def forward(L, params, syndromes, p, workspace=None):
     return logits, workspace
 
 
+def infer(L, params, syndromes, p, workspace=None):
+    """logits [B][8] of the fused inference kernel (identical to forward's)."""
+    torch = _torch()
+    B = syndromes.shape[0]
+    dev = syndromes.device
+    if workspace is None:
+        b = ctypes.c_size_t()
+        _lib.check(_lib._lib().mcmc_cnn_infer_workspace_size(int(L), ctypes.byref(b)),
+                   "mcmc_cnn_infer_workspace_size")
+        workspace = torch.empty((max(b.value, 1),), dtype=torch.uint8, device=dev)
+    logits = torch.zeros((B, 8), dtype=torch.float32, device=dev)
+    syndromes = syndromes.contiguous()
+    p = p.to(dtype=torch.float32).contiguous()
+    _lib.check(_lib._lib().mcmc_cnn_infer(int(L), B, _ptr(params), _ptr(syndromes), _ptr(p),
+                                          _ptr(logits), _ptr(workspace), workspace.numel(),
+                                          _stream(dev)), "mcmc_cnn_infer")
+    return logits, workspace
+
+
 def backward(L, params, logits, class_target, budget, workspace, budget_weight=0.5,
              want_loss=True):
     """(grads [param_count] fp32, per-sample loss [B] or None) of the batch

@@ -277,3 +277,22 @@ def test_training_reduces_loss():
     last = float(last.mean())
     say(f"loss {first:.4f} -> {last:.4f}")
     assert last < 0.5 * first
+
+
+@pytest.mark.parametrize("L,B", [(2, 1), (3, 37), (5, 70), (13, 23), (13, 1001), (25, 3)])
+def test_fused_inference_matches_layered_forward(L, B):
+    """The fused kernel runs the layered forward's operations in the same
+    order: identical logits, bit for bit, on ragged batches (partial sample
+    groups, partial 16-pixel tiles)."""
+    props = torch.cuda.get_device_properties(0)
+    say(f"infer L={L} B={B} (LDS per block {getattr(props, 'shared_memory_per_block', '?')})")
+    syn = torch.from_numpy(uniform_syndromes(L, B, SEED + 31 * L + B, density=0.15)).to(DEV)
+    p = torch.from_numpy(uniform_rates(B, SEED + 5 + B)).to(DEV)
+    prm = cnn_init(L, SEED + 6)
+    rng = np.random.default_rng(SEED + 7)
+    prm += rng.normal(0.0, 0.05, size=prm.size).astype(np.float32)   # non-zero biases
+    d_prm = torch.from_numpy(prm).to(DEV)
+    ref, _ = gate.forward(L, d_prm, syn, p)
+    got, _ = gate.infer(L, d_prm, syn, p)
+    torch.cuda.synchronize()
+    assert torch.equal(got[:, :7], ref[:, :7])
