@@ -37,6 +37,13 @@ OPS_PER_UPDATE = 40
 # v_bitop3: two XORs, v_add3: two adds) retire two operations per slot, so the
 # integer-operation peak is 157.3 T ops/s
 PEAK_INT_OPS = 256 * 128 * 2.4e9 * 2
+# HBM traffic of the chain kernel from rocprofv3 FETCH_SIZE (x2.000, the
+# counter's reading of a 256 MiB copy) + WRITE_SIZE (x1.000) at 16384 syndromes
+# per launch (the counters file under profiles/ for chains_r0 at L=13): bytes
+# per syndrome, valid only for the kernel sources it was measured on
+CHAIN_TRAFFIC_PER_SYNDROME = 46788694 / 16384
+CHAIN_TRAFFIC_SOURCES = ("chain_body.h", "chain_r0.hip", "device_common.h", "internal.h")
+CHAIN_TRAFFIC_SHA = "6df32d91d2f46754"
 # gate network at L=13: 2 flops per multiply-add over the three 3x3 convolutions
 # (3->32, 32->32, 32->32 on 169 pixels) and the 5408x7 head
 CNN_FLOPS_PER_SAMPLE = 2 * (169 * 32 * 27 + 2 * 169 * 32 * 288 + 7 * 5408)
@@ -169,13 +176,30 @@ def main():
                    "n_temps": K, "batch": n, "updates_per_syndrome": updates_per_syndrome},
         "logical_error": {"rate": p_l, "wilson95": [centre - half, centre + half],
                           "samples": total},
-        "roofline": {"bound": "alu", "kernel": "chain_kernel<13>", "achieved": achieved,
-                     "peak": peak, "unit": "Tops/s", "frac": achieved / peak, "traffic": None,
+        "roofline": {"bound": "alu", "kernel": "chains_r0_kernel (L 2..13, at L=13)",
+                     "achieved": achieved, "peak": peak, "unit": "Tops/s",
+                     "frac": achieved / peak, "traffic": chain_traffic(n),
+                     "traffic_unit": "bytes per launch",
+                     "algorithmic_bytes": n * (4 * 104 + 16 * 20 + 4 * 100),
                      "chain_ms_per_launch": chain_ms, "ops_per_update": OPS_PER_UPDATE,
                      "updates_per_launch": chain_updates},
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
+
+
+def chain_traffic(n):
+    """Measured HBM bytes of one chain-kernel launch of n syndromes, or None
+    when the kernel sources differ from the ones the counters were taken on."""
+    import hashlib
+    here = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1302_2669_amd", "csrc")
+    h = hashlib.sha256()
+    for f in CHAIN_TRAFFIC_SOURCES:
+        with open(os.path.join(here, f), "rb") as fh:
+            h.update(fh.read())
+    if h.hexdigest()[:16] != CHAIN_TRAFFIC_SHA:
+        return None
+    return CHAIN_TRAFFIC_PER_SYNDROME * n
 
 
 def bench_mixed(args, mc, torch, dev):
