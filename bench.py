@@ -56,7 +56,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--batch", type=int, default=BATCH)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=256)
+    ap.add_argument("--cpu-sample", type=int, default=640)
+    ap.add_argument("--no-budget-curve", action="store_true",
+                    help="skip the logical error vs sweep budget curve")
     ap.add_argument("--workload", choices=["metric", "mixed", "gated"], default="metric",
                     help="metric: L=13 p=0.15 (default); mixed: L in 5..25, p in [0.05,0.18]; "
                          "gated: gate network trained and timed against the plain decoder")
@@ -98,9 +100,10 @@ def main():
            for b in range(warm + steps)]
     torch.cuda.synchronize()
 
-    def step(b, sweeps=SWEEPS):
+    def step(b, sweeps=SWEEPS, burn=BURN, workspace=ws):
         return mc.decode_batch(batches[b], L, P, sweeps, SEED, chains=CHAINS, n_temps=K,
-                               burn=BURN, syndrome_ids=ids[b], want_correction=True, workspace=ws)
+                               burn=burn, syndrome_ids=ids[b], want_correction=True,
+                               workspace=workspace)
 
     for b in range(warm):
         step(b)
@@ -145,6 +148,47 @@ def main():
     achieved = chain_updates * OPS_PER_UPDATE / (chain_ms * 1e-3) / 1e12
     peak = PEAK_INT_OPS / 1e12
 
+    # logical error vs sweep budget on the same syndromes and chains (chains
+    # are keyed by sweep, so a shorter budget is a prefix of the same run):
+    # the smallest budget within 2% relative of the full one is the
+    # matched-error operating point
+    curve = None
+    if not args.no_budget_curve:
+        nb = min(4, steps)
+        full_chosen = chosen[:nb]
+        curve = []
+        # counted sweeps (burn-in 0) from L^2/8 to 4 L^2, and L^2 split into
+        # L^2/2 uncounted + L^2/2 counted (same cost as L^2)
+        points = [(SWEEPS // 8, 0), (SWEEPS // 4, 0), (SWEEPS // 2, 0), (SWEEPS, 0),
+                  (2 * SWEEPS, 0), (4 * SWEEPS, 0), (SWEEPS - SWEEPS // 2, SWEEPS // 2)]
+        ws_big = None
+        for b, burn in points:
+            if b + burn > SWEEPS and ws_big is None:
+                ws_big = torch.empty((mc.workspace_size(mc.make_params(
+                    L, P, 4 * SWEEPS, SEED, chains=CHAINS, n_temps=K), n),),
+                    dtype=torch.uint8, device=dev)
+            outs = []
+            c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            c0.record(stream)
+            for i in range(nb):
+                outs.append(step(warm + i, sweeps=b, burn=burn,
+                                 workspace=ws if ws_big is None else ws_big)["chosen"])
+            c1.record(stream)
+            torch.cuda.synchronize()
+            ms_b = c0.elapsed_time(c1) / nb
+            wrong = sum(int((o != t).sum().item()) for o, t in zip(outs, truth[warm:warm + nb]))
+            right_full = [f == t for f, t in zip(full_chosen, truth[warm:warm + nb])]
+            right_b = [o == t for o, t in zip(outs, truth[warm:warm + nb])]
+            worse = sum(int((rf & ~rb).sum().item()) for rf, rb in zip(right_full, right_b))
+            better = sum(int((~rf & rb).sum().item()) for rf, rb in zip(right_full, right_b))
+            curve.append({"sweeps": b, "burn": burn, "logical_error": wrong / (n * nb),
+                          "syndromes_per_s": n / (ms_b * 1e-3),
+                          "full_right_budget_wrong": worse, "full_wrong_budget_right": better})
+        ref_err = next(c for c in curve if c["sweeps"] == SWEEPS and c["burn"] == 0)["logical_error"]
+        for c in curve:
+            c["rel_error_change"] = (c["logical_error"] - ref_err) / ref_err
+        matched = next(c for c in curve if c["rel_error_change"] <= 0.02)
+
     if args.copy_probe_mb:
         src = torch.ones((args.copy_probe_mb << 20,), dtype=torch.uint8, device=dev)
         dst = torch.empty_like(src)
@@ -184,6 +228,12 @@ def main():
                      "chain_ms_per_launch": chain_ms, "ops_per_update": OPS_PER_UPDATE,
                      "updates_per_launch": chain_updates},
         "cpu_baseline": cpu,
+        "budget_curve": curve,
+        "matched_error_budget": None if curve is None else
+            {"sweeps": matched["sweeps"], "syndromes_per_s": matched["syndromes_per_s"],
+             "rel_error_change": matched["rel_error_change"],
+             "note": "smallest counted budget (no burn-in) within 2% relative of the L^2 "
+                     "logical error on the same syndromes and chains"},
     }
     print(json.dumps(line), flush=True)
 

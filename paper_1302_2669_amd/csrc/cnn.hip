@@ -270,7 +270,7 @@ __global__ void __launch_bounds__(256) head_fwd_kernel(int L, int64_t B, const b
       const int st = st0 + j;
       if (st < LL) {
         const bf16x8 a = bm < B ? load8(a3 + bm * kh + st * 32 + 8 * grp) : zero8();
-        const bf16x8 b = load8(whb + (int64_t)n * kh + st * 32 + 8 * grp);
+        const bf16x8 b = n < 7 ? load8(whb + (int64_t)n * kh + st * 32 + 8 * grp) : zero8();
         acc[j] = mfma(a, b, acc[j]);
       }
     }
@@ -298,15 +298,20 @@ constexpr int ASTR = 40;      // bf16 per pixel of a 32-channel activation (80 B
 constexpr int W1STR = 104;    // bf16 per row of conv1 weights (96 used)
 constexpr int W23STR = 296;   // bf16 per row of conv2/conv3 weights (288 used)
 constexpr int INFER_WEIGHT_BYTES = 32 * W1STR * 2 + 2 * 32 * W23STR * 2;
-constexpr int INFER_PART_BYTES = INFER_WAVES * 256 * 4;
+constexpr int INFER_PART_BYTES = INFER_WAVES * 256 * 4 + 16;   // + a 16-byte zero slot
 
 __device__ __forceinline__ bf16x8 lds8(const bf16* p) {
   return __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(p));
 }
 
+// One convolution over the group's pixels, LDS to LDS.  Each wave takes two
+// 16-pixel tiles per trip (four independent MFMA chains); an A operand whose
+// tap falls outside the image (or whose pixel is past the group) is read from
+// a 16-byte slot of zeros, so the loads carry no branches.
 template <int CIN, int WSTR, int INSTR>
 __device__ __forceinline__ void conv_lds(int L, int LL, int npix, const bf16* in, const bf16* w,
-                                         const float* __restrict__ bias, bf16* out) {
+                                         const float* __restrict__ bias, bf16* out,
+                                         const bf16* zslot) {
   constexpr int KP = (9 * CIN + 31) / 32 * 32;
   constexpr int STEPS = KP / 32;
   constexpr int CHUNKS = CIN / 8;
@@ -319,36 +324,46 @@ __device__ __forceinline__ void conv_lds(int L, int LL, int npix, const bf16* in
   }
   const float bias0 = bias[n], bias1 = bias[n + 16];
   const int ntiles = (npix + 15) / 16;
-  for (int t = wave; t < ntiles; t += INFER_WAVES) {
-    const int q = t * 16 + n;
-    const bool ok = q < npix;
-    int sm = 0, y = 0, x = 0;
-    if (ok) {
-      sm = q / LL;
-      const int r = q - sm * LL;
-      y = r / L;
-      x = r - y * L;
+  for (int t0 = wave; t0 < ntiles; t0 += 2 * INFER_WAVES) {
+    int q[2], y[2], x[2];
+    bool ok[2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      q[u] = (t0 + u * INFER_WAVES) * 16 + n;
+      ok[u] = q[u] < npix;
+      const int r = ok[u] ? q[u] % LL : 0;
+      y[u] = r / L;
+      x[u] = r - y[u] * L;
     }
-    f32x4 acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
+    f32x4 acc[2][2] = {{{0, 0, 0, 0}, {0, 0, 0, 0}}, {{0, 0, 0, 0}, {0, 0, 0, 0}}};
 #pragma unroll
     for (int st = 0; st < STEPS; ++st) {
       const int g = 4 * st + grp;
       const int tap = g / CHUNKS, cc = g % CHUNKS;
-      bf16x8 a = zero8();
-      if (tap < 9 && ok) {
-        const int yy = y + tap_dy(tap), xx = x + tap_dx(tap);
-        if (yy >= 0 && yy < L && xx >= 0 && xx < L)
-          a = lds8(in + (sm * LL + yy * L + xx) * INSTR + cc * 8);
+      const int dy = tap_dy(tap), dx = tap_dx(tap);
+      bf16x8 a[2];
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int yy = y[u] + dy, xx = x[u] + dx;
+        const bool in_img = ok[u] && tap < 9 && yy >= 0 && yy < L && xx >= 0 && xx < L;
+        const bf16* src = in_img ? in + (q[u] + dy * L + dx) * INSTR + cc * 8 : zslot;
+        a[u] = lds8(src);
       }
-      acc0 = mfma(a, bw0[st], acc0);
-      acc1 = mfma(a, bw1[st], acc1);
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        acc[u][0] = mfma(a[u], bw0[st], acc[u][0]);
+        acc[u][1] = mfma(a[u], bw1[st], acc[u][1]);
+      }
     }
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int po = t * 16 + 4 * grp + i;
-      if (po >= npix) continue;
-      out[po * ASTR + n] = (bf16)fmaxf(acc0[i] + bias0, 0.0f);
-      out[po * ASTR + n + 16] = (bf16)fmaxf(acc1[i] + bias1, 0.0f);
+    for (int u = 0; u < 2; ++u) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int po = (t0 + u * INFER_WAVES) * 16 + 4 * grp + i;
+        if (po >= npix) continue;
+        out[po * ASTR + n] = (bf16)fmaxf(acc[u][0][i] + bias0, 0.0f);
+        out[po * ASTR + n + 16] = (bf16)fmaxf(acc[u][1][i] + bias1, 0.0f);
+      }
     }
   }
 }
@@ -364,7 +379,8 @@ __global__ void __launch_bounds__(INFER_THREADS) infer_kernel(
   bf16* w2s = w1s + 32 * W1STR;
   bf16* w3s = w2s + 32 * W23STR;
   float* part = reinterpret_cast<float*>(w3s + 32 * W23STR);     // [waves][16][16]
-  bf16* bufA = reinterpret_cast<bf16*>(part + INFER_WAVES * 256);
+  bf16* zslot = reinterpret_cast<bf16*>(part + INFER_WAVES * 256);
+  bf16* bufA = zslot + 8;
   bf16* bufB = bufA + npix * ASTR;
   const int64_t s0 = (int64_t)blockIdx.x * S;
   const int nsm = (int)min((int64_t)S, B - s0);
@@ -382,6 +398,7 @@ __global__ void __launch_bounds__(INFER_THREADS) infer_kernel(
     *reinterpret_cast<uint4*>(w3s + r * W23STR + c * 8) =
         *reinterpret_cast<const uint4*>(wb3 + r * 288 + c * 8);
   }
+  if (tid < 8) zslot[tid] = (bf16)0.0f;
   // input planes, 8 channels per pixel (the layout of the layered x0)
   for (int q = tid; q < npix; q += INFER_THREADS) {
     const int sm = q / LL, r = q - sm * LL, y = r / L, x = r - (r / L) * L;
@@ -395,11 +412,11 @@ __global__ void __launch_bounds__(INFER_THREADS) infer_kernel(
     *reinterpret_cast<uint4*>(bufA + q * 8) = __builtin_bit_cast(uint4, v);
   }
   __syncthreads();
-  conv_lds<8, W1STR, 8>(L, LL, npix, bufA, w1s, b1, bufB);
+  conv_lds<8, W1STR, 8>(L, LL, npix, bufA, w1s, b1, bufB, zslot);
   __syncthreads();
-  conv_lds<32, W23STR, ASTR>(L, LL, npix, bufB, w2s, b2, bufA);
+  conv_lds<32, W23STR, ASTR>(L, LL, npix, bufB, w2s, b2, bufA, zslot);
   __syncthreads();
-  conv_lds<32, W23STR, ASTR>(L, LL, npix, bufA, w3s, b3, bufB);
+  conv_lds<32, W23STR, ASTR>(L, LL, npix, bufA, w3s, b3, bufB, zslot);
   __syncthreads();
 
   // head: wave j runs chain j over pixel steps j, j+8, ...
@@ -409,7 +426,8 @@ __global__ void __launch_bounds__(INFER_THREADS) infer_kernel(
     f32x4 acc = {0, 0, 0, 0};
     for (int st = wave; st < LL; st += INFER_WAVES) {
       const bf16x8 a = n < nsm ? lds8(bufB + (n * LL + st) * ASTR + 8 * grp) : zero8();
-      const bf16x8 b = load8(whb + (int64_t)n * kh + st * 32 + 8 * grp);
+      // rows 7..15 of the padded head weights are zero: not read
+      const bf16x8 b = n < 7 ? load8(whb + (int64_t)n * kh + st * 32 + 8 * grp) : zero8();
       acc = mfma(a, b, acc);
     }
 #pragma unroll
