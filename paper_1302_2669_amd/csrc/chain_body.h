@@ -103,6 +103,11 @@ __device__ __forceinline__ void row_fence(uint32_t (&st)[R][W], int32_t& dn, int
     for (int w = 0; w < W; ++w) asm volatile("" : "+v"(st[r][w]));
   asm volatile("" : "+v"(dn), "+v"(acc));
 }
+// Philox blocks two at a time (interleaved rounds, more independent work per
+// wave) unless the including kernel turns it off; the words are identical.
+#ifndef MCMC_PAIRED_PHILOX
+#define MCMC_PAIRED_PHILOX 1
+#endif
 #ifndef MCMC_ROW_FENCE
 #define MCMC_ROW_FENCE() row_fence(st, dn, acc_total)
 #endif
@@ -181,6 +186,7 @@ __device__ __forceinline__ void run_chain(const RunArgs& a, const GroupDesc& g, 
   for (int sweep = g.sweep_begin; sweep < g.sweep_end; ++sweep) {
     rng.begin_sweep((uint32_t)sweep);
     uint4 blk = make_uint4(0, 0, 0, 0);
+    uint4 blk_next = make_uint4(0, 0, 0, 0);
     int32_t dn = 0;     // weight change of the current phase
     int32_t acc_total = 0;
 
@@ -208,7 +214,18 @@ __device__ __forceinline__ void run_chain(const RunArgs& a, const GroupDesc& g, 
         constexpr int j = par + 2 * m;
         constexpr int w = j / 16, nib = (j % 16) / 2;
         constexpr int d = d0 + m;
+#if MCMC_PAIRED_PHILOX
+        // blocks two at a time (the second waits in blk_next); a lone last
+        // block of the sweep is computed alone
+        if constexpr ((d & 7) == 0) {
+          if constexpr (d / 4 + 1 < S) rng.template block_pair<d / 4>(blk, blk_next);
+          else blk = rng.template block<d / 4>();
+        } else if constexpr ((d & 7) == 4) {
+          blk = blk_next;
+        }
+#else
         if constexpr ((d & 3) == 0) blk = rng.template block<d / 4>();
+#endif
         const uint32_t thr = lds_tbl[(sum[w] >> (4 * nib)) & 15u][lane];
         rbits = push_accept(rbits, word_of(blk, d & 3), thr);
       });

@@ -2,6 +2,9 @@
 // Each kernel's L range is small enough to compile in about two minutes and
 // to share one register budget; a batch runs one kernel per range its
 // syndromes fall in.
+// At 80 VGPRs, computing Philox blocks in pairs costs more spills than the
+// extra independent work gains at 6 waves per SIMD: blocks one at a time.
+#define MCMC_PAIRED_PHILOX 0
 #include "chain_body.h"
 
 namespace mcmc {

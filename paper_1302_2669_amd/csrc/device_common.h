@@ -104,6 +104,32 @@ __device__ __forceinline__ uint4 philox_rounds(uint4 c, uint32_t k0, uint32_t k1
   return c;
 }
 
+// The same rounds on two counters at once, interleaved: the two products of
+// one round of each counter are independent, which doubles the work a wave
+// can issue between dependent multiplies.
+__device__ __forceinline__ void philox_rounds2(uint4& c, uint4& e, uint32_t k0, uint32_t k1,
+                                               int first) {
+  k0 += (uint32_t)first * PHILOX_W0;
+  k1 += (uint32_t)first * PHILOX_W1;
+  int r = first;
+  if ((10 - first) & 1) {
+    c = philox_round(c, k0, k1);
+    e = philox_round(e, k0, k1);
+    k0 += PHILOX_W0;
+    k1 += PHILOX_W1;
+    ++r;
+  }
+#pragma unroll 1
+  for (; r < 10; r += 2) {
+    c = philox_round(c, k0, k1);
+    e = philox_round(e, k0, k1);
+    c = philox_round(c, k0 + PHILOX_W0, k1 + PHILOX_W1);
+    e = philox_round(e, k0 + PHILOX_W0, k1 + PHILOX_W1);
+    k0 += 2 * PHILOX_W0;
+    k1 += 2 * PHILOX_W1;
+  }
+}
+
 __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1) {
   return philox_rounds(c, k0, k1, 0);
 }
@@ -144,6 +170,20 @@ struct ChainRng {
     const uint4 c = make_uint4(qh ^ sid_lo ^ (k0 + PHILOX_W0), ql,
                                sw_hi ^ lo0 ^ (k1 + PHILOX_W1), sw_lo);
     return philox_rounds(c, k0, k1, 2);
+  }
+  // Blocks BLK and BLK + 1 together (identical words to two block() calls).
+  template <int BLK>
+  __device__ __forceinline__ void block_pair(uint4& b0, uint4& b1) const {
+    constexpr uint64_t pa = (uint64_t)PHILOX_M0 * (uint64_t)(uint32_t)BLK;
+    constexpr uint64_t pc = (uint64_t)PHILOX_M0 * (uint64_t)(uint32_t)(BLK + 1);
+    constexpr uint32_t ha = (uint32_t)(pa >> 32), la = (uint32_t)pa;
+    constexpr uint32_t hc = (uint32_t)(pc >> 32), lc = (uint32_t)pc;
+    uint32_t qh, ql, rh, rl;
+    mulhilo(PHILOX_M1, ha ^ ctr3_sw ^ k1, qh, ql);
+    mulhilo(PHILOX_M1, hc ^ ctr3_sw ^ k1, rh, rl);
+    b0 = make_uint4(qh ^ sid_lo ^ (k0 + PHILOX_W0), ql, sw_hi ^ la ^ (k1 + PHILOX_W1), sw_lo);
+    b1 = make_uint4(rh ^ sid_lo ^ (k0 + PHILOX_W0), rl, sw_hi ^ lc ^ (k1 + PHILOX_W1), sw_lo);
+    philox_rounds2(b0, b1, k0, k1, 2);
   }
 };
 
