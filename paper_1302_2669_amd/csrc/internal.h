@@ -90,7 +90,7 @@ struct RunArgs {
 constexpr int N_RANGES = 5;
 constexpr int RANGE_LO[N_RANGES] = {2, 14, 17, 20, 23};
 constexpr int RANGE_HI[N_RANGES] = {13, 16, 19, 22, 25};
-constexpr int RANGE_WAVES[N_RANGES] = {6, 5, 3, 3, 3};
+constexpr int RANGE_WAVES[N_RANGES] = {5, 5, 3, 3, 3};
 inline int range_of(int L) {
   for (int r = 0; r < N_RANGES; ++r)
     if (L >= RANGE_LO[r] && L <= RANGE_HI[r]) return r;
