@@ -187,6 +187,9 @@ __device__ __forceinline__ void run_chain(const RunArgs& a, const GroupDesc& g, 
     rng.begin_sweep((uint32_t)sweep);
     uint4 blk = make_uint4(0, 0, 0, 0);
     uint4 blk_next = make_uint4(0, 0, 0, 0);
+#if MCMC_PAIRED_PHILOX == 4
+    uint4 quad[4];
+#endif
     int32_t dn = 0;     // weight change of the current phase
     int32_t acc_total = 0;
 
@@ -214,7 +217,17 @@ __device__ __forceinline__ void run_chain(const RunArgs& a, const GroupDesc& g, 
         constexpr int j = par + 2 * m;
         constexpr int w = j / 16, nib = (j % 16) / 2;
         constexpr int d = d0 + m;
-#if MCMC_PAIRED_PHILOX
+#if MCMC_PAIRED_PHILOX == 4
+        // blocks four at a time while four remain in the sweep
+        if constexpr ((d & 15) == 0 && d / 4 + 3 < S) {
+          rng.template block_quad<d / 4>(quad);
+          blk = quad[0];
+        } else if constexpr ((d & 3) == 0 && (d & ~15) / 4 + 3 < S) {
+          blk = quad[(d / 4) & 3];
+        } else if constexpr ((d & 3) == 0) {
+          blk = rng.template block<d / 4>();
+        }
+#elif MCMC_PAIRED_PHILOX
         // blocks two at a time (the second waits in blk_next); a lone last
         // block of the sweep is computed alone
         if constexpr ((d & 7) == 0) {

@@ -130,6 +130,30 @@ __device__ __forceinline__ void philox_rounds2(uint4& c, uint4& e, uint32_t k0, 
   }
 }
 
+// Four counters at once, interleaved like philox_rounds2.
+__device__ __forceinline__ void philox_rounds4(uint4 (&c)[4], uint32_t k0, uint32_t k1,
+                                               int first) {
+  k0 += (uint32_t)first * PHILOX_W0;
+  k1 += (uint32_t)first * PHILOX_W1;
+  int r = first;
+  if ((10 - first) & 1) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) c[i] = philox_round(c[i], k0, k1);
+    k0 += PHILOX_W0;
+    k1 += PHILOX_W1;
+    ++r;
+  }
+#pragma unroll 1
+  for (; r < 10; r += 2) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) c[i] = philox_round(c[i], k0, k1);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) c[i] = philox_round(c[i], k0 + PHILOX_W0, k1 + PHILOX_W1);
+    k0 += 2 * PHILOX_W0;
+    k1 += 2 * PHILOX_W1;
+  }
+}
+
 __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1) {
   return philox_rounds(c, k0, k1, 0);
 }
@@ -184,6 +208,19 @@ struct ChainRng {
     b0 = make_uint4(qh ^ sid_lo ^ (k0 + PHILOX_W0), ql, sw_hi ^ la ^ (k1 + PHILOX_W1), sw_lo);
     b1 = make_uint4(rh ^ sid_lo ^ (k0 + PHILOX_W0), rl, sw_hi ^ lc ^ (k1 + PHILOX_W1), sw_lo);
     philox_rounds2(b0, b1, k0, k1, 2);
+  }
+  // Blocks BLK .. BLK + 3 together.
+  template <int BLK>
+  __device__ __forceinline__ void block_quad(uint4 (&b)[4]) const {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const uint64_t pa = (uint64_t)PHILOX_M0 * (uint64_t)(uint32_t)(BLK + i);
+      const uint32_t ha = (uint32_t)(pa >> 32), la = (uint32_t)pa;
+      uint32_t qh, ql;
+      mulhilo(PHILOX_M1, ha ^ ctr3_sw ^ k1, qh, ql);
+      b[i] = make_uint4(qh ^ sid_lo ^ (k0 + PHILOX_W0), ql, sw_hi ^ la ^ (k1 + PHILOX_W1), sw_lo);
+    }
+    philox_rounds4(b, k0, k1, 2);
   }
 };
 
