@@ -14,6 +14,7 @@ import numpy as np
 SEED_SMALL = 0x1302266900000001      # L = 3, p = 0.10, 1000 samples, 4 x 1 chains, 2000 sweeps
 SEED_L9 = 0x1302266900000002         # L = 9, p in {0.05, 0.10, 0.15}, 4 x 4 chains, 81 sweeps
 SEED_METRIC = 0x1302266900000013     # L = 13, p = 0.15, 4 x 4 chains, 169 sweeps
+SEED_L25 = 0x1302266900000004        # L = 25, p in {0.16, 0.17, 0.18}, 4 x 8 chains, up to 4 L^2
 
 
 def n_stab(L):

@@ -17,7 +17,8 @@ torch = pytest.importorskip("torch")
 import paper_1302_2669_amd as mc  # noqa: E402
 from oracle import decoder, geometry, init, sampler  # noqa: E402
 
-from paper_1302_2669_amd.inputs import uniform_syndromes, SEED_SMALL, SEED_L9, SEED_METRIC  # noqa: E402
+from paper_1302_2669_amd.inputs import (uniform_syndromes, SEED_SMALL, SEED_L9,  # noqa: E402
+                                        SEED_METRIC, SEED_L25)
 
 DEV = "cuda"
 RTOL = 1e-12
@@ -241,3 +242,55 @@ def test_metric_workload_sampled():
     assert np.array_equal(geometry.syndrome(lat, g["correction"][chk]), syn[chk])
     assert np.array_equal(geometry.class_index(lat, g["correction"][chk]), g["chosen"][chk])
     say(f"  logical error rate L=13 p=0.15: {(g['chosen'] != cls_d.cpu().numpy()).mean():.4f}")
+
+
+@pytest.mark.parametrize("p", [0.16, 0.17, 0.18])
+def test_near_threshold_workload_checkpointed(p):
+    """L = 25, 2 x 10^4 samples, 4 classes x 8 chains, up to 4 L^2 sweeps,
+    run as one batch in checkpointed segments (resume): 25, L^2, 2 L^2, 3 L^2,
+    4 L^2.  The first segment is replayed on the oracle for sampled syndromes
+    (every chain: S, A, final states); the full length is checked against a
+    one-shot decode of a sub-batch and by properties that hold at any size.
+    The logical error at each checkpoint is the error vs sweep-count curve."""
+    L, n, chains = 25, 20000, 8
+    say(f"near-threshold workload L=25 p={p}")
+    syn_d, cls_d, _ = mc.sample_errors(L, p, SEED_L25, n, device=DEV)
+    first = mc.decode_batch(syn_d, L, p, 25, SEED_L25, chains=chains, want_sums=True,
+                            chain_state=True)
+    cs = first["chain_state"]
+    if p == 0.17:
+        g = to_np({k: v for k, v in first.items() if k != "chain_state"})
+        st, nf = mc.unpack_chain_state(cs, n, L, p, 25, SEED_L25, chains)
+        st, nf = st.cpu().numpy(), nf.cpu().numpy()
+        pick = np.array([0, n - 1])
+        lat = geometry.Lattice(L)
+        o_syn, _, _ = sampler.sample(lat, p, SEED_L25, pick)
+        assert np.array_equal(syn_d.cpu().numpy()[pick], o_syn)
+        o = decoder.decode(L, o_syn, p, 25, SEED_L25, chains_per_class=chains, syndrome_ids=pick)
+        for k in ("sum_n", "accepts", "chosen", "correction"):
+            assert np.array_equal(g[k][pick], o[k]), k
+        assert np.array_equal(st[pick], o["states"])
+        assert np.array_equal(nf[pick], o["n_final"])
+    prev, curve = 25, []
+    for m in (1, 2, 3, 4):
+        total = m * L * L
+        out = mc.decode_batch(syn_d, L, p, total, SEED_L25, chains=chains, want_sums=True,
+                              resume_from=(cs, prev))
+        prev = total
+        err = float((out["chosen"] != cls_d).float().mean())
+        curve.append((total, err))
+    say(f"  logical error vs sweeps at L=25 p={p}: {curve}")
+    g = to_np({k: v for k, v in out.items() if k != "chain_state"})
+    sub = 96
+    one = to_np(mc.decode_batch(syn_d[:sub], L, p, 4 * L * L, SEED_L25, chains=chains,
+                                want_sums=True))
+    for k in ("sum_n", "accepts", "chosen", "correction", "class_prob", "mean_n"):
+        assert np.array_equal(g[k][:sub], one[k]), k
+    assert np.allclose(g["class_prob"].sum(axis=1), 1.0, rtol=1e-13)
+    key = g["sum_n"].sum(axis=(2, 3))
+    assert np.array_equal(np.argmin(key, axis=1), g["chosen"])
+    lat = geometry.Lattice(L)
+    chk = np.arange(0, n, 1999)
+    syn = syn_d.cpu().numpy()
+    assert np.array_equal(geometry.syndrome(lat, g["correction"][chk]), syn[chk])
+    assert np.array_equal(geometry.class_index(lat, g["correction"][chk]), g["chosen"][chk])
