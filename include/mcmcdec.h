@@ -239,7 +239,9 @@ int mcmc_plan_create(const mcmc_item* h_items, int64_t n, uint64_t seed, uint32_
 int mcmc_plan_destroy(mcmc_plan* plan);
 /* Replace the plan's items (same rules as mcmc_plan_create; seed, init and
  * tuning kept).  Reuses the plan's device tables when they are large enough,
- * else reallocates them; recorded graphs are dropped.  Synchronous copies. */
+ * else reallocates them; recorded graphs are dropped.  Synchronous copies.
+ * Invalid items leave the plan unchanged; a failed allocation or copy
+ * (EDEVICE) leaves it empty (executions then do nothing). */
 int mcmc_plan_rebuild(mcmc_plan* plan, const mcmc_item* h_items, int64_t n);
 
 /* Total chains (length of the per-chain outputs), workspace bytes, and the

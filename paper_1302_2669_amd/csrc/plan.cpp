@@ -252,7 +252,27 @@ namespace {
 // (Re)build the plan's groups, items, tiles and tables from an item array
 // (already validated) and copy them to the device, growing the plan's device
 // block only when it is too small.
+int build_plan_into(mcmc_plan* p, const mcmc_item* items, int64_t n);
+
+// Empty plan: executes nothing.  The state a failed build leaves behind, so
+// that no later call uses descriptors that were never uploaded.
+void clear_plan(mcmc_plan* p) {
+  p->n = 0;
+  p->groups.clear();
+  p->items.clear();
+  p->tiles.clear();
+  p->tables.clear();
+  p->total_chains = p->total_rows = p->total_updates = 0;
+  for (int r = 0; r < N_RANGES; ++r) p->range_first[r] = p->range_tiles[r] = 0;
+}
+
 int build_plan(mcmc_plan* p, const mcmc_item* items, int64_t n) {
+  const int st = build_plan_into(p, items, n);
+  if (st != MCMC_OK) clear_plan(p);
+  return st;
+}
+
+int build_plan_into(mcmc_plan* p, const mcmc_item* items, int64_t n) {
   release_graphs(p);
   p->n = n;
   p->groups.clear();

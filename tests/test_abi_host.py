@@ -113,3 +113,72 @@ def test_plan_rejects_invalid_items_before_allocating():
     assert lib.mcmc_plan_create(None, 3, 1, 1, ctypes.byref(h)) == -1
     assert lib.mcmc_plan_create(None, 0, 1, 5, ctypes.byref(h)) == -1
     assert lib.mcmc_plan_destroy(None) == 0
+
+
+@pytest.mark.parametrize("L", [2, 5, 13, 25])
+def test_gate_network_sizes_match_oracle(L):
+    """Parameter count and the layer layout of the C side agree with the
+    oracle's parameter shapes; workspace queries are consistent."""
+    from oracle import cnn
+    lib = _lib._lib()
+    n = ctypes.c_int64()
+    assert lib.mcmc_cnn_param_count(L, ctypes.byref(n)) == 0
+    assert n.value == sum(int(np.prod(s)) for _, s in cnn.param_shapes(L))
+    b, bi = ctypes.c_size_t(), ctypes.c_size_t()
+    assert lib.mcmc_cnn_workspace_size(L, 1000, ctypes.byref(b)) == 0
+    assert lib.mcmc_cnn_infer_workspace_size(L, ctypes.byref(bi)) == 0
+    offs = (ctypes.c_int64 * 7)()
+    assert lib.mcmc_cnn_workspace_offsets(L, 1000, offs) == 0
+    o = list(offs)
+    # activations hold 1000 L^2 pixels x 32 bf16 each and do not overlap
+    assert all(x % 256 == 0 for x in o) and len(set(o)) == 7
+    assert o[2] - o[1] >= 1000 * L * L * 32 * 2
+    assert 0 < bi.value < b.value
+    assert lib.mcmc_cnn_workspace_size(L, 0, ctypes.byref(b)) == 0 and b.value == 0
+
+
+def test_gate_network_rejects_before_launch():
+    lib = _lib._lib()
+    d = ctypes.c_void_p(0x1000)
+    n = ctypes.c_int64()
+    assert lib.mcmc_cnn_param_count(1, ctypes.byref(n)) == -2
+    assert lib.mcmc_cnn_param_count(26, ctypes.byref(n)) == -2
+    assert lib.mcmc_cnn_param_count(13, None) == -1
+    big = (1 << 24) + 1
+    for fn in (lib.mcmc_cnn_forward, lib.mcmc_cnn_infer):
+        assert fn(13, 8, None, d, d, d, d, 1 << 30, None) == -1       # no parameters
+        assert fn(13, 8, d, d, d, d, None, 0, None) == -5             # no workspace
+        assert fn(13, 8, d, d, d, d, d, 16, None) == -5               # workspace too small
+        assert fn(13, big, d, d, d, d, d, 1 << 30, None) == -2        # batch too large
+        assert fn(1, 8, d, d, d, d, d, 1 << 30, None) == -2           # bad L
+        assert fn(13, 0, None, None, None, None, None, 0, None) == 0   # empty batch
+    assert lib.mcmc_cnn_backward(13, 8, d, d, d, d, ctypes.c_float(-1.0), d, None, d, 1 << 30,
+                                 None) == -2                           # negative budget weight
+    assert lib.mcmc_cnn_backward(13, 8, d, d, None, d, ctypes.c_float(0.5), d, None, d, 1 << 30,
+                                 None) == -1                           # no class targets
+    f = ctypes.c_float
+    assert lib.mcmc_cnn_step(10, 0, f(1e-3), f(0.9), f(0.999), f(1e-8), d, d, d, d, None) == -2
+    assert lib.mcmc_cnn_step(10, 1, f(1e-3), f(1.0), f(0.999), f(1e-8), d, d, d, d, None) == -2
+    assert lib.mcmc_cnn_step(10, 1, f(1e-3), f(0.9), f(0.999), f(0.0), d, d, d, d, None) == -2
+    assert lib.mcmc_cnn_step(0, 1, f(1e-3), f(0.9), f(0.999), f(1e-8), None, None, None, None,
+                             None) == 0
+    assert lib.mcmc_cnn_gate(8, d, f(1.5), d, d, None, None) == -2
+    assert lib.mcmc_cnn_gate(8, None, f(0.9), d, d, None, None) == -1
+
+
+def test_gated_config_rejected_before_allocating():
+    lib = _lib._lib()
+    h = ctypes.c_void_p()
+
+    def cfg(**kw):
+        c = _lib.GateConfig(L=13, n_temps=1, chains=4, burn=0, sweeps_short=13, sweeps_full=169,
+                            p=0.15, seed=1, init=1, threshold=0.99, escalate=0.0, max_batch=64)
+        for k, v in kw.items():
+            setattr(c, k, v)
+        return c
+    for bad, status in ((dict(L=1), -2), (dict(p=0.8), -2), (dict(max_batch=0), -2),
+                        (dict(threshold=1.5), -2), (dict(escalate=-0.1), -2),
+                        (dict(sweeps_short=-1), -2), (dict(init=7), -1)):
+        assert lib.mcmc_gated_create(ctypes.byref(cfg(**bad)), ctypes.byref(h)) == status, bad
+    assert lib.mcmc_gated_create(None, ctypes.byref(h)) == -1
+    assert lib.mcmc_gated_destroy(None) == 0
