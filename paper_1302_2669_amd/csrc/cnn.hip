@@ -232,14 +232,29 @@ __global__ void wgrad_reduce_kernel(int64_t chunks, int cin_real, const float* _
     const int co = i / (9 * cin_real), rem = i % (9 * cin_real);
     const int tap = rem / cin_real, ci = rem % cin_real;
     const int c = tap * CIN + ci;
-    float s = 0.0f;
-    for (int64_t k = 0; k < chunks; ++k) s += part[(k * CH + co) * KP + c];
-    gW[i] = s;
+    // 8 interleaved partial sums (chunk k into sum k % 8), then added in order
+    float s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int64_t k = 0;
+    for (; k + 8 <= chunks; k += 8)
+#pragma unroll
+      for (int j = 0; j < 8; ++j) s[j] += part[((k + j) * CH + co) * KP + c];
+    for (int j = 0; k < chunks; ++k, ++j) s[j] += part[(k * CH + co) * KP + c];
+    float t = s[0];
+#pragma unroll
+    for (int j = 1; j < 8; ++j) t += s[j];
+    gW[i] = t;
   }
   if (i < CH) {
-    float s = 0.0f;
-    for (int64_t k = 0; k < chunks; ++k) s += partb[k * CH + i];
-    gb[i] = s;
+    float s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int64_t k = 0;
+    for (; k + 8 <= chunks; k += 8)
+#pragma unroll
+      for (int j = 0; j < 8; ++j) s[j] += partb[(k + j) * CH + i];
+    for (int j = 0; k < chunks; ++k, ++j) s[j] += partb[k * CH + i];
+    float t = s[0];
+#pragma unroll
+    for (int j = 1; j < 8; ++j) t += s[j];
+    gb[i] = t;
   }
 }
 
@@ -251,37 +266,34 @@ __global__ void wgrad_reduce_kernel(int64_t chunks, int cin_real, const float* _
 // give the same bits.
 constexpr int HEAD_CHAINS = 8;
 
-__global__ void __launch_bounds__(256) head_fwd_kernel(int L, int64_t B, const bf16* __restrict__ a3,
-                                                       const bf16* __restrict__ whb,
-                                                       const float* __restrict__ bh,
-                                                       float* __restrict__ logits) {
-  const int lane = threadIdx.x & 63, grp = lane >> 4, n = lane & 15;
-  const int64_t tile = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+// One workgroup of HEAD_CHAINS waves per 16 samples: wave j runs chain j and
+// the chains are added in order through LDS.
+__global__ void __launch_bounds__(64 * HEAD_CHAINS) head_fwd_kernel(
+    int L, int64_t B, const bf16* __restrict__ a3, const bf16* __restrict__ whb,
+    const float* __restrict__ bh, float* __restrict__ logits) {
+  __shared__ float part[HEAD_CHAINS][16][16];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, grp = lane >> 4, n = lane & 15;
+  const int64_t tile = blockIdx.x;
   const int64_t bm = tile * 16 + n;
   const int LL = L * L;
   const int64_t kh = (int64_t)LL * CH;
-  f32x4 acc[HEAD_CHAINS];
-#pragma unroll
-  for (int j = 0; j < HEAD_CHAINS; ++j) acc[j] = f32x4{0, 0, 0, 0};
-#pragma unroll 1
-  for (int st0 = 0; st0 < LL; st0 += HEAD_CHAINS) {
-#pragma unroll
-    for (int j = 0; j < HEAD_CHAINS; ++j) {
-      const int st = st0 + j;
-      if (st < LL) {
-        const bf16x8 a = bm < B ? load8(a3 + bm * kh + st * 32 + 8 * grp) : zero8();
-        const bf16x8 b = n < 7 ? load8(whb + (int64_t)n * kh + st * 32 + 8 * grp) : zero8();
-        acc[j] = mfma(a, b, acc[j]);
-      }
-    }
+  f32x4 acc = {0, 0, 0, 0};
+  for (int st = wave; st < LL; st += HEAD_CHAINS) {
+    const bf16x8 a = bm < B ? load8(a3 + bm * kh + st * 32 + 8 * grp) : zero8();
+    const bf16x8 b = n < 7 ? load8(whb + (int64_t)n * kh + st * 32 + 8 * grp) : zero8();
+    acc = mfma(a, b, acc);
   }
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int64_t bo = tile * 16 + 4 * grp + i;
-    float t = acc[0][i];
-#pragma unroll
-    for (int j = 1; j < HEAD_CHAINS; ++j) t = t + acc[j][i];
-    if (bo < B && n < 7) logits[bo * 8 + n] = t + bh[n];
+  for (int i = 0; i < 4; ++i) part[wave][4 * grp + i][n] = acc[i];
+  __syncthreads();
+  if (threadIdx.x < 16 * 8) {
+    const int row = threadIdx.x >> 3, o = threadIdx.x & 7;
+    const int64_t bo = tile * 16 + row;
+    if (bo < B && o < 7) {
+      float t = part[0][row][o];
+      for (int j = 1; j < HEAD_CHAINS; ++j) t = t + part[j][row][o];
+      logits[bo * 8 + o] = t + bh[o];
+    }
   }
 }
 
@@ -293,6 +305,7 @@ __global__ void __launch_bounds__(256) head_fwd_kernel(int L, int64_t B, const b
 // ReLU, bf16; head: 8 interleaved chains), so the logits are identical.
 constexpr int INFER_THREADS = 512;
 constexpr int INFER_WAVES = INFER_THREADS / 64;
+static_assert(INFER_WAVES == HEAD_CHAINS, "both head paths add the same chains in the same order");
 constexpr int ASTR = 40;      // bf16 per pixel of a 32-channel activation (80 B: 16 lanes
                               // reading 16 B each at this stride hit disjoint banks)
 constexpr int W1STR = 104;    // bf16 per row of conv1 weights (96 used)
@@ -473,23 +486,50 @@ __global__ void loss_kernel(int64_t B, const float* __restrict__ logits,
 }
 
 // grad Wh[o][f] = sum_b dz[b][o] a3[b][f]; grad bh[o] = sum_b dz[b][o].
+// grad Wh[o][f] = sum_b dz[b][o] a3[b][f]: the batch is cut into
+// HEAD_SEGS contiguous segments (blockIdx.y), each summed in batch order into
+// hpart[seg][o][f]; head_wgrad_reduce adds the segments in order.
+constexpr int HEAD_SEGS = 8;
+
 __global__ void head_wgrad_kernel(int L, int64_t B, const float* __restrict__ dz,
-                                  const bf16* __restrict__ a3, float* __restrict__ gWh,
-                                  float* __restrict__ gbh) {
+                                  const bf16* __restrict__ a3, float* __restrict__ hpart) {
   const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t kh = (int64_t)L * L * CH;
-  if (f < kh) {
-    float s[7] = {0, 0, 0, 0, 0, 0, 0};
-    for (int64_t b = 0; b < B; ++b) {
-      const float a = (float)a3[b * kh + f];
-      for (int o = 0; o < 7; ++o) s[o] += dz[b * 8 + o] * a;
-    }
-    for (int o = 0; o < 7; ++o) gWh[o * kh + f] = s[o];
+  if (f >= kh) return;
+  const int seg = blockIdx.y;
+  const int64_t per = (B + HEAD_SEGS - 1) / HEAD_SEGS;
+  const int64_t b0 = seg * per, b1 = b0 + per < B ? b0 + per : B;
+  float s[7] = {0, 0, 0, 0, 0, 0, 0};
+  for (int64_t b = b0; b < b1; ++b) {
+    const float a = (float)a3[b * kh + f];
+#pragma unroll
+    for (int o = 0; o < 7; ++o) s[o] += dz[b * 8 + o] * a;
   }
-  if (f < 7) {
-    float s = 0.0f;
-    for (int64_t b = 0; b < B; ++b) s += dz[b * 8 + f];
-    gbh[f] = s;
+#pragma unroll
+  for (int o = 0; o < 7; ++o) hpart[((int64_t)seg * 7 + o) * kh + f] = s[o];
+}
+
+__global__ void head_wgrad_reduce_kernel(int L, int64_t B, const float* __restrict__ hpart,
+                                         const float* __restrict__ dz, float* __restrict__ gWh,
+                                         float* __restrict__ gbh) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t kh = (int64_t)L * L * CH;
+  if (i < 7 * kh) {
+    float t = hpart[i];
+    for (int seg = 1; seg < HEAD_SEGS; ++seg) t += hpart[(int64_t)seg * 7 * kh + i];
+    gWh[i] = t;
+  }
+  if (i < 7) {
+    float s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int64_t b = 0;
+    for (; b + 8 <= B; b += 8)
+#pragma unroll
+      for (int j = 0; j < 8; ++j) s[j] += dz[(b + j) * 8 + i];
+    for (int j = 0; b < B; ++b, ++j) s[j] += dz[b * 8 + i];
+    float t = s[0];
+#pragma unroll
+    for (int j = 1; j < 8; ++j) t += s[j];
+    gbh[i] = t;
   }
 }
 
@@ -626,6 +666,7 @@ CnnWorkspace cnn_workspace(int L, int64_t B) {
   w.dp1 = take((size_t)P * CH * 2);
   w.part = take((size_t)chunks * CH * 288 * 4);
   w.partb = take((size_t)chunks * CH * 4);
+  w.hpart = take((size_t)HEAD_SEGS * 7 * kh * 4);
   w.loss = take((size_t)B * 4);
   w.bytes = off;
   return w;
@@ -708,7 +749,8 @@ hipError_t cnn_forward(int L, int64_t B, const float* prm, const uint8_t* syn, c
                      WSP(bf16, wb2), prm + off.b2, nullptr, WSP(bf16, a2));
   hipLaunchKernelGGL((conv_kernel<32, false>), dim3(g), dim3(256), 0, s, L, P, WSP(bf16, a2),
                      WSP(bf16, wb3), prm + off.b3, nullptr, WSP(bf16, a3));
-  hipLaunchKernelGGL(head_fwd_kernel, dim3(blocks_for((B + 15) / 16, 4)), dim3(256), 0, s, L, B,
+  hipLaunchKernelGGL(head_fwd_kernel, dim3((unsigned)((B + 15) / 16)), dim3(64 * HEAD_CHAINS), 0, s,
+                     L, B,
                      WSP(bf16, a3), WSP(bf16, whb), prm + off.bh, logits);
   return hipGetLastError();
 }
@@ -723,15 +765,17 @@ hipError_t cnn_backward(int L, int64_t B, const float* prm, const float* logits,
   float* lossv = loss ? loss : WSP(float, loss);
   hipLaunchKernelGGL(loss_kernel, dim3(blocks_for(B, 256)), dim3(256), 0, s, B, logits, tgt,
                      budget, wb, WSP(float, dz), lossv);
-  hipLaunchKernelGGL(head_wgrad_kernel, dim3(blocks_for(kh, 256)), dim3(256), 0, s, L, B,
-                     WSP(float, dz), WSP(bf16, a3), grads + off.Wh, grads + off.bh);
+  hipLaunchKernelGGL(head_wgrad_kernel, dim3(blocks_for(kh, 256), HEAD_SEGS), dim3(256), 0, s, L,
+                     B, WSP(float, dz), WSP(bf16, a3), WSP(float, hpart));
+  hipLaunchKernelGGL(head_wgrad_reduce_kernel, dim3(blocks_for(7 * kh, 256)), dim3(256), 0, s, L,
+                     B, WSP(float, hpart), WSP(float, dz), grads + off.Wh, grads + off.bh);
   hipLaunchKernelGGL(head_dgrad_kernel, dim3(blocks_for(B * kh, 256)), dim3(256), 0, s, L, B,
                      WSP(float, dz), WSP(bf16, whb), WSP(bf16, a3), WSP(bf16, dp3));
   const unsigned g = blocks_for((P + 15) / 16, 4);
   // conv3: weights, then data back into a2's gradient
   hipLaunchKernelGGL((conv_wgrad_kernel<32>), dim3((unsigned)chunks), dim3(256), 0, s, L, P,
                      WSP(bf16, dp3), WSP(bf16, a2), WSP(float, part), WSP(float, partb));
-  hipLaunchKernelGGL((wgrad_reduce_kernel<32>), dim3(blocks_for(CH * 9 * CH, 256)), dim3(256), 0,
+  hipLaunchKernelGGL((wgrad_reduce_kernel<32>), dim3(blocks_for(CH * 9 * CH, 64)), dim3(64), 0,
                      s, chunks, CH, WSP(float, part), WSP(float, partb), grads + off.W3,
                      grads + off.b3);
   hipLaunchKernelGGL((conv_kernel<32, true>), dim3(g), dim3(256), 0, s, L, P, WSP(bf16, dp3),
@@ -739,7 +783,7 @@ hipError_t cnn_backward(int L, int64_t B, const float* prm, const float* logits,
   // conv2
   hipLaunchKernelGGL((conv_wgrad_kernel<32>), dim3((unsigned)chunks), dim3(256), 0, s, L, P,
                      WSP(bf16, dp2), WSP(bf16, a1), WSP(float, part), WSP(float, partb));
-  hipLaunchKernelGGL((wgrad_reduce_kernel<32>), dim3(blocks_for(CH * 9 * CH, 256)), dim3(256), 0,
+  hipLaunchKernelGGL((wgrad_reduce_kernel<32>), dim3(blocks_for(CH * 9 * CH, 64)), dim3(64), 0,
                      s, chunks, CH, WSP(float, part), WSP(float, partb), grads + off.W2,
                      grads + off.b2);
   hipLaunchKernelGGL((conv_kernel<32, true>), dim3(g), dim3(256), 0, s, L, P, WSP(bf16, dp2),
@@ -747,7 +791,7 @@ hipError_t cnn_backward(int L, int64_t B, const float* prm, const float* logits,
   // conv1: weights only
   hipLaunchKernelGGL((conv_wgrad_kernel<8>), dim3((unsigned)chunks), dim3(256), 0, s, L, P,
                      WSP(bf16, dp1), WSP(bf16, x0), WSP(float, part), WSP(float, partb));
-  hipLaunchKernelGGL((wgrad_reduce_kernel<8>), dim3(blocks_for(CH * 9 * 3, 256)), dim3(256), 0, s,
+  hipLaunchKernelGGL((wgrad_reduce_kernel<8>), dim3(blocks_for(CH * 9 * 3, 64)), dim3(64), 0, s,
                      chunks, 3, WSP(float, part), WSP(float, partb), grads + off.W1,
                      grads + off.b1);
   return hipGetLastError();

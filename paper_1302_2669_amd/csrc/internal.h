@@ -152,8 +152,8 @@ struct CnnOffsets {
 };
 // Byte offsets of the buffers in a gate-network workspace for L and batch B.
 struct CnnWorkspace {
-  size_t x0, a1, a2, a3, wb1, wb2, wb3, wt2, wt3, whb, dz, dp3, dp2, dp1, part, partb, loss,
-      bytes;
+  size_t x0, a1, a2, a3, wb1, wb2, wb3, wt2, wt3, whb, dz, dp3, dp2, dp1, part, partb, hpart,
+      loss, bytes;
 };
 // Byte offsets of the bf16 weight copies (the workspace of cnn_infer).
 struct CnnWeights {
