@@ -38,12 +38,12 @@ OPS_PER_UPDATE = 40
 # integer-operation peak is 157.3 T ops/s
 PEAK_INT_OPS = 256 * 128 * 2.4e9 * 2
 # HBM traffic of the chain kernel from rocprofv3 FETCH_SIZE (x2.000, the
-# counter's reading of a 256 MiB copy) + WRITE_SIZE (x1.000) at 16384 syndromes
+# counter's reading of a 256 MiB copy) + WRITE_SIZE (x1.000) at 65536 syndromes
 # per launch (the counters file under profiles/ for chains_r0 at L=13): bytes
 # per syndrome, valid only for the kernel sources it was measured on
-CHAIN_TRAFFIC_PER_SYNDROME = 46788694 / 16384
+CHAIN_TRAFFIC_PER_SYNDROME = 81189978 / 65536
 CHAIN_TRAFFIC_SOURCES = ("chain_body.h", "chain_r0.hip", "device_common.h", "internal.h")
-CHAIN_TRAFFIC_SHA = "6df32d91d2f46754"
+CHAIN_TRAFFIC_SHA = "a146930fd924b69a"
 # gate network at L=13: 2 flops per multiply-add over the three 3x3 convolutions
 # (3->32, 32->32, 32->32 on 169 pixels) and the 5408x7 head
 CNN_FLOPS_PER_SAMPLE = 2 * (169 * 32 * 27 + 2 * 169 * 32 * 288 + 7 * 5408)
