@@ -31,6 +31,9 @@ __device__ __forceinline__ bf16x8 load8(const bf16* p) {
   const uint4 v = *reinterpret_cast<const uint4*>(p);
   return __builtin_bit_cast(bf16x8, v);
 }
+__device__ __forceinline__ bf16x8 lds8(const bf16* p) {
+  return __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(p));
+}
 __device__ __forceinline__ bf16x8 zero8() { return __builtin_bit_cast(bf16x8, make_uint4(0, 0, 0, 0)); }
 
 __device__ __forceinline__ f32x4 mfma(bf16x8 a, bf16x8 b, f32x4 c) {
@@ -148,76 +151,133 @@ __global__ void __launch_bounds__(256) conv_kernel(int L, int64_t P, const bf16*
   }
 }
 
-// ---- weight gradients: partial sums over one chunk of 256 pixels ----------
-// part[chunk][co][c] = sum_{p in chunk} dpre[p][co] * in[p + tap(c)][ci(c)],
-// c = tap*CIN + ci < 9*CIN (columns up to KP are zero).
-constexpr int WG_CHUNK = 256;
+// ---- weight gradients ------------------------------------------------------
+// Workgroup w handles samples [w*G, (w+1)*G) in order and writes
+// part[w][co][c] = sum over its samples and pixels of dpre[p][co] *
+// in[p + tap(c)][ci(c)] (c = tap*CIN + ci < 9*CIN; columns up to KP are zero)
+// and partb[w][co] = sum of dpre[p][co].  Each sample is staged in LDS
+// channel-major on its image padded by one zero pixel on every side
+// ((L+2)^2 positions, rounded up to a multiple of 32): the MFMA k index runs
+// over padded positions, so a tap is a constant offset of dy*(L+2)+dx and no
+// bounds test is needed (padding positions hold zeros in both operands).
+constexpr int WG_THREADS = 256;
+
+struct WgradGeom {
+  int PW, PS, KPAD, DSTR, OFF, ISTR;
+};
+__host__ __device__ inline WgradGeom wgrad_geom(int L) {
+  WgradGeom g;
+  g.PW = L + 2;
+  g.PS = g.PW * g.PW;
+  g.KPAD = (g.PS + 31) / 32 * 32;
+  g.DSTR = g.KPAD + 8;                       // 16-byte rows, 16 lanes on disjoint banks
+  g.OFF = (g.PW + 1 + 7) / 8 * 8;            // room for the most negative tap offset
+  int istr = g.OFF + g.KPAD + g.PW + 1 + 1;
+  istr = (istr + 1) / 2 * 2;
+  if (((istr / 2) & 1) == 0) istr += 2;      // odd word stride: 16 lanes, 16 banks
+  g.ISTR = istr;
+  return g;
+}
+template <int CIN>
+inline size_t wgrad_lds_bytes(int L) {
+  const WgradGeom g = wgrad_geom(L);
+  return ((size_t)CH * g.DSTR + (size_t)CIN * g.ISTR) * 2;
+}
 
 template <int CIN>
-__global__ void __launch_bounds__(256) conv_wgrad_kernel(int L, int64_t P,
-                                                         const bf16* __restrict__ dpre,
-                                                         const bf16* __restrict__ in,
-                                                         float* __restrict__ part,
-                                                         float* __restrict__ partb) {
+__global__ void __launch_bounds__(WG_THREADS) conv_wgrad_kernel(int L, int64_t B, int G,
+                                                                const bf16* __restrict__ dpre,
+                                                                const bf16* __restrict__ in,
+                                                                float* __restrict__ part,
+                                                                float* __restrict__ partb) {
   constexpr int KP = (9 * CIN + 31) / 32 * 32;
-  constexpr int NT = KP / 16;          // column tiles
-  constexpr int TILES = 2 * NT;        // x 2 row tiles of 16 output channels
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int grp = lane >> 4, n = lane & 15;
-  const int64_t chunk = blockIdx.x;
-  const int64_t p0 = chunk * WG_CHUNK;
-  const int LL = L * L;
-  for (int t = wave; t < TILES; t += 4) {
-    const int mt = t / NT, nt = t % NT;
-    const int co = mt * 16 + n;                  // A row of this lane
-    const int c = nt * 16 + n;                   // B column of this lane
-    const int tap = c / CIN, ci = c % CIN;
-    const bool col_ok = c < 9 * CIN;
-    const int dy = col_ok ? tap_dy(tap) : 0, dx = col_ok ? tap_dx(tap) : 0;
-    f32x4 acc = {0, 0, 0, 0};
-#pragma unroll 1
-    for (int s = 0; s < WG_CHUNK / 32; ++s) {
-      bf16x8 a, bb;
-#pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        const int64_t p = p0 + s * 32 + 8 * grp + j;
-        bf16 av = (bf16)0.0f, bv = (bf16)0.0f;
-        if (p < P) {
-          av = dpre[p * CH + co];
-          if (col_ok) {
-            const int64_t b = p / LL;
-            const int r = (int)(p - b * LL), y = r / L + dy, x = r % L + dx;
-            if (y >= 0 && y < L && x >= 0 && x < L) bv = in[(b * LL + y * L + x) * CIN + ci];
-          }
-        }
-        a[j] = av;
-        bb[j] = bv;
-      }
-      acc = mfma(a, bb, acc);
-    }
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int orow = mt * 16 + 4 * grp + i;
-      part[(chunk * CH + orow) * KP + nt * 16 + n] = acc[i];
-    }
-  }
-  // bias partials: 8 runs of 32 pixels per channel, then summed in run order
+  constexpr int NT = KP / 16;                 // column tiles
+  constexpr int TILES = 2 * NT;               // x 2 row tiles of 16 output channels
+  constexpr int TPW = (TILES + 3) / 4;        // tiles per wave
+  extern __shared__ __align__(16) unsigned char wsm[];
+  const WgradGeom gm = wgrad_geom(L);
+  bf16* dT = reinterpret_cast<bf16*>(wsm);            // [CH][DSTR]
+  bf16* iT = dT + CH * gm.DSTR;                       // [CIN][ISTR]
   __shared__ float runs[8][CH];
-  {
-    const int co = threadIdx.x & 31, run = threadIdx.x >> 5;
-    float s = 0.0f;
-    for (int j = 0; j < 32; ++j) {
-      const int64_t p = p0 + run * 32 + j;
-      if (p < P) s += (float)dpre[p * CH + co];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int grp = lane >> 4, n = lane & 15;
+  const int LL = L * L;
+  const int64_t s0 = (int64_t)blockIdx.x * G;
+  const int64_t s1 = s0 + G < B ? s0 + G : B;
+  f32x4 acc[TPW];
+#pragma unroll
+  for (int u = 0; u < TPW; ++u) acc[u] = f32x4{0, 0, 0, 0};
+  float bsum = 0.0f;
+  const int nwords = (CH * gm.DSTR + CIN * gm.ISTR) / 2;
+  for (int64_t smp = s0; smp < s1; ++smp) {
+    __syncthreads();
+    for (int i = tid; i < nwords; i += WG_THREADS) reinterpret_cast<uint32_t*>(wsm)[i] = 0u;
+    __syncthreads();
+    const int64_t pix0 = smp * LL;
+    for (int i = tid; i < LL * CH; i += WG_THREADS) {
+      const int r = i / CH, co = i % CH;
+      const int q = (r / L + 1) * gm.PW + (r % L + 1);
+      dT[co * gm.DSTR + q] = dpre[(pix0 + r) * CH + co];
     }
-    runs[run][co] = s;
+    for (int i = tid; i < LL * CIN; i += WG_THREADS) {
+      const int r = i / CIN, ci = i % CIN;
+      const int q = (r / L + 1) * gm.PW + (r % L + 1);
+      iT[ci * gm.ISTR + gm.OFF + q] = in[(pix0 + r) * CIN + ci];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < TPW; ++u) {
+      const int t = wave + 4 * u;
+      if (t >= TILES) continue;
+      const int mt = t / NT, nt = t % NT;
+      const int co = mt * 16 + n;
+      const int c = nt * 16 + n;
+      const bool col_ok = c < 9 * CIN;
+      const int tap = col_ok ? c / CIN : 4, ci = col_ok ? c % CIN : 0;
+      const int shift = tap_dy(tap) * gm.PW + tap_dx(tap);
+      const bf16* arow = dT + co * gm.DSTR + 8 * grp;
+      const bf16* brow = iT + ci * gm.ISTR + gm.OFF + shift + 8 * grp;
+      for (int k = 0; k < gm.KPAD; k += 32) {
+        const bf16x8 a = lds8(arow + k);
+        bf16x8 bb;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) bb[j] = brow[k + j];
+        if (!col_ok) bb = zero8();
+        acc[u] = mfma(a, bb, acc[u]);
+      }
+    }
+    // bias: 8 runs of the padded row per channel, in run order
+    {
+      const int co = tid & 31, run = tid >> 5;
+      const int per = gm.KPAD / 8;
+      float s = 0.0f;
+      for (int j = 0; j < per; ++j) s += (float)dT[co * gm.DSTR + run * per + j];
+      runs[run][co] = s;
+    }
+    __syncthreads();
+    if (tid < CH) {
+      float s = 0.0f;
+      for (int r = 0; r < 8; ++r) s += runs[r][tid];
+      bsum += s;
+    }
   }
-  __syncthreads();
-  if (threadIdx.x < CH) {
-    float s = 0.0f;
-    for (int r = 0; r < 8; ++r) s += runs[r][threadIdx.x];
-    partb[chunk * CH + threadIdx.x] = s;
+#pragma unroll
+  for (int u = 0; u < TPW; ++u) {
+    const int t = wave + 4 * u;
+    if (t >= TILES) continue;
+    const int mt = t / NT, nt = t % NT;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      part[((int64_t)blockIdx.x * CH + mt * 16 + 4 * grp + i) * KP + nt * 16 + n] = acc[u][i];
   }
+  if (tid < CH) partb[(int64_t)blockIdx.x * CH + tid] = bsum;
+}
+
+// Samples per weight-gradient workgroup: enough workgroups to fill the chip
+// twice, at most one sample each for small batches.
+inline int wgrad_group(int64_t B) {
+  const int64_t target = 512;
+  return (int)(B <= target ? 1 : (B + target - 1) / target);
 }
 
 // grad W[co][tap][ci] (ci < cin_real) and grad b[co]: sums of the chunk
@@ -313,9 +373,6 @@ constexpr int W23STR = 296;   // bf16 per row of conv2/conv3 weights (288 used)
 constexpr int INFER_WEIGHT_BYTES = 32 * W1STR * 2 + 2 * 32 * W23STR * 2;
 constexpr int INFER_PART_BYTES = INFER_WAVES * 256 * 4 + 16;   // + a 16-byte zero slot
 
-__device__ __forceinline__ bf16x8 lds8(const bf16* p) {
-  return __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(p));
-}
 
 // One convolution over the group's pixels, LDS to LDS.  Each wave takes two
 // 16-pixel tiles per trip (four independent MFMA chains); an A operand whose
@@ -643,7 +700,7 @@ CnnOffsets cnn_offsets(int L) {
 CnnWorkspace cnn_workspace(int L, int64_t B) {
   CnnWorkspace w{};
   const int64_t P = B * L * L, kh = (int64_t)L * L * CH;
-  const int64_t chunks = (P + WG_CHUNK - 1) / WG_CHUNK;
+  const int64_t chunks = (B + wgrad_group(B) - 1) / wgrad_group(B);   // weight-gradient rows
   size_t off = 0;
   auto take = [&](size_t bytes) {
     const size_t at = off;
@@ -761,7 +818,13 @@ hipError_t cnn_backward(int L, int64_t B, const float* prm, const float* logits,
   const CnnWorkspace wl = cnn_workspace(L, B);
   const CnnOffsets off = cnn_offsets(L);
   const int64_t P = B * L * L, kh = (int64_t)L * L * CH;
-  const int64_t chunks = (P + WG_CHUNK - 1) / WG_CHUNK;
+  const int G = wgrad_group(B);
+  const int64_t chunks = (B + G - 1) / G;
+  const size_t lds32 = wgrad_lds_bytes<32>(L), lds8 = wgrad_lds_bytes<8>(L);
+  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&conv_wgrad_kernel<32>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds32);
+  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&conv_wgrad_kernel<8>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds8);
   float* lossv = loss ? loss : WSP(float, loss);
   hipLaunchKernelGGL(loss_kernel, dim3(blocks_for(B, 256)), dim3(256), 0, s, B, logits, tgt,
                      budget, wb, WSP(float, dz), lossv);
@@ -773,7 +836,8 @@ hipError_t cnn_backward(int L, int64_t B, const float* prm, const float* logits,
                      WSP(float, dz), WSP(bf16, whb), WSP(bf16, a3), WSP(bf16, dp3));
   const unsigned g = blocks_for((P + 15) / 16, 4);
   // conv3: weights, then data back into a2's gradient
-  hipLaunchKernelGGL((conv_wgrad_kernel<32>), dim3((unsigned)chunks), dim3(256), 0, s, L, P,
+  hipLaunchKernelGGL((conv_wgrad_kernel<32>), dim3((unsigned)chunks), dim3(WG_THREADS), lds32, s,
+                     L, B, G,
                      WSP(bf16, dp3), WSP(bf16, a2), WSP(float, part), WSP(float, partb));
   hipLaunchKernelGGL((wgrad_reduce_kernel<32>), dim3(blocks_for(CH * 9 * CH, 64)), dim3(64), 0,
                      s, chunks, CH, WSP(float, part), WSP(float, partb), grads + off.W3,
@@ -781,7 +845,8 @@ hipError_t cnn_backward(int L, int64_t B, const float* prm, const float* logits,
   hipLaunchKernelGGL((conv_kernel<32, true>), dim3(g), dim3(256), 0, s, L, P, WSP(bf16, dp3),
                      WSP(bf16, wt3), nullptr, WSP(bf16, a2), WSP(bf16, dp2));
   // conv2
-  hipLaunchKernelGGL((conv_wgrad_kernel<32>), dim3((unsigned)chunks), dim3(256), 0, s, L, P,
+  hipLaunchKernelGGL((conv_wgrad_kernel<32>), dim3((unsigned)chunks), dim3(WG_THREADS), lds32, s,
+                     L, B, G,
                      WSP(bf16, dp2), WSP(bf16, a1), WSP(float, part), WSP(float, partb));
   hipLaunchKernelGGL((wgrad_reduce_kernel<32>), dim3(blocks_for(CH * 9 * CH, 64)), dim3(64), 0,
                      s, chunks, CH, WSP(float, part), WSP(float, partb), grads + off.W2,
@@ -789,7 +854,8 @@ hipError_t cnn_backward(int L, int64_t B, const float* prm, const float* logits,
   hipLaunchKernelGGL((conv_kernel<32, true>), dim3(g), dim3(256), 0, s, L, P, WSP(bf16, dp2),
                      WSP(bf16, wt2), nullptr, WSP(bf16, a1), WSP(bf16, dp1));
   // conv1: weights only
-  hipLaunchKernelGGL((conv_wgrad_kernel<8>), dim3((unsigned)chunks), dim3(256), 0, s, L, P,
+  hipLaunchKernelGGL((conv_wgrad_kernel<8>), dim3((unsigned)chunks), dim3(WG_THREADS), lds8, s,
+                     L, B, G,
                      WSP(bf16, dp1), WSP(bf16, x0), WSP(float, part), WSP(float, partb));
   hipLaunchKernelGGL((wgrad_reduce_kernel<8>), dim3(blocks_for(CH * 9 * 3, 64)), dim3(64), 0, s,
                      chunks, 3, WSP(float, part), WSP(float, partb), grads + off.W1,
