@@ -280,41 +280,36 @@ inline int wgrad_group(int64_t B) {
   return (int)(B <= target ? 1 : (B + target - 1) / target);
 }
 
-// grad W[co][tap][ci] (ci < cin_real) and grad b[co]: sums of the chunk
-// partials in chunk order.
+// grad W[co][tap][ci] (ci < cin_real) and grad b[co] from the per-workgroup
+// partials: a workgroup takes 16 outputs (index i: the W entries, then the
+// 32 biases) and 16 row segments; segment g adds rows g, g+16, ... in order,
+// and the 16 segment sums are added in segment order.
+constexpr int RED_OUT = 16, RED_SEG = 16;
+
 template <int CIN>
-__global__ void wgrad_reduce_kernel(int64_t chunks, int cin_real, const float* __restrict__ part,
-                                    const float* __restrict__ partb, float* __restrict__ gW,
-                                    float* __restrict__ gb) {
+__global__ void __launch_bounds__(RED_OUT * RED_SEG) wgrad_reduce_kernel(
+    int64_t rows, int cin_real, const float* __restrict__ part, const float* __restrict__ partb,
+    float* __restrict__ gW, float* __restrict__ gb) {
   constexpr int KP = (9 * CIN + 31) / 32 * 32;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < CH * 9 * cin_real) {
+  __shared__ float seg_sum[RED_SEG][RED_OUT];
+  const int o = threadIdx.x % RED_OUT, g = threadIdx.x / RED_OUT;
+  const int nW = CH * 9 * cin_real;
+  const int i = blockIdx.x * RED_OUT + o;
+  float acc = 0.0f;
+  if (i < nW) {
     const int co = i / (9 * cin_real), rem = i % (9 * cin_real);
-    const int tap = rem / cin_real, ci = rem % cin_real;
-    const int c = tap * CIN + ci;
-    // 8 interleaved partial sums (chunk k into sum k % 8), then added in order
-    float s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    int64_t k = 0;
-    for (; k + 8 <= chunks; k += 8)
-#pragma unroll
-      for (int j = 0; j < 8; ++j) s[j] += part[((k + j) * CH + co) * KP + c];
-    for (int j = 0; k < chunks; ++k, ++j) s[j] += part[(k * CH + co) * KP + c];
-    float t = s[0];
-#pragma unroll
-    for (int j = 1; j < 8; ++j) t += s[j];
-    gW[i] = t;
+    const int c = (rem / cin_real) * CIN + rem % cin_real;
+    for (int64_t k = g; k < rows; k += RED_SEG) acc += part[(k * CH + co) * KP + c];
+  } else if (i < nW + CH) {
+    for (int64_t k = g; k < rows; k += RED_SEG) acc += partb[k * CH + (i - nW)];
   }
-  if (i < CH) {
-    float s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    int64_t k = 0;
-    for (; k + 8 <= chunks; k += 8)
-#pragma unroll
-      for (int j = 0; j < 8; ++j) s[j] += partb[(k + j) * CH + i];
-    for (int j = 0; k < chunks; ++k, ++j) s[j] += partb[k * CH + i];
-    float t = s[0];
-#pragma unroll
-    for (int j = 1; j < 8; ++j) t += s[j];
-    gb[i] = t;
+  seg_sum[g][o] = acc;
+  __syncthreads();
+  if (g == 0 && i < nW + CH) {
+    float t = seg_sum[0][o];
+    for (int j = 1; j < RED_SEG; ++j) t += seg_sum[j][o];
+    if (i < nW) gW[i] = t;
+    else gb[i - nW] = t;
   }
 }
 
@@ -839,7 +834,8 @@ hipError_t cnn_backward(int L, int64_t B, const float* prm, const float* logits,
   hipLaunchKernelGGL((conv_wgrad_kernel<32>), dim3((unsigned)chunks), dim3(WG_THREADS), lds32, s,
                      L, B, G,
                      WSP(bf16, dp3), WSP(bf16, a2), WSP(float, part), WSP(float, partb));
-  hipLaunchKernelGGL((wgrad_reduce_kernel<32>), dim3(blocks_for(CH * 9 * CH, 64)), dim3(64), 0,
+  hipLaunchKernelGGL((wgrad_reduce_kernel<32>), dim3(blocks_for(CH * 9 * CH + CH, RED_OUT)),
+                     dim3(RED_OUT * RED_SEG), 0,
                      s, chunks, CH, WSP(float, part), WSP(float, partb), grads + off.W3,
                      grads + off.b3);
   hipLaunchKernelGGL((conv_kernel<32, true>), dim3(g), dim3(256), 0, s, L, P, WSP(bf16, dp3),
@@ -848,7 +844,8 @@ hipError_t cnn_backward(int L, int64_t B, const float* prm, const float* logits,
   hipLaunchKernelGGL((conv_wgrad_kernel<32>), dim3((unsigned)chunks), dim3(WG_THREADS), lds32, s,
                      L, B, G,
                      WSP(bf16, dp2), WSP(bf16, a1), WSP(float, part), WSP(float, partb));
-  hipLaunchKernelGGL((wgrad_reduce_kernel<32>), dim3(blocks_for(CH * 9 * CH, 64)), dim3(64), 0,
+  hipLaunchKernelGGL((wgrad_reduce_kernel<32>), dim3(blocks_for(CH * 9 * CH + CH, RED_OUT)),
+                     dim3(RED_OUT * RED_SEG), 0,
                      s, chunks, CH, WSP(float, part), WSP(float, partb), grads + off.W2,
                      grads + off.b2);
   hipLaunchKernelGGL((conv_kernel<32, true>), dim3(g), dim3(256), 0, s, L, P, WSP(bf16, dp2),
@@ -857,7 +854,8 @@ hipError_t cnn_backward(int L, int64_t B, const float* prm, const float* logits,
   hipLaunchKernelGGL((conv_wgrad_kernel<8>), dim3((unsigned)chunks), dim3(WG_THREADS), lds8, s,
                      L, B, G,
                      WSP(bf16, dp1), WSP(bf16, x0), WSP(float, part), WSP(float, partb));
-  hipLaunchKernelGGL((wgrad_reduce_kernel<8>), dim3(blocks_for(CH * 9 * 3, 64)), dim3(64), 0, s,
+  hipLaunchKernelGGL((wgrad_reduce_kernel<8>), dim3(blocks_for(CH * 9 * 3 + CH, RED_OUT)),
+                     dim3(RED_OUT * RED_SEG), 0, s,
                      chunks, 3, WSP(float, part), WSP(float, partb), grads + off.W1,
                      grads + off.b1);
   return hipGetLastError();
