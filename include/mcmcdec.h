@@ -418,9 +418,14 @@ int mcmc_gated_plan(mcmc_gated* gated, mcmc_plan** h_plan);
  * parameters d_params.  h_ids [n] host syndrome ids (NULL => i), h_p [n] host
  * rates (NULL => the configured p).  Outputs: d_chosen [n] (required),
  * d_route [n] (0..3) and d_logits [n][8] (or NULL), d_correction [n][n_q]
- * (or NULL), h_counts [4] syndromes per final route (or NULL).  Synchronous:
- * it waits for the gate (and for the short-budget estimates when escalating)
- * before building each Metropolis plan, and returns with the stream drained.
+ * (or NULL), h_counts [4] syndromes per final route (or NULL).
+ * Without escalation the routes become a three-group plan on the device and
+ * the persistent kernel reads its tile ranges there: the call enqueues
+ * everything and returns (it waits on the stream only to fill h_counts, and
+ * on its own host-to-device copies of the previous call before reusing their
+ * staging buffers).  With escalation it waits for the gate and for the short
+ * runs' estimates to build each plan on the host, and returns with the
+ * stream drained.
  */
 int mcmc_gated_decode(mcmc_gated* gated, const float* d_params, const uint8_t* d_syndromes,
                       const uint32_t* h_ids, const double* h_p, int64_t n, uint8_t* d_chosen,

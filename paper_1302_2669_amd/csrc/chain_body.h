@@ -380,11 +380,19 @@ __device__ __forceinline__ void chains_persistent(const RunArgs& a) {
     uint32_t tile = 0;
     if (lane == 0) tile = atomicAdd(a.queue, 1u);
     tile = __builtin_amdgcn_readfirstlane(tile);  // lane 0 is active: the loop is wave-uniform
-    if ((int64_t)tile >= a.n_tiles) break;
     GroupDesc g;
     int L;
     int64_t first;
-    if (a.tiles) {
+    if (a.tile_cum) {
+      const uint32_t c0 = a.tile_cum[0], c1 = a.tile_cum[1], c2 = a.tile_cum[2];
+      if (tile >= c2) break;
+      const int gi = tile < c0 ? 0 : (tile < c1 ? 1 : 2);
+      g = a.groups[gi];
+      L = g.L;
+      first = (int64_t)(tile - (gi == 0 ? 0u : (gi == 1 ? c0 : c1))) * TILE;
+    } else if ((int64_t)tile >= a.n_tiles) {
+      break;
+    } else if (a.tiles) {
       const TileDesc td = a.tiles[tile];
       g = a.groups[td.group];
       L = td.L;

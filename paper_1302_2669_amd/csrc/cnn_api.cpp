@@ -4,9 +4,11 @@
 #include <stdint.h>
 #include <string.h>
 
+#include <algorithm>
 #include <new>
 #include <vector>
 
+#include "device_common.h"
 #include "host_common.h"
 
 using namespace mcmc;
@@ -135,12 +137,31 @@ struct mcmc_gated {
   int32_t* h_idx = nullptr;   // escalated batch indices
   float* h_pf = nullptr;
   std::vector<mcmc_item> items;
+  // device-built budget plan (the path without escalation): groups [3],
+  // items [N], tables [N][K][4], beta_bar [N], ids [N], counters [8],
+  // cumulative tiles [4]; pinned staging of ids, tables, beta and counts
+  void* dblock = nullptr;
+  GroupDesc* d_groups = nullptr;
+  ItemDesc* d_items = nullptr;
+  uint32_t* d_tables = nullptr;
+  double* d_beta = nullptr;
+  uint32_t* d_ids = nullptr;
+  uint32_t* d_counts = nullptr;
+  uint32_t* d_tile_cum = nullptr;
+  uint32_t* h_ids = nullptr;
+  uint32_t* h_tab = nullptr;
+  double* h_beta = nullptr;
+  uint32_t* h_cnt = nullptr;
+  hipEvent_t staged = nullptr;       // the last call's host-to-device copies
+  bool staged_pending = false;
 };
 
 namespace {
 
 struct GatedWorkspace {
-  size_t cnn, logits, pf, route, cls, conf, flag, idx, prob, chosen, plan, bytes;
+  size_t cnn, logits, pf, route, cls, conf, flag, idx, prob, chosen, plan;
+  // device-built path: queue, class starts, per-chain sums, final rows
+  size_t q, irows, in_n, S, A, nf, frows, bytes;
 };
 
 GatedWorkspace gated_workspace(const mcmc_gated* g) {
@@ -163,6 +184,15 @@ GatedWorkspace gated_workspace(const mcmc_gated* g) {
   w.prob = take((size_t)n * 4 * sizeof(double));
   w.chosen = take((size_t)n);
   w.plan = take(g->plan_ws);
+  const int64_t chains = n * 4 * (int64_t)g->cfg.n_temps * g->cfg.chains;
+  const int64_t rows = n * (int64_t)words_per_config(g->cfg.L) * 4;
+  w.q = take(kQueueSlots * sizeof(uint32_t));
+  w.irows = take((size_t)rows * sizeof(uint32_t));
+  w.in_n = take((size_t)n * 4 * sizeof(int32_t));
+  w.S = take((size_t)chains * sizeof(int64_t));
+  w.A = take((size_t)chains * sizeof(int64_t));
+  w.nf = take((size_t)chains * sizeof(int32_t));
+  w.frows = take((size_t)rows * sizeof(uint32_t));
   w.bytes = off;
   return w;
 }
@@ -174,6 +204,15 @@ void free_gated(mcmc_gated* g) {
   if (g->h_flag) (void)hipHostFree(g->h_flag);
   if (g->h_idx) (void)hipHostFree(g->h_idx);
   if (g->h_pf) (void)hipHostFree(g->h_pf);
+  if (g->h_ids) (void)hipHostFree(g->h_ids);
+  if (g->h_tab) (void)hipHostFree(g->h_tab);
+  if (g->h_beta) (void)hipHostFree(g->h_beta);
+  if (g->h_cnt) (void)hipHostFree(g->h_cnt);
+  if (g->staged) {
+    (void)hipEventSynchronize(g->staged);
+    (void)hipEventDestroy(g->staged);
+  }
+  if (g->dblock) (void)hipFree(g->dblock);
   delete g;
 }
 
@@ -233,6 +272,34 @@ int mcmc_gated_create(const mcmc_gate_config* h_cfg, mcmc_gated** out) {
   ok = ok && hipHostMalloc((void**)&g->h_flag, n, hipHostMallocDefault) == hipSuccess;
   ok = ok && hipHostMalloc((void**)&g->h_idx, n * 4, hipHostMallocDefault) == hipSuccess;
   ok = ok && hipHostMalloc((void**)&g->h_pf, n * 4, hipHostMallocDefault) == hipSuccess;
+  // device-built budget plan storage
+  const size_t K4 = 4 * (size_t)c.n_temps;
+  const size_t sz_g = align_up(3 * sizeof(GroupDesc)), sz_i = align_up(n * sizeof(ItemDesc));
+  // tables: one per syndrome, then the configured rate's at slot N
+  const size_t sz_t = align_up((n + 1) * K4 * 4), sz_b = align_up(n * 8), sz_id = align_up(n * 4);
+  const size_t sz_c = align_up(8 * 4), sz_tc = align_up(4 * 4);
+  ok = ok && hipMalloc(&g->dblock, sz_g + sz_i + sz_t + sz_b + sz_id + sz_c + sz_tc) == hipSuccess;
+  if (ok) {
+    char* b = (char*)g->dblock;
+    g->d_groups = (GroupDesc*)b;
+    g->d_items = (ItemDesc*)(b + sz_g);
+    g->d_tables = (uint32_t*)(b + sz_g + sz_i);
+    g->d_beta = (double*)(b + sz_g + sz_i + sz_t);
+    g->d_ids = (uint32_t*)(b + sz_g + sz_i + sz_t + sz_b);
+    g->d_counts = (uint32_t*)(b + sz_g + sz_i + sz_t + sz_b + sz_id);
+    g->d_tile_cum = (uint32_t*)(b + sz_g + sz_i + sz_t + sz_b + sz_id + sz_c);
+  }
+  ok = ok && hipHostMalloc((void**)&g->h_ids, n * 4, hipHostMallocDefault) == hipSuccess;
+  ok = ok && hipHostMalloc((void**)&g->h_tab, n * K4 * 4, hipHostMallocDefault) == hipSuccess;
+  ok = ok && hipHostMalloc((void**)&g->h_beta, n * 8, hipHostMallocDefault) == hipSuccess;
+  ok = ok && hipHostMalloc((void**)&g->h_cnt, 8 * 4, hipHostMallocDefault) == hipSuccess;
+  ok = ok && hipEventCreateWithFlags(&g->staged, hipEventDisableTiming) == hipSuccess;
+  if (ok) {
+    // the configured rate's table after the per-syndrome slots, for batches
+    // without their own rates
+    fill_table(c.p, c.n_temps, g->h_tab);
+    ok = hipMemcpy(g->d_tables + n * K4, g->h_tab, K4 * 4, hipMemcpyHostToDevice) == hipSuccess;
+  }
   if (!ok) {
     free_gated(g);
     return st != MCMC_OK ? st : MCMC_EDEVICE;
@@ -258,6 +325,139 @@ int mcmc_gated_plan(mcmc_gated* g, mcmc_plan** h_plan) {
   return MCMC_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// The gated decode without escalation, with no host synchronisation: the
+// gate's routes are turned into a three-group plan on the device
+// (launch_budget_plan) and the persistent kernel reads its tile ranges there.
+int gated_decode_device(mcmc_gated* g, const float* d_params, const uint8_t* d_syndromes,
+                        const uint32_t* h_ids, const double* h_p, int64_t n, uint8_t* d_chosen,
+                        uint8_t* route, float* logits, uint8_t* d_correction, int64_t* h_counts,
+                        char* ws, const GatedWorkspace& wl, hipStream_t s) {
+  const mcmc_gate_config& c = g->cfg;
+  // the previous call's copies out of the staging buffers must be done
+  if (g->staged_pending && hipEventSynchronize(g->staged) != hipSuccess) return MCMC_EDEVICE;
+  for (int64_t i = 0; i < n; ++i) {
+    g->h_pf[i] = (float)(h_p ? h_p[i] : c.p);
+    g->h_ids[i] = h_ids ? h_ids[i] : (uint32_t)i;
+  }
+  float* pf = (float*)(ws + wl.pf);
+  bool ok = hipMemcpyAsync(pf, g->h_pf, (size_t)n * 4, hipMemcpyHostToDevice, s) == hipSuccess;
+  ok = ok && hipMemcpyAsync(g->d_ids, g->h_ids, (size_t)n * 4, hipMemcpyHostToDevice, s) ==
+                 hipSuccess;
+  if (h_p) {
+    fill_tables_parallel(h_p, n, c.n_temps, g->h_tab, g->h_beta);
+    ok = ok && hipMemcpyAsync(g->d_tables, g->h_tab, (size_t)n * 4 * c.n_temps * 4,
+                              hipMemcpyHostToDevice, s) == hipSuccess;
+    ok = ok && hipMemcpyAsync(g->d_beta, g->h_beta, (size_t)n * 8, hipMemcpyHostToDevice, s) ==
+                   hipSuccess;
+  }
+  ok = ok && hipEventRecord(g->staged, s) == hipSuccess;
+  if (!ok) return MCMC_EDEVICE;
+  g->staged_pending = true;
+
+  int st = hip_status(cnn_infer(c.L, n, d_params, d_syndromes, pf, logits, ws + wl.cnn, s));
+  if (st != MCMC_OK) return st;
+  st = hip_status(cnn_gate(n, logits, c.threshold, route, (uint8_t*)(ws + wl.cls),
+                           (float*)(ws + wl.conf), s));
+  if (st != MCMC_OK) return st;
+
+  BudgetArgs ba{};
+  ba.n = n;
+  ba.route = route;
+  ba.ids = g->d_ids;
+  ba.beta = h_p ? g->d_beta : nullptr;
+  ba.beta0 = beta_bar(c.p);
+  ba.table0_off = c.max_batch * 4 * (int64_t)c.n_temps;
+  ba.L = c.L;
+  ba.K = c.n_temps;
+  ba.C = c.chains;
+  ba.burn = c.burn;
+  ba.sweeps[0] = c.sweeps_full;
+  ba.sweeps[1] = c.sweeps_short;
+  ba.sweeps[2] = 0;
+  ba.counts = g->d_counts;
+  ba.groups = g->d_groups;
+  ba.items = g->d_items;
+  ba.tile_cum = g->d_tile_cum;
+  st = hip_status(launch_budget_plan(ba, s));
+  if (st != MCMC_OK) return st;
+
+  uint32_t* queue = (uint32_t*)(ws + wl.q);
+  uint32_t* irows = (uint32_t*)(ws + wl.irows);
+  int32_t* in_n = (int32_t*)(ws + wl.in_n);
+  int64_t* S = (int64_t*)(ws + wl.S);
+  int32_t* nf = (int32_t*)(ws + wl.nf);
+  uint32_t* frows = d_correction ? (uint32_t*)(ws + wl.frows) : nullptr;
+  st = hip_status(launch_zero(queue, kQueueSlots, s));
+  if (st != MCMC_OK) return st;
+  StartArgs sa{};
+  sa.syn = d_syndromes;
+  sa.items = g->d_items;
+  sa.groups = g->d_groups;
+  sa.n = n;
+  sa.rows = irows;
+  sa.weights = in_n;
+  st = hip_status(c.init == MCMC_INIT_MATCHING ? launch_init_matching(sa, s) : launch_init(sa, s));
+  if (st != MCMC_OK) return st;
+
+  const int r = range_of(c.L);
+  const int64_t per_item = 4 * (int64_t)c.n_temps * c.chains;
+  const int64_t max_tiles = (n * per_item + TILE - 1) / TILE + 3;
+  RunArgs a{};
+  a.groups = g->d_groups;
+  a.items = g->d_items;
+  a.tables = g->d_tables;
+  a.tile_cum = g->d_tile_cum;
+  a.n_tiles = max_tiles;
+  a.queue = queue + r;
+  a.lmin = RANGE_LO[r];
+  a.lmax = RANGE_HI[r];
+  a.k0 = (uint32_t)(c.seed & 0xFFFFFFFFull);
+  a.k1 = (uint32_t)(c.seed >> 32);
+  a.init_rows = irows;
+  a.init_n = in_n;
+  a.S_out = S;
+  a.A_out = (int64_t*)(ws + wl.A);
+  a.n_out = nf;
+  a.final_rows = frows;
+  a.total_chains = n * per_item;
+  const int64_t waves = std::min<int64_t>(max_tiles, (int64_t)device_cus() * 4 * RANGE_WAVES[r]);
+  st = hip_status(launch_chains(r, a, (int)waves, 256, s));
+  if (st != MCMC_OK) return st;
+
+  DecideArgs d{};
+  d.items = g->d_items;
+  d.groups = g->d_groups;
+  d.ln2 = log(2.0);
+  d.n = n;
+  d.S = S;
+  d.n_final = nf;
+  d.final_rows = frows;
+  d.class_prob = (double*)(ws + wl.prob);
+  d.mean_n = nullptr;
+  d.chosen = d_chosen;
+  d.correction = d_correction;
+  st = hip_status(launch_decide(d, s));
+  if (st != MCMC_OK) return st;
+  if (h_counts) {
+    if (hipMemcpyAsync(g->h_cnt, g->d_counts, 3 * 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return MCMC_EDEVICE;
+    h_counts[0] = g->h_cnt[2];    // no sweep
+    h_counts[1] = g->h_cnt[1];    // short budget
+    h_counts[2] = g->h_cnt[0];    // full budget
+    h_counts[3] = 0;
+  }
+  return MCMC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 int mcmc_gated_decode(mcmc_gated* g, const float* d_params, const uint8_t* d_syndromes,
                       const uint32_t* h_ids, const double* h_p, int64_t n, uint8_t* d_chosen,
                       uint8_t* d_route, float* d_logits, uint8_t* d_correction,
@@ -279,6 +479,14 @@ int mcmc_gated_decode(mcmc_gated* g, const float* d_params, const uint8_t* d_syn
   char* ws = (char*)d_workspace;
   float* logits = d_logits ? d_logits : (float*)(ws + wl.logits);
   uint8_t* route = d_route ? d_route : (uint8_t*)(ws + wl.route);
+  if (c.escalate <= 0.0f)
+    return gated_decode_device(g, d_params, d_syndromes, h_ids, h_p, n, d_chosen, route, logits,
+                               d_correction, h_counts, ws, wl, s);
+  // escalation: the routes come back to the host to build each plan
+  if (g->staged_pending) {
+    if (hipEventSynchronize(g->staged) != hipSuccess) return MCMC_EDEVICE;
+    g->staged_pending = false;
+  }
   float* pf = (float*)(ws + wl.pf);
   double* prob = (double*)(ws + wl.prob);
 

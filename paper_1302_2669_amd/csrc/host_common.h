@@ -41,6 +41,10 @@ inline void fill_table(double p, int32_t K, uint32_t* out) {
   }
 }
 
+// Tables [n][K][4] and beta_bar [n] of n rates, on up to 16 host threads
+// (each value is computed exactly as fill_table / beta_bar compute it).
+void fill_tables_parallel(const double* p, int64_t n, int32_t K, uint32_t* tables, double* beta);
+
 inline int hip_status(hipError_t e) { return e == hipSuccess ? MCMC_OK : MCMC_EDEVICE; }
 
 // Compute units of the current device (cached per device).

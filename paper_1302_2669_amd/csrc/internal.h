@@ -64,6 +64,10 @@ struct RunArgs {
   const uint32_t* syndrome_ids;  // [n] or nullptr (=> s)
   uint32_t table0[MCMC_TEMPS_MAX][4];
   int64_t n_tiles;
+  // device-built plan: cumulative tile counts of groups 0, 1, 2 (tile t of
+  // group g covers tasks (t - tiles before g) * TILE ...); when set, tiles and
+  // n_tiles are not used by the kernel
+  const uint32_t* tile_cum;
   uint32_t* queue;               // tile counter of this launch, zero at start
   int32_t lmin, lmax;            // L range compiled into the launched kernel
   uint32_t k0, k1;               // Philox key
@@ -144,6 +148,26 @@ hipError_t launch_sample(int L, uint32_t threshold, uint32_t k0, uint32_t k1, co
 hipError_t launch_sample_items(const ItemDesc* items, const GroupDesc* groups, int64_t n,
                                uint32_t k0, uint32_t k1, uint8_t* syn, uint8_t* true_class,
                                hipStream_t s);
+
+// ---- device-built budget plans ----------------------------------------------
+// One code size, three groups by sweep budget: 0 = sweeps[0] (full), 1 =
+// sweeps[1] (short), 2 = sweeps[2] (none); route r of syndrome i puts it in
+// group 0 (r = 2), 1 (r = 1) or 2 (r = 0).
+struct BudgetArgs {
+  int64_t n;
+  const uint8_t* route;         // [n]
+  const uint32_t* ids;          // [n] syndrome ids
+  const double* beta;           // [n] beta_bar per syndrome (tables [n][K][4]), or nullptr
+  double beta0;                 // beta_bar when beta is nullptr
+  int64_t table0_off;           // offset of the one table [K][4] when beta is nullptr
+  int32_t L, K, C, burn;
+  int32_t sweeps[3];
+  uint32_t* counts;             // [8] scratch, cleared here
+  GroupDesc* groups;            // [3] out
+  ItemDesc* items;              // [n] out
+  uint32_t* tile_cum;           // [3] out: cumulative tiles of groups 0..2
+};
+hipError_t launch_budget_plan(const BudgetArgs& a, hipStream_t s);
 
 // ---- gate network -----------------------------------------------------------
 // Offsets (in floats) of the parameter blocks in the flat fp32 vector.

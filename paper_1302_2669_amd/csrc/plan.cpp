@@ -28,6 +28,39 @@
 #include "host_common.h"
 #include "internal.h"
 
+namespace mcmc {
+
+void fill_tables_parallel(const double* p, int64_t n, int32_t K, uint32_t* tables, double* beta) {
+  auto fill = [&](int64_t lo, int64_t hi) {
+    for (int64_t i = lo; i < hi; ++i) {
+      uint32_t* dst = tables + i * 4 * (int64_t)K;
+      if (i > lo && p[i] == p[i - 1]) {
+        std::copy(dst - 4 * K, dst, dst);
+        beta[i] = beta[i - 1];
+      } else {
+        fill_table(p[i], K, dst);
+        beta[i] = beta_bar(p[i]);
+      }
+    }
+  };
+  const int64_t kChunk = 4096;
+  const int workers = (int)std::min<int64_t>(
+      std::max(1u, std::min(16u, std::thread::hardware_concurrency())), (n + kChunk - 1) / kChunk);
+  if (workers <= 1) {
+    fill(0, n);
+    return;
+  }
+  std::vector<std::thread> pool;
+  const int64_t per = (n + workers - 1) / workers;
+  for (int w = 0; w < workers; ++w) {
+    const int64_t lo = w * per, hi = std::min(n, lo + per);
+    if (lo < hi) pool.emplace_back(fill, lo, hi);
+  }
+  for (auto& t : pool) t.join();
+}
+
+}  // namespace mcmc
+
 using namespace mcmc;
 
 struct GraphEntry {

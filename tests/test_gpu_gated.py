@@ -105,6 +105,10 @@ def test_gated_per_syndrome_rates():
     logits, _ = gate.forward(L, prm, syn, torch.from_numpy(p.astype(np.float32)).to(DEV))
     torch.cuda.synchronize()
     assert torch.equal(logits[:, :7], out["logits"][:, :7])
+    # a following call without rates uses the configured rate, not the tables
+    # the previous call uploaded
+    out2 = g.decode(prm, syn, want_correction=True)
+    check_routes(L, syn, np.full(n, 0.1), np.arange(n, dtype=np.int64), out2, chains, 4, 12, seed)
     g.close()
 
 
