@@ -16,6 +16,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+
+#include "host_common.h"
 #include "internal.h"
 
 namespace mcmc {
@@ -437,7 +440,8 @@ __global__ void __launch_bounds__(INFER_THREADS) infer_kernel(
     int L, int S, int64_t B, const uint8_t* __restrict__ syn, const float* __restrict__ p,
     const bf16* __restrict__ wb1, const bf16* __restrict__ wb2, const bf16* __restrict__ wb3,
     const bf16* __restrict__ whb, const float* __restrict__ b1, const float* __restrict__ b2,
-    const float* __restrict__ b3, const float* __restrict__ bh, float* __restrict__ logits) {
+    const float* __restrict__ b3, const float* __restrict__ bh, float* __restrict__ logits,
+    int64_t n_groups) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int LL = L * L, npix = S * LL, nst = 2 * L * (L - 1), ns = L * (L - 1);
   bf16* w1s = reinterpret_cast<bf16*>(smem);
@@ -447,8 +451,6 @@ __global__ void __launch_bounds__(INFER_THREADS) infer_kernel(
   bf16* zslot = reinterpret_cast<bf16*>(part + INFER_WAVES * 256);
   bf16* bufA = zslot + 8;
   bf16* bufB = bufA + npix * ASTR;
-  const int64_t s0 = (int64_t)blockIdx.x * S;
-  const int nsm = (int)min((int64_t)S, B - s0);
   const int tid = threadIdx.x;
 
   for (int i = tid; i < 32 * 12; i += INFER_THREADS) {
@@ -464,6 +466,12 @@ __global__ void __launch_bounds__(INFER_THREADS) infer_kernel(
         *reinterpret_cast<const uint4*>(wb3 + r * 288 + c * 8);
   }
   if (tid < 8) zslot[tid] = (bf16)0.0f;
+  // persistent: the weights stay in LDS while the workgroup walks its groups
+  // of S samples (the barriers between the stages already order every
+  // buffer's reuse from one group to the next)
+  for (int64_t grp = blockIdx.x; grp < n_groups; grp += gridDim.x) {
+  const int64_t s0 = grp * S;
+  const int nsm = (int)min((int64_t)S, B - s0);
   // input planes, 8 channels per pixel (the layout of the layered x0)
   for (int q = tid; q < npix; q += INFER_THREADS) {
     const int sm = q / LL, r = q - sm * LL, y = r / L, x = r - (r / L) * L;
@@ -506,6 +514,7 @@ __global__ void __launch_bounds__(INFER_THREADS) infer_kernel(
       for (int j = 1; j < INFER_WAVES; ++j) t = t + part[j * 256 + row * 16 + o];
       logits[(s0 + row) * 8 + o] = t + bh[o];
     }
+  }
   }
 }
 
@@ -774,9 +783,11 @@ hipError_t cnn_infer(int L, int64_t B, const float* prm, const uint8_t* syn, con
   (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&infer_kernel),
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   const int64_t groups = (B + S - 1) / S;
-  hipLaunchKernelGGL(infer_kernel, dim3((unsigned)groups), dim3(INFER_THREADS), lds, s, L, S, B,
-                     syn, p, wb1, wb2, wb3, whb, prm + off.b1, prm + off.b2, prm + off.b3,
-                     prm + off.bh, logits);
+  const int per_cu = std::max<int>(1, std::min<int>(4, (int)(163840 / lds)));
+  const int64_t wgs = std::min<int64_t>(groups, (int64_t)device_cus() * per_cu);
+  hipLaunchKernelGGL(infer_kernel, dim3((unsigned)wgs), dim3(INFER_THREADS), lds, s, L, S, B, syn,
+                     p, wb1, wb2, wb3, whb, prm + off.b1, prm + off.b2, prm + off.b3, prm + off.bh,
+                     logits, groups);
   return hipGetLastError();
 }
 
