@@ -132,26 +132,32 @@ __global__ void __launch_bounds__(256) conv_kernel(int L, int64_t P, const bf16*
       if (yy >= 0 && yy < L && xx >= 0 && xx < L)
         a = load8(in + ((b * LL + yy * L + xx) * CIN + cc * 8));
     }
-    const bf16x8 b0 = load8(w + (int64_t)n * KP + s * 32 + 8 * grp);
-    const bf16x8 b1 = load8(w + (int64_t)(n + 16) * KP + s * 32 + 8 * grp);
-    acc0 = mfma(a, b0, acc0);
-    acc1 = mfma(a, b1, acc1);
+    const bf16x8 w0 = load8(w + (int64_t)n * KP + s * 32 + 8 * grp);
+    const bf16x8 w1 = load8(w + (int64_t)(n + 16) * KP + s * 32 + 8 * grp);
+    // weights as the A operand: D[channel][pixel], so lane (n, grp) ends
+    // with channels 4 grp .. 4 grp + 3 (and + 16) of pixel n
+    acc0 = mfma(w0, a, acc0);
+    acc1 = mfma(w1, a, acc1);
   }
+  if (pm >= P) return;
+  bf16x8 o;   // channels 4 grp + i at o[i], 16 + 4 grp + i at o[4 + i]
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
-    const int64_t po = tile * 16 + 4 * grp + i;
-    if (po >= P) continue;
+    const int c0 = 4 * grp + i, c1 = 16 + 4 * grp + i;
     float v0 = acc0[i], v1 = acc1[i];
     if (!MIRROR) {
-      v0 = fmaxf(v0 + bias[n], 0.0f);
-      v1 = fmaxf(v1 + bias[n + 16], 0.0f);
+      v0 = fmaxf(v0 + bias[c0], 0.0f);
+      v1 = fmaxf(v1 + bias[c1], 0.0f);
     } else {
-      v0 = (float)mask[po * CH + n] > 0.0f ? v0 : 0.0f;
-      v1 = (float)mask[po * CH + n + 16] > 0.0f ? v1 : 0.0f;
+      v0 = (float)mask[pm * CH + c0] > 0.0f ? v0 : 0.0f;
+      v1 = (float)mask[pm * CH + c1] > 0.0f ? v1 : 0.0f;
     }
-    out[po * CH + n] = (bf16)v0;
-    out[po * CH + n + 16] = (bf16)v1;
+    o[i] = (bf16)v0;
+    o[4 + i] = (bf16)v1;
   }
+  const uint4 ov = __builtin_bit_cast(uint4, o);
+  *reinterpret_cast<uint2*>(out + pm * CH + 4 * grp) = make_uint2(ov.x, ov.y);
+  *reinterpret_cast<uint2*>(out + pm * CH + 16 + 4 * grp) = make_uint2(ov.z, ov.w);
 }
 
 // ---- weight gradients ------------------------------------------------------
@@ -336,10 +342,17 @@ __global__ void __launch_bounds__(64 * HEAD_CHAINS) head_fwd_kernel(
   const int LL = L * L;
   const int64_t kh = (int64_t)LL * CH;
   f32x4 acc = {0, 0, 0, 0};
-  for (int st = wave; st < LL; st += HEAD_CHAINS) {
-    const bf16x8 a = bm < B ? load8(a3 + bm * kh + st * 32 + 8 * grp) : zero8();
-    const bf16x8 b = n < 7 ? load8(whb + (int64_t)n * kh + st * 32 + 8 * grp) : zero8();
-    acc = mfma(a, b, acc);
+  for (int st0 = wave; st0 < LL; st0 += 8 * HEAD_CHAINS) {
+    bf16x8 aq[8], bq[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int st = st0 + j * HEAD_CHAINS;
+      aq[j] = (st < LL && bm < B) ? load8(a3 + bm * kh + st * 32 + 8 * grp) : zero8();
+      bq[j] = (st < LL && n < 7) ? load8(whb + (int64_t)n * kh + st * 32 + 8 * grp) : zero8();
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+      if (st0 + j * HEAD_CHAINS < LL) acc = mfma(aq[j], bq[j], acc);
   }
 #pragma unroll
   for (int i = 0; i < 4; ++i) part[wave][4 * grp + i][n] = acc[i];
@@ -373,9 +386,12 @@ constexpr int INFER_PART_BYTES = INFER_WAVES * 256 * 4 + 16;   // + a 16-byte ze
 
 
 // One convolution over the group's pixels, LDS to LDS.  Each wave takes two
-// 16-pixel tiles per trip (four independent MFMA chains); an A operand whose
-// tap falls outside the image (or whose pixel is past the group) is read from
-// a 16-byte slot of zeros, so the loads carry no branches.
+// 16-pixel tiles per trip (four independent MFMA chains).  Weights are the
+// A operand (held in VGPRs for the layer), activations the B operand, so a
+// lane ends with four consecutive channels of one pixel and writes them in
+// one 8-byte store.  A tap outside the image (or a pixel past the group) is
+// read from a 16-byte slot of zeros: the validity of the nine taps of a
+// lane's pixel is a 9-bit mask computed once per tile.
 template <int CIN, int WSTR, int INSTR>
 __device__ __forceinline__ void conv_lds(int L, int LL, int npix, const bf16* in, const bf16* w,
                                          const float* __restrict__ bias, bf16* out,
@@ -384,54 +400,66 @@ __device__ __forceinline__ void conv_lds(int L, int LL, int npix, const bf16* in
   constexpr int STEPS = KP / 32;
   constexpr int CHUNKS = CIN / 8;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, grp = lane >> 4, n = lane & 15;
-  bf16x8 bw0[STEPS], bw1[STEPS];
+  bf16x8 w0[STEPS], w1[STEPS];
 #pragma unroll
   for (int st = 0; st < STEPS; ++st) {
-    bw0[st] = lds8(w + n * WSTR + st * 32 + 8 * grp);
-    bw1[st] = lds8(w + (n + 16) * WSTR + st * 32 + 8 * grp);
+    w0[st] = lds8(w + n * WSTR + st * 32 + 8 * grp);
+    w1[st] = lds8(w + (n + 16) * WSTR + st * 32 + 8 * grp);
   }
-  const float bias0 = bias[n], bias1 = bias[n + 16];
+  float bias0[4], bias1[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    bias0[i] = bias[4 * grp + i];
+    bias1[i] = bias[16 + 4 * grp + i];
+  }
   const int ntiles = (npix + 15) / 16;
   for (int t0 = wave; t0 < ntiles; t0 += 2 * INFER_WAVES) {
-    int q[2], y[2], x[2];
-    bool ok[2];
+    int q[2];
+    uint32_t valid[2];
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
       q[u] = (t0 + u * INFER_WAVES) * 16 + n;
-      ok[u] = q[u] < npix;
-      const int r = ok[u] ? q[u] % LL : 0;
-      y[u] = r / L;
-      x[u] = r - y[u] * L;
+      const bool ok = q[u] < npix;
+      const int r = ok ? q[u] % LL : 0;
+      const int y = r / L, x = r - (r / L) * L;
+      uint32_t m = 0;
+#pragma unroll
+      for (int tap = 0; tap < 9; ++tap) {
+        const int yy = y + tap_dy(tap), xx = x + tap_dx(tap);
+        m |= (uint32_t)(yy >= 0 && yy < L && xx >= 0 && xx < L) << tap;
+      }
+      valid[u] = ok ? m : 0u;
     }
     f32x4 acc[2][2] = {{{0, 0, 0, 0}, {0, 0, 0, 0}}, {{0, 0, 0, 0}, {0, 0, 0, 0}}};
 #pragma unroll
     for (int st = 0; st < STEPS; ++st) {
       const int g = 4 * st + grp;
       const int tap = g / CHUNKS, cc = g % CHUNKS;
-      const int dy = tap_dy(tap), dx = tap_dx(tap);
-      bf16x8 a[2];
+      const int toff = (tap_dy(tap) * L + tap_dx(tap)) * INSTR + cc * 8;
+      bf16x8 xa[2];
 #pragma unroll
       for (int u = 0; u < 2; ++u) {
-        const int yy = y[u] + dy, xx = x[u] + dx;
-        const bool in_img = ok[u] && tap < 9 && yy >= 0 && yy < L && xx >= 0 && xx < L;
-        const bf16* src = in_img ? in + (q[u] + dy * L + dx) * INSTR + cc * 8 : zslot;
-        a[u] = lds8(src);
+        const bool in_img = tap < 9 && ((valid[u] >> tap) & 1u);
+        xa[u] = lds8(in_img ? in + q[u] * INSTR + toff : zslot);
       }
 #pragma unroll
       for (int u = 0; u < 2; ++u) {
-        acc[u][0] = mfma(a[u], bw0[st], acc[u][0]);
-        acc[u][1] = mfma(a[u], bw1[st], acc[u][1]);
+        acc[u][0] = mfma(w0[st], xa[u], acc[u][0]);
+        acc[u][1] = mfma(w1[st], xa[u], acc[u][1]);
       }
     }
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
+      if (q[u] >= npix) continue;
+      bf16x8 o;
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const int po = (t0 + u * INFER_WAVES) * 16 + 4 * grp + i;
-        if (po >= npix) continue;
-        out[po * ASTR + n] = (bf16)fmaxf(acc[u][0][i] + bias0, 0.0f);
-        out[po * ASTR + n + 16] = (bf16)fmaxf(acc[u][1][i] + bias1, 0.0f);
+        o[i] = (bf16)fmaxf(acc[u][0][i] + bias0[i], 0.0f);
+        o[4 + i] = (bf16)fmaxf(acc[u][1][i] + bias1[i], 0.0f);
       }
+      const uint4 ov = __builtin_bit_cast(uint4, o);
+      *reinterpret_cast<uint2*>(out + q[u] * ASTR + 4 * grp) = make_uint2(ov.x, ov.y);
+      *reinterpret_cast<uint2*>(out + q[u] * ASTR + 16 + 4 * grp) = make_uint2(ov.z, ov.w);
     }
   }
 }
@@ -497,11 +525,24 @@ __global__ void __launch_bounds__(INFER_THREADS) infer_kernel(
     const int lane = tid & 63, wave = tid >> 6, grp = lane >> 4, n = lane & 15;
     const int64_t kh = (int64_t)LL * CH;
     f32x4 acc = {0, 0, 0, 0};
-    for (int st = wave; st < LL; st += INFER_WAVES) {
-      const bf16x8 a = n < nsm ? lds8(bufB + (n * LL + st) * ASTR + 8 * grp) : zero8();
-      // rows 7..15 of the padded head weights are zero: not read
-      const bf16x8 b = n < 7 ? load8(whb + (int64_t)n * kh + st * 32 + 8 * grp) : zero8();
-      acc = mfma(a, b, acc);
+    // eight of this chain's steps per trip: their weight loads (from L2) are
+    // all in flight before the first product; rows 7..15 of the padded head
+    // weights are zero and not read
+    for (int st0 = wave; st0 < LL; st0 += 8 * INFER_WAVES) {
+      bf16x8 bq[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int st = st0 + j * INFER_WAVES;
+        bq[j] = (st < LL && n < 7) ? load8(whb + (int64_t)n * kh + st * 32 + 8 * grp) : zero8();
+      }
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int st = st0 + j * INFER_WAVES;
+        if (st < LL) {
+          const bf16x8 a = n < nsm ? lds8(bufB + (n * LL + st) * ASTR + 8 * grp) : zero8();
+          acc = mfma(a, bq[j], acc);
+        }
+      }
     }
 #pragma unroll
     for (int i = 0; i < 4; ++i) part[wave * 256 + (4 * grp + i) * 16 + n] = acc[i];
