@@ -14,7 +14,8 @@ Modules
 geometry   planar code of distance L, supports, colours, logical lines (Sec. II)
 philox     Philox4x32-10 counter-based generator (Salmon et al., SC'11)
 tables     beta-bar (Eq. betaBar), temperature ladder, uint32 acceptance table
-sampler    depolarizing errors (Eq. pauliChannel), syndromes, true class
+sampler    depolarizing or independent bit/phase-flip errors (Eq. pauliChannel),
+           syndromes, true class
 init       one syndrome-consistent representative per logical class
 chains     colour-phased Metropolis chains (Sec. IV, Sec. IV.A, Sec. V)
 estimator  thermodynamic integration (Eq. main) and the class decision

@@ -12,6 +12,13 @@ qubits, is a sum over the support of
 The move is taken if Delta n <= 0, else with probability exp(-beta Delta n),
 realised as u < A[Delta n] with u a uniform 32-bit Philox word.
 
+Under independent bit/phase-flip noise (noise = 1) the energy is m, the
+number of x parts plus the number of z parts, and a move flips one part per
+qubit of its support, so
+    star:      Delta m = sum (1 - 2x)
+    plaquette: Delta m = sum (1 - 2z)
+with the same acceptance rule.
+
 Scan order (the paper draws a random stabilizer per step; its parallel version,
 Sec. V, probes one stabilizer in every region of group i mod 4 at step i): one
 sweep visits colour 0, 1, 2, 3 in turn and, within a colour, every site once in
@@ -33,11 +40,14 @@ import numpy as np
 from . import geometry, philox
 
 
-def delta_n(lat, state, s):
-    """int64 [T]: change in weight if site s were applied to each row of
+def delta_n(lat, state, s, noise=0):
+    """int64 [T]: change in energy if site s were applied to each row of
     `state` (uint8 [T, n_q])."""
     codes = state[:, lat.supports[s]].astype(np.int64)
     x, z = codes & 1, codes >> 1
+    if noise == 1:
+        part = x if lat.site_is_star[s] else z
+        return (1 - 2 * part).sum(axis=1)
     if lat.site_is_star[s]:
         return ((1 - z) * (1 - 2 * x)).sum(axis=1)
     return ((1 - x) * (1 - 2 * z)).sum(axis=1)
@@ -61,13 +71,14 @@ def _sweep_uniforms(lat, sweep, sid, ctr3, k0, k1):
 
 def run(lat, state, syndrome_id, cls, temp, chain, table, seed,
         sweep_begin, sweep_end, burn, n=None, S=None, A=None,
-        trace=False, check_invariants=False, syndromes=None):
+        trace=False, check_invariants=False, syndromes=None, noise=0):
     """Advance T independent chains over absolute sweeps [sweep_begin, sweep_end).
 
     state      uint8 [T, n_q] Pauli codes (modified copy is returned)
     syndrome_id, cls, temp, chain   [T] logical coordinates of each chain
     table      uint32 [T, 4] acceptance thresholds A[1..4] of each chain
-    n, S, A    carried-in weight / energy sum / accept count (None = fresh start)
+    n, S, A    carried-in energy / energy sum / accept count (None = fresh start)
+    noise      0 depolarizing (energy = weight), 1 bit/phase flips (x + z parts)
     Returns dict(state, n, S, A, trace) with trace int64 [T, 4*(end-begin)]
     (n after every phase) when requested.
     """
@@ -78,7 +89,8 @@ def run(lat, state, syndrome_id, cls, temp, chain, table, seed,
                              np.asarray(chain).reshape(T))
     k0, k1 = philox.seed_key(seed)
     thr = np.asarray(table, dtype=np.uint64).reshape(T, 4)
-    n = geometry.weight(state).astype(np.int64) if n is None else np.array(n, dtype=np.int64)
+    n = geometry.energy(state, noise).astype(np.int64) if n is None else \
+        np.array(n, dtype=np.int64)
     S = np.zeros(T, dtype=np.int64) if S is None else np.array(S, dtype=np.int64)
     A = np.zeros(T, dtype=np.int64) if A is None else np.array(A, dtype=np.int64)
     rows = np.arange(T)
@@ -91,7 +103,7 @@ def run(lat, state, syndrome_id, cls, temp, chain, table, seed,
         u = _sweep_uniforms(lat, sweep, sid, ctr3, k0, k1)
         for phase in range(4):
             for s in lat.phase_sites[phase]:
-                delta = delta_n(lat, state, s)
+                delta = delta_n(lat, state, s, noise)
                 ud = u[:, lat.draw_index[s]]
                 a_of_delta = thr[rows, np.clip(delta, 1, 4) - 1]
                 accept = (delta <= 0) | (ud < a_of_delta)
@@ -105,7 +117,8 @@ def run(lat, state, syndrome_id, cls, temp, chain, table, seed,
             if check_invariants:
                 assert np.array_equal(geometry.syndrome(lat, state), syn_ref), "syndrome changed"
                 assert np.array_equal(geometry.class_index(lat, state), cls_arr), "class changed"
-                assert np.array_equal(geometry.weight(state), n), "incremental n != recount"
+                assert np.array_equal(geometry.energy(state, noise), n), \
+                    "incremental n != recount"
 
     out = dict(state=state, n=n, S=S, A=A)
     if trace:

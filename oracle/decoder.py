@@ -19,7 +19,11 @@ INIT_MATCHING = 1
 
 
 def decode(L, syndromes, p, sweeps, seed, chains_per_class=1, n_temps=1, burn=0,
-           syndrome_ids=None, trace=False, check_invariants=False, init_mode=INIT_MATCHING):
+           syndrome_ids=None, trace=False, check_invariants=False, init_mode=INIT_MATCHING,
+           noise=tables.DEPOLARIZING, beta_scale=None):
+    """noise: tables.DEPOLARIZING (p = depolarizing rate) or tables.BITPHASE
+    (p = flip rate q of each part); beta_scale: beta*/beta_bar for K = 1
+    (None = the model's default)."""
     lat = geometry.Lattice(L)
     syn = np.asarray(syndromes, dtype=np.uint8).reshape(-1, lat.n_stab)
     syn = (syn != 0).astype(np.uint8)
@@ -29,7 +33,7 @@ def decode(L, syndromes, p, sweeps, seed, chains_per_class=1, n_temps=1, burn=0,
     K, C = int(n_temps), int(chains_per_class)
     if K != 1 and K % 2 != 0:
         raise ValueError("n_temps must be 1 or even")
-    tab = tables.tables(p, K)                                  # [K, 4]
+    tab = tables.tables(p, K, noise, beta_scale)              # [K, 4]
     start = init.matching_representatives if init_mode == INIT_MATCHING else init.representatives
     reps = np.stack([start(lat, syn[i]) for i in range(n)]) \
         if n else np.zeros((0, 4, lat.n_qubits), np.uint8)
@@ -42,21 +46,22 @@ def decode(L, syndromes, p, sweeps, seed, chains_per_class=1, n_temps=1, burn=0,
     res = chains.run(lat, state0, ids[si] if n else ids, ci, ki + 1, hi, tab[ki], seed,
                      0, burn + sweeps, burn, trace=trace,
                      check_invariants=check_invariants,
-                     syndromes=syn[si] if n else None)
+                     syndromes=syn[si] if n else None, noise=noise)
 
     shape = (n, 4, K, C)
     S = res["S"].reshape(shape)
     A = res["A"].reshape(shape)
     nf = res["n"].reshape(shape)
     states = res["state"].reshape(shape + (lat.n_qubits,))
-    bb = tables.beta_bar(p)
+    bb = tables.beta_bar(p, noise)
+    bs = tables.ladder(p, K, noise, beta_scale)[0] if K == 1 else bb
     prob = np.zeros((n, 4))
     mean = np.zeros((n, 4))
     key = np.zeros((n, 4), dtype=np.int64)
     chosen = np.zeros(n, dtype=np.int64)
     for i in range(n):
         prob[i], mean[i], key[i], chosen[i] = estimator.estimate(
-            S[i], nf[i], C, sweeps, bb, lat.n_qubits, lat.n_stab)
+            S[i], nf[i], C, sweeps, bb, lat.n_qubits, lat.n_stab, noise, bs)
     correction = states[np.arange(n), chosen, K - 1, 0] if n else \
         np.zeros((0, lat.n_qubits), np.uint8)
     out = dict(class_prob=prob, mean_n=mean, sum_n=S, accepts=A, n_final=nf, key=key,

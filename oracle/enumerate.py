@@ -12,6 +12,9 @@ and n = popcount(x | z).  The weight histogram h_E[n] gives Z_E(beta),
 <n>_{beta,E} and P(E) = Z_E(beta_bar) / sum_E' Z_E'(beta_bar) exactly.
 Feasible for L <= 4 (2^12 x 2^12 pairs per class at L = 4).
 
+With noise = 1 (independent bit/phase flips) the energy is
+popcount(x) + popcount(z) instead, histogrammed over 0..2 n_q.
+
 `brute_force_histograms` is an independent route to the same numbers: it runs
 over all 4^n_q Pauli errors, groups them by (syndrome, class) and histograms
 their weights.  It uses neither the representatives nor the stabilizer span.
@@ -39,28 +42,35 @@ def _span(generators):
     return arr
 
 
-def class_histograms(lat, syn):
-    """int64 [4, n_q + 1]: number of class-E configurations of each weight."""
+def class_histograms(lat, syn, noise=0):
+    """int64 [4, n_q + 1] (noise 0) or [4, 2 n_q + 1] (noise 1): number of
+    class-E configurations of each energy."""
     if lat.n_qubits > 63:
         raise ValueError("enumeration limited to n_q <= 63")
     stars = [_mask(lat.supports[s]) for s in range(lat.n_stars)]
     plaqs = [_mask(lat.supports[s]) for s in range(lat.n_stars, lat.n_stab)]
     xs0, zs0 = _span(stars), _span(plaqs)
     reps = init.representatives(lat, np.asarray(syn, dtype=np.uint8))
-    hist = np.zeros((4, lat.n_qubits + 1), dtype=np.int64)
+    nb = (2 * lat.n_qubits if noise == 1 else lat.n_qubits) + 1
+    hist = np.zeros((4, nb), dtype=np.int64)
     for e in range(4):
         xr = _mask(np.nonzero(reps[e] & 1)[0])
         zr = _mask(np.nonzero(reps[e] & 2)[0])
         zs = zs0 ^ np.uint64(zr)
+        zc = np.bitwise_count(zs).astype(np.int64)
         for x in (xs0 ^ np.uint64(xr)):
-            w = np.bitwise_count(zs | x).astype(np.int64)
-            hist[e] += np.bincount(w, minlength=lat.n_qubits + 1)
+            if noise == 1:
+                w = zc + int(np.bitwise_count(x))
+            else:
+                w = np.bitwise_count(zs | x).astype(np.int64)
+            hist[e] += np.bincount(w, minlength=nb)
     return hist
 
 
-def brute_force_histograms(lat):
+def brute_force_histograms(lat, noise=0):
     """int64 [2^n_stab, 4, n_q + 1] over all 4^n_q errors, indexed by the
-    syndrome read as a little-endian bit string in site order."""
+    syndrome read as a little-endian bit string in site order; with noise = 1
+    the last axis is x-part count + z-part count, 0..2 n_q."""
     nq = lat.n_qubits
     if nq > 13:
         raise ValueError("brute force limited to n_q <= 13")
@@ -80,10 +90,14 @@ def brute_force_histograms(lat):
     bz = (np.bitwise_count(allv & np.uint64(_mask(lat.row0))) & 1).astype(np.int64)
     bx = (np.bitwise_count(allv & np.uint64(_mask(lat.column0))) & 1).astype(np.int64)
     n_syn = 1 << lat.n_stab
-    hist = np.zeros((n_syn, 4, nq + 1), dtype=np.int64)
-    nb = nq + 1
+    nb = (2 * nq if noise == 1 else nq) + 1
+    hist = np.zeros((n_syn, 4, nb), dtype=np.int64)
+    zcount = np.bitwise_count(allv).astype(np.int64)
     for x in range(1 << nq):
-        w = np.bitwise_count(allv | np.uint64(x)).astype(np.int64)
+        if noise == 1:
+            w = zcount + bin(x).count("1")
+        else:
+            w = np.bitwise_count(allv | np.uint64(x)).astype(np.int64)
         syn_idx = star_syn | (int(plaq_syn[x]) << n_st)
         cls = int(bx[x]) + 2 * bz
         flat = (syn_idx * 4 + cls) * nb + w

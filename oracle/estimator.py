@@ -10,6 +10,15 @@ Sec. IV.A: as beta -> 0 every qubit is I, X, Y, Z with probability 1/4, so
   counted sweep it is the mean current weight of the chains.
 * K = 1 (single temperature, beta* = beta_bar): trapezoid on {0, beta_bar},
   I_E = (beta_bar / 2) (f0 + <n>_{E,1}).
+* K = 1 with beta* below beta_bar (the bit/phase-flip model's beta* =
+  0.85 beta_bar): the paper does not say how to integrate past the one
+  sampled temperature; here the trapezoid covers [0, beta*] and <n> is held
+  at its beta* value on [beta*, beta_bar]:
+  I_E = (beta* / 2)(f0 + <n>_{E,1}) + (beta_bar - beta*) <n>_{E,1},
+  which is the plain trapezoid when beta* = beta_bar.
+* Independent bit/phase flips: n is the number of x parts plus z parts, and
+  at beta -> 0 each of the 2 n_q parts is set with probability 1/2, so
+  f0 = n_q.
 * K even (the paper's equidistant temperatures with Simpson's rule):
   h = beta_bar / K, I_E = (h / 3)(f0 + 4 f1 + 2 f2 + ... + 4 f_{K-1} + f_K),
   accumulated in ascending k.
@@ -32,14 +41,16 @@ def simpson_weights(K):
     return [4 if k % 2 == 1 else 2 for k in range(1, K)] + [1]
 
 
-def estimate(S, n_final, chains, sweeps, beta_bar, n_q, n_stab):
-    return estimate_log_z(S, n_final, chains, sweeps, beta_bar, n_q, n_stab)[:4]
+def estimate(S, n_final, chains, sweeps, beta_bar, n_q, n_stab, noise=0, beta_star=None):
+    return estimate_log_z(S, n_final, chains, sweeps, beta_bar, n_q, n_stab, noise,
+                          beta_star)[:4]
 
 
-def estimate_log_z(S, n_final, chains, sweeps, beta_bar, n_q, n_stab):
+def estimate_log_z(S, n_final, chains, sweeps, beta_bar, n_q, n_stab, noise=0, beta_star=None):
     """S, n_final: int64 [4, K, chains] for one syndrome.
 
-    Returns (class_prob [4], mean_n [4] at beta_bar, key [4] int, chosen int);
+    Returns (class_prob [4], mean_n [4] at the last temperature (beta_bar, or
+    beta* for K = 1), key [4] int, chosen int);
     `estimate_log_z` returns the four log Z_E as well.
     """
     S = np.asarray(S, dtype=np.int64)
@@ -50,11 +61,12 @@ def estimate_log_z(S, n_final, chains, sweeps, beta_bar, n_q, n_stab):
     sums = src.sum(axis=2)                                     # [4, K] exact int
     denom = float(chains * T) if T > 0 else float(chains)
     mean = [[float(sums[e, k]) / denom for k in range(K)] for e in range(4)]
-    f0 = 0.75 * n_q
+    f0 = float(n_q) if noise == 1 else 0.75 * n_q
+    bs = beta_bar if beta_star is None else beta_star
     logz = []
     for e in range(4):
         if K == 1:
-            integral = (beta_bar / 2.0) * (f0 + mean[e][0])
+            integral = (bs / 2.0) * (f0 + mean[e][0]) + (beta_bar - bs) * mean[e][0]
         else:
             h = beta_bar / K
             acc = f0

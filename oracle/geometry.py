@@ -132,6 +132,19 @@ def weight(codes):
     return (np.asarray(codes) != 0).sum(axis=-1)
 
 
+def flip_count(codes):
+    """Number of bit flips plus phase flips (x parts + z parts; Y counts
+    twice): the energy of the independent bit/phase-flip model."""
+    codes = np.asarray(codes).astype(np.int64)
+    return pauli_x(codes).sum(axis=-1) + pauli_z(codes).sum(axis=-1)
+
+
+def energy(codes, noise):
+    """The chain energy of a noise model: weight (0, depolarizing) or
+    flip_count (1, independent bit/phase flips)."""
+    return flip_count(codes) if noise == 1 else weight(codes)
+
+
 def syndrome(lat, codes):
     """Anyon configuration of an error (Sec. II).
 
