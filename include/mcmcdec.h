@@ -35,6 +35,12 @@
  *  Accept    Delta n <= 0, or u < A_k[Delta n] with
  *            A_k[D] = floor(2^32 exp(-beta_k D)), beta_k = k*beta_bar/K,
  *            beta_bar = -log((p/3)/(1-p)) (Eq. betaBar, Sec. IV).
+ *  Noise     depolarizing (default): n = number of non-identity qubits.
+ *            Independent bit/phase flips (Eq. pauliChannel with
+ *            p_b = p_p = p, Sec. IV.A's last paragraph): n = number of x
+ *            parts + number of z parts (Y counts twice), beta_bar =
+ *            log((1-p)/p), and the single temperature beta* = 0.85 beta_bar
+ *            unless the caller sets another scale.
  *
  * Pointers
  * --------
@@ -77,6 +83,11 @@ enum mcmc_status {
 #define MCMC_CHAINS_MAX (1 << 20)
 #define MCMC_SWEEPS_MAX (1 << 28)
 
+/* noise models (mcmc_params.noise) */
+#define MCMC_NOISE_DEPOLARIZING 0u /* X, Y, Z with p/3 each; 0 < p < 0.75        */
+#define MCMC_NOISE_BITPHASE 1u     /* x part and z part each with p,
+                                      independently; 0 < p < 0.5               */
+
 /* flags */
 #define MCMC_TRACE 1u  /* write n after every colour phase to d_trace          */
 #define MCMC_RESUME 2u /* start from d_chain_state instead of the class starts */
@@ -100,16 +111,24 @@ typedef struct mcmc_params {
   int32_t sweep_begin; /* with MCMC_RESUME: first absolute sweep of this call
                           (the state in d_chain_state is the one after sweep
                           sweep_begin-1); must be 0 otherwise                   */
-  double p;            /* depolarizing rate, 0 < p < 0.75 (beta_bar > 0)        */
+  double p;            /* error rate of the noise model (beta_bar > 0)          */
   uint64_t seed;       /* Philox key                                            */
   uint32_t flags;      /* MCMC_TRACE | MCMC_RESUME                              */
   uint32_t init;       /* MCMC_INIT_CANONICAL or MCMC_INIT_MATCHING             */
+  uint32_t noise;      /* MCMC_NOISE_DEPOLARIZING (0) or MCMC_NOISE_BITPHASE    */
+  uint32_t reserved;   /* must be 0                                             */
+  double beta_scale;   /* K = 1: beta* = beta_scale * beta_bar, in (0, 4];
+                          0 selects the model's default (1 depolarizing, 0.85
+                          bit/phase flips).  K > 1: must be 0 or 1 (the ladder
+                          runs to beta_bar).  With beta* < beta_bar the
+                          estimator integrates the trapezoid over [0, beta*]
+                          and holds <n> at its beta* value up to beta_bar.   */
 } mcmc_params;
 
 /* Human-readable name of a status code (static string). */
 const char* mcmc_strerror(int status);
 
-/* ABI version of this header: 0x00010000 for 1.0. */
+/* ABI version of this header: 0x00010100 for 1.1. */
 int32_t mcmc_abi_version(void);
 
 /* n_q and n_stab of a distance-L code (Sec. II: n_stab = 2L(L-1),
@@ -127,6 +146,11 @@ int mcmc_lattice(int32_t L, int32_t* h_supports, int32_t* h_colour, int32_t* h_d
  * Sec. IV).  ERANGE if p is outside (0, 0.75) or n_temps outside 1..64. */
 int mcmc_acceptance_table(double p, int32_t n_temps, uint32_t* h_table);
 
+/* The thresholds a decode with *h_prm uses: [n_temps][4] for its noise
+ * model, rate and beta_scale (beta_k = k beta_bar/K, or beta* for K = 1).
+ * Same errors as mcmc_workspace_size for the parameters it reads. */
+int mcmc_params_table(const mcmc_params* h_prm, uint32_t* h_table);
+
 /* Bytes of device workspace mcmc_decode_batch needs for n syndromes. */
 int mcmc_workspace_size(const mcmc_params* h_prm, int64_t n, size_t* h_bytes);
 
@@ -141,8 +165,10 @@ int mcmc_chain_state_size(const mcmc_params* h_prm, int64_t n, size_t* h_bytes);
  *  d_syndrome_ids[n] uint32 Philox counter word 2, NULL => i (required to be
  *                distinct for independent chains across calls)
  *  d_class_prob  [n][4] double   estimated P(E) (Eq. main with the closed-form
- *                beta=0 endpoint; trapezoid for K=1, Simpson for even K)
- *  d_mean_n      [n][4] double   pooled <n> at beta_bar (k = K)
+ *                beta=0 endpoint, 3/4 n_q depolarizing or n_q bit/phase;
+ *                trapezoid for K=1, Simpson for even K)
+ *  d_mean_n      [n][4] double   pooled <n> at the highest temperature index
+ *                (beta_bar for K > 1, beta* for K = 1)
  *  d_sum_n       [n][4][K][chains] int64  sum of n after every counted colour
  *                phase, or NULL
  *  d_accepts     [n][4][K][chains] int64  accepted moves (burn-in included), or NULL
@@ -177,7 +203,8 @@ int mcmc_init_representatives(int32_t L, uint32_t init, const uint8_t* d_syndrom
                               uint8_t* d_reps, void* stream);
 
 /* Unpack a chain-state buffer into d_states [n][4][K][chains][n_q] uint8 and
- * d_weights [n][4][K][chains] int32 (either may be NULL). */
+ * d_weights [n][4][K][chains] int32, each chain's energy n under the noise
+ * model of *h_prm (either pointer may be NULL). */
 int mcmc_unpack_chain_state(const mcmc_params* h_prm, int64_t n, const void* d_chain_state,
                             uint8_t* d_states, int32_t* d_weights, void* stream);
 
@@ -192,6 +219,16 @@ int mcmc_unpack_chain_state(const mcmc_params* h_prm, int64_t n, const void* d_c
 int mcmc_sample_errors(int32_t L, double p, uint64_t seed, const uint32_t* d_sample_ids,
                        uint32_t id_base, int64_t n, uint8_t* d_syndromes, uint8_t* d_true_class,
                        uint8_t* d_errors, void* stream);
+
+/* The same for a chosen noise model.  MCMC_NOISE_DEPOLARIZING is
+ * mcmc_sample_errors.  MCMC_NOISE_BITPHASE (Eq. pauliChannel with
+ * p_b = p_p = p, 0 < p < 0.5): the same two words, x part iff
+ * u0 < floor(p 2^32), z part iff u1 < floor(p 2^32).  EINVAL for another
+ * model. */
+int mcmc_sample_errors_model(int32_t L, uint32_t noise, double p, uint64_t seed,
+                             const uint32_t* d_sample_ids, uint32_t id_base, int64_t n,
+                             uint8_t* d_syndromes, uint8_t* d_true_class, uint8_t* d_errors,
+                             void* stream);
 
 /*
  * Mixed batches (syndromes of different L, p, sweep budget, chains and

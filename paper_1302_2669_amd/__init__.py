@@ -10,13 +10,15 @@ import ctypes
 import numpy as np
 
 from . import _lib
-from ._lib import (MCMC_INIT_CANONICAL, MCMC_INIT_MATCHING, MCMC_L_MAX, MCMC_L_MIN, MCMC_RESUME,
-                   MCMC_TRACE, McmcError, Params)
+from ._lib import (MCMC_INIT_CANONICAL, MCMC_INIT_MATCHING, MCMC_L_MAX, MCMC_L_MIN,
+                   MCMC_NOISE_BITPHASE, MCMC_NOISE_DEPOLARIZING, MCMC_RESUME, MCMC_TRACE,
+                   McmcError, Params)
 
 __all__ = ["Params", "McmcError", "geometry", "lattice", "acceptance_table", "workspace_size",
            "chain_state_size", "decode_batch", "sample_errors", "init_representatives",
            "unpack_chain_state", "MCMC_TRACE", "MCMC_RESUME", "MCMC_L_MIN", "MCMC_L_MAX",
-           "MCMC_INIT_CANONICAL", "MCMC_INIT_MATCHING", "MixedPlan"]
+           "MCMC_INIT_CANONICAL", "MCMC_INIT_MATCHING", "MCMC_NOISE_DEPOLARIZING",
+           "MCMC_NOISE_BITPHASE", "params_table", "MixedPlan"]
 
 
 def _torch():
@@ -66,10 +68,20 @@ def acceptance_table(p, n_temps=1):
 
 
 def make_params(L, p, sweeps, seed, chains=1, n_temps=1, burn=0, sweep_begin=0, flags=0,
-                init=MCMC_INIT_MATCHING):
+                init=MCMC_INIT_MATCHING, noise=MCMC_NOISE_DEPOLARIZING, beta_scale=0.0):
+    """beta_scale 0 selects the noise model's default beta*/beta_bar."""
     return Params(L=int(L), n_temps=int(n_temps), chains=int(chains), burn=int(burn),
                   sweeps=int(sweeps), sweep_begin=int(sweep_begin), p=float(p),
-                  seed=int(seed) & ((1 << 64) - 1), flags=int(flags), init=int(init))
+                  seed=int(seed) & ((1 << 64) - 1), flags=int(flags), init=int(init),
+                  noise=int(noise), reserved=0, beta_scale=float(beta_scale))
+
+
+def params_table(prm):
+    """[n_temps, 4] uint32 thresholds a decode with these Params uses."""
+    out = np.zeros((prm.n_temps, 4), dtype=np.uint32)
+    _lib.check(_lib._lib().mcmc_params_table(ctypes.byref(prm), out.ctypes.data),
+               "mcmc_params_table")
+    return out
 
 
 def workspace_size(prm, n):
@@ -88,8 +100,12 @@ def chain_state_size(prm, n):
 
 def decode_batch(syndromes, L, p, sweeps, seed, chains=1, n_temps=1, burn=0, syndrome_ids=None,
                  want_sums=False, want_correction=True, trace=False, chain_state=None,
-                 resume_from=None, workspace=None, init=MCMC_INIT_MATCHING):
-    """Decode a [n, n_stab] uint8 device tensor of syndromes.
+                 resume_from=None, workspace=None, init=MCMC_INIT_MATCHING,
+                 noise=MCMC_NOISE_DEPOLARIZING, beta_scale=0.0):
+    """Decode a [n, n_stab] uint8 device tensor of syndromes.  `noise` picks
+    the error model p refers to (depolarizing, or independent bit/phase flips
+    of rate p per part); `beta_scale` sets beta*/beta_bar for n_temps = 1
+    (0: the model's default).
 
     Returns a dict of device tensors: class_prob [n,4] f64, mean_n [n,4] f64,
     chosen [n] u8, and when requested correction [n,n_q] u8, sum_n/accepts
@@ -106,7 +122,8 @@ def decode_batch(syndromes, L, p, sweeps, seed, chains=1, n_temps=1, burn=0, syn
     syndromes = syndromes.contiguous()
     flags = (_lib.MCMC_TRACE if trace else 0) | (_lib.MCMC_RESUME if resume_from is not None else 0)
     begin = 0 if resume_from is None else int(resume_from[1])
-    prm = make_params(L, p, sweeps, seed, chains, n_temps, burn, begin, flags, init)
+    prm = make_params(L, p, sweeps, seed, chains, n_temps, burn, begin, flags, init, noise,
+                      beta_scale)
     out = {
         "class_prob": torch.empty((n, 4), dtype=torch.float64, device=dev),
         "mean_n": torch.empty((n, 4), dtype=torch.float64, device=dev),
@@ -141,18 +158,21 @@ def decode_batch(syndromes, L, p, sweeps, seed, chains=1, n_temps=1, burn=0, syn
     return out
 
 
-def sample_errors(L, p, seed, n, device="cuda", id_base=0, sample_ids=None, want_errors=False):
-    """Depolarizing samples: (syndromes [n,n_stab] u8, true_class [n] u8, errors or None)."""
+def sample_errors(L, p, seed, n, device="cuda", id_base=0, sample_ids=None, want_errors=False,
+                  noise=MCMC_NOISE_DEPOLARIZING):
+    """Samples of the noise model: (syndromes [n,n_stab] u8, true_class [n] u8,
+    errors [n,n_q] u8 or None)."""
     torch = _torch()
     nq, ns = geometry(L)
     syn = torch.empty((n, ns), dtype=torch.uint8, device=device)
     cls = torch.empty((n,), dtype=torch.uint8, device=device)
     err = torch.empty((n, nq), dtype=torch.uint8, device=device) if want_errors else None
     ids = None if sample_ids is None else sample_ids.to(device=device, dtype=torch.int32).contiguous()
-    st = _lib._lib().mcmc_sample_errors(int(L), float(p), int(seed) & ((1 << 64) - 1), _ptr(ids),
-                                        int(id_base), int(n), _ptr(syn), _ptr(cls), _ptr(err),
-                                        _stream(syn.device))
-    _lib.check(st, "mcmc_sample_errors")
+    st = _lib._lib().mcmc_sample_errors_model(int(L), int(noise), float(p),
+                                              int(seed) & ((1 << 64) - 1), _ptr(ids), int(id_base),
+                                              int(n), _ptr(syn), _ptr(cls), _ptr(err),
+                                              _stream(syn.device))
+    _lib.check(st, "mcmc_sample_errors_model")
     return syn, cls, err
 
 
@@ -167,10 +187,11 @@ def init_representatives(syndromes, L, init=MCMC_INIT_MATCHING):
     return reps
 
 
-def unpack_chain_state(chain_state, n, L, p, sweeps, seed, chains=1, n_temps=1, burn=0):
+def unpack_chain_state(chain_state, n, L, p, sweeps, seed, chains=1, n_temps=1, burn=0,
+                       noise=MCMC_NOISE_DEPOLARIZING):
     torch = _torch()
     nq, _ = geometry(L)
-    prm = make_params(L, p, sweeps, seed, chains, n_temps, burn)
+    prm = make_params(L, p, sweeps, seed, chains, n_temps, burn, noise=noise)
     states = torch.empty((n, 4, n_temps, chains, nq), dtype=torch.uint8, device=chain_state.device)
     weights = torch.empty((n, 4, n_temps, chains), dtype=torch.int32, device=chain_state.device)
     st = _lib._lib().mcmc_unpack_chain_state(ctypes.byref(prm), int(n), _ptr(chain_state),

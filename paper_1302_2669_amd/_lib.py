@@ -18,6 +18,7 @@ MCMC_L_MIN, MCMC_L_MAX = 2, 25
 MCMC_TEMPS_MAX = 64
 MCMC_TRACE, MCMC_RESUME = 1, 2
 MCMC_INIT_CANONICAL, MCMC_INIT_MATCHING = 0, 1
+MCMC_NOISE_DEPOLARIZING, MCMC_NOISE_BITPHASE = 0, 1
 MCMC_CNN_BATCH_MAX = 1 << 24
 
 
@@ -39,6 +40,9 @@ class Params(ctypes.Structure):
         ("seed", ctypes.c_uint64),
         ("flags", ctypes.c_uint32),
         ("init", ctypes.c_uint32),
+        ("noise", ctypes.c_uint32),
+        ("reserved", ctypes.c_uint32),
+        ("beta_scale", ctypes.c_double),
     ]
 
 
@@ -96,6 +100,7 @@ _SIGNATURES = {
     "mcmc_geometry": (ctypes.c_int, [_I32, _PI32, _PI32]),
     "mcmc_lattice": (ctypes.c_int, [_I32, _P, _P, _P]),
     "mcmc_acceptance_table": (ctypes.c_int, [_D, _I32, _P]),
+    "mcmc_params_table": (ctypes.c_int, [_PPRM, _P]),
     "mcmc_workspace_size": (ctypes.c_int, [_PPRM, _I64, _PSZ]),
     "mcmc_chain_state_size": (ctypes.c_int, [_PPRM, _I64, _PSZ]),
     "mcmc_decode_batch": (ctypes.c_int, [_P, _P, _I64, _PPRM, _P, _P, _P, _P, _P, _P, _P, _P,
@@ -103,6 +108,8 @@ _SIGNATURES = {
     "mcmc_init_representatives": (ctypes.c_int, [_I32, _U32, _P, _I64, _P, _P]),
     "mcmc_unpack_chain_state": (ctypes.c_int, [_PPRM, _I64, _P, _P, _P, _P]),
     "mcmc_sample_errors": (ctypes.c_int, [_I32, _D, _U64, _P, _U32, _I64, _P, _P, _P, _P]),
+    "mcmc_sample_errors_model": (ctypes.c_int,
+                                 [_I32, _U32, _D, _U64, _P, _U32, _I64, _P, _P, _P, _P]),
     "mcmc_plan_create": (ctypes.c_int, [ctypes.POINTER(Item), _I64, _U64, _U32,
                                         ctypes.POINTER(_P)]),
     "mcmc_plan_destroy": (ctypes.c_int, [_P]),

@@ -41,6 +41,17 @@ ChainStateLayout chain_state_layout(int L, int64_t T) {
 }
 
 hipError_t launch_chains(int range, const RunArgs& a, int waves, int wg, hipStream_t s) {
+  if (a.noise == MCMC_NOISE_BITPHASE) {
+    switch (range) {
+      case 0: return launch_chains_flip_range<0>(a, waves, wg, s);
+      case 1: return launch_chains_flip_range<1>(a, waves, wg, s);
+      case 2: return launch_chains_flip_range<2>(a, waves, wg, s);
+      case 3: return launch_chains_flip_range<3>(a, waves, wg, s);
+      case 4: return launch_chains_flip_range<4>(a, waves, wg, s);
+      default: return hipErrorInvalidValue;
+    }
+  }
+  if (a.noise != MCMC_NOISE_DEPOLARIZING) return hipErrorInvalidValue;
   switch (range) {
     case 0: return launch_chains_range<0>(a, waves, wg, s);
     case 1: return launch_chains_range<1>(a, waves, wg, s);
@@ -61,9 +72,15 @@ int check_params(const mcmc_params* prm, int64_t n) {
   if (!prm) return MCMC_EINVAL;
   if (n < 0) return MCMC_ERANGE;
   if (!valid_L(prm->L)) return MCMC_ERANGE;
-  if (!valid_p(prm->p)) return MCMC_ERANGE;
+  if (!valid_noise(prm->noise) || prm->reserved != 0) return MCMC_EINVAL;
+  if (!valid_rate(prm->noise, prm->p)) return MCMC_ERANGE;
   if (prm->n_temps < 1 || prm->n_temps > MCMC_TEMPS_MAX) return MCMC_ERANGE;
   if (prm->n_temps != 1 && (prm->n_temps % 2) != 0) return MCMC_EINVAL;
+  if (prm->n_temps == 1) {
+    if (!(prm->beta_scale >= 0.0 && prm->beta_scale <= 4.0)) return MCMC_ERANGE;  // NaN too
+  } else if (prm->beta_scale != 0.0 && prm->beta_scale != 1.0) {
+    return MCMC_ERANGE;
+  }
   if (prm->chains < 1 || prm->chains > MCMC_CHAINS_MAX) return MCMC_ERANGE;
   if (prm->burn < 0 || prm->sweeps < 0) return MCMC_ERANGE;
   if ((int64_t)prm->burn + prm->sweeps > MCMC_SWEEPS_MAX) return MCMC_ERANGE;
@@ -117,7 +134,7 @@ const char* mcmc_strerror(int status) {
   }
 }
 
-int32_t mcmc_abi_version(void) { return 0x00010000; }
+int32_t mcmc_abi_version(void) { return 0x00010100; }
 
 int mcmc_geometry(int32_t L, int32_t* n_qubits, int32_t* n_stab) {
   if (!valid_L(L)) return MCMC_ERANGE;
@@ -162,6 +179,14 @@ int mcmc_acceptance_table(double p, int32_t n_temps, uint32_t* table) {
   if (!table) return MCMC_EINVAL;
   if (!valid_p(p) || n_temps < 1 || n_temps > MCMC_TEMPS_MAX) return MCMC_ERANGE;
   fill_table(p, n_temps, table);
+  return MCMC_OK;
+}
+
+int mcmc_params_table(const mcmc_params* prm, uint32_t* table) {
+  if (!table) return MCMC_EINVAL;
+  const int st = check_params(prm, 0);
+  if (st != MCMC_OK) return st;
+  fill_params_table(prm, table);
   return MCMC_OK;
 }
 
@@ -222,6 +247,7 @@ int mcmc_decode_batch(const uint8_t* syndromes, const uint32_t* syndrome_ids, in
     sa.L = L;
     sa.rows = init_rows;
     sa.weights = init_n;
+    sa.noise = (int32_t)prm->noise;
     st = hip_status(prm->init == MCMC_INIT_MATCHING ? launch_init_matching(sa, s)
                                                     : launch_init(sa, s));
     if (st != MCMC_OK) return st;
@@ -238,7 +264,8 @@ int mcmc_decode_batch(const uint8_t* syndromes, const uint32_t* syndrome_ids, in
   a.g0.n_items = (int32_t)n;
   a.g0.n_tasks = T;
   a.syndrome_ids = syndrome_ids;
-  fill_table(prm->p, prm->n_temps, &a.table0[0][0]);
+  fill_params_table(prm, &a.table0[0][0]);
+  a.noise = (int32_t)prm->noise;
   a.n_tiles = (T + TILE - 1) / TILE;
   a.queue = queue;
   a.lmin = a.lmax = L;
@@ -285,7 +312,9 @@ int mcmc_decode_batch(const uint8_t* syndromes, const uint32_t* syndrome_ids, in
 
   DecideArgs d{};
   d.g0 = a.g0;
-  d.beta_bar = beta_bar(prm->p);
+  d.beta_bar = beta_bar_of(prm->noise, prm->p);
+  d.beta_star = beta_top(prm);
+  d.noise = (int32_t)prm->noise;
   d.ln2 = log(2.0);
   d.n = n;
   d.S = S;
@@ -322,21 +351,31 @@ int mcmc_unpack_chain_state(const mcmc_params* prm, int64_t n, const void* chain
   if (!chain_state) return MCMC_EINVAL;
   const int64_t T = n * 4 * (int64_t)prm->n_temps * prm->chains;
   const ChainStateLayout cl = chain_state_layout(prm->L, T);
-  return hip_status(launch_unpack(prm->L, (const uint32_t*)((const char*)chain_state + cl.rows),
-                                        T, T, states, weights, (hipStream_t)stream));
+  return hip_status(launch_unpack(prm->L, (int)prm->noise,
+                                  (const uint32_t*)((const char*)chain_state + cl.rows), T, T,
+                                  states, weights, (hipStream_t)stream));
+}
+
+int mcmc_sample_errors_model(int32_t L, uint32_t noise, double p, uint64_t seed,
+                             const uint32_t* sample_ids, uint32_t id_base, int64_t n,
+                             uint8_t* syndromes, uint8_t* true_class, uint8_t* errors,
+                             void* stream) {
+  if (!valid_noise(noise)) return MCMC_EINVAL;
+  if (!valid_L(L) || !valid_rate(noise, p) || n < 0) return MCMC_ERANGE;
+  if (n == 0) return MCMC_OK;
+  if (!syndromes || !true_class) return MCMC_EINVAL;
+  if (n > 0x7FFFFFFF) return MCMC_ERANGE;
+  const uint32_t thr = (uint32_t)floor(ldexp(p, 32));
+  return hip_status(launch_sample(L, (int)noise, thr, (uint32_t)(seed & 0xFFFFFFFFull),
+                                  (uint32_t)(seed >> 32), sample_ids, id_base, n, syndromes,
+                                  true_class, errors, (hipStream_t)stream));
 }
 
 int mcmc_sample_errors(int32_t L, double p, uint64_t seed, const uint32_t* sample_ids,
                        uint32_t id_base, int64_t n, uint8_t* syndromes, uint8_t* true_class,
                        uint8_t* errors, void* stream) {
-  if (!valid_L(L) || !valid_p(p) || n < 0) return MCMC_ERANGE;
-  if (n == 0) return MCMC_OK;
-  if (!syndromes || !true_class) return MCMC_EINVAL;
-  if (n > 0x7FFFFFFF) return MCMC_ERANGE;
-  const uint32_t thr = (uint32_t)floor(ldexp(p, 32));
-  return hip_status(launch_sample(L, thr, (uint32_t)(seed & 0xFFFFFFFFull),
-                                        (uint32_t)(seed >> 32), sample_ids, id_base, n, syndromes,
-                                        true_class, errors, (hipStream_t)stream));
+  return mcmc_sample_errors_model(L, MCMC_NOISE_DEPOLARIZING, p, seed, sample_ids, id_base, n,
+                                  syndromes, true_class, errors, stream);
 }
 
 }  // extern "C"

@@ -23,6 +23,13 @@
 //
 // Accumulation: n after every colour phase of a counted sweep is added to S
 // (int64); A counts accepted moves.  No cross-lane reduction is needed.
+//
+// Noise models (template parameter NOISE): 0 = depolarizing, n = number of
+// non-identity qubits (the c above); 1 = independent bit/phase flips, n =
+// number of x parts + z parts, so a star qubit contributes c = 2[x = 0] and a
+// plaquette qubit c = 2[z = 0].  Under NOISE 1 the padding Y of a row end
+// would read as c = 0, so the one padded field a star reads (the east end of
+// its odd row) is forced to c = 1 there.
 #pragma once
 
 #include "device_common.h"
@@ -39,6 +46,21 @@ __device__ __forceinline__ uint32_t c_plaq(uint32_t v) {
   const uint32_t x = v & 0x55555555u;
   const uint32_t id = ~(v | (v >> 1)) & 0x55555555u;
   return (id << 1) | x;
+}
+
+// Independent bit/phase flips: c = 2[x = 0] (star), 2[z = 0] (plaquette).
+__device__ __forceinline__ uint32_t c_star_flip(uint32_t v) { return ~(v << 1) & 0xAAAAAAAAu; }
+__device__ __forceinline__ uint32_t c_plaq_flip(uint32_t v) { return ~v & 0xAAAAAAAAu; }
+
+template <int NOISE>
+__device__ __forceinline__ uint32_t c_star_of(uint32_t v) {
+  if constexpr (NOISE == 1) return c_star_flip(v);
+  else return c_star(v);
+}
+template <int NOISE>
+__device__ __forceinline__ uint32_t c_plaq_of(uint32_t v) {
+  if constexpr (NOISE == 1) return c_plaq_flip(v);
+  else return c_plaq(v);
 }
 
 // Sum of the eight nibbles of v.
@@ -131,7 +153,7 @@ __device__ __forceinline__ ItemDesc item_of(const RunArgs& a, int64_t idx, int R
 
 // One chain (lane) of group g: task t of the group.  lds_tbl is this
 // workgroup's threshold table, column `col` belongs to this lane.
-template <int L>
+template <int L, int NOISE>
 __device__ __forceinline__ void run_chain(const RunArgs& a, const GroupDesc& g, int64_t t,
                                           uint32_t (*lds_tbl)[256], const int col) {
   using G = Geo<L>;
@@ -264,11 +286,15 @@ __device__ __forceinline__ void run_chain(const RunArgs& a, const GroupDesc& g, 
         constexpr int nsite = (L - par + 1) / 2;
         constexpr int rank0 = star_row_rank<L>(i, phi);
         uint32_t cO[W], sum[W], acc[W];
-        static_for<W>([&](auto WW) { cO[decltype(WW)::value] = c_star(st[2 * i + 1][decltype(WW)::value]); });
         static_for<W>([&](auto WW) {
           constexpr int w = decltype(WW)::value;
-          const uint32_t cN = c_star(st[2 * i][w]);
-          const uint32_t cS = c_star(st[2 * i + 2][w]);
+          cO[w] = c_star_of<NOISE>(st[2 * i + 1][w]);
+          if constexpr (NOISE == 1) cO[w] |= 0x55555555u & ~field_mask(L - 1, w);  // pad: c = 1
+        });
+        static_for<W>([&](auto WW) {
+          constexpr int w = decltype(WW)::value;
+          const uint32_t cN = c_star_of<NOISE>(st[2 * i][w]);
+          const uint32_t cS = c_star_of<NOISE>(st[2 * i + 2][w]);
           uint32_t cWest;
           if constexpr (w == 0) cWest = (cO[0] << 2) | 1u;
           else cWest = (cO[w] << 2) | (cO[w - 1] >> 30);
@@ -304,12 +330,12 @@ __device__ __forceinline__ void run_chain(const RunArgs& a, const GroupDesc& g, 
         constexpr int rank0 = plaq_row_rank<L>(i, phi - 2);
         if constexpr (nsite > 0) {
           uint32_t cE[W], sum[W], acc[W];
-          static_for<W>([&](auto WW) { cE[decltype(WW)::value] = c_plaq(st[2 * i][decltype(WW)::value]); });
+          static_for<W>([&](auto WW) { cE[decltype(WW)::value] = c_plaq_of<NOISE>(st[2 * i][decltype(WW)::value]); });
           static_for<W>([&](auto WW) {
             constexpr int w = decltype(WW)::value;
             uint32_t cN = 0x55555555u, cS = 0x55555555u;
-            if constexpr (i > 0) cN = c_plaq(st[2 * i - 1][w]);
-            if constexpr (i < L - 1) cS = c_plaq(st[2 * i + 1][w]);
+            if constexpr (i > 0) cN = c_plaq_of<NOISE>(st[2 * i - 1][w]);
+            if constexpr (i < L - 1) cS = c_plaq_of<NOISE>(st[2 * i + 1][w]);
             uint32_t cEast = cE[w] >> 2;
             if constexpr (w + 1 < W) cEast |= cE[w + 1] << 30;
             constexpr uint32_t M = 0x33333333u;
@@ -359,19 +385,19 @@ __device__ __forceinline__ void run_chain(const RunArgs& a, const GroupDesc& g, 
 // next tile from the launch's queue (tiles are ordered longest first by the
 // planner) and runs the code of that tile's L; tiles of another L range are
 // skipped.  Every wave leaves once the queue is exhausted.
-template <int LMIN, int LMAX>
+template <int LMIN, int LMAX, int NOISE>
 __device__ __forceinline__ void dispatch_tile(const RunArgs& a, const GroupDesc& g, int L, int64_t t,
                                               uint32_t (*lds_tbl)[256], int col) {
   if constexpr (LMIN <= LMAX) {
     if (L == LMIN) {
-      run_chain<LMIN>(a, g, t, lds_tbl, col);
+      run_chain<LMIN, NOISE>(a, g, t, lds_tbl, col);
       return;
     }
-    dispatch_tile<LMIN + 1, LMAX>(a, g, L, t, lds_tbl, col);
+    dispatch_tile<LMIN + 1, LMAX, NOISE>(a, g, L, t, lds_tbl, col);
   }
 }
 
-template <int LMIN, int LMAX>
+template <int LMIN, int LMAX, int NOISE = 0>
 __device__ __forceinline__ void chains_persistent(const RunArgs& a) {
   __shared__ uint32_t lds_tbl[9][256];
   const int col = threadIdx.x;
@@ -404,7 +430,7 @@ __device__ __forceinline__ void chains_persistent(const RunArgs& a) {
     }
     if (L < LMIN || L > LMAX) continue;
     const int64_t t = first + lane;
-    if (t < g.n_tasks) dispatch_tile<LMIN, LMAX>(a, g, L, t, lds_tbl, col);
+    if (t < g.n_tasks) dispatch_tile<LMIN, LMAX, NOISE>(a, g, L, t, lds_tbl, col);
   }
 }
 

@@ -1,0 +1,25 @@
+// Persistent chain kernel for L = 23..25 under independent bit/phase flips
+// (energy = x parts + z parts; two-word rows, 3 waves per SIMD).  Same launch shape and
+// Philox grouping as the depolarizing kernel of this range; only the per-qubit
+// weight-change terms differ.
+#define MCMC_PAIRED_PHILOX 4
+#include "chain_body.h"
+
+namespace mcmc {
+
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
+chains_flip_r4_kernel(const RunArgs a) {
+  chains_persistent<23, 25, 1>(a);
+}
+
+template <>
+hipError_t launch_chains_flip_range<4>(const RunArgs& a, int waves, int wg, hipStream_t s) {
+  if (a.n_tiles == 0) return hipSuccess;
+  if (wg != 64 && wg != 128 && wg != 256) return hipErrorInvalidValue;
+  const int per_wg = wg / 64;
+  const int blocks = (waves + per_wg - 1) / per_wg;
+  hipLaunchKernelGGL(chains_flip_r4_kernel, dim3((unsigned)blocks), dim3((unsigned)wg), 0, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace mcmc

@@ -85,6 +85,7 @@ struct RunArgs {
   const int64_t* resume_A;
   int16_t* trace;                // [chain][trace_len] or nullptr
   int64_t trace_len;
+  int32_t noise;                 // MCMC_NOISE_*: selects the kernel family
 };
 
 // Persistent chain kernels, one per L range, each with the register budget
@@ -103,6 +104,11 @@ inline int range_of(int L) {
 inline bool range_is_wide(int r) { return RANGE_LO[r] > 16; }
 template <int R>
 hipError_t launch_chains_range(const RunArgs& a, int waves, int wg, hipStream_t s);
+// The same ranges under independent bit/phase flips (energy = x parts +
+// z parts).
+template <int R>
+hipError_t launch_chains_flip_range(const RunArgs& a, int waves, int wg, hipStream_t s);
+// Picks the kernel of `range` for a.noise.
 hipError_t launch_chains(int range, const RunArgs& a, int waves, int wg, hipStream_t s);
 hipError_t launch_zero(uint32_t* p, int64_t n, hipStream_t s);
 
@@ -117,11 +123,12 @@ struct StartArgs {
   uint32_t* rows;                // [RW][4] per item, or nullptr
   int32_t* weights;              // [orig*4 + cls], or nullptr
   uint8_t* bytes;                // [orig][4][n_q] (implicit only), or nullptr
+  int32_t noise;                 // weights count x|z (0) or x + z parts (1)
 };
 hipError_t launch_init(const StartArgs& a, hipStream_t s);
 hipError_t launch_init_matching(const StartArgs& a, hipStream_t s);
 
-hipError_t launch_unpack(int L, const uint32_t* rows, int64_t count, int64_t stride,
+hipError_t launch_unpack(int L, int noise, const uint32_t* rows, int64_t count, int64_t stride,
                          uint8_t* out, int32_t* weights, hipStream_t s);
 
 struct DecideArgs {
@@ -129,6 +136,8 @@ struct DecideArgs {
   const GroupDesc* groups;
   GroupDesc g0;
   double beta_bar;             // uniform batch
+  double beta_star;            // uniform batch: the K = 1 temperature (beta_bar by default)
+  int32_t noise;               // uniform batch: beta=0 endpoint 3/4 n_q (0) or n_q (1)
   double ln2;                  // log 2 from the host's libm
   int64_t n;
   const int64_t* S;            // per chain
@@ -141,7 +150,8 @@ struct DecideArgs {
 };
 hipError_t launch_decide(const DecideArgs& a, hipStream_t s);
 
-hipError_t launch_sample(int L, uint32_t threshold, uint32_t k0, uint32_t k1, const uint32_t* ids,
+hipError_t launch_sample(int L, int noise, uint32_t threshold, uint32_t k0, uint32_t k1,
+                         const uint32_t* ids,
                          uint32_t id_base, int64_t n, uint8_t* syn, uint8_t* true_class,
                          uint8_t* errors, hipStream_t s);
 // One sample per plan item (its L, p, id; syndrome written at syn_off, class at orig).

@@ -74,7 +74,8 @@ __global__ void __launch_bounds__(256) init_kernel(const StartArgs a) {
     uint32_t zbits = colpar;
     if (i == 0 && xbar) xbits ^= (1u << L) - 1u;
     if (zbar) zbits ^= 1u;
-    weight += __builtin_popcount(xbits | zbits);
+    weight += a.noise ? __builtin_popcount(xbits) + __builtin_popcount(zbits)
+                      : __builtin_popcount(xbits | zbits);
     if (a.bytes) {  // qubit (2i, 2k) is number i*side + k; odd-row qubits are I
       const int side = 2 * L - 1, nq = 2 * L * L - 2 * L + 1;
       uint8_t* out = a.bytes + (si.orig * 4 + cls) * nq;
@@ -126,7 +127,8 @@ hipError_t launch_zero(uint32_t* p, int64_t n, hipStream_t s) {
 // Unpack `count` packed configurations (word-major, element stride `stride`)
 // into one byte per qubit (row-major over the grid) and/or their weights.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) unpack_kernel(int L, const uint32_t* __restrict__ rows,
+__global__ void __launch_bounds__(256) unpack_kernel(int L, int noise,
+                                                     const uint32_t* __restrict__ rows,
                                                      int64_t count, int64_t stride,
                                                      uint8_t* __restrict__ out,
                                                      int32_t* __restrict__ weights) {
@@ -140,7 +142,7 @@ __global__ void __launch_bounds__(256) unpack_kernel(int L, const uint32_t* __re
     for (int f = 0; f < fields; ++f) {
       const uint32_t word = rows[(int64_t)(r * W + f / 16) * stride + e];
       const uint8_t code = (uint8_t)((word >> (2 * (f % 16))) & 3u);
-      weight += code != 0;
+      weight += noise ? (code & 1) + (code >> 1) : code != 0;
       if (out) out[e * nq + q] = code;
       ++q;
     }
@@ -148,10 +150,11 @@ __global__ void __launch_bounds__(256) unpack_kernel(int L, const uint32_t* __re
   if (weights) weights[e] = weight;
 }
 
-hipError_t launch_unpack(int L, const uint32_t* rows, int64_t count, int64_t stride, uint8_t* out,
-                         int32_t* weights, hipStream_t s) {
+hipError_t launch_unpack(int L, int noise, const uint32_t* rows, int64_t count, int64_t stride,
+                         uint8_t* out, int32_t* weights, hipStream_t s) {
   if (count == 0) return hipSuccess;
   hipLaunchKernelGGL(unpack_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, L,
+                     noise,
                      rows, count, stride, out, weights);
   return hipGetLastError();
 }
@@ -160,8 +163,11 @@ hipError_t launch_unpack(int L, const uint32_t* rows, int64_t count, int64_t str
 // Estimator and decision (Eq. main, Sec. IV.A), one thread per syndrome, FP64
 // in a fixed order with no contraction:
 //   mean_{E,k} = (sum_c S) / (C * 4 * sweeps)   (mean final weight if sweeps = 0)
-//   K = 1 : I_E = (beta_bar / 2) (f0 + mean_{E,1})                (trapezoid)
+//   K = 1 : I_E = (beta* / 2)(f0 + mean_{E,1}) + (beta_bar - beta*) mean_{E,1}
+//           (trapezoid to the sampled temperature, <n> held above it; the
+//           plain trapezoid when beta* = beta_bar)
 //   K even: I_E = (h / 3)(f0 + 4 f1 + 2 f2 + ... + f_K), h = beta_bar / K
+//   f0 = <n> at beta = 0: 3/4 n_q (depolarizing), n_q (bit/phase flips)
 //   log Z_E = n_stab log 2 - I_E,  P_E = softmax(log Z)
 // Decision by the integer key sum_{k<K} w_k S_{E,k} + S_{E,K} (all I_E share
 // f0 and the denominator), ties to the lowest class.
@@ -172,7 +178,8 @@ __global__ void __launch_bounds__(128) decide_kernel(const DecideArgs a) {
   if (s >= a.n) return;
   GroupDesc g;
   int64_t orig, chain_off, rows_off, corr_off;
-  double beta_bar;
+  double beta_bar, beta_star;
+  int noise = 0;
   if (a.items) {
     const ItemDesc it = a.items[s];
     g = a.groups[it.group];
@@ -181,6 +188,7 @@ __global__ void __launch_bounds__(128) decide_kernel(const DecideArgs a) {
     rows_off = it.rows_off;
     corr_off = it.corr_off;
     beta_bar = it.beta_bar;
+    beta_star = it.beta_bar;
   } else {
     g = a.g0;
     orig = s;
@@ -188,12 +196,15 @@ __global__ void __launch_bounds__(128) decide_kernel(const DecideArgs a) {
     rows_off = s * (int64_t)words_per_config(g.L) * 4;
     corr_off = s * (int64_t)(2 * g.L * g.L - 2 * g.L + 1);
     beta_bar = a.beta_bar;
+    beta_star = a.beta_star;
+    noise = a.noise;
   }
   const int K = g.K, C = g.C, L = g.L;
   const int sweeps = g.sweep_end - g.burn;
   const bool counted = sweeps > 0;
   const double denom = counted ? (double)((int64_t)C * 4 * sweeps) : (double)C;
-  const double f0 = 0.75 * (double)(2 * L * L - 2 * L + 1);
+  const double nq = (double)(2 * L * L - 2 * L + 1);
+  const double f0 = noise ? nq : 0.75 * nq;
   const double log_z0 = (double)(2 * L * (L - 1)) * a.ln2;
   double logz[4];
   int64_t key[4];
@@ -219,7 +230,7 @@ __global__ void __launch_bounds__(128) decide_kernel(const DecideArgs a) {
     }
     double integral;
     if (K == 1) {
-      integral = (beta_bar / 2.0) * (f0 + mean_first);
+      integral = (beta_star / 2.0) * (f0 + mean_first) + (beta_bar - beta_star) * mean_first;
     } else {
       const double h = beta_bar / (double)K;
       integral = (acc * h) / 3.0;
@@ -267,7 +278,8 @@ hipError_t launch_decide(const DecideArgs& a, hipStream_t s) {
 // ---------------------------------------------------------------------------
 constexpr int SAMPLE_MAX_NQ = 2 * MCMC_L_MAX * MCMC_L_MAX - 2 * MCMC_L_MAX + 1;
 
-__device__ __forceinline__ void sample_one(int L, uint32_t threshold, uint32_t k0, uint32_t k1,
+__device__ __forceinline__ void sample_one(int L, int noise, uint32_t threshold, uint32_t k0,
+                                           uint32_t k1,
                                            uint32_t sid, uint8_t* err, uint8_t* __restrict__ syn,
                                            uint8_t* __restrict__ true_class,
                                            uint8_t* __restrict__ errors) {
@@ -282,6 +294,10 @@ __device__ __forceinline__ void sample_one(int L, uint32_t threshold, uint32_t k
       if (q >= nq) break;
       const uint32_t u0 = h ? w.z : w.x;
       const uint32_t u1 = h ? w.w : w.y;
+      if (noise) {  // independent flips: x part from u0, z part from u1
+        err[q] = (uint8_t)((u0 < threshold ? 1 : 0) | (u1 < threshold ? 2 : 0));
+        continue;
+      }
       const uint32_t type = (uint32_t)(((uint64_t)u1 * 3u) >> 32);  // 0 X, 1 Y, 2 Z
       const uint8_t code = (uint8_t)(type == 0 ? 1 : (type == 1 ? 3 : 2));
       err[q] = u0 < threshold ? code : (uint8_t)0;
@@ -314,7 +330,8 @@ __device__ __forceinline__ void sample_one(int L, uint32_t threshold, uint32_t k
     for (int q = threadIdx.x; q < nq; q += blockDim.x) errors[q] = err[q];
 }
 
-__global__ void __launch_bounds__(256) sample_kernel(int L, uint32_t threshold, uint32_t k0,
+__global__ void __launch_bounds__(256) sample_kernel(int L, int noise, uint32_t threshold,
+                                                     uint32_t k0,
                                                      uint32_t k1, const uint32_t* __restrict__ ids,
                                                      uint32_t id_base, int64_t n,
                                                      uint8_t* __restrict__ syn,
@@ -326,7 +343,7 @@ __global__ void __launch_bounds__(256) sample_kernel(int L, uint32_t threshold, 
   const uint32_t sid = ids ? ids[smp] : id_base + (uint32_t)smp;
   const int nq = 2 * L * L - 2 * L + 1;
   const int nstab = 2 * L * (L - 1);
-  sample_one(L, threshold, k0, k1, sid, err, syn + smp * nstab, true_class + smp,
+  sample_one(L, noise, threshold, k0, k1, sid, err, syn + smp * nstab, true_class + smp,
              errors ? errors + smp * nq : nullptr);
 }
 
@@ -339,7 +356,7 @@ __global__ void __launch_bounds__(256) sample_items_kernel(const ItemDesc* __res
   const int64_t smp = blockIdx.x;
   if (smp >= n) return;
   const ItemDesc it = items[smp];
-  sample_one(groups[it.group].L, it.err_thr, k0, k1, it.sid, err, syn + it.syn_off,
+  sample_one(groups[it.group].L, 0, it.err_thr, k0, k1, it.sid, err, syn + it.syn_off,
              true_class + it.orig, nullptr);
 }
 
@@ -352,11 +369,12 @@ hipError_t launch_sample_items(const ItemDesc* items, const GroupDesc* groups, i
   return hipGetLastError();
 }
 
-hipError_t launch_sample(int L, uint32_t threshold, uint32_t k0, uint32_t k1, const uint32_t* ids,
-                         uint32_t id_base, int64_t n, uint8_t* syn, uint8_t* true_class,
-                         uint8_t* errors, hipStream_t s) {
+hipError_t launch_sample(int L, int noise, uint32_t threshold, uint32_t k0, uint32_t k1,
+                         const uint32_t* ids, uint32_t id_base, int64_t n, uint8_t* syn,
+                         uint8_t* true_class, uint8_t* errors, hipStream_t s) {
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(sample_kernel, dim3((unsigned)n), dim3(256), 0, s, L, threshold, k0, k1, ids,
+  hipLaunchKernelGGL(sample_kernel, dim3((unsigned)n), dim3(256), 0, s, L, noise, threshold, k0,
+                     k1, ids,
                      id_base, n, syn, true_class, errors);
   return hipGetLastError();
 }
@@ -536,7 +554,8 @@ __global__ void __launch_bounds__(MATCH_THREADS) init_matching_kernel(const Star
       const int fields = (r & 1) ? L - 1 : L;
       const uint32_t xb = xp[r][tid], zb = zp[r][tid];
       const uint32_t valid = fields >= 32 ? ~0u : ((1u << fields) - 1u);
-      weight += __builtin_popcount((xb | zb) & valid);
+      weight += a.noise ? __builtin_popcount(xb & valid) + __builtin_popcount(zb & valid)
+                        : __builtin_popcount((xb | zb) & valid);
       if (a.rows) {
         for (int w = 0; w < W; ++w) {
           uint32_t word = 0;

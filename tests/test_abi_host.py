@@ -27,7 +27,7 @@ def test_exports_every_declared_symbol():
     assert decl == _lib.exported_symbols()
     for name in decl:
         assert hasattr(lib, name), name
-    assert lib.mcmc_abi_version() == 0x00010000
+    assert lib.mcmc_abi_version() == 0x00010100
 
 
 @pytest.mark.parametrize("L", list(range(2, 26)))
@@ -45,6 +45,20 @@ def test_geometry_and_lattice_match_oracle(L):
 @pytest.mark.parametrize("K", [1, 2, 20, 64])
 def test_tables_match_oracle(p, K):
     assert np.array_equal(mc.acceptance_table(p, K), tables.tables(p, K))
+
+
+@pytest.mark.parametrize("noise,p", [(0, 0.05), (0, 0.15), (1, 0.02), (1, 0.08), (1, 0.1),
+                                     (1, 0.3), (1, 0.49)])
+@pytest.mark.parametrize("K,scale", [(1, 0.0), (1, 1.0), (1, 0.85), (1, 0.5), (1, 4.0),
+                                     (2, 0.0), (20, 1.0)])
+def test_params_tables_match_oracle(noise, p, K, scale):
+    """The thresholds of a decode under each noise model equal the oracle's
+    (beta* = scale * beta_bar for K = 1, the model default when scale is 0)."""
+    prm = mc.make_params(9, p, 10, 1, n_temps=K, noise=noise, beta_scale=scale)
+    want = tables.tables(p, K, noise, None if scale == 0.0 else scale)
+    assert np.array_equal(mc.params_table(prm), want)
+    if noise == 0 and scale in (0.0, 1.0):
+        assert np.array_equal(mc.params_table(prm), mc.acceptance_table(p, K))
 
 
 def test_out_of_range_rejected():
@@ -67,12 +81,24 @@ def _ws(**kw):
     (dict(n_temps=3), -1), (dict(n_temps=0), -2), (dict(n_temps=66), -2),
     (dict(chains=0), -2), (dict(sweeps=-1), -2), (dict(burn=-2), -2),
     (dict(L=30), -2), (dict(p=0.8), -2), (dict(flags=8), -1), (dict(sweep_begin=3), -1),
-    (dict(init=2), -1),
+    (dict(init=2), -1), (dict(noise=2), -1), (dict(noise=1, p=0.5), -2),
+    (dict(noise=1, p=0.0), -2), (dict(beta_scale=-0.5), -2), (dict(beta_scale=4.5), -2),
+    (dict(beta_scale=float("nan")), -2), (dict(n_temps=2, beta_scale=0.85), -2),
 ])
 def test_param_validation(kw, status):
     with pytest.raises(mc.McmcError) as e:
         _ws(**kw)
     assert e.value.status == status
+
+
+def test_param_reserved_must_be_zero():
+    prm = mc.make_params(9, 0.1, 10, 1)
+    prm.reserved = 1
+    with pytest.raises(mc.McmcError) as e:
+        mc.workspace_size(prm, 4)
+    assert e.value.status == -1
+    for kw in (dict(noise=1, p=0.45), dict(n_temps=2, beta_scale=1.0), dict(beta_scale=0.85)):
+        assert _ws(**kw) > 0
 
 
 def test_decode_rejects_before_launch():
@@ -94,6 +120,9 @@ def test_decode_rejects_before_launch():
     assert lib.mcmc_decode_batch(*args(prm=bad)) == -1      # trace requested, no buffer
     assert lib.mcmc_sample_errors(9, 0.1, 1, None, 0, 4, None, dummy, None, None) == -1
     assert lib.mcmc_sample_errors(9, 0.9, 1, None, 0, 4, dummy, dummy, None, None) == -2
+    assert lib.mcmc_sample_errors_model(9, 2, 0.1, 1, None, 0, 4, dummy, dummy, None, None) == -1
+    assert lib.mcmc_sample_errors_model(9, 1, 0.6, 1, None, 0, 4, dummy, dummy, None, None) == -2
+    assert lib.mcmc_sample_errors_model(9, 1, 0.1, 1, None, 0, 4, None, dummy, None, None) == -1
 
 
 def test_plan_rejects_invalid_items_before_allocating():

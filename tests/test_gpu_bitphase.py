@@ -1,0 +1,181 @@
+"""Parity of the HIP path with the CPU oracle under independent bit/phase
+flips (Eq. pauliChannel with p_b = p_p = q; Sec. IV.A's last paragraph),
+through the C-ABI.
+
+Same bar as the depolarizing parity tests: errors, syndromes, class starts,
+trajectories, energy sums, accept counts, final states and weights,
+decisions and corrections bit-exact; FP64 class probabilities and means
+within 1e-12 relative.
+"""
+
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+import paper_1302_2669_amd as mc  # noqa: E402
+from oracle import decoder, geometry, sampler, tables  # noqa: E402
+
+from paper_1302_2669_amd.inputs import SEED_L9, SEED_METRIC  # noqa: E402
+
+DEV = "cuda"
+RTOL = 1e-12
+BP = mc.MCMC_NOISE_BITPHASE
+
+
+def setup_module(module):
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a HIP device")
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def to_np(d):
+    torch.cuda.synchronize()
+    return {k: v.cpu().numpy() for k, v in d.items()}
+
+
+def gpu_decode(L, syn, q, sweeps, seed, chains=1, K=1, burn=0, ids=None, scale=0.0, trace=True,
+               init=mc.MCMC_INIT_MATCHING):
+    s = torch.from_numpy(np.ascontiguousarray(syn, dtype=np.uint8)).to(DEV)
+    tid = None if ids is None else torch.from_numpy(np.asarray(ids, dtype=np.int64))
+    out = mc.decode_batch(s, L, q, sweeps, seed, chains=chains, n_temps=K, burn=burn,
+                          syndrome_ids=tid, want_sums=True, trace=trace, chain_state=True,
+                          init=init, noise=BP, beta_scale=scale)
+    res = to_np({k: v for k, v in out.items() if k != "chain_state"})
+    st, w = mc.unpack_chain_state(out["chain_state"], syn.shape[0], L, q, sweeps, seed, chains, K,
+                                  burn, noise=BP)
+    res["states"], res["n_final"] = st.cpu().numpy(), w.cpu().numpy()
+    return res
+
+
+def oracle_decode(L, syn, q, sweeps, seed, chains=1, K=1, burn=0, ids=None, scale=0.0, trace=True,
+                  init=mc.MCMC_INIT_MATCHING):
+    o = decoder.decode(L, syn, q, sweeps, seed, chains_per_class=chains, n_temps=K, burn=burn,
+                       syndrome_ids=ids, trace=trace, init_mode=init, noise=tables.BITPHASE,
+                       beta_scale=None if scale == 0.0 else scale)
+    o["n_final"] = o["n_final"].astype(np.int32)
+    return o
+
+
+def assert_parity(g, o, check_trace=True):
+    assert np.array_equal(g["sum_n"], o["sum_n"]), "energy sums differ"
+    assert np.array_equal(g["accepts"], o["accepts"]), "accept counts differ"
+    if check_trace:
+        assert np.array_equal(g["trace"], o["trace"]), "trajectories differ"
+    assert np.array_equal(g["states"], o["states"]), "final states differ"
+    assert np.array_equal(g["n_final"], o["n_final"]), "final energies differ"
+    assert np.array_equal(g["chosen"], o["chosen"]), "decisions differ"
+    assert np.array_equal(g["correction"], o["correction"]), "corrections differ"
+    np.testing.assert_allclose(g["class_prob"], o["class_prob"], rtol=RTOL, atol=0)
+    np.testing.assert_allclose(g["mean_n"], o["mean_n"], rtol=RTOL, atol=0)
+
+
+@pytest.mark.parametrize("L,q", [(2, 0.3), (3, 0.1), (9, 0.49), (13, 0.1), (17, 0.08), (25, 0.1)])
+def test_sampler_parity(L, q):
+    say(f"bit/phase sampler L={L} q={q}")
+    n = 257
+    syn, cls, err = mc.sample_errors(L, q, SEED_L9, n, device=DEV, id_base=500, want_errors=True,
+                                     noise=BP)
+    torch.cuda.synchronize()
+    lat = geometry.Lattice(L)
+    o_syn, o_cls, o_err = sampler.sample(lat, q, SEED_L9, np.arange(500, 500 + n), noise=BP)
+    assert np.array_equal(err.cpu().numpy(), o_err)
+    assert np.array_equal(syn.cpu().numpy(), o_syn)
+    assert np.array_equal(cls.cpu().numpy(), o_cls)
+
+
+CASES = [
+    # L, q, sweeps, burn, chains, K, scale, n
+    (2, 0.10, 40, 5, 3, 1, 0.0, 6),
+    (3, 0.10, 50, 10, 2, 1, 0.0, 8),
+    (3, 0.08, 30, 0, 2, 1, 1.0, 6),
+    (3, 0.10, 20, 0, 1, 4, 0.0, 5),
+    (4, 0.05, 15, 3, 2, 2, 1.0, 5),
+    (5, 0.10, 12, 2, 2, 1, 0.7, 6),
+    (7, 0.30, 8, 0, 1, 1, 0.0, 5),
+    (13, 0.10, 4, 1, 2, 1, 0.0, 3),
+    (14, 0.09, 3, 0, 1, 1, 0.0, 2),
+    (16, 0.10, 2, 0, 1, 2, 0.0, 2),
+    (17, 0.10, 2, 1, 1, 1, 0.0, 2),
+    (20, 0.08, 2, 0, 1, 1, 0.0, 2),
+    (23, 0.10, 2, 0, 1, 1, 0.0, 2),
+    (25, 0.10, 2, 0, 1, 1, 0.0, 2),
+]
+
+
+@pytest.mark.parametrize("L,q,sweeps,burn,chains,K,scale,n", CASES)
+def test_chain_parity(L, q, sweeps, burn, chains, K, scale, n):
+    say(f"bit/phase chains L={L} q={q} sweeps={sweeps} burn={burn} chains={chains} K={K} "
+        f"scale={scale} n={n}")
+    lat = geometry.Lattice(L)
+    syn, _, _ = sampler.sample(lat, q, SEED_L9 + L, np.arange(n), noise=tables.BITPHASE)
+    ids = np.arange(n) * 5 + 1
+    g = gpu_decode(L, syn, q, sweeps, SEED_L9, chains, K, burn, ids=ids, scale=scale)
+    o = oracle_decode(L, syn, q, sweeps, SEED_L9, chains, K, burn, ids=ids, scale=scale)
+    assert_parity(g, o)
+
+
+@pytest.mark.parametrize("L", [3, 13, 25])
+def test_canonical_start_parity(L):
+    say(f"bit/phase canonical start L={L}")
+    lat = geometry.Lattice(L)
+    syn, _, _ = sampler.sample(lat, 0.1, SEED_L9 - L, np.arange(3), noise=tables.BITPHASE)
+    g = gpu_decode(L, syn, 0.1, 3, 7, 2, 1, 1, init=mc.MCMC_INIT_CANONICAL)
+    o = oracle_decode(L, syn, 0.1, 3, 7, 2, 1, 1, init=mc.MCMC_INIT_CANONICAL)
+    assert_parity(g, o)
+
+
+def test_edge_syndromes():
+    """Empty and fully lit syndromes, zero counted sweeps, burn-in only."""
+    say("bit/phase edge syndromes")
+    for L, q in ((3, 0.1), (13, 0.1), (17, 0.05)):
+        lat = geometry.Lattice(L)
+        syn = np.stack([np.zeros(lat.n_stab, np.uint8), np.ones(lat.n_stab, np.uint8)])
+        for sweeps, burn in ((0, 0), (0, 3), (3, 0)):
+            g = gpu_decode(L, syn, q, sweeps, 99, 2, 1, burn)
+            o = oracle_decode(L, syn, q, sweeps, 99, 2, 1, burn)
+            assert_parity(g, o)
+
+
+def test_resume_is_bit_exact():
+    say("bit/phase resume")
+    L, q, chains, sweeps, burn, n = 9, 0.1, 2, 30, 5, 16
+    lat = geometry.Lattice(L)
+    syn = torch.from_numpy(sampler.sample(lat, q, 3, np.arange(n), noise=tables.BITPHASE)[0]).to(DEV)
+    kw = dict(chains=chains, burn=burn, want_sums=True, noise=BP)
+    whole = mc.decode_batch(syn, L, q, sweeps, 5, chain_state=True, **kw)
+    first = mc.decode_batch(syn, L, q, 12 - burn, 5, chain_state=True, **kw)
+    second = mc.decode_batch(syn, L, q, sweeps, 5, resume_from=(first["chain_state"], 12), **kw)
+    a = to_np({k: v for k, v in whole.items() if k != "chain_state"})
+    b = to_np({k: v for k, v in second.items() if k != "chain_state"})
+    for k in ("sum_n", "accepts", "chosen", "correction", "class_prob", "mean_n"):
+        assert np.array_equal(a[k], b[k]), k
+
+
+def test_workload_sampled():
+    """L = 13, q = 0.10, 4 x 4 chains, L^2 sweeps at beta* = 0.85 beta_bar:
+    the GPU decodes 8192 samples at once; an evenly spaced subset is replayed
+    on the oracle (same ids) and must match bit for bit."""
+    L, q, n, sweeps, chains = 13, 0.10, 8192, 169, 4
+    say(f"bit/phase workload L={L} q={q} n={n} sweeps={sweeps}")
+    syn_d, cls_d, _ = mc.sample_errors(L, q, SEED_METRIC, n, device=DEV, noise=BP)
+    out = mc.decode_batch(syn_d, L, q, sweeps, SEED_METRIC, chains=chains, want_sums=True,
+                          noise=BP)
+    g = to_np(out)
+    syn = syn_d.cpu().numpy()
+    sel = np.linspace(0, n - 1, 12).astype(np.int64)
+    o = oracle_decode(L, syn[sel], q, sweeps, SEED_METRIC, chains, 1, 0, ids=sel, trace=False)
+    for k in ("sum_n", "accepts", "chosen", "correction"):
+        assert np.array_equal(g[k][sel], o[k]), k
+    np.testing.assert_allclose(g["class_prob"][sel], o["class_prob"], rtol=RTOL, atol=0)
+    err = float((g["chosen"] != cls_d.cpu().numpy()).mean())
+    say(f"bit/phase L={L} q={q} logical error {err:.4f}")
+    assert 0.0 < err < 0.5
