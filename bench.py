@@ -25,6 +25,7 @@ import time
 import numpy as np
 
 L, P, CHAINS, SWEEPS, BURN, K = 13, 0.15, 4, 169, 0, 1
+Q_BITPHASE = 0.10
 SEED = 0x1302266900000013
 BATCH = 65536
 # integer operations per stabilizer update in the minimal scalar formulation:
@@ -59,9 +60,11 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=640)
     ap.add_argument("--no-budget-curve", action="store_true",
                     help="skip the logical error vs sweep budget curve")
-    ap.add_argument("--workload", choices=["metric", "mixed", "gated"], default="metric",
+    ap.add_argument("--workload", choices=["metric", "mixed", "gated", "bitphase"],
+                    default="metric",
                     help="metric: L=13 p=0.15 (default); mixed: L in 5..25, p in [0.05,0.18]; "
-                         "gated: gate network trained and timed against the plain decoder")
+                         "gated: gate network trained and timed against the plain decoder; "
+                         "bitphase: L=13, independent bit/phase flips q=0.10")
     ap.add_argument("--gate-train", type=int, default=1_000_000)
     ap.add_argument("--gate-epochs", type=int, default=4)
     ap.add_argument("--gate-eval", type=int, default=100_000)
@@ -84,6 +87,8 @@ def main():
         return bench_mixed(args, mc, torch, dev)
     if args.workload == "gated":
         return bench_gated(args, mc, torch, dev)
+    if args.workload == "bitphase":
+        return bench_bitphase(args, mc, torch, dev)
     n = args.batch
     nq, ns = mc.geometry(L)
     steps, warm = args.steps, args.warmup
@@ -411,20 +416,107 @@ def bench_gated(args, mc, torch, dev):
     print(json.dumps(line), flush=True)
 
 
-def cpu_baseline(n_sample, ns):
+def bench_bitphase(args, mc, torch, dev):
+    """Independent bit/phase flips (Eq. pauliChannel with p_b = p_p = q) at
+    the rate the paper studies for this model, q = 0.10, L = 13, 4 x 4
+    chains, L^2 sweeps at beta* = 0.85 beta_bar (the paper's choice for this
+    model).  Also the logical error at beta*/beta_bar = 0.70, 0.85 and 1.00
+    on the same syndromes and chains."""
+    q, bp = Q_BITPHASE, mc.MCMC_NOISE_BITPHASE
+    n, steps, warm = args.batch, args.steps, args.warmup
+    nq, ns = mc.geometry(L)
+    batches, truth = [], []
+    for b in range(warm + steps):
+        syn, cls, _ = mc.sample_errors(L, q, SEED, n, device=dev, id_base=b * n, noise=bp)
+        batches.append(syn)
+        truth.append(cls)
+    prm = mc.make_params(L, q, SWEEPS, SEED, chains=CHAINS, noise=bp)
+    ws = torch.empty((mc.workspace_size(prm, n),), dtype=torch.uint8, device=dev)
+    ids = [torch.arange(b * n, (b + 1) * n, dtype=torch.int32, device=dev)
+           for b in range(warm + steps)]
+    torch.cuda.synchronize()
+
+    def step(b, sweeps=SWEEPS, scale=0.0):
+        return mc.decode_batch(batches[b], L, q, sweeps, SEED, chains=CHAINS, syndrome_ids=ids[b],
+                               want_correction=True, workspace=ws, noise=bp, beta_scale=scale)
+
+    for b in range(warm):
+        step(b)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream(dev)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    chosen = []
+    t0 = time.perf_counter()
+    ev[0].record(stream)
+    for i in range(steps):
+        chosen.append(step(warm + i)["chosen"])
+        ev[i + 1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    step_ms = float(np.mean([ev[i].elapsed_time(ev[i + 1]) for i in range(steps)]))
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for i in range(steps):
+        step(warm + i, sweeps=0)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    chain_ms = step_ms - e0.elapsed_time(e1) / steps
+    updates_per_syndrome = 4 * CHAINS * SWEEPS * ns
+    achieved = n * updates_per_syndrome * OPS_PER_UPDATE / (chain_ms * 1e-3) / 1e12
+    peak = PEAK_INT_OPS / 1e12
+    fails = sum(int((c != t).sum().item()) for c, t in zip(chosen, truth[warm:]))
+    total = n * steps
+    nb = min(4, steps)
+    scan = []
+    for scale in (0.70, 0.85, 1.00):
+        outs = [step(warm + i, scale=scale)["chosen"] for i in range(nb)]
+        wrong = sum(int((o != t).sum().item()) for o, t in zip(outs, truth[warm:warm + nb]))
+        scan.append({"beta_scale": scale, "logical_error": wrong / (n * nb), "samples": n * nb})
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(args.cpu_sample, ns, noise=1, p=q)
+    line = {
+        "metric": "decoded syndromes/sec + stabilizer updates/sec at L=13, independent "
+                  "bit/phase flips q=0.10",
+        "value": total / wall,
+        "unit": "syndromes/s",
+        "stabilizer_updates_per_s": total / wall * updates_per_syndrome,
+        "n_gpus": 1, "steps": steps, "warmup": warm, "ms_per_step": wall * 1e3 / steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32",
+        "data": "synthetic: i.i.d. bit and phase flips from the library's Philox sampler",
+        "config": {"workload": "planar code L=13, independent bit/phase flips q=0.10, 4 classes "
+                               "x 4 chains, 169 sweeps (L^2), beta* = 0.85 beta_bar, batch of "
+                               f"{n} syndromes per step",
+                   "L": L, "q": q, "chains_per_class": CHAINS, "sweeps": SWEEPS, "batch": n,
+                   "beta_scale": 0.85, "updates_per_syndrome": updates_per_syndrome},
+        "logical_error": {"rate": fails / total, "samples": total},
+        "beta_scale_scan": scan,
+        "roofline": {"bound": "alu", "kernel": "chains_flip_r0_kernel (L 2..13, at L=13)",
+                     "achieved": achieved, "peak": peak, "unit": "Tops/s",
+                     "frac": achieved / peak, "traffic": None,
+                     "chain_ms_per_launch": chain_ms, "ops_per_update": OPS_PER_UPDATE,
+                     "updates_per_launch": n * updates_per_syndrome},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def cpu_baseline(n_sample, ns, noise=0, p=P):
     """The oracle, as written, on a bounded sample of the same workload."""
     here = os.path.dirname(os.path.abspath(__file__))
     if here not in sys.path:
         sys.path.insert(0, here)
     from oracle import decoder, geometry, sampler
     lat = geometry.Lattice(L)
-    syn, _, _ = sampler.sample(lat, P, SEED, np.arange(n_sample))
+    syn, _, _ = sampler.sample(lat, p, SEED, np.arange(n_sample), noise=noise)
     t0 = time.perf_counter()
-    decoder.decode(L, syn, P, SWEEPS, SEED, chains_per_class=CHAINS, n_temps=K, burn=BURN)
+    decoder.decode(L, syn, p, SWEEPS, SEED, chains_per_class=CHAINS, n_temps=K, burn=BURN,
+                   noise=noise)
     dt = time.perf_counter() - t0
+    model = "bit/phase flips q" if noise else "p"
     return {"value": n_sample / dt, "unit": "syndromes/s", "cores": 1, "kind": "oracle",
-            "sample": f"{n_sample} syndromes of the same workload (L=13, p=0.15, 4x4 chains, "
-                      f"169 sweeps), NumPy oracle in one process, {dt:.1f} s",
+            "sample": f"{n_sample} syndromes of the same workload (L=13, {model}={p}, 4x4 "
+                      f"chains, 169 sweeps), NumPy oracle in one process, {dt:.1f} s",
             "stabilizer_updates_per_s": n_sample * 4 * CHAINS * K * (BURN + SWEEPS) * ns / dt}
 
 
