@@ -124,3 +124,80 @@ def run(lat, state, syndrome_id, cls, temp, chain, table, seed,
     if trace:
         out["trace"] = (np.stack(tr, axis=1) if tr else np.zeros((T, 0), dtype=np.int64))
     return out
+
+
+# ---------------------------------------------------------------------------
+# Random scan (Sec. IV as written): every step picks one stabilizer uniformly
+# at random among all n_stab and applies the Metropolis rule to it; the
+# energy n is summed after every step.  A "sweep" is n_stab steps, so budgets
+# compare with the colour-phased scan.  Step t of a sweep draws block t >> 1
+# at counter (t >> 1, sweep, syndrome_id, 2<<30 | cls<<28 | temp<<20 | chain)
+# and uses its words 2(t&1) (site: floor(u * n_stab / 2^32)) and 2(t&1)+1
+# (acceptance).
+# ---------------------------------------------------------------------------
+def _padded_supports(lat):
+    sup = np.full((lat.n_stab, 4), -1, dtype=np.int64)
+    for s in range(lat.n_stab):
+        sup[s, :len(lat.supports[s])] = lat.supports[s]
+    return sup
+
+
+def run_random(lat, state, syndrome_id, cls, temp, chain, table, seed,
+               sweep_begin, sweep_end, burn, n=None, S=None, A=None,
+               check_invariants=False, syndromes=None, noise=0):
+    """Advance T independent random-scan chains over absolute sweeps
+    [sweep_begin, sweep_end); arguments and result as `run` (no trace)."""
+    state = np.array(state, dtype=np.uint8, copy=True)
+    T = state.shape[0]
+    sid = np.asarray(syndrome_id, dtype=np.uint64).reshape(T)
+    ctr3 = philox.chain_ctr3(np.asarray(cls).reshape(T), np.asarray(temp).reshape(T),
+                             np.asarray(chain).reshape(T), philox.DOMAIN_RANDOM_SCAN)
+    k0, k1 = philox.seed_key(seed)
+    thr = np.asarray(table, dtype=np.uint64).reshape(T, 4)
+    n = geometry.energy(state, noise).astype(np.int64) if n is None else \
+        np.array(n, dtype=np.int64)
+    S = np.zeros(T, dtype=np.int64) if S is None else np.array(S, dtype=np.int64)
+    A = np.zeros(T, dtype=np.int64) if A is None else np.array(A, dtype=np.int64)
+    rows = np.arange(T)
+    sup = _padded_supports(lat)
+    is_star = lat.site_is_star
+    n_stab = np.uint64(lat.n_stab)
+    if check_invariants:
+        cls_arr = np.asarray(cls).reshape(T)
+        syn_ref = np.asarray(syndromes, dtype=np.uint8).reshape(T, lat.n_stab)
+
+    for sweep in range(sweep_begin, sweep_end):
+        blocks = np.arange(lat.n_stab // 2, dtype=np.uint64)
+        w = philox.philox4x32_10(blocks[None, :], np.uint64(sweep), sid[:, None],
+                                 ctr3[:, None], k0, k1)
+        w = np.stack(w, axis=-1).astype(np.uint64)           # [T, n_stab/2, 4]
+        for t in range(lat.n_stab):
+            u_site = w[:, t >> 1, 2 * (t & 1)]
+            u_acc = w[:, t >> 1, 2 * (t & 1) + 1]
+            site = ((u_site * n_stab) >> np.uint64(32)).astype(np.int64)
+            q = sup[site]                                       # [T, 4], -1 padded
+            valid = q >= 0
+            codes = np.where(valid, state[rows[:, None], np.where(valid, q, 0)], 0).astype(np.int64)
+            x, z = codes & 1, codes >> 1
+            star = is_star[site][:, None]
+            if noise == 1:
+                part = np.where(star, x, z)
+                delta = np.where(valid, 1 - 2 * part, 0).sum(axis=1)
+            else:
+                other, own = np.where(star, z, x), np.where(star, x, z)
+                delta = np.where(valid, (1 - other) * (1 - 2 * own), 0).sum(axis=1)
+            accept = (delta <= 0) | (u_acc < thr[rows, np.clip(delta, 1, 4) - 1])
+            flip = np.where(is_star[site], 1, 2).astype(np.uint8)
+            for k in range(4):
+                m = accept & valid[:, k]
+                state[rows[m], q[m, k]] ^= flip[m]
+            n += np.where(accept, delta, 0)
+            A += accept
+            if sweep >= burn:
+                S += n
+        if check_invariants:
+            assert np.array_equal(geometry.syndrome(lat, state), syn_ref), "syndrome changed"
+            assert np.array_equal(geometry.class_index(lat, state), cls_arr), "class changed"
+            assert np.array_equal(geometry.energy(state, noise), n), "incremental n != recount"
+
+    return dict(state=state, n=n, S=S, A=A)

@@ -16,14 +16,19 @@ from . import chains, estimator, geometry, init, tables
 
 INIT_CANONICAL = 0
 INIT_MATCHING = 1
+SCAN_COLOUR = 0      # colour-phased systematic sweeps (Sec. V's grouping)
+SCAN_RANDOM = 1      # one uniformly random stabilizer per step (Sec. IV)
 
 
 def decode(L, syndromes, p, sweeps, seed, chains_per_class=1, n_temps=1, burn=0,
            syndrome_ids=None, trace=False, check_invariants=False, init_mode=INIT_MATCHING,
-           noise=tables.DEPOLARIZING, beta_scale=None):
+           noise=tables.DEPOLARIZING, beta_scale=None, scan=SCAN_COLOUR):
     """noise: tables.DEPOLARIZING (p = depolarizing rate) or tables.BITPHASE
     (p = flip rate q of each part); beta_scale: beta*/beta_bar for K = 1
-    (None = the model's default)."""
+    (None = the model's default); scan: SCAN_COLOUR or SCAN_RANDOM (no
+    trace)."""
+    if scan == SCAN_RANDOM and trace:
+        raise ValueError("the random scan keeps no trace")
     lat = geometry.Lattice(L)
     syn = np.asarray(syndromes, dtype=np.uint8).reshape(-1, lat.n_stab)
     syn = (syn != 0).astype(np.uint8)
@@ -43,10 +48,16 @@ def decode(L, syndromes, p, sweeps, seed, chains_per_class=1, n_temps=1, burn=0,
                                  indexing="ij")
     si, ci, ki, hi = (a.reshape(-1) for a in (si, ci, ki, hi))
     state0 = reps[si, ci] if n else np.zeros((0, lat.n_qubits), np.uint8)
-    res = chains.run(lat, state0, ids[si] if n else ids, ci, ki + 1, hi, tab[ki], seed,
-                     0, burn + sweeps, burn, trace=trace,
-                     check_invariants=check_invariants,
-                     syndromes=syn[si] if n else None, noise=noise)
+    if scan == SCAN_RANDOM:
+        res = chains.run_random(lat, state0, ids[si] if n else ids, ci, ki + 1, hi, tab[ki],
+                                seed, 0, burn + sweeps, burn,
+                                check_invariants=check_invariants,
+                                syndromes=syn[si] if n else None, noise=noise)
+    else:
+        res = chains.run(lat, state0, ids[si] if n else ids, ci, ki + 1, hi, tab[ki], seed,
+                         0, burn + sweeps, burn, trace=trace,
+                         check_invariants=check_invariants,
+                         syndromes=syn[si] if n else None, noise=noise)
 
     shape = (n, 4, K, C)
     S = res["S"].reshape(shape)
@@ -61,7 +72,8 @@ def decode(L, syndromes, p, sweeps, seed, chains_per_class=1, n_temps=1, burn=0,
     chosen = np.zeros(n, dtype=np.int64)
     for i in range(n):
         prob[i], mean[i], key[i], chosen[i] = estimator.estimate(
-            S[i], nf[i], C, sweeps, bb, lat.n_qubits, lat.n_stab, noise, bs)
+            S[i], nf[i], C, sweeps, bb, lat.n_qubits, lat.n_stab, noise, bs,
+            lat.n_stab if scan == SCAN_RANDOM else 4)
     correction = states[np.arange(n), chosen, K - 1, 0] if n else \
         np.zeros((0, lat.n_qubits), np.uint8)
     out = dict(class_prob=prob, mean_n=mean, sum_n=S, accepts=A, n_final=nf, key=key,

@@ -7,7 +7,9 @@ Sec. IV.A: as beta -> 0 every qubit is I, X, Y, Z with probability 1/4, so
 <n>_{0,E} = (3/4) n_q exactly; that endpoint is used in closed form.
 
 * pooled <n>_{E,k} = (sum over chains of S) / (chains * 4 * sweeps); with no
-  counted sweep it is the mean current weight of the chains.
+  counted sweep it is the mean current weight of the chains.  The random
+  scan samples n after every one of its n_stab steps per sweep, so there the
+  denominator is chains * n_stab * sweeps.
 * K = 1 (single temperature, beta* = beta_bar): trapezoid on {0, beta_bar},
   I_E = (beta_bar / 2) (f0 + <n>_{E,1}).
 * K = 1 with beta* below beta_bar (the bit/phase-flip model's beta* =
@@ -41,12 +43,14 @@ def simpson_weights(K):
     return [4 if k % 2 == 1 else 2 for k in range(1, K)] + [1]
 
 
-def estimate(S, n_final, chains, sweeps, beta_bar, n_q, n_stab, noise=0, beta_star=None):
+def estimate(S, n_final, chains, sweeps, beta_bar, n_q, n_stab, noise=0, beta_star=None,
+             samples_per_sweep=4):
     return estimate_log_z(S, n_final, chains, sweeps, beta_bar, n_q, n_stab, noise,
-                          beta_star)[:4]
+                          beta_star, samples_per_sweep)[:4]
 
 
-def estimate_log_z(S, n_final, chains, sweeps, beta_bar, n_q, n_stab, noise=0, beta_star=None):
+def estimate_log_z(S, n_final, chains, sweeps, beta_bar, n_q, n_stab, noise=0, beta_star=None,
+                   samples_per_sweep=4):
     """S, n_final: int64 [4, K, chains] for one syndrome.
 
     Returns (class_prob [4], mean_n [4] at the last temperature (beta_bar, or
@@ -56,7 +60,7 @@ def estimate_log_z(S, n_final, chains, sweeps, beta_bar, n_q, n_stab, noise=0, b
     S = np.asarray(S, dtype=np.int64)
     n_final = np.asarray(n_final, dtype=np.int64)
     K = S.shape[1]
-    T = 4 * sweeps
+    T = samples_per_sweep * sweeps
     src = S if T > 0 else n_final
     sums = src.sum(axis=2)                                     # [4, K] exact int
     denom = float(chains * T) if T > 0 else float(chains)

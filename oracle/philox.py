@@ -16,6 +16,8 @@ keying makes every draw a function of logical coordinates only):
   chain move    : (d >> 2, sweep, syndrome_id, 0<<30 | cls<<28 | temp<<20 | chain),
                   draw d of the sweep uses word d & 3
   error sampler : (q >> 1, 0, sample_id, 1<<30), qubit q uses words 2(q&1), 2(q&1)+1
+  random scan   : (t >> 1, sweep, syndrome_id, 2<<30 | cls<<28 | temp<<20 | chain),
+                  step t of the sweep uses words 2(t&1) (site) and 2(t&1)+1 (accept)
 
 Arithmetic is done on uint64 numpy arrays and masked to 32 bits, vectorised
 over any number of counters.
@@ -31,6 +33,7 @@ MASK = 0xFFFFFFFF
 
 DOMAIN_CHAIN = 0
 DOMAIN_SAMPLER = 1
+DOMAIN_RANDOM_SCAN = 2
 
 
 def philox4x32_10(c0, c1, c2, c3, k0, k1):
@@ -56,12 +59,12 @@ def seed_key(seed):
     return seed & MASK, seed >> 32
 
 
-def chain_ctr3(cls, temp, chain):
+def chain_ctr3(cls, temp, chain, domain=DOMAIN_CHAIN):
     """Fourth counter word of a chain-move draw; arguments broadcast."""
     cls = np.asarray(cls, dtype=np.uint64)
     temp = np.asarray(temp, dtype=np.uint64)
     chain = np.asarray(chain, dtype=np.uint64)
-    return ((np.uint64(DOMAIN_CHAIN) << np.uint64(30)) | (cls << np.uint64(28))
+    return ((np.uint64(domain) << np.uint64(30)) | (cls << np.uint64(28))
             | (temp << np.uint64(20)) | chain)
 
 
