@@ -91,6 +91,14 @@ enum mcmc_status {
 /* flags */
 #define MCMC_TRACE 1u  /* write n after every colour phase to d_trace          */
 #define MCMC_RESUME 2u /* start from d_chain_state instead of the class starts */
+#define MCMC_RANDOM_SCAN 4u /* Sec. IV's chain: each step applies the Metropolis
+                               rule to one stabilizer chosen uniformly at random
+                               (Philox block t>>1 of sweep s at counter (t>>1, s,
+                               syndrome_id, 2<<30 | cls<<28 | temp<<20 | chain),
+                               word 2(t&1) -> site floor(u n_stab / 2^32), word
+                               2(t&1)+1 -> acceptance); n_stab steps per sweep,
+                               n summed after every step (d_sum_n counts
+                               n_stab samples per sweep).  Not with MCMC_TRACE. */
 
 /* class starts (Sec. IV: one starting configuration per class, consistent
  * with the syndrome) */
@@ -113,7 +121,7 @@ typedef struct mcmc_params {
                           sweep_begin-1); must be 0 otherwise                   */
   double p;            /* error rate of the noise model (beta_bar > 0)          */
   uint64_t seed;       /* Philox key                                            */
-  uint32_t flags;      /* MCMC_TRACE | MCMC_RESUME                              */
+  uint32_t flags;      /* MCMC_TRACE | MCMC_RESUME | MCMC_RANDOM_SCAN           */
   uint32_t init;       /* MCMC_INIT_CANONICAL or MCMC_INIT_MATCHING             */
   uint32_t noise;      /* MCMC_NOISE_DEPOLARIZING (0) or MCMC_NOISE_BITPHASE    */
   uint32_t reserved;   /* must be 0                                             */

@@ -11,12 +11,13 @@ import numpy as np
 
 from . import _lib
 from ._lib import (MCMC_INIT_CANONICAL, MCMC_INIT_MATCHING, MCMC_L_MAX, MCMC_L_MIN,
-                   MCMC_NOISE_BITPHASE, MCMC_NOISE_DEPOLARIZING, MCMC_RESUME, MCMC_TRACE,
-                   McmcError, Params)
+                   MCMC_NOISE_BITPHASE, MCMC_NOISE_DEPOLARIZING, MCMC_RANDOM_SCAN, MCMC_RESUME,
+                   MCMC_TRACE, McmcError, Params)
 
 __all__ = ["Params", "McmcError", "geometry", "lattice", "acceptance_table", "workspace_size",
            "chain_state_size", "decode_batch", "sample_errors", "init_representatives",
-           "unpack_chain_state", "MCMC_TRACE", "MCMC_RESUME", "MCMC_L_MIN", "MCMC_L_MAX",
+           "unpack_chain_state", "MCMC_TRACE", "MCMC_RESUME", "MCMC_RANDOM_SCAN", "MCMC_L_MIN",
+           "MCMC_L_MAX",
            "MCMC_INIT_CANONICAL", "MCMC_INIT_MATCHING", "MCMC_NOISE_DEPOLARIZING",
            "MCMC_NOISE_BITPHASE", "params_table", "MixedPlan"]
 
@@ -101,11 +102,12 @@ def chain_state_size(prm, n):
 def decode_batch(syndromes, L, p, sweeps, seed, chains=1, n_temps=1, burn=0, syndrome_ids=None,
                  want_sums=False, want_correction=True, trace=False, chain_state=None,
                  resume_from=None, workspace=None, init=MCMC_INIT_MATCHING,
-                 noise=MCMC_NOISE_DEPOLARIZING, beta_scale=0.0):
+                 noise=MCMC_NOISE_DEPOLARIZING, beta_scale=0.0, random_scan=False):
     """Decode a [n, n_stab] uint8 device tensor of syndromes.  `noise` picks
     the error model p refers to (depolarizing, or independent bit/phase flips
     of rate p per part); `beta_scale` sets beta*/beta_bar for n_temps = 1
-    (0: the model's default).
+    (0: the model's default); `random_scan` runs Sec. IV's one-random-
+    stabilizer-per-step chains instead of the colour-phased sweeps.
 
     Returns a dict of device tensors: class_prob [n,4] f64, mean_n [n,4] f64,
     chosen [n] u8, and when requested correction [n,n_q] u8, sum_n/accepts
@@ -120,7 +122,8 @@ def decode_batch(syndromes, L, p, sweeps, seed, chains=1, n_temps=1, burn=0, syn
     if syndromes.dtype != torch.uint8 or syndromes.dim() != 2 or syndromes.shape[1] != ns:
         raise ValueError(f"syndromes must be uint8 [n, {ns}]")
     syndromes = syndromes.contiguous()
-    flags = (_lib.MCMC_TRACE if trace else 0) | (_lib.MCMC_RESUME if resume_from is not None else 0)
+    flags = ((_lib.MCMC_TRACE if trace else 0) | (_lib.MCMC_RESUME if resume_from is not None else 0)
+             | (_lib.MCMC_RANDOM_SCAN if random_scan else 0))
     begin = 0 if resume_from is None else int(resume_from[1])
     prm = make_params(L, p, sweeps, seed, chains, n_temps, burn, begin, flags, init, noise,
                       beta_scale)

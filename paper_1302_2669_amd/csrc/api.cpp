@@ -84,7 +84,8 @@ int check_params(const mcmc_params* prm, int64_t n) {
   if (prm->chains < 1 || prm->chains > MCMC_CHAINS_MAX) return MCMC_ERANGE;
   if (prm->burn < 0 || prm->sweeps < 0) return MCMC_ERANGE;
   if ((int64_t)prm->burn + prm->sweeps > MCMC_SWEEPS_MAX) return MCMC_ERANGE;
-  if (prm->flags & ~(MCMC_TRACE | MCMC_RESUME)) return MCMC_EINVAL;
+  if (prm->flags & ~(MCMC_TRACE | MCMC_RESUME | MCMC_RANDOM_SCAN)) return MCMC_EINVAL;
+  if ((prm->flags & MCMC_RANDOM_SCAN) && (prm->flags & MCMC_TRACE)) return MCMC_EINVAL;
   if (prm->init != MCMC_INIT_CANONICAL && prm->init != MCMC_INIT_MATCHING) return MCMC_EINVAL;
   if (prm->flags & MCMC_RESUME) {
     if (prm->sweep_begin < 0 || prm->sweep_begin > prm->burn + prm->sweeps) return MCMC_ERANGE;
@@ -291,9 +292,14 @@ int mcmc_decode_batch(const uint8_t* syndromes, const uint32_t* syndrome_ids, in
       a.resume_A = (const int64_t*)(cs + cl.A);
     }
   }
-  const int range = range_of(L);
-  const int64_t waves = std::min<int64_t>(a.n_tiles, default_waves(range, device_cus()));
-  st = hip_status(launch_chains(range, a, (int)waves, 256, s));
+  const bool random_scan = (prm->flags & MCMC_RANDOM_SCAN) != 0;
+  if (random_scan) {
+    st = hip_status(launch_chains_random(a, s));
+  } else {
+    const int range = range_of(L);
+    const int64_t waves = std::min<int64_t>(a.n_tiles, default_waves(range, device_cus()));
+    st = hip_status(launch_chains(range, a, (int)waves, 256, s));
+  }
   if (st != MCMC_OK) return st;
 
   if (chain_state) {  // n, S, A of every chain next to the rows
@@ -315,6 +321,7 @@ int mcmc_decode_batch(const uint8_t* syndromes, const uint32_t* syndrome_ids, in
   d.beta_bar = beta_bar_of(prm->noise, prm->p);
   d.beta_star = beta_top(prm);
   d.noise = (int32_t)prm->noise;
+  d.samples_per_sweep = random_scan ? n_stab(L) : 4;
   d.ln2 = log(2.0);
   d.n = n;
   d.S = S;

@@ -110,6 +110,10 @@ template <int R>
 hipError_t launch_chains_flip_range(const RunArgs& a, int waves, int wg, hipStream_t s);
 // Picks the kernel of `range` for a.noise.
 hipError_t launch_chains(int range, const RunArgs& a, int waves, int wg, hipStream_t s);
+// Random-scan chains of a uniform batch (g0, table0, a.noise; no trace):
+// one 64-lane workgroup per 64 chains, each lane's state in LDS.
+hipError_t launch_chains_random(const RunArgs& a, hipStream_t s);
+size_t random_scan_lds_bytes(int L);
 hipError_t launch_zero(uint32_t* p, int64_t n, hipStream_t s);
 
 // Class starts of syndromes given either implicitly (L, n: syndrome s at
@@ -138,6 +142,7 @@ struct DecideArgs {
   double beta_bar;             // uniform batch
   double beta_star;            // uniform batch: the K = 1 temperature (beta_bar by default)
   int32_t noise;               // uniform batch: beta=0 endpoint 3/4 n_q (0) or n_q (1)
+  int32_t samples_per_sweep;   // uniform batch: n samples per sweep, 0 => 4 (colour phases)
   double ln2;                  // log 2 from the host's libm
   int64_t n;
   const int64_t* S;            // per chain

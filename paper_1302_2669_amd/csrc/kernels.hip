@@ -162,7 +162,8 @@ hipError_t launch_unpack(int L, int noise, const uint32_t* rows, int64_t count, 
 // ---------------------------------------------------------------------------
 // Estimator and decision (Eq. main, Sec. IV.A), one thread per syndrome, FP64
 // in a fixed order with no contraction:
-//   mean_{E,k} = (sum_c S) / (C * 4 * sweeps)   (mean final weight if sweeps = 0)
+//   mean_{E,k} = (sum_c S) / (C * 4 * sweeps)   (mean final weight if sweeps = 0;
+//                n_stab samples per sweep instead of 4 for the random scan)
 //   K = 1 : I_E = (beta* / 2)(f0 + mean_{E,1}) + (beta_bar - beta*) mean_{E,1}
 //           (trapezoid to the sampled temperature, <n> held above it; the
 //           plain trapezoid when beta* = beta_bar)
@@ -180,6 +181,7 @@ __global__ void __launch_bounds__(128) decide_kernel(const DecideArgs a) {
   int64_t orig, chain_off, rows_off, corr_off;
   double beta_bar, beta_star;
   int noise = 0;
+  int64_t per_sweep = 4;
   if (a.items) {
     const ItemDesc it = a.items[s];
     g = a.groups[it.group];
@@ -198,11 +200,12 @@ __global__ void __launch_bounds__(128) decide_kernel(const DecideArgs a) {
     beta_bar = a.beta_bar;
     beta_star = a.beta_star;
     noise = a.noise;
+    if (a.samples_per_sweep > 0) per_sweep = a.samples_per_sweep;
   }
   const int K = g.K, C = g.C, L = g.L;
   const int sweeps = g.sweep_end - g.burn;
   const bool counted = sweeps > 0;
-  const double denom = counted ? (double)((int64_t)C * 4 * sweeps) : (double)C;
+  const double denom = counted ? (double)((int64_t)C * per_sweep * sweeps) : (double)C;
   const double nq = (double)(2 * L * L - 2 * L + 1);
   const double f0 = noise ? nq : 0.75 * nq;
   const double log_z0 = (double)(2 * L * (L - 1)) * a.ln2;

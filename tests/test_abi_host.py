@@ -81,6 +81,7 @@ def _ws(**kw):
     (dict(n_temps=3), -1), (dict(n_temps=0), -2), (dict(n_temps=66), -2),
     (dict(chains=0), -2), (dict(sweeps=-1), -2), (dict(burn=-2), -2),
     (dict(L=30), -2), (dict(p=0.8), -2), (dict(flags=8), -1), (dict(sweep_begin=3), -1),
+    (dict(flags=5), -1),
     (dict(init=2), -1), (dict(noise=2), -1), (dict(noise=1, p=0.5), -2),
     (dict(noise=1, p=0.0), -2), (dict(beta_scale=-0.5), -2), (dict(beta_scale=4.5), -2),
     (dict(beta_scale=float("nan")), -2), (dict(n_temps=2, beta_scale=0.85), -2),

@@ -1,0 +1,124 @@
+"""Random-scan chains (Sec. IV: one uniformly random stabilizer per step) on
+the GPU, through the C-ABI: bit-exact with the oracle's random scan, and the
+same stationary averages as the colour-phased kernels."""
+
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+import paper_1302_2669_amd as mc  # noqa: E402
+from oracle import decoder, geometry, sampler, tables  # noqa: E402
+
+from paper_1302_2669_amd.inputs import SEED_L9  # noqa: E402
+
+DEV = "cuda"
+RTOL = 1e-12
+
+
+def setup_module(module):
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a HIP device")
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def to_np(d):
+    torch.cuda.synchronize()
+    return {k: v.cpu().numpy() for k, v in d.items()}
+
+
+CASES = [
+    # L, noise, p, sweeps, burn, chains, K, n
+    (2, 0, 0.15, 20, 3, 3, 1, 6),
+    (3, 0, 0.10, 12, 2, 2, 1, 6),
+    (3, 1, 0.08, 10, 0, 2, 2, 5),
+    (5, 0, 0.18, 4, 1, 2, 1, 5),
+    (5, 1, 0.10, 4, 0, 1, 1, 4),
+    (9, 0, 0.15, 2, 0, 2, 1, 3),
+    (13, 0, 0.15, 2, 1, 1, 1, 2),
+    (13, 1, 0.10, 2, 0, 1, 2, 2),
+    (16, 0, 0.12, 1, 0, 1, 1, 2),
+    (17, 0, 0.16, 1, 0, 1, 1, 2),
+    (25, 1, 0.10, 1, 0, 1, 1, 2),
+]
+
+
+@pytest.mark.parametrize("L,noise,p,sweeps,burn,chains,K,n", CASES)
+def test_random_scan_parity(L, noise, p, sweeps, burn, chains, K, n):
+    say(f"random scan L={L} noise={noise} p={p} sweeps={sweeps} burn={burn} chains={chains} "
+        f"K={K} n={n}")
+    lat = geometry.Lattice(L)
+    syn, _, _ = sampler.sample(lat, p, SEED_L9 + 3 * L, np.arange(n), noise=noise)
+    ids = np.arange(n) * 3 + 2
+    s = torch.from_numpy(syn).to(DEV)
+    out = mc.decode_batch(s, L, p, sweeps, SEED_L9, chains=chains, n_temps=K, burn=burn,
+                          syndrome_ids=torch.from_numpy(ids), want_sums=True, chain_state=True,
+                          noise=noise, random_scan=True)
+    g = to_np({k: v for k, v in out.items() if k != "chain_state"})
+    st, w = mc.unpack_chain_state(out["chain_state"], n, L, p, sweeps, SEED_L9, chains, K, burn,
+                                  noise=noise)
+    o = decoder.decode(L, syn, p, sweeps, SEED_L9, chains_per_class=chains, n_temps=K, burn=burn,
+                       syndrome_ids=ids, noise=noise, scan=decoder.SCAN_RANDOM)
+    assert np.array_equal(g["sum_n"], o["sum_n"]), "energy sums differ"
+    assert np.array_equal(g["accepts"], o["accepts"]), "accept counts differ"
+    assert np.array_equal(st.cpu().numpy(), o["states"]), "final states differ"
+    assert np.array_equal(w.cpu().numpy(), o["n_final"].astype(np.int32)), "final energies differ"
+    assert np.array_equal(g["chosen"], o["chosen"])
+    assert np.array_equal(g["correction"], o["correction"])
+    np.testing.assert_allclose(g["class_prob"], o["class_prob"], rtol=RTOL, atol=0)
+    np.testing.assert_allclose(g["mean_n"], o["mean_n"], rtol=RTOL, atol=0)
+
+
+def test_random_scan_resume_is_bit_exact():
+    say("random scan resume")
+    L, p, chains, sweeps, burn, n = 7, 0.12, 2, 12, 3, 8
+    lat = geometry.Lattice(L)
+    syn = torch.from_numpy(sampler.sample(lat, p, 4, np.arange(n))[0]).to(DEV)
+    kw = dict(chains=chains, burn=burn, want_sums=True, random_scan=True)
+    whole = mc.decode_batch(syn, L, p, sweeps, 5, chain_state=True, **kw)
+    first = mc.decode_batch(syn, L, p, 7 - burn, 5, chain_state=True, **kw)
+    second = mc.decode_batch(syn, L, p, sweeps, 5, resume_from=(first["chain_state"], 7), **kw)
+    a = to_np({k: v for k, v in whole.items() if k != "chain_state"})
+    b = to_np({k: v for k, v in second.items() if k != "chain_state"})
+    for k in ("sum_n", "accepts", "chosen", "correction", "class_prob", "mean_n"):
+        assert np.array_equal(a[k], b[k]), k
+
+
+def test_trace_is_rejected_with_random_scan():
+    s = torch.zeros((2, mc.geometry(5)[1]), dtype=torch.uint8, device=DEV)
+    with pytest.raises(mc.McmcError) as e:
+        mc.decode_batch(s, 5, 0.1, 3, 1, trace=True, random_scan=True)
+    assert e.value.status == -1
+
+
+@pytest.mark.parametrize("noise,p", [(0, 0.10), (1, 0.07)])
+def test_scans_agree_in_equilibrium(noise, p):
+    """L = 5: per (syndrome, class) the pooled <n> of the random scan and of
+    the colour-phased scan estimate the same equilibrium average; their
+    differences, in units of the combined standard error, have mean ~0 and
+    spread ~1 over 256 syndromes x 4 classes."""
+    L, n, chains, sweeps, burn = 5, 256, 8, 300, 100
+    say(f"scan agreement L={L} noise={noise} p={p}")
+    syn, _, _ = mc.sample_errors(L, p, 0x5CA9, n, device=DEV, noise=noise)
+    res = {}
+    for rs in (False, True):
+        out = mc.decode_batch(syn, L, p, sweeps, 0x5CA9 + rs, chains=chains, burn=burn,
+                              want_sums=True, want_correction=False, noise=noise, random_scan=rs)
+        per = 4 if not rs else 2 * L * (L - 1)
+        S = out["sum_n"].double().cpu().numpy()[:, :, 0, :] / (per * sweeps)   # [n, 4, chains]
+        res[rs] = (S.mean(axis=2), S.std(axis=2, ddof=1) / np.sqrt(chains))
+    (m0, s0), (m1, s1) = res[False], res[True]
+    ok = (s0 > 0) & (s1 > 0)
+    z = ((m0 - m1) / np.sqrt(s0 ** 2 + s1 ** 2))[ok]
+    say(f"  z mean {z.mean():.3f}, z std {z.std():.3f}, {z.size} pairs")
+    assert z.size > 500
+    assert abs(z.mean()) < 5 / np.sqrt(z.size) + 0.05
+    assert 0.7 < z.std() < 1.5
