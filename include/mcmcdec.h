@@ -478,6 +478,78 @@ int mcmc_gated_decode(mcmc_gated* gated, const float* d_params, const uint8_t* d
                       int64_t* h_counts, void* d_workspace, size_t workspace_bytes,
                       void* stream);
 
+/*
+ * Imperfect stabilizer measurements (Sec. VI).  Stabilizers are measured in
+ * `rounds` = T rounds; before round t every data qubit suffers depolarizing
+ * noise of rate p (interval t) and every outcome of rounds 0..T-2 is wrong
+ * with probability p_m; the last round is perfect.  Round t reports
+ * s_t = syn(E_0 ... E_t) xor M_t.  A hypothesis (E_0..E_{T-1}, M_0..M_{T-2})
+ * with n data errors and m wrong outcomes has weight exp(-beta_bar (n + xi m)),
+ * xi = log((1-p_m)/p_m) / beta_bar.  Chains (one per class and replica, at
+ * beta_bar) move by spatial stabilizers within an interval and by Sec. VI's
+ * time moves (a Pauli on one qubit in intervals t and t+1 with the outcomes
+ * of round t that it anticommutes with toggled).  A sweep is every spatial
+ * move (t = 0..T-1, sites in order) then every time move (t = 0..T-2,
+ * qubits in order, X before Z); draw d of the sweep is word d & 3 of Philox
+ * at (d >> 2, sweep, id, 3<<30 | cls<<28 | 1<<20 | chain).  A move with
+ * E = dn + xi dm <= 0 is taken, else iff u < floor(2^32 exp(-beta_bar E)).
+ * n and m are summed after each half of a counted sweep; the decision is the
+ * class with the smallest S_n + xi S_m (float64), ties to the lowest class.
+ * Class starts: every flipped outcome before the last round blamed on the
+ * measurement (M_t = s_t, t < T-1), no data error before the last interval,
+ * and E_{T-1} the class-c MCMC_INIT_MATCHING start of s_{T-1}.
+ * The per-chain state lives in LDS: ERANGE when
+ * T ceil(n_q/16) + (T-1) ceil(n_stab/32) words per chain (times 64 chains)
+ * plus the lattice tables exceed 160 KiB (e.g. L = 13 allows T <= 21).
+ */
+#define MCMC_ROUNDS_MAX 64
+
+typedef struct mcmc_spacetime_params {
+  int32_t L;          /* MCMC_L_MIN..MCMC_L_MAX                               */
+  int32_t rounds;     /* T, 1..MCMC_ROUNDS_MAX (T = 1: one perfect round)      */
+  int32_t chains;     /* chains per class, >= 1                                */
+  int32_t burn;       /* uncounted sweeps, >= 0                                */
+  int32_t sweeps;     /* counted sweeps, >= 0                                  */
+  int32_t reserved;   /* must be 0                                             */
+  double p;           /* depolarizing rate per interval, 0 < p < 0.75          */
+  double p_m;         /* outcome error rate, 0 < p_m < 0.5                     */
+  uint64_t seed;      /* Philox key                                            */
+} mcmc_spacetime_params;
+
+/* Bytes of device workspace for n observation histories. */
+int mcmc_spacetime_workspace_size(const mcmc_spacetime_params* h_prm, int64_t n,
+                                  size_t* h_bytes);
+
+/* Host tables of a decode: spatial thresholds [4] (Delta n = 1..4), time-move
+ * thresholds [25] at (dn+2)*5 + dm+2, the always-accept mask (bit (dn+2)*5 +
+ * dm+2 set iff dn + xi dm <= 0) and xi.  Any pointer may be NULL. */
+int mcmc_spacetime_tables(const mcmc_spacetime_params* h_prm, uint32_t* h_spatial,
+                          uint32_t* h_time, uint32_t* h_always, double* h_xi);
+
+/*
+ * Decode n observation histories d_obs [n][T][n_stab] uint8 (nonzero = -1
+ * outcome).  d_ids [n] Philox counter word 2 (NULL => i).  Outputs (device):
+ * d_class_prob [n][4] (Eq. main, trapezoid on [0, beta_bar], beta = 0
+ * endpoint 3/4 n_q T + xi n_stab (T-1)/2), d_mean_n / d_mean_m [n][4] pooled
+ * <n>, <m> (or NULL), d_sum_n / d_sum_m / d_accepts [n][4][chains] int64 (or
+ * NULL), d_chosen [n] (required), d_correction [n][n_q] the accumulated data
+ * error of chain 0 of the chosen class (or NULL).  Asynchronous on `stream`.
+ */
+int mcmc_decode_spacetime(const uint8_t* d_obs, const uint32_t* d_ids, int64_t n,
+                          const mcmc_spacetime_params* h_prm, double* d_class_prob,
+                          double* d_mean_n, double* d_mean_m, int64_t* d_sum_n, int64_t* d_sum_m,
+                          int64_t* d_accepts, uint8_t* d_chosen, uint8_t* d_correction,
+                          void* d_workspace, size_t workspace_bytes, void* stream);
+
+/* Samples of the model for ids id_base + i: interval t's data errors follow
+ * mcmc_sample_errors' rule with counter word 1 = 1 + t; outcome k of round
+ * t < T-1 is wrong iff word k & 3 of Philox at (k >> 2, 0x80000000 | t, id,
+ * 1<<30) is below floor(p_m 2^32).  d_obs [n][T][n_stab], d_true_class [n]
+ * (class of E_0 ... E_{T-1}). */
+int mcmc_sample_spacetime(int32_t L, int32_t rounds, double p, double p_m, uint64_t seed,
+                          uint32_t id_base, int64_t n, uint8_t* d_obs, uint8_t* d_true_class,
+                          void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -33,9 +33,14 @@ is word d & 3 of Philox at counter
 After the spatial half and after the time half of a counted sweep, n is added
 to S_n and m to S_m.
 
-Class starts: no wrong outcome (M = 0), E_t = class-0 representative of the
-syndrome change s_t xor s_{t-1} (s_{-1} = 0) for t < T-1, and E_{T-1} the
-class-c representative of its change, so that C_{T-1} is in class c.
+Class starts (Sec. VI names none): every flipped outcome before the last
+round is blamed on the measurement, M_t = s_t for t < T-1, with no data error
+before the last interval, and E_{T-1} is the class-c matching start of the
+perfect last round's syndrome s_{T-1} (the single-round decoder's start).
+Each true data error is then relaxed back to its interval by time moves that
+remove two wrong outcomes each, all downhill; explaining every syndrome
+change by data strings instead (canonical strings per interval) leaves the
+chains stuck far above the true energy at beta_bar.
 
 Sampling: interval t's data errors use the depolarizing rule with counter
 word 1 = 1 + t (the single-round sampler uses 0); round t's outcome k
@@ -137,16 +142,11 @@ def starts(lat, obs):
     """Class starts of one observation history [T, n_stab]: (E [4, T, n_q],
     M [4, T, n_stab])."""
     T = obs.shape[0]
-    prev = np.zeros(lat.n_stab, dtype=np.uint8)
     E = np.zeros((4, T, lat.n_qubits), dtype=np.uint8)
-    for t in range(T):
-        reps = init.representatives(lat, obs[t] ^ prev)
-        if t < T - 1:
-            E[:, t] = reps[0]
-        else:
-            E[:, t] = reps
-        prev = obs[t]
-    return E, np.zeros((4, T, lat.n_stab), dtype=np.uint8)
+    E[:, T - 1] = init.matching_representatives(lat, obs[T - 1])
+    M = np.zeros((4, T, lat.n_stab), dtype=np.uint8)
+    M[:, :T - 1] = obs[:T - 1]
+    return E, M
 
 
 def run(lat, E, M, syndrome_id, cls, chain, beta, xi, seed, sweep_begin, sweep_end, burn,

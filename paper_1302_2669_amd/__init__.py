@@ -19,7 +19,8 @@ __all__ = ["Params", "McmcError", "geometry", "lattice", "acceptance_table", "wo
            "unpack_chain_state", "MCMC_TRACE", "MCMC_RESUME", "MCMC_RANDOM_SCAN", "MCMC_L_MIN",
            "MCMC_L_MAX",
            "MCMC_INIT_CANONICAL", "MCMC_INIT_MATCHING", "MCMC_NOISE_DEPOLARIZING",
-           "MCMC_NOISE_BITPHASE", "params_table", "MixedPlan"]
+           "MCMC_NOISE_BITPHASE", "params_table", "MixedPlan", "spacetime_params",
+           "spacetime_tables", "sample_spacetime", "decode_spacetime"]
 
 
 def _torch():
@@ -202,6 +203,77 @@ def unpack_chain_state(chain_state, n, L, p, sweeps, seed, chains=1, n_temps=1, 
                                              _stream(chain_state.device))
     _lib.check(st, "mcmc_unpack_chain_state")
     return states, weights
+
+
+def spacetime_params(L, rounds, p, p_m, sweeps, seed, chains=1, burn=0):
+    return _lib.SpaceTimeParams(L=int(L), rounds=int(rounds), chains=int(chains), burn=int(burn),
+                                sweeps=int(sweeps), reserved=0, p=float(p), p_m=float(p_m),
+                                seed=int(seed) & ((1 << 64) - 1))
+
+
+def spacetime_tables(prm):
+    """(spatial [4], time [5, 5] indexed (dn+2, dm+2), always [5, 5] bool, xi)."""
+    sp = np.zeros(4, dtype=np.uint32)
+    tt = np.zeros(25, dtype=np.uint32)
+    al = ctypes.c_uint32()
+    xi = ctypes.c_double()
+    _lib.check(_lib._lib().mcmc_spacetime_tables(ctypes.byref(prm), sp.ctypes.data,
+                                                 tt.ctypes.data, ctypes.byref(al),
+                                                 ctypes.byref(xi)), "mcmc_spacetime_tables")
+    always = np.array([(al.value >> e) & 1 for e in range(25)], dtype=bool).reshape(5, 5)
+    return sp, tt.reshape(5, 5), always, xi.value
+
+
+def sample_spacetime(L, rounds, p, p_m, seed, n, device="cuda", id_base=0):
+    """(observations [n, rounds, n_stab] u8, true_class [n] u8) of the
+    imperfect-measurement model."""
+    torch = _torch()
+    _, ns = geometry(L)
+    obs = torch.empty((n, rounds, ns), dtype=torch.uint8, device=device)
+    cls = torch.empty((n,), dtype=torch.uint8, device=device)
+    st = _lib._lib().mcmc_sample_spacetime(int(L), int(rounds), float(p), float(p_m),
+                                           int(seed) & ((1 << 64) - 1), int(id_base), int(n),
+                                           _ptr(obs), _ptr(cls), _stream(obs.device))
+    _lib.check(st, "mcmc_sample_spacetime")
+    return obs, cls
+
+
+def decode_spacetime(obs, L, p, p_m, sweeps, seed, chains=1, burn=0, syndrome_ids=None,
+                     want_sums=False, want_correction=True, workspace=None):
+    """Decode observation histories obs [n, rounds, n_stab] u8 (device) under
+    imperfect measurements.  Returns class_prob, mean_n, mean_m, chosen and
+    optionally correction, sum_n, sum_m, accepts ([n, 4, chains])."""
+    torch = _torch()
+    dev = obs.device
+    n, T = int(obs.shape[0]), int(obs.shape[1])
+    nq, ns = geometry(L)
+    if obs.dtype != torch.uint8 or obs.dim() != 3 or obs.shape[2] != ns:
+        raise ValueError(f"observations must be uint8 [n, rounds, {ns}]")
+    obs = obs.contiguous()
+    prm = spacetime_params(L, T, p, p_m, sweeps, seed, chains, burn)
+    b = ctypes.c_size_t()
+    _lib.check(_lib._lib().mcmc_spacetime_workspace_size(ctypes.byref(prm), n, ctypes.byref(b)),
+               "mcmc_spacetime_workspace_size")
+    out = {"class_prob": torch.empty((n, 4), dtype=torch.float64, device=dev),
+           "mean_n": torch.empty((n, 4), dtype=torch.float64, device=dev),
+           "mean_m": torch.empty((n, 4), dtype=torch.float64, device=dev),
+           "chosen": torch.empty((n,), dtype=torch.uint8, device=dev)}
+    if want_correction:
+        out["correction"] = torch.empty((n, nq), dtype=torch.uint8, device=dev)
+    if want_sums:
+        for k in ("sum_n", "sum_m", "accepts"):
+            out[k] = torch.empty((n, 4, chains), dtype=torch.int64, device=dev)
+    if workspace is None:
+        workspace = torch.empty((max(b.value, 1),), dtype=torch.uint8, device=dev)
+    ids = None if syndrome_ids is None else \
+        syndrome_ids.to(device=dev, dtype=torch.int32).contiguous()
+    st = _lib._lib().mcmc_decode_spacetime(
+        _ptr(obs), _ptr(ids), n, ctypes.byref(prm), _ptr(out["class_prob"]), _ptr(out["mean_n"]),
+        _ptr(out["mean_m"]), _ptr(out.get("sum_n")), _ptr(out.get("sum_m")),
+        _ptr(out.get("accepts")), _ptr(out["chosen"]), _ptr(out.get("correction")),
+        _ptr(workspace), workspace.numel(), _stream(dev))
+    _lib.check(st, "mcmc_decode_spacetime")
+    return out
 
 
 # numpy twin of the C mcmc_item struct (natural alignment, 48 bytes)

@@ -20,6 +20,7 @@ MCMC_TRACE, MCMC_RESUME, MCMC_RANDOM_SCAN = 1, 2, 4
 MCMC_INIT_CANONICAL, MCMC_INIT_MATCHING = 0, 1
 MCMC_NOISE_DEPOLARIZING, MCMC_NOISE_BITPHASE = 0, 1
 MCMC_CNN_BATCH_MAX = 1 << 24
+MCMC_ROUNDS_MAX = 64
 
 
 class McmcError(RuntimeError):
@@ -57,6 +58,20 @@ class Item(ctypes.Structure):
         ("p", ctypes.c_double),
         ("syn_offset", ctypes.c_int64),
         ("corr_offset", ctypes.c_int64),
+    ]
+
+
+class SpaceTimeParams(ctypes.Structure):
+    _fields_ = [
+        ("L", ctypes.c_int32),
+        ("rounds", ctypes.c_int32),
+        ("chains", ctypes.c_int32),
+        ("burn", ctypes.c_int32),
+        ("sweeps", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+        ("p", ctypes.c_double),
+        ("p_m", ctypes.c_double),
+        ("seed", ctypes.c_uint64),
     ]
 
 
@@ -139,6 +154,11 @@ _SIGNATURES = {
     "mcmc_gated_plan": (ctypes.c_int, [_P, ctypes.POINTER(_P)]),
     "mcmc_gated_decode": (ctypes.c_int, [_P, _P, _P, _P, _P, _I64, _P, _P, _P, _P,
                                          ctypes.POINTER(_I64), _P, _SZ, _P]),
+    "mcmc_spacetime_workspace_size": (ctypes.c_int, [ctypes.POINTER(SpaceTimeParams), _I64, _PSZ]),
+    "mcmc_spacetime_tables": (ctypes.c_int, [ctypes.POINTER(SpaceTimeParams), _P, _P, _P, _P]),
+    "mcmc_decode_spacetime": (ctypes.c_int, [_P, _P, _I64, ctypes.POINTER(SpaceTimeParams), _P,
+                                             _P, _P, _P, _P, _P, _P, _P, _P, _SZ, _P]),
+    "mcmc_sample_spacetime": (ctypes.c_int, [_I32, _I32, _D, _D, _U64, _U32, _I64, _P, _P, _P]),
 }
 
 _handle = None

@@ -164,6 +164,39 @@ hipError_t launch_sample_items(const ItemDesc* items, const GroupDesc* groups, i
                                uint32_t k0, uint32_t k1, uint8_t* syn, uint8_t* true_class,
                                hipStream_t s);
 
+// ---- imperfect measurements (space-time hypotheses) ---------------------------
+// LDS of one 64-chain workgroup of the space-time kernel must stay within this.
+constexpr size_t SPACETIME_LDS_MAX = 160 * 1024;
+size_t spacetime_lds_bytes(int L, int T);
+struct SpaceTimeArgs {
+  int32_t L, T, chains, burn, sweep_end;
+  int64_t n;                    // observation histories
+  int64_t n_tasks;              // n * 4 * chains
+  const uint32_t* ids;          // [n] or nullptr (=> i)
+  const uint8_t* obs;           // [n][T][n_stab] observed outcomes
+  const uint8_t* reps;          // [i*4 + cls][n_q] matching starts of the last round
+  const int32_t* rep_weight;    // [i*4 + cls]
+  uint32_t k0, k1;
+  uint32_t sp_thr[4];           // spatial moves: A[Delta n], Delta n = 1..4
+  uint32_t t_thr[25];           // time moves: [(dn+2)*5 + dm+2]
+  uint32_t t_always;            // bit (dn+2)*5 + dm+2: dn + xi dm <= 0
+  double xi, beta_bar;
+  int64_t *Sn, *Sm, *A;         // [n][4][chains]
+  int32_t *n_final, *m_final;
+  uint8_t* final_c;             // [n][4][n_q] accumulated error of chain 0, or nullptr
+  double *class_prob, *mean_n, *mean_m;
+  uint8_t* chosen;
+  uint8_t* correction;          // [n][n_q] or nullptr
+};
+hipError_t launch_spacetime_sample(int L, int T, uint32_t thr_d, uint32_t thr_m, uint32_t k0,
+                                   uint32_t k1, uint32_t id_base, int64_t n, uint8_t* obs,
+                                   uint8_t* true_class, hipStream_t s);
+// Copies the last round of every history: last [n][n_stab].
+hipError_t launch_spacetime_last(int64_t n, int T, int nstab, const uint8_t* obs, uint8_t* last,
+                                 hipStream_t s);
+hipError_t launch_spacetime_chains(const SpaceTimeArgs& a, hipStream_t s);
+hipError_t launch_spacetime_decide(const SpaceTimeArgs& a, hipStream_t s);
+
 // ---- device-built budget plans ----------------------------------------------
 // One code size, three groups by sweep budget: 0 = sweeps[0] (full), 1 =
 // sweeps[1] (short), 2 = sweeps[2] (none); route r of syndrome i puts it in

@@ -1,0 +1,394 @@
+// Imperfect stabilizer measurements (Sec. VI): Metropolis chains over
+// space-time hypotheses with energy n + xi m.
+//
+// A hypothesis of T measurement rounds holds the depolarizing data error E_t
+// of every interval t = 0..T-1 and the wrong outcomes M_t of every round
+// t < T-1 (the last round is perfect).  Round t reports
+// s_t = syn(E_0 ... E_t) xor M_t.  Moves that keep every s_t and the class of
+// the accumulated error:
+//   spatial (t, k): stabilizer k applied to E_t;
+//   time (t, q, P), t < T-1: Pauli P (X or Z) applied to qubit q in E_t and
+//     E_{t+1}, and M_t toggled on the stabilizers that anticommute with P on
+//     q (its plaquettes for X, its stars for Z) -- Sec. VI's deformation.
+// A sweep takes every spatial move (t, then site order) and then every time
+// move (t, q, X before Z); draw d of the sweep (in that order) is word d & 3
+// of Philox at counter (d >> 2, sweep, syndrome_id,
+// 3<<30 | cls<<28 | 1<<20 | chain).  n and m are summed after each half of a
+// counted sweep.
+//
+// Mapping.  One lane per chain.  A hypothesis is T (2 n_q)-bit data planes
+// (16 qubits per word, qubit order) and T-1 n_stab-bit outcome planes: far
+// more state than registers hold, so it lives in LDS, word-major with the
+// wave's 64 lanes side by side (no bank conflicts), next to per-site qubit
+// lists and per-qubit stabilizer lists shared by the workgroup.  Moves run
+// in the exact sequential order above, so the chains are bit-identical to a
+// sequential implementation.  One 64-lane workgroup per 64 chains.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "device_common.h"
+#include "internal.h"
+
+namespace mcmc {
+namespace {
+
+constexpr int ST_LANES = 64;
+constexpr uint32_t ST_NONE = 0xFFFFu;
+
+__device__ __forceinline__ uint32_t pack2(uint32_t lo, uint32_t hi) { return lo | (hi << 16); }
+
+// ---- sampler ----------------------------------------------------------------
+// Interval t: the depolarizing rule of the single-round sampler with counter
+// word 1 = 1 + t; round t < T-1: outcome k wrong iff word k & 3 of Philox at
+// (k >> 2, 0x80000000 | t, id, 1<<30) is below floor(p_M 2^32).
+__global__ void __launch_bounds__(256) st_sample_kernel(int L, int T, uint32_t thr_d,
+                                                        uint32_t thr_m, uint32_t k0, uint32_t k1,
+                                                        uint32_t id_base, int64_t n,
+                                                        uint8_t* __restrict__ obs,
+                                                        uint8_t* __restrict__ true_class) {
+  __shared__ uint8_t acc[2 * 32 * 32];   // accumulated error, n_q <= 2*25*25
+  const int64_t smp = blockIdx.x;
+  if (smp >= n) return;
+  const uint32_t sid = id_base + (uint32_t)smp;
+  const int side = 2 * L - 1;
+  const int nq = 2 * L * L - 2 * L + 1;
+  const int nstab = 2 * L * (L - 1);
+  const int nstar = L * (L - 1);
+  for (int q = threadIdx.x; q < nq; q += blockDim.x) acc[q] = 0;
+  __syncthreads();
+  for (int t = 0; t < T; ++t) {
+    for (int pr = threadIdx.x; pr < (nq + 1) / 2; pr += blockDim.x) {
+      const uint4 w = philox4x32_10(make_uint4((uint32_t)pr, (uint32_t)(1 + t), sid, 1u << 30),
+                                    k0, k1);
+      for (int h = 0; h < 2; ++h) {
+        const int q = 2 * pr + h;
+        if (q >= nq) break;
+        const uint32_t u0 = h ? w.z : w.x;
+        const uint32_t u1 = h ? w.w : w.y;
+        const uint32_t type = (uint32_t)(((uint64_t)u1 * 3u) >> 32);
+        const uint8_t code = (uint8_t)(type == 0 ? 1 : (type == 1 ? 3 : 2));
+        if (u0 < thr_d) acc[q] ^= code;
+      }
+    }
+    __syncthreads();
+    uint8_t* o = obs + (smp * T + t) * nstab;
+    for (int k = threadIdx.x; k < nstab; k += blockDim.x) {
+      int r, c, bit;
+      if (k < nstar) {
+        r = 2 * (k / L) + 1; c = 2 * (k % L); bit = 2;
+      } else {
+        const int kk = k - nstar;
+        r = 2 * (kk / (L - 1)); c = 2 * (kk % (L - 1)) + 1; bit = 1;
+      }
+      int par = 0;
+      if (r > 0) par ^= (acc[((r - 1) * side + c) >> 1] & bit) != 0;
+      if (r < side - 1) par ^= (acc[((r + 1) * side + c) >> 1] & bit) != 0;
+      if (c > 0) par ^= (acc[(r * side + c - 1) >> 1] & bit) != 0;
+      if (c < side - 1) par ^= (acc[(r * side + c + 1) >> 1] & bit) != 0;
+      if (t < T - 1) {
+        const uint4 w = philox4x32_10(make_uint4((uint32_t)(k >> 2), 0x80000000u | (uint32_t)t,
+                                                 sid, 1u << 30), k0, k1);
+        par ^= word_of(w, k & 3) < thr_m;
+      }
+      o[k] = (uint8_t)par;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    int bx = 0, bz = 0;
+    for (int r = 0; r < side; r += 2) bx ^= acc[(r * side) >> 1] & 1;
+    for (int c = 0; c < side; c += 2) bz ^= (acc[c >> 1] >> 1) & 1;
+    true_class[smp] = (uint8_t)(bx + 2 * bz);
+  }
+}
+
+// ---- class starts: the perfect last round of every history -------------------
+__global__ void __launch_bounds__(256) st_last_kernel(int64_t n, int T, int nstab,
+                                                      const uint8_t* __restrict__ obs,
+                                                      uint8_t* __restrict__ last) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n * nstab) return;
+  const int64_t h = i / nstab;
+  last[i] = obs[(h * T + (T - 1)) * nstab + (i - h * nstab)] != 0;
+}
+
+// ---- chains -----------------------------------------------------------------
+__global__ void __launch_bounds__(ST_LANES) st_chain_kernel(const SpaceTimeArgs a) {
+  extern __shared__ uint32_t st_lds[];
+  const int L = a.L, T = a.T;
+  const int nq = 2 * L * L - 2 * L + 1;
+  const int nstab = 2 * L * (L - 1);
+  const int nstar = L * (L - 1);
+  const int WQ = (nq + 15) / 16;       // data words per interval
+  const int WM = (nstab + 31) / 32;    // outcome words per round
+  const int lane = threadIdx.x;
+  uint32_t* site_q = st_lds;                       // [nstab][2]: 4 qubits (16 bit each)
+  uint32_t* qubit_s = site_q + 2 * nstab;          // [nq][2]: plaquettes, stars of q
+  uint32_t* Ew = qubit_s + 2 * nq;                 // [T*WQ][64]
+  uint32_t* Mw = Ew + (int64_t)T * WQ * ST_LANES;  // [(T-1)*WM][64]
+
+  const int side = 2 * L - 1;
+  for (int s = lane; s < nstab; s += ST_LANES) {
+    uint32_t q[4] = {ST_NONE, ST_NONE, ST_NONE, ST_NONE};
+    int r, c;
+    if (s < nstar) { r = 2 * (s / L) + 1; c = 2 * (s % L); }
+    else { const int k = s - nstar; r = 2 * (k / (L - 1)); c = 2 * (k % (L - 1)) + 1; }
+    int k = 0;
+    if (r > 0) q[k++] = (uint32_t)(((r - 1) * side + c) >> 1);
+    if (r < side - 1) q[k++] = (uint32_t)(((r + 1) * side + c) >> 1);
+    if (c > 0) q[k++] = (uint32_t)((r * side + c - 1) >> 1);
+    if (c < side - 1) q[k++] = (uint32_t)((r * side + c + 1) >> 1);
+    site_q[2 * s] = pack2(q[0], q[1]);
+    site_q[2 * s + 1] = pack2(q[2], q[3]);
+  }
+  for (int qi = lane; qi < nq; qi += ST_LANES) {
+    // grid cell of qubit qi: index = (r * side + c) / 2 with r + c even
+    const int r = (2 * qi) / side;
+    const int c = 2 * qi - r * side;
+    uint32_t pl[2] = {ST_NONE, ST_NONE}, sr[2] = {ST_NONE, ST_NONE};
+    int np = 0, ns = 0;
+    const int dr[4] = {-1, 1, 0, 0}, dc[4] = {0, 0, -1, 1};
+    for (int d = 0; d < 4; ++d) {
+      const int rr = r + dr[d], cc = c + dc[d];
+      if (rr < 0 || rr >= side || cc < 0 || cc >= side) continue;
+      if (rr & 1) {  // star at (odd, even)
+        sr[ns++] = (uint32_t)(((rr - 1) / 2) * L + cc / 2);
+      } else {       // plaquette at (even, odd)
+        pl[np++] = (uint32_t)(nstar + (rr / 2) * (L - 1) + (cc - 1) / 2);
+      }
+    }
+    qubit_s[2 * qi] = pack2(pl[0], pl[1]);
+    qubit_s[2 * qi + 1] = pack2(sr[0], sr[1]);
+  }
+  __syncthreads();
+
+  const int64_t task = (int64_t)blockIdx.x * ST_LANES + lane;
+  if (task >= a.n_tasks) return;
+  const int C = a.chains;
+  const int64_t item = task / (4 * C);
+  const int rem = (int)(task - item * 4 * C);
+  const int cls = rem / C, chain = rem % C;
+  const uint32_t sid = a.ids ? a.ids[item] : (uint32_t)item;
+
+  // class start: every flipped outcome before the last round blamed on the
+  // measurement (M_t = s_t), no data error before the last interval, and the
+  // class-cls matching start of the last round's syndrome in interval T-1
+  int32_t n = 0, m = 0;
+  for (int k = 0; k < (T - 1) * WQ; ++k) Ew[k * ST_LANES + lane] = 0u;
+  {
+    const uint8_t* b = a.reps + (item * 4 + cls) * nq;
+    for (int w = 0; w < WQ; ++w) {
+      uint32_t word = 0;
+      for (int f = 0; f < 16; ++f) {
+        const int q = 16 * w + f;
+        if (q < nq) word |= (uint32_t)(b[q] & 3u) << (2 * f);
+      }
+      Ew[((T - 1) * WQ + w) * ST_LANES + lane] = word;
+    }
+    n = a.rep_weight[item * 4 + cls];
+  }
+  for (int t = 0; t + 1 < T; ++t) {
+    const uint8_t* o = a.obs + (item * T + t) * nstab;
+    for (int w = 0; w < WM; ++w) {
+      uint32_t word = 0;
+      for (int b = 0; b < 32; ++b) {
+        const int k = 32 * w + b;
+        if (k < nstab && o[k] != 0) word |= 1u << b;
+      }
+      Mw[(t * WM + w) * ST_LANES + lane] = word;
+      m += __builtin_popcount(word);
+    }
+  }
+
+  const uint32_t ctr3 = (3u << 30) | ((uint32_t)cls << 28) | (1u << 20) | (uint32_t)chain;
+  int64_t Sn = 0, Sm = 0, Acnt = 0;
+  for (int sweep = 0; sweep < a.sweep_end; ++sweep) {
+    const bool counted = sweep >= a.burn;
+    uint4 blk = make_uint4(0, 0, 0, 0);
+    uint32_t d = 0;
+    auto draw = [&]() -> uint32_t {
+      if ((d & 3u) == 0)
+        blk = philox4x32_10(make_uint4(d >> 2, (uint32_t)sweep, sid, ctr3), a.k0, a.k1);
+      const uint32_t u = word_of(blk, (int)(d & 3u));
+      ++d;
+      return u;
+    };
+    // spatial moves
+    for (int t = 0; t < T; ++t) {
+      uint32_t* E = Ew + t * WQ * ST_LANES + lane;
+      for (int s = 0; s < nstab; ++s) {
+        const uint32_t u = draw();
+        const bool star = s < nstar;
+        const uint32_t qq[4] = {site_q[2 * s] & 0xFFFFu, site_q[2 * s] >> 16,
+                                site_q[2 * s + 1] & 0xFFFFu, site_q[2 * s + 1] >> 16};
+        int delta = 0;
+        for (int k = 0; k < 4; ++k) {
+          if (qq[k] == ST_NONE) continue;
+          const uint32_t code = (E[(qq[k] >> 4) * ST_LANES] >> (2 * (qq[k] & 15u))) & 3u;
+          const int x = (int)(code & 1u), z = (int)(code >> 1);
+          delta += star ? (1 - z) * (1 - 2 * x) : (1 - x) * (1 - 2 * z);
+        }
+        const uint32_t thr = delta == 1 ? a.sp_thr[0]
+                           : (delta == 2 ? a.sp_thr[1] : (delta == 3 ? a.sp_thr[2] : a.sp_thr[3]));
+        if (delta <= 0 || u < thr) {
+          const uint32_t bit = star ? 1u : 2u;
+          for (int k = 0; k < 4; ++k) {
+            if (qq[k] == ST_NONE) continue;
+            E[(qq[k] >> 4) * ST_LANES] ^= bit << (2 * (qq[k] & 15u));
+          }
+          n += delta;
+          ++Acnt;
+        }
+      }
+    }
+    if (counted) { Sn += n; Sm += m; }
+    // time moves
+    for (int t = 0; t + 1 < T; ++t) {
+      uint32_t* E0 = Ew + t * WQ * ST_LANES + lane;
+      uint32_t* E1 = E0 + WQ * ST_LANES;
+      uint32_t* Mt = Mw + t * WM * ST_LANES + lane;
+      for (int q = 0; q < nq; ++q) {
+        const int wq = (q >> 4) * ST_LANES;
+        const int sh = 2 * (q & 15);
+        for (int kind = 0; kind < 2; ++kind) {
+          const uint32_t u = draw();
+          const uint32_t c0 = (E0[wq] >> sh) & 3u, c1 = (E1[wq] >> sh) & 3u;
+          int dn;
+          if (kind == 0)
+            dn = (1 - (int)(c0 >> 1)) * (1 - 2 * (int)(c0 & 1u)) +
+                 (1 - (int)(c1 >> 1)) * (1 - 2 * (int)(c1 & 1u));
+          else
+            dn = (1 - (int)(c0 & 1u)) * (1 - 2 * (int)(c0 >> 1)) +
+                 (1 - (int)(c1 & 1u)) * (1 - 2 * (int)(c1 >> 1));
+          const uint32_t ss = qubit_s[2 * q + kind];
+          const uint32_t sa = ss & 0xFFFFu, sb = ss >> 16;
+          int dm = 0;
+          if (sa != ST_NONE) dm += 1 - 2 * (int)((Mt[(sa >> 5) * ST_LANES] >> (sa & 31u)) & 1u);
+          if (sb != ST_NONE) dm += 1 - 2 * (int)((Mt[(sb >> 5) * ST_LANES] >> (sb & 31u)) & 1u);
+          const int e = (dn + 2) * 5 + (dm + 2);
+          if (((a.t_always >> e) & 1u) || u < a.t_thr[e]) {
+            const uint32_t bit = (kind == 0 ? 1u : 2u) << sh;
+            E0[wq] ^= bit;
+            E1[wq] ^= bit;
+            if (sa != ST_NONE) Mt[(sa >> 5) * ST_LANES] ^= 1u << (sa & 31u);
+            if (sb != ST_NONE) Mt[(sb >> 5) * ST_LANES] ^= 1u << (sb & 31u);
+            n += dn;
+            m += dm;
+            ++Acnt;
+          }
+        }
+      }
+    }
+    if (counted) { Sn += n; Sm += m; }
+  }
+
+  const int64_t out = item * 4 * C + rem;
+  a.Sn[out] = Sn;
+  a.Sm[out] = Sm;
+  a.A[out] = Acnt;
+  a.n_final[out] = n;
+  a.m_final[out] = m;
+  if (a.final_c && chain == 0) {  // accumulated data error of this hypothesis
+    uint8_t* o = a.final_c + (item * 4 + cls) * nq;
+    for (int w = 0; w < WQ; ++w) {
+      uint32_t word = 0;
+      for (int t = 0; t < T; ++t) word ^= Ew[(t * WQ + w) * ST_LANES + lane];
+      for (int f = 0; f < 16; ++f) {
+        const int q = 16 * w + f;
+        if (q < nq) o[q] = (uint8_t)((word >> (2 * f)) & 3u);
+      }
+    }
+  }
+}
+
+// ---- estimator --------------------------------------------------------------
+#pragma clang fp contract(off)
+__global__ void __launch_bounds__(128) st_decide_kernel(const SpaceTimeArgs a) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.n) return;
+  const int C = a.chains, L = a.L, T = a.T;
+  const int sweeps = a.sweep_end - a.burn;
+  const bool counted = sweeps > 0;
+  const double denom = counted ? (double)((int64_t)C * 2 * sweeps) : (double)C;
+  const double nq = (double)(2 * L * L - 2 * L + 1), nstab = (double)(2 * L * (L - 1));
+  const double f0 = 0.75 * nq * (double)T + a.xi * (0.5 * nstab * (double)(T - 1));
+  double key[4], logz[4];
+  for (int e = 0; e < 4; ++e) {
+    int64_t sn = 0, sm = 0;
+    for (int c = 0; c < C; ++c) {
+      const int64_t k = (i * 4 + e) * C + c;
+      sn += counted ? a.Sn[k] : (int64_t)a.n_final[k];
+      sm += counted ? a.Sm[k] : (int64_t)a.m_final[k];
+    }
+    key[e] = (double)sn + a.xi * (double)sm;
+    logz[e] = -((a.beta_bar / 2.0) * (f0 + key[e] / denom));
+    if (a.mean_n) a.mean_n[i * 4 + e] = (double)sn / denom;
+    if (a.mean_m) a.mean_m[i * 4 + e] = (double)sm / denom;
+  }
+  double mx = logz[0];
+  for (int e = 1; e < 4; ++e) mx = logz[e] > mx ? logz[e] : mx;
+  double ex[4];
+  for (int e = 0; e < 4; ++e) ex[e] = exp(logz[e] - mx);
+  const double tot = ((ex[0] + ex[1]) + ex[2]) + ex[3];
+  for (int e = 0; e < 4; ++e) a.class_prob[i * 4 + e] = ex[e] / tot;
+  int best = 0;
+  for (int e = 1; e < 4; ++e)
+    if (key[e] < key[best]) best = e;
+  a.chosen[i] = (uint8_t)best;
+  if (a.correction) {
+    const int nqi = 2 * L * L - 2 * L + 1;
+    const uint8_t* src = a.final_c + (i * 4 + best) * nqi;
+    for (int q = 0; q < nqi; ++q) a.correction[i * nqi + q] = src[q];
+  }
+}
+
+unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
+
+}  // namespace
+
+size_t spacetime_lds_bytes(int L, int T) {
+  const int nq = 2 * L * L - 2 * L + 1, nstab = 2 * L * (L - 1);
+  const size_t words = (size_t)2 * nstab + (size_t)2 * nq +
+                       ((size_t)T * ((nq + 15) / 16) + (size_t)(T - 1) * ((nstab + 31) / 32)) *
+                           ST_LANES;
+  return words * sizeof(uint32_t);
+}
+
+hipError_t launch_spacetime_sample(int L, int T, uint32_t thr_d, uint32_t thr_m, uint32_t k0,
+                                   uint32_t k1, uint32_t id_base, int64_t n, uint8_t* obs,
+                                   uint8_t* true_class, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(st_sample_kernel, dim3((unsigned)n), dim3(256), 0, s, L, T, thr_d, thr_m, k0,
+                     k1, id_base, n, obs, true_class);
+  return hipGetLastError();
+}
+
+hipError_t launch_spacetime_last(int64_t n, int T, int nstab, const uint8_t* obs, uint8_t* last,
+                                 hipStream_t s) {
+  const int64_t total = n * nstab;
+  if (total == 0) return hipSuccess;
+  hipLaunchKernelGGL(st_last_kernel, dim3(blocks_for(total, 256)), dim3(256), 0, s, n, T, nstab,
+                     obs, last);
+  return hipGetLastError();
+}
+
+hipError_t launch_spacetime_chains(const SpaceTimeArgs& a, hipStream_t s) {
+  if (a.n_tasks == 0) return hipSuccess;
+  const size_t lds = spacetime_lds_bytes(a.L, a.T);
+  if (lds > SPACETIME_LDS_MAX) return hipErrorInvalidValue;
+  const hipError_t e = hipFuncSetAttribute((const void*)st_chain_kernel,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)SPACETIME_LDS_MAX);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(st_chain_kernel, dim3(blocks_for(a.n_tasks, ST_LANES)), dim3(ST_LANES), lds,
+                     s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_spacetime_decide(const SpaceTimeArgs& a, hipStream_t s) {
+  if (a.n == 0) return hipSuccess;
+  hipLaunchKernelGGL(st_decide_kernel, dim3(blocks_for(a.n, 128)), dim3(128), 0, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace mcmc

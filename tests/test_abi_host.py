@@ -212,3 +212,48 @@ def test_gated_config_rejected_before_allocating():
         assert lib.mcmc_gated_create(ctypes.byref(cfg(**bad)), ctypes.byref(h)) == status, bad
     assert lib.mcmc_gated_create(None, ctypes.byref(h)) == -1
     assert lib.mcmc_gated_destroy(None) == 0
+
+
+@pytest.mark.parametrize("p,pm", [(0.05, 0.05), (0.1, 0.02), (0.15, 0.3), (0.03, 0.45)])
+def test_spacetime_tables_match_oracle(p, pm):
+    """Space-time thresholds and xi of the C side equal the oracle's."""
+    from oracle import spacetime as stm
+    prm = mc.spacetime_params(5, 3, p, pm, 10, 1)
+    sp, tt, always, xi = mc.spacetime_tables(prm)
+    assert xi == stm.xi_of(p, pm)
+    assert np.array_equal(sp, tables.acceptance_table(tables.beta_bar(p)))
+    o_thr, o_always = stm.time_table(tables.beta_bar(p), stm.xi_of(p, pm))
+    assert np.array_equal(always, o_always)
+    assert np.array_equal(tt, np.where(o_always, 0, o_thr))
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(rounds=0), -2), (dict(rounds=65), -2), (dict(p_m=0.5), -2), (dict(p_m=0.0), -2),
+    (dict(p=0.8), -2), (dict(L=26), -2), (dict(chains=0), -2), (dict(sweeps=-1), -2),
+    (dict(L=13, rounds=22), -2), (dict(L=25, rounds=6), -2),
+])
+def test_spacetime_validation(kw, status):
+    base = dict(L=5, rounds=3, p=0.05, p_m=0.05, sweeps=4, seed=1, chains=2)
+    base.update(kw)
+    prm = mc.spacetime_params(**base)
+    b = ctypes.c_size_t()
+    assert _lib._lib().mcmc_spacetime_workspace_size(ctypes.byref(prm), 8, ctypes.byref(b)) == status
+
+
+def test_spacetime_limits_and_reserved():
+    b = ctypes.c_size_t()
+    prm = mc.spacetime_params(13, 21, 0.05, 0.05, 4, 1)
+    assert _lib._lib().mcmc_spacetime_workspace_size(ctypes.byref(prm), 8, ctypes.byref(b)) == 0
+    prm.reserved = 3
+    assert _lib._lib().mcmc_spacetime_workspace_size(ctypes.byref(prm), 8, ctypes.byref(b)) == -1
+    lib = _lib._lib()
+    dummy = ctypes.c_void_p(0x1000)
+    assert lib.mcmc_sample_spacetime(5, 0, 0.05, 0.05, 1, 0, 4, dummy, dummy, None) == -2
+    assert lib.mcmc_sample_spacetime(5, 3, 0.05, 0.05, 1, 0, 4, None, dummy, None) == -1
+    good = mc.spacetime_params(5, 3, 0.05, 0.05, 4, 1)
+    assert lib.mcmc_decode_spacetime(None, None, 4, ctypes.byref(good), dummy, None, None, None,
+                                     None, None, dummy, None, dummy, 1 << 30, None) == -1
+    assert lib.mcmc_decode_spacetime(dummy, None, 4, ctypes.byref(good), dummy, None, None, None,
+                                     None, None, dummy, None, dummy, 16, None) == -5
+    assert lib.mcmc_decode_spacetime(dummy, None, 0, ctypes.byref(good), dummy, None, None, None,
+                                     None, None, dummy, None, None, 0, None) == 0

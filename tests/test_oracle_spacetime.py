@@ -85,7 +85,7 @@ def test_starts_are_consistent(L, T):
         E, M = stm.starts(lat, obs[i])
         assert np.array_equal(stm.observations(lat, E, M), np.broadcast_to(obs[i], (4,) + obs[i].shape))
         assert stm.hyp_class(lat, E).tolist() == [0, 1, 2, 3]
-        assert not M.any()
+        assert not M[:, T - 1].any() and not E[:, :T - 1].any()
 
 
 @pytest.mark.parametrize("L,T", [(2, 2), (3, 3), (4, 2)])
