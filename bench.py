@@ -60,11 +60,12 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=640)
     ap.add_argument("--no-budget-curve", action="store_true",
                     help="skip the logical error vs sweep budget curve")
-    ap.add_argument("--workload", choices=["metric", "mixed", "gated", "bitphase"],
+    ap.add_argument("--workload", choices=["metric", "mixed", "gated", "bitphase", "spacetime"],
                     default="metric",
                     help="metric: L=13 p=0.15 (default); mixed: L in 5..25, p in [0.05,0.18]; "
                          "gated: gate network trained and timed against the plain decoder; "
-                         "bitphase: L=13, independent bit/phase flips q=0.10")
+                         "bitphase: L=13, independent bit/phase flips q=0.10; "
+                         "spacetime: L=7, 7 measurement rounds, p = p_M = 0.02")
     ap.add_argument("--gate-train", type=int, default=1_000_000)
     ap.add_argument("--gate-epochs", type=int, default=4)
     ap.add_argument("--gate-eval", type=int, default=100_000)
@@ -89,6 +90,8 @@ def main():
         return bench_gated(args, mc, torch, dev)
     if args.workload == "bitphase":
         return bench_bitphase(args, mc, torch, dev)
+    if args.workload == "spacetime":
+        return bench_spacetime(args, mc, torch, dev)
     n = args.batch
     nq, ns = mc.geometry(L)
     steps, warm = args.steps, args.warmup
@@ -498,6 +501,110 @@ def bench_bitphase(args, mc, torch, dev):
                      "updates_per_launch": n * updates_per_syndrome},
         "cpu_baseline": cpu,
     }
+    print(json.dumps(line), flush=True)
+
+
+def bench_spacetime(args, mc, torch, dev):
+    """Imperfect measurements (Sec. VI): L = 7, T = 7 rounds (the last one
+    perfect), depolarizing p = 0.02 per interval and outcome error p_M = 0.02,
+    4 classes x 4 chains, 784 = 16 L^2 sweeps of every spatial and time move
+    (the local moves relax slowly in space-time), 9216 histories per step
+    (147456 chains: 2304 one-wave workgroups, as many as the LDS lets the
+    256 CUs hold at once).
+    Also the logical error of decoding the last round alone with the
+    single-round decoder (L^2 sweeps), on the same histories."""
+    Ls, T, p, pm, chains, sweeps, n = 7, 7, 0.02, 0.02, 4, 784, 9216
+    steps, warm = args.steps, args.warmup
+    nq, ns = mc.geometry(Ls)
+    hist, truth = [], []
+    for b in range(warm + steps):
+        o, c = mc.sample_spacetime(Ls, T, p, pm, SEED, n, device=dev, id_base=b * n)
+        hist.append(o)
+        truth.append(c)
+    prm = mc.spacetime_params(Ls, T, p, pm, sweeps, SEED, chains)
+    import ctypes
+    from paper_1302_2669_amd import _lib
+    b_ = ctypes.c_size_t()
+    _lib.check(_lib._lib().mcmc_spacetime_workspace_size(ctypes.byref(prm), n, ctypes.byref(b_)),
+               "mcmc_spacetime_workspace_size")
+    ws = torch.empty((b_.value,), dtype=torch.uint8, device=dev)
+    ids = [torch.arange(b * n, (b + 1) * n, dtype=torch.int32, device=dev)
+           for b in range(warm + steps)]
+
+    def step(b, sw=sweeps):
+        return mc.decode_spacetime(hist[b], Ls, p, pm, sw, SEED, chains=chains,
+                                   syndrome_ids=ids[b], want_correction=True, workspace=ws)
+
+    for b in range(warm):
+        step(b)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream(dev)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    chosen = []
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for i in range(steps):
+        chosen.append(step(warm + i)["chosen"])
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    step_ms = e0.elapsed_time(e1) / steps
+    z0, z1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    z0.record(stream)
+    for i in range(steps):
+        step(warm + i, sw=0)
+    z1.record(stream)
+    torch.cuda.synchronize()
+    chain_ms = step_ms - z0.elapsed_time(z1) / steps
+    moves_per_history = 4 * chains * sweeps * (T * ns + 2 * (T - 1) * nq)
+    achieved = n * moves_per_history * OPS_PER_UPDATE / (chain_ms * 1e-3) / 1e12
+    fails = sum(int((c != t).sum().item()) for c, t in zip(chosen, truth[warm:]))
+    total = n * steps
+    p_eff = 1 - (1 - p) ** T
+    last_fail = 0
+    for i in range(steps):
+        out = mc.decode_batch(hist[warm + i][:, T - 1].contiguous(), Ls, p_eff, Ls * Ls, SEED,
+                              chains=chains, want_correction=False)
+        last_fail += int((out["chosen"] != truth[warm + i]).sum().item())
+    line = {
+        "metric": "decoded measurement histories/sec, imperfect measurements (L=7, 7 rounds)",
+        "value": total / wall, "unit": "histories/s",
+        "moves_per_s": total / wall * moves_per_history,
+        "n_gpus": 1, "steps": steps, "warmup": warm, "ms_per_step": wall * 1e3 / steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32+f64",
+        "data": "synthetic: depolarizing data errors and wrong outcomes from the library's "
+                "Philox sampler",
+        "config": {"workload": "planar code L=7, T=7 measurement rounds (last perfect), "
+                               "p = p_M = 0.02, 4 classes x 4 chains, 784 sweeps of all "
+                               f"spatial and time moves, {n} histories per step",
+                   "L": Ls, "rounds": T, "p": p, "p_m": pm, "chains_per_class": chains,
+                   "sweeps": sweeps, "batch": n, "moves_per_history": moves_per_history},
+        "logical_error": {"rate": fails / total, "samples": total,
+                          "last_round_only": last_fail / total},
+        "roofline": {"bound": "alu", "kernel": "st_chain_kernel (space-time chains)",
+                     "achieved": achieved, "peak": PEAK_INT_OPS / 1e12, "unit": "Tops/s",
+                     "frac": achieved / (PEAK_INT_OPS / 1e12), "traffic": None,
+                     "chain_ms_per_launch": chain_ms, "ops_per_update": OPS_PER_UPDATE,
+                     "updates_per_launch": n * moves_per_history},
+        "cpu_baseline": None,
+    }
+    if not args.no_cpu_baseline:
+        here = os.path.dirname(os.path.abspath(__file__))
+        if here not in sys.path:
+            sys.path.insert(0, here)
+        from oracle import geometry, spacetime as stm
+        # one history at a quarter of the sweeps (the oracle's cost is linear in
+        # sweeps), scaled to the full budget
+        ns_cpu, frac = 1, 4
+        obs_cpu, _, _, _ = stm.sample(geometry.Lattice(Ls), p, pm, T, SEED, np.arange(ns_cpu))
+        c0 = time.perf_counter()
+        stm.decode(Ls, obs_cpu, p, pm, sweeps // frac, SEED, chains_per_class=chains)
+        dt = time.perf_counter() - c0
+        line["cpu_baseline"] = {"value": ns_cpu / (dt * frac), "unit": "histories/s",
+                                "cores": 1, "kind": "oracle",
+                                "sample": f"{ns_cpu} history of the same workload at "
+                                          f"{sweeps // frac} of its {sweeps} sweeps, NumPy "
+                                          f"oracle in one process, {dt:.1f} s, time x{frac}"}
     print(json.dumps(line), flush=True)
 
 
