@@ -34,6 +34,11 @@ namespace {
 
 constexpr int ST_LANES = 64;
 constexpr uint32_t ST_NONE = 0xFFFFu;
+constexpr int ST_SAMPLE_NQ = 2048;   // accumulated-error bytes of the sampler
+static_assert(2 * MCMC_L_MAX * MCMC_L_MAX - 2 * MCMC_L_MAX + 1 <= ST_SAMPLE_NQ,
+              "sampler buffer holds every qubit of the largest code");
+static_assert(2 * MCMC_L_MAX * MCMC_L_MAX - 2 * MCMC_L_MAX + 1 < (int)ST_NONE,
+              "qubit and stabilizer indices fit the 16-bit table entries");
 
 __device__ __forceinline__ uint32_t pack2(uint32_t lo, uint32_t hi) { return lo | (hi << 16); }
 
@@ -46,7 +51,7 @@ __global__ void __launch_bounds__(256) st_sample_kernel(int L, int T, uint32_t t
                                                         uint32_t id_base, int64_t n,
                                                         uint8_t* __restrict__ obs,
                                                         uint8_t* __restrict__ true_class) {
-  __shared__ uint8_t acc[2 * 32 * 32];   // accumulated error, n_q <= 2*25*25
+  __shared__ uint8_t acc[ST_SAMPLE_NQ];  // accumulated error of the sample
   const int64_t smp = blockIdx.x;
   if (smp >= n) return;
   const uint32_t sid = id_base + (uint32_t)smp;
