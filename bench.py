@@ -581,7 +581,7 @@ def bench_spacetime(args, mc, torch, dev):
                    "sweeps": sweeps, "batch": n, "moves_per_history": moves_per_history},
         "logical_error": {"rate": fails / total, "samples": total,
                           "last_round_only": last_fail / total},
-        "roofline": {"bound": "alu", "kernel": "st_chain_kernel (space-time chains)",
+        "roofline": {"bound": "alu", "kernel": "st_chain_fast_kernel<7> (space-time chains)",
                      "achieved": achieved, "peak": PEAK_INT_OPS / 1e12, "unit": "Tops/s",
                      "frac": achieved / (PEAK_INT_OPS / 1e12), "traffic": None,
                      "chain_ms_per_launch": chain_ms, "ops_per_update": OPS_PER_UPDATE,

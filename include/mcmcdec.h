@@ -490,8 +490,9 @@ int mcmc_gated_decode(mcmc_gated* gated, const float* d_params, const uint8_t* d
  * time moves (a Pauli on one qubit in intervals t and t+1 with the outcomes
  * of round t that it anticommutes with toggled).  A sweep is every spatial
  * move (t = 0..T-1, sites in order) then every time move (t = 0..T-2,
- * qubits in order, X before Z); draw d of the sweep is word d & 3 of Philox
- * at (d >> 2, sweep, id, 3<<30 | cls<<28 | 1<<20 | chain).  A move with
+ * qubits in order, X before Z); move (t, k) uses draw d = t n_stab + k and
+ * move (t, q, P) d = T n_stab + 2 t (n_q + 1) + 2 q + (P == Z), word d & 3 of
+ * Philox at (d >> 2, sweep, id, 3<<30 | cls<<28 | 1<<20 | chain).  A move with
  * E = dn + xi dm <= 0 is taken, else iff u < floor(2^32 exp(-beta_bar E)).
  * n and m are summed after each half of a counted sweep; the decision is the
  * class with the smallest S_n + xi S_m (float64), ties to the lowest class.

@@ -26,9 +26,11 @@ toggled outcomes of (1 - 2 M).  A move with E = Delta n + xi Delta m <= 0 is
 taken; otherwise with probability exp(-beta E), as u < floor(2^32 exp(-beta E)).
 
 Sweep (absolute index s): first every spatial move, t = 0..T-1 and k in site
-order; then every time move, t = 0..T-2, q = 0..n_q-1, X before Z.  Draw d
-of the sweep (spatial: t n_stab + k; time: T n_stab + 2 (t n_q + q) + (P==Z))
-is word d & 3 of Philox at counter
+order; then every time move, t = 0..T-2, q = 0..n_q-1, X before Z.  Move
+(t, k) uses draw d = t n_stab + k, move (t, q, P) draw
+d = T n_stab + 2 t (n_q + 1) + 2 q + (P==Z) (two draws per round are left
+unused so that every round starts a Philox block: n_stab and 2 (n_q + 1) are
+multiples of 4); draw d is word d & 3 of Philox at counter
 (d >> 2, sweep, syndrome_id, 3<<30 | cls<<28 | 1<<20 | chain).
 After the spatial half and after the time half of a counted sweep, n is added
 to S_n and m to S_m.
@@ -169,7 +171,7 @@ def run(lat, E, M, syndrome_id, cls, chain, beta, xi, seed, sweep_begin, sweep_e
     Sn = np.zeros(C, np.int64) if Sn is None else np.array(Sn, np.int64)
     Sm = np.zeros(C, np.int64) if Sm is None else np.array(Sm, np.int64)
     A = np.zeros(C, np.int64) if A is None else np.array(A, np.int64)
-    n_draws = T * lat.n_stab + 2 * (T - 1) * lat.n_qubits
+    n_draws = T * lat.n_stab + 2 * (T - 1) * (lat.n_qubits + 1)
     if check_invariants:
         cls_arr = np.asarray(cls).reshape(C)
         obs = np.broadcast_to(obs, (C,) + obs.shape[-2:])
@@ -197,7 +199,7 @@ def run(lat, E, M, syndrome_id, cls, chain, beta, xi, seed, sweep_begin, sweep_e
         for t in range(T - 1):
             for q in range(lat.n_qubits):
                 for kind in (0, 1):              # 0: X (x part, plaquettes), 1: Z
-                    d = T * lat.n_stab + 2 * (t * lat.n_qubits + q) + kind
+                    d = T * lat.n_stab + 2 * t * (lat.n_qubits + 1) + 2 * q + kind
                     dn = np.zeros(C, np.int64)
                     for tt in (t, t + 1):
                         c = E[:, tt, q].astype(np.int64)

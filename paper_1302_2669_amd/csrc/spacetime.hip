@@ -11,8 +11,10 @@
 //     E_{t+1}, and M_t toggled on the stabilizers that anticommute with P on
 //     q (its plaquettes for X, its stars for Z) -- Sec. VI's deformation.
 // A sweep takes every spatial move (t, then site order) and then every time
-// move (t, q, X before Z); draw d of the sweep (in that order) is word d & 3
-// of Philox at counter (d >> 2, sweep, syndrome_id,
+// move (t, q, X before Z).  Move (t, k) uses draw d = t n_stab + k, move
+// (t, q, P) d = T n_stab + 2 t (n_q + 1) + 2 q + (P == Z): two draws per
+// round are skipped so that every round starts a Philox block.  Draw d is
+// word d & 3 at counter (d >> 2, sweep, syndrome_id,
 // 3<<30 | cls<<28 | 1<<20 | chain).  n and m are summed after each half of a
 // counted sweep.
 //
@@ -23,6 +25,12 @@
 // lists and per-qubit stabilizer lists shared by the workgroup.  Moves run
 // in the exact sequential order above, so the chains are bit-identical to a
 // sequential implementation.  One 64-lane workgroup per 64 chains.
+//
+// For L <= ST_FAST_L_MAX a second kernel, templated on L, runs the same moves
+// with the words of the current interval (spatial half) or of intervals t,
+// t+1 and round t's outcomes (time half) in registers: every qubit, site and
+// stabilizer index is then a compile-time constant, and LDS is touched once
+// per interval instead of on every move.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -35,6 +43,7 @@ namespace {
 constexpr int ST_LANES = 64;
 constexpr uint32_t ST_NONE = 0xFFFFu;
 constexpr int ST_SAMPLE_NQ = 2048;   // accumulated-error bytes of the sampler
+constexpr int ST_FAST_L_MAX = 7;     // largest L of the register-resident kernel
 static_assert(2 * MCMC_L_MAX * MCMC_L_MAX - 2 * MCMC_L_MAX + 1 <= ST_SAMPLE_NQ,
               "sampler buffer holds every qubit of the largest code");
 static_assert(2 * MCMC_L_MAX * MCMC_L_MAX - 2 * MCMC_L_MAX + 1 < (int)ST_NONE,
@@ -247,8 +256,8 @@ __global__ void __launch_bounds__(ST_LANES) st_chain_kernel(const SpaceTimeArgs 
       }
     }
     if (counted) { Sn += n; Sm += m; }
-    // time moves
-    for (int t = 0; t + 1 < T; ++t) {
+    // time moves (two unused draws close every round)
+    for (int t = 0; t + 1 < T; ++t, d += 2) {
       uint32_t* E0 = Ew + t * WQ * ST_LANES + lane;
       uint32_t* E1 = E0 + WQ * ST_LANES;
       uint32_t* Mt = Mw + t * WM * ST_LANES + lane;
@@ -301,6 +310,239 @@ __global__ void __launch_bounds__(ST_LANES) st_chain_kernel(const SpaceTimeArgs 
       for (int f = 0; f < 16; ++f) {
         const int q = 16 * w + f;
         if (q < nq) o[q] = (uint8_t)((word >> (2 * f)) & 3u);
+      }
+    }
+  }
+}
+
+// ---- chains, register-resident intervals (small codes) -----------------------
+template <int L>
+struct StGeo {
+  static constexpr int SIDE = 2 * L - 1;
+  static constexpr int NQ = 2 * L * L - 2 * L + 1;
+  static constexpr int NSTAB = 2 * L * (L - 1);
+  static constexpr int NSTAR = L * (L - 1);
+  static constexpr int WQ = (NQ + 15) / 16;
+  static constexpr int WM = (NSTAB + 31) / 32;
+  // qubit k (0..3) of site s in the generic kernel's order, -1 if missing
+  static constexpr int site_qubit(int s, int k) {
+    int r = 0, c = 0;
+    if (s < NSTAR) { r = 2 * (s / L) + 1; c = 2 * (s % L); }
+    else { r = 2 * ((s - NSTAR) / (L - 1)); c = 2 * ((s - NSTAR) % (L - 1)) + 1; }
+    int q[4] = {-1, -1, -1, -1};
+    int n = 0;
+    if (r > 0) q[n++] = ((r - 1) * SIDE + c) / 2;
+    if (r < SIDE - 1) q[n++] = ((r + 1) * SIDE + c) / 2;
+    if (c > 0) q[n++] = (r * SIDE + c - 1) / 2;
+    if (c < SIDE - 1) q[n++] = (r * SIDE + c + 1) / 2;
+    return q[k];
+  }
+  // stabilizer k (0..1) anticommuting with X (kind 0: plaquettes) or Z
+  // (kind 1: stars) on qubit q, -1 if missing
+  static constexpr int qubit_stab(int q, int kind, int k) {
+    const int r = (2 * q) / SIDE, c = 2 * q - r * SIDE;
+    int pl[2] = {-1, -1}, st[2] = {-1, -1};
+    int np = 0, ns = 0;
+    const int dr[4] = {-1, 1, 0, 0}, dc[4] = {0, 0, -1, 1};
+    for (int d = 0; d < 4; ++d) {
+      const int rr = r + dr[d], cc = c + dc[d];
+      if (rr < 0 || rr >= SIDE || cc < 0 || cc >= SIDE) continue;
+      if (rr & 1) st[ns++] = ((rr - 1) / 2) * L + cc / 2;
+      else pl[np++] = NSTAR + (rr / 2) * (L - 1) + (cc - 1) / 2;
+    }
+    return kind == 0 ? pl[k] : st[k];
+  }
+};
+
+// After every move the state words pass through an empty asm statement, and
+// each Philox block index is made opaque: a flip only touches bits that the
+// compiler can prove other moves do not read, so without the fences it
+// extracts every move's fields from the words as loaded and keeps them all
+// live (hundreds of registers, then scratch).
+template <int N>
+__device__ __forceinline__ void st_fence(uint32_t (&x)[N]) {
+#pragma unroll
+  for (int i = 0; i < N; ++i) asm volatile("" : "+v"(x[i]));
+}
+__device__ __forceinline__ uint32_t st_opaque(uint32_t v) {
+  asm volatile("" : "+v"(v));
+  return v;
+}
+
+template <int L>
+__global__ void __launch_bounds__(ST_LANES) __attribute__((amdgpu_waves_per_eu(2)))
+st_chain_fast_kernel(const SpaceTimeArgs a) {
+  using G = StGeo<L>;
+  constexpr int NQ = G::NQ, NSTAB = G::NSTAB, NSTAR = G::NSTAR, WQ = G::WQ, WM = G::WM;
+  extern __shared__ uint32_t st_lds[];
+  const int T = a.T;
+  const int lane = threadIdx.x;
+  uint32_t* tthr = st_lds;                          // [25] time-move thresholds
+  uint32_t* sthr = st_lds + 28;                     // [4] spatial thresholds
+  uint32_t* Ew = st_lds + 32;                       // [T*WQ][64]
+  uint32_t* Mw = Ew + (int64_t)T * WQ * ST_LANES;   // [(T-1)*WM][64]
+  if (lane < 25) tthr[lane] = a.t_thr[lane];
+  if (lane < 4) sthr[lane] = a.sp_thr[lane];
+  __syncthreads();
+
+  const int64_t task = (int64_t)blockIdx.x * ST_LANES + lane;
+  if (task >= a.n_tasks) return;
+  const int C = a.chains;
+  const int64_t item = task / (4 * C);
+  const int rem = (int)(task - item * 4 * C);
+  const int cls = rem / C, chain = rem % C;
+  const uint32_t sid = a.ids ? a.ids[item] : (uint32_t)item;
+
+  int32_t n = 0, m = 0;
+  for (int k = 0; k < (T - 1) * WQ; ++k) Ew[k * ST_LANES + lane] = 0u;
+  {
+    const uint8_t* b = a.reps + (item * 4 + cls) * NQ;
+    for (int w = 0; w < WQ; ++w) {
+      uint32_t word = 0;
+      for (int f = 0; f < 16; ++f) {
+        const int q = 16 * w + f;
+        if (q < NQ) word |= (uint32_t)(b[q] & 3u) << (2 * f);
+      }
+      Ew[((T - 1) * WQ + w) * ST_LANES + lane] = word;
+    }
+    n = a.rep_weight[item * 4 + cls];
+  }
+  for (int t = 0; t + 1 < T; ++t) {
+    const uint8_t* o = a.obs + (item * T + t) * NSTAB;
+    for (int w = 0; w < WM; ++w) {
+      uint32_t word = 0;
+      for (int b = 0; b < 32; ++b) {
+        const int k = 32 * w + b;
+        if (k < NSTAB && o[k] != 0) word |= 1u << b;
+      }
+      Mw[(t * WM + w) * ST_LANES + lane] = word;
+      m += __builtin_popcount(word);
+    }
+  }
+
+  const uint32_t ctr3 = (3u << 30) | ((uint32_t)cls << 28) | (1u << 20) | (uint32_t)chain;
+  const uint32_t always = a.t_always;
+  int64_t Sn = 0, Sm = 0, Acnt = 0;
+  for (int sweep = 0; sweep < a.sweep_end; ++sweep) {
+    const bool counted = sweep >= a.burn;
+    // spatial half: interval t in registers
+    for (int t = 0; t < T; ++t) {
+      uint32_t e[WQ];
+#pragma unroll
+      for (int w = 0; w < WQ; ++w) e[w] = Ew[(t * WQ + w) * ST_LANES + lane];
+      const uint32_t blk0 = (uint32_t)(t * (NSTAB / 4));
+      uint4 blk = make_uint4(0, 0, 0, 0);
+      static_for<NSTAB>([&](auto SS) {
+        constexpr int s = decltype(SS)::value;
+        constexpr bool star = s < NSTAR;
+        if constexpr ((s & 3) == 0) {
+          blk = philox4x32_10(
+              make_uint4(st_opaque(blk0 + (uint32_t)(s / 4)), (uint32_t)sweep, sid, ctr3), a.k0,
+              a.k1);
+        }
+        const uint32_t u = word_of(blk, s & 3);
+        int delta = 0;
+        static_for<4>([&](auto KK) {
+          constexpr int q = G::site_qubit(s, decltype(KK)::value);
+          if constexpr (q >= 0) {
+            const uint32_t code = (e[q >> 4] >> (2 * (q & 15))) & 3u;
+            const int x = (int)(code & 1u), z = (int)(code >> 1);
+            delta += star ? (1 - z) * (1 - 2 * x) : (1 - x) * (1 - 2 * z);
+          }
+        });
+        // threshold by table lookup and both tests evaluated (no select chain,
+        // no short circuit): a branch per move would split the unrolled sweep
+        // into thousands of exec-masked blocks; (delta - 1) & 3 stays in the
+        // table for delta <= 0, where the lookup is not used
+        const bool acc = (delta <= 0) | (u < sthr[(delta - 1) & 3]);
+        const uint32_t flip = acc ? (star ? 1u : 2u) : 0u;
+        static_for<4>([&](auto KK) {
+          constexpr int q = G::site_qubit(s, decltype(KK)::value);
+          if constexpr (q >= 0) e[q >> 4] ^= flip << (2 * (q & 15));
+        });
+        n += acc ? delta : 0;
+        Acnt += acc ? 1 : 0;
+        st_fence(e);
+        asm volatile("" : "+v"(n));
+      });
+#pragma unroll
+      for (int w = 0; w < WQ; ++w) Ew[(t * WQ + w) * ST_LANES + lane] = e[w];
+    }
+    if (counted) { Sn += n; Sm += m; }
+    // time half: intervals t, t+1 and round t's outcomes in registers
+    for (int t = 0; t + 1 < T; ++t) {
+      uint32_t e0[WQ], e1[WQ], mm[WM];
+#pragma unroll
+      for (int w = 0; w < WQ; ++w) {
+        e0[w] = Ew[(t * WQ + w) * ST_LANES + lane];
+        e1[w] = Ew[((t + 1) * WQ + w) * ST_LANES + lane];
+      }
+#pragma unroll
+      for (int w = 0; w < WM; ++w) mm[w] = Mw[(t * WM + w) * ST_LANES + lane];
+      const uint32_t blk0 = (uint32_t)((T * NSTAB + 2 * t * (NQ + 1)) / 4);
+      uint4 blk = make_uint4(0, 0, 0, 0);
+      static_for<2 * NQ>([&](auto RR) {
+        constexpr int r = decltype(RR)::value;
+        constexpr int q = r >> 1, kind = r & 1;
+        constexpr int w = q >> 4, sh = 2 * (q & 15);
+        if constexpr ((r & 3) == 0) {
+          blk = philox4x32_10(
+              make_uint4(st_opaque(blk0 + (uint32_t)(r / 4)), (uint32_t)sweep, sid, ctr3), a.k0,
+              a.k1);
+        }
+        const uint32_t u = word_of(blk, r & 3);
+        const uint32_t c0 = (e0[w] >> sh) & 3u, c1 = (e1[w] >> sh) & 3u;
+        int dn;
+        if constexpr (kind == 0)
+          dn = (1 - (int)(c0 >> 1)) * (1 - 2 * (int)(c0 & 1u)) +
+               (1 - (int)(c1 >> 1)) * (1 - 2 * (int)(c1 & 1u));
+        else
+          dn = (1 - (int)(c0 & 1u)) * (1 - 2 * (int)(c0 >> 1)) +
+               (1 - (int)(c1 & 1u)) * (1 - 2 * (int)(c1 >> 1));
+        constexpr int sa = G::qubit_stab(q, kind, 0), sb = G::qubit_stab(q, kind, 1);
+        int dm = 0;
+        if constexpr (sa >= 0) dm += 1 - 2 * (int)((mm[sa >> 5] >> (sa & 31)) & 1u);
+        if constexpr (sb >= 0) dm += 1 - 2 * (int)((mm[sb >> 5] >> (sb & 31)) & 1u);
+        const int ei = (dn + 2) * 5 + (dm + 2);
+        const bool acc = (((always >> ei) & 1u) != 0) | (u < tthr[ei]);
+        const uint32_t fl = acc ? (uint32_t)(kind == 0 ? 1u : 2u) << sh : 0u;
+        e0[w] ^= fl;
+        e1[w] ^= fl;
+        if constexpr (sa >= 0) mm[sa >> 5] ^= (acc ? 1u : 0u) << (sa & 31);
+        if constexpr (sb >= 0) mm[sb >> 5] ^= (acc ? 1u : 0u) << (sb & 31);
+        n += acc ? dn : 0;
+        m += acc ? dm : 0;
+        Acnt += acc ? 1 : 0;
+        st_fence(e0);
+        st_fence(e1);
+        st_fence(mm);
+        asm volatile("" : "+v"(n), "+v"(m));
+      });
+#pragma unroll
+      for (int w = 0; w < WQ; ++w) {
+        Ew[(t * WQ + w) * ST_LANES + lane] = e0[w];
+        Ew[((t + 1) * WQ + w) * ST_LANES + lane] = e1[w];
+      }
+#pragma unroll
+      for (int w = 0; w < WM; ++w) Mw[(t * WM + w) * ST_LANES + lane] = mm[w];
+    }
+    if (counted) { Sn += n; Sm += m; }
+  }
+
+  const int64_t out = item * 4 * C + rem;
+  a.Sn[out] = Sn;
+  a.Sm[out] = Sm;
+  a.A[out] = Acnt;
+  a.n_final[out] = n;
+  a.m_final[out] = m;
+  if (a.final_c && chain == 0) {
+    uint8_t* o = a.final_c + (item * 4 + cls) * NQ;
+    for (int w = 0; w < WQ; ++w) {
+      uint32_t word = 0;
+      for (int t = 0; t < T; ++t) word ^= Ew[(t * WQ + w) * ST_LANES + lane];
+      for (int f = 0; f < 16; ++f) {
+        const int q = 16 * w + f;
+        if (q < NQ) o[q] = (uint8_t)((word >> (2 * f)) & 3u);
       }
     }
   }
@@ -377,8 +619,37 @@ hipError_t launch_spacetime_last(int64_t n, int T, int nstab, const uint8_t* obs
   return hipGetLastError();
 }
 
+namespace {
+
+template <int L>
+hipError_t launch_fast(const SpaceTimeArgs& a, hipStream_t s) {
+  const size_t lds = (32 + ((size_t)a.T * StGeo<L>::WQ + (size_t)(a.T - 1) * StGeo<L>::WM) *
+                               ST_LANES) * sizeof(uint32_t);
+  if (lds > SPACETIME_LDS_MAX) return hipErrorInvalidValue;
+  const hipError_t e = hipFuncSetAttribute((const void*)st_chain_fast_kernel<L>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)SPACETIME_LDS_MAX);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(st_chain_fast_kernel<L>, dim3(blocks_for(a.n_tasks, ST_LANES)),
+                     dim3(ST_LANES), lds, s, a);
+  return hipGetLastError();
+}
+
+template <int LL>
+hipError_t dispatch_fast(const SpaceTimeArgs& a, hipStream_t s) {
+  if constexpr (LL > ST_FAST_L_MAX) {
+    return hipErrorInvalidValue;
+  } else {
+    if (a.L == LL) return launch_fast<LL>(a, s);
+    return dispatch_fast<LL + 1>(a, s);
+  }
+}
+
+}  // namespace
+
 hipError_t launch_spacetime_chains(const SpaceTimeArgs& a, hipStream_t s) {
   if (a.n_tasks == 0) return hipSuccess;
+  if (a.L <= ST_FAST_L_MAX) return dispatch_fast<2>(a, s);
   const size_t lds = spacetime_lds_bytes(a.L, a.T);
   if (lds > SPACETIME_LDS_MAX) return hipErrorInvalidValue;
   const hipError_t e = hipFuncSetAttribute((const void*)st_chain_kernel,
