@@ -42,9 +42,9 @@ PEAK_INT_OPS = 256 * 128 * 2.4e9 * 2
 # counter's reading of a 256 MiB copy) + WRITE_SIZE (x1.000) at 65536 syndromes
 # per launch (the counters file under profiles/ for chains_r0 at L=13): bytes
 # per syndrome, valid only for the kernel sources it was measured on
-CHAIN_TRAFFIC_PER_SYNDROME = 81267181 / 65536
+CHAIN_TRAFFIC_PER_SYNDROME = 81374413 / 65536
 CHAIN_TRAFFIC_SOURCES = ("chain_body.h", "chain_r0.hip", "device_common.h", "internal.h")
-CHAIN_TRAFFIC_SHA = "ebc3acd1bd704a66"
+CHAIN_TRAFFIC_SHA = "c4e52844b477af8f"
 # gate network at L=13: 2 flops per multiply-add over the three 3x3 convolutions
 # (3->32, 32->32, 32->32 on 169 pixels) and the 5408x7 head
 CNN_FLOPS_PER_SAMPLE = 2 * (169 * 32 * 27 + 2 * 169 * 32 * 288 + 7 * 5408)
