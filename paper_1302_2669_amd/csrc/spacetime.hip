@@ -29,8 +29,9 @@
 // For L <= ST_FAST_L_MAX a second kernel, templated on L, runs the same moves
 // with the words of the current interval (spatial half) or of intervals t,
 // t+1 and round t's outcomes (time half) in registers: every qubit, site and
-// stabilizer index is then a compile-time constant, and LDS is touched once
-// per interval instead of on every move.
+// stabilizer index is then a compile-time constant.  Its hypotheses live in a
+// global buffer, word-major over all chains, read and written once per
+// interval: without LDS the occupancy is set by registers alone.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -43,7 +44,7 @@ namespace {
 constexpr int ST_LANES = 64;
 constexpr uint32_t ST_NONE = 0xFFFFu;
 constexpr int ST_SAMPLE_NQ = 2048;   // accumulated-error bytes of the sampler
-constexpr int ST_FAST_L_MAX = 7;     // largest L of the register-resident kernel
+constexpr int ST_FAST_L_MAX = SPACETIME_FAST_L_MAX;
 static_assert(2 * MCMC_L_MAX * MCMC_L_MAX - 2 * MCMC_L_MAX + 1 <= ST_SAMPLE_NQ,
               "sampler buffer holds every qubit of the largest code");
 static_assert(2 * MCMC_L_MAX * MCMC_L_MAX - 2 * MCMC_L_MAX + 1 < (int)ST_NONE,
@@ -370,23 +371,27 @@ __device__ __forceinline__ uint32_t st_opaque(uint32_t v) {
 }
 
 template <int L>
-__global__ void __launch_bounds__(ST_LANES) __attribute__((amdgpu_waves_per_eu(2)))
+// 4 waves per SIMD (128 registers): the few spills the cap costs are stores
+// in the move sequences whose values are read back only after the last sweep.
+__global__ void __launch_bounds__(ST_LANES) __attribute__((amdgpu_waves_per_eu(4)))
 st_chain_fast_kernel(const SpaceTimeArgs a) {
   using G = StGeo<L>;
   constexpr int NQ = G::NQ, NSTAB = G::NSTAB, NSTAR = G::NSTAR, WQ = G::WQ, WM = G::WM;
-  extern __shared__ uint32_t st_lds[];
+  __shared__ uint32_t tthr[32];                     // [25] time-move thresholds
+  __shared__ uint32_t sthr[4];                      // spatial thresholds
   const int T = a.T;
   const int lane = threadIdx.x;
-  uint32_t* tthr = st_lds;                          // [25] time-move thresholds
-  uint32_t* sthr = st_lds + 28;                     // [4] spatial thresholds
-  uint32_t* Ew = st_lds + 32;                       // [T*WQ][64]
-  uint32_t* Mw = Ew + (int64_t)T * WQ * ST_LANES;   // [(T-1)*WM][64]
   if (lane < 25) tthr[lane] = a.t_thr[lane];
   if (lane < 4) sthr[lane] = a.sp_thr[lane];
   __syncthreads();
 
   const int64_t task = (int64_t)blockIdx.x * ST_LANES + lane;
   if (task >= a.n_tasks) return;
+  // the hypothesis in global memory, word-major over all chains (coalesced):
+  // it is read and written once per interval, not per move
+  const int64_t stride = a.n_tasks;
+  uint32_t* Ew = a.state + task;                        // [T*WQ][stride]
+  uint32_t* Mw = Ew + (int64_t)T * WQ * stride;         // [(T-1)*WM][stride]
   const int C = a.chains;
   const int64_t item = task / (4 * C);
   const int rem = (int)(task - item * 4 * C);
@@ -394,7 +399,7 @@ st_chain_fast_kernel(const SpaceTimeArgs a) {
   const uint32_t sid = a.ids ? a.ids[item] : (uint32_t)item;
 
   int32_t n = 0, m = 0;
-  for (int k = 0; k < (T - 1) * WQ; ++k) Ew[k * ST_LANES + lane] = 0u;
+  for (int k = 0; k < (T - 1) * WQ; ++k) Ew[k * stride] = 0u;
   {
     const uint8_t* b = a.reps + (item * 4 + cls) * NQ;
     for (int w = 0; w < WQ; ++w) {
@@ -403,7 +408,7 @@ st_chain_fast_kernel(const SpaceTimeArgs a) {
         const int q = 16 * w + f;
         if (q < NQ) word |= (uint32_t)(b[q] & 3u) << (2 * f);
       }
-      Ew[((T - 1) * WQ + w) * ST_LANES + lane] = word;
+      Ew[((T - 1) * WQ + w) * stride] = word;
     }
     n = a.rep_weight[item * 4 + cls];
   }
@@ -415,7 +420,7 @@ st_chain_fast_kernel(const SpaceTimeArgs a) {
         const int k = 32 * w + b;
         if (k < NSTAB && o[k] != 0) word |= 1u << b;
       }
-      Mw[(t * WM + w) * ST_LANES + lane] = word;
+      Mw[(t * WM + w) * stride] = word;
       m += __builtin_popcount(word);
     }
   }
@@ -429,7 +434,7 @@ st_chain_fast_kernel(const SpaceTimeArgs a) {
     for (int t = 0; t < T; ++t) {
       uint32_t e[WQ];
 #pragma unroll
-      for (int w = 0; w < WQ; ++w) e[w] = Ew[(t * WQ + w) * ST_LANES + lane];
+      for (int w = 0; w < WQ; ++w) e[w] = Ew[(t * WQ + w) * stride];
       const uint32_t blk0 = (uint32_t)(t * (NSTAB / 4));
       uint4 blk = make_uint4(0, 0, 0, 0);
       static_for<NSTAB>([&](auto SS) {
@@ -466,7 +471,7 @@ st_chain_fast_kernel(const SpaceTimeArgs a) {
         asm volatile("" : "+v"(n));
       });
 #pragma unroll
-      for (int w = 0; w < WQ; ++w) Ew[(t * WQ + w) * ST_LANES + lane] = e[w];
+      for (int w = 0; w < WQ; ++w) Ew[(t * WQ + w) * stride] = e[w];
     }
     if (counted) { Sn += n; Sm += m; }
     // time half: intervals t, t+1 and round t's outcomes in registers
@@ -474,11 +479,11 @@ st_chain_fast_kernel(const SpaceTimeArgs a) {
       uint32_t e0[WQ], e1[WQ], mm[WM];
 #pragma unroll
       for (int w = 0; w < WQ; ++w) {
-        e0[w] = Ew[(t * WQ + w) * ST_LANES + lane];
-        e1[w] = Ew[((t + 1) * WQ + w) * ST_LANES + lane];
+        e0[w] = Ew[(t * WQ + w) * stride];
+        e1[w] = Ew[((t + 1) * WQ + w) * stride];
       }
 #pragma unroll
-      for (int w = 0; w < WM; ++w) mm[w] = Mw[(t * WM + w) * ST_LANES + lane];
+      for (int w = 0; w < WM; ++w) mm[w] = Mw[(t * WM + w) * stride];
       const uint32_t blk0 = (uint32_t)((T * NSTAB + 2 * t * (NQ + 1)) / 4);
       uint4 blk = make_uint4(0, 0, 0, 0);
       static_for<2 * NQ>([&](auto RR) {
@@ -520,11 +525,11 @@ st_chain_fast_kernel(const SpaceTimeArgs a) {
       });
 #pragma unroll
       for (int w = 0; w < WQ; ++w) {
-        Ew[(t * WQ + w) * ST_LANES + lane] = e0[w];
-        Ew[((t + 1) * WQ + w) * ST_LANES + lane] = e1[w];
+        Ew[(t * WQ + w) * stride] = e0[w];
+        Ew[((t + 1) * WQ + w) * stride] = e1[w];
       }
 #pragma unroll
-      for (int w = 0; w < WM; ++w) Mw[(t * WM + w) * ST_LANES + lane] = mm[w];
+      for (int w = 0; w < WM; ++w) Mw[(t * WM + w) * stride] = mm[w];
     }
     if (counted) { Sn += n; Sm += m; }
   }
@@ -539,7 +544,7 @@ st_chain_fast_kernel(const SpaceTimeArgs a) {
     uint8_t* o = a.final_c + (item * 4 + cls) * NQ;
     for (int w = 0; w < WQ; ++w) {
       uint32_t word = 0;
-      for (int t = 0; t < T; ++t) word ^= Ew[(t * WQ + w) * ST_LANES + lane];
+      for (int t = 0; t < T; ++t) word ^= Ew[(t * WQ + w) * stride];
       for (int f = 0; f < 16; ++f) {
         const int q = 16 * w + f;
         if (q < NQ) o[q] = (uint8_t)((word >> (2 * f)) & 3u);
@@ -623,15 +628,9 @@ namespace {
 
 template <int L>
 hipError_t launch_fast(const SpaceTimeArgs& a, hipStream_t s) {
-  const size_t lds = (32 + ((size_t)a.T * StGeo<L>::WQ + (size_t)(a.T - 1) * StGeo<L>::WM) *
-                               ST_LANES) * sizeof(uint32_t);
-  if (lds > SPACETIME_LDS_MAX) return hipErrorInvalidValue;
-  const hipError_t e = hipFuncSetAttribute((const void*)st_chain_fast_kernel<L>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           (int)SPACETIME_LDS_MAX);
-  if (e != hipSuccess) return e;
+  if (!a.state) return hipErrorInvalidValue;
   hipLaunchKernelGGL(st_chain_fast_kernel<L>, dim3(blocks_for(a.n_tasks, ST_LANES)),
-                     dim3(ST_LANES), lds, s, a);
+                     dim3(ST_LANES), 0, s, a);
   return hipGetLastError();
 }
 

@@ -28,7 +28,7 @@ int check_st(const mcmc_spacetime_params* prm, int64_t n) {
 }
 
 struct StLayout {
-  size_t ds, reps, rep_w, Sn, Sm, A, nf, mf, fc, bytes;
+  size_t ds, reps, rep_w, Sn, Sm, A, nf, mf, fc, state, bytes;
 };
 
 StLayout st_layout(const mcmc_spacetime_params* prm, int64_t n) {
@@ -46,6 +46,11 @@ StLayout st_layout(const mcmc_spacetime_params* prm, int64_t n) {
   w.nf = off;    off = align_up(off + (size_t)chains * sizeof(int32_t));
   w.mf = off;    off = align_up(off + (size_t)chains * sizeof(int32_t));
   w.fc = off;    off = align_up(off + (size_t)(n * 4 * nq));
+  w.state = off;
+  if (L <= SPACETIME_FAST_L_MAX) {
+    const int64_t words = (int64_t)T * ((nq + 15) / 16) + (int64_t)(T - 1) * ((ns + 31) / 32);
+    off = align_up(off + (size_t)(words * chains) * sizeof(uint32_t));
+  }
   w.bytes = off;
   return w;
 }
@@ -140,6 +145,7 @@ int mcmc_decode_spacetime(const uint8_t* obs, const uint32_t* ids, int64_t n,
   a.mean_m = mean_m;
   a.chosen = chosen;
   a.correction = correction;
+  a.state = L <= SPACETIME_FAST_L_MAX ? (uint32_t*)(ws + wl.state) : nullptr;
   st = hip_status(launch_spacetime_chains(a, s));
   if (st != MCMC_OK) return st;
   return hip_status(launch_spacetime_decide(a, s));
