@@ -43,8 +43,13 @@ PEAK_INT_OPS = 256 * 128 * 2.4e9 * 2
 # per launch (the counters file under profiles/ for chains_r0 at L=13): bytes
 # per syndrome, valid only for the kernel sources it was measured on
 CHAIN_TRAFFIC_PER_SYNDROME = 81374413 / 65536
-CHAIN_TRAFFIC_SOURCES = ("chain_body.h", "chain_r0.hip", "device_common.h", "internal.h")
-CHAIN_TRAFFIC_SHA = "c4e52844b477af8f"
+# (file, first line, line after) of the sources the chain kernel is built from:
+# whole files, and internal.h from the launch descriptors to the kernel-range
+# table (the rest of that header declares other kernels)
+CHAIN_TRAFFIC_SOURCES = (("chain_body.h", None, None), ("chain_r0.hip", None, None),
+                         ("device_common.h", None, None),
+                         ("internal.h", "struct GroupDesc {", "hipError_t launch_chains("))
+CHAIN_TRAFFIC_SHA = "86b1af7578cf38a7"
 # gate network at L=13: 2 flops per multiply-add over the three 3x3 convolutions
 # (3->32, 32->32, 32->32 on 169 pixels) and the 5408x7 head
 CNN_FLOPS_PER_SAMPLE = 2 * (169 * 32 * 27 + 2 * 169 * 32 * 288 + 7 * 5408)
@@ -252,9 +257,16 @@ def chain_traffic(n):
     import hashlib
     here = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1302_2669_amd", "csrc")
     h = hashlib.sha256()
-    for f in CHAIN_TRAFFIC_SOURCES:
-        with open(os.path.join(here, f), "rb") as fh:
-            h.update(fh.read())
+    for f, first, after in CHAIN_TRAFFIC_SOURCES:
+        with open(os.path.join(here, f), "r") as fh:
+            text = fh.read()
+        if first is not None:
+            i = text.find(first)
+            j = text.find(after, i)
+            if i < 0 or j < 0:
+                return None
+            text = text[i:j]
+        h.update(text.encode())
     if h.hexdigest()[:16] != CHAIN_TRAFFIC_SHA:
         return None
     return CHAIN_TRAFFIC_PER_SYNDROME * n
