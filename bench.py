@@ -42,14 +42,14 @@ PEAK_INT_OPS = 256 * 128 * 2.4e9 * 2
 # counter's reading of a 256 MiB copy) + WRITE_SIZE (x1.000) at 65536 syndromes
 # per launch (the counters file under profiles/ for chains_r0 at L=13): bytes
 # per syndrome, valid only for the kernel sources it was measured on
-CHAIN_TRAFFIC_PER_SYNDROME = 81374413 / 65536
+CHAIN_TRAFFIC_PER_SYNDROME = 81232846 / 65536
 # (file, first line, line after) of the sources the chain kernel is built from:
 # whole files, and internal.h from the launch descriptors to the kernel-range
 # table (the rest of that header declares other kernels)
 CHAIN_TRAFFIC_SOURCES = (("chain_body.h", None, None), ("chain_r0.hip", None, None),
                          ("device_common.h", None, None),
                          ("internal.h", "struct GroupDesc {", "hipError_t launch_chains("))
-CHAIN_TRAFFIC_SHA = "86b1af7578cf38a7"
+CHAIN_TRAFFIC_SHA = "0940c00ba5a05ddf"
 # gate network at L=13: 2 flops per multiply-add over the three 3x3 convolutions
 # (3->32, 32->32, 32->32 on 169 pixels) and the 5408x7 head
 CNN_FLOPS_PER_SAMPLE = 2 * (169 * 32 * 27 + 2 * 169 * 32 * 288 + 7 * 5408)

@@ -136,7 +136,7 @@ typedef struct mcmc_params {
 /* Human-readable name of a status code (static string). */
 const char* mcmc_strerror(int status);
 
-/* ABI version of this header: 0x00010100 for 1.1. */
+/* ABI version of this header: 0x00010200 for 1.2. */
 int32_t mcmc_abi_version(void);
 
 /* n_q and n_stab of a distance-L code (Sec. II: n_stab = 2L(L-1),
@@ -239,10 +239,11 @@ int mcmc_sample_errors_model(int32_t L, uint32_t noise, double p, uint64_t seed,
                              void* stream);
 
 /*
- * Mixed batches (syndromes of different L, p, sweep budget, chains and
- * temperature count in one decode).  A plan is built once on the host from an
- * array of items; executing it enqueues the class starts, the persistent
- * chain kernels (one per L range its syndromes fall in: 2-13, 14-16, and on a
+ * Mixed batches (syndromes of different L, noise model, p, sweep budget,
+ * chains and temperature count in one decode).  A plan is built once on the
+ * host from an array of items; executing it enqueues the class starts, the
+ * persistent chain kernels (one per L range and noise model its syndromes
+ * fall in; ranges 2-13, 14-16, and on a
  * second stream 17-19, 20-22, 23-25; waves take 64-chain tiles from an atomic
  * queue, longest tiles first) and the estimator, with no host
  * synchronisation.  The same sequence can be recorded into a HIP graph once
@@ -257,9 +258,12 @@ typedef struct mcmc_item {
   int32_t chains;       /* chains per class and temperature, >= 1                  */
   int32_t n_temps;      /* 1 or even 2..64                                         */
   uint32_t syndrome_id; /* Philox counter word 2 of this syndrome's chains         */
-  double p;             /* depolarizing rate, 0 < p < 0.75                         */
+  double p;             /* error rate of its noise model (as mcmc_params.p)        */
   int64_t syn_offset;   /* byte offset of its n_stab(L) syndrome bytes in the input */
   int64_t corr_offset;  /* byte offset of its n_q(L) correction bytes in the output */
+  uint32_t noise;       /* MCMC_NOISE_DEPOLARIZING (0) or MCMC_NOISE_BITPHASE      */
+  uint32_t reserved;    /* must be 0                                               */
+  double beta_scale;    /* as mcmc_params.beta_scale (0: the model's default)      */
 } mcmc_item;
 
 /* Launch shape of a plan: workgroup size (64, 128 or 256) of the L <= 16
@@ -315,9 +319,9 @@ int mcmc_plan_graph_launch(mcmc_plan* plan, const uint8_t* d_syndromes, double* 
                            uint8_t* d_chosen, uint8_t* d_correction, void* d_workspace,
                            size_t workspace_bytes, void* stream);
 
-/* Depolarizing samples for the plan's items (the rule of mcmc_sample_errors
- * with each item's L and p, sample id = its syndrome_id): syndromes written at
- * the items' syn_offset in d_syndromes, classes to d_true_class [n]. */
+/* Samples for the plan's items (the rule of mcmc_sample_errors_model with
+ * each item's L, noise model and p, sample id = its syndrome_id): syndromes
+ * written at the items' syn_offset in d_syndromes, classes to d_true_class [n]. */
 int mcmc_plan_sample(const mcmc_plan* plan, uint64_t seed, uint8_t* d_syndromes,
                      uint8_t* d_true_class, void* stream);
 

@@ -276,10 +276,11 @@ def decode_spacetime(obs, L, p, p_m, sweeps, seed, chains=1, burn=0, syndrome_id
     return out
 
 
-# numpy twin of the C mcmc_item struct (natural alignment, 48 bytes)
+# numpy twin of the C mcmc_item struct (natural alignment, 64 bytes)
 _ITEM_DTYPE = np.dtype([("L", "<i4"), ("sweeps", "<i4"), ("burn", "<i4"), ("chains", "<i4"),
                         ("n_temps", "<i4"), ("syndrome_id", "<u4"), ("p", "<f8"),
-                        ("syn_offset", "<i8"), ("corr_offset", "<i8")], align=True)
+                        ("syn_offset", "<i8"), ("corr_offset", "<i8"), ("noise", "<u4"),
+                        ("reserved", "<u4"), ("beta_scale", "<f8")], align=True)
 assert _ITEM_DTYPE.itemsize == ctypes.sizeof(_lib.Item)
 
 
@@ -288,7 +289,8 @@ class MixedPlan:
     decoded by one plan (see mcmc_plan_* in the C header).
 
     `items` is a sequence of dicts with keys L, p, sweeps and optionally burn
-    (0), chains (1), n_temps (1), syndrome_id (position).  Syndromes are passed
+    (0), chains (1), n_temps (1), syndrome_id (position), noise (depolarizing)
+    and beta_scale (0: the model's default).  Syndromes are passed
     as one flat uint8 device tensor: item i's n_stab(L_i) bytes after those of
     items 0..i-1; corrections come back the same way (n_q(L_i) bytes each).
     """
@@ -298,18 +300,19 @@ class MixedPlan:
         cols = {k: np.asarray([it.get(k, d) if k != "syndrome_id" else it.get(k, i)
                                for i, it in enumerate(items)])
                 for k, d in (("L", 0), ("p", 0.0), ("sweeps", 0), ("burn", 0), ("chains", 1),
-                             ("n_temps", 1), ("syndrome_id", 0))} if n else {}
+                             ("n_temps", 1), ("syndrome_id", 0), ("noise", 0),
+                             ("beta_scale", 0.0))} if n else {}
         self._build(n, cols, seed, init)
 
     @classmethod
     def from_arrays(cls, L, p, sweeps, seed, chains=1, n_temps=1, burn=0, syndrome_ids=None,
-                    init=MCMC_INIT_MATCHING):
+                    init=MCMC_INIT_MATCHING, noise=MCMC_NOISE_DEPOLARIZING, beta_scale=0.0):
         """Same as the constructor, from per-item arrays (scalars broadcast)."""
         p = np.asarray(p, dtype=np.float64).reshape(-1)
         n = p.size
         bc = lambda v: np.broadcast_to(np.asarray(v), (n,))  # noqa: E731
         cols = dict(L=bc(L), p=p, sweeps=bc(sweeps), burn=bc(burn), chains=bc(chains),
-                    n_temps=bc(n_temps),
+                    n_temps=bc(n_temps), noise=bc(noise), beta_scale=bc(beta_scale),
                     syndrome_id=np.arange(n) if syndrome_ids is None else bc(syndrome_ids))
         self = cls.__new__(cls)
         self._build(n, cols, seed, init)
@@ -338,6 +341,8 @@ class MixedPlan:
             arr["p"] = cols["p"]
             arr["syn_offset"] = self.syn_offsets[:-1]
             arr["corr_offset"] = self.corr_offsets[:-1]
+            arr["noise"] = cols["noise"]
+            arr["beta_scale"] = cols["beta_scale"]
             self.L[:] = L
             np.cumsum(4 * arr["n_temps"].astype(np.int64) * arr["chains"],
                       out=self.chain_offsets[1:])
@@ -406,7 +411,8 @@ class MixedPlan:
         return out
 
     def sample(self, seed, device="cuda"):
-        """Depolarizing samples of every item: (flat syndromes, true classes)."""
+        """Samples of every item under its own noise model and rate: (flat
+        syndromes, true classes)."""
         torch = _torch()
         syn = torch.empty((max(self.syn_bytes, 1),), dtype=torch.uint8, device=device)
         cls = torch.empty((max(self.n, 1),), dtype=torch.uint8, device=device)

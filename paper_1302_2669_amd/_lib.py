@@ -58,6 +58,9 @@ class Item(ctypes.Structure):
         ("p", ctypes.c_double),
         ("syn_offset", ctypes.c_int64),
         ("corr_offset", ctypes.c_int64),
+        ("noise", ctypes.c_uint32),
+        ("reserved", ctypes.c_uint32),
+        ("beta_scale", ctypes.c_double),
     ]
 
 
@@ -164,6 +167,10 @@ _SIGNATURES = {
 _handle = None
 
 
+# layout of the structures below (mcmc_params, mcmc_item, ...)
+ABI_VERSION = 0x00010200
+
+
 def _lib():
     global _handle
     if _handle is None:
@@ -176,6 +183,9 @@ def _lib():
             fn = getattr(h, name)
             fn.restype = res
             fn.argtypes = args
+        if h.mcmc_abi_version() != ABI_VERSION:
+            raise ImportError(f"{LIB_PATH} has ABI {h.mcmc_abi_version():#010x}, this binding "
+                              f"expects {ABI_VERSION:#010x}: rebuild the library")
         _handle = h
     return _handle
 

@@ -135,7 +135,7 @@ const char* mcmc_strerror(int status) {
   }
 }
 
-int32_t mcmc_abi_version(void) { return 0x00010100; }
+int32_t mcmc_abi_version(void) { return 0x00010200; }
 
 int mcmc_geometry(int32_t L, int32_t* n_qubits, int32_t* n_stab) {
   if (!valid_L(L)) return MCMC_ERANGE;

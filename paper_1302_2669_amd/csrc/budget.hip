@@ -82,6 +82,7 @@ __global__ void __launch_bounds__(256) budget_scatter_kernel(const BudgetArgs a)
   it.corr_off = i * (int64_t)(2 * L * L - 2 * L + 1);
   it.table_off = a.beta ? i * 4 * (int64_t)a.K : a.table0_off;
   it.beta_bar = a.beta ? a.beta[i] : a.beta0;
+  it.beta_star = it.beta_bar;
   it.sid = a.ids[i];
   it.group = g;
   it.err_thr = 0;

@@ -42,7 +42,8 @@ struct ItemDesc {               // one syndrome, plan order
   uint32_t sid;                 // Philox counter word 2 (also the sample id)
   int32_t group;
   uint32_t err_thr;             // floor(p 2^32), for sampling this item's errors
-  uint32_t pad;
+  int32_t noise;                // MCMC_NOISE_* of this syndrome
+  double beta_star;             // its K = 1 temperature (beta_bar for K > 1)
 };
 
 struct TileDesc {

@@ -21,6 +21,7 @@ namespace mcmc {
 // Syndrome s of a start launch: its L, input bytes, start block and caller index.
 struct StartItem {
   int L;
+  int noise;                    // energy counted as x|z (0) or x + z parts (1)
   const uint8_t* sy;
   int64_t rows_off, orig;
 };
@@ -29,11 +30,13 @@ __device__ __forceinline__ StartItem start_item(const StartArgs& a, int64_t s) {
   if (a.items) {
     const ItemDesc it = a.items[s];
     r.L = a.groups[it.group].L;
+    r.noise = it.noise;
     r.sy = a.syn + it.syn_off;
     r.rows_off = it.rows_off;
     r.orig = it.orig;
   } else {
     r.L = a.L;
+    r.noise = a.noise;
     r.sy = a.syn + s * (int64_t)(2 * a.L * (a.L - 1));
     r.rows_off = s * (int64_t)words_per_config(a.L) * 4;
     r.orig = s;
@@ -74,7 +77,7 @@ __global__ void __launch_bounds__(256) init_kernel(const StartArgs a) {
     uint32_t zbits = colpar;
     if (i == 0 && xbar) xbits ^= (1u << L) - 1u;
     if (zbar) zbits ^= 1u;
-    weight += a.noise ? __builtin_popcount(xbits) + __builtin_popcount(zbits)
+    weight += si.noise ? __builtin_popcount(xbits) + __builtin_popcount(zbits)
                       : __builtin_popcount(xbits | zbits);
     if (a.bytes) {  // qubit (2i, 2k) is number i*side + k; odd-row qubits are I
       const int side = 2 * L - 1, nq = 2 * L * L - 2 * L + 1;
@@ -190,7 +193,8 @@ __global__ void __launch_bounds__(128) decide_kernel(const DecideArgs a) {
     rows_off = it.rows_off;
     corr_off = it.corr_off;
     beta_bar = it.beta_bar;
-    beta_star = it.beta_bar;
+    beta_star = it.beta_star;
+    noise = it.noise;
   } else {
     g = a.g0;
     orig = s;
@@ -359,7 +363,7 @@ __global__ void __launch_bounds__(256) sample_items_kernel(const ItemDesc* __res
   const int64_t smp = blockIdx.x;
   if (smp >= n) return;
   const ItemDesc it = items[smp];
-  sample_one(groups[it.group].L, 0, it.err_thr, k0, k1, it.sid, err, syn + it.syn_off,
+  sample_one(groups[it.group].L, it.noise, it.err_thr, k0, k1, it.sid, err, syn + it.syn_off,
              true_class + it.orig, nullptr);
 }
 
@@ -557,7 +561,7 @@ __global__ void __launch_bounds__(MATCH_THREADS) init_matching_kernel(const Star
       const int fields = (r & 1) ? L - 1 : L;
       const uint32_t xb = xp[r][tid], zb = zp[r][tid];
       const uint32_t valid = fields >= 32 ? ~0u : ((1u << fields) - 1u);
-      weight += a.noise ? __builtin_popcount(xb & valid) + __builtin_popcount(zb & valid)
+      weight += si.noise ? __builtin_popcount(xb & valid) + __builtin_popcount(zb & valid)
                         : __builtin_popcount((xb | zb) & valid);
       if (a.rows) {
         for (int w = 0; w < W; ++w) {

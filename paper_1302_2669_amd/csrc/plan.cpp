@@ -77,7 +77,10 @@ struct mcmc_plan {
   std::vector<ItemDesc> items;       // plan order
   std::vector<TileDesc> tiles;       // by kernel range, each longest first
   std::vector<uint32_t> tables;
-  int64_t range_first[N_RANGES] = {0}, range_tiles[N_RANGES] = {0};
+  // tiles by launch slot: kernel range r under noise model m is slot m * N_RANGES + r
+  static constexpr int kSlots = 2 * N_RANGES;
+  int64_t range_first[kSlots] = {0}, range_tiles[kSlots] = {0};
+  std::vector<int> group_noise;      // noise model of each group
   int64_t total_chains = 0, total_rows = 0, total_updates = 0;
   size_t corr_bytes = 0;
   // device copies
@@ -116,9 +119,15 @@ PlanWorkspace plan_workspace(const mcmc_plan* p) {
 }
 
 int check_item(const mcmc_item& it) {
-  if (!valid_L(it.L) || !valid_p(it.p)) return MCMC_ERANGE;
+  if (!valid_noise(it.noise) || it.reserved != 0) return MCMC_EINVAL;
+  if (!valid_L(it.L) || !valid_rate(it.noise, it.p)) return MCMC_ERANGE;
   if (it.n_temps < 1 || it.n_temps > MCMC_TEMPS_MAX) return MCMC_ERANGE;
   if (it.n_temps != 1 && (it.n_temps % 2) != 0) return MCMC_EINVAL;
+  if (it.n_temps == 1) {
+    if (!(it.beta_scale >= 0.0 && it.beta_scale <= 4.0)) return MCMC_ERANGE;  // NaN too
+  } else if (it.beta_scale != 0.0 && it.beta_scale != 1.0) {
+    return MCMC_ERANGE;
+  }
   if (it.chains < 1 || it.chains > MCMC_CHAINS_MAX) return MCMC_ERANGE;
   if (it.burn < 0 || it.sweeps < 0 || (int64_t)it.burn + it.sweeps > MCMC_SWEEPS_MAX)
     return MCMC_ERANGE;
@@ -173,25 +182,27 @@ int enqueue(mcmc_plan* p, const uint8_t* syn, double* prob, double* mean_n, int6
 
   const mcmc_tuning& tu = p->tuning;
   const int cus = device_cus();
-  auto run_range = [&](int r, hipStream_t on) -> int {
-    if (p->range_tiles[r] == 0) return MCMC_OK;
+  auto run_range = [&](int slot, hipStream_t on) -> int {
+    if (p->range_tiles[slot] == 0) return MCMC_OK;
+    const int r = slot % N_RANGES;
     RunArgs ra = a;
-    ra.tiles = p->d_tiles + p->range_first[r];
-    ra.n_tiles = p->range_tiles[r];
-    ra.queue = queue + r;
+    ra.noise = slot / N_RANGES;
+    ra.tiles = p->d_tiles + p->range_first[slot];
+    ra.n_tiles = p->range_tiles[slot];
+    ra.queue = queue + slot;
     ra.lmin = RANGE_LO[r];
     ra.lmax = RANGE_HI[r];
     const bool wide = range_is_wide(r);
     // occupancy offset from the kernel's own register-limited occupancy
     const int per_simd = std::max(1, RANGE_WAVES[r] + (wide ? tu.occ_wide : tu.occ_narrow));
     const int wg = wide ? tu.wg_wide : tu.wg_narrow;
-    const int64_t waves = std::min<int64_t>(p->range_tiles[r], (int64_t)cus * 4 * per_simd);
+    const int64_t waves = std::min<int64_t>(p->range_tiles[slot], (int64_t)cus * 4 * per_simd);
     return hip_status(launch_chains(r, ra, (int)waves, wg, on));
   };
   bool narrow = false, wide = false;
-  for (int r = 0; r < N_RANGES; ++r) {
-    if (p->range_tiles[r] == 0) continue;
-    (range_is_wide(r) ? wide : narrow) = true;
+  for (int slot = 0; slot < mcmc_plan::kSlots; ++slot) {
+    if (p->range_tiles[slot] == 0) continue;
+    (range_is_wide(slot % N_RANGES) ? wide : narrow) = true;
   }
   hipStream_t wide_stream = s;
   if (narrow && wide && tu.concurrent) {
@@ -201,8 +212,10 @@ int enqueue(mcmc_plan* p, const uint8_t* syn, double* prob, double* mean_n, int6
     wide_stream = p->side;
   }
   for (int r = N_RANGES - 1; r >= 0; --r) {   // longest tiles first
-    st = run_range(r, range_is_wide(r) ? wide_stream : s);
-    if (st != MCMC_OK) return st;
+    for (int m = 0; m < 2; ++m) {
+      st = run_range(m * N_RANGES + r, range_is_wide(r) ? wide_stream : s);
+      if (st != MCMC_OK) return st;
+    }
   }
   if (wide_stream != s) {
     if (hipEventRecord(p->join, p->side) != hipSuccess) return MCMC_EDEVICE;
@@ -239,10 +252,11 @@ int check_exec(const mcmc_plan* p, const uint8_t* syn, const double* prob, const
 // of (L, K, chains, burn, sweeps, items) groups.
 std::string plan_signature(const mcmc_plan* p) {
   std::string s = "cus=" + std::to_string(device_cus());
-  for (const GroupDesc& g : p->groups) {
+  for (size_t i = 0; i < p->groups.size(); ++i) {
+    const GroupDesc& g = p->groups[i];
     s += ";" + std::to_string(g.L) + "," + std::to_string(g.K) + "," + std::to_string(g.C) + "," +
          std::to_string(g.burn) + "," + std::to_string(g.sweep_end - g.burn) + "," +
-         std::to_string(g.n_items);
+         std::to_string(g.n_items) + (p->group_noise[i] ? ",b" : "");
   }
   return s;
 }
@@ -292,11 +306,12 @@ int build_plan_into(mcmc_plan* p, const mcmc_item* items, int64_t n);
 void clear_plan(mcmc_plan* p) {
   p->n = 0;
   p->groups.clear();
+  p->group_noise.clear();
   p->items.clear();
   p->tiles.clear();
   p->tables.clear();
   p->total_chains = p->total_rows = p->total_updates = 0;
-  for (int r = 0; r < N_RANGES; ++r) p->range_first[r] = p->range_tiles[r] = 0;
+  for (int r = 0; r < mcmc_plan::kSlots; ++r) p->range_first[r] = p->range_tiles[r] = 0;
 }
 
 int build_plan(mcmc_plan* p, const mcmc_item* items, int64_t n) {
@@ -309,20 +324,21 @@ int build_plan_into(mcmc_plan* p, const mcmc_item* items, int64_t n) {
   release_graphs(p);
   p->n = n;
   p->groups.clear();
+  p->group_noise.clear();
   p->items.clear();
   p->tiles.clear();
   p->tables.clear();
   p->total_chains = p->total_rows = p->total_updates = 0;
-  for (int r = 0; r < N_RANGES; ++r) p->range_first[r] = p->range_tiles[r] = 0;
+  for (int r = 0; r < mcmc_plan::kSlots; ++r) p->range_first[r] = p->range_tiles[r] = 0;
 
   // groups: (L, K, C, burn, sweeps) -> items, in order of first appearance
   // (a batch has few distinct keys: linear search with a last-hit cache)
-  using Key = std::tuple<int, int, int, int, int>;
+  using Key = std::tuple<int, int, int, int, int, int>;   // L, K, C, burn, sweeps, noise
   std::vector<std::pair<Key, std::vector<int64_t>>> by_key;
   size_t last = 0;
   for (int64_t i = 0; i < n; ++i) {
     const mcmc_item& it = items[i];
-    const Key k{it.L, it.n_temps, it.chains, it.burn, it.sweeps};
+    const Key k{it.L, it.n_temps, it.chains, it.burn, it.sweeps, (int)it.noise};
     if (by_key.empty() || by_key[last].first != k) {
       last = by_key.size();
       for (size_t j = 0; j < by_key.size(); ++j)
@@ -364,17 +380,27 @@ int build_plan_into(mcmc_plan* p, const mcmc_item* items, int64_t n) {
   // acceptance tables and beta_bar per item, in parallel over contiguous
   // chunks (an item with the rate and ladder of the one before copies its rows)
   p->tables.resize((size_t)t_acc);
-  std::vector<double> bbar(n);
+  std::vector<double> bbar(n), bstar(n);
   auto fill = [&](int64_t lo, int64_t hi) {
     for (int64_t i = lo; i < hi; ++i) {
       const mcmc_item& it = items[i];
       uint32_t* dst = p->tables.data() + table_off[i];
-      if (i > lo && it.p == items[i - 1].p && it.n_temps == items[i - 1].n_temps) {
+      const mcmc_item* prev = i > lo ? &items[i - 1] : nullptr;
+      if (prev && it.p == prev->p && it.n_temps == prev->n_temps && it.noise == prev->noise &&
+          it.beta_scale == prev->beta_scale) {
         std::copy(dst - 4 * it.n_temps, dst, dst);
         bbar[i] = bbar[i - 1];
+        bstar[i] = bstar[i - 1];
       } else {
-        fill_table(it.p, it.n_temps, dst);
-        bbar[i] = beta_bar(it.p);
+        // the same tables and temperatures as a uniform decode of this item
+        mcmc_params prm{};
+        prm.p = it.p;
+        prm.n_temps = it.n_temps;
+        prm.noise = it.noise;
+        prm.beta_scale = it.beta_scale;
+        fill_params_table(&prm, dst);
+        bbar[i] = beta_bar_of(it.noise, it.p);
+        bstar[i] = beta_top(&prm);
       }
     }
   };
@@ -418,6 +444,8 @@ int build_plan_into(mcmc_plan* p, const mcmc_item* items, int64_t n) {
       it.corr_off = src.corr_offset;
       it.table_off = table_off[i];
       it.beta_bar = bbar[i];
+      it.beta_star = bstar[i];
+      it.noise = (int32_t)src.noise;
       it.sid = src.syndrome_id;
       it.group = gid;
       it.err_thr = (uint32_t)floor(ldexp(src.p, 32));
@@ -426,17 +454,19 @@ int build_plan_into(mcmc_plan* p, const mcmc_item* items, int64_t n) {
                           ((int64_t)src.burn + src.sweeps) * n_stab(src.L);
     }
     p->groups.push_back(g);
+    p->group_noise.push_back(std::get<5>(k));
   }
-  // tiles per kernel range, each range longest first (groups are already in
-  // descending cost order)
-  for (int r = 0; r < N_RANGES; ++r) {
-    p->range_first[r] = (int64_t)p->tiles.size();
+  // tiles per launch slot (kernel range and noise model), each slot longest
+  // first (groups are already in descending cost order)
+  for (int slot = 0; slot < mcmc_plan::kSlots; ++slot) {
+    const int r = slot % N_RANGES, m = slot / N_RANGES;
+    p->range_first[slot] = (int64_t)p->tiles.size();
     for (size_t gi = 0; gi < p->groups.size(); ++gi) {
       const GroupDesc& g = p->groups[gi];
-      if (range_of(g.L) != r) continue;
+      if (range_of(g.L) != r || p->group_noise[gi] != m) continue;
       for (int64_t f = 0; f < g.n_tasks; f += TILE) p->tiles.push_back(TileDesc{(int32_t)gi, g.L, f});
     }
-    p->range_tiles[r] = (int64_t)p->tiles.size() - p->range_first[r];
+    p->range_tiles[slot] = (int64_t)p->tiles.size() - p->range_first[slot];
   }
   if ((int64_t)p->tiles.size() > 0xFFFFFFFFll) return MCMC_ERANGE;
 

@@ -27,7 +27,7 @@ def test_exports_every_declared_symbol():
     assert decl == _lib.exported_symbols()
     for name in decl:
         assert hasattr(lib, name), name
-    assert lib.mcmc_abi_version() == 0x00010100
+    assert lib.mcmc_abi_version() == 0x00010200
 
 
 @pytest.mark.parametrize("L", list(range(2, 26)))
@@ -132,7 +132,10 @@ def test_plan_rejects_invalid_items_before_allocating():
     good = dict(L=9, sweeps=10, burn=0, chains=2, n_temps=1, syndrome_id=0, p=0.1,
                 syn_offset=0, corr_offset=0)
     for bad, status in ((dict(L=1), -2), (dict(L=26), -2), (dict(p=0.9), -2), (dict(n_temps=3), -1),
-                        (dict(chains=0), -2), (dict(sweeps=-1), -2), (dict(syn_offset=-4), -2)):
+                        (dict(chains=0), -2), (dict(sweeps=-1), -2), (dict(syn_offset=-4), -2),
+                        (dict(noise=2), -1), (dict(reserved=1), -1), (dict(noise=1, p=0.5), -2),
+                        (dict(beta_scale=-0.1), -2), (dict(beta_scale=float("nan")), -2),
+                        (dict(n_temps=2, beta_scale=0.85), -2)):
         arr = (_lib.Item * 2)()
         for i in range(2):
             for k, v in good.items():
@@ -140,6 +143,16 @@ def test_plan_rejects_invalid_items_before_allocating():
         for k, v in bad.items():
             setattr(arr[1], k, v)
         assert lib.mcmc_plan_create(arr, 2, 1, 1, ctypes.byref(h)) == status
+    # both noise models and a lowered beta* pass validation in one plan
+    arr = (_lib.Item * 2)()
+    for i in range(2):
+        for k, v in good.items():
+            setattr(arr[i], k, v)
+    arr[1].noise, arr[1].p, arr[1].beta_scale = 1, 0.45, 0.85
+    assert lib.mcmc_plan_create(arr, 2, 1, 1, ctypes.byref(h)) in (0, -3, -4, -6)
+    if h:
+        assert lib.mcmc_plan_destroy(h) == 0
+        h = ctypes.c_void_p()
     assert lib.mcmc_plan_create(None, 3, 1, 1, ctypes.byref(h)) == -1
     assert lib.mcmc_plan_create(None, 0, 1, 5, ctypes.byref(h)) == -1
     assert lib.mcmc_plan_destroy(None) == 0

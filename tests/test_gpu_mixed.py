@@ -25,17 +25,20 @@ def say(msg):
     sys.stdout.flush()
 
 
-def make_batch(Ls, ps, sweeps, seed, chains=None, n_temps=None, burns=None):
+def make_batch(Ls, ps, sweeps, seed, chains=None, n_temps=None, burns=None, noise=None,
+               scales=None):
     items, syns = [], []
     for i, (L, p, sw) in enumerate(zip(Ls, ps, sweeps)):
         lat = geometry.Lattice(int(L))
-        syn, _, _ = sampler.sample(lat, float(p), seed, [1000 + i])
+        nz = int(noise[i]) if noise is not None else 0
+        syn, _, _ = sampler.sample(lat, float(p), seed, [1000 + i], noise=nz)
         syns.append(syn[0])
         items.append(dict(L=int(L), p=float(p), sweeps=int(sw),
                           burn=int(burns[i]) if burns is not None else 0,
                           chains=int(chains[i]) if chains is not None else 2,
                           n_temps=int(n_temps[i]) if n_temps is not None else 1,
-                          syndrome_id=7 * i + 1))
+                          syndrome_id=7 * i + 1, noise=nz,
+                          beta_scale=float(scales[i]) if scales is not None else 0.0))
     flat = torch.from_numpy(np.concatenate(syns)).to(DEV)
     return items, syns, flat
 
@@ -52,7 +55,8 @@ def uniform(item, syn, seed):
     s = torch.from_numpy(syn[None]).to(DEV)
     o = mc.decode_batch(s, item["L"], item["p"], item["sweeps"], seed, chains=item["chains"],
                         n_temps=item["n_temps"], burn=item["burn"],
-                        syndrome_ids=torch.tensor([item["syndrome_id"]]), want_sums=True)
+                        syndrome_ids=torch.tensor([item["syndrome_id"]]), want_sums=True,
+                        noise=item.get("noise", 0), beta_scale=item.get("beta_scale", 0.0))
     torch.cuda.synchronize()
     return dict(sum_n=o["sum_n"].reshape(-1).cpu().numpy(),
                 accepts=o["accepts"].reshape(-1).cpu().numpy(), chosen=int(o["chosen"][0]),
@@ -174,4 +178,79 @@ def test_plan_sampler_parity():
         a, b = plan.syn_offsets[i], plan.syn_offsets[i + 1]
         assert np.array_equal(syn[a:b], o_syn[0])
         assert cls[i] == o_cls[0]
+    plan.close()
+
+
+def test_mixed_noise_models_equal_uniform_decodes():
+    """Items of both noise models, with default and explicit beta*, in every
+    kernel range of one plan: each equals its uniform decode bit for bit, in
+    every launch shape."""
+    say("mixed plan with both noise models")
+    rng = np.random.default_rng(17)
+    Ls = [3, 25, 5, 17, 9, 13, 2, 20, 16, 23, 7, 14, 19, 22, 3, 21, 18, 4, 13, 25]
+    noise = [i % 2 for i in range(len(Ls))]
+    ps = [float(rng.uniform(0.05, 0.15)) for _ in Ls]
+    scales = [(0.0, 0.7, 1.0, 0.0, 1.3)[i % 5] for i in range(len(Ls))]
+    n_temps = [2 if i % 7 == 3 else 1 for i in range(len(Ls))]
+    scales = [0.0 if k == 2 else s for k, s in zip(n_temps, scales)]
+    sweeps = [min(L * L, 30) for L in Ls]
+    chains = rng.integers(1, 4, len(Ls))
+    burns = [i % 2 for i in range(len(Ls))]
+    items, syns, flat = make_batch(Ls, ps, sweeps, 23, chains, n_temps, burns, noise, scales)
+    plan = mc.MixedPlan(items, seed=0x5EED)
+    out = plan.execute(flat, want_sums=True)
+    torch.cuda.synchronize()
+    for i, it in enumerate(items):
+        same(per_item(plan, out, i), uniform(it, syns[i], 0x5EED))
+    base = {k: v.clone() for k, v in out.items()}
+    for tun in (dict(wg_narrow=64, occ_narrow=-4, wg_wide=128, occ_wide=-2, concurrent=0),
+                dict(wg_narrow=128, occ_narrow=3, wg_wide=64, occ_wide=2, concurrent=1)):
+        plan.tuning = tun
+        o2 = plan.execute(flat, want_sums=True)
+        torch.cuda.synchronize()
+        for k in base:
+            assert torch.equal(base[k], o2[k]), (tun, k)
+    plan.close()
+
+
+def test_mixed_bitphase_items_against_oracle():
+    say("mixed plan bit/phase items vs oracle")
+    Ls, ps, sweeps = [5, 9, 14, 18, 22], [0.07, 0.1, 0.12, 0.09, 0.1], [6, 5, 3, 2, 2]
+    noise, scales = [1, 1, 0, 1, 1], [0.0, 0.9, 0.0, 1.0, 0.0]
+    items, syns, flat = make_batch(Ls, ps, sweeps, 6, noise=noise, scales=scales)
+    plan = mc.MixedPlan(items, seed=31)
+    out = plan.execute(flat, want_sums=True)
+    torch.cuda.synchronize()
+    for i, it in enumerate(items):
+        g = per_item(plan, out, i)
+        o = decoder.decode(it["L"], syns[i][None], it["p"], it["sweeps"], 31,
+                           chains_per_class=it["chains"], syndrome_ids=[it["syndrome_id"]],
+                           noise=it["noise"],
+                           beta_scale=None if it["beta_scale"] == 0.0 else it["beta_scale"])
+        assert np.array_equal(g["sum_n"], o["sum_n"].reshape(-1))
+        assert np.array_equal(g["accepts"], o["accepts"].reshape(-1))
+        assert g["chosen"] == int(o["chosen"][0])
+        assert np.array_equal(g["correction"], o["correction"][0])
+        np.testing.assert_allclose(g["class_prob"], o["class_prob"][0], rtol=1e-12, atol=0)
+        np.testing.assert_allclose(g["mean_n"], o["mean_n"][0], rtol=1e-12, atol=0)
+    plan.close()
+
+
+def test_plan_sampler_noise_models():
+    """A plan's sampler follows each item's noise model (oracle sampler)."""
+    say("plan sampler, both noise models")
+    L, p, _ = mixed_workload(40, seed=13)
+    items = [dict(L=int(l), p=float(q), sweeps=1, syndrome_id=2000 + 5 * i, noise=i % 2)
+             for i, (l, q) in enumerate(zip(L, p))]
+    plan = mc.MixedPlan(items, seed=1)
+    syn, cls = plan.sample(0xBEEF)
+    torch.cuda.synchronize()
+    syn, cls = syn.cpu().numpy(), cls.cpu().numpy()
+    for i, it in enumerate(items):
+        lat = geometry.Lattice(it["L"])
+        o_syn, o_cls, _ = sampler.sample(lat, it["p"], 0xBEEF, [it["syndrome_id"]],
+                                         noise=it["noise"])
+        a, b = plan.syn_offsets[i], plan.syn_offsets[i + 1]
+        assert np.array_equal(syn[a:b], o_syn[0]), i
+        assert cls[i] == o_cls[0], i
     plan.close()
