@@ -32,6 +32,9 @@ BATCH = 65536
 # Philox4x32-10 share 20 (5 mul_lo + 5 mul_hi + 10 xor), weight change 8-12,
 # accept 4, flip 4, accumulate 3 -> 40 at the low end
 OPS_PER_UPDATE = 40
+# random scan: two uniforms per step (40), the site pick (a high multiply, 1),
+# weight change, accept and flip as above (16) and the per-step sums (3)
+RS_OPS_PER_UPDATE = 60
 # MI355X vector ALU: 256 CUs x 128 lanes per clock x 2.4 GHz = 78.6 T lane
 # slots/s (the FP32 vector peak of 157.3 TFLOP/s counts an FMA as two flops);
 # three-operand integer instructions (v_mad_u64_u32: mul_lo + mul_hi,
@@ -65,7 +68,8 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=640)
     ap.add_argument("--no-budget-curve", action="store_true",
                     help="skip the logical error vs sweep budget curve")
-    ap.add_argument("--workload", choices=["metric", "mixed", "gated", "bitphase", "spacetime"],
+    ap.add_argument("--workload", choices=["metric", "mixed", "gated", "bitphase", "spacetime",
+                                           "randomscan"],
                     default="metric",
                     help="metric: L=13 p=0.15 (default); mixed: L in 5..25, p in [0.05,0.18]; "
                          "gated: gate network trained and timed against the plain decoder; "
@@ -97,6 +101,8 @@ def main():
         return bench_bitphase(args, mc, torch, dev)
     if args.workload == "spacetime":
         return bench_spacetime(args, mc, torch, dev)
+    if args.workload == "randomscan":
+        return bench_randomscan(args, mc, torch, dev)
     n = args.batch
     nq, ns = mc.geometry(L)
     steps, warm = args.steps, args.warmup
@@ -620,7 +626,82 @@ def bench_spacetime(args, mc, torch, dev):
     print(json.dumps(line), flush=True)
 
 
-def cpu_baseline(n_sample, ns, noise=0, p=P):
+def bench_randomscan(args, mc, torch, dev):
+    """The paper's own random-scan chain (Sec. IV: one stabilizer picked at
+    random per step, n summed after every step) at the metric point: L = 13,
+    p = 0.15, 4 x 4 chains, 169 sweeps of n_stab steps.  A cross-check of the
+    colour-phased scan, not the throughput path."""
+    n, steps, warm = args.batch, args.steps, args.warmup
+    nq, ns = mc.geometry(L)
+    batches, truth = [], []
+    for b in range(warm + steps):
+        syn, cls, _ = mc.sample_errors(L, P, SEED, n, device=dev, id_base=b * n)
+        batches.append(syn)
+        truth.append(cls)
+    prm = mc.make_params(L, P, SWEEPS, SEED, chains=CHAINS, flags=mc.MCMC_RANDOM_SCAN)
+    ws = torch.empty((mc.workspace_size(prm, n),), dtype=torch.uint8, device=dev)
+    ids = [torch.arange(b * n, (b + 1) * n, dtype=torch.int32, device=dev)
+           for b in range(warm + steps)]
+    torch.cuda.synchronize()
+
+    def step(b, sweeps=SWEEPS):
+        return mc.decode_batch(batches[b], L, P, sweeps, SEED, chains=CHAINS, syndrome_ids=ids[b],
+                               want_correction=True, workspace=ws, random_scan=True)
+
+    for b in range(warm):
+        step(b)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream(dev)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    chosen = []
+    t0 = time.perf_counter()
+    ev[0].record(stream)
+    for i in range(steps):
+        chosen.append(step(warm + i)["chosen"])
+        ev[i + 1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    step_ms = float(np.mean([ev[i].elapsed_time(ev[i + 1]) for i in range(steps)]))
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for i in range(steps):
+        step(warm + i, sweeps=0)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    chain_ms = step_ms - e0.elapsed_time(e1) / steps
+    updates_per_syndrome = 4 * CHAINS * SWEEPS * ns
+    achieved = n * updates_per_syndrome * RS_OPS_PER_UPDATE / (chain_ms * 1e-3) / 1e12
+    peak = PEAK_INT_OPS / 1e12
+    fails = sum(int((c != t).sum().item()) for c, t in zip(chosen, truth[warm:]))
+    total = n * steps
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(min(args.cpu_sample, 64), ns, random_scan=True)
+    line = {
+        "metric": "decoded syndromes/sec + stabilizer updates/sec at L=13 p=0.15, random scan",
+        "value": total / wall,
+        "unit": "syndromes/s",
+        "stabilizer_updates_per_s": total / wall * updates_per_syndrome,
+        "n_gpus": 1, "steps": steps, "warmup": warm, "ms_per_step": wall * 1e3 / steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32",
+        "data": "synthetic: i.i.d. depolarizing samples from the library's Philox sampler",
+        "config": {"workload": "planar code L=13, depolarizing p=0.15, 4 classes x 4 chains, "
+                               "169 sweeps of n_stab random-site steps, single temperature, "
+                               f"batch of {n} syndromes per step",
+                   "L": L, "p": P, "chains_per_class": CHAINS, "sweeps": SWEEPS, "batch": n,
+                   "updates_per_syndrome": updates_per_syndrome},
+        "logical_error": {"rate": fails / total, "samples": total},
+        "roofline": {"bound": "alu", "kernel": "chains_random_kernel (at L=13)",
+                     "achieved": achieved, "peak": peak, "unit": "Tops/s",
+                     "frac": achieved / peak, "traffic": None,
+                     "chain_ms_per_launch": chain_ms, "ops_per_update": RS_OPS_PER_UPDATE,
+                     "updates_per_launch": n * updates_per_syndrome},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def cpu_baseline(n_sample, ns, noise=0, p=P, random_scan=False):
     """The oracle, as written, on a bounded sample of the same workload."""
     here = os.path.dirname(os.path.abspath(__file__))
     if here not in sys.path:
@@ -630,12 +711,13 @@ def cpu_baseline(n_sample, ns, noise=0, p=P):
     syn, _, _ = sampler.sample(lat, p, SEED, np.arange(n_sample), noise=noise)
     t0 = time.perf_counter()
     decoder.decode(L, syn, p, SWEEPS, SEED, chains_per_class=CHAINS, n_temps=K, burn=BURN,
-                   noise=noise)
+                   noise=noise, scan=decoder.SCAN_RANDOM if random_scan else decoder.SCAN_COLOUR)
     dt = time.perf_counter() - t0
     model = "bit/phase flips q" if noise else "p"
+    scan = ", random scan" if random_scan else ""
     return {"value": n_sample / dt, "unit": "syndromes/s", "cores": 1, "kind": "oracle",
             "sample": f"{n_sample} syndromes of the same workload (L=13, {model}={p}, 4x4 "
-                      f"chains, 169 sweeps), NumPy oracle in one process, {dt:.1f} s",
+                      f"chains, 169 sweeps{scan}), NumPy oracle in one process, {dt:.1f} s",
             "stabilizer_updates_per_s": n_sample * 4 * CHAINS * K * (BURN + SWEEPS) * ns / dt}
 
 
