@@ -526,12 +526,12 @@ def bench_spacetime(args, mc, torch, dev):
     """Imperfect measurements (Sec. VI): L = 7, T = 7 rounds (the last one
     perfect), depolarizing p = 0.02 per interval and outcome error p_M = 0.02,
     4 classes x 4 chains, 784 = 16 L^2 sweeps of every spatial and time move
-    (the local moves relax slowly in space-time), 9216 histories per step
-    (147456 chains: 2304 one-wave workgroups, as many as the LDS lets the
-    256 CUs hold at once).
+    (the local moves relax slowly in space-time), 32768 histories per step
+    (524288 chains: 8192 one-wave workgroups, 8 waves on each of the 1024
+    SIMDs, the register-resident kernel's full residency).
     Also the logical error of decoding the last round alone with the
     single-round decoder (L^2 sweeps), on the same histories."""
-    Ls, T, p, pm, chains, sweeps, n = 7, 7, 0.02, 0.02, 4, 784, 9216
+    Ls, T, p, pm, chains, sweeps, n = 7, 7, 0.02, 0.02, 4, 784, 32768
     steps, warm = args.steps, args.warmup
     nq, ns = mc.geometry(Ls)
     hist, truth = [], []

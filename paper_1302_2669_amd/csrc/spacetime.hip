@@ -371,9 +371,12 @@ __device__ __forceinline__ uint32_t st_opaque(uint32_t v) {
 }
 
 template <int L>
-// 4 waves per SIMD (128 registers): the few spills the cap costs are stores
-// in the move sequences whose values are read back only after the last sweep.
-__global__ void __launch_bounds__(ST_LANES) __attribute__((amdgpu_waves_per_eu(4)))
+// 8 waves per SIMD (64 registers), the most a SIMD holds: the move sequence is
+// latency-bound (Philox chains, table loads), and more resident waves hide
+// more of it than the extra spills cost (measured at L = 7: 4.9e11 moves/s
+// against 4.3e11 at 4 waves).  The spills are stores in the move sequences
+// whose values are read back only after the last sweep.
+__global__ void __launch_bounds__(ST_LANES) __attribute__((amdgpu_waves_per_eu(8)))
 st_chain_fast_kernel(const SpaceTimeArgs a) {
   using G = StGeo<L>;
   constexpr int NQ = G::NQ, NSTAB = G::NSTAB, NSTAR = G::NSTAR, WQ = G::WQ, WM = G::WM;
