@@ -208,6 +208,31 @@ def main():
             c["rel_error_change"] = (c["logical_error"] - ref_err) / ref_err
         matched = next(c for c in curve if c["rel_error_change"] <= 0.02)
 
+    # end to end: syndromes from pinned host memory, decisions, class
+    # probabilities and corrections back to pinned host memory, same stream
+    ne = min(4, steps)
+    h_syn = [batches[warm + i].cpu().pin_memory() for i in range(ne)]
+    h_chosen = torch.empty((n,), dtype=torch.uint8).pin_memory()
+    h_prob = torch.empty((n, 4), dtype=torch.float64).pin_memory()
+    h_corr = torch.empty((n, nq), dtype=torch.uint8).pin_memory()
+    d_syn = torch.empty_like(batches[0])
+    torch.cuda.synchronize()
+    t_e2e = time.perf_counter()
+    for i in range(ne):
+        d_syn.copy_(h_syn[i], non_blocking=True)
+        o = mc.decode_batch(d_syn, L, P, SWEEPS, SEED, chains=CHAINS, n_temps=K, burn=BURN,
+                            syndrome_ids=ids[warm + i], want_correction=True, workspace=ws)
+        h_chosen.copy_(o["chosen"], non_blocking=True)
+        h_prob.copy_(o["class_prob"], non_blocking=True)
+        h_corr.copy_(o["correction"], non_blocking=True)
+        torch.cuda.synchronize()
+        if i == 0 and not torch.equal(h_chosen, chosen[0].cpu()):
+            raise RuntimeError("end-to-end decisions differ from the resident run")
+    e2e = {"syndromes_per_s": n * ne / (time.perf_counter() - t_e2e), "steps": ne,
+           "note": "syndromes copied in from pinned host memory and decisions, class "
+                   "probabilities and corrections copied back, on the decode stream, "
+                   "synchronised per batch"}
+
     if args.copy_probe_mb:
         src = torch.ones((args.copy_probe_mb << 20,), dtype=torch.uint8, device=dev)
         dst = torch.empty_like(src)
@@ -247,6 +272,7 @@ def main():
                      "chain_ms_per_launch": chain_ms, "ops_per_update": OPS_PER_UPDATE,
                      "updates_per_launch": chain_updates},
         "cpu_baseline": cpu,
+        "end_to_end": e2e,
         "budget_curve": curve,
         "matched_error_budget": None if curve is None else
             {"sweeps": matched["sweeps"], "syndromes_per_s": matched["syndromes_per_s"],
