@@ -122,3 +122,27 @@ def test_scans_agree_in_equilibrium(noise, p):
     assert z.size > 500
     assert abs(z.mean()) < 5 / np.sqrt(z.size) + 0.05
     assert 0.7 < z.std() < 1.5
+
+
+def test_workload_sampled():
+    """The benchmarked launch: L = 13, p = 0.15, 4 x 4 chains, 169 sweeps,
+    65536 syndromes decoded at once with the random scan; four syndromes
+    spread over the batch are replayed on the oracle (same ids) and must
+    match bit for bit."""
+    from paper_1302_2669_amd.inputs import SEED_METRIC
+    L, p, n, sweeps, chains = 13, 0.15, 65536, 169, 4
+    say(f"random-scan workload L={L} p={p} n={n} sweeps={sweeps}")
+    syn_d, cls_d, _ = mc.sample_errors(L, p, SEED_METRIC, n, device=DEV)
+    out = to_np(mc.decode_batch(syn_d, L, p, sweeps, SEED_METRIC, chains=chains, want_sums=True,
+                                random_scan=True))
+    syn = syn_d.cpu().numpy()
+    sel = np.array([0, 21845, 43690, n - 1])
+    o = decoder.decode(L, syn[sel], p, sweeps, SEED_METRIC, chains_per_class=chains,
+                       syndrome_ids=sel, scan=decoder.SCAN_RANDOM)
+    for k in ("sum_n", "accepts", "chosen", "correction"):
+        assert np.array_equal(out[k][sel], o[k]), k
+    np.testing.assert_allclose(out["class_prob"][sel], o["class_prob"], rtol=RTOL, atol=0)
+    np.testing.assert_allclose(out["mean_n"][sel], o["mean_n"], rtol=RTOL, atol=0)
+    err = float((out["chosen"] != cls_d.cpu().numpy()).mean())
+    say(f"  logical error {err:.4f}")
+    assert 0.2 < err < 0.4

@@ -113,3 +113,33 @@ def test_decoder_beats_ignoring_outcome_errors():
     say(f"  logical error: space-time {e_st:.4f}, final round only {e_last:.4f}")
     assert e_st < 0.10
     assert e_st <= e_last + 0.01
+
+
+def test_workload_sampled():
+    """The benchmarked launch: L = 7, T = 7, p = p_M = 0.02, 4 x 4 chains,
+    784 sweeps, 32768 histories sampled on the GPU and decoded in one call
+    (the register-resident kernel at full residency).  The last history is
+    replayed on the oracle with the same id (about a minute of CPU) and must
+    match bit for bit."""
+    L, T, p, pm, n, sweeps, chains = 7, 7, 0.02, 0.02, 32768, 784, 4
+    say(f"space-time workload L={L} T={T} n={n} sweeps={sweeps}")
+    obs, cls = mc.sample_spacetime(L, T, p, pm, SEED, n, device=DEV, id_base=7)
+    ids = torch.arange(7, 7 + n, dtype=torch.int32, device=DEV)
+    g = mc.decode_spacetime(obs, L, p, pm, sweeps, SEED, chains=chains, syndrome_ids=ids,
+                            want_sums=True)
+    torch.cuda.synchronize()
+    g = {k: v.cpu().numpy() for k, v in g.items()}
+    sel = np.array([n - 1])
+    o_obs = obs.cpu().numpy()[sel]
+    lat = geometry.Lattice(L)
+    r_obs, r_cls, _, _ = stm.sample(lat, p, pm, T, SEED, 7 + sel)
+    assert np.array_equal(o_obs, r_obs) and np.array_equal(cls.cpu().numpy()[sel], r_cls)
+    say("  replaying history n-1 on the oracle")
+    o = stm.decode(L, o_obs, p, pm, sweeps, SEED, chains_per_class=chains, syndrome_ids=7 + sel)
+    for k in ("sum_n", "sum_m", "accepts", "chosen", "correction"):
+        assert np.array_equal(g[k][sel], o[k]), k
+    for k in ("class_prob", "mean_n", "mean_m"):
+        np.testing.assert_allclose(g[k][sel], o[k], rtol=RTOL, atol=0)
+    err = float((g["chosen"] != cls.cpu().numpy()).mean())
+    say(f"  logical error {err:.4f}")
+    assert err < 0.08
