@@ -269,9 +269,11 @@ typedef struct mcmc_item {
 /* Launch shape of a plan: workgroup size (64, 128 or 256) of the L <= 16
  * kernels (narrow) and of the L >= 17 kernels (wide); the persistent grid of
  * each kernel in waves per SIMD, as an offset (narrow -4..8, wide -2..8)
- * from the occupancy its register budget allows; and whether the two groups
- * run on two streams at once (1) or one after the other (0).  Never changes
- * results. */
+ * from the occupancy its register budget allows; and the streams: all
+ * kernels one after the other on the caller's stream (0), the L >= 17 kernels
+ * on one side stream beside the L <= 16 ones (1), or each of the three
+ * L >= 17 kernels on a side stream of its own (2), joined to the caller's
+ * stream before the estimator.  Never changes results. */
 typedef struct mcmc_tuning {
   int32_t wg_narrow, occ_narrow;
   int32_t wg_wide, occ_wide;
@@ -281,7 +283,7 @@ typedef struct mcmc_tuning {
 typedef struct mcmc_plan mcmc_plan; /* opaque */
 
 /* Build a plan for n items (host array, copied).  Allocates the plan's device
- * tables (hipMalloc) and two streams; *plan receives the handle.  ERANGE /
+ * tables (hipMalloc) and four streams; *plan receives the handle.  ERANGE /
  * EINVAL for an invalid item (checked before anything is allocated). */
 int mcmc_plan_create(const mcmc_item* h_items, int64_t n, uint64_t seed, uint32_t init,
                      mcmc_plan** plan);

@@ -88,7 +88,8 @@ def test_mixed_plan_equals_uniform_decodes():
     # every launch shape gives the same bits
     base = {k: v.clone() for k, v in out.items()}
     for tun in (dict(wg_narrow=64, occ_narrow=-4, wg_wide=128, occ_wide=-2, concurrent=0),
-                dict(wg_narrow=128, occ_narrow=3, wg_wide=64, occ_wide=2, concurrent=1)):
+                dict(wg_narrow=128, occ_narrow=3, wg_wide=64, occ_wide=2, concurrent=1),
+                dict(wg_narrow=256, occ_narrow=0, wg_wide=256, occ_wide=1, concurrent=2)):
         plan.tuning = tun
         o2 = plan.execute(flat, want_sums=True)
         torch.cuda.synchronize()
@@ -204,7 +205,8 @@ def test_mixed_noise_models_equal_uniform_decodes():
         same(per_item(plan, out, i), uniform(it, syns[i], 0x5EED))
     base = {k: v.clone() for k, v in out.items()}
     for tun in (dict(wg_narrow=64, occ_narrow=-4, wg_wide=128, occ_wide=-2, concurrent=0),
-                dict(wg_narrow=128, occ_narrow=3, wg_wide=64, occ_wide=2, concurrent=1)):
+                dict(wg_narrow=128, occ_narrow=3, wg_wide=64, occ_wide=2, concurrent=1),
+                dict(wg_narrow=256, occ_narrow=0, wg_wide=256, occ_wide=1, concurrent=2)):
         plan.tuning = tun
         o2 = plan.execute(flat, want_sums=True)
         torch.cuda.synchronize()
