@@ -69,7 +69,7 @@ def main():
     ap.add_argument("--no-budget-curve", action="store_true",
                     help="skip the logical error vs sweep budget curve")
     ap.add_argument("--workload", choices=["metric", "mixed", "gated", "bitphase", "spacetime",
-                                           "randomscan"],
+                                           "randomscan", "context"],
                     default="metric",
                     help="metric: L=13 p=0.15 (default); mixed: L in 5..25, p in [0.05,0.18]; "
                          "gated: gate network trained and timed against the plain decoder; "
@@ -103,6 +103,8 @@ def main():
         return bench_spacetime(args, mc, torch, dev)
     if args.workload == "randomscan":
         return bench_randomscan(args, mc, torch, dev)
+    if args.workload == "context":
+        return bench_context(args, mc, torch, dev)
     n = args.batch
     nq, ns = mc.geometry(L)
     steps, warm = args.steps, args.warmup
@@ -723,6 +725,48 @@ def bench_randomscan(args, mc, torch, dev):
                      "chain_ms_per_launch": chain_ms, "ops_per_update": RS_OPS_PER_UPDATE,
                      "updates_per_launch": n * updates_per_syndrome},
         "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def bench_context(args, mc, torch, dev):
+    """Logical error rates set beside the paper's own figures (context, not a
+    throughput line).  (a) Sec. IV.A's proof-of-principle point: at
+    depolarizing p = 0.13 the single-temperature decoder's logical error falls
+    below p from L = 6 on.  (b) Its threshold of 15-16%: logical error against
+    p for several L, where curves of growing L cross.  The paper starts its
+    chains from enhanced matching and samples L^4 steps per chain (about L^2/2
+    sweeps); these runs start from the greedy matching start, 4 classes x 4
+    chains, at budgets of L^2, 4 L^2 and 16 L^2 sweeps (65536, 16384 and 8192
+    syndromes per point)."""
+    z = 1.96
+
+    def point(L, p, mult, n, seed):
+        syn, cls, _ = mc.sample_errors(L, p, seed, n, device=dev)
+        out = mc.decode_batch(syn, L, p, mult * L * L, seed, chains=CHAINS, want_correction=False)
+        wrong = int((out["chosen"] != cls).sum().item())
+        r = wrong / n
+        den = 1 + z * z / n
+        c = (r + z * z / (2 * n)) / den
+        h = z * np.sqrt(r * (1 - r) / n + z * z / (4 * n * n)) / den
+        return {"L": L, "p": p, "sweeps": mult * L * L, "logical_error": r,
+                "wilson95": [c - h, c + h], "samples": n}
+
+    t0 = time.perf_counter()
+    small, scan = [], []
+    for mult, n in ((1, args.batch), (4, args.batch // 4), (16, args.batch // 8)):
+        small += [point(L, 0.13, mult, n, SEED + 100 + L) for L in (4, 5, 6, 7, 8)]
+        scan += [point(L, p, mult, n, SEED + 1000 * L + int(p * 1000))
+                 for L in (9, 13, 17, 21, 25) for p in (0.14, 0.15, 0.16, 0.17)]
+    line = {
+        "metric": "logical error rate beside the paper's figures (context)",
+        "value": None, "unit": "logical error", "n_gpus": 1, "higher_is_better": False,
+        "data": "synthetic: i.i.d. depolarizing samples from the library's Philox sampler",
+        "config": {"workload": "depolarizing noise, greedy matching start, 4 classes x 4 chains, "
+                               "L^2, 4 L^2 and 16 L^2 sweeps"},
+        "proof_of_principle_p013": small,
+        "threshold_scan": scan,
+        "seconds": time.perf_counter() - t0,
     }
     print(json.dumps(line), flush=True)
 
