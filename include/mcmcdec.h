@@ -243,9 +243,9 @@ int mcmc_sample_errors_model(int32_t L, uint32_t noise, double p, uint64_t seed,
  * chains and temperature count in one decode).  A plan is built once on the
  * host from an array of items; executing it enqueues the class starts, the
  * persistent chain kernels (one per L range and noise model its syndromes
- * fall in; ranges 2-13, 14-16, and on a
- * second stream 17-19, 20-22, 23-25; waves take 64-chain tiles from an atomic
- * queue, longest tiles first) and the estimator, with no host
+ * fall in; ranges 2-13, 14-16 on the caller's stream and 17-19, 20-22, 23-25
+ * on side streams, as mcmc_tuning.concurrent sets; waves take 64-chain tiles
+ * from an atomic queue, longest tiles first) and the estimator, with no host
  * synchronisation.  The same sequence can be recorded into a HIP graph once
  * and replayed (mcmc_plan_graph_launch).  Per-syndrome results are identical
  * to mcmc_decode_batch with that syndrome's parameters and id, whatever the
