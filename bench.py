@@ -90,16 +90,19 @@ def main():
 
     # the oracle baseline first, in forked workers, before anything touches the GPU
     args.cpu = None
-    if not args.no_cpu_baseline and args.workload in ("metric", "bitphase", "randomscan"):
+    if not args.no_cpu_baseline and args.workload in ("metric", "bitphase", "randomscan",
+                                                      "spacetime"):
         ns = 2 * L * (L - 1)
         if args.workload == "metric":
             args.cpu = cpu_baseline(args.cpu_sample, ns, workers=host_cores())
         elif args.workload == "bitphase":
             args.cpu = cpu_baseline(args.cpu_sample, ns, noise=1, p=Q_BITPHASE,
                                     workers=host_cores())
-        else:
+        elif args.workload == "randomscan":
             args.cpu = cpu_baseline(min(args.cpu_sample, 64), ns, random_scan=True,
                                     workers=host_cores())
+        else:
+            args.cpu = cpu_baseline_spacetime(host_cores())
 
     import torch
     import paper_1302_2669_amd as mc
@@ -568,7 +571,8 @@ def bench_spacetime(args, mc, torch, dev):
     SIMDs, the register-resident kernel's full residency).
     Also the logical error of decoding the last round alone with the
     single-round decoder (L^2 sweeps), on the same histories."""
-    Ls, T, p, pm, chains, sweeps, n = 7, 7, 0.02, 0.02, 4, 784, 32768
+    Ls, T, p, pm, chains, sweeps = ST_L, ST_T, ST_P, ST_PM, ST_CHAINS, ST_SWEEPS
+    n = 32768
     steps, warm = args.steps, args.warmup
     nq, ns = mc.geometry(Ls)
     hist, truth = [], []
@@ -641,25 +645,8 @@ def bench_spacetime(args, mc, torch, dev):
                      "frac": achieved / (PEAK_INT_OPS / 1e12), "traffic": None,
                      "chain_ms_per_launch": chain_ms, "ops_per_update": OPS_PER_UPDATE,
                      "updates_per_launch": n * moves_per_history},
-        "cpu_baseline": None,
+        "cpu_baseline": args.cpu,
     }
-    if not args.no_cpu_baseline:
-        here = os.path.dirname(os.path.abspath(__file__))
-        if here not in sys.path:
-            sys.path.insert(0, here)
-        from oracle import geometry, spacetime as stm
-        # one history at a quarter of the sweeps (the oracle's cost is linear in
-        # sweeps), scaled to the full budget
-        ns_cpu, frac = 1, 4
-        obs_cpu, _, _, _ = stm.sample(geometry.Lattice(Ls), p, pm, T, SEED, np.arange(ns_cpu))
-        c0 = time.perf_counter()
-        stm.decode(Ls, obs_cpu, p, pm, sweeps // frac, SEED, chains_per_class=chains)
-        dt = time.perf_counter() - c0
-        line["cpu_baseline"] = {"value": ns_cpu / (dt * frac), "unit": "histories/s",
-                                "cores": 1, "kind": "oracle",
-                                "sample": f"{ns_cpu} history of the same workload at "
-                                          f"{sweeps // frac} of its {sweeps} sweeps, NumPy "
-                                          f"oracle in one process, {dt:.1f} s, time x{frac}"}
     print(json.dumps(line), flush=True)
 
 
@@ -794,6 +781,43 @@ def _oracle_shard(job):
                    scan=decoder.SCAN_RANDOM if random_scan else decoder.SCAN_COLOUR)
     return time.perf_counter() - t0
 
+
+# the space-time workload's constants, shared by the bench and its oracle baseline
+ST_L, ST_T, ST_P, ST_PM, ST_CHAINS, ST_SWEEPS = 7, 7, 0.02, 0.02, 4, 784
+
+
+def _st_shard(job):
+    """One worker: history id `hid` at sweeps // frac of the budget on the
+    oracle; returns the seconds it took."""
+    hid, frac = job
+    here = os.path.dirname(os.path.abspath(__file__))
+    if here not in sys.path:
+        sys.path.insert(0, here)
+    from oracle import geometry, spacetime as stm
+    obs, _, _, _ = stm.sample(geometry.Lattice(ST_L), ST_P, ST_PM, ST_T, SEED, np.array([hid]))
+    t0 = time.perf_counter()
+    stm.decode(ST_L, obs, ST_P, ST_PM, ST_SWEEPS // frac, SEED, chains_per_class=ST_CHAINS,
+               syndrome_ids=np.array([hid]))
+    return time.perf_counter() - t0
+
+
+def cpu_baseline_spacetime(workers):
+    """The space-time oracle on one history per worker process at a quarter of
+    the sweeps (its cost is linear in sweeps), scaled to the full budget."""
+    frac = 4
+    t0 = time.perf_counter()
+    if workers == 1:
+        _st_shard((0, frac))
+    else:
+        import multiprocessing as mp
+        with mp.get_context("fork").Pool(workers) as pool:
+            pool.map(_st_shard, [(w, frac) for w in range(workers)])
+    dt = time.perf_counter() - t0
+    return {"value": workers / (dt * frac), "unit": "histories/s", "cores": workers,
+            "kind": "oracle",
+            "sample": f"{workers} histories of the same workload at {ST_SWEEPS // frac} of its "
+                      f"{ST_SWEEPS} sweeps, NumPy oracle in {workers} processes of one history "
+                      f"each, {dt:.1f} s wall, time x{frac}"}
 
 def host_cores():
     """Cores this process may run on, at most 16 (one GPU's share of the host)."""
