@@ -541,6 +541,7 @@ int mcmc_spacetime_tables(const mcmc_spacetime_params* h_prm, uint32_t* h_spatia
  * <n>, <m> (or NULL), d_sum_n / d_sum_m / d_accepts [n][4][chains] int64 (or
  * NULL), d_chosen [n] (required), d_correction [n][n_q] the accumulated data
  * error of chain 0 of the chosen class (or NULL).  Asynchronous on `stream`.
+ * ERANGE for n > 2^28 or n * 4 * chains > 2^36.
  */
 int mcmc_decode_spacetime(const uint8_t* d_obs, const uint32_t* d_ids, int64_t n,
                           const mcmc_spacetime_params* h_prm, double* d_class_prob,

@@ -15,7 +15,9 @@ using namespace mcmc;
 int check_st(const mcmc_spacetime_params* prm, int64_t n) {
   if (!prm) return MCMC_EINVAL;
   if (prm->reserved != 0) return MCMC_EINVAL;
-  if (n < 0 || !valid_L(prm->L)) return MCMC_ERANGE;
+  // n <= 2^28 keeps every grid of the decode (n n_stab / 256 blocks for the
+  // last-round copy) within 32-bit block counts
+  if (n < 0 || n > ((int64_t)1 << 28) || !valid_L(prm->L)) return MCMC_ERANGE;
   if (prm->rounds < 1 || prm->rounds > MCMC_ROUNDS_MAX) return MCMC_ERANGE;
   if (!valid_p(prm->p) || !(prm->p_m > 0.0 && prm->p_m < 0.5)) return MCMC_ERANGE;
   if (prm->chains < 1 || prm->chains > MCMC_CHAINS_MAX) return MCMC_ERANGE;

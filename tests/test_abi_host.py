@@ -270,3 +270,14 @@ def test_spacetime_limits_and_reserved():
                                      None, None, dummy, None, dummy, 16, None) == -5
     assert lib.mcmc_decode_spacetime(dummy, None, 0, ctypes.byref(good), dummy, None, None, None,
                                      None, None, dummy, None, None, 0, None) == 0
+
+
+def test_spacetime_history_count_limit():
+    """At most 2^28 histories per decode (every grid stays within 32-bit
+    block counts)."""
+    b = ctypes.c_size_t()
+    prm = mc.spacetime_params(5, 3, 0.05, 0.05, 4, 1)
+    lib = _lib._lib()
+    assert lib.mcmc_spacetime_workspace_size(ctypes.byref(prm), 1 << 28, ctypes.byref(b)) == 0
+    assert lib.mcmc_spacetime_workspace_size(ctypes.byref(prm), (1 << 28) + 1,
+                                             ctypes.byref(b)) == -2
