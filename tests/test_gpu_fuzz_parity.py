@@ -119,3 +119,56 @@ def test_random_spacetime_configuration(cfg):
         assert np.array_equal(g[k], o[k]), k
     for k in ("class_prob", "mean_n", "mean_m"):
         np.testing.assert_allclose(g[k], o[k], rtol=RTOL, atol=0)
+
+
+@pytest.mark.parametrize("plan_seed", [1, 2, 3])
+def test_random_mixed_plan(plan_seed):
+    """A plan of 60 randomly drawn items (every kernel range, both noise
+    models, several beta*/beta_bar, temperature counts, chains, burn-in and
+    sweeps, random ids): each item's results equal its uniform decode, and a
+    sampled third of them equal the oracle."""
+    rng = np.random.default_rng(plan_seed)
+    items, syns = [], []
+    for i in range(60):
+        L = int(rng.integers(2, 26))
+        noise = int(rng.integers(0, 2))
+        p = float(rng.uniform(0.03, 0.25))
+        K = int(rng.choice([1, 1, 2]))
+        it = dict(L=L, p=p, noise=noise, n_temps=K, chains=int(rng.integers(1, 4)),
+                  burn=int(rng.integers(0, 3)), sweeps=int(rng.integers(0, 6 if L <= 13 else 3)),
+                  syndrome_id=int(rng.integers(0, 1 << 31)),
+                  beta_scale=float(rng.choice([0.0, 0.8, 1.2])) if K == 1 else 0.0)
+        syn, _, _ = sampler.sample(geometry.Lattice(L), p, 1000 + plan_seed, [it["syndrome_id"]],
+                                   noise=noise)
+        items.append(it)
+        syns.append(syn[0])
+    say(f"random plan {plan_seed}: {len(items)} items")
+    flat = torch.from_numpy(np.concatenate(syns)).to(DEV)
+    seed = 0xC0FFEE + plan_seed
+    plan = mc.MixedPlan(items, seed=seed)
+    out = plan.execute(flat, want_sums=True)
+    torch.cuda.synchronize()
+    got = {k: v.cpu().numpy() for k, v in out.items()}
+    for i, it in enumerate(items):
+        a, b = plan.chain_offsets[i], plan.chain_offsets[i + 1]
+        c0, c1 = plan.corr_offsets[i], plan.corr_offsets[i + 1]
+        u = mc.decode_batch(torch.from_numpy(syns[i][None]).to(DEV), it["L"], it["p"], it["sweeps"],
+                            seed, chains=it["chains"], n_temps=it["n_temps"], burn=it["burn"],
+                            syndrome_ids=torch.tensor([it["syndrome_id"]]), want_sums=True,
+                            noise=it["noise"], beta_scale=it["beta_scale"])
+        torch.cuda.synchronize()
+        assert np.array_equal(got["sum_n"][a:b], u["sum_n"].reshape(-1).cpu().numpy()), i
+        assert np.array_equal(got["accepts"][a:b], u["accepts"].reshape(-1).cpu().numpy()), i
+        assert got["chosen"][i] == int(u["chosen"][0]), i
+        assert np.array_equal(got["correction"][c0:c1], u["correction"][0].cpu().numpy()), i
+        assert np.array_equal(got["class_prob"][i], u["class_prob"][0].cpu().numpy()), i
+        if i % 3 == 0:
+            o = decoder.decode(it["L"], syns[i][None], it["p"], it["sweeps"], seed,
+                               chains_per_class=it["chains"], n_temps=it["n_temps"],
+                               burn=it["burn"], syndrome_ids=[it["syndrome_id"]],
+                               noise=it["noise"],
+                               beta_scale=None if it["beta_scale"] == 0.0 else it["beta_scale"])
+            assert np.array_equal(got["sum_n"][a:b], o["sum_n"].reshape(-1)), i
+            assert got["chosen"][i] == int(o["chosen"][0]), i
+            np.testing.assert_allclose(got["class_prob"][i], o["class_prob"][0], rtol=RTOL, atol=0)
+    plan.close()
