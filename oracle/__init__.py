@@ -21,6 +21,8 @@ chains     colour-phased Metropolis chains (Sec. IV, Sec. IV.A, Sec. V)
 estimator  thermodynamic integration (Eq. main) and the class decision
 enumerate  exact class partition functions by enumerating stabilizer products
 decoder    the whole decode, composed from the above
+spacetime  imperfect measurements (Sec. VI): sampler, starts, chains, decode
+cnn        the gate network in float64 (forward, backward, Adam, bf16 rounding)
 
 Every floating-point quantity is float64.  Integer work uses numpy integer
 arrays; nothing here is blocked, fused or reordered beyond the paper's steps.
