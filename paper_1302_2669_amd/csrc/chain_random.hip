@@ -8,8 +8,12 @@
 // Mapping.  One lane per chain as in the colour-phased kernels, but a random
 // site needs its rows by a runtime index, so each lane's packed configuration
 // lives in LDS, word-major with the wave's 64 lanes side by side
-// (word k of lane l at [k][l]: any rows, no bank conflicts).  A step reads and
-// rewrites the words of the site's 3-4 qubits.  Workgroups are one wave; no
+// (word k of lane l at [k][l]: any rows, no bank conflicts), plus one spare
+// word per lane.  The site table holds each qubit's word index and bit
+// offset, so a step issues its four word reads at once (a missing neighbour
+// reads the spare word), looks the weight change of each code up in a
+// 2-bit-field constant, and applies an accepted move with four LDS XORs
+// (two qubits of a site may share a word).  Workgroups are one wave; no
 // barrier after the set-up.
 //
 // Randomness: step t of a sweep uses block t >> 1 of Philox4x32-10 at counter
@@ -27,33 +31,36 @@ namespace {
 constexpr int RS_LANES = 64;
 constexpr uint32_t RS_NONE = 0xFFFFu;
 
-// Per site: its 3-4 qubits as (grid row << 8 | field) 16-bit codes, two per
-// word, RS_NONE for a missing neighbour of a boundary stabilizer.
+// Per site: its 3-4 qubits as 16-bit codes, two per word: the qubit's word
+// of the packed configuration (grid row * words per row + field / 16) << 5 |
+// its bit offset 2 (field % 16); RS_NONE for a missing neighbour of a
+// boundary stabilizer (word indices stay below 2^11, so no code equals it).
 struct SiteQubits {
   uint32_t q01, q23;
 };
 
-__device__ __forceinline__ uint32_t qcode(int row, int field) {
-  return ((uint32_t)row << 8) | (uint32_t)field;
+__device__ __forceinline__ uint32_t qcode(int W, int row, int field) {
+  return ((uint32_t)(row * W + (field >> 4)) << 5) | (uint32_t)(2 * (field & 15));
 }
 
 __device__ SiteQubits site_qubits(int L, int s) {
   const int nstar = L * (L - 1);
+  const int W = words_per_row(L);
   uint32_t q[4] = {RS_NONE, RS_NONE, RS_NONE, RS_NONE};
   int k = 0;
   if (s < nstar) {  // star (i, j) at grid (2i+1, 2j)
     const int i = s / L, j = s % L;
-    q[k++] = qcode(2 * i, j);
-    q[k++] = qcode(2 * i + 2, j);
-    if (j > 0) q[k++] = qcode(2 * i + 1, j - 1);
-    if (j < L - 1) q[k++] = qcode(2 * i + 1, j);
+    q[k++] = qcode(W, 2 * i, j);
+    q[k++] = qcode(W, 2 * i + 2, j);
+    if (j > 0) q[k++] = qcode(W, 2 * i + 1, j - 1);
+    if (j < L - 1) q[k++] = qcode(W, 2 * i + 1, j);
   } else {          // plaquette (i, j) at grid (2i, 2j+1)
     const int t = s - nstar;
     const int i = t / (L - 1), j = t % (L - 1);
-    if (i > 0) q[k++] = qcode(2 * i - 1, j);
-    if (i < L - 1) q[k++] = qcode(2 * i + 1, j);
-    q[k++] = qcode(2 * i, j);
-    q[k++] = qcode(2 * i, j + 1);
+    if (i > 0) q[k++] = qcode(W, 2 * i - 1, j);
+    if (i < L - 1) q[k++] = qcode(W, 2 * i + 1, j);
+    q[k++] = qcode(W, 2 * i, j);
+    q[k++] = qcode(W, 2 * i, j + 1);
   }
   SiteQubits r;
   r.q01 = q[0] | (q[1] << 16);
@@ -108,42 +115,80 @@ __global__ void __launch_bounds__(RS_LANES) chains_random_kernel(const RunArgs a
 
   const uint32_t ctr3 = (2u << 30) | ((uint32_t)cls << 28) | ((uint32_t)(kt + 1) << 20) |
                         (uint32_t)chain;
+  // missing neighbours of boundary stabilizers read and "flip" a spare word
+  // of the lane (with a zero mask), so that every step issues its four reads
+  // and four XORs without branches
+  const int sink = RW * RS_LANES + lane;
   for (int sweep = g.sweep_begin; sweep < g.sweep_end; ++sweep) {
     const bool counted = sweep >= g.burn;
-    uint4 blk = make_uint4(0, 0, 0, 0);
+    // The draws and the site entry of step t + 1 are taken while step t is
+    // processed (the site table is read-only), so that their latency
+    // overlaps the current step.
+    uint4 blk = philox4x32_10(make_uint4(0u, (uint32_t)sweep, sid, ctr3), a.k0, a.k1);
+    int s = (int)__umulhi(blk.x, (uint32_t)nstab);
+    uint32_t u_acc = blk.y;
+    SiteQubits sq = sites[s];
     for (int step = 0; step < nstab; ++step) {
-      if ((step & 1) == 0)
-        blk = philox4x32_10(make_uint4((uint32_t)(step >> 1), (uint32_t)sweep, sid, ctr3), a.k0,
-                            a.k1);
-      const uint32_t u_site = (step & 1) ? blk.z : blk.x;
-      const uint32_t u_acc = (step & 1) ? blk.w : blk.y;
-      const int s = (int)__umulhi(u_site, (uint32_t)nstab);
-      const bool star = s < nstar;
-      const SiteQubits sq = sites[s];
-      const uint32_t qc[4] = {sq.q01 & 0xFFFFu, sq.q01 >> 16, sq.q23 & 0xFFFFu, sq.q23 >> 16};
-      int delta = 0;
-      for (int k = 0; k < 4; ++k) {
-        if (qc[k] == RS_NONE) continue;
-        const int row = (int)(qc[k] >> 8), field = (int)(qc[k] & 0xFFu);
-        const uint32_t word = st[(row * W + (field >> 4)) * RS_LANES + lane];
-        const uint32_t code = (word >> (2 * (field & 15))) & 3u;
-        const int x = (int)(code & 1u), z = (int)(code >> 1);
-        const int own = star ? x : z, other = star ? z : x;
-        delta += NOISE == 1 ? 1 - 2 * own : (1 - other) * (1 - 2 * own);
+      int s_next = 0;
+      uint32_t acc_next = 0;
+      SiteQubits sq_next = sq;
+      if (step + 1 < nstab) {
+        uint32_t u_site_next;
+        if (((step + 1) & 1) == 0) {
+          blk = philox4x32_10(make_uint4((uint32_t)((step + 1) >> 1), (uint32_t)sweep, sid, ctr3),
+                              a.k0, a.k1);
+          u_site_next = blk.x;
+          acc_next = blk.y;
+        } else {
+          u_site_next = blk.z;
+          acc_next = blk.w;
+        }
+        s_next = (int)__umulhi(u_site_next, (uint32_t)nstab);
+        sq_next = sites[s_next];
       }
-      const uint32_t thr = delta == 1 ? thr1 : (delta == 2 ? thr2 : (delta == 3 ? thr3 : thr4));
-      const bool accept = delta <= 0 || u_acc < thr;
+      const bool star = s < nstar;
+      const uint32_t qc[4] = {sq.q01 & 0xFFFFu, sq.q01 >> 16, sq.q23 & 0xFFFFu, sq.q23 >> 16};
+      int addr[4];
+      uint32_t sh[4];
+      bool valid[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        valid[k] = qc[k] != RS_NONE;
+        addr[k] = valid[k] ? (int)(qc[k] >> 5) * RS_LANES + lane : sink;
+        sh[k] = qc[k] & 31u;
+      }
+      uint32_t word[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) word[k] = st[addr[k]];
+      // change of the qubit's weight when the site's Pauli is applied, plus
+      // one, in 2-bit fields by its code (x + 2z): depolarizing, the weight
+      // (1 - other)(1 - 2 own) of own = the part the site flips (x for a star,
+      // z for a plaquette); bit/phase flips, 1 - 2 own
+      const uint32_t lut = NOISE == 1 ? (star ? 0x22u : 0x0Au) : (star ? 0x52u : 0x46u);
+      int delta = 0;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const uint32_t code = (word[k] >> sh[k]) & 3u;
+        const int term = (int)((lut >> (2u * code)) & 3u) - 1;
+        delta += valid[k] ? term : 0;
+      }
+      // threshold of delta = 1..4 (delta <= 0 is accepted whatever it is)
+      const uint32_t t12 = delta == 1 ? thr1 : thr2;
+      const uint32_t t34 = delta == 3 ? thr3 : thr4;
+      const uint32_t thr = delta <= 2 ? t12 : t34;
+      const bool accept = (delta <= 0) | (u_acc < thr);
       if (accept) {
         const uint32_t bit = star ? 1u : 2u;
-        for (int k = 0; k < 4; ++k) {
-          if (qc[k] == RS_NONE) continue;
-          const int row = (int)(qc[k] >> 8), field = (int)(qc[k] & 0xFFu);
-          st[(row * W + (field >> 4)) * RS_LANES + lane] ^= bit << (2 * (field & 15));
-        }
+        // read-modify-writes in LDS order: two qubits of a site may share a word
+#pragma unroll
+        for (int k = 0; k < 4; ++k) atomicXor(&st[addr[k]], valid[k] ? bit << sh[k] : 0u);
         n += delta;
         ++Acnt;
       }
       if (counted) Ssum += n;
+      s = s_next;
+      sq = sq_next;
+      u_acc = acc_next;
     }
   }
 
@@ -162,7 +207,7 @@ __global__ void __launch_bounds__(RS_LANES) chains_random_kernel(const RunArgs a
 size_t random_scan_lds_bytes(int L) {
   const int nstab = 2 * L * (L - 1);
   return (size_t)2 * nstab * sizeof(uint32_t) +
-         (size_t)words_per_config(L) * RS_LANES * sizeof(uint32_t);
+         (size_t)(words_per_config(L) + 1) * RS_LANES * sizeof(uint32_t);
 }
 
 hipError_t launch_chains_random(const RunArgs& a, hipStream_t s) {
