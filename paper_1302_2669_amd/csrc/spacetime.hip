@@ -141,6 +141,7 @@ __global__ void __launch_bounds__(ST_LANES) st_chain_kernel(const SpaceTimeArgs 
   uint32_t* qubit_s = site_q + 2 * nstab;          // [nq][2]: plaquettes, stars of q
   uint32_t* Ew = qubit_s + 2 * nq;                 // [T*WQ][64]
   uint32_t* Mw = Ew + (int64_t)T * WQ * ST_LANES;  // [(T-1)*WM][64]
+  uint32_t* tthr = Mw + (int64_t)(T - 1) * WM * ST_LANES;  // [25] time-move thresholds
 
   const int side = 2 * L - 1;
   for (int s = lane; s < nstab; s += ST_LANES) {
@@ -175,7 +176,10 @@ __global__ void __launch_bounds__(ST_LANES) st_chain_kernel(const SpaceTimeArgs 
     qubit_s[2 * qi] = pack2(pl[0], pl[1]);
     qubit_s[2 * qi + 1] = pack2(sr[0], sr[1]);
   }
+  if (lane < 25) tthr[lane] = a.t_thr[lane];
   __syncthreads();
+  const uint32_t sp1 = a.sp_thr[0], sp2 = a.sp_thr[1], sp3 = a.sp_thr[2], sp4 = a.sp_thr[3];
+  const uint32_t t_always = a.t_always;
 
   const int64_t task = (int64_t)blockIdx.x * ST_LANES + lane;
   if (task >= a.n_tasks) return;
@@ -228,7 +232,10 @@ __global__ void __launch_bounds__(ST_LANES) st_chain_kernel(const SpaceTimeArgs 
       ++d;
       return u;
     };
-    // spatial moves
+    // spatial moves: the site's four words are read at once (a missing
+    // neighbour reads word 0 of the interval and flips nothing), the weight
+    // change of each code comes from a 2-bit-field constant, and accepted
+    // flips are LDS XORs (two qubits of a site may share a word)
     for (int t = 0; t < T; ++t) {
       uint32_t* E = Ew + t * WQ * ST_LANES + lane;
       for (int s = 0; s < nstab; ++s) {
@@ -236,57 +243,70 @@ __global__ void __launch_bounds__(ST_LANES) st_chain_kernel(const SpaceTimeArgs 
         const bool star = s < nstar;
         const uint32_t qq[4] = {site_q[2 * s] & 0xFFFFu, site_q[2 * s] >> 16,
                                 site_q[2 * s + 1] & 0xFFFFu, site_q[2 * s + 1] >> 16};
-        int delta = 0;
+        int widx[4];
+        uint32_t sh[4];
+        bool valid[4];
+#pragma unroll
         for (int k = 0; k < 4; ++k) {
-          if (qq[k] == ST_NONE) continue;
-          const uint32_t code = (E[(qq[k] >> 4) * ST_LANES] >> (2 * (qq[k] & 15u))) & 3u;
-          const int x = (int)(code & 1u), z = (int)(code >> 1);
-          delta += star ? (1 - z) * (1 - 2 * x) : (1 - x) * (1 - 2 * z);
+          valid[k] = qq[k] != ST_NONE;
+          widx[k] = valid[k] ? (int)(qq[k] >> 4) * ST_LANES : 0;
+          sh[k] = 2u * (qq[k] & 15u);
         }
-        const uint32_t thr = delta == 1 ? a.sp_thr[0]
-                           : (delta == 2 ? a.sp_thr[1] : (delta == 3 ? a.sp_thr[2] : a.sp_thr[3]));
-        if (delta <= 0 || u < thr) {
+        uint32_t w[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) w[k] = E[widx[k]];
+        // (1 - other)(1 - 2 own) + 1 by code x + 2z, own = x for a star
+        const uint32_t lut = star ? 0x52u : 0x46u;
+        int delta = 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const uint32_t code = (w[k] >> sh[k]) & 3u;
+          delta += valid[k] ? (int)((lut >> (2u * code)) & 3u) - 1 : 0;
+        }
+        const uint32_t t12 = delta == 1 ? sp1 : sp2;
+        const uint32_t t34 = delta == 3 ? sp3 : sp4;
+        const uint32_t thr = delta <= 2 ? t12 : t34;
+        if ((delta <= 0) | (u < thr)) {
           const uint32_t bit = star ? 1u : 2u;
-          for (int k = 0; k < 4; ++k) {
-            if (qq[k] == ST_NONE) continue;
-            E[(qq[k] >> 4) * ST_LANES] ^= bit << (2 * (qq[k] & 15u));
-          }
+#pragma unroll
+          for (int k = 0; k < 4; ++k) atomicXor(&E[widx[k]], valid[k] ? bit << sh[k] : 0u);
           n += delta;
           ++Acnt;
         }
       }
     }
     if (counted) { Sn += n; Sm += m; }
-    // time moves (two unused draws close every round)
+    // time moves (two unused draws close every round), branch-free as above:
+    // a missing stabilizer reads word 0 of the round and flips nothing
     for (int t = 0; t + 1 < T; ++t, d += 2) {
       uint32_t* E0 = Ew + t * WQ * ST_LANES + lane;
       uint32_t* E1 = E0 + WQ * ST_LANES;
       uint32_t* Mt = Mw + t * WM * ST_LANES + lane;
       for (int q = 0; q < nq; ++q) {
         const int wq = (q >> 4) * ST_LANES;
-        const int sh = 2 * (q & 15);
+        const uint32_t sh = 2u * (uint32_t)(q & 15);
         for (int kind = 0; kind < 2; ++kind) {
           const uint32_t u = draw();
-          const uint32_t c0 = (E0[wq] >> sh) & 3u, c1 = (E1[wq] >> sh) & 3u;
-          int dn;
-          if (kind == 0)
-            dn = (1 - (int)(c0 >> 1)) * (1 - 2 * (int)(c0 & 1u)) +
-                 (1 - (int)(c1 >> 1)) * (1 - 2 * (int)(c1 & 1u));
-          else
-            dn = (1 - (int)(c0 & 1u)) * (1 - 2 * (int)(c0 >> 1)) +
-                 (1 - (int)(c1 & 1u)) * (1 - 2 * (int)(c1 >> 1));
           const uint32_t ss = qubit_s[2 * q + kind];
           const uint32_t sa = ss & 0xFFFFu, sb = ss >> 16;
-          int dm = 0;
-          if (sa != ST_NONE) dm += 1 - 2 * (int)((Mt[(sa >> 5) * ST_LANES] >> (sa & 31u)) & 1u);
-          if (sb != ST_NONE) dm += 1 - 2 * (int)((Mt[(sb >> 5) * ST_LANES] >> (sb & 31u)) & 1u);
+          const bool va = sa != ST_NONE, vb = sb != ST_NONE;
+          const int ia = va ? (int)(sa >> 5) * ST_LANES : 0;
+          const int ib = vb ? (int)(sb >> 5) * ST_LANES : 0;
+          const uint32_t c0 = (E0[wq] >> sh) & 3u, c1 = (E1[wq] >> sh) & 3u;
+          const uint32_t ma = Mt[ia], mb = Mt[ib];
+          // X on the qubit changes the weight by (1 - z)(1 - 2x), Z by
+          // (1 - x)(1 - 2z): plus one, by code x + 2z
+          const uint32_t lut = kind == 0 ? 0x52u : 0x46u;
+          const int dn = (int)((lut >> (2u * c0)) & 3u) + (int)((lut >> (2u * c1)) & 3u) - 2;
+          const int dm = (va ? 1 - 2 * (int)((ma >> (sa & 31u)) & 1u) : 0) +
+                         (vb ? 1 - 2 * (int)((mb >> (sb & 31u)) & 1u) : 0);
           const int e = (dn + 2) * 5 + (dm + 2);
-          if (((a.t_always >> e) & 1u) || u < a.t_thr[e]) {
+          if (((t_always >> e) & 1u) | (u < tthr[e])) {
             const uint32_t bit = (kind == 0 ? 1u : 2u) << sh;
-            E0[wq] ^= bit;
-            E1[wq] ^= bit;
-            if (sa != ST_NONE) Mt[(sa >> 5) * ST_LANES] ^= 1u << (sa & 31u);
-            if (sb != ST_NONE) Mt[(sb >> 5) * ST_LANES] ^= 1u << (sb & 31u);
+            atomicXor(&E0[wq], bit);
+            atomicXor(&E1[wq], bit);
+            atomicXor(&Mt[ia], va ? 1u << (sa & 31u) : 0u);
+            atomicXor(&Mt[ib], vb ? 1u << (sb & 31u) : 0u);
             n += dn;
             m += dm;
             ++Acnt;
@@ -605,7 +625,8 @@ size_t spacetime_lds_bytes(int L, int T) {
   const int nq = 2 * L * L - 2 * L + 1, nstab = 2 * L * (L - 1);
   const size_t words = (size_t)2 * nstab + (size_t)2 * nq +
                        ((size_t)T * ((nq + 15) / 16) + (size_t)(T - 1) * ((nstab + 31) / 32)) *
-                           ST_LANES;
+                           ST_LANES +
+                       25;
   return words * sizeof(uint32_t);
 }
 
