@@ -460,6 +460,9 @@ st_chain_fast_kernel(const SpaceTimeArgs a) {
       for (int w = 0; w < WQ; ++w) e[w] = Ew[(t * WQ + w) * stride];
       const uint32_t blk0 = (uint32_t)(t * (NSTAB / 4));
       uint4 blk = make_uint4(0, 0, 0, 0);
+      // accepted moves of this interval, in a fenced 32-bit counter: left as
+      // a 64-bit sum the compiler defers and spills every move's flag
+      uint32_t na = 0;
       static_for<NSTAB>([&](auto SS) {
         constexpr int s = decltype(SS)::value;
         constexpr bool star = s < NSTAR;
@@ -489,10 +492,11 @@ st_chain_fast_kernel(const SpaceTimeArgs a) {
           if constexpr (q >= 0) e[q >> 4] ^= flip << (2 * (q & 15));
         });
         n += acc ? delta : 0;
-        Acnt += acc ? 1 : 0;
+        na += acc ? 1u : 0u;
         st_fence(e);
-        asm volatile("" : "+v"(n));
+        asm volatile("" : "+v"(n), "+v"(na));
       });
+      Acnt += na;
 #pragma unroll
       for (int w = 0; w < WQ; ++w) Ew[(t * WQ + w) * stride] = e[w];
     }
@@ -509,6 +513,7 @@ st_chain_fast_kernel(const SpaceTimeArgs a) {
       for (int w = 0; w < WM; ++w) mm[w] = Mw[(t * WM + w) * stride];
       const uint32_t blk0 = (uint32_t)((T * NSTAB + 2 * t * (NQ + 1)) / 4);
       uint4 blk = make_uint4(0, 0, 0, 0);
+      uint32_t na = 0;   // accepted moves of this round, as above
       static_for<2 * NQ>([&](auto RR) {
         constexpr int r = decltype(RR)::value;
         constexpr int q = r >> 1, kind = r & 1;
@@ -540,12 +545,13 @@ st_chain_fast_kernel(const SpaceTimeArgs a) {
         if constexpr (sb >= 0) mm[sb >> 5] ^= (acc ? 1u : 0u) << (sb & 31);
         n += acc ? dn : 0;
         m += acc ? dm : 0;
-        Acnt += acc ? 1 : 0;
+        na += acc ? 1u : 0u;
         st_fence(e0);
         st_fence(e1);
         st_fence(mm);
-        asm volatile("" : "+v"(n), "+v"(m));
+        asm volatile("" : "+v"(n), "+v"(m), "+v"(na));
       });
+      Acnt += na;
 #pragma unroll
       for (int w = 0; w < WQ; ++w) {
         Ew[(t * WQ + w) * stride] = e0[w];
