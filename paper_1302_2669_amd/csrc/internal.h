@@ -170,7 +170,7 @@ hipError_t launch_sample_items(const ItemDesc* items, const GroupDesc* groups, i
 constexpr size_t SPACETIME_LDS_MAX = 160 * 1024;
 // Codes up to this L run the register-resident kernel, whose hypotheses live
 // in a global buffer (SpaceTimeArgs::state) instead of LDS.
-constexpr int SPACETIME_FAST_L_MAX = 9;
+constexpr int SPACETIME_FAST_L_MAX = 13;
 size_t spacetime_lds_bytes(int L, int T);
 struct SpaceTimeArgs {
   int32_t L, T, chains, burn, sweep_end;

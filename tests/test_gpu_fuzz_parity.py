@@ -85,7 +85,7 @@ def draw_st_configs(count, seed):
     rng = np.random.default_rng(seed)
     out = []
     for _ in range(count):
-        L = int(rng.integers(2, 10))
+        L = int(rng.integers(2, 16))
         T = int(rng.integers(1, 6))
         p = float(rng.uniform(0.01, 0.15))
         pm = float(rng.uniform(0.01, 0.2))

@@ -49,8 +49,13 @@ CASES = [
     (4, 2, 0.12, 0.2, 8, 0, 1, 4),
     (5, 4, 0.05, 0.08, 4, 1, 2, 3),
     (9, 3, 0.06, 0.04, 2, 0, 1, 2),
+    (10, 2, 0.05, 0.05, 2, 1, 1, 2),
+    (11, 3, 0.04, 0.06, 1, 0, 2, 2),
+    (12, 2, 0.05, 0.05, 1, 0, 1, 1),
     (13, 2, 0.04, 0.04, 1, 1, 1, 2),
+    (14, 2, 0.05, 0.05, 1, 0, 1, 1),
     (17, 2, 0.05, 0.05, 1, 0, 1, 1),
+    (25, 2, 0.03, 0.03, 1, 0, 1, 1),
 ]
 
 
