@@ -505,11 +505,9 @@ int mcmc_gated_decode(mcmc_gated* gated, const float* d_params, const uint8_t* d
  * Class starts: every flipped outcome before the last round blamed on the
  * measurement (M_t = s_t, t < T-1), no data error before the last interval,
  * and E_{T-1} the class-c MCMC_INIT_MATCHING start of s_{T-1}.
- * Up to L = 13 the chains keep their current intervals in registers and the
- * rest of each hypothesis in the workspace; above, the whole hypothesis
- * lives in LDS.  For every L: ERANGE when T ceil(n_q/16) + (T-1)
- * ceil(n_stab/32) words per chain (times 64 chains) plus the lattice and
- * threshold tables exceed 160 KiB (e.g. L = 13 allows T <= 21).
+ * The hypotheses, T ceil(n_q/16) + (T-1) ceil(n_stab/32) words per chain,
+ * live in the workspace; up to L = 13 the chains keep their current
+ * intervals in registers.
  */
 #define MCMC_ROUNDS_MAX 64
 

@@ -166,10 +166,11 @@ hipError_t launch_sample_items(const ItemDesc* items, const GroupDesc* groups, i
                                hipStream_t s);
 
 // ---- imperfect measurements (space-time hypotheses) ---------------------------
-// LDS of one 64-chain workgroup of the space-time kernel must stay within this.
+// LDS of one 64-chain workgroup of the space-time kernel (lattice tables)
+// must stay within this.
 constexpr size_t SPACETIME_LDS_MAX = 160 * 1024;
-// Codes up to this L run the register-resident kernel, whose hypotheses live
-// in a global buffer (SpaceTimeArgs::state) instead of LDS.
+// Codes up to this L run the register-resident kernel; larger ones the
+// kernel that reads and writes the hypothesis buffer per move.
 constexpr int SPACETIME_FAST_L_MAX = 13;
 size_t spacetime_lds_bytes(int L, int T);
 struct SpaceTimeArgs {
@@ -191,7 +192,7 @@ struct SpaceTimeArgs {
   double *class_prob, *mean_n, *mean_m;
   uint8_t* chosen;
   uint8_t* correction;          // [n][n_q] or nullptr
-  uint32_t* state;              // L <= SPACETIME_FAST_L_MAX: [words per chain][n_tasks]
+  uint32_t* state;              // hypotheses: [words per chain][n_tasks]
 };
 hipError_t launch_spacetime_sample(int L, int T, uint32_t thr_d, uint32_t thr_m, uint32_t k0,
                                    uint32_t k1, uint32_t id_base, int64_t n, uint8_t* obs,

@@ -20,18 +20,18 @@
 //
 // Mapping.  One lane per chain.  A hypothesis is T (2 n_q)-bit data planes
 // (16 qubits per word, qubit order) and T-1 n_stab-bit outcome planes: far
-// more state than registers hold, so it lives in LDS, word-major with the
-// wave's 64 lanes side by side (no bank conflicts), next to per-site qubit
-// lists and per-qubit stabilizer lists shared by the workgroup.  Moves run
-// in the exact sequential order above, so the chains are bit-identical to a
-// sequential implementation.  One 64-lane workgroup per 64 chains.
+// more state than registers hold, so it lives in a global buffer, word-major
+// over all chains (a wave's access to one word is one 256-byte line).  Moves
+// run in the exact sequential order above, so the chains are bit-identical to
+// a sequential implementation.
 //
-// For L <= ST_FAST_L_MAX a second kernel, templated on L, runs the same moves
-// with the words of the current interval (spatial half) or of intervals t,
-// t+1 and round t's outcomes (time half) in registers: every qubit, site and
-// stabilizer index is then a compile-time constant.  Its hypotheses live in a
-// global buffer, word-major over all chains, read and written once per
-// interval: without LDS the occupancy is set by registers alone.
+// For L <= ST_FAST_L_MAX a kernel templated on L keeps the words of the
+// current interval (spatial half) or of intervals t, t+1 and round t's
+// outcomes (time half) in registers, where every qubit, site and stabilizer
+// index is a compile-time constant; the buffer is then read and written once
+// per interval.  Above, st_chain_kernel reads and writes the buffer per move,
+// with per-site qubit lists and per-qubit stabilizer lists in LDS.  Neither
+// holds hypotheses in LDS, so occupancy is set by registers alone.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -139,9 +139,7 @@ __global__ void __launch_bounds__(ST_LANES) st_chain_kernel(const SpaceTimeArgs 
   const int lane = threadIdx.x;
   uint32_t* site_q = st_lds;                       // [nstab][2]: 4 qubits (16 bit each)
   uint32_t* qubit_s = site_q + 2 * nstab;          // [nq][2]: plaquettes, stars of q
-  uint32_t* Ew = qubit_s + 2 * nq;                 // [T*WQ][64]
-  uint32_t* Mw = Ew + (int64_t)T * WQ * ST_LANES;  // [(T-1)*WM][64]
-  uint32_t* tthr = Mw + (int64_t)(T - 1) * WM * ST_LANES;  // [25] time-move thresholds
+  uint32_t* tthr = qubit_s + 2 * nq;               // [25] time-move thresholds
 
   const int side = 2 * L - 1;
   for (int s = lane; s < nstab; s += ST_LANES) {
@@ -183,6 +181,11 @@ __global__ void __launch_bounds__(ST_LANES) st_chain_kernel(const SpaceTimeArgs 
 
   const int64_t task = (int64_t)blockIdx.x * ST_LANES + lane;
   if (task >= a.n_tasks) return;
+  // the hypothesis in global memory, word-major over all chains (a wave's
+  // accesses to one word are one coalesced 256-byte line)
+  const int64_t stride = a.n_tasks;
+  uint32_t* Ew = a.state + task;                        // [T*WQ][stride]
+  uint32_t* Mw = Ew + (int64_t)T * WQ * stride;         // [(T-1)*WM][stride]
   const int C = a.chains;
   const int64_t item = task / (4 * C);
   const int rem = (int)(task - item * 4 * C);
@@ -193,7 +196,7 @@ __global__ void __launch_bounds__(ST_LANES) st_chain_kernel(const SpaceTimeArgs 
   // measurement (M_t = s_t), no data error before the last interval, and the
   // class-cls matching start of the last round's syndrome in interval T-1
   int32_t n = 0, m = 0;
-  for (int k = 0; k < (T - 1) * WQ; ++k) Ew[k * ST_LANES + lane] = 0u;
+  for (int k = 0; k < (T - 1) * WQ; ++k) Ew[k * stride] = 0u;
   {
     const uint8_t* b = a.reps + (item * 4 + cls) * nq;
     for (int w = 0; w < WQ; ++w) {
@@ -202,7 +205,7 @@ __global__ void __launch_bounds__(ST_LANES) st_chain_kernel(const SpaceTimeArgs 
         const int q = 16 * w + f;
         if (q < nq) word |= (uint32_t)(b[q] & 3u) << (2 * f);
       }
-      Ew[((T - 1) * WQ + w) * ST_LANES + lane] = word;
+      Ew[(int64_t)((T - 1) * WQ + w) * stride] = word;
     }
     n = a.rep_weight[item * 4 + cls];
   }
@@ -214,7 +217,7 @@ __global__ void __launch_bounds__(ST_LANES) st_chain_kernel(const SpaceTimeArgs 
         const int k = 32 * w + b;
         if (k < nstab && o[k] != 0) word |= 1u << b;
       }
-      Mw[(t * WM + w) * ST_LANES + lane] = word;
+      Mw[(int64_t)(t * WM + w) * stride] = word;
       m += __builtin_popcount(word);
     }
   }
@@ -234,22 +237,23 @@ __global__ void __launch_bounds__(ST_LANES) st_chain_kernel(const SpaceTimeArgs 
     };
     // spatial moves: the site's four words are read at once (a missing
     // neighbour reads word 0 of the interval and flips nothing), the weight
-    // change of each code comes from a 2-bit-field constant, and accepted
-    // flips are LDS XORs (two qubits of a site may share a word)
+    // change of each code comes from a 2-bit-field constant, and an accepted
+    // move writes each word back once with the flips of every qubit of the
+    // site in that word (two qubits of a site may share a word)
     for (int t = 0; t < T; ++t) {
-      uint32_t* E = Ew + t * WQ * ST_LANES + lane;
+      uint32_t* E = Ew + (int64_t)t * WQ * stride;
       for (int s = 0; s < nstab; ++s) {
         const uint32_t u = draw();
         const bool star = s < nstar;
         const uint32_t qq[4] = {site_q[2 * s] & 0xFFFFu, site_q[2 * s] >> 16,
                                 site_q[2 * s + 1] & 0xFFFFu, site_q[2 * s + 1] >> 16};
-        int widx[4];
+        int64_t widx[4];
         uint32_t sh[4];
         bool valid[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
           valid[k] = qq[k] != ST_NONE;
-          widx[k] = valid[k] ? (int)(qq[k] >> 4) * ST_LANES : 0;
+          widx[k] = valid[k] ? (int64_t)(qq[k] >> 4) * stride : 0;
           sh[k] = 2u * (qq[k] & 15u);
         }
         uint32_t w[4];
@@ -268,8 +272,16 @@ __global__ void __launch_bounds__(ST_LANES) st_chain_kernel(const SpaceTimeArgs 
         const uint32_t thr = delta <= 2 ? t12 : t34;
         if ((delta <= 0) | (u < thr)) {
           const uint32_t bit = star ? 1u : 2u;
+          uint32_t mask[4];
 #pragma unroll
-          for (int k = 0; k < 4; ++k) atomicXor(&E[widx[k]], valid[k] ? bit << sh[k] : 0u);
+          for (int k = 0; k < 4; ++k) mask[k] = valid[k] ? bit << sh[k] : 0u;
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            uint32_t v = w[k];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) v ^= widx[j] == widx[k] ? mask[j] : 0u;
+            E[widx[k]] = v;   // words read twice get the same value twice
+          }
           n += delta;
           ++Acnt;
         }
@@ -279,20 +291,21 @@ __global__ void __launch_bounds__(ST_LANES) st_chain_kernel(const SpaceTimeArgs 
     // time moves (two unused draws close every round), branch-free as above:
     // a missing stabilizer reads word 0 of the round and flips nothing
     for (int t = 0; t + 1 < T; ++t, d += 2) {
-      uint32_t* E0 = Ew + t * WQ * ST_LANES + lane;
-      uint32_t* E1 = E0 + WQ * ST_LANES;
-      uint32_t* Mt = Mw + t * WM * ST_LANES + lane;
+      uint32_t* E0 = Ew + (int64_t)t * WQ * stride;
+      uint32_t* E1 = E0 + (int64_t)WQ * stride;
+      uint32_t* Mt = Mw + (int64_t)t * WM * stride;
       for (int q = 0; q < nq; ++q) {
-        const int wq = (q >> 4) * ST_LANES;
+        const int64_t wq = (int64_t)(q >> 4) * stride;
         const uint32_t sh = 2u * (uint32_t)(q & 15);
         for (int kind = 0; kind < 2; ++kind) {
           const uint32_t u = draw();
           const uint32_t ss = qubit_s[2 * q + kind];
           const uint32_t sa = ss & 0xFFFFu, sb = ss >> 16;
           const bool va = sa != ST_NONE, vb = sb != ST_NONE;
-          const int ia = va ? (int)(sa >> 5) * ST_LANES : 0;
-          const int ib = vb ? (int)(sb >> 5) * ST_LANES : 0;
-          const uint32_t c0 = (E0[wq] >> sh) & 3u, c1 = (E1[wq] >> sh) & 3u;
+          const int64_t ia = va ? (int64_t)(sa >> 5) * stride : 0;
+          const int64_t ib = vb ? (int64_t)(sb >> 5) * stride : 0;
+          const uint32_t w0 = E0[wq], w1 = E1[wq];
+          const uint32_t c0 = (w0 >> sh) & 3u, c1 = (w1 >> sh) & 3u;
           const uint32_t ma = Mt[ia], mb = Mt[ib];
           // X on the qubit changes the weight by (1 - z)(1 - 2x), Z by
           // (1 - x)(1 - 2z): plus one, by code x + 2z
@@ -303,10 +316,13 @@ __global__ void __launch_bounds__(ST_LANES) st_chain_kernel(const SpaceTimeArgs 
           const int e = (dn + 2) * 5 + (dm + 2);
           if (((t_always >> e) & 1u) | (u < tthr[e])) {
             const uint32_t bit = (kind == 0 ? 1u : 2u) << sh;
-            atomicXor(&E0[wq], bit);
-            atomicXor(&E1[wq], bit);
-            atomicXor(&Mt[ia], va ? 1u << (sa & 31u) : 0u);
-            atomicXor(&Mt[ib], vb ? 1u << (sb & 31u) : 0u);
+            const uint32_t fa = va ? 1u << (sa & 31u) : 0u;
+            const uint32_t fb = vb ? 1u << (sb & 31u) : 0u;
+            E0[wq] = w0 ^ bit;
+            E1[wq] = w1 ^ bit;
+            // the two stabilizers' outcomes may share a word
+            Mt[ia] = ma ^ fa ^ (ia == ib ? fb : 0u);
+            Mt[ib] = mb ^ fb ^ (ia == ib ? fa : 0u);
             n += dn;
             m += dm;
             ++Acnt;
@@ -327,7 +343,7 @@ __global__ void __launch_bounds__(ST_LANES) st_chain_kernel(const SpaceTimeArgs 
     uint8_t* o = a.final_c + (item * 4 + cls) * nq;
     for (int w = 0; w < WQ; ++w) {
       uint32_t word = 0;
-      for (int t = 0; t < T; ++t) word ^= Ew[(t * WQ + w) * ST_LANES + lane];
+      for (int t = 0; t < T; ++t) word ^= Ew[(int64_t)(t * WQ + w) * stride];
       for (int f = 0; f < 16; ++f) {
         const int q = 16 * w + f;
         if (q < nq) o[q] = (uint8_t)((word >> (2 * f)) & 3u);
@@ -628,11 +644,9 @@ unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1) / per)
 }  // namespace
 
 size_t spacetime_lds_bytes(int L, int T) {
+  (void)T;  // the hypotheses live in the workspace; LDS holds the lattice tables
   const int nq = 2 * L * L - 2 * L + 1, nstab = 2 * L * (L - 1);
-  const size_t words = (size_t)2 * nstab + (size_t)2 * nq +
-                       ((size_t)T * ((nq + 15) / 16) + (size_t)(T - 1) * ((nstab + 31) / 32)) *
-                           ST_LANES +
-                       25;
+  const size_t words = (size_t)2 * nstab + (size_t)2 * nq + 25;
   return words * sizeof(uint32_t);
 }
 
@@ -679,12 +693,9 @@ hipError_t dispatch_fast(const SpaceTimeArgs& a, hipStream_t s) {
 hipError_t launch_spacetime_chains(const SpaceTimeArgs& a, hipStream_t s) {
   if (a.n_tasks == 0) return hipSuccess;
   if (a.L <= ST_FAST_L_MAX) return dispatch_fast<2>(a, s);
+  if (!a.state) return hipErrorInvalidValue;
   const size_t lds = spacetime_lds_bytes(a.L, a.T);
   if (lds > SPACETIME_LDS_MAX) return hipErrorInvalidValue;
-  const hipError_t e = hipFuncSetAttribute((const void*)st_chain_kernel,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           (int)SPACETIME_LDS_MAX);
-  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(st_chain_kernel, dim3(blocks_for(a.n_tasks, ST_LANES)), dim3(ST_LANES), lds,
                      s, a);
   return hipGetLastError();

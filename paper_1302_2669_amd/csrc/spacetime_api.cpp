@@ -48,8 +48,8 @@ StLayout st_layout(const mcmc_spacetime_params* prm, int64_t n) {
   w.nf = off;    off = align_up(off + (size_t)chains * sizeof(int32_t));
   w.mf = off;    off = align_up(off + (size_t)chains * sizeof(int32_t));
   w.fc = off;    off = align_up(off + (size_t)(n * 4 * nq));
-  w.state = off;
-  if (L <= SPACETIME_FAST_L_MAX) {
+  w.state = off;   // the hypotheses, word-major over all chains
+  {
     const int64_t words = (int64_t)T * ((nq + 15) / 16) + (int64_t)(T - 1) * ((ns + 31) / 32);
     off = align_up(off + (size_t)(words * chains) * sizeof(uint32_t));
   }
@@ -147,7 +147,7 @@ int mcmc_decode_spacetime(const uint8_t* obs, const uint32_t* ids, int64_t n,
   a.mean_m = mean_m;
   a.chosen = chosen;
   a.correction = correction;
-  a.state = L <= SPACETIME_FAST_L_MAX ? (uint32_t*)(ws + wl.state) : nullptr;
+  a.state = (uint32_t*)(ws + wl.state);
   st = hip_status(launch_spacetime_chains(a, s));
   if (st != MCMC_OK) return st;
   return hip_status(launch_spacetime_decide(a, s));
