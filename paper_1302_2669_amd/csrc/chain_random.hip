@@ -7,13 +7,13 @@
 //
 // Mapping.  One lane per chain as in the colour-phased kernels, but a random
 // site needs its rows by a runtime index, so each lane's packed configuration
-// lives in LDS, word-major with the wave's 64 lanes side by side
+// lives in LDS, word-major with the workgroup's lanes side by side
 // (word k of lane l at [k][l]: any rows, no bank conflicts), plus one spare
 // word per lane.  The site table holds each qubit's word index and bit
 // offset, so a step issues its four word reads at once (a missing neighbour
 // reads the spare word), looks the weight change of each code up in a
 // 2-bit-field constant, and applies an accepted move with four LDS XORs
-// (two qubits of a site may share a word).  Workgroups are one wave; no
+// (two qubits of a site may share a word).  Workgroups are two waves; no
 // barrier after the set-up.
 //
 // Randomness: step t of a sweep uses block t >> 1 of Philox4x32-10 at counter
@@ -28,7 +28,10 @@
 namespace mcmc {
 namespace {
 
-constexpr int RS_LANES = 64;
+// two waves per workgroup share one copy of the site table, so that a CU
+// holds more chains' configurations (5 waves per SIMD at L = 13 instead of 4);
+// the largest code (L = 25) still fits the default 64 KB of dynamic LDS
+constexpr int RS_LANES = 128;
 constexpr uint32_t RS_NONE = 0xFFFFu;
 
 // Per site: its 3-4 qubits as 16-bit codes, two per word: the qubit's word
