@@ -56,6 +56,8 @@ CASES = [
     (14, 2, 0.05, 0.05, 1, 0, 1, 1),
     (17, 2, 0.05, 0.05, 1, 0, 1, 1),
     (25, 2, 0.03, 0.03, 1, 0, 1, 1),
+    (3, 64, 0.05, 0.05, 1, 0, 1, 2),     # the most rounds, register kernel
+    (14, 24, 0.02, 0.02, 1, 0, 1, 1),    # many rounds, buffer kernel
 ]
 
 
