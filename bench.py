@@ -356,6 +356,14 @@ def bench_mixed(args, mc, torch, dev):
                                "[0.05,0.18], L^2 sweeps, 4 chains per class, one plan",
                    "tuning": tuning, "updates_per_step": plan.total_updates},
         "logical_error": {"rate": fail, "samples": n},
+        # the five range kernels together over the whole execution (starts and
+        # estimator included, under 1% of it)
+        "roofline": {"bound": "alu", "kernel": "chains_r0..r4_kernel (whole plan)",
+                     "achieved": plan.total_updates * OPS_PER_UPDATE / (ms * 1e-3) / 1e12,
+                     "peak": PEAK_INT_OPS / 1e12, "unit": "Tops/s",
+                     "frac": plan.total_updates * OPS_PER_UPDATE / (ms * 1e-3) / PEAK_INT_OPS,
+                     "traffic": None, "ms_per_execution": ms,
+                     "ops_per_update": OPS_PER_UPDATE},
     }
     print(json.dumps(line), flush=True)
 
