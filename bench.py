@@ -822,17 +822,33 @@ def cpu_baseline_spacetime(workers):
             pool.map(_st_shard, [(w, frac) for w in range(workers)])
     dt = time.perf_counter() - t0
     return {"value": workers / (dt * frac), "unit": "histories/s", "cores": workers,
-            "kind": "oracle",
+            "kind": "oracle", "host": host_core_note(workers),
             "sample": f"{workers} histories of the same workload at {ST_SWEEPS // frac} of its "
                       f"{ST_SWEEPS} sweeps, NumPy oracle in {workers} processes of one history "
                       f"each, {dt:.1f} s wall, time x{frac}"}
 
-def host_cores():
-    """Cores this process may run on, at most 16 (one GPU's share of the host)."""
+CPU_CORE_CAP = 16
+
+
+def _affinity():
     try:
-        return max(1, min(16, len(os.sched_getaffinity(0))))
+        return len(os.sched_getaffinity(0))
     except AttributeError:
-        return max(1, min(16, os.cpu_count() or 1))
+        return os.cpu_count() or 1
+
+
+def host_cores():
+    """Worker processes of the oracle baseline: the cores this process may run
+    on, at most CPU_CORE_CAP (one GPU's share of a multi-GPU host)."""
+    return max(1, min(CPU_CORE_CAP, _affinity()))
+
+
+def host_core_note(workers):
+    """What the host offered and what the baseline used."""
+    return {"host_cpus": os.cpu_count(), "host_affinity": _affinity(), "cap": CPU_CORE_CAP,
+            "cores_used": workers,
+            "note": f"one forked process per core, capped at {CPU_CORE_CAP} cores (one GPU's "
+                    "share of the host)"}
 
 
 def cpu_baseline(n_sample, ns, noise=0, p=P, random_scan=False, workers=1):
@@ -852,6 +868,7 @@ def cpu_baseline(n_sample, ns, noise=0, p=P, random_scan=False, workers=1):
     model = "bit/phase flips q" if noise else "p"
     scan = ", random scan" if random_scan else ""
     return {"value": total / dt, "unit": "syndromes/s", "cores": workers, "kind": "oracle",
+            "host": host_core_note(workers),
             "sample": f"{total} syndromes of the same workload (L=13, {model}={p}, 4x4 "
                       f"chains, 169 sweeps{scan}), NumPy oracle in {workers} processes of "
                       f"{n_sample} syndromes each, {dt:.1f} s wall",

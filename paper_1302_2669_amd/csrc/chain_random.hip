@@ -83,7 +83,7 @@ __global__ void __launch_bounds__(RS_LANES) chains_random_kernel(const RunArgs a
   const int nstar = L * (L - 1);
   const int lane = threadIdx.x;
   SiteQubits* sites = reinterpret_cast<SiteQubits*>(rs_lds);
-  uint32_t* st = rs_lds + 2 * nstab;             // [RW][64]
+  uint32_t* st = rs_lds + 2 * nstab;             // [RW][RS_LANES]
   for (int s = lane; s < nstab; s += RS_LANES) sites[s] = site_qubits(L, s);
   __syncthreads();
 

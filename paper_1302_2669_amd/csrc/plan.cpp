@@ -692,7 +692,11 @@ int mcmc_plan_autotune(mcmc_plan* p, const uint8_t* syndromes, double* class_pro
   }
   hipStream_t s = (hipStream_t)stream;
   hipEvent_t e0 = nullptr, e1 = nullptr;
-  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return MCMC_EDEVICE;
+  if (hipEventCreate(&e0) != hipSuccess) return MCMC_EDEVICE;
+  if (hipEventCreate(&e1) != hipSuccess) {
+    hipEventDestroy(e0);
+    return MCMC_EDEVICE;
+  }
   auto time_of = [&](const mcmc_tuning& t, float* ms) -> int {
     p->tuning = t;
     if (hipEventRecord(e0, s) != hipSuccess) return MCMC_EDEVICE;

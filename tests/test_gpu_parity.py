@@ -132,6 +132,32 @@ def test_chain_parity(L, p, sweeps, burn, chains, K, n, mode):
     assert_parity(g, o)
 
 
+TI_CASES = [
+    # L, p, sweeps, burn, chains, K, n: the paper's 21 temperatures (K = 20, Sec. IV.A)
+    # at the small workload's size and budget, at larger L for a few sweeps, and the
+    # largest ladder the library takes (K = 64)
+    (3, 0.10, 2000, 0, 1, 20, 4),
+    (9, 0.12, 6, 1, 2, 20, 3),
+    (13, 0.15, 3, 0, 1, 20, 2),
+    (5, 0.08, 3, 1, 1, 64, 2),
+]
+
+
+@pytest.mark.parametrize("L,p,sweeps,burn,chains,K,n", TI_CASES)
+def test_thermodynamic_integration_parity(L, p, sweeps, burn, chains, K, n):
+    """Every temperature's trajectory, sums and accept counts bit-exact; the
+    Simpson class probabilities within 1e-12 relative."""
+    say(f"TI chains L={L} p={p} sweeps={sweeps} burn={burn} chains={chains} K={K} n={n}")
+    lat = geometry.Lattice(L)
+    syn, _, _ = sampler.sample(lat, p, SEED_SMALL + L, np.arange(n))
+    ids = np.arange(n) * 5 + 1
+    g = gpu_decode(L, syn, p, sweeps, SEED_SMALL, chains, K, burn, ids=ids)
+    o = decoder.decode(L, syn, p, sweeps, SEED_SMALL, chains_per_class=chains, n_temps=K,
+                       burn=burn, syndrome_ids=ids, trace=True)
+    o["n_final"] = o["n_final"].astype(np.int32)
+    assert_parity(g, o)
+
+
 def test_edge_syndromes():
     """Empty and fully lit syndromes, zero counted sweeps, burn-in only."""
     say("edge syndromes")
