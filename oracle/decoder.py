@@ -11,11 +11,12 @@ correction, Sec. II).
 
 import numpy as np
 
-from . import chains, estimator, geometry, init, tables
+from . import chains, estimator, geometry, init, matching, tables
 
 
 INIT_CANONICAL = 0
 INIT_MATCHING = 1
+INIT_MWPM = 2       # exact minimum-weight matching per type and parity (Sec. III)
 SCAN_COLOUR = 0      # colour-phased systematic sweeps (Sec. V's grouping)
 SCAN_RANDOM = 1      # one uniformly random stabilizer per step (Sec. IV)
 
@@ -39,7 +40,8 @@ def decode(L, syndromes, p, sweeps, seed, chains_per_class=1, n_temps=1, burn=0,
     if K != 1 and K % 2 != 0:
         raise ValueError("n_temps must be 1 or even")
     tab = tables.tables(p, K, noise, beta_scale)              # [K, 4]
-    start = init.matching_representatives if init_mode == INIT_MATCHING else init.representatives
+    start = {INIT_CANONICAL: init.representatives, INIT_MATCHING: init.matching_representatives,
+             INIT_MWPM: matching.mwpm_representatives}[init_mode]
     reps = np.stack([start(lat, syn[i]) for i in range(n)]) \
         if n else np.zeros((0, 4, lat.n_qubits), np.uint8)
 
