@@ -107,6 +107,18 @@ enum mcmc_status {
 #define MCMC_INIT_MATCHING 1u  /* greedy matching per anyon type plus the
                                   cheapest parity change per class (an
                                   approximation of Sec. III's enhanced matching) */
+#define MCMC_INIT_MWPM 2u      /* Sec. III's enhanced matching, exact: per anyon
+                                  type and line parity the part with the fewest
+                                  errors of that type (a minimum-weight perfect
+                                  matching of the lit sites and the boundaries the
+                                  parity needs, under shortest-path distances);
+                                  class c = x part of parity c&1 + z part of
+                                  parity c>>1.  Ties between equal-weight
+                                  matchings go to the smallest sum of a per-pair
+                                  splitmix64 key; paths are fixed per pair (see
+                                  mcmc_init_representatives).  With no counted
+                                  sweep the decision is the enhanced-matching
+                                  decoder (fewest errors, Y counting once). */
 
 typedef struct mcmc_params {
   int32_t L;           /* code distance, MCMC_L_MIN..MCMC_L_MAX                  */
@@ -136,7 +148,7 @@ typedef struct mcmc_params {
 /* Human-readable name of a status code (static string). */
 const char* mcmc_strerror(int status);
 
-/* ABI version of this header: 0x00010200 for 1.2. */
+/* ABI version of this header: 0x00010300 for 1.3. */
 int32_t mcmc_abi_version(void);
 
 /* n_q and n_stab of a distance-L code (Sec. II: n_stab = 2L(L-1),
@@ -205,8 +217,26 @@ int mcmc_decode_batch(const uint8_t* d_syndromes, const uint32_t* d_syndrome_ids
 
 /* The four class starting configurations (Sec. IV: one chain start per
  * class, consistent with the syndrome) of n syndromes: d_reps [n][4][n_q]
- * uint8, row k of class k; `init` is MCMC_INIT_CANONICAL or
- * MCMC_INIT_MATCHING.  Asynchronous; needs no workspace. */
+ * uint8, row k of class k; `init` is MCMC_INIT_CANONICAL, MCMC_INIT_MATCHING
+ * or MCMC_INIT_MWPM.  Asynchronous; needs no workspace.
+ *
+ * MCMC_INIT_MWPM in full (Sec. III).  Per anyon type (plaquettes: x parts,
+ * left/right boundaries, parity = x parts on grid column 0; stars: z parts,
+ * top/bottom, parity = z parts on grid row 0) and parity b, the vertex set is
+ * the lit sites (i, j) of the type plus NEAR (left/top) if b = 1 plus FAR
+ * (right/bottom) if (lit count + b) is odd, and the distances are
+ *   d(a, a') = min(|di| + |dj|, near(a) + near(a'), far(a) + far(a')),
+ *   d(a, NEAR) = near(a), d(a, FAR) = far(a), d(NEAR, FAR) = L,
+ * near/far = j+1 / L-1-j (plaquettes), i+1 / L-1-i (stars).  The matching
+ * minimises the sum of W = d 2^53 + 2 t over its pairs, t = splitmix64 at
+ * state (min(id) << 12) | max(id) shifted right by 21 (id = site index,
+ * NEAR 4094, FAR 4095), so the total distance is the minimum and ties go to
+ * the smallest t sum.  Pair a < a' (site order): direct path if the
+ * Manhattan distance is d (plaquettes along a's grid row to the column of
+ * a', then along that column; stars along a's grid column to the row of a',
+ * then along that row), else both strings to the nearer boundary (NEAR on a
+ * tie); boundary matches are straight strings and NEAR-FAR is the logical
+ * string (X on grid row 0, Z on grid column 0). */
 int mcmc_init_representatives(int32_t L, uint32_t init, const uint8_t* d_syndromes, int64_t n,
                               uint8_t* d_reps, void* stream);
 

@@ -10,7 +10,8 @@ import ctypes
 import numpy as np
 
 from . import _lib
-from ._lib import (MCMC_INIT_CANONICAL, MCMC_INIT_MATCHING, MCMC_L_MAX, MCMC_L_MIN,
+from ._lib import (MCMC_INIT_CANONICAL, MCMC_INIT_MATCHING, MCMC_INIT_MWPM, MCMC_L_MAX,
+                   MCMC_L_MIN,
                    MCMC_NOISE_BITPHASE, MCMC_NOISE_DEPOLARIZING, MCMC_RANDOM_SCAN, MCMC_RESUME,
                    MCMC_TRACE, McmcError, Params)
 
@@ -18,7 +19,7 @@ __all__ = ["Params", "McmcError", "geometry", "lattice", "acceptance_table", "wo
            "chain_state_size", "decode_batch", "sample_errors", "init_representatives",
            "unpack_chain_state", "MCMC_TRACE", "MCMC_RESUME", "MCMC_RANDOM_SCAN", "MCMC_L_MIN",
            "MCMC_L_MAX",
-           "MCMC_INIT_CANONICAL", "MCMC_INIT_MATCHING", "MCMC_NOISE_DEPOLARIZING",
+           "MCMC_INIT_CANONICAL", "MCMC_INIT_MATCHING", "MCMC_INIT_MWPM", "MCMC_NOISE_DEPOLARIZING",
            "MCMC_NOISE_BITPHASE", "params_table", "MixedPlan", "spacetime_params",
            "spacetime_tables", "sample_spacetime", "decode_spacetime"]
 

@@ -17,7 +17,7 @@ STATUS = {0: "MCMC_OK", -1: "MCMC_EINVAL", -2: "MCMC_ERANGE", -3: "MCMC_ENOMEM",
 MCMC_L_MIN, MCMC_L_MAX = 2, 25
 MCMC_TEMPS_MAX = 64
 MCMC_TRACE, MCMC_RESUME, MCMC_RANDOM_SCAN = 1, 2, 4
-MCMC_INIT_CANONICAL, MCMC_INIT_MATCHING = 0, 1
+MCMC_INIT_CANONICAL, MCMC_INIT_MATCHING, MCMC_INIT_MWPM = 0, 1, 2
 MCMC_NOISE_DEPOLARIZING, MCMC_NOISE_BITPHASE = 0, 1
 MCMC_CNN_BATCH_MAX = 1 << 24
 MCMC_ROUNDS_MAX = 64
@@ -168,7 +168,7 @@ _handle = None
 
 
 # layout of the structures below (mcmc_params, mcmc_item, ...)
-ABI_VERSION = 0x00010200
+ABI_VERSION = 0x00010300
 
 
 def _lib():

@@ -6,6 +6,7 @@ rebuilds unconditionally.
 """
 
 import concurrent.futures as cf
+import hashlib
 import os
 import shutil
 import subprocess
@@ -47,15 +48,42 @@ def _compile(src, obj):
     return obj
 
 
-def build(jobs=None, verbose=True):
+def _key(src):
+    """Hash of a source, every header it may include and the flags."""
+    h = hashlib.sha256()
+    h.update(" ".join(COMMON).encode())
+    hdrs = sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".h"))
+    for f in [src] + hdrs + [os.path.join(HERE, "..", "include", "mcmcdec.h")]:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:24]
+
+
+def build(jobs=None, verbose=True, cache=False):
+    """Compile every source and link the library.  With cache=True (for
+    development) an object whose source, headers and flags are unchanged is
+    reused from _build/."""
     jobs = jobs or min(8, os.cpu_count() or 4)
     srcs = sources()
+    cache_dir = os.path.join(HERE, "..", "_build")
     with tempfile.TemporaryDirectory(prefix="mcmcdec_build_") as tmp:
-        objs = [os.path.join(tmp, os.path.basename(s) + ".o") for s in srcs]
+        objs, todo = [], []
+        for s in srcs:
+            if cache:
+                os.makedirs(cache_dir, exist_ok=True)
+                o = os.path.join(cache_dir, os.path.basename(s) + "." + _key(s) + ".o")
+                if not os.path.exists(o):
+                    todo.append((s, o))
+            else:
+                o = os.path.join(tmp, os.path.basename(s) + ".o")
+                todo.append((s, o))
+            objs.append(o)
         with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
-            futs = [ex.submit(_compile, s, o) for s, o in zip(srcs, objs)]
+            futs = [ex.submit(_compile, s, o + ".part") for s, o in todo]
             for f in futs:
                 f.result()
+        for s, o in todo:
+            os.replace(o + ".part", o)
         tmp_lib = LIB + ".tmp"
         cmd = [hipcc(), "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp_lib] + objs
         res = subprocess.run(cmd, capture_output=True, text=True)
@@ -68,4 +96,4 @@ def build(jobs=None, verbose=True):
 
 
 if __name__ == "__main__":
-    build()
+    build(cache="--cache" in sys.argv)

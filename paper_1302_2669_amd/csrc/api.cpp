@@ -86,7 +86,9 @@ int check_params(const mcmc_params* prm, int64_t n) {
   if ((int64_t)prm->burn + prm->sweeps > MCMC_SWEEPS_MAX) return MCMC_ERANGE;
   if (prm->flags & ~(MCMC_TRACE | MCMC_RESUME | MCMC_RANDOM_SCAN)) return MCMC_EINVAL;
   if ((prm->flags & MCMC_RANDOM_SCAN) && (prm->flags & MCMC_TRACE)) return MCMC_EINVAL;
-  if (prm->init != MCMC_INIT_CANONICAL && prm->init != MCMC_INIT_MATCHING) return MCMC_EINVAL;
+  if (prm->init != MCMC_INIT_CANONICAL && prm->init != MCMC_INIT_MATCHING &&
+      prm->init != MCMC_INIT_MWPM)
+    return MCMC_EINVAL;
   if (prm->flags & MCMC_RESUME) {
     if (prm->sweep_begin < 0 || prm->sweep_begin > prm->burn + prm->sweeps) return MCMC_ERANGE;
   } else if (prm->sweep_begin != 0) {
@@ -135,7 +137,7 @@ const char* mcmc_strerror(int status) {
   }
 }
 
-int32_t mcmc_abi_version(void) { return 0x00010200; }
+int32_t mcmc_abi_version(void) { return 0x00010300; }
 
 int mcmc_geometry(int32_t L, int32_t* n_qubits, int32_t* n_stab) {
   if (!valid_L(L)) return MCMC_ERANGE;
@@ -249,8 +251,7 @@ int mcmc_decode_batch(const uint8_t* syndromes, const uint32_t* syndrome_ids, in
     sa.rows = init_rows;
     sa.weights = init_n;
     sa.noise = (int32_t)prm->noise;
-    st = hip_status(prm->init == MCMC_INIT_MATCHING ? launch_init_matching(sa, s)
-                                                    : launch_init(sa, s));
+    st = hip_status(launch_init_mode(prm->init, sa, s));
     if (st != MCMC_OK) return st;
   }
 
@@ -337,7 +338,8 @@ int mcmc_decode_batch(const uint8_t* syndromes, const uint32_t* syndrome_ids, in
 int mcmc_init_representatives(int32_t L, uint32_t init, const uint8_t* syndromes, int64_t n,
                               uint8_t* reps, void* stream) {
   if (!valid_L(L)) return MCMC_ERANGE;
-  if (init != MCMC_INIT_CANONICAL && init != MCMC_INIT_MATCHING) return MCMC_EINVAL;
+  if (init != MCMC_INIT_CANONICAL && init != MCMC_INIT_MATCHING && init != MCMC_INIT_MWPM)
+    return MCMC_EINVAL;
   if (n < 0) return MCMC_ERANGE;
   if (n == 0) return MCMC_OK;
   if (!syndromes || !reps) return MCMC_EINVAL;
@@ -347,7 +349,7 @@ int mcmc_init_representatives(int32_t L, uint32_t init, const uint8_t* syndromes
   sa.n = n;
   sa.L = L;
   sa.bytes = reps;
-  return hip_status(init == MCMC_INIT_MATCHING ? launch_init_matching(sa, s) : launch_init(sa, s));
+  return hip_status(launch_init_mode(init, sa, s));
 }
 
 int mcmc_unpack_chain_state(const mcmc_params* prm, int64_t n, const void* chain_state,

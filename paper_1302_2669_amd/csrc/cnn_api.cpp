@@ -244,7 +244,8 @@ int mcmc_gated_create(const mcmc_gate_config* h_cfg, mcmc_gated** out) {
   if (!(c.threshold >= 0.0f && c.threshold <= 1.0f)) return MCMC_ERANGE;
   if (!(c.escalate >= 0.0f && c.escalate <= 1.0f)) return MCMC_ERANGE;
   if (c.sweeps_short < 0 || c.sweeps_full < 0) return MCMC_ERANGE;
-  if (c.init != MCMC_INIT_CANONICAL && c.init != MCMC_INIT_MATCHING) return MCMC_EINVAL;
+  if (c.init != MCMC_INIT_CANONICAL && c.init != MCMC_INIT_MATCHING && c.init != MCMC_INIT_MWPM)
+    return MCMC_EINVAL;
   if (cnn_infer_group(c.L) < 1) return MCMC_EDEVICE;
   mcmc_gated* g = new (std::nothrow) mcmc_gated();
   if (!g) return MCMC_ENOMEM;
@@ -400,7 +401,8 @@ int gated_decode_device(mcmc_gated* g, const float* d_params, const uint8_t* d_s
   sa.n = n;
   sa.rows = irows;
   sa.weights = in_n;
-  st = hip_status(c.init == MCMC_INIT_MATCHING ? launch_init_matching(sa, s) : launch_init(sa, s));
+  sa.max_L = c.L;
+  st = hip_status(launch_init_mode(c.init, sa, s));
   if (st != MCMC_OK) return st;
 
   const int r = range_of(c.L);

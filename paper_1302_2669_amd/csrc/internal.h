@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include "../../include/mcmcdec.h"
+#include "device_common.h"
 
 namespace mcmc {
 
@@ -129,9 +130,44 @@ struct StartArgs {
   int32_t* weights;              // [orig*4 + cls], or nullptr
   uint8_t* bytes;                // [orig][4][n_q] (implicit only), or nullptr
   int32_t noise;                 // weights count x|z (0) or x + z parts (1)
+  int32_t max_L;                 // with items: the largest L among them
 };
 hipError_t launch_init(const StartArgs& a, hipStream_t s);
 hipError_t launch_init_matching(const StartArgs& a, hipStream_t s);
+// Exact minimum-weight matching starts (MCMC_INIT_MWPM): one workgroup per
+// syndrome, dynamic LDS sized for the largest L.
+hipError_t launch_init_mwpm(const StartArgs& a, hipStream_t s);
+// The start kernel of an MCMC_INIT_* mode.
+hipError_t launch_init_mode(uint32_t init, const StartArgs& a, hipStream_t s);
+
+#ifdef __HIPCC__
+// Syndrome s of a start launch: its L, input bytes, start block and caller index.
+struct StartItem {
+  int L;
+  int noise;                    // energy counted as x|z (0) or x + z parts (1)
+  const uint8_t* sy;
+  int64_t rows_off, orig;
+};
+__device__ inline StartItem start_item(const StartArgs& a, int64_t s) {
+  StartItem r;
+  if (a.items) {
+    const ItemDesc it = a.items[s];
+    r.L = a.groups[it.group].L;
+    r.noise = it.noise;
+    r.sy = a.syn + it.syn_off;
+    r.rows_off = it.rows_off;
+    r.orig = it.orig;
+  } else {
+    r.L = a.L;
+    r.noise = a.noise;
+    r.sy = a.syn + s * (int64_t)(2 * a.L * (a.L - 1));
+    r.rows_off = s * (int64_t)words_per_config(a.L) * 4;
+    r.orig = s;
+  }
+  return r;
+}
+
+#endif
 
 hipError_t launch_unpack(int L, int noise, const uint32_t* rows, int64_t count, int64_t stride,
                          uint8_t* out, int32_t* weights, hipStream_t s);

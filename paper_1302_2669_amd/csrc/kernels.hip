@@ -18,32 +18,6 @@ namespace mcmc {
 // class c multiplies it by X-bar (X on row 0) if bx != c&1 and by Z-bar
 // (Z on column 0) if bz != c>>1.  One thread per (syndrome, class).
 // ---------------------------------------------------------------------------
-// Syndrome s of a start launch: its L, input bytes, start block and caller index.
-struct StartItem {
-  int L;
-  int noise;                    // energy counted as x|z (0) or x + z parts (1)
-  const uint8_t* sy;
-  int64_t rows_off, orig;
-};
-__device__ __forceinline__ StartItem start_item(const StartArgs& a, int64_t s) {
-  StartItem r;
-  if (a.items) {
-    const ItemDesc it = a.items[s];
-    r.L = a.groups[it.group].L;
-    r.noise = it.noise;
-    r.sy = a.syn + it.syn_off;
-    r.rows_off = it.rows_off;
-    r.orig = it.orig;
-  } else {
-    r.L = a.L;
-    r.noise = a.noise;
-    r.sy = a.syn + s * (int64_t)(2 * a.L * (a.L - 1));
-    r.rows_off = s * (int64_t)words_per_config(a.L) * 4;
-    r.orig = s;
-  }
-  return r;
-}
-
 __global__ void __launch_bounds__(256) init_kernel(const StartArgs a) {
   const int64_t sc = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (sc >= a.n * 4) return;
@@ -591,6 +565,12 @@ hipError_t launch_init_matching(const StartArgs& a, hipStream_t s) {
                      dim3((unsigned)((a.n + MATCH_THREADS - 1) / MATCH_THREADS)),
                      dim3(MATCH_THREADS), 0, s, a);
   return hipGetLastError();
+}
+
+hipError_t launch_init_mode(uint32_t init, const StartArgs& a, hipStream_t s) {
+  if (init == MCMC_INIT_MWPM) return launch_init_mwpm(a, s);
+  if (init == MCMC_INIT_MATCHING) return launch_init_matching(a, s);
+  return launch_init(a, s);
 }
 
 }  // namespace mcmc

@@ -1,0 +1,153 @@
+// Minimum-weight matching class starts (arXiv:1302.2669, Sec. III and Sec. IV).
+//
+// Sec. III decodes each anyon type on its own by minimum-weight matching and
+// forces the other line parity with an extra boundary anyon; the 2 x 2
+// combinations are the four class hypotheses, and Sec. IV starts each class's
+// chain from its hypothesis.  Each (type, parity) problem is solved exactly
+// (mwpm_solver.h): a minimum T-join of the lattice graph, i.e. a minimum-weight
+// perfect matching of the lit sites and the boundary vertices the parity
+// needs, under shortest-path distances, ties broken by a per-pair splitmix64
+// key so that the optimum is unique.
+//
+// Paths: a matched anyon pair a < a' (site order) whose Manhattan distance is
+// its distance takes the direct path (plaquettes: along a's grid row to the
+// column of a', then along that column; stars: along a's grid column to the
+// row of a', then along that row), else both anyons go to the nearer
+// boundary option (NEAR on a tie); anyon-boundary matches take the straight
+// string and NEAR-FAR the logical string.  Class c = x part of parity c & 1
+// with z part of parity c >> 1.
+//
+// One workgroup per syndrome.  Its waves each solve one (type, parity)
+// problem at a time with the whole solver state in LDS (up to four problems
+// at once, fewer at large L), XOR their parts into bit planes, and the
+// workgroup packs the four class starts.
+#include "device_common.h"
+#include "internal.h"
+
+#define MW_FN __device__ __forceinline__
+#define MW_HD __host__ __device__ inline
+#include "mwpm_solver.h"
+
+namespace mcmc {
+
+namespace {
+
+struct Wave64 {
+  static constexpr int N = 64;
+  int lane;
+  MW_FN void sync() const {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+  MW_FN void argmin(int64_t& key, int& idx) const {
+    for (int o = 32; o > 0; o >>= 1) {
+      const int64_t k2 = __shfl_xor(key, o, 64);
+      const int i2 = __shfl_xor(idx, o, 64);
+      if (k2 < key || (k2 == key && i2 < idx)) { key = k2; idx = i2; }
+    }
+  }
+  MW_FN bool any(bool p) const { return __ballot(p) != 0ull; }
+  MW_FN int compact(bool take, int& count) const {
+    const uint64_t bal = __ballot(take);
+    const int slot = count + __popcll(bal & ((1ull << lane) - 1ull));
+    count += __popcll(bal);
+    return slot;
+  }
+  MW_FN void xor_word(uint32_t* p, uint32_t v) const { atomicXor(p, v); }
+};
+
+// waves per workgroup: all four problems of a syndrome at once when their
+// state fits in 64 KB, else two or one wave taking the problems in turn
+int mwpm_waves(int L) {
+  const size_t r = mw::region_bytes(mw::capacity(L));
+  if (4 * r <= 64 * 1024) return 4;
+  if (2 * r <= 64 * 1024) return 2;
+  return 1;
+}
+
+size_t mwpm_lds(int L) {
+  return mwpm_waves(L) * mw::region_bytes(mw::capacity(L)) +
+         (4 * mw::ROWS + 4) * sizeof(uint32_t);
+}
+
+}  // namespace
+
+// Wave w solves problems w, w + waves, ... of the four (type = problem >> 1:
+// 0 plaquettes / x parts, 1 stars / z parts; parity = problem & 1).
+__global__ void __launch_bounds__(256) init_mwpm_kernel(const StartArgs a, int cap, int waves) {
+  extern __shared__ __align__(16) uint8_t mw_lds[];
+  const int64_t s = blockIdx.x;
+  if (s >= a.n) return;
+  const StartItem si = start_item(a, s);
+  const int L = si.L;
+  const int wave = threadIdx.x >> 6;
+  const size_t region = mw::region_bytes(cap);
+  uint32_t* planes = reinterpret_cast<uint32_t*>(mw_lds + waves * region);  // [4][ROWS]
+  int* wsum = reinterpret_cast<int*>(planes + 4 * mw::ROWS);
+  for (int k = threadIdx.x; k < 4 * mw::ROWS; k += blockDim.x) planes[k] = 0u;
+  if (threadIdx.x < 4) wsum[threadIdx.x] = 0;
+  __syncthreads();
+  if (wave < waves) {
+    mw::Solver<Wave64> m;
+    m.wv.lane = threadIdx.x & 63;
+    m.carve(mw_lds + wave * region, cap);
+    for (int p = wave; p < 4; p += waves) {
+      m.load(si.sy, L, (p >> 1) != 0, p & 1);
+      m.solve();
+      m.wv.sync();
+      m.paint(planes + p * mw::ROWS, p & 1);
+      m.wv.sync();
+    }
+  }
+  __syncthreads();
+  // class c: x part of parity c & 1 (problem c & 1), z part of parity c >> 1
+  // (problem 2 + (c >> 1))
+  const int R = 2 * L - 1, W = words_per_row(L);
+  const int nq = 2 * L * L - 2 * L + 1, side_len = 2 * L - 1;
+  for (int t = threadIdx.x; t < 4 * R; t += blockDim.x) {
+    const int cls = t / R, r = t % R;
+    const uint32_t xb = planes[(cls & 1) * mw::ROWS + r];
+    const uint32_t zb = planes[(2 + (cls >> 1)) * mw::ROWS + r];
+    const int fields = (r & 1) ? L - 1 : L;
+    const uint32_t valid = fields >= 32 ? ~0u : ((1u << fields) - 1u);
+    atomicAdd(&wsum[cls], si.noise ? __builtin_popcount(xb & valid) + __builtin_popcount(zb & valid)
+                                    : __builtin_popcount((xb | zb) & valid));
+    if (a.rows) {
+      for (int w = 0; w < W; ++w) {
+        uint32_t word = 0;
+        for (int f = 0; f < 16; ++f) {
+          const int kk = 16 * w + f;
+          const uint32_t code = kk < fields ? (((xb >> kk) & 1u) | (((zb >> kk) & 1u) << 1)) : 3u;
+          word |= code << (2 * f);
+        }
+        a.rows[si.rows_off + (r * W + w) * 4 + cls] = word;
+      }
+    }
+    if (a.bytes) {
+      uint8_t* out = a.bytes + (si.orig * 4 + cls) * nq + (r * side_len + (r & 1)) / 2;
+      for (int kk = 0; kk < fields; ++kk)
+        out[kk] = (uint8_t)(((xb >> kk) & 1u) | (((zb >> kk) & 1u) << 1));
+    }
+  }
+  __syncthreads();
+  if (a.weights && threadIdx.x < 4) a.weights[si.orig * 4 + threadIdx.x] = wsum[threadIdx.x];
+}
+
+hipError_t launch_init_mwpm(const StartArgs& a, hipStream_t s) {
+  if (a.n == 0) return hipSuccess;
+  const int L = a.items ? a.max_L : a.L;
+  if (L < MCMC_L_MIN || L > MCMC_L_MAX) return hipErrorInvalidValue;
+  const int cap = mw::capacity(L);
+  const int waves = mwpm_waves(L);
+  const size_t lds = mwpm_lds(L);
+  if (lds > 64 * 1024) {
+    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(init_mwpm_kernel),
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(init_mwpm_kernel, dim3((unsigned)a.n), dim3(256), lds, s, a, cap, waves);
+  return hipGetLastError();
+}
+
+}  // namespace mcmc

@@ -171,7 +171,8 @@ int enqueue(mcmc_plan* p, const uint8_t* syn, double* prob, double* mean_n, int6
   sa.n = p->n;
   sa.rows = init_rows;
   sa.weights = init_n;
-  st = hip_status(p->init == MCMC_INIT_MATCHING ? launch_init_matching(sa, s) : launch_init(sa, s));
+  for (const GroupDesc& g : p->groups) sa.max_L = std::max(sa.max_L, g.L);
+  st = hip_status(launch_init_mode(p->init, sa, s));
   if (st != MCMC_OK) return st;
 
   RunArgs a{};
@@ -542,7 +543,8 @@ int mcmc_plan_create(const mcmc_item* items, int64_t n, uint64_t seed, uint32_t 
                      mcmc_plan** out) {
   if (!out) return MCMC_EINVAL;
   *out = nullptr;
-  if (init != MCMC_INIT_CANONICAL && init != MCMC_INIT_MATCHING) return MCMC_EINVAL;
+  if (init != MCMC_INIT_CANONICAL && init != MCMC_INIT_MATCHING && init != MCMC_INIT_MWPM)
+    return MCMC_EINVAL;
   int st = check_items(items, n);
   if (st != MCMC_OK) return st;
   mcmc_plan* p = new (std::nothrow) mcmc_plan();

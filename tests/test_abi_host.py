@@ -27,7 +27,7 @@ def test_exports_every_declared_symbol():
     assert decl == _lib.exported_symbols()
     for name in decl:
         assert hasattr(lib, name), name
-    assert lib.mcmc_abi_version() == 0x00010200
+    assert lib.mcmc_abi_version() == 0x00010300
 
 
 @pytest.mark.parametrize("L", list(range(2, 26)))
@@ -82,7 +82,7 @@ def _ws(**kw):
     (dict(chains=0), -2), (dict(sweeps=-1), -2), (dict(burn=-2), -2),
     (dict(L=30), -2), (dict(p=0.8), -2), (dict(flags=8), -1), (dict(sweep_begin=3), -1),
     (dict(flags=5), -1),
-    (dict(init=2), -1), (dict(noise=2), -1), (dict(noise=1, p=0.5), -2),
+    (dict(init=3), -1), (dict(noise=2), -1), (dict(noise=1, p=0.5), -2),
     (dict(noise=1, p=0.0), -2), (dict(beta_scale=-0.5), -2), (dict(beta_scale=4.5), -2),
     (dict(beta_scale=float("nan")), -2), (dict(n_temps=2, beta_scale=0.85), -2),
 ])
