@@ -79,6 +79,8 @@ def main():
     ap.add_argument("--gate-epochs", type=int, default=4)
     ap.add_argument("--gate-eval", type=int, default=100_000)
     ap.add_argument("--mixed-n", type=int, default=100000)
+    ap.add_argument("--init", choices=["greedy", "mwpm"], default="greedy",
+                    help="class starts: greedy matching, or Sec. III's exact enhanced matching")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="also run one device copy of this size (HBM counter calibration)")
     args = ap.parse_args()
@@ -106,6 +108,7 @@ def main():
 
     import torch
     import paper_1302_2669_amd as mc
+    args.init_mode = mc.MCMC_INIT_MWPM if args.init == "mwpm" else mc.MCMC_INIT_MATCHING
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
@@ -140,7 +143,7 @@ def main():
     def step(b, sweeps=SWEEPS, burn=BURN, workspace=ws):
         return mc.decode_batch(batches[b], L, P, sweeps, SEED, chains=CHAINS, n_temps=K,
                                burn=burn, syndrome_ids=ids[b], want_correction=True,
-                               workspace=workspace)
+                               workspace=workspace, init=args.init_mode)
 
     for b in range(warm):
         step(b)
@@ -196,7 +199,7 @@ def main():
         curve = []
         # counted sweeps (burn-in 0) from L^2/8 to 4 L^2, and L^2 split into
         # L^2/2 uncounted + L^2/2 counted (same cost as L^2)
-        points = [(SWEEPS // 8, 0), (SWEEPS // 4, 0), (SWEEPS // 2, 0), (SWEEPS, 0),
+        points = [(0, 0), (SWEEPS // 8, 0), (SWEEPS // 4, 0), (SWEEPS // 2, 0), (SWEEPS, 0),
                   (2 * SWEEPS, 0), (4 * SWEEPS, 0), (SWEEPS - SWEEPS // 2, SWEEPS // 2)]
         ws_big = None
         for b, burn in points:
@@ -239,7 +242,8 @@ def main():
     for i in range(ne):
         d_syn.copy_(h_syn[i], non_blocking=True)
         o = mc.decode_batch(d_syn, L, P, SWEEPS, SEED, chains=CHAINS, n_temps=K, burn=BURN,
-                            syndrome_ids=ids[warm + i], want_correction=True, workspace=ws)
+                            syndrome_ids=ids[warm + i], want_correction=True, workspace=ws,
+                            init=args.init_mode)
         h_chosen.copy_(o["chosen"], non_blocking=True)
         h_prob.copy_(o["class_prob"], non_blocking=True)
         h_corr.copy_(o["correction"], non_blocking=True)
@@ -275,7 +279,10 @@ def main():
         "data": "synthetic: i.i.d. depolarizing samples from the library's Philox sampler",
         "config": {"workload": "planar code L=13, depolarizing p=0.15, 4 classes x 4 chains, "
                                "169 sweeps (L^2), single temperature, batch of "
-                               f"{n} syndromes per step",
+                               f"{n} syndromes per step, "
+                               + ("exact enhanced-matching starts (Sec. III)" if args.init == "mwpm"
+                                  else "greedy matching starts"),
+                   "start": args.init,
                    "L": L, "p": P, "chains_per_class": CHAINS, "sweeps": SWEEPS, "burn": BURN,
                    "n_temps": K, "batch": n, "updates_per_syndrome": updates_per_syndrome},
         "logical_error": {"rate": p_l, "wilson95": [centre - half, centre + half],
@@ -289,6 +296,7 @@ def main():
                      "updates_per_launch": chain_updates},
         "cpu_baseline": cpu,
         "end_to_end": e2e,
+        "starts_and_estimator_ms_per_step": overhead_ms,
         "budget_curve": curve,
         "matched_error_budget": None if curve is None else
             {"sweeps": matched["sweeps"], "syndromes_per_s": matched["syndromes_per_s"],
@@ -738,34 +746,42 @@ def bench_context(args, mc, torch, dev):
     below p from L = 6 on.  (b) Its threshold of 15-16%: logical error against
     p for several L, where curves of growing L cross.  The paper starts its
     chains from enhanced matching and samples L^4 steps per chain (about L^2/2
-    sweeps); these runs start from the greedy matching start, 4 classes x 4
-    chains, at budgets of L^2, 4 L^2 and 16 L^2 sweeps (65536, 16384 and 8192
-    syndromes per point)."""
+    sweeps).  4 classes x 4 chains, class starts from --init, budgets of 0
+    (the decision of the starts alone: with the exact enhanced-matching starts
+    this is Sec. III's enhanced-matching decoder), L^2/2, L^2 and 4 L^2 sweeps
+    (65536, 65536, 32768 and 16384 syndromes per point)."""
     z = 1.96
 
-    def point(L, p, mult, n, seed):
+    def point(L, p, frac, n, seed):
+        sweeps = int(round(frac * L * L))
         syn, cls, _ = mc.sample_errors(L, p, seed, n, device=dev)
-        out = mc.decode_batch(syn, L, p, mult * L * L, seed, chains=CHAINS, want_correction=False)
+        out = mc.decode_batch(syn, L, p, sweeps, seed, chains=CHAINS, want_correction=False,
+                              init=args.init_mode)
         wrong = int((out["chosen"] != cls).sum().item())
         r = wrong / n
         den = 1 + z * z / n
         c = (r + z * z / (2 * n)) / den
         h = z * np.sqrt(r * (1 - r) / n + z * z / (4 * n * n)) / den
-        return {"L": L, "p": p, "sweeps": mult * L * L, "logical_error": r,
+        return {"L": L, "p": p, "sweeps": sweeps, "logical_error": r,
                 "wilson95": [c - h, c + h], "samples": n}
 
     t0 = time.perf_counter()
     small, scan = [], []
-    for mult, n in ((1, args.batch), (4, args.batch // 4), (16, args.batch // 8)):
-        small += [point(L, 0.13, mult, n, SEED + 100 + L) for L in (4, 5, 6, 7, 8)]
-        scan += [point(L, p, mult, n, SEED + 1000 * L + int(p * 1000))
+    for frac, n in ((0.0, args.batch), (0.5, args.batch), (1.0, args.batch // 2),
+                    (4.0, args.batch // 4)):
+        small += [point(L, 0.13, frac, n, SEED + 100 + L) for L in (4, 5, 6, 7, 8)]
+        scan += [point(L, p, frac, n, SEED + 1000 * L + int(p * 1000))
                  for L in (9, 13, 17, 21, 25) for p in (0.14, 0.15, 0.16, 0.17)]
+        print(f"context: budget {frac} L^2 done, {time.perf_counter() - t0:.0f} s",
+              file=sys.stderr, flush=True)
+    start = ("exact enhanced-matching starts (Sec. III)" if args.init == "mwpm"
+             else "greedy matching starts")
     line = {
         "metric": "logical error rate beside the paper's figures (context)",
         "value": None, "unit": "logical error", "n_gpus": 1, "higher_is_better": False,
         "data": "synthetic: i.i.d. depolarizing samples from the library's Philox sampler",
-        "config": {"workload": "depolarizing noise, greedy matching start, 4 classes x 4 chains, "
-                               "L^2, 4 L^2 and 16 L^2 sweeps"},
+        "config": {"workload": f"depolarizing noise, {start}, 4 classes x 4 chains, "
+                               "0, L^2/2, L^2 and 4 L^2 sweeps", "start": args.init},
         "proof_of_principle_p013": small,
         "threshold_scan": scan,
         "seconds": time.perf_counter() - t0,

@@ -32,9 +32,9 @@ boundary) restricts the same problem.
 
 Ties.  Many matchings can share the minimum weight.  Every matching edge
 {u, v} therefore carries the weight W = d 2^53 + 2 t(u, v), where t is the
-top 43 bits of the splitmix64 output (Steele, Lea and Flood, OOPSLA 2014) at
-state (min(id) << 12) | max(id); an anyon's id is its site index, NEAR is
-4094 and FAR is 4095.  Over any perfect matching (at most 301 edges at
+top 43 bits of the 64-bit product K(u) K(v), K(x) = the splitmix64 output
+(Steele, Lea and Flood, OOPSLA 2014) at state id(x); an anyon's id is its
+site index, NEAR is 4094 and FAR is 4095.  Over any perfect matching (at most 301 edges at
 L = 25) the t terms add up to less than 2^53, so W orders matchings by total
 distance first; among equal distances the smallest sum of t wins, which is
 unique unless two matchings' t sums collide (probability below
@@ -76,8 +76,8 @@ def splitmix64(state):
 
 
 def tie_break(id_a, id_b):
-    lo, hi = min(id_a, id_b), max(id_a, id_b)
-    return splitmix64((lo << 12) | hi) >> (64 - T_BITS)
+    """Top 43 bits of the 64-bit product of the two ends' splitmix64 keys."""
+    return ((splitmix64(id_a) * splitmix64(id_b)) & _M64) >> (64 - T_BITS)
 
 
 # ---------------------------------------------------------------------------

@@ -17,10 +17,11 @@
 // string and NEAR-FAR the logical string.  Class c = x part of parity c & 1
 // with z part of parity c >> 1.
 //
-// One workgroup per syndrome.  Its waves each solve one (type, parity)
-// problem at a time with the whole solver state in LDS (up to four problems
-// at once, fewer at large L), XOR their parts into bit planes, and the
-// workgroup packs the four class starts.
+// One workgroup per syndrome.  Its two waves each solve one anyon type (both
+// parities, the second from the first's solution) with the whole solver state
+// in LDS (at large L one wave takes both types in turn), XOR their parts into
+// bit planes, and the workgroup packs the four class starts.  Two launches: one sized for typical
+// syndromes (more resident waves), one for the rest.
 #include "device_common.h"
 #include "internal.h"
 
@@ -57,30 +58,57 @@ struct Wave64 {
   MW_FN void xor_word(uint32_t* p, uint32_t v) const { atomicXor(p, v); }
 };
 
-// waves per workgroup: all four problems of a syndrome at once when their
-// state fits in 64 KB, else two or one wave taking the problems in turn
-int mwpm_waves(int L) {
-  const size_t r = mw::region_bytes(mw::capacity(L));
-  if (4 * r <= 64 * 1024) return 4;
-  if (2 * r <= 64 * 1024) return 2;
-  return 1;
+// waves per workgroup: one per anyon type when both states fit in 64 KB,
+// else one wave taking the types in turn
+int mwpm_waves(int cap) { return 2 * mw::region_bytes(cap) <= 64 * 1024 ? 2 : 1; }
+
+size_t mwpm_lds(int cap) {
+  return mwpm_waves(cap) * mw::region_bytes(cap) + (4 * mw::ROWS + 4) * sizeof(uint32_t);
 }
 
-size_t mwpm_lds(int L) {
-  return mwpm_waves(L) * mw::region_bytes(mw::capacity(L)) +
-         (4 * mw::ROWS + 4) * sizeof(uint32_t);
+// Capacity of the first launch: the problems of typical syndromes (lit sites
+// of one type up to about 2/5 of them, at least 94), so that more waves fit
+// per compute unit; the rare larger syndromes go to a second launch sized for
+// a fully lit code.
+int mwpm_small_capacity(int L) {
+  const int full = mw::capacity(L);
+  int c = 2 * L * (L - 1) / 5 + 8;
+  if (c < 96) c = 96;
+  c = (c + 3) & ~3;
+  return c < full ? c : full;
 }
+
+// vertices of the second-parity problem of a type with k lit sites (the
+// larger of the two): k + NEAR + FAR, or k + FAR + NEAR + the dummy
+__device__ __forceinline__ int max_vertices(int k) { return (k & 1) ? k + 3 : k + 2; }
 
 }  // namespace
 
-// Wave w solves problems w, w + waves, ... of the four (type = problem >> 1:
-// 0 plaquettes / x parts, 1 stars / z parts; parity = problem & 1).
-__global__ void __launch_bounds__(256) init_mwpm_kernel(const StartArgs a, int cap, int waves) {
+// Wave w solves anyon types w, w + waves (0 plaquettes / x parts, 1 stars /
+// z parts): parity 0 from the start, then parity 1 from parity 0's solution;
+// problem p = 2 type + parity paints plane p.  The small launch (big = 0) takes the syndromes whose problems fit `cap`
+// vertices, the big launch (big = 1) the others.
+__global__ void __launch_bounds__(128) init_mwpm_kernel(const StartArgs a, int cap, int waves,
+                                                        int small_cap, int big) {
   extern __shared__ __align__(16) uint8_t mw_lds[];
+  __shared__ int lit[2];
   const int64_t s = blockIdx.x;
   if (s >= a.n) return;
   const StartItem si = start_item(a, s);
   const int L = si.L;
+  const int nsite = L * (L - 1);
+  if (threadIdx.x < 2) lit[threadIdx.x] = 0;
+  __syncthreads();
+  int cs = 0, cp = 0;
+  for (int t = threadIdx.x; t < nsite; t += blockDim.x) {
+    cs += si.sy[t] != 0;
+    cp += si.sy[nsite + t] != 0;
+  }
+  if (cs) atomicAdd(&lit[1], cs);
+  if (cp) atomicAdd(&lit[0], cp);
+  __syncthreads();
+  const int need = max(max_vertices(lit[0]), max_vertices(lit[1]));
+  if ((need <= small_cap) == (big != 0)) return;  // the other launch takes it
   const int wave = threadIdx.x >> 6;
   const size_t region = mw::region_bytes(cap);
   uint32_t* planes = reinterpret_cast<uint32_t*>(mw_lds + waves * region);  // [4][ROWS]
@@ -92,11 +120,15 @@ __global__ void __launch_bounds__(256) init_mwpm_kernel(const StartArgs a, int c
     mw::Solver<Wave64> m;
     m.wv.lane = threadIdx.x & 63;
     m.carve(mw_lds + wave * region, cap);
-    for (int p = wave; p < 4; p += waves) {
-      m.load(si.sy, L, (p >> 1) != 0, p & 1);
+    for (int t = wave; t < 2; t += waves) {
+      m.load(si.sy, L, t != 0, 0);
       m.solve();
       m.wv.sync();
-      m.paint(planes + p * mw::ROWS, p & 1);
+      m.paint(planes + (2 * t) * mw::ROWS, 0);
+      m.wv.sync();
+      m.solve_other_parity(si.sy);
+      m.wv.sync();
+      m.paint(planes + (2 * t + 1) * mw::ROWS, 1);
       m.wv.sync();
     }
   }
@@ -138,16 +170,22 @@ hipError_t launch_init_mwpm(const StartArgs& a, hipStream_t s) {
   if (a.n == 0) return hipSuccess;
   const int L = a.items ? a.max_L : a.L;
   if (L < MCMC_L_MIN || L > MCMC_L_MAX) return hipErrorInvalidValue;
-  const int cap = mw::capacity(L);
-  const int waves = mwpm_waves(L);
-  const size_t lds = mwpm_lds(L);
-  if (lds > 64 * 1024) {
-    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(init_mwpm_kernel),
-                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  const int full = mw::capacity(L), small = mwpm_small_capacity(L);
+  for (int big = 0; big <= (full > small ? 1 : 0); ++big) {
+    const int cap = big ? full : small;
+    const size_t lds = mwpm_lds(cap);
+    if (lds > 64 * 1024) {
+      const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(init_mwpm_kernel),
+                                               hipFuncAttributeMaxDynamicSharedMemorySize,
+                                               (int)lds);
+      if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(init_mwpm_kernel, dim3((unsigned)a.n), dim3(128), lds, s, a, cap,
+                       mwpm_waves(cap), small, big);
+    const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(init_mwpm_kernel, dim3((unsigned)a.n), dim3(256), lds, s, a, cap, waves);
-  return hipGetLastError();
+  return hipSuccess;
 }
 
 }  // namespace mcmc

@@ -14,35 +14,49 @@
 //   xor_word(p, v)         *p ^= v (atomically across lanes)
 //
 // Problem (one anyon type, one line parity): vertices 0..nv-1 are the lit
-// sites in ascending site order (nid = site index, crd = i << 8 | j), then
-// NEAR (id 4094) if the parity is odd, then FAR (id 4095) if the number of
-// lit sites plus the parity is odd.  Matching weight of a pair:
-// W = d 2^53 + 2 t with d the shortest-path distance
+// sites in ascending site order (crd = i << 8 | j), then NEAR (crd 0xff00) if
+// the parity is odd, then FAR (crd 0xff01) if the number of lit sites plus
+// the parity is odd.  Matching weight of a pair (twice the d 2^53 + 2 t of
+// the plain definition, which orders matchings the same way):
+// W = d 2^54 + 4 t with d the shortest-path distance
 //   d(a, a') = min(|di| + |dj|, near(a) + near(a'), far(a) + far(a')),
 //   d(a, NEAR) = near(a), d(a, FAR) = far(a), d(NEAR, FAR) = L,
 // near/far = j+1 / L-1-j (plaquettes), i+1 / L-1-i (stars), and t the top 43
-// bits of splitmix64 (Steele, Lea, Flood, OOPSLA 2014) at state
-// (min(id) << 12) | max(id).
+// bits of the 64-bit product K(a) K(a') of the ends' keys, K = splitmix64
+// (Steele, Lea, Flood, OOPSLA 2014) at the site index (NEAR 4094, FAR 4095).
 //
 // Solver: Edmonds' primal-dual blossom algorithm for a minimum-weight perfect
 // matching (dual bookkeeping as in Galil, ACM Computing Surveys 1986).  Node
-// ids: vertices 0..cap-1, blossoms cap..2cap-1.  Dual feasibility:
+// ids: vertices 0..cap-1, blossoms cap..cap+cap/2-1 (a laminar family of odd
+// sets of at least 3 of nv vertices has fewer than nv/2 members).  Dual feasibility:
 // slack(i, j) = W_ij - u_i - u_j + sum of z_B over blossoms holding both >= 0;
-// between different outermost blossoms only the u terms remain.  All W are
-// even and all u start at 0, so every dual change is an integer.  Each stage
-// labels the outermost nodes with an exposed base S and grows alternating
-// trees until an augmenting path joins two of them; every vertex keeps its
-// least-slack edge (best, bestS) to an S vertex outside its own outermost
-// node, and each step takes the smallest of: a free vertex's best, half an S
-// vertex's best, half the dual of an outermost T blossom.
+// between different outermost blossoms only the u terms remain.  Start: u_v
+// = half the lightest pair at v (even, as every W is a multiple of 4) and the
+// mutual nearest neighbours matched (their pairs are tight).  Every exposed
+// vertex roots an alternating tree (S at even depth, T at odd).  All roots
+// take every dual change, and tight edges join equal parities, so all S
+// vertices share one parity and every dual change is an integer.  Every
+// vertex keeps its least-slack edge (best, bestS) to an S vertex outside its
+// own outermost node; each step takes the smallest of a free vertex's best,
+// half an S vertex's best and half the dual of an outermost T blossom, and
+// either acts on the tight edge or blossom it names (grow, shrink, augment,
+// expand) or changes the duals by it.  After an augmentation only the two
+// trees it joined dissolve; the others keep growing.
 #pragma once
 
 #include <stdint.h>
 
+#ifndef MW_COUNT
+#define MW_COUNT(what) ((void)0)
+#endif
+
 namespace mcmc {
 namespace mw {
 
-constexpr uint16_t NEAR = 4094, FAR = 4095;
+constexpr uint16_t NEAR_ID = 4094, FAR_ID = 4095;
+constexpr uint16_t CRD_NEAR = 0xff00, CRD_FAR = 0xff01, CRD_DUMMY = 0xff02;
+// weight of the dummy vertex's pairs other than the one with FAR: never tight
+constexpr int64_t W_NEVER = (int64_t)1 << 61;
 constexpr int64_t INF = (int64_t)1 << 62;
 constexpr int16_t FREE = 0, S = 1, T = 2;
 constexpr int ROWS = 2 * MCMC_L_MAX - 1;
@@ -58,53 +72,48 @@ MW_FN uint64_t splitmix64(uint64_t state) {
 // regions below keep 8-byte alignment)
 MW_HD int capacity(int L) { return ((L * (L - 1) + 2) + 3) & ~3; }
 
-// bytes of one problem's state
+// bytes of one problem's state (nodes: nn = cap + cap / 2)
 MW_HD size_t region_bytes(int cap) {
-  // int64: u, best [cap], z [cap] (blossom b at z[b - cap])
-  // int16: nid, crd, mate, top, bestS, freel, list [cap]
-  //        par, lab, tS, tT, base, bfirst, cnext, cprev, cex, cey, mark [2 cap]
-  //        stack [4 cap] ((node, vertex) pairs)
-  return (size_t)cap * (3 * 8 + 7 * 2 + 11 * 2 * 2 + 4 * 2);
+  // int64: u, best, key [cap], z [cap/2] (blossom b at z[b - cap])
+  // int16: crd, mate, top, bestS, list [cap], freel [cap/2]
+  //        par, lab, tS, tT, base, bfirst, cnext, cprev, cex, cey, mark [nn]
+  //        stack [2 nn] ((node, vertex) pairs)
+  return (size_t)cap * 78;
 }
 
 template <class WV>
 struct Solver {
   WV wv;
   int64_t *u, *best, *z;
-  uint16_t *nid, *crd;
+  uint64_t* key;
+  uint16_t* crd;
   int16_t *mate, *top, *bestS, *freel, *list;
   int16_t *par, *lab, *tS, *tT, *base, *bfirst, *cnext, *cprev, *cex, *cey, *mark;
   int16_t* stk;
-  int nv, cap, L, nfree, k_lit;
+  int nv, cap, nn, L, nfree, k_lit;
   bool star, fail;
 
   MW_FN void carve(uint8_t* r, int cap_) {
     cap = cap_;
+    nn = cap + cap / 2;
     int64_t* p64 = reinterpret_cast<int64_t*>(r);
     u = p64;
     best = p64 + cap;
-    z = p64 + 2 * cap;
-    int16_t* p16 = reinterpret_cast<int16_t*>(p64 + 3 * cap);
-    nid = reinterpret_cast<uint16_t*>(p16); p16 += cap;
+    key = reinterpret_cast<uint64_t*>(p64 + 2 * cap);
+    z = p64 + 3 * cap;
+    int16_t* p16 = reinterpret_cast<int16_t*>(p64 + 3 * cap + cap / 2);
     crd = reinterpret_cast<uint16_t*>(p16); p16 += cap;
     mate = p16; p16 += cap;
     top = p16; p16 += cap;
     bestS = p16; p16 += cap;
-    freel = p16; p16 += cap;
     list = p16; p16 += cap;
-    par = p16; p16 += 2 * cap;
-    lab = p16; p16 += 2 * cap;
-    tS = p16; p16 += 2 * cap;
-    tT = p16; p16 += 2 * cap;
-    base = p16; p16 += 2 * cap;
-    bfirst = p16; p16 += 2 * cap;
-    cnext = p16; p16 += 2 * cap;
-    cprev = p16; p16 += 2 * cap;
-    cex = p16; p16 += 2 * cap;
-    cey = p16; p16 += 2 * cap;
-    mark = p16; p16 += 2 * cap;
+    freel = p16; p16 += cap / 2;
+    int16_t** node[11] = {&par, &lab, &tS, &tT, &base, &bfirst, &cnext, &cprev, &cex, &cey,
+                          &mark};
+    for (int k = 0; k < 11; ++k) { *node[k] = p16; p16 += nn; }
     stk = p16;
   }
+  MW_FN bool is_boundary(int v) const { return crd[v] >= CRD_NEAR; }
 
   // ---------------------------------------------------------------- weights
   MW_FN void near_far(int v, int& nr, int& fr) const {
@@ -112,8 +121,8 @@ struct Solver {
     if (star) { nr = i + 1; fr = L - 1 - i; } else { nr = j + 1; fr = L - 1 - j; }
   }
   MW_FN int dist(int a, int b) const {
-    const int ia = nid[a], ib = nid[b];
-    if (ia < NEAR && ib < NEAR) {
+    const bool ba = is_boundary(a), bb = is_boundary(b);
+    if (!ba && !bb) {
       int na, fa, nb, fb;
       near_far(a, na, fa);
       near_far(b, nb, fb);
@@ -122,17 +131,20 @@ struct Solver {
       const int via = na + nb < fa + fb ? na + nb : fa + fb;
       return man < via ? man : via;
     }
-    if (ia < NEAR) { int na, fa; near_far(a, na, fa); return ib == NEAR ? na : fa; }
-    if (ib < NEAR) { int nb, fb; near_far(b, nb, fb); return ia == NEAR ? nb : fb; }
+    if (!ba) { int na, fa; near_far(a, na, fa); return crd[b] == CRD_NEAR ? na : fa; }
+    if (!bb) { int nb, fb; near_far(b, nb, fb); return crd[a] == CRD_NEAR ? nb : fb; }
     return L;
   }
   MW_FN int64_t weight(int a, int b) const {
-    const uint32_t ia = nid[a], ib = nid[b];
-    const uint32_t lo = ia < ib ? ia : ib, hi = ia < ib ? ib : ia;
-    const uint64_t t = splitmix64(((uint64_t)lo << 12) | hi) >> 21;
-    return ((int64_t)dist(a, b) << 53) + 2 * (int64_t)t;
+    if ((crd[a] | crd[b]) >= CRD_DUMMY && (crd[a] == CRD_DUMMY || crd[b] == CRD_DUMMY))
+      return (crd[a] == CRD_FAR || crd[b] == CRD_FAR) ? 0 : W_NEVER;
+    const uint64_t t = (key[a] * key[b]) >> 21;
+    return ((int64_t)dist(a, b) << 54) + 4 * (int64_t)t;
   }
-  MW_FN int64_t slack(int a, int b) const { return weight(a, b) - u[a] - u[b]; }
+  MW_FN int64_t slack(int a, int b) const {
+    MW_COUNT(slack);
+    return weight(a, b) - u[a] - u[b];
+  }
 
   // ---------------------------------------------------------------- structure
   // the child of node B that holds vertex v
@@ -183,6 +195,7 @@ struct Solver {
   // vertices outside its outermost node, and offer x to every vertex outside
   // that node.
   MW_FN void refresh(int cnt) {
+    for (int k = 0; k < cnt; ++k) MW_COUNT(refresh_vertex);
     for (int k = 0; k < cnt; ++k) {
       const int x = list[k];
       const int tx = top[x];
@@ -217,7 +230,7 @@ struct Solver {
       const int c = child_of(Bn, vv);
       const int first = bfirst[Bn];
       const int k = cycle_index(Bn, c);
-      if (fail || sp + 1 > 2 * cap) { fail = true; return; }
+      if (fail || sp + 1 > nn) { fail = true; return; }
       stk[2 * sp] = (int16_t)c;
       stk[2 * sp + 1] = (int16_t)vv;
       ++sp;
@@ -225,7 +238,7 @@ struct Solver {
         const bool fwd = (k & 1) != 0;
         int pos = c;
         for (int steps = 0; pos != first; ++steps) {
-          if (steps > cap || sp + 2 > 2 * cap) { fail = true; return; }
+          if (steps > cap || sp + 2 > nn) { fail = true; return; }
           const int a = fwd ? cnext[pos] : cprev[pos];
           const int b = fwd ? cnext[a] : cprev[a];
           int x, y;  // x in a, y in b
@@ -364,32 +377,13 @@ struct Solver {
   }
 
   // ---------------------------------------------------------------- solve
-  MW_FN void solve() {
-    for (int x = wv.lane; x < 2 * cap; x += WV::N) {
-      par[x] = -1;
-      lab[x] = FREE;
-      mark[x] = 0;
-      bfirst[x] = -1;
-      base[x] = (int16_t)(x < cap ? x : -1);
-      tS[x] = tT[x] = cnext[x] = cprev[x] = cex[x] = cey[x] = 0;  // always valid indices
-    }
-    for (int v = wv.lane; v < cap; v += WV::N) {
-      mate[v] = -1;
-      top[v] = (int16_t)v;
-      u[v] = 0;
-      z[v] = 0;
-      freel[v] = (int16_t)(2 * cap - 1 - v);
-    }
-    nfree = cap;
-    wv.sync();
-    int matched = 0;
-    for (int stage = 0; stage <= nv / 2 && matched < nv && !fail; ++stage) {
-      for (int x = wv.lane; x < 2 * cap; x += WV::N) lab[x] = FREE;
-      wv.sync();
-      for (int v = wv.lane; v < nv; v += WV::N)
-        if (mate[v] < 0) lab[top[v]] = S;
-      wv.sync();
-      for (int y = wv.lane; y < nv; y += WV::N) {
+  // best / bestS of every vertex in list[0..cnt): its least slack to an S
+  // vertex outside its outermost node
+  MW_FN void recompute(int cnt) {
+    for (int k = 0; k < cnt; ++k) MW_COUNT(recompute_vertex);
+    if (cnt >= WV::N / 4) {  // many: one vertex per lane
+      for (int k = wv.lane; k < cnt; k += WV::N) {
+        const int y = list[k];
         const int ty = top[y];
         int64_t b = INF;
         int bs = -1;
@@ -403,88 +397,263 @@ struct Solver {
         bestS[y] = (int16_t)bs;
       }
       wv.sync();
-      bool augmented = false;
-      const int ev_max = 8 * nv + 64;
-      for (int ev = 0; !augmented && !fail; ++ev) {
-        if (ev > ev_max) { fail = true; break; }
-        int64_t key = INF;
-        int idx = 0x7fff;
-        bool odd = false;
-        for (int j = wv.lane; j < nv; j += WV::N) {
-          const int16_t l = lab[top[j]];
-          const int64_t b = best[j];
-          if (b >= INF || l == T) continue;
-          int64_t kk = b;
-          if (l == S) {
-            odd |= (b & 1) != 0;  // the slack between two S vertices is even
-            kk = b >> 1;
-          }
-          if (kk < key || (kk == key && j < idx)) { key = kk; idx = j; }
+      return;
+    }
+    for (int k = 0; k < cnt; ++k) {  // few: one vertex at a time across the lanes
+      const int y = list[k];
+      const int ty = top[y];
+      int64_t b = INF;
+      int bs = 0x7fff;
+      for (int x = wv.lane; x < nv; x += WV::N) {
+        const int tx = top[x];
+        if (tx == ty || lab[tx] != S) continue;
+        const int64_t sl = slack(x, y);
+        if (sl < b) { b = sl; bs = x; }
+      }
+      wv.argmin(b, bs);
+      wv.sync();
+      best[y] = b;
+      bestS[y] = (int16_t)(b < INF ? bs : -1);
+      wv.sync();
+    }
+  }
+
+  // root of the tree holding outermost node x (S or T)
+  MW_FN int root_of(int x) const {
+    for (int g = 0; g < 2 * cap; ++g) {
+      if (lab[x] == T) {
+        x = top[tS[x]];
+      } else {
+        const int p = s_parent(x);
+        if (p < 0) return x;
+        x = p;
+      }
+    }
+    return -1;
+  }
+
+  MW_FN void solve() {
+    for (int x = wv.lane; x < nn; x += WV::N) {
+      par[x] = -1;
+      lab[x] = FREE;
+      mark[x] = 0;
+      bfirst[x] = -1;
+      base[x] = (int16_t)(x < cap ? x : -1);
+      tS[x] = tT[x] = cnext[x] = cprev[x] = cex[x] = cey[x] = 0;  // always valid indices
+    }
+    for (int v = wv.lane; v < cap; v += WV::N) {
+      mate[v] = -1;
+      top[v] = (int16_t)v;
+    }
+    for (int k = wv.lane; k < cap / 2; k += WV::N) {
+      z[k] = 0;
+      freel[k] = (int16_t)(nn - 1 - k);
+    }
+    nfree = cap / 2;
+    wv.sync();
+    // start: u_v = half the lightest pair at v (W is a multiple of 4, so every
+    // u is even and every S vertex keeps the parity of the roots); mutual
+    // nearest neighbours are tight and matched
+    for (int v = wv.lane; v < nv; v += WV::N) {
+      int64_t b = INF;
+      int bs = -1;
+      for (int x = 0; x < nv; ++x) {
+        if (x == v) continue;
+        const int64_t w = weight(x, v);
+        if (w < b) { b = w; bs = x; }
+      }
+      u[v] = b >> 1;
+      bestS[v] = (int16_t)bs;
+    }
+    wv.sync();
+    int matched = 0;
+    for (int v0 = 0; v0 < nv; v0 += WV::N) {
+      const int v = v0 + wv.lane;
+      bool pair = false;
+      if (v < nv) {
+        const int w = bestS[v];
+        pair = w > v && bestS[w] == v;
+        if (pair) { mate[v] = (int16_t)w; mate[w] = (int16_t)v; }
+      }
+      int dummy = 0;
+      wv.compact(pair, dummy);
+      matched += 2 * dummy;
+    }
+    wv.sync();
+    for (int v = wv.lane; v < nv; v += WV::N)
+      if (mate[v] < 0) lab[v] = S;
+    wv.sync();
+    {
+      const int cnt = collect([&](int y) { (void)y; return true; });
+      recompute(cnt);
+    }
+    run(matched);
+  }
+
+  // The other parity of the type just solved, from its solution: the
+  // structure (matching, blossoms, duals) stays and two exposed vertices join.
+  // With an even number k of lit sites the solved problem had no boundary
+  // vertex and NEAR and FAR join.  With k odd it had FAR; NEAR joins with a
+  // dummy vertex whose only pair is with FAR (weight 0), so that a perfect
+  // matching matches the dummy to FAR and the rest is a perfect matching of
+  // the lit sites and NEAR.  The new vertices' duals are the largest that keep
+  // every slack non-negative, with a common parity.
+  MW_FN void solve_other_parity(const uint8_t* sy) {
+    const int k = k_lit;
+    if (fail) { load(sy, L, star, 1); solve(); return; }
+    const bool odd = (k & 1) != 0;
+    const int va = odd ? k + 1 : k, vb = va + 1;  // the two new vertices
+    if (wv.lane == 0) {
+      crd[va] = CRD_NEAR; key[va] = splitmix64(NEAR_ID);
+      if (odd) { crd[vb] = CRD_DUMMY; key[vb] = 0; }
+      else { crd[vb] = CRD_FAR; key[vb] = splitmix64(FAR_ID); }
+    }
+    for (int v = va + wv.lane; v <= vb; v += WV::N) {
+      mate[v] = -1; top[v] = (int16_t)v; par[v] = -1; base[v] = (int16_t)v;
+      mark[v] = 0; bfirst[v] = -1;
+    }
+    const int matched = nv;
+    nv = vb + 1;
+    wv.sync();
+    int64_t ua = new_dual(va, vb, 0), ub = new_dual(vb, va, 0);
+    // the pair of the two new vertices: lower the larger dual until its slack
+    // is >= 0 (the amount is even)
+    const int64_t over = u_parity_floor(weight(va, vb) - ua - ub);
+    if (over < 0) { if (ua >= ub) ua += over; else ub += over; }
+    if (wv.lane == 0) { u[va] = ua; u[vb] = ub; }
+    wv.sync();
+    for (int x = wv.lane; x < nn; x += WV::N) lab[x] = FREE;
+    wv.sync();
+    for (int v = wv.lane; v < nv; v += WV::N)
+      if (mate[v] < 0) lab[top[v]] = S;
+    wv.sync();
+    const int cnt = collect([&](int y) { (void)y; return true; });
+    recompute(cnt);
+    run(matched);
+  }
+
+  // the largest even number <= x (two's complement)
+  MW_FN static int64_t u_parity_floor(int64_t x) { return x - (x & 1); }
+
+  // dual of new vertex v: min over the old vertices w (not v, not `skip`) of
+  // W(v, w) - u_w, rounded down to parity `par`
+  MW_FN int64_t new_dual(int v, int skip, int64_t par_) {
+    int64_t b = INF;
+    int bi = 0;
+    for (int w = wv.lane; w < nv; w += WV::N) {
+      if (w == v || w == skip) continue;
+      const int64_t d = weight(v, w) - u[w];
+      if (d < b) b = d;
+    }
+    wv.argmin(b, bi);
+    const int64_t down = u_parity_floor(b - par_) + par_;
+    return down;
+  }
+
+  // the event loop, from `matched` matched vertices and a labelled forest
+  MW_FN void run(int matched) {
+    const int ev_max = 16 * nv * (nv / 2 + 2) + 64;
+    for (int ev = 0; matched < nv && !fail; ++ev) {
+      if (ev > ev_max) { fail = true; break; }
+      MW_COUNT(event);
+      int64_t key = INF;
+      int idx = 0x7fff;
+      bool odd = false;
+      for (int j = wv.lane; j < nv; j += WV::N) {
+        const int16_t l = lab[top[j]];
+        const int64_t b = best[j];
+        if (b >= INF || l == T) continue;
+        int64_t kk = b;
+        if (l == S) {
+          odd |= (b & 1) != 0;  // the slack between two S vertices is even
+          kk = b >> 1;
         }
-        wv.argmin(key, idx);
-        int64_t bkey = INF;
-        int bidx = 0x7fff;
-        for (int b = cap + wv.lane; b < 2 * cap; b += WV::N) {
+        if (kk < key || (kk == key && j < idx)) { key = kk; idx = j; }
+      }
+      if (nfree < cap / 2) {  // half the dual of an outermost T blossom (index >= cap)
+        for (int b = cap + wv.lane; b < nn; b += WV::N) {
           if (base[b] < 0 || par[b] >= 0 || lab[b] != T) continue;
           const int64_t kk = z[b - cap] >> 1;
-          if (kk < bkey || (kk == bkey && b < bidx)) { bkey = kk; bidx = b; }
+          if (kk < key || (kk == key && b < idx)) { key = kk; idx = b; }
         }
-        wv.argmin(bkey, bidx);
-        if (wv.any(odd)) { fail = true; break; }
-        if (key == 0) {
-          const int j = idx, i = bestS[j];
-          if (i < 0) { fail = true; break; }
-          const int Bj = top[j];
-          if (lab[Bj] == FREE) {  // grow: Bj becomes T, its mate's node S
-            const int mb = mate[base[Bj]];
-            if (mb < 0) { fail = true; break; }
-            lab[Bj] = T;
-            tS[Bj] = (int16_t)i;
-            tT[Bj] = (int16_t)j;
-            const int Bm = top[mb];
-            lab[Bm] = S;
-            wv.sync();
-            const int cnt = collect([&](int y) { return top[y] == Bm; });
-            refresh(cnt);
-          } else {
-            int ri = top[i], rj = Bj, g = 0;
-            for (int x = s_parent(ri); x >= 0 && g <= cap; x = s_parent(x), ++g) ri = x;
-            g = 0;
-            for (int x = s_parent(rj); x >= 0 && g <= cap; x = s_parent(x), ++g) rj = x;
-            if (ri != rj) {
-              augment_path(i, j);
-              augment_path(j, i);
-              matched += 2;
-              augmented = true;
-              wv.sync();
-            } else {
-              shrink(i, j);
-            }
-          }
-        } else if (bkey == 0) {
-          expand_t(bidx);
+      }
+      wv.argmin(key, idx);
+      if (wv.any(odd)) { fail = true; break; }
+      if (key == 0 && idx >= cap) {
+        MW_COUNT(expand);
+        expand_t(idx);
+      } else if (key == 0) {
+        const int j = idx, i = bestS[j];
+        if (i < 0) { fail = true; break; }
+        const int Bj = top[j];
+        if (lab[Bj] == FREE) {  // grow: Bj becomes T, its mate's node S
+          MW_COUNT(grow);
+          const int mb = mate[base[Bj]];
+          if (mb < 0) { fail = true; break; }
+          lab[Bj] = T;
+          tS[Bj] = (int16_t)i;
+          tT[Bj] = (int16_t)j;
+          const int Bm = top[mb];
+          lab[Bm] = S;
+          wv.sync();
+          const int cnt = collect([&](int y) { return top[y] == Bm; });
+          refresh(cnt);
         } else {
-          const int64_t delta = key < bkey ? key : bkey;
-          if (delta >= INF) { fail = true; break; }
-          for (int v = wv.lane; v < nv; v += WV::N) {
-            const int16_t l = lab[top[v]];
-            const int64_t b = best[v];
-            if (l == S) {
-              u[v] += delta;
-              if (b < INF) best[v] = b - 2 * delta;
-            } else if (l == T) {
-              u[v] -= delta;
-            } else if (b < INF) {
-              best[v] = b - delta;
+          const int ri = root_of(top[i]), rj = root_of(Bj);
+          if (ri < 0 || rj < 0) { fail = true; break; }
+          if (ri != rj) {
+            MW_COUNT(augment);
+            // the two trees dissolve after the augmentation; the others stay
+            for (int x = wv.lane; x < nn; x += WV::N) {
+              if (par[x] >= 0 || lab[x] == FREE || (x >= cap && base[x] < 0) ||
+                  (x < cap && x >= nv))
+                continue;
+              const int r = root_of(x);
+              mark[x] = (int16_t)(r == ri || r == rj);
             }
+            wv.sync();
+            const int cnt = collect([&](int y) {
+              return mark[top[y]] != 0 || (bestS[y] >= 0 && mark[top[bestS[y]]] != 0);
+            });
+            augment_path(i, j);
+            augment_path(j, i);
+            matched += 2;
+            wv.sync();
+            for (int x = wv.lane; x < nn; x += WV::N) {
+              if (mark[x]) lab[x] = FREE;
+              mark[x] = 0;
+            }
+            wv.sync();
+            recompute(cnt);
+          } else {
+            MW_COUNT(shrink);
+            shrink(i, j);
           }
-          for (int b = cap + wv.lane; b < 2 * cap; b += WV::N) {
+        }
+      } else {
+        const int64_t delta = key;
+        if (delta >= INF) { fail = true; break; }
+        MW_COUNT(dual);
+        for (int v = wv.lane; v < nv; v += WV::N) {
+          const int16_t l = lab[top[v]];
+          const int64_t b = best[v];
+          if (l == S) {
+            u[v] += delta;
+            if (b < INF) best[v] = b - 2 * delta;
+          } else if (l == T) {
+            u[v] -= delta;
+          } else if (b < INF) {
+            best[v] = b - delta;
+          }
+        }
+        if (nfree < cap / 2) {
+          for (int b = cap + wv.lane; b < nn; b += WV::N) {
             if (base[b] < 0 || par[b] >= 0) continue;
             if (lab[b] == S) z[b - cap] += 2 * delta;
             else if (lab[b] == T) z[b - cap] -= 2 * delta;
           }
-          wv.sync();
         }
+        wv.sync();
       }
     }
     if (matched < nv) fail = true;
@@ -504,15 +673,15 @@ struct Solver {
       const bool lit = t < nsite && sy[first + t] != 0;
       const int slot = wv.compact(lit, k);
       if (lit) {
-        nid[slot] = (uint16_t)(first + t);
+        key[slot] = splitmix64((uint64_t)(first + t));
         crd[slot] = (uint16_t)(((t / nc) << 8) | (t % nc));
       }
     }
     k_lit = k;
     int n = k;
     if (wv.lane == 0) {
-      if (parity) { nid[n] = NEAR; crd[n] = 0; }
-      if ((k + parity) & 1) { nid[n + parity] = FAR; crd[n + parity] = 0; }
+      if (parity) { key[n] = splitmix64(NEAR_ID); crd[n] = CRD_NEAR; }
+      if ((k + parity) & 1) { key[n + parity] = splitmix64(FAR_ID); crd[n + parity] = CRD_FAR; }
     }
     n += parity + ((k + parity) & 1);
     nv = n;
@@ -549,9 +718,9 @@ struct Solver {
     }
     for (int a = wv.lane; a < nv; a += WV::N) {
       const int b = mate[a];
-      if (b < a) continue;
-      const int ida = nid[a], idb = nid[b];
-      if (ida < NEAR && idb < NEAR) {
+      if (b < a || crd[a] == CRD_DUMMY || crd[b] == CRD_DUMMY) continue;
+      const bool ba = is_boundary(a), bb = is_boundary(b);
+      if (!ba && !bb) {
         const int i1 = crd[a] >> 8, j1 = crd[a] & 255, i2 = crd[b] >> 8, j2 = crd[b] & 255;
         int na, fa, nb, fb;
         near_far(a, na, fa);
@@ -572,8 +741,8 @@ struct Solver {
           paint_side(pl, i1, j1, side);
           paint_side(pl, i2, j2, side);
         }
-      } else if (ida < NEAR) {
-        paint_side(pl, crd[a] >> 8, crd[a] & 255, idb == NEAR ? 0 : 1);
+      } else if (!ba) {
+        paint_side(pl, crd[a] >> 8, crd[a] & 255, crd[b] == CRD_NEAR ? 0 : 1);
       } else {
         paint_logical(pl);
       }

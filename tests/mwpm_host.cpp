@@ -4,7 +4,8 @@
 // sanitizers.
 //
 // stdin:  int32 L, int32 n, then n syndromes of n_stab bytes.
-// stdout: per syndrome and problem p = 0..3 (type p >> 1, parity p & 1):
+// stdout: per syndrome and problem p = 0..3 (type p >> 1, parity p & 1,
+//         solved as the kernel does: parity 1 from parity 0's solution):
 //         int32 failed, then 2L-1 uint32 bit rows of the part.
 #include <stddef.h>
 #include <stdint.h>
@@ -44,17 +45,20 @@ int main() {
   std::vector<uint8_t> syn(nstab);
   for (int s = 0; s < n; ++s) {
     if (fread(syn.data(), 1, nstab, stdin) != (size_t)nstab) return 3;
-    for (int p = 0; p < 4; ++p) {
+    for (int t = 0; t < 2; ++t) {  // as the kernel: parity 0, then parity 1 from it
       uint8_t* region = static_cast<uint8_t*>(malloc(mcmc::mw::region_bytes(cap)));
-      std::vector<uint32_t> plane(rows, 0u);
       mcmc::mw::Solver<Wave1> m;
       m.carve(region, cap);
-      m.load(syn.data(), L, (p >> 1) != 0, p & 1);
-      m.solve();
-      m.paint(plane.data(), p & 1);
-      const int32_t failed = m.fail ? 1 : 0;
-      fwrite(&failed, 4, 1, stdout);
-      fwrite(plane.data(), 4, rows, stdout);
+      m.load(syn.data(), L, t != 0, 0);
+      for (int parity = 0; parity < 2; ++parity) {
+        if (parity) m.solve_other_parity(syn.data());
+        else m.solve();
+        std::vector<uint32_t> plane(rows, 0u);
+        m.paint(plane.data(), parity);
+        const int32_t failed = m.fail ? 1 : 0;
+        fwrite(&failed, 4, 1, stdout);
+        fwrite(plane.data(), 4, rows, stdout);
+      }
       free(region);
     }
   }
