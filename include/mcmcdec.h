@@ -215,6 +215,27 @@ int mcmc_decode_batch(const uint8_t* d_syndromes, const uint32_t* d_syndrome_ids
                       uint8_t* d_correction, void* d_chain_state, int16_t* d_trace,
                       void* d_workspace, size_t workspace_bytes, void* stream);
 
+/*
+ * mcmc_decode_batch for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * Same arguments, results and errors as mcmc_decode_batch, without the
+ * workspace: the decode's scratch (mcmc_workspace_size bytes) lives in a
+ * buffer of MCMC_NOALLOC_SCRATCH_BYTES inside the library, one per device,
+ * reserved when the library's code is loaded on that device and held until the
+ * process ends; nothing is allocated per call.  A decode needing more than
+ * that (at L = 13 with 4 x 4 chains, more than about 59000 syndromes) returns
+ * MCMC_EWORKSPACE before anything is enqueued.  Every call on a device shares
+ * that device's buffer and keeps nothing in it between calls: calls ordered on
+ * one stream are safe, calls that overlap on one device (other streams, other
+ * host threads) race and corrupt each other's results.
+ */
+#define MCMC_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int mcmc_decode_batch_noalloc(const uint8_t* d_syndromes, const uint32_t* d_syndrome_ids,
+                              int64_t n, const mcmc_params* h_prm, double* d_class_prob,
+                              double* d_mean_n, int64_t* d_sum_n, int64_t* d_accepts,
+                              uint8_t* d_chosen, uint8_t* d_correction, void* d_chain_state,
+                              int16_t* d_trace, void* stream);
+
 /* The four class starting configurations (Sec. IV: one chain start per
  * class, consistent with the syndrome) of n syndromes: d_reps [n][4][n_q]
  * uint8, row k of class k; `init` is MCMC_INIT_CANONICAL, MCMC_INIT_MATCHING

@@ -123,6 +123,8 @@ _SIGNATURES = {
     "mcmc_chain_state_size": (ctypes.c_int, [_PPRM, _I64, _PSZ]),
     "mcmc_decode_batch": (ctypes.c_int, [_P, _P, _I64, _PPRM, _P, _P, _P, _P, _P, _P, _P, _P,
                                          _P, _SZ, _P]),
+    "mcmc_decode_batch_noalloc": (ctypes.c_int, [_P, _P, _I64, _PPRM, _P, _P, _P, _P, _P, _P,
+                                                 _P, _P, _P]),
     "mcmc_init_representatives": (ctypes.c_int, [_I32, _U32, _P, _I64, _P, _P]),
     "mcmc_unpack_chain_state": (ctypes.c_int, [_PPRM, _I64, _P, _P, _P, _P]),
     "mcmc_sample_errors": (ctypes.c_int, [_I32, _D, _U64, _P, _U32, _I64, _P, _P, _P, _P]),

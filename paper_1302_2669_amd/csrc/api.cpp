@@ -11,6 +11,7 @@
 #include "internal.h"
 
 #include <algorithm>
+#include <mutex>
 
 namespace mcmc {
 
@@ -63,6 +64,34 @@ hipError_t launch_chains(int range, const RunArgs& a, int waves, int wg, hipStre
 }
 
 }  // namespace mcmc
+
+// Scratch of mcmc_decode_batch_noalloc: one copy on every device the library
+// runs on, held until the process ends.  Host code uses only the per-device
+// address that hipGetSymbolAddress returns for it, never this name.
+static __device__ __align__(256) uint8_t scratch[MCMC_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+std::mutex g_scratch_mu;
+constexpr int kMaxDevices = 64;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// address of the current device's scratch; looked up once per device, with
+// that device current
+int scratch_on_current_device(void** out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return MCMC_EDEVICE;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return MCMC_EDEVICE;
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return MCMC_OK;
+}
+
+}  // namespace
 
 namespace {
 
@@ -333,6 +362,25 @@ int mcmc_decode_batch(const uint8_t* syndromes, const uint32_t* syndrome_ids, in
   d.chosen = chosen;
   d.correction = correction;
   return hip_status(launch_decide(d, s));
+}
+
+int mcmc_decode_batch_noalloc(const uint8_t* syndromes, const uint32_t* syndrome_ids, int64_t n,
+                              const mcmc_params* prm, double* class_prob, double* mean_n,
+                              int64_t* sum_n, int64_t* accepts, uint8_t* chosen,
+                              uint8_t* correction, void* chain_state, int16_t* trace,
+                              void* stream) {
+  const int st = check_params(prm, n);
+  if (st != MCMC_OK) return st;
+  if (n == 0) return MCMC_OK;
+  if (workspace_layout(prm, n).bytes > MCMC_NOALLOC_SCRATCH_BYTES) return MCMC_EWORKSPACE;
+  void* ws = nullptr;
+  const int sst = scratch_on_current_device(&ws);
+  if (sst != MCMC_OK) return sst;
+  // the same kernels as mcmc_decode_batch, with the device's scratch as the
+  // workspace (its tile counter is zeroed by a kernel at the start of every call)
+  return mcmc_decode_batch(syndromes, syndrome_ids, n, prm, class_prob, mean_n, sum_n, accepts,
+                           chosen, correction, chain_state, trace, ws,
+                           MCMC_NOALLOC_SCRATCH_BYTES, stream);
 }
 
 int mcmc_init_representatives(int32_t L, uint32_t init, const uint8_t* syndromes, int64_t n,
