@@ -41,12 +41,40 @@ struct Wave64 {
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
+  MW_FN int uni(int x) const { return __builtin_amdgcn_readfirstlane(x); }
+  MW_FN int64_t uni64(int64_t x) const {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)x);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(x >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+  }
+  // one step of the (key, idx) minimum: combine with the value DPP control
+  // CTRL brings in (lanes it does not reach keep the identity)
+  template <int CTRL, int ROWS>
+  MW_FN static void min_step(uint32_t& lo, int& hi, int& id) {
+    const uint32_t lo2 = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)lo, CTRL, ROWS, 0xf, false);
+    const int hi2 = __builtin_amdgcn_update_dpp(0x40000000, hi, CTRL, ROWS, 0xf, false);
+    const int id2 = __builtin_amdgcn_update_dpp(0x7fff, id, CTRL, ROWS, 0xf, false);
+    const bool take = hi2 < hi || (hi2 == hi && (lo2 < lo || (lo2 == lo && id2 < id)));
+    if (take) { lo = lo2; hi = hi2; id = id2; }
+  }
+  // smallest (key, idx) over the wave: prefix minima within each row of 16
+  // lanes (row_shr 1, 2, 4, 8), then row 0's result into row 1 and row 2's
+  // into row 3 (row_bcast:15), then row 1's into rows 2 and 3
+  // (row_bcast:31); lane 63 holds the minimum.  Keys are below 2^62.
   MW_FN void argmin(int64_t& key, int& idx) const {
-    for (int o = 32; o > 0; o >>= 1) {
-      const int64_t k2 = __shfl_xor(key, o, 64);
-      const int i2 = __shfl_xor(idx, o, 64);
-      if (k2 < key || (k2 == key && i2 < idx)) { key = k2; idx = i2; }
-    }
+    uint32_t lo = (uint32_t)key;
+    int hi = (int)(key >> 32);
+    int id = idx;
+    min_step<0x111, 0xf>(lo, hi, id);
+    min_step<0x112, 0xf>(lo, hi, id);
+    min_step<0x114, 0xf>(lo, hi, id);
+    min_step<0x118, 0xf>(lo, hi, id);
+    min_step<0x142, 0xa>(lo, hi, id);
+    min_step<0x143, 0xc>(lo, hi, id);
+    lo = (uint32_t)__builtin_amdgcn_readlane((int)lo, 63);
+    hi = __builtin_amdgcn_readlane(hi, 63);
+    idx = __builtin_amdgcn_readlane(id, 63);
+    key = (int64_t)(((uint64_t)(uint32_t)hi << 32) | lo);
   }
   MW_FN bool any(bool p) const { return __ballot(p) != 0ull; }
   MW_FN int compact(bool take, int& count) const {

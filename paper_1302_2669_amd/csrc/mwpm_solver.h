@@ -12,6 +12,9 @@
 //   any(p)                 p in some lane
 //   compact(take, &count)  slot of this lane among the takers; count += takers
 //   xor_word(p, v)         *p ^= v (atomically across lanes)
+//   uni(x), uni64(x)       x, known to be the same in every lane (kept in
+//                          scalar registers, so that branches on it are
+//                          scalar)
 //
 // Problem (one anyon type, one line parity): vertices 0..nv-1 are the lit
 // sites in ascending site order (crd = i << 8 | j), then NEAR (crd 0xff00) if
@@ -114,6 +117,9 @@ struct Solver {
     stk = p16;
   }
   MW_FN bool is_boundary(int v) const { return crd[v] >= CRD_NEAR; }
+  // an element every lane reads at the same index, as a wave-uniform value
+  MW_FN int rd(const int16_t* a, int i) const { return wv.uni((int)a[i]); }
+  MW_FN int64_t rd(const int64_t* a, int i) const { return wv.uni64(a[i]); }
 
   // ---------------------------------------------------------------- weights
   MW_FN void near_far(int v, int& nr, int& fr) const {
@@ -150,28 +156,30 @@ struct Solver {
   // the child of node B that holds vertex v
   MW_FN int child_of(int B, int v) {
     int x = v;
-    for (int g = 0; g < 2 * cap && par[x] != B; ++g) {
-      if (par[x] < 0) break;
-      x = par[x];
+    for (int g = 0; g < 2 * cap; ++g) {
+      const int p = rd(par, x);
+      if (p == B) return x;
+      if (p < 0) break;
+      x = p;
     }
-    if (par[x] != B) fail = true;
+    fail = true;
     return x;
   }
   // the S node above S node B in its tree, -1 for a root
   MW_FN int s_parent(int B) const {
-    const int m = mate[base[B]];
+    const int m = rd(mate, rd(base, B));
     if (m < 0) return -1;
-    return top[tS[top[m]]];
+    return rd(top, rd(tS, rd(top, m)));
   }
   // (x in X, y in the tree parent of X)
   MW_FN void up_edge(int X, int& x, int& y) const {
-    if (lab[X] == S) { x = base[X]; y = mate[x]; }
-    else { x = tT[X]; y = tS[X]; }
+    if (rd(lab, X) == S) { x = rd(base, X); y = rd(mate, x); }
+    else { x = rd(tT, X); y = rd(tS, X); }
   }
   // index of child c along B's cycle from its base child
   MW_FN int cycle_index(int B, int c) {
     int k = 0;
-    for (int x = bfirst[B]; x != c; x = cnext[x]) {
+    for (int x = rd(bfirst, B); x != c; x = rd(cnext, x)) {
       if (++k > cap) { fail = true; return 0; }
     }
     return k;
@@ -197,8 +205,8 @@ struct Solver {
   MW_FN void refresh(int cnt) {
     for (int k = 0; k < cnt; ++k) MW_COUNT(refresh_vertex);
     for (int k = 0; k < cnt; ++k) {
-      const int x = list[k];
-      const int tx = top[x];
+      const int x = rd(list, k);
+      const int tx = rd(top, x);
       int64_t bk = INF;
       int bi = 0x7fff;
       for (int y = wv.lane; y < nv; y += WV::N) {
@@ -225,10 +233,10 @@ struct Solver {
     for (int guard = 0; sp > 0 && !fail; ++guard) {
       if (guard > 8 * cap) { fail = true; return; }
       --sp;
-      const int Bn = stk[2 * sp], vv = stk[2 * sp + 1];
+      const int Bn = rd(stk, 2 * sp), vv = rd(stk, 2 * sp + 1);
       if (Bn < cap) continue;  // a vertex is its own base
       const int c = child_of(Bn, vv);
-      const int first = bfirst[Bn];
+      const int first = rd(bfirst, Bn);
       const int k = cycle_index(Bn, c);
       if (fail || sp + 1 > nn) { fail = true; return; }
       stk[2 * sp] = (int16_t)c;
@@ -239,10 +247,10 @@ struct Solver {
         int pos = c;
         for (int steps = 0; pos != first; ++steps) {
           if (steps > cap || sp + 2 > nn) { fail = true; return; }
-          const int a = fwd ? cnext[pos] : cprev[pos];
-          const int b = fwd ? cnext[a] : cprev[a];
+          const int a = rd(fwd ? cnext : cprev, pos);
+          const int b = rd(fwd ? cnext : cprev, a);
           int x, y;  // x in a, y in b
-          if (fwd) { x = cex[a]; y = cey[a]; } else { x = cey[b]; y = cex[b]; }
+          if (fwd) { x = rd(cex, a); y = rd(cey, a); } else { x = rd(cey, b); y = rd(cex, b); }
           mate[x] = (int16_t)y;
           mate[y] = (int16_t)x;
           stk[2 * sp] = (int16_t)a; stk[2 * sp + 1] = (int16_t)x; ++sp;
@@ -258,13 +266,13 @@ struct Solver {
   // match v to w and flip the alternating path from v up to its tree's root
   MW_FN void augment_path(int v, int w) {
     for (int g = 0; g <= cap && !fail; ++g) {
-      const int B = top[v];
-      const int t0 = mate[base[B]];
+      const int B = rd(top, v);
+      const int t0 = rd(mate, rd(base, B));
       rotate(B, v);
       mate[v] = (int16_t)w;
       if (t0 < 0) return;
-      const int Tn = top[t0];
-      const int s = tS[Tn], t = tT[Tn];
+      const int Tn = rd(top, t0);
+      const int s = rd(tS, Tn), t = rd(tT, Tn);
       rotate(Tn, t);
       mate[t] = (int16_t)s;
       v = s;
@@ -275,21 +283,21 @@ struct Solver {
 
   // a new blossom from the tight edge (i, j) between two S nodes of one tree
   MW_FN void shrink(int i, int j) {
-    const int Bi = top[i], Bj = top[j];
+    const int Bi = rd(top, i), Bj = rd(top, j);
     int A = -1, g = 0;
     for (int x = Bi; x >= 0 && g <= cap; x = s_parent(x), ++g) mark[x] = 1;
     g = 0;
     for (int x = Bj; x >= 0 && g <= cap; x = s_parent(x), ++g)
-      if (mark[x]) { A = x; break; }
+      if (rd(mark, x)) { A = x; break; }
     g = 0;
     for (int x = Bi; x >= 0 && g <= cap; x = s_parent(x), ++g) mark[x] = 0;
     if (A < 0 || nfree <= 0) { fail = true; return; }
-    const int b = freel[--nfree];
+    const int b = rd(freel, --nfree);
     for (int X = Bi, gg = 0; X != A; ++gg) {  // going up from Bi: edge kept at X
       if (gg > 2 * cap) { fail = true; return; }
       int x, y;
       up_edge(X, x, y);
-      const int P = top[y];
+      const int P = rd(top, y);
       cnext[X] = (int16_t)P; cprev[P] = (int16_t)X;
       cex[X] = (int16_t)x; cey[X] = (int16_t)y;
       X = P;
@@ -298,7 +306,7 @@ struct Solver {
       if (gg > 2 * cap) { fail = true; return; }
       int x, y;
       up_edge(X, x, y);
-      const int P = top[y];
+      const int P = rd(top, y);
       cnext[P] = (int16_t)X; cprev[X] = (int16_t)P;
       cex[P] = (int16_t)y; cey[P] = (int16_t)x;
       X = P;
@@ -308,11 +316,11 @@ struct Solver {
     int c = A, gg = 0;
     do {
       par[c] = (int16_t)b;
-      c = cnext[c];
+      c = rd(cnext, c);
       if (++gg > 2 * cap) { fail = true; return; }
     } while (c != A);
     bfirst[b] = (int16_t)A;
-    base[b] = base[A];
+    base[b] = (int16_t)rd(base, A);
     z[b - cap] = 0;
     lab[b] = S;
     par[b] = -1;
@@ -328,16 +336,16 @@ struct Solver {
   // path from the child holding the label edge to the base child alternate
   // T, S, ..., T; the other children become free
   MW_FN void expand_t(int B) {
-    const int s = tS[B], t = tT[B];
+    const int s = rd(tS, B), t = rd(tT, B);
     const int c = child_of(B, t);
-    const int first = bfirst[B];
+    const int first = rd(bfirst, B);
     const int k = cycle_index(B, c);
     if (fail) return;
     int x = first, g = 0;
     do {
       par[x] = -1;
       lab[x] = FREE;
-      x = cnext[x];
+      x = rd(cnext, x);
       if (++g > 2 * cap) { fail = true; return; }
     } while (x != first);
     lab[c] = T; tS[c] = (int16_t)s; tT[c] = (int16_t)t;
@@ -345,10 +353,10 @@ struct Solver {
     int pos = c;
     for (g = 0; pos != first; ++g) {
       if (g > cap) { fail = true; return; }
-      const int a = fwd ? cnext[pos] : cprev[pos];
-      const int b = fwd ? cnext[a] : cprev[a];
+      const int a = rd(fwd ? cnext : cprev, pos);
+      const int b = rd(fwd ? cnext : cprev, a);
       int ex, ey;  // ex in a, ey in b
-      if (fwd) { ex = cex[a]; ey = cey[a]; } else { ex = cey[b]; ey = cex[b]; }
+      if (fwd) { ex = rd(cex, a); ey = rd(cey, a); } else { ex = rd(cey, b); ey = rd(cex, b); }
       lab[a] = S;
       mark[a] = 1;
       lab[b] = T; tS[b] = (int16_t)ex; tT[b] = (int16_t)ey;
@@ -370,7 +378,7 @@ struct Solver {
     g = 0;
     do {
       mark[x] = 0;
-      x = cnext[x];
+      x = rd(cnext, x);
     } while (x != first && ++g <= 2 * cap);
     wv.sync();
     refresh(cnt);
@@ -400,8 +408,8 @@ struct Solver {
       return;
     }
     for (int k = 0; k < cnt; ++k) {  // few: one vertex at a time across the lanes
-      const int y = list[k];
-      const int ty = top[y];
+      const int y = rd(list, k);
+      const int ty = rd(top, y);
       int64_t b = INF;
       int bs = 0x7fff;
       for (int x = wv.lane; x < nv; x += WV::N) {
@@ -418,11 +426,26 @@ struct Solver {
     }
   }
 
-  // root of the tree holding outermost node x (S or T)
-  MW_FN int root_of(int x) const {
+  // root of the tree holding outermost node x (S or T), for a different x in
+  // every lane (plain reads)
+  MW_FN int root_of_lane(int x) const {
     for (int g = 0; g < 2 * cap; ++g) {
       if (lab[x] == T) {
         x = top[tS[x]];
+      } else {
+        const int m = mate[base[x]];
+        if (m < 0) return x;
+        x = top[tS[top[m]]];
+      }
+    }
+    return -1;
+  }
+
+  // the same for one x shared by every lane
+  MW_FN int root_of(int x) const {
+    for (int g = 0; g < 2 * cap; ++g) {
+      if (rd(lab, x) == T) {
+        x = rd(top, rd(tS, x));
       } else {
         const int p = s_parent(x);
         if (p < 0) return x;
@@ -583,23 +606,23 @@ struct Solver {
         MW_COUNT(expand);
         expand_t(idx);
       } else if (key == 0) {
-        const int j = idx, i = bestS[j];
+        const int j = idx, i = rd(bestS, j);
         if (i < 0) { fail = true; break; }
-        const int Bj = top[j];
-        if (lab[Bj] == FREE) {  // grow: Bj becomes T, its mate's node S
+        const int Bj = rd(top, j);
+        if (rd(lab, Bj) == FREE) {  // grow: Bj becomes T, its mate's node S
           MW_COUNT(grow);
-          const int mb = mate[base[Bj]];
+          const int mb = rd(mate, rd(base, Bj));
           if (mb < 0) { fail = true; break; }
           lab[Bj] = T;
           tS[Bj] = (int16_t)i;
           tT[Bj] = (int16_t)j;
-          const int Bm = top[mb];
+          const int Bm = rd(top, mb);
           lab[Bm] = S;
           wv.sync();
           const int cnt = collect([&](int y) { return top[y] == Bm; });
           refresh(cnt);
         } else {
-          const int ri = root_of(top[i]), rj = root_of(Bj);
+          const int ri = root_of(rd(top, i)), rj = root_of(Bj);
           if (ri < 0 || rj < 0) { fail = true; break; }
           if (ri != rj) {
             MW_COUNT(augment);
@@ -608,7 +631,7 @@ struct Solver {
               if (par[x] >= 0 || lab[x] == FREE || (x >= cap && base[x] < 0) ||
                   (x < cap && x >= nv))
                 continue;
-              const int r = root_of(x);
+              const int r = root_of_lane(x);
               mark[x] = (int16_t)(r == ri || r == rj);
             }
             wv.sync();

@@ -32,6 +32,8 @@ struct Wave1 {
     return slot;
   }
   void xor_word(uint32_t* p, uint32_t v) const { *p ^= v; }
+  int uni(int x) const { return x; }
+  int64_t uni64(int64_t x) const { return x; }
 };
 
 int main() {
