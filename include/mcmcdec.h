@@ -466,6 +466,65 @@ int mcmc_cnn_step(int64_t n_params, int64_t step, float lr, float beta1, float b
                   float* d_params, const float* d_grads, float* d_m, float* d_v, void* stream);
 
 /*
+ * Initial parameters for distance L: He-normal weights (standard deviation
+ * sqrt(2 / fan-in), fan-in 27, 288, 288 and 32 L^2 for W1, W2, W3, Wh) and
+ * zero biases.  Weight i of the flat vector is
+ * sqrt(-2 ln((a + 1) 2^-32)) cos(2 pi b 2^-32) sqrt(2 / fan-in), computed in
+ * double and rounded to float, where (a, b) are words 2(i&1), 2(i&1)+1 of
+ * Philox4x32-10 at counter (i >> 1, 0, 0, 3<<30 | 3<<28 | 0xFE<<20), key =
+ * seed (Box-Muller).
+ */
+int mcmc_cnn_init(int32_t L, uint64_t seed, float* d_params, void* stream);
+
+/*
+ * Budget labels of the gate from three decisions of each syndrome (no
+ * sweep, short budget, full budget): d_budget[i] = 0 if d_zero[i] ==
+ * d_full[i], else 1 if d_short[i] == d_full[i], else 2.
+ */
+int mcmc_gate_budget_labels(int64_t n, const uint8_t* d_zero, const uint8_t* d_short,
+                            const uint8_t* d_full, int32_t* d_budget, void* stream);
+
+/*
+ * The keyed shuffle of training epoch `epoch`: d_perm [n] a permutation of
+ * 0..n-1.  With b the smallest even number >= 2 for which 2^b >= n and
+ * h = b/2, position i maps through a 4-round Feistel network on b bits
+ * ((l, r) -> (r, l xor F_k(r)), l the high h bits), F_k(r) = the low h bits
+ * of word 0 of Philox4x32-10 at counter (r, k, epoch, 3<<30 | 3<<28 | 0xFD<<20),
+ * key = seed, repeated (cycle walking) until the value is below n.
+ */
+int mcmc_cnn_permutation(int64_t n, uint64_t seed, uint32_t epoch, int32_t* d_perm,
+                         void* stream);
+
+/*
+ * One training epoch on the device: the samples (syndromes [n][n_stab],
+ * rates [n] fp32, class targets [n][4] fp32, budget labels [n] int32) are
+ * taken in the order of mcmc_cnn_permutation(n, seed, epoch) in mini-batches
+ * of `batch` (the last partial batch dropped); each batch runs
+ * mcmc_cnn_forward, mcmc_cnn_backward and one Adam step (mcmc_cnn_step) with
+ * step number *h_step + 1 and learning rate
+ * lr + (lr_final - lr) * *h_step / max(1, total_steps - 1), then *h_step is
+ * incremented.  d_loss_sum[0] receives the sum of the epoch's per-sample
+ * losses (added batch by batch in sample order).  The workspace holds the
+ * permutation, the gathered batch, logits, gradients and the network's own
+ * workspace (mcmc_cnn_train_workspace_size).
+ */
+typedef struct mcmc_train_config {
+  float lr, lr_final;     /* learning rate at the first and last step           */
+  float beta1, beta2, eps;
+  float budget_weight;    /* weight of the budget term of the loss              */
+  int64_t batch;          /* samples per step, 1..MCMC_CNN_BATCH_MAX             */
+  int64_t total_steps;    /* steps of the whole run (for the learning rate)      */
+  uint64_t seed;          /* key of the shuffle                                  */
+} mcmc_train_config;
+int mcmc_cnn_train_workspace_size(int32_t L, int64_t n, int64_t batch, size_t* h_bytes);
+int mcmc_cnn_train_epoch(int32_t L, int64_t n, const mcmc_train_config* h_cfg, uint32_t epoch,
+                         int64_t* h_step, float* d_params, float* d_m, float* d_v,
+                         const uint8_t* d_syndromes, const float* d_p,
+                         const float* d_class_target, const int32_t* d_budget,
+                         double* d_loss_sum, void* d_workspace, size_t workspace_bytes,
+                         void* stream);
+
+/*
  * Gate from logits [batch][8]: d_class = argmax of the class logits (ties to
  * the lowest); with q = softmax of the budget logits, d_confidence
  * [batch][2] = (q0, q0 + q1) (or NULL): the predicted probabilities that no

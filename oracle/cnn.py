@@ -167,3 +167,79 @@ def adam(params, grads, m, v, lr, beta1, beta2, eps, step):
         out_p[k] = params[k] - lr * mh / (np.sqrt(vh) + eps)
         out_m[k], out_v[k] = mm, vv
     return out_p, out_m, out_v
+
+
+# ---------------------------------------------------------------------------
+# Training support: initial parameters, budget labels, the epoch shuffle.
+# Philox4x32-10 with key = seed, fourth counter word 3<<30 | 3<<28 | field<<20
+# (field 0xFE: initial weights, 0xFD: shuffle).
+# ---------------------------------------------------------------------------
+def _ctr3(field):
+    return (3 << 30) | (3 << 28) | (field << 20)
+
+
+def he_init(L, seed):
+    """Initial parameters (float32 [param_count]): weight i of a block with
+    fan-in f is sqrt(-2 ln u1) cos(2 pi u2) sqrt(2/f) (Box-Muller), u1 =
+    (a + 1) / 2^32, u2 = b / 2^32, (a, b) = words 2(i&1), 2(i&1)+1 of Philox
+    at counter (i >> 1, 0, 0, ctr3(0xFE)); biases zero.  Blocks: W1 [32][9][3]
+    (f = 27), b1, W2 [32][9][32] (f = 288), b2, W3 (f = 288), b3,
+    Wh [7][32 L^2] (f = 32 L^2), bh."""
+    from . import philox
+    sizes = [(C * 9 * 3, 27), (C, 0), (C * 9 * C, 9 * C), (C, 0), (C * 9 * C, 9 * C), (C, 0),
+             (7 * L * L * C, L * L * C), (7, 0)]
+    total = sum(s for s, _ in sizes)
+    fan = np.zeros(total)
+    at = 0
+    for size, f in sizes:
+        fan[at:at + size] = f
+        at += size
+    i = np.arange(total, dtype=np.uint64)
+    k0, k1 = philox.seed_key(seed)
+    w = philox.philox4x32_10(i >> np.uint64(1), 0, 0, _ctr3(0xFE), k0, k1)
+    odd = (i & np.uint64(1)).astype(bool)
+    a = np.where(odd, w[2], w[0]).astype(np.float64)
+    b = np.where(odd, w[3], w[1]).astype(np.float64)
+    u1 = (a + 1.0) * 2.0 ** -32
+    u2 = b * 2.0 ** -32
+    z = np.sqrt(-2.0 * np.log(u1)) * np.cos(2.0 * np.pi * u2)
+    out = np.where(fan > 0, z * np.sqrt(2.0 / np.maximum(fan, 1)), 0.0)
+    return out.astype(np.float32)
+
+
+def budget_labels(d_zero, d_short, d_full):
+    """0 if the no-sweep decision is the full-budget one, else 1 if the short
+    budget's is, else 2."""
+    d_zero, d_short, d_full = (np.asarray(v) for v in (d_zero, d_short, d_full))
+    return np.where(d_zero == d_full, 0, np.where(d_short == d_full, 1, 2)).astype(np.int32)
+
+
+def epoch_permutation(n, seed, epoch):
+    """int64 [n]: position i -> a 4-round Feistel network on b bits (b the
+    smallest even number >= 2 with 2^b >= n, halves of h = b/2 bits,
+    (l, r) -> (r, l xor F_k(r)), F_k(r) = low h bits of Philox word 0 at
+    counter (r, k, epoch, ctr3(0xFD))), repeated until the value is below n."""
+    from . import philox
+    b = 2
+    while (1 << b) < n:
+        b += 2
+    h = b // 2
+    mask = (1 << h) - 1
+    k0, k1 = philox.seed_key(seed)
+
+    def f(k, r):
+        return int(philox.philox4x32_10(r, k, epoch, _ctr3(0xFD), k0, k1)[0]) & mask
+
+    def net(x):
+        left, right = x >> h, x & mask
+        for k in range(4):
+            left, right = right, left ^ f(k, right)
+        return (left << h) | right
+
+    out = np.zeros(n, dtype=np.int64)
+    for i in range(n):
+        y = net(i)
+        while y >= n:
+            y = net(y)
+        out[i] = y
+    return out

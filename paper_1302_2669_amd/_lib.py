@@ -105,6 +105,20 @@ class GateConfig(ctypes.Structure):
     ]
 
 
+class TrainConfig(ctypes.Structure):
+    _fields_ = [
+        ("lr", ctypes.c_float),
+        ("lr_final", ctypes.c_float),
+        ("beta1", ctypes.c_float),
+        ("beta2", ctypes.c_float),
+        ("eps", ctypes.c_float),
+        ("budget_weight", ctypes.c_float),
+        ("batch", ctypes.c_int64),
+        ("total_steps", ctypes.c_int64),
+        ("seed", ctypes.c_uint64),
+    ]
+
+
 _P = ctypes.c_void_p
 _I32, _I64, _U32, _U64, _D, _SZ = (ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32,
                                    ctypes.c_uint64, ctypes.c_double, ctypes.c_size_t)
@@ -153,6 +167,13 @@ _SIGNATURES = {
     "mcmc_cnn_step": (ctypes.c_int, [_I64, _I64, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                                      ctypes.c_float, _P, _P, _P, _P, _P]),
     "mcmc_cnn_gate": (ctypes.c_int, [_I64, _P, ctypes.c_float, _P, _P, _P, _P]),
+    "mcmc_cnn_init": (ctypes.c_int, [_I32, _U64, _P, _P]),
+    "mcmc_gate_budget_labels": (ctypes.c_int, [_I64, _P, _P, _P, _P, _P]),
+    "mcmc_cnn_permutation": (ctypes.c_int, [_I64, _U64, _U32, _P, _P]),
+    "mcmc_cnn_train_workspace_size": (ctypes.c_int, [_I32, _I64, _I64, _PSZ]),
+    "mcmc_cnn_train_epoch": (ctypes.c_int, [_I32, _I64, ctypes.POINTER(TrainConfig), _U32,
+                                            ctypes.POINTER(ctypes.c_int64), _P, _P, _P, _P, _P,
+                                            _P, _P, _P, _P, _SZ, _P]),
     "mcmc_gated_create": (ctypes.c_int, [ctypes.POINTER(GateConfig), ctypes.POINTER(_P)]),
     "mcmc_gated_destroy": (ctypes.c_int, [_P]),
     "mcmc_gated_workspace_size": (ctypes.c_int, [_P, _PSZ]),

@@ -112,6 +112,131 @@ int mcmc_cnn_step(int64_t n_params, int64_t step, float lr, float beta1, float b
                              (hipStream_t)stream));
 }
 
+int mcmc_cnn_init(int32_t L, uint64_t seed, float* d_params, void* stream) {
+  if (!valid_L(L)) return MCMC_ERANGE;
+  if (!d_params) return MCMC_EINVAL;
+  return hip_status(cnn_init_params(L, seed, d_params, (hipStream_t)stream));
+}
+
+int mcmc_gate_budget_labels(int64_t n, const uint8_t* d_zero, const uint8_t* d_short,
+                            const uint8_t* d_full, int32_t* d_budget, void* stream) {
+  if (n < 0) return MCMC_ERANGE;
+  if (n == 0) return MCMC_OK;
+  if (!d_zero || !d_short || !d_full || !d_budget) return MCMC_EINVAL;
+  return hip_status(gate_budget_labels(n, d_zero, d_short, d_full, d_budget,
+                                       (hipStream_t)stream));
+}
+
+int mcmc_cnn_permutation(int64_t n, uint64_t seed, uint32_t epoch, int32_t* d_perm,
+                         void* stream) {
+  if (!cnn_batch_ok(n)) return MCMC_ERANGE;
+  if (n == 0) return MCMC_OK;
+  if (!d_perm) return MCMC_EINVAL;
+  return hip_status(cnn_permutation(n, seed, epoch, d_perm, (hipStream_t)stream));
+}
+
+namespace {
+
+// Training workspace: the epoch's permutation, the gathered batch, logits,
+// gradients, per-sample losses, then the network's own workspace.
+struct TrainWorkspace {
+  size_t perm, syn, p, tgt, bud, logits, grads, loss, net, bytes;
+};
+
+TrainWorkspace train_workspace(int L, int64_t n, int64_t B) {
+  TrainWorkspace w{};
+  size_t off = 0;
+  const int ns = 2 * L * (L - 1);
+  w.perm = off;   off = align_up(off + (size_t)n * sizeof(int32_t));
+  w.syn = off;    off = align_up(off + (size_t)B * ns);
+  w.p = off;      off = align_up(off + (size_t)B * sizeof(float));
+  w.tgt = off;    off = align_up(off + (size_t)B * 4 * sizeof(float));
+  w.bud = off;    off = align_up(off + (size_t)B * sizeof(int32_t));
+  w.logits = off; off = align_up(off + (size_t)B * 8 * sizeof(float));
+  w.grads = off;  off = align_up(off + (size_t)cnn_offsets(L).total * sizeof(float));
+  w.loss = off;   off = align_up(off + (size_t)B * sizeof(float));
+  w.net = off;    off = align_up(off + cnn_workspace(L, B).bytes);
+  w.bytes = off;
+  return w;
+}
+
+bool train_config_ok(const mcmc_train_config* c) {
+  return c && c->batch >= 1 && c->batch <= MCMC_CNN_BATCH_MAX && c->total_steps >= 1 &&
+         c->lr >= 0.0f && c->lr_final >= 0.0f && isfinite(c->lr) && isfinite(c->lr_final) &&
+         c->beta1 >= 0.0f && c->beta1 < 1.0f && c->beta2 >= 0.0f && c->beta2 < 1.0f &&
+         c->eps > 0.0f && c->budget_weight >= 0.0f && isfinite(c->budget_weight);
+}
+
+}  // namespace
+
+int mcmc_cnn_train_workspace_size(int32_t L, int64_t n, int64_t batch, size_t* h_bytes) {
+  if (!valid_L(L) || !cnn_batch_ok(n) || batch < 1 || batch > MCMC_CNN_BATCH_MAX)
+    return MCMC_ERANGE;
+  if (!h_bytes) return MCMC_EINVAL;
+  *h_bytes = train_workspace(L, n, batch).bytes;
+  return MCMC_OK;
+}
+
+int mcmc_cnn_train_epoch(int32_t L, int64_t n, const mcmc_train_config* h_cfg, uint32_t epoch,
+                         int64_t* h_step, float* d_params, float* d_m, float* d_v,
+                         const uint8_t* d_syndromes, const float* d_p,
+                         const float* d_class_target, const int32_t* d_budget,
+                         double* d_loss_sum, void* d_workspace, size_t workspace_bytes,
+                         void* stream) {
+  if (!valid_L(L) || !cnn_batch_ok(n)) return MCMC_ERANGE;
+  if (!h_cfg || !h_step) return MCMC_EINVAL;
+  if (!train_config_ok(h_cfg) || *h_step < 0) return MCMC_ERANGE;
+  if (!d_params || !d_m || !d_v || !d_loss_sum) return MCMC_EINVAL;
+  if (n > 0 && (!d_syndromes || !d_p || !d_class_target || !d_budget)) return MCMC_EINVAL;
+  const int64_t B = h_cfg->batch;
+  const TrainWorkspace w = train_workspace(L, n, B);
+  int st = check_ws(d_workspace, workspace_bytes, w.bytes);
+  if (st != MCMC_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  char* ws = (char*)d_workspace;
+  int32_t* perm = (int32_t*)(ws + w.perm);
+  uint8_t* bsyn = (uint8_t*)(ws + w.syn);
+  float* bp = (float*)(ws + w.p);
+  float* btgt = (float*)(ws + w.tgt);
+  int32_t* bbud = (int32_t*)(ws + w.bud);
+  float* logits = (float*)(ws + w.logits);
+  float* grads = (float*)(ws + w.grads);
+  float* loss = (float*)(ws + w.loss);
+  char* net = ws + w.net;
+  const int ns = 2 * L * (L - 1);
+  const int64_t P = cnn_offsets(L).total;
+  st = hip_status(cnn_loss_sum(0, loss, d_loss_sum, true, s));
+  if (st != MCMC_OK) return st;
+  st = hip_status(cnn_permutation(n, h_cfg->seed, epoch, perm, s));
+  if (st != MCMC_OK) return st;
+  for (int64_t at = 0; at + B <= n; at += B) {
+    const int32_t* idx = perm + at;
+    st = hip_status(cnn_gather(B, ns, idx, d_syndromes, bsyn, s));
+    if (st == MCMC_OK) st = hip_status(cnn_gather(B, 4, idx, (const uint8_t*)d_p, (uint8_t*)bp, s));
+    if (st == MCMC_OK)
+      st = hip_status(cnn_gather(B, 16, idx, (const uint8_t*)d_class_target, (uint8_t*)btgt, s));
+    if (st == MCMC_OK)
+      st = hip_status(cnn_gather(B, 4, idx, (const uint8_t*)d_budget, (uint8_t*)bbud, s));
+    if (st == MCMC_OK) st = hip_status(cnn_forward(L, B, d_params, bsyn, bp, logits, net, s));
+    if (st == MCMC_OK)
+      st = hip_status(cnn_backward(L, B, d_params, logits, btgt, bbud, h_cfg->budget_weight,
+                                   grads, loss, net, s));
+    if (st != MCMC_OK) return st;
+    // learning rate falls linearly from lr to lr_final over total_steps steps
+    const int64_t t = *h_step;
+    const double frac = (double)t / (double)std::max<int64_t>(1, h_cfg->total_steps - 1);
+    const float lr = (float)((double)h_cfg->lr + ((double)h_cfg->lr_final - h_cfg->lr) * frac);
+    const float c1 = (float)(1.0 - pow((double)h_cfg->beta1, (double)(t + 1)));
+    const float c2 = (float)(1.0 - pow((double)h_cfg->beta2, (double)(t + 1)));
+    st = hip_status(cnn_adam(P, d_params, grads, d_m, d_v, lr, h_cfg->beta1, h_cfg->beta2,
+                             h_cfg->eps, c1, c2, s));
+    if (st == MCMC_OK) st = hip_status(cnn_loss_sum(B, loss, d_loss_sum, false, s));
+    if (st != MCMC_OK) return st;
+    *h_step = t + 1;
+  }
+  return MCMC_OK;
+}
+
 int mcmc_cnn_gate(int64_t batch, const float* d_logits, float threshold, uint8_t* d_route,
                   uint8_t* d_class, float* d_confidence, void* stream) {
   if (!cnn_batch_ok(batch)) return MCMC_ERANGE;

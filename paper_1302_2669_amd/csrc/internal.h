@@ -301,6 +301,15 @@ hipError_t cnn_gather(int64_t n, int row, const int32_t* idx, const uint8_t* src
 // dst[idx[k]] = src[k], k < n
 hipError_t cnn_scatter(int64_t n, const int32_t* idx, const uint8_t* src, uint8_t* dst,
                        hipStream_t s);
+// training support (cnn_train.hip)
+hipError_t cnn_init_params(int L, uint64_t seed, float* prm, hipStream_t s);
+hipError_t gate_budget_labels(int64_t n, const uint8_t* d0, const uint8_t* d1, const uint8_t* d2,
+                              int32_t* budget, hipStream_t s);
+int permutation_half_bits(int64_t n);
+hipError_t cnn_permutation(int64_t n, uint64_t seed, uint32_t epoch, int32_t* perm,
+                           hipStream_t s);
+// acc[0] (+)= sum of loss[0..B) in index order (reset: acc[0] = 0 first)
+hipError_t cnn_loss_sum(int64_t B, const float* loss, double* acc, bool reset, hipStream_t s);
 // corr[idx[k]][..] = reps[k][cls[idx[k]]][..], rows of n_q bytes
 hipError_t cnn_pick(int64_t n, int nq, const int32_t* idx, const uint8_t* cls,
                     const uint8_t* reps, uint8_t* corr, hipStream_t s);

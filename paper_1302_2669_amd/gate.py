@@ -117,16 +117,54 @@ def gate(logits, threshold=0.99):
     return route, cls, conf
 
 
+def init_params(L, seed, device="cuda"):
+    """Initial parameters [param_count] fp32 on the device (mcmc_cnn_init:
+    He-normal weights from the library's Philox stream, zero biases)."""
+    torch = _torch()
+    prm = torch.empty((param_count(L),), dtype=torch.float32, device=device)
+    _lib.check(_lib._lib().mcmc_cnn_init(int(L), int(seed) & ((1 << 64) - 1), _ptr(prm),
+                                         _stream(prm.device)), "mcmc_cnn_init")
+    return prm
+
+
+def permutation(n, seed, epoch, device="cuda"):
+    """The keyed shuffle of one training epoch, int32 [n] on the device."""
+    torch = _torch()
+    perm = torch.empty((n,), dtype=torch.int32, device=device)
+    _lib.check(_lib._lib().mcmc_cnn_permutation(int(n), int(seed) & ((1 << 64) - 1), int(epoch),
+                                                _ptr(perm), _stream(perm.device)),
+               "mcmc_cnn_permutation")
+    return perm
+
+
+def budget_labels(d_zero, d_short, d_full):
+    """int32 [n]: 0 if the no-sweep decision equals the full one, else 1 if
+    the short one does, else 2 (mcmc_gate_budget_labels)."""
+    torch = _torch()
+    n = d_full.shape[0]
+    out = torch.empty((n,), dtype=torch.int32, device=d_full.device)
+    _lib.check(_lib._lib().mcmc_gate_budget_labels(
+        n, _ptr(d_zero.contiguous()), _ptr(d_short.contiguous()), _ptr(d_full.contiguous()),
+        _ptr(out), _stream(d_full.device)), "mcmc_gate_budget_labels")
+    return out
+
+
 class GateNet:
-    """Parameters and Adam state of one network on the device."""
+    """Parameters and Adam state of one network on the device; init_params is
+    a host array or a device tensor of the initial parameters."""
 
     def __init__(self, L, init_params, device="cuda"):
         torch = _torch()
         self.L = int(L)
-        init = np.asarray(init_params, dtype=np.float32)
-        if init.size != param_count(L):
-            raise ValueError(f"expected {param_count(L)} parameters, got {init.size}")
-        self.params = torch.from_numpy(init.copy()).to(device)
+        if isinstance(init_params, torch.Tensor):
+            if init_params.numel() != param_count(L):
+                raise ValueError(f"expected {param_count(L)} parameters")
+            self.params = init_params.detach().to(device=device, dtype=torch.float32).clone()
+        else:
+            init = np.asarray(init_params, dtype=np.float32)
+            if init.size != param_count(L):
+                raise ValueError(f"expected {param_count(L)} parameters, got {init.size}")
+            self.params = torch.from_numpy(init.copy()).to(device)
         self.m = torch.zeros_like(self.params)
         self.v = torch.zeros_like(self.params)
         self.step_count = 0
@@ -209,39 +247,43 @@ def mcmc_labels(L, syndromes, p, ids, seed, sweeps_short=None, sweeps_full=None,
     d_full = run(sweeps_full, 1, chains)["chosen"]
     d_short = run(sweeps_short, 1, chains)["chosen"]
     d_zero = run(0, 1, chains)["chosen"]
-    budget = torch.full((n,), 2, dtype=torch.int32, device=syndromes.device)
-    budget[d_short == d_full] = 1
-    budget[d_zero == d_full] = 0
-    return soft, budget, d_full
+    return soft, budget_labels(d_zero, d_short, d_full), d_full
 
 
 def train(net, syndromes, p, class_target, budget, epochs=2, batch=512, lr=1e-3, seed=0,
           budget_weight=0.5, lr_final=None, log=None):
-    """Adam over shuffled mini-batches (the last partial batch of an epoch is
-    dropped); the learning rate falls linearly from lr to lr_final (lr/10 by
-    default) over the run.  Returns the mean loss of each epoch."""
+    """Adam over shuffled mini-batches, one mcmc_cnn_train_epoch call per
+    epoch (the last partial batch of an epoch is dropped); the learning rate
+    falls linearly from lr to lr_final (lr/10 by default) over the run.
+    Returns the mean loss of each epoch."""
     torch = _torch()
     n = syndromes.shape[0]
     dev = syndromes.device
-    p = p.to(dtype=torch.float32)
-    gen = torch.Generator().manual_seed(int(seed))
-    lr_final = lr / 10.0 if lr_final is None else lr_final
-    steps = max(1, epochs * (n // batch))
-    t = 0
+    L = net.L
+    cfg = _lib.TrainConfig(lr=float(lr), lr_final=float(lr / 10.0 if lr_final is None else lr_final),
+                           beta1=0.9, beta2=0.999, eps=1e-8, budget_weight=float(budget_weight),
+                           batch=int(batch), total_steps=max(1, epochs * (n // batch)),
+                           seed=int(seed) & ((1 << 64) - 1))
+    b = ctypes.c_size_t()
+    _lib.check(_lib._lib().mcmc_cnn_train_workspace_size(L, n, int(batch), ctypes.byref(b)),
+               "mcmc_cnn_train_workspace_size")
+    ws = torch.empty((max(b.value, 1),), dtype=torch.uint8, device=dev)
+    syn = syndromes.contiguous()
+    pp = p.to(device=dev, dtype=torch.float32).contiguous()
+    tgt = class_target.to(device=dev, dtype=torch.float32).contiguous()
+    bud = budget.to(device=dev, dtype=torch.int32).contiguous()
+    loss_sum = torch.zeros((1,), dtype=torch.float64, device=dev)
+    step = ctypes.c_int64(net.step_count)
     history = []
     for e in range(epochs):
-        perm = torch.randperm(n, generator=gen).to(dev)
-        total = torch.zeros((), dtype=torch.float64, device=dev)
-        for s in range(0, n - batch + 1, batch):
-            idx = perm[s:s + batch]
-            rate = lr + (lr_final - lr) * (t / max(1, steps - 1))
-            loss = net.train_step(syndromes[idx], p[idx], class_target[idx], budget[idx], rate,
-                                  budget_weight)
-            total += loss.double().sum()
-            t += 1
-        history.append(float(total) / max(1, (n // batch) * batch))
+        _lib.check(_lib._lib().mcmc_cnn_train_epoch(
+            L, n, ctypes.byref(cfg), e, ctypes.byref(step), _ptr(net.params), _ptr(net.m),
+            _ptr(net.v), _ptr(syn), _ptr(pp), _ptr(tgt), _ptr(bud), _ptr(loss_sum), _ptr(ws),
+            ws.numel(), _stream(dev)), "mcmc_cnn_train_epoch")
+        history.append(float(loss_sum.item()) / max(1, (n // batch) * batch))
         if log:
             log(f"epoch {e}: mean loss {history[-1]:.4f}")
+    net.step_count = step.value
     return history
 
 

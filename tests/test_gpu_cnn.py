@@ -296,3 +296,80 @@ def test_fused_inference_matches_layered_forward(L, B):
     got, _ = gate.infer(L, d_prm, syn, p)
     torch.cuda.synchronize()
     assert torch.equal(got[:, :7], ref[:, :7])
+
+
+# ---------------------------------------------------------------- training support
+@pytest.mark.parametrize("L", [3, 13])
+def test_init_params_match_oracle(L):
+    """mcmc_cnn_init against the oracle's Box-Muller draws from the same
+    Philox words: both compute in double and round to float; the device's
+    log and cos may differ from the host's in the last place of the double,
+    which reaches the float only at a rounding boundary (1 ulp allowed)."""
+    say(f"cnn init L={L}")
+    g = gate.init_params(L, 99).cpu().numpy()
+    o = cnn.he_init(L, 99)
+    np.testing.assert_allclose(g, o, rtol=2 ** -23, atol=0)
+    assert (g == o).mean() > 0.999
+
+
+@pytest.mark.parametrize("n", [1, 5, 64, 1000, 4097, 100000])
+def test_epoch_permutation_matches_oracle(n):
+    say(f"cnn permutation n={n}")
+    g = gate.permutation(n, 0xABC, 3).cpu().numpy()
+    if n <= 4097:
+        assert np.array_equal(g, cnn.epoch_permutation(n, 0xABC, 3))
+    assert np.array_equal(np.sort(g), np.arange(n))
+
+
+def test_budget_labels_match_oracle():
+    say("budget labels")
+    rng = np.random.default_rng(4)
+    d = [torch.from_numpy(rng.integers(0, 4, 5000).astype(np.uint8)).to(DEV) for _ in range(3)]
+    g = gate.budget_labels(*d).cpu().numpy()
+    o = cnn.budget_labels(*(x.cpu().numpy() for x in d))
+    assert np.array_equal(g, o)
+
+
+def test_train_epochs_equal_the_step_sequence():
+    """mcmc_cnn_train_epoch equals its definition run from the single-step
+    entry points: each epoch's shuffle, mini-batches in that order, forward,
+    backward, one Adam step at the scheduled rate; parameters, moments and the
+    epoch loss sums bit for bit."""
+    say("train epoch vs steps")
+    L, n, B, epochs, lr = 5, 700, 128, 2, 2e-3
+    syn = torch.from_numpy(uniform_syndromes(L, n, seed=31, density=0.2)).to(DEV)
+    p = torch.from_numpy(uniform_rates(n, 32)).to(DEV)
+    t_np, b_np = cnn_targets(n, 33)
+    tgt = torch.from_numpy(t_np).to(DEV)
+    bud = torch.from_numpy(b_np).to(DEV)
+    init = gate.init_params(L, 7)
+    net = gate.GateNet(L, init, device=DEV)
+    hist = gate.train(net, syn, p, tgt, bud, epochs=epochs, batch=B, lr=lr, seed=21)
+    # the definition, step by step
+    prm = init.clone()
+    m = torch.zeros_like(prm)
+    v = torch.zeros_like(prm)
+    total = epochs * (n // B)
+    t = 0
+    ref_hist = []
+    for e in range(epochs):
+        perm = torch.from_numpy(cnn.epoch_permutation(n, 21, e)).to(DEV)
+        acc = 0.0
+        for s in range(0, n - B + 1, B):
+            idx = perm[s:s + B]
+            logits, ws = gate.forward(L, prm, syn[idx], p[idx])
+            grads, loss = gate.backward(L, prm, logits, tgt[idx], bud[idx], ws, 0.5)
+            lo, hi = np.float64(np.float32(lr)), np.float64(np.float32(lr / 10.0))
+            rate = np.float32(lo + (hi - lo) * (t / max(1, total - 1)))
+            t += 1
+            gate.adam_step(prm, grads, m, v, t, lr=float(rate))
+            bs = 0.0
+            for x in loss.double().cpu().numpy():
+                bs += x
+            acc += bs
+        ref_hist.append(acc / ((n // B) * B))
+    torch.cuda.synchronize()
+    assert torch.equal(prm, net.params)
+    assert torch.equal(m, net.m) and torch.equal(v, net.v)
+    assert hist == ref_hist
+    assert net.step_count == total

@@ -84,3 +84,45 @@ def test_adam_first_step():
     z = {"w": np.zeros(3)}
     out, m, v = cnn.adam(p, g, z, z, 0.01, 0.9, 0.999, 1e-12, 1)
     assert np.allclose(out["w"], p["w"] - 0.01 * np.sign(g["w"]), atol=1e-9)
+
+
+# ---------------------------------------------------------------- training support
+@pytest.mark.parametrize("L", [3, 13])
+def test_he_init_statistics(L):
+    """He-normal blocks: mean 0 and standard deviation sqrt(2 / fan-in) within
+    sampling error (normal draws by Box-Muller from Philox); biases zero."""
+    from oracle import cnn
+    prm = cnn.he_init(L, 5).astype(np.float64)
+    blocks = [(32 * 27, 27), (32, 0), (32 * 288, 288), (32, 0), (32 * 288, 288), (32, 0),
+              (7 * 32 * L * L, 32 * L * L), (7, 0)]
+    at = 0
+    for size, fan in blocks:
+        x = prm[at:at + size]
+        at += size
+        if fan == 0:
+            assert (x == 0).all()
+            continue
+        sd = np.sqrt(2.0 / fan)
+        assert abs(x.mean()) < 5 * sd / np.sqrt(size)
+        assert abs(x.std() / sd - 1) < 5 * np.sqrt(0.5 / size) + 1e-3
+    assert at == prm.size
+    assert not np.array_equal(cnn.he_init(L, 5), cnn.he_init(L, 6))
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 7, 64, 1000, 4097])
+def test_epoch_permutation_is_a_bijection(n):
+    from oracle import cnn
+    p0 = cnn.epoch_permutation(n, 11, 0)
+    assert sorted(p0.tolist()) == list(range(n))
+    if n >= 64:
+        assert not np.array_equal(p0, cnn.epoch_permutation(n, 11, 1))
+        assert not np.array_equal(p0, cnn.epoch_permutation(n, 12, 0))
+        assert not np.array_equal(p0, np.arange(n))
+
+
+def test_budget_label_rule():
+    from oracle import cnn
+    full = np.array([0, 1, 2, 3, 1, 2])
+    zero = np.array([0, 0, 2, 1, 3, 0])
+    short = np.array([1, 1, 0, 3, 2, 2])
+    assert cnn.budget_labels(zero, short, full).tolist() == [0, 1, 0, 1, 2, 1]
