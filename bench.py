@@ -431,7 +431,10 @@ def bench_gated(args, mc, torch, dev):
     t0 = now()
     p_tr = uniform_rates(n_tr, seed).astype(np.float64)
     syn, _, ids = gate.sample_dataset(L, p_tr, seed, id_base=0)
-    soft, bud, _ = gate.mcmc_labels(L, syn, p_tr, ids, seed, init=init)
+    # class targets relative to the start decision: the class head then says
+    # whether (and how) the no-sweep answer is wrong
+    soft, bud, _ = gate.mcmc_labels(L, syn, p_tr, ids, seed, init=init, relative=True)
+    start_right = float(soft[:, 0].mean())
     label_mix = [float((bud == k).float().mean()) for k in range(3)]
     t1 = now()
     net = gate.GateNet(L, gate.init_params(L, seed, device=dev), device=dev)
@@ -459,9 +462,12 @@ def bench_gated(args, mc, torch, dev):
         pr = out["chosen"] == cls_e
         err_plain = float((~pr).float().mean())
         points = []
-        for thr, esc in ((0.99, 0.99), (0.99, 0.0), (0.95, 0.99), (0.9, 0.99), (0.9, 0.0)):
+        # (threshold, escalation margin, class route)
+        for thr, esc, cr in ((0.99, 0.0, True), (0.99, 0.0, False), (0.99, 3.0, False),
+                             (0.95, 0.0, True), (0.95, 3.0, False), (0.9, 3.0, False),
+                             (0.9, 0.0, True)):
             g = gate.GatedDecoder(L, P, seed, max_batch=n_ev, chains=CHAINS, threshold=thr,
-                                  escalate=esc, init=init)
+                                  escalate=esc, init=init, class_route=cr)
             res = g.decode(net.params, syn_e, p=p_ev, ids=ids_e, want_correction=True)
             ta = now()
             for _ in range(reps):
@@ -474,7 +480,13 @@ def bench_gated(args, mc, torch, dev):
             err = float((~gr).float().mean())
             b_dis, c_dis = int((pr & ~gr).sum()), int((~pr & gr).sum())
             mcnemar = binomtest(b_dis, b_dis + c_dis, 0.5).pvalue if b_dis + c_dis else 1.0
-            points.append({"threshold": thr, "escalate": esc, "syndromes_per_s": n_ev / t_g,
+            # syndromes the class head answered with a class other than the
+            # start decision
+            zc = res["logits"][:, :4]
+            conf = torch.softmax(zc, dim=1).max(dim=1).values
+            moved = int(((conf >= thr) & (zc.argmax(dim=1) != 0)).sum()) if cr else 0
+            points.append({"threshold": thr, "escalate": esc, "class_route": cr,
+                           "class_head_other_class": moved, "syndromes_per_s": n_ev / t_g,
                            "speedup": t_plain / t_g, "work_saving": n_ev * SWEEPS / max(1, work),
                            "logical_error": err, "rel_error_change": (err - err_plain) / err_plain,
                            "plain_right_gated_wrong": b_dis, "plain_wrong_gated_right": c_dis,
@@ -513,7 +525,7 @@ def bench_gated(args, mc, torch, dev):
     # the matched-error operating point: the fastest decoder, the plain one
     # included (the gate is switched off when it does not pay), whose logical
     # error is within 2% relative of the plain decoder's on the same syndromes
-    plain_point = {"threshold": None, "escalate": None, "gate": "off",
+    plain_point = {"threshold": None, "escalate": None, "class_route": None, "gate": "off",
                    "syndromes_per_s": uni["plain_syndromes_per_s"], "speedup": 1.0,
                    "rel_error_change": 0.0}
     matched = [q for q in uni["points"] if q["rel_error_change"] <= 0.02] + [plain_point]
@@ -531,10 +543,13 @@ def bench_gated(args, mc, torch, dev):
                                f"{n_ev} evaluation syndromes, budgets 0 / L / L^2, "
                                "4 classes x 4 chains",
                    "labels_s": t1 - t0, "train_s": t2 - t1, "final_train_loss": hist[-1],
-                   "start": args.init, "train_budget_label_mix": label_mix},
+                   "start": args.init, "train_budget_label_mix": label_mix,
+                   "train_mean_p_start_decision_right": start_right,
+                   "class_targets": "relative to the start decision",
+                   "escalate": "replica margin z of the short run's decision"},
         "speedup_vs_plain": head["speedup"],
         "operating_point": {"threshold": head["threshold"], "escalate": head["escalate"],
-                            "gate": head.get("gate", "on"),
+                            "class_route": head["class_route"], "gate": head.get("gate", "on"),
                             "rel_error_change": head["rel_error_change"],
                             "rule": "fastest decoder (plain included) within 2% relative "
                                     "logical error of plain"},

@@ -148,7 +148,7 @@ typedef struct mcmc_params {
 /* Human-readable name of a status code (static string). */
 const char* mcmc_strerror(int status);
 
-/* ABI version of this header: 0x00010300 for 1.3. */
+/* ABI version of this header: 0x00010400 for 1.4. */
 int32_t mcmc_abi_version(void);
 
 /* n_q and n_stab of a distance-L code (Sec. II: n_stab = 2L(L-1),
@@ -485,6 +485,18 @@ int mcmc_gate_budget_labels(int64_t n, const uint8_t* d_zero, const uint8_t* d_s
                             const uint8_t* d_full, int32_t* d_budget, void* stream);
 
 /*
+ * Class targets of the gate read relative to each syndrome's start decision
+ * (the class whose start has the fewest errors, i.e. the no-sweep decision):
+ * d_targets[i][k] = d_class_prob[i][k ^ (d_start_class[i] & 3)], f32 [n][4].
+ * Classes are indexed by the two logical parities (bit 0: X-bar, bit 1:
+ * Z-bar), so XOR composes two classes and entry 0 is the probability that
+ * the start decision is the right class.  The two arrays must not overlap
+ * (EINVAL).
+ */
+int mcmc_gate_relative_targets(int64_t n, const uint8_t* d_start_class, const float* d_class_prob,
+                               float* d_targets, void* stream);
+
+/*
  * The keyed shuffle of training epoch `epoch`: d_perm [n] a permutation of
  * 0..n-1.  With b the smallest even number >= 2 for which 2^b >= n and
  * h = b/2, position i maps through a 4-round Feistel network on b bits
@@ -526,26 +538,42 @@ int mcmc_cnn_train_epoch(int32_t L, int64_t n, const mcmc_train_config* h_cfg, u
 
 /*
  * Gate from logits [batch][8]: d_class = argmax of the class logits (ties to
- * the lowest); with q = softmax of the budget logits, d_confidence
- * [batch][2] = (q0, q0 + q1) (or NULL): the predicted probabilities that no
- * sweep, and that at most the short budget, already give the full-budget
- * decision.  d_route = 0 if q0 >= threshold, else 1 if q0 + q1 >= threshold,
- * else 2.
+ * the lowest); with q = softmax of the budget logits and c = the largest
+ * entry of the class softmax, d_confidence [batch][3] = (q0, q0 + q1, c) (or
+ * NULL): the predicted probabilities that no sweep, and that at most the
+ * short budget, already give the full-budget decision, and the class head's
+ * confidence.  d_route = 0 if q0 >= threshold, else 1 if q0 + q1 >=
+ * threshold, else 2.  With class_route != 0 (a class head trained on targets
+ * relative to the start decision, mcmc_gate_relative_targets) the route is
+ * also 0 when c >= threshold: the answer is then the start decision composed
+ * with d_class.
  */
-int mcmc_cnn_gate(int64_t batch, const float* d_logits, float threshold, uint8_t* d_route,
-                  uint8_t* d_class, float* d_confidence, void* stream);
+int mcmc_cnn_gate(int64_t batch, const float* d_logits, float threshold, int32_t class_route,
+                  uint8_t* d_route, uint8_t* d_class, float* d_confidence, void* stream);
 
 /*
  * Gated decoder for one code size.  The network (mcmc_cnn_infer) runs on the
- * whole batch and
- * its gate sets each syndrome's sweep budget: route 0 = no counted sweep (the
- * decision from the class starts alone), 1 = sweeps_short, 2 = sweeps_full.
- * All syndromes then run as one mixed plan (one persistent launch of every
- * budget).  With escalate > 0, a route-1 syndrome whose largest estimated
- * class probability is below `escalate` is decoded again with sweeps_full
- * (route 3): its chains are keyed by sweep, so this extends the same chains.
- * Every output is exactly that of mcmc_decode_batch with the syndrome's p,
- * id and final budget; the network only chooses the budget.
+ * whole batch and its gate sets each syndrome's sweep budget: route 0 = no
+ * counted sweep (the decision from the class starts alone), 1 =
+ * sweeps_short, 2 = sweeps_full.  All syndromes then run as one mixed plan
+ * (one persistent launch of every budget).  Every output is exactly that of
+ * mcmc_decode_batch with the syndrome's p, id and final budget; the network
+ * only chooses the budget, except under class_route (below).
+ *
+ * class_route != 0: the class head is read relative to the start decision
+ * (mcmc_cnn_gate); a syndrome it is confident on takes route 0 and its answer
+ * is the no-sweep decision composed with the predicted class, its correction
+ * the start of that class.  Not combined with escalation (EINVAL).
+ *
+ * escalate > 0: a route-1 syndrome whose short-run decision has a replica
+ * margin below `escalate` is decoded again with sweeps_full (route 3): its
+ * chains are keyed by sweep, so this extends the same chains.  The margin:
+ * each replica r (chain index) has, per class e, its share of the decision
+ * key, sum_k w_k S[e][k][r] (w = 4, 2, ..., 4, 1 as in the decision, 1 for
+ * K = 1); with m_e and v_e the mean and sample variance of those over the C
+ * replicas, b the decided class and s the runner-up, z = (m_s - m_b) /
+ * sqrt((v_b + v_s) / C) (infinite if the spread is zero and m_s > m_b, zero
+ * if m_s = m_b).  Needs chains >= 2.
  */
 typedef struct mcmc_gate_config {
   int32_t L;            /* code distance                                           */
@@ -556,11 +584,13 @@ typedef struct mcmc_gate_config {
   int32_t sweeps_full;  /* counted sweeps of route 2                               */
   double p;             /* rate used when no per-syndrome rates are given          */
   uint64_t seed;        /* Philox key of the chains                                */
-  uint32_t init;        /* MCMC_INIT_CANONICAL or MCMC_INIT_MATCHING                */
+  uint32_t init;        /* MCMC_INIT_CANONICAL, _MATCHING or _MWPM                  */
   float threshold;      /* minimum gate confidence for routes 0 and 1             */
-  float escalate;       /* route-1 syndromes below this class probability take
-                           the full budget; 0 = never                             */
+  float escalate;       /* route-1 syndromes with a replica margin below this
+                           take the full budget; 0 = never                        */
   int64_t max_batch;    /* largest batch a call may pass                           */
+  int32_t class_route;  /* 1: the class head, relative to the start decision,
+                           may answer (route 0); 0: the budget head alone         */
 } mcmc_gate_config;
 
 typedef struct mcmc_gated mcmc_gated; /* opaque */

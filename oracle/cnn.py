@@ -170,7 +170,8 @@ def adam(params, grads, m, v, lr, beta1, beta2, eps, step):
 
 
 # ---------------------------------------------------------------------------
-# Training support: initial parameters, budget labels, the epoch shuffle.
+# Training support: initial parameters, budget labels, relative class
+# targets, the epoch shuffle.
 # Philox4x32-10 with key = seed, fourth counter word 3<<30 | 3<<28 | field<<20
 # (field 0xFE: initial weights, 0xFD: shuffle).
 # ---------------------------------------------------------------------------
@@ -212,6 +213,18 @@ def budget_labels(d_zero, d_short, d_full):
     budget's is, else 2."""
     d_zero, d_short, d_full = (np.asarray(v) for v in (d_zero, d_short, d_full))
     return np.where(d_zero == d_full, 0, np.where(d_short == d_full, 1, 2)).astype(np.int32)
+
+
+def relative_targets(class_prob, start_class):
+    """Class targets read relative to the start decision: out[i][k] =
+    class_prob[i][k ^ start_class[i]].  A class is bx + 2 bz with bx, bz the
+    parities of the two logical operators (geometry.class_index), so
+    composing an error with a class-c operator maps class e to e ^ c, and
+    entry 0 is the probability that the start decision is the right class."""
+    prob = np.asarray(class_prob)
+    s = np.asarray(start_class).astype(np.int64)
+    k = np.arange(4)
+    return prob[np.arange(prob.shape[0])[:, None], k[None, :] ^ s[:, None]]
 
 
 def epoch_permutation(n, seed, epoch):

@@ -102,6 +102,7 @@ class GateConfig(ctypes.Structure):
         ("threshold", ctypes.c_float),
         ("escalate", ctypes.c_float),
         ("max_batch", ctypes.c_int64),
+        ("class_route", ctypes.c_int32),
     ]
 
 
@@ -166,9 +167,10 @@ _SIGNATURES = {
                                          _SZ, _P]),
     "mcmc_cnn_step": (ctypes.c_int, [_I64, _I64, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                                      ctypes.c_float, _P, _P, _P, _P, _P]),
-    "mcmc_cnn_gate": (ctypes.c_int, [_I64, _P, ctypes.c_float, _P, _P, _P, _P]),
+    "mcmc_cnn_gate": (ctypes.c_int, [_I64, _P, ctypes.c_float, _I32, _P, _P, _P, _P]),
     "mcmc_cnn_init": (ctypes.c_int, [_I32, _U64, _P, _P]),
     "mcmc_gate_budget_labels": (ctypes.c_int, [_I64, _P, _P, _P, _P, _P]),
+    "mcmc_gate_relative_targets": (ctypes.c_int, [_I64, _P, _P, _P, _P]),
     "mcmc_cnn_permutation": (ctypes.c_int, [_I64, _U64, _U32, _P, _P]),
     "mcmc_cnn_train_workspace_size": (ctypes.c_int, [_I32, _I64, _I64, _PSZ]),
     "mcmc_cnn_train_epoch": (ctypes.c_int, [_I32, _I64, ctypes.POINTER(TrainConfig), _U32,
@@ -191,7 +193,7 @@ _handle = None
 
 
 # layout of the structures below (mcmc_params, mcmc_item, ...)
-ABI_VERSION = 0x00010300
+ABI_VERSION = 0x00010400
 
 
 def _lib():

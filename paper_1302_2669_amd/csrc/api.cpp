@@ -166,7 +166,7 @@ const char* mcmc_strerror(int status) {
   }
 }
 
-int32_t mcmc_abi_version(void) { return 0x00010300; }
+int32_t mcmc_abi_version(void) { return 0x00010400; }
 
 int mcmc_geometry(int32_t L, int32_t* n_qubits, int32_t* n_stab) {
   if (!valid_L(L)) return MCMC_ERANGE;

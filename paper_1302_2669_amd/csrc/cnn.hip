@@ -661,41 +661,100 @@ __global__ void adam_kernel(int64_t n, float* __restrict__ prm, const float* __r
 }
 
 // Gate: class = argmax of the class logits (ties to the lowest); budget
-// probabilities q = softmax of the budget logits; conf = (q0, q0 + q1), the
-// probabilities that 0 and that at most the short budget reach the
-// full-budget decision.  route = 0 if q0 >= thr, else 1 if q0 + q1 >= thr,
-// else 2.
+// probabilities q = softmax of the budget logits; conf = (q0, q0 + q1, c),
+// the probabilities that 0 and that at most the short budget reach the
+// full-budget decision, and c = the class softmax's largest entry.
+// route = 0 if q0 >= thr, else 1 if q0 + q1 >= thr, else 2.  With
+// class_route the class head is read relative to the start decision: when
+// c >= thr the route is 0 and flip = the argmax class (the class to compose
+// with the start decision), else flip = 0.
 __global__ void gate_kernel(int64_t B, const float* __restrict__ logits, float thr,
-                            uint8_t* __restrict__ route, uint8_t* __restrict__ cls,
-                            float* __restrict__ conf) {
+                            int class_route, uint8_t* __restrict__ route,
+                            uint8_t* __restrict__ cls, float* __restrict__ conf,
+                            uint8_t* __restrict__ flip) {
   const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= B) return;
   const float* z = logits + b * 8;
   int best = 0;
   for (int k = 1; k < 4; ++k)
     if (z[k] > z[best]) best = k;
+  float ec = 0.0f;
+  for (int k = 0; k < 4; ++k) ec += expf(z[k] - z[best]);
+  const float cmax = 1.0f / ec;
   const float m = fmaxf(fmaxf(z[4], z[5]), z[6]);
   const float e0 = expf(z[4] - m), e1 = expf(z[5] - m), e2 = expf(z[6] - m);
   const float sum = (e0 + e1) + e2;
   const float q0 = e0 / sum, q01 = (e0 + e1) / sum;
-  route[b] = (uint8_t)(q0 >= thr ? 0 : (q01 >= thr ? 1 : 2));
+  uint8_t r = (uint8_t)(q0 >= thr ? 0 : (q01 >= thr ? 1 : 2));
+  uint8_t f = 0;
+  if (class_route && cmax >= thr) {
+    r = 0;
+    f = (uint8_t)best;
+  }
+  route[b] = r;
   cls[b] = (uint8_t)best;
+  if (flip) flip[b] = f;
   if (conf) {
-    conf[2 * b] = q0;
-    conf[2 * b + 1] = q01;
+    conf[3 * b] = q0;
+    conf[3 * b + 1] = q01;
+    conf[3 * b + 2] = cmax;
   }
 }
 
-// flag[i] = 1 when syndrome i took the short budget and the largest of its
-// estimated class probabilities is below thr.
+// Escalation margin of syndrome i from its short run's per-chain sums
+// (block [4][K][C] at i 4KC): replica r's key of class e is the decision key
+// restricted to that replica, sum_k w_k S[e][k][r] (w = 4, 2, ..., 4, 1 as in
+// the decision; 1 for K = 1).  m_e = mean over the C replicas, v_e = their
+// sample variance; with b the decided class (least m, ties to the lowest)
+// and s the runner-up, z = (m_s - m_b) / sqrt((v_b + v_s) / C) (+inf when
+// the spread is zero and m_s > m_b, 0 when m_s = m_b).
+// flag[i] = route[i] == 1 && z < thr.
 __global__ void escalate_kernel(int64_t n, const uint8_t* __restrict__ route,
-                                const double* __restrict__ prob, double thr,
+                                const int64_t* __restrict__ sum_n, int K, int C, double thr,
                                 uint8_t* __restrict__ flag) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const double* q = prob + i * 4;
-  const double m = fmax(fmax(q[0], q[1]), fmax(q[2], q[3]));
-  flag[i] = (uint8_t)(route[i] == 1 && m < thr);
+  if (route[i] != 1) {
+    flag[i] = 0;
+    return;
+  }
+  const int64_t* blk = sum_n + i * 4 * (int64_t)K * C;
+  double mean[4], var[4];
+  for (int e = 0; e < 4; ++e) {
+    double s1 = 0.0;
+    for (int r = 0; r < C; ++r) {
+      int64_t key = 0;
+      for (int k = 0; k < K; ++k) {
+        const int64_t w = k + 1 == K ? 1 : ((k + 1) % 2 == 1 ? 4 : 2);
+        key += w * blk[((int64_t)e * K + k) * C + r];
+      }
+      s1 += (double)key;
+    }
+    mean[e] = s1 / (double)C;
+    double s2 = 0.0;
+    for (int r = 0; r < C; ++r) {
+      int64_t key = 0;
+      for (int k = 0; k < K; ++k) {
+        const int64_t w = k + 1 == K ? 1 : ((k + 1) % 2 == 1 ? 4 : 2);
+        key += w * blk[((int64_t)e * K + k) * C + r];
+      }
+      const double d = (double)key - mean[e];
+      s2 += d * d;
+    }
+    var[e] = s2 / (double)(C - 1);
+  }
+  int b = 0;
+  for (int e = 1; e < 4; ++e)
+    if (mean[e] < mean[b]) b = e;
+  int s = b == 0 ? 1 : 0;
+  for (int e = 0; e < 4; ++e)
+    if (e != b && mean[e] < mean[s]) s = e;
+  const double gap = mean[s] - mean[b];
+  const double se = sqrt((var[b] + var[s]) / (double)C);
+  bool esc;
+  if (se > 0.0) esc = gap / se < thr;
+  else esc = !(gap > 0.0);
+  flag[i] = (uint8_t)esc;
 }
 
 __global__ void gather_kernel(int64_t n, int row, const int32_t* __restrict__ idx,
@@ -920,18 +979,18 @@ hipError_t cnn_adam(int64_t n, float* prm, const float* g, float* m, float* v, f
   return hipGetLastError();
 }
 
-hipError_t cnn_gate(int64_t B, const float* logits, float thr, uint8_t* route, uint8_t* cls,
-                    float* conf, hipStream_t s) {
-  hipLaunchKernelGGL(gate_kernel, dim3(blocks_for(B, 256)), dim3(256), 0, s, B, logits, thr, route,
-                     cls, conf);
+hipError_t cnn_gate(int64_t B, const float* logits, float thr, bool class_route, uint8_t* route,
+                    uint8_t* cls, float* conf, uint8_t* flip, hipStream_t s) {
+  hipLaunchKernelGGL(gate_kernel, dim3(blocks_for(B, 256)), dim3(256), 0, s, B, logits, thr,
+                     class_route ? 1 : 0, route, cls, conf, flip);
   return hipGetLastError();
 }
 
-hipError_t cnn_escalate_flags(int64_t n, const uint8_t* route, const double* prob, double thr,
-                              uint8_t* flag, hipStream_t s) {
+hipError_t cnn_escalate_flags(int64_t n, const uint8_t* route, const int64_t* sum_n, int K, int C,
+                              double thr, uint8_t* flag, hipStream_t s) {
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(escalate_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, route, prob,
-                     thr, flag);
+  hipLaunchKernelGGL(escalate_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, route, sum_n,
+                     K, C, thr, flag);
   return hipGetLastError();
 }
 

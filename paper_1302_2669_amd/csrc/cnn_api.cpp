@@ -127,6 +127,20 @@ int mcmc_gate_budget_labels(int64_t n, const uint8_t* d_zero, const uint8_t* d_s
                                        (hipStream_t)stream));
 }
 
+int mcmc_gate_relative_targets(int64_t n, const uint8_t* d_start_class, const float* d_class_prob,
+                               float* d_targets, void* stream) {
+  if (n < 0) return MCMC_ERANGE;
+  if (n == 0) return MCMC_OK;
+  if (!d_start_class || !d_class_prob || !d_targets) return MCMC_EINVAL;
+  // the permutation reads a row while writing it: the buffers must not overlap
+  const char* a = (const char*)d_class_prob;
+  const char* b = (const char*)d_targets;
+  const size_t bytes = (size_t)n * 4 * sizeof(float);
+  if (a < b + bytes && b < a + bytes) return MCMC_EINVAL;
+  return hip_status(gate_relative_targets(n, d_start_class, d_class_prob, d_targets,
+                                          (hipStream_t)stream));
+}
+
 int mcmc_cnn_permutation(int64_t n, uint64_t seed, uint32_t epoch, int32_t* d_perm,
                          void* stream) {
   if (!cnn_batch_ok(n)) return MCMC_ERANGE;
@@ -237,14 +251,15 @@ int mcmc_cnn_train_epoch(int32_t L, int64_t n, const mcmc_train_config* h_cfg, u
   return MCMC_OK;
 }
 
-int mcmc_cnn_gate(int64_t batch, const float* d_logits, float threshold, uint8_t* d_route,
-                  uint8_t* d_class, float* d_confidence, void* stream) {
+int mcmc_cnn_gate(int64_t batch, const float* d_logits, float threshold, int32_t class_route,
+                  uint8_t* d_route, uint8_t* d_class, float* d_confidence, void* stream) {
   if (!cnn_batch_ok(batch)) return MCMC_ERANGE;
   if (!(threshold >= 0.0f && threshold <= 1.0f)) return MCMC_ERANGE;
   if (batch == 0) return MCMC_OK;
   if (!d_logits || !d_route || !d_class) return MCMC_EINVAL;
   return hip_status(
-      cnn_gate(batch, d_logits, threshold, d_route, d_class, d_confidence, (hipStream_t)stream));
+      cnn_gate(batch, d_logits, threshold, class_route != 0, d_route, d_class, d_confidence,
+               nullptr, (hipStream_t)stream));
 }
 
 }  // extern "C"
@@ -284,7 +299,7 @@ struct mcmc_gated {
 namespace {
 
 struct GatedWorkspace {
-  size_t cnn, logits, pf, route, cls, conf, flag, idx, prob, chosen, plan;
+  size_t cnn, logits, pf, route, cls, flip, conf, flag, idx, prob, chosen, plan;
   // device-built path: queue, class starts, per-chain sums, final rows
   size_t q, irows, in_n, S, A, nf, frows, bytes;
 };
@@ -303,7 +318,8 @@ GatedWorkspace gated_workspace(const mcmc_gated* g) {
   w.pf = take((size_t)n * sizeof(float));
   w.route = take((size_t)n);
   w.cls = take((size_t)n);
-  w.conf = take((size_t)n * 2 * sizeof(float));
+  w.flip = take((size_t)n);
+  w.conf = take((size_t)n * 3 * sizeof(float));
   w.flag = take((size_t)n);
   w.idx = take((size_t)n * sizeof(int32_t));
   w.prob = take((size_t)n * 4 * sizeof(double));
@@ -367,7 +383,10 @@ int mcmc_gated_create(const mcmc_gate_config* h_cfg, mcmc_gated** out) {
   if (!valid_L(c.L) || !valid_p(c.p)) return MCMC_ERANGE;
   if (c.max_batch < 1 || c.max_batch > MCMC_CNN_BATCH_MAX) return MCMC_ERANGE;
   if (!(c.threshold >= 0.0f && c.threshold <= 1.0f)) return MCMC_ERANGE;
-  if (!(c.escalate >= 0.0f && c.escalate <= 1.0f)) return MCMC_ERANGE;
+  if (!(c.escalate >= 0.0f && c.escalate <= 1e6f)) return MCMC_ERANGE;
+  if (c.escalate > 0.0f && c.chains < 2) return MCMC_ERANGE;  // the margin needs replicas
+  if (c.class_route != 0 && c.class_route != 1) return MCMC_EINVAL;
+  if (c.class_route && c.escalate > 0.0f) return MCMC_EINVAL;
   if (c.sweeps_short < 0 || c.sweeps_full < 0) return MCMC_ERANGE;
   if (c.init != MCMC_INIT_CANONICAL && c.init != MCMC_INIT_MATCHING && c.init != MCMC_INIT_MWPM)
     return MCMC_EINVAL;
@@ -486,8 +505,9 @@ int gated_decode_device(mcmc_gated* g, const float* d_params, const uint8_t* d_s
 
   int st = hip_status(cnn_infer(c.L, n, d_params, d_syndromes, pf, logits, ws + wl.cnn, s));
   if (st != MCMC_OK) return st;
-  st = hip_status(cnn_gate(n, logits, c.threshold, route, (uint8_t*)(ws + wl.cls),
-                           (float*)(ws + wl.conf), s));
+  uint8_t* flip = c.class_route ? (uint8_t*)(ws + wl.flip) : nullptr;
+  st = hip_status(cnn_gate(n, logits, c.threshold, c.class_route != 0, route,
+                           (uint8_t*)(ws + wl.cls), (float*)(ws + wl.conf), flip, s));
   if (st != MCMC_OK) return st;
 
   BudgetArgs ba{};
@@ -567,6 +587,7 @@ int gated_decode_device(mcmc_gated* g, const float* d_params, const uint8_t* d_s
   d.mean_n = nullptr;
   d.chosen = d_chosen;
   d.correction = d_correction;
+  d.flip = flip;
   st = hip_status(launch_decide(d, s));
   if (st != MCMC_OK) return st;
   if (h_counts) {
@@ -624,8 +645,8 @@ int mcmc_gated_decode(mcmc_gated* g, const float* d_params, const uint8_t* d_syn
     return MCMC_EDEVICE;
   st = hip_status(cnn_infer(c.L, n, d_params, d_syndromes, pf, logits, ws + wl.cnn, s));
   if (st != MCMC_OK) return st;
-  st = hip_status(cnn_gate(n, logits, c.threshold, route, (uint8_t*)(ws + wl.cls),
-                           (float*)(ws + wl.conf), s));
+  st = hip_status(cnn_gate(n, logits, c.threshold, false, route, (uint8_t*)(ws + wl.cls),
+                           (float*)(ws + wl.conf), nullptr, s));
   if (st != MCMC_OK) return st;
   if (hipMemcpyAsync(g->h_route, route, (size_t)n, hipMemcpyDeviceToHost, s) != hipSuccess)
     return MCMC_EDEVICE;
@@ -645,16 +666,20 @@ int mcmc_gated_decode(mcmc_gated* g, const float* d_params, const uint8_t* d_syn
   size_t need = 0;
   mcmc_plan_info(g->plan, nullptr, &need, nullptr);
   if (need > g->plan_ws) return MCMC_EWORKSPACE;
-  st = mcmc_plan_execute(g->plan, d_syndromes, prob, nullptr, nullptr, nullptr, d_chosen,
+  // per-chain sums of every item (item i's [4][K][C] block at i 4KC)
+  int64_t* sums = (int64_t*)(ws + wl.S);
+  st = mcmc_plan_execute(g->plan, d_syndromes, prob, nullptr, sums, nullptr, d_chosen,
                          d_correction, ws + wl.plan, g->plan_ws, stream);
   if (st != MCMC_OK) return st;
 
-  // short-budget syndromes whose own estimate is not confident: full budget
-  // (the chains are keyed by sweep, so this continues the same chains)
+  // short-budget syndromes whose decision margin across the replicas is
+  // small: full budget (the chains are keyed by sweep, so this continues the
+  // same chains)
   int64_t m = 0;
   if (c.escalate > 0.0f && cnt[1] > 0) {
     uint8_t* flag = (uint8_t*)(ws + wl.flag);
-    st = hip_status(cnn_escalate_flags(n, route, prob, (double)c.escalate, flag, s));
+    st = hip_status(cnn_escalate_flags(n, route, sums, c.n_temps, c.chains, (double)c.escalate,
+                                       flag, s));
     if (st != MCMC_OK) return st;
     if (hipMemcpyAsync(g->h_flag, flag, (size_t)n, hipMemcpyDeviceToHost, s) != hipSuccess)
       return MCMC_EDEVICE;

@@ -1,6 +1,7 @@
 // Gate-network training support on the device (not part of the paper's
-// method): initial parameters, the budget labels, the keyed shuffle of each
-// epoch and the epoch's loss sum.  The epoch loop itself (gather, forward,
+// method): initial parameters, the budget labels, class targets relative to
+// the start decision, the keyed shuffle of each epoch and the epoch's loss
+// sum.  The epoch loop itself (gather, forward,
 // backward, Adam) is sequenced by mcmc_cnn_train_epoch in cnn_api.cpp.
 //
 // Random numbers: Philox4x32-10 with key = seed, domain 3 of the fourth
@@ -52,6 +53,19 @@ __global__ void __launch_bounds__(256) budget_labels_kernel(int64_t n, const uin
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   budget[i] = d0[i] == d2[i] ? 0 : (d1[i] == d2[i] ? 1 : 2);
+}
+
+// Class targets relative to the start decision: out[i][k] = prob[i][k ^ s_i]
+// with s_i the low two bits of start[i] (classes are the two logical
+// parities, so XOR composes two classes).
+__global__ void __launch_bounds__(256) relative_targets_kernel(int64_t n, const uint8_t* __restrict__ start,
+                                                               const float* __restrict__ prob,
+                                                               float* __restrict__ out) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 4 * n) return;
+  const int64_t i = t >> 2;
+  const int k = (int)(t & 3);
+  out[t] = prob[i * 4 + (k ^ (start[i] & 3))];
 }
 
 // Keyed permutation of [0, n): a 4-round balanced Feistel network on b bits
@@ -117,6 +131,14 @@ hipError_t gate_budget_labels(int64_t n, const uint8_t* d0, const uint8_t* d1, c
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(budget_labels_kernel, dim3(blocks(n)), dim3(256), 0, s, n, d0, d1, d2,
                      budget);
+  return hipGetLastError();
+}
+
+hipError_t gate_relative_targets(int64_t n, const uint8_t* start, const float* prob, float* out,
+                                 hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(relative_targets_kernel, dim3(blocks(4 * n)), dim3(256), 0, s, n, start, prob,
+                     out);
   return hipGetLastError();
 }
 

@@ -189,6 +189,7 @@ struct DecideArgs {
   double* mean_n;              // [n][4] or nullptr
   uint8_t* chosen;             // [n]
   uint8_t* correction;         // uniform: [n][n_q]; plan: at item corr_off; or nullptr
+  const uint8_t* flip;         // [n] (caller's index): class composed with the decision, or nullptr
 };
 hipError_t launch_decide(const DecideArgs& a, hipStream_t s);
 
@@ -290,11 +291,14 @@ hipError_t cnn_backward(int L, int64_t B, const float* prm, const float* logits,
                         hipStream_t s);
 hipError_t cnn_adam(int64_t n, float* prm, const float* g, float* m, float* v, float lr, float b1,
                     float b2, float eps, float c1, float c2, hipStream_t s);
-hipError_t cnn_gate(int64_t B, const float* logits, float thr, uint8_t* route, uint8_t* cls,
-                    float* conf, hipStream_t s);
-// flag[i] = route[i] == 1 && max_k prob[i][k] < thr
-hipError_t cnn_escalate_flags(int64_t n, const uint8_t* route, const double* prob, double thr,
-                              uint8_t* flag, hipStream_t s);
+// route, argmax class, confidences [B][3] (or nullptr) and, when flip is
+// not nullptr, the class to compose with the start decision (class route)
+hipError_t cnn_gate(int64_t B, const float* logits, float thr, bool class_route, uint8_t* route,
+                    uint8_t* cls, float* conf, uint8_t* flip, hipStream_t s);
+// flag[i] = route[i] == 1 && the replica margin z of the short run's decision
+// (per-chain sums sum_n, [4][K][C] per syndrome) is below thr
+hipError_t cnn_escalate_flags(int64_t n, const uint8_t* route, const int64_t* sum_n, int K, int C,
+                              double thr, uint8_t* flag, hipStream_t s);
 // dst[k][0..row) = src[idx[k]][0..row), k < n
 hipError_t cnn_gather(int64_t n, int row, const int32_t* idx, const uint8_t* src, uint8_t* dst,
                       hipStream_t s);
@@ -305,6 +309,9 @@ hipError_t cnn_scatter(int64_t n, const int32_t* idx, const uint8_t* src, uint8_
 hipError_t cnn_init_params(int L, uint64_t seed, float* prm, hipStream_t s);
 hipError_t gate_budget_labels(int64_t n, const uint8_t* d0, const uint8_t* d1, const uint8_t* d2,
                               int32_t* budget, hipStream_t s);
+// out[i][k] = prob[i][k ^ (start[i] & 3)]
+hipError_t gate_relative_targets(int64_t n, const uint8_t* start, const float* prob, float* out,
+                                 hipStream_t s);
 int permutation_half_bits(int64_t n);
 hipError_t cnn_permutation(int64_t n, uint64_t seed, uint32_t epoch, int32_t* perm,
                            hipStream_t s);

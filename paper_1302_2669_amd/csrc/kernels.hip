@@ -229,6 +229,9 @@ __global__ void __launch_bounds__(128) decide_kernel(const DecideArgs a) {
   int best = 0;
   for (int e = 1; e < 4; ++e)
     if (key[e] < key[best]) best = e;
+  // a gate's class route: the decision composed with the predicted class
+  // (classes are the two logical parities, so composition is XOR)
+  if (a.flip) best ^= a.flip[orig] & 3;
   a.chosen[orig] = (uint8_t)best;
 
   if (a.correction && a.final_rows) {

@@ -100,20 +100,21 @@ def adam_step(params, grads, m, v, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e
                "mcmc_cnn_step")
 
 
-def gate(logits, threshold=0.99):
-    """(route [B] u8, class [B] u8, confidence [B][2] fp32): the budget
-    route, the argmax class, and the predicted probabilities (q0, q0 + q1)
-    that no sweep / at most the short budget reaches the full-budget
-    decision."""
+def gate(logits, threshold=0.99, class_route=False):
+    """(route [B] u8, class [B] u8, confidence [B][3] fp32): the route, the
+    argmax class, and (q0, q0 + q1, c): the predicted probabilities that no
+    sweep / at most the short budget reaches the full-budget decision, and
+    the class head's largest softmax entry (with class_route, c >= threshold
+    also gives route 0)."""
     torch = _torch()
     B = logits.shape[0]
     dev = logits.device
     route = torch.empty((B,), dtype=torch.uint8, device=dev)
     cls = torch.empty((B,), dtype=torch.uint8, device=dev)
-    conf = torch.empty((B, 2), dtype=torch.float32, device=dev)
+    conf = torch.empty((B, 3), dtype=torch.float32, device=dev)
     _lib.check(_lib._lib().mcmc_cnn_gate(B, _ptr(logits.contiguous()), float(threshold),
-                                         _ptr(route), _ptr(cls), _ptr(conf), _stream(dev)),
-               "mcmc_cnn_gate")
+                                         1 if class_route else 0, _ptr(route), _ptr(cls),
+                                         _ptr(conf), _stream(dev)), "mcmc_cnn_gate")
     return route, cls, conf
 
 
@@ -146,6 +147,20 @@ def budget_labels(d_zero, d_short, d_full):
     _lib.check(_lib._lib().mcmc_gate_budget_labels(
         n, _ptr(d_zero.contiguous()), _ptr(d_short.contiguous()), _ptr(d_full.contiguous()),
         _ptr(out), _stream(d_full.device)), "mcmc_gate_budget_labels")
+    return out
+
+
+def relative_targets(start_class, class_prob):
+    """float32 [n][4]: class probabilities read relative to each syndrome's
+    start decision, out[i][k] = class_prob[i][k ^ start_class[i]]
+    (mcmc_gate_relative_targets)."""
+    torch = _torch()
+    n = class_prob.shape[0]
+    prob = class_prob.to(torch.float32).contiguous()
+    out = torch.empty((n, 4), dtype=torch.float32, device=prob.device)
+    _lib.check(_lib._lib().mcmc_gate_relative_targets(
+        n, _ptr(start_class.to(torch.uint8).contiguous()), _ptr(prob), _ptr(out),
+        _stream(prob.device)), "mcmc_gate_relative_targets")
     return out
 
 
@@ -216,14 +231,15 @@ def sample_dataset(L, p, seed, id_base=0, device="cuda"):
 
 
 def mcmc_labels(L, syndromes, p, ids, seed, sweeps_short=None, sweeps_full=None, chains=4,
-                label_temps=20, label_chains=1, init=MCMC_INIT_MATCHING):
+                label_temps=20, label_chains=1, init=MCMC_INIT_MATCHING, relative=False):
     """Training targets made by the decoder itself, for n syndromes of
     distance L ([n][n_stab] device tensor), rates p (host float array) and ids
     (host int array):
 
     * class_target [n][4]: the class probabilities of thermodynamic
       integration over `label_temps` temperatures (Simpson's rule),
-      `sweeps_full` sweeps, `label_chains` chains;
+      `sweeps_full` sweeps, `label_chains` chains; with `relative`, read
+      relative to the no-sweep decision (relative_targets);
     * budget [n]: the smallest of (0, sweeps_short, sweeps_full) counted
       sweeps whose decision (the plain decoder: one temperature, `chains`
       chains) equals the one at sweeps_full (0 sweeps: the decision from the
@@ -247,6 +263,8 @@ def mcmc_labels(L, syndromes, p, ids, seed, sweeps_short=None, sweeps_full=None,
     d_full = run(sweeps_full, 1, chains)["chosen"]
     d_short = run(sweeps_short, 1, chains)["chosen"]
     d_zero = run(0, 1, chains)["chosen"]
+    if relative:
+        soft = relative_targets(d_zero, soft)
     return soft, budget_labels(d_zero, d_short, d_full), d_full
 
 
@@ -292,7 +310,7 @@ class GatedDecoder:
 
     def __init__(self, L, p, seed, max_batch, sweeps_short=None, sweeps_full=None, chains=4,
                  n_temps=1, burn=0, threshold=0.99, escalate=0.0, init=MCMC_INIT_MATCHING,
-                 device="cuda"):
+                 class_route=False, device="cuda"):
         torch = _torch()
         cfg = _lib.GateConfig()
         cfg.L = int(L)
@@ -307,6 +325,7 @@ class GatedDecoder:
         cfg.threshold = float(threshold)
         cfg.escalate = float(escalate)
         cfg.max_batch = int(max_batch)
+        cfg.class_route = 1 if class_route else 0
         self.cfg = cfg
         self.L = int(L)
         self.nq, self.ns = geometry(L)

@@ -27,7 +27,7 @@ def test_exports_every_declared_symbol():
     assert decl == _lib.exported_symbols()
     for name in decl:
         assert hasattr(lib, name), name
-    assert lib.mcmc_abi_version() == 0x00010300
+    assert lib.mcmc_abi_version() == 0x00010400
 
 
 @pytest.mark.parametrize("L", list(range(2, 26)))
@@ -205,8 +205,13 @@ def test_gate_network_rejects_before_launch():
     assert lib.mcmc_cnn_step(10, 1, f(1e-3), f(0.9), f(0.999), f(0.0), d, d, d, d, None) == -2
     assert lib.mcmc_cnn_step(0, 1, f(1e-3), f(0.9), f(0.999), f(1e-8), None, None, None, None,
                              None) == 0
-    assert lib.mcmc_cnn_gate(8, d, f(1.5), d, d, None, None) == -2
-    assert lib.mcmc_cnn_gate(8, None, f(0.9), d, d, None, None) == -1
+    assert lib.mcmc_cnn_gate(8, d, f(1.5), 0, d, d, None, None) == -2
+    assert lib.mcmc_cnn_gate(8, None, f(0.9), 0, d, d, None, None) == -1
+    rt = lib.mcmc_gate_relative_targets
+    assert rt(-1, d, d, d, None) == -2
+    assert rt(0, None, None, None, None) == 0
+    assert rt(4, None, d, ctypes.c_void_p(0x9000), None) == -1
+    assert rt(4, d, d, ctypes.c_void_p(0x1000 + 63), None) == -1     # overlapping rows
 
 
 def test_gated_config_rejected_before_allocating():
@@ -221,6 +226,8 @@ def test_gated_config_rejected_before_allocating():
         return c
     for bad, status in ((dict(L=1), -2), (dict(p=0.8), -2), (dict(max_batch=0), -2),
                         (dict(threshold=1.5), -2), (dict(escalate=-0.1), -2),
+                        (dict(escalate=2.0, chains=1), -2), (dict(class_route=2), -1),
+                        (dict(class_route=1, escalate=2.0), -1),
                         (dict(sweeps_short=-1), -2), (dict(init=7), -1)):
         assert lib.mcmc_gated_create(ctypes.byref(cfg(**bad)), ctypes.byref(h)) == status, bad
     assert lib.mcmc_gated_create(None, ctypes.byref(h)) == -1

@@ -235,26 +235,46 @@ def test_adam_step_matches_oracle():
     np.testing.assert_allclose(d[0].cpu().numpy(), op["w"], rtol=1e-5, atol=lr * 1e-4)
 
 
-def test_gate_decisions():
+@pytest.mark.parametrize("class_route", [False, True])
+def test_gate_decisions(class_route):
     B = 5000
     rng = np.random.default_rng(SEED + 8)
     z = rng.normal(scale=3.0, size=(B, 8)).astype(np.float32)
     z[:10, :4] = 0.0        # class ties -> lowest class
     d = torch.from_numpy(z).to(DEV)
     thr = 0.9
-    route, cls, conf = gate.gate(d, thr)
+    route, cls, conf = gate.gate(d, thr, class_route=class_route)
     torch.cuda.synchronize()
     route, cls, conf = route.cpu().numpy(), cls.cpu().numpy(), conf.cpu().numpy()
     assert np.array_equal(cls, np.argmax(z[:, :4].astype(np.float64), axis=1))
-    zb = z[:, 4:7].astype(np.float64)
-    q = np.exp(zb - zb.max(axis=1, keepdims=True))
-    q /= q.sum(axis=1, keepdims=True)
-    ref_conf = np.stack([q[:, 0], q[:, 0] + q[:, 1]], axis=1)
+
+    def softmax(v):
+        e = np.exp(v - v.max(axis=1, keepdims=True))
+        return e / e.sum(axis=1, keepdims=True)
+
+    q = softmax(z[:, 4:7].astype(np.float64))
+    c = softmax(z[:, :4].astype(np.float64)).max(axis=1)
+    ref_conf = np.stack([q[:, 0], q[:, 0] + q[:, 1], c], axis=1)
     np.testing.assert_allclose(conf, ref_conf, rtol=1e-5, atol=1e-7)
     ref_route = np.where(ref_conf[:, 0] >= thr, 0, np.where(ref_conf[:, 1] >= thr, 1, 2))
+    if class_route:
+        ref_route = np.where(c >= thr, 0, ref_route)
     clear = (np.abs(ref_conf - thr) > 1e-5).all(axis=1)
     assert np.array_equal(route[clear], ref_route[clear])
     assert {0, 1, 2} <= set(np.unique(route))
+
+
+def test_relative_targets_match_oracle():
+    """Class targets relative to the start decision (a permutation of each
+    row), bit for bit; start classes read through their low two bits."""
+    n = 3001
+    rng = np.random.default_rng(SEED + 9)
+    prob = rng.dirichlet(np.ones(4), size=n).astype(np.float32)
+    start = rng.integers(0, 256, size=n).astype(np.uint8)
+    out = gate.relative_targets(torch.from_numpy(start).to(DEV), torch.from_numpy(prob).to(DEV))
+    torch.cuda.synchronize()
+    ref = cnn.relative_targets(prob, start & 3)
+    assert np.array_equal(out.cpu().numpy(), ref)
 
 
 def test_training_reduces_loss():

@@ -69,7 +69,7 @@ def test_trained_gate_saves_work_at_matched_error():
     plan.close()
 
     g = gate.GatedDecoder(L, 0.1, SEED, max_batch=n_eval, chains=4, threshold=0.99,
-                          escalate=0.99)
+                          escalate=2.0)
     res = g.decode(net.params, syn_e, p=p_ev, ids=ids_e)
     base = g.decode(untrained, syn_e, p=p_ev, ids=ids_e)
     g.close()

@@ -126,3 +126,49 @@ def test_budget_label_rule():
     zero = np.array([0, 0, 2, 1, 3, 0])
     short = np.array([1, 1, 0, 3, 2, 2])
     assert cnn.budget_labels(zero, short, full).tolist() == [0, 1, 0, 1, 2, 1]
+
+
+def test_relative_targets_by_enumeration():
+    """Class probabilities read relative to the start decision, against a
+    direct count at L = 3: every configuration F with the syndrome (a class
+    start times every stabilizer product), grouped by the logical class of the
+    Pauli product F x R, R the start of the decided class, each weighted by
+    exp(-beta_bar n(F))."""
+    from oracle import enumerate as en
+    from oracle import geometry, matching, sampler, tables
+    L, p = 3, 0.15
+    lat = geometry.Lattice(L)
+    beta = tables.beta_bar(p)
+    syn, _, _ = sampler.sample(lat, p, 0x5E1, np.arange(40))
+    stars = [lat.supports[s] for s in range(lat.n_stars)]
+    plaqs = [lat.supports[s] for s in range(lat.n_stars, lat.n_stab)]
+
+    def span(gens):
+        out = [np.zeros(lat.n_qubits, dtype=np.uint8)]
+        for g in gens:
+            v = np.zeros(lat.n_qubits, dtype=np.uint8)
+            v[list(g)] = 1
+            out = out + [o ^ v for o in out]
+        return np.array(out)
+
+    xs, zs = span(stars), span(plaqs)
+    seen = set()
+    for i in range(syn.shape[0]):
+        reps = matching.mwpm_representatives(lat, syn[i])
+        start = int(np.argmin(geometry.weight(reps)))
+        seen.add(start)
+        prob = en.class_probabilities(en.class_histograms(lat, syn[i]), beta)
+        rel = cnn.relative_targets(prob[None, :], np.array([start]))[0]
+        direct = np.zeros(4)
+        for e in range(4):
+            xr, zr = reps[e] & 1, (reps[e] >> 1) & 1
+            x = xs ^ xr[None, :]
+            z = zs ^ zr[None, :]
+            F = (x[:, None, :] | (z[None, :, :] << 1)).reshape(-1, lat.n_qubits)
+            assert (geometry.syndrome(lat, F) == syn[i]).all()
+            k = geometry.class_index(lat, F ^ reps[start][None, :])
+            np.add.at(direct, k, np.exp(-beta * geometry.weight(F)))
+        direct /= direct.sum()
+        np.testing.assert_allclose(rel, direct, rtol=1e-12, atol=1e-15)
+        assert rel[0] == prob[start]
+    assert len(seen) >= 2      # some syndromes decide a class other than the identity
