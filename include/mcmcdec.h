@@ -320,15 +320,18 @@ typedef struct mcmc_item {
 /* Launch shape of a plan: workgroup size (64, 128 or 256) of the L <= 16
  * kernels (narrow) and of the L >= 17 kernels (wide); the persistent grid of
  * each kernel in waves per SIMD, as an offset (narrow -4..8, wide -2..8)
- * from the occupancy its register budget allows; and the streams: all
- * kernels one after the other on the caller's stream (0), the L >= 17 kernels
- * on one side stream beside the L <= 16 ones (1), or each of the three
- * L >= 17 kernels on a side stream of its own (2), joined to the caller's
- * stream before the estimator.  Never changes results. */
+ * from the occupancy its register budget allows; the streams: all kernels
+ * one after the other on the caller's stream (0), the L >= 17 kernels on one
+ * side stream beside the L <= 16 ones (1), or each of the three L >= 17
+ * kernels on a side stream of its own (2), joined to the caller's stream
+ * before the estimator; and the chain mapping of codes with L <= 8: one
+ * chain per lane (pair_small 0) or two chains per lane, the rows of both in
+ * the same registers (1).  Never changes results. */
 typedef struct mcmc_tuning {
   int32_t wg_narrow, occ_narrow;
   int32_t wg_wide, occ_wide;
   int32_t concurrent;
+  int32_t pair_small;
 } mcmc_tuning;
 
 typedef struct mcmc_plan mcmc_plan; /* opaque */

@@ -85,6 +85,7 @@ class Tuning(ctypes.Structure):
         ("wg_wide", ctypes.c_int32),
         ("occ_wide", ctypes.c_int32),
         ("concurrent", ctypes.c_int32),
+        ("pair_small", ctypes.c_int32),
     ]
 
 

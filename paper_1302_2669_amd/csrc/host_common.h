@@ -15,7 +15,8 @@ constexpr size_t kAlign = 256;
 // Tile-queue counters at the head of every workspace, one per chain kernel
 // range; all of them are zeroed before each launch sequence.
 constexpr int kQueueSlots = 16;
-static_assert(kQueueSlots >= 2 * N_RANGES, "one queue counter per kernel range and noise model");
+static_assert(kQueueSlots >= 2 * N_RANGES + 2,
+              "one queue counter per kernel range and noise model, and per pair launch");
 
 inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 

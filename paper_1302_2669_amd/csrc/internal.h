@@ -112,6 +112,13 @@ template <int R>
 hipError_t launch_chains_flip_range(const RunArgs& a, int waves, int wg, hipStream_t s);
 // Picks the kernel of `range` for a.noise.
 hipError_t launch_chains(int range, const RunArgs& a, int waves, int wg, hipStream_t s);
+// The second chain mapping: two chains per lane for codes up to PAIR_L_MAX,
+// plans only (a.items, a.tiles, a.tables; no trace, resume or state export);
+// a.tiles are pair tiles of 2 * TILE tasks.  PAIR_WAVES: the kernel's
+// register-limited waves per SIMD.
+constexpr int PAIR_L_MAX = 8;
+constexpr int PAIR_WAVES = 5;
+hipError_t launch_chains_pair(const RunArgs& a, int waves, int wg, hipStream_t s);
 // Random-scan chains of a uniform batch (g0, table0, a.noise; no trace):
 // one 64-lane workgroup per 64 chains, each lane's state in LDS.
 hipError_t launch_chains_random(const RunArgs& a, hipStream_t s);

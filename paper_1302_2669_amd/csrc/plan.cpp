@@ -81,6 +81,10 @@ struct mcmc_plan {
   // tiles by launch slot: kernel range r under noise model m is slot m * N_RANGES + r
   static constexpr int kSlots = 2 * N_RANGES;
   int64_t range_first[kSlots] = {0}, range_tiles[kSlots] = {0};
+  // codes of at most PAIR_L_MAX: their one-chain tiles close slot (m, 0)
+  // (small_tiles[m] of them), and the same tasks as 128-task pair tiles for
+  // the two-chains-per-lane kernel (pair_first[m], pair_tiles[m])
+  int64_t small_tiles[2] = {0}, pair_first[2] = {0}, pair_tiles[2] = {0};
   std::vector<int> group_noise;      // noise model of each group
   int64_t total_chains = 0, total_rows = 0, total_updates = 0;
   size_t corr_bytes = 0;
@@ -192,12 +196,28 @@ int enqueue(mcmc_plan* p, const uint8_t* syn, double* prob, double* mean_n, int6
   const mcmc_tuning& tu = p->tuning;
   const int cus = device_cus();
   auto run_range = [&](int slot, hipStream_t on) -> int {
-    if (p->range_tiles[slot] == 0) return MCMC_OK;
-    const int r = slot % N_RANGES;
+    const int r = slot % N_RANGES, m = slot / N_RANGES;
+    // the small codes of range 0 under the two-chains-per-lane mapping
+    const bool pair = r == 0 && tu.pair_small != 0 && p->small_tiles[m] > 0;
+    if (pair) {
+      RunArgs ra = a;
+      ra.noise = m;
+      ra.tiles = p->d_tiles + p->pair_first[m];
+      ra.n_tiles = p->pair_tiles[m];
+      ra.queue = queue + mcmc_plan::kSlots + m;
+      ra.lmin = 2;
+      ra.lmax = PAIR_L_MAX;
+      const int per_simd = std::max(1, PAIR_WAVES + tu.occ_narrow);
+      const int64_t waves = std::min<int64_t>(ra.n_tiles, (int64_t)cus * 4 * per_simd);
+      const int st2 = hip_status(launch_chains_pair(ra, (int)waves, tu.wg_narrow, on));
+      if (st2 != MCMC_OK) return st2;
+    }
+    const int64_t n_tiles = p->range_tiles[slot] - (pair ? p->small_tiles[m] : 0);
+    if (n_tiles == 0) return MCMC_OK;
     RunArgs ra = a;
-    ra.noise = slot / N_RANGES;
+    ra.noise = m;
     ra.tiles = p->d_tiles + p->range_first[slot];
-    ra.n_tiles = p->range_tiles[slot];
+    ra.n_tiles = n_tiles;
     ra.queue = queue + slot;
     ra.lmin = RANGE_LO[r];
     ra.lmax = RANGE_HI[r];
@@ -205,7 +225,7 @@ int enqueue(mcmc_plan* p, const uint8_t* syn, double* prob, double* mean_n, int6
     // occupancy offset from the kernel's own register-limited occupancy
     const int per_simd = std::max(1, RANGE_WAVES[r] + (wide ? tu.occ_wide : tu.occ_narrow));
     const int wg = wide ? tu.wg_wide : tu.wg_narrow;
-    const int64_t waves = std::min<int64_t>(p->range_tiles[slot], (int64_t)cus * 4 * per_simd);
+    const int64_t waves = std::min<int64_t>(n_tiles, (int64_t)cus * 4 * per_simd);
     return hip_status(launch_chains(r, ra, (int)waves, wg, on));
   };
   // stream of each kernel range: the caller's, or a side stream for the
@@ -295,8 +315,8 @@ bool read_cache(const char* path, const std::string& sig, mcmc_tuning* t) {
     *tab = 0;
     if (sig != line) continue;
     mcmc_tuning v{};
-    if (sscanf(tab + 1, "%d %d %d %d %d", &v.wg_narrow, &v.occ_narrow, &v.wg_wide, &v.occ_wide,
-               &v.concurrent) == 5) {
+    if (sscanf(tab + 1, "%d %d %d %d %d %d", &v.wg_narrow, &v.occ_narrow, &v.wg_wide,
+               &v.occ_wide, &v.concurrent, &v.pair_small) == 6) {
       *t = v;
       found = true;
     }
@@ -308,8 +328,8 @@ bool read_cache(const char* path, const std::string& sig, mcmc_tuning* t) {
 void write_cache(const char* path, const std::string& sig, const mcmc_tuning& t) {
   FILE* f = fopen(path, "a");
   if (!f) return;
-  fprintf(f, "%s\t%d %d %d %d %d\n", sig.c_str(), t.wg_narrow, t.occ_narrow, t.wg_wide,
-          t.occ_wide, t.concurrent);
+  fprintf(f, "%s\t%d %d %d %d %d %d\n", sig.c_str(), t.wg_narrow, t.occ_narrow, t.wg_wide,
+          t.occ_wide, t.concurrent, t.pair_small);
   fclose(f);
 }
 
@@ -335,6 +355,7 @@ void clear_plan(mcmc_plan* p) {
   p->tables.clear();
   p->total_chains = p->total_rows = p->total_updates = 0;
   for (int r = 0; r < mcmc_plan::kSlots; ++r) p->range_first[r] = p->range_tiles[r] = 0;
+  for (int m = 0; m < 2; ++m) p->small_tiles[m] = p->pair_first[m] = p->pair_tiles[m] = 0;
 }
 
 int build_plan(mcmc_plan* p, const mcmc_item* items, int64_t n) {
@@ -353,6 +374,7 @@ int build_plan_into(mcmc_plan* p, const mcmc_item* items, int64_t n) {
   p->tables.clear();
   p->total_chains = p->total_rows = p->total_updates = 0;
   for (int r = 0; r < mcmc_plan::kSlots; ++r) p->range_first[r] = p->range_tiles[r] = 0;
+  for (int m = 0; m < 2; ++m) p->small_tiles[m] = p->pair_first[m] = p->pair_tiles[m] = 0;
 
   // groups: (L, K, C, burn, sweeps) -> items, in order of first appearance
   // (a batch has few distinct keys: linear search with a last-hit cache)
@@ -484,12 +506,29 @@ int build_plan_into(mcmc_plan* p, const mcmc_item* items, int64_t n) {
   for (int slot = 0; slot < mcmc_plan::kSlots; ++slot) {
     const int r = slot % N_RANGES, m = slot / N_RANGES;
     p->range_first[slot] = (int64_t)p->tiles.size();
-    for (size_t gi = 0; gi < p->groups.size(); ++gi) {
-      const GroupDesc& g = p->groups[gi];
-      if (range_of(g.L) != r || p->group_noise[gi] != m) continue;
-      for (int64_t f = 0; f < g.n_tasks; f += TILE) p->tiles.push_back(TileDesc{(int32_t)gi, g.L, f});
+    // in range 0 the codes the pair kernel can take come last
+    for (int part = 0; part < 2; ++part) {
+      const int64_t before = (int64_t)p->tiles.size();
+      for (size_t gi = 0; gi < p->groups.size(); ++gi) {
+        const GroupDesc& g = p->groups[gi];
+        if (range_of(g.L) != r || p->group_noise[gi] != m) continue;
+        if ((g.L <= PAIR_L_MAX) != (part == 1)) continue;
+        for (int64_t f = 0; f < g.n_tasks; f += TILE)
+          p->tiles.push_back(TileDesc{(int32_t)gi, g.L, f});
+      }
+      if (r == 0 && part == 1) p->small_tiles[m] = (int64_t)p->tiles.size() - before;
     }
     p->range_tiles[slot] = (int64_t)p->tiles.size() - p->range_first[slot];
+  }
+  for (int m = 0; m < 2; ++m) {
+    p->pair_first[m] = (int64_t)p->tiles.size();
+    for (size_t gi = 0; gi < p->groups.size(); ++gi) {
+      const GroupDesc& g = p->groups[gi];
+      if (g.L > PAIR_L_MAX || p->group_noise[gi] != m) continue;
+      for (int64_t f = 0; f < g.n_tasks; f += 2 * TILE)
+        p->tiles.push_back(TileDesc{(int32_t)gi, g.L, f});
+    }
+    p->pair_tiles[m] = (int64_t)p->tiles.size() - p->pair_first[m];
   }
   if ((int64_t)p->tiles.size() > 0xFFFFFFFFll) return MCMC_ERANGE;
 
@@ -572,6 +611,7 @@ int mcmc_plan_create(const mcmc_item* items, int64_t n, uint64_t seed, uint32_t 
   p->tuning.wg_wide = 256;
   p->tuning.occ_narrow = 0;
   p->tuning.occ_wide = 0;
+  p->tuning.pair_small = 1;   // measured faster at every L <= 8 (1.02-1.7x)
   p->tuning.concurrent = 2;
   *out = p;
   return MCMC_OK;
@@ -620,6 +660,7 @@ int mcmc_plan_set_tuning(mcmc_plan* p, const mcmc_tuning* t) {
   if (t->occ_narrow < -4 || t->occ_narrow > 8 || t->occ_wide < -2 || t->occ_wide > 8)
     return MCMC_ERANGE;
   if (t->concurrent < 0 || t->concurrent > 2) return MCMC_EINVAL;
+  if (t->pair_small != 0 && t->pair_small != 1) return MCMC_EINVAL;
   p->tuning = *t;
   release_graphs(p);  // captured graphs hold the old launch shape
   return MCMC_OK;
@@ -727,6 +768,7 @@ int mcmc_plan_autotune(mcmc_plan* p, const uint8_t* syndromes, double* class_pro
       [](mcmc_tuning& t) { t.concurrent = 0; },
       [](mcmc_tuning& t) { t.concurrent = 1; },
       [](mcmc_tuning& t) { t.concurrent = 2; },
+      [](mcmc_tuning& t) { t.pair_small = 1 - t.pair_small; },
   };
   for (size_t i = 0; st == MCMC_OK && i < moves.size(); ++i) {
     mcmc_tuning cand = best;

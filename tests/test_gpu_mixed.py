@@ -256,3 +256,50 @@ def test_plan_sampler_noise_models():
         assert np.array_equal(syn[a:b], o_syn[0]), i
         assert cls[i] == o_cls[0], i
     plan.close()
+
+
+@pytest.mark.parametrize("noise", [0, 1])
+def test_pair_mapping_equals_one_chain_mapping(noise):
+    """Two chains per lane for the small codes (mcmc_tuning.pair_small):
+    every output equal to the one-chain mapping's and to the uniform decodes,
+    at every small L, with chain counts that make a lane's two chains belong
+    to different items, classes and temperatures, and groups whose task
+    count is not a multiple of a pair tile."""
+    say(f"pair mapping noise={noise}")
+    rng = np.random.default_rng(31 + noise)
+    n = 90
+    Ls = np.concatenate([np.arange(2, 9), rng.integers(2, 9, n - 10), [9, 13, 17]])
+    ps = rng.uniform(0.03, 0.15, Ls.size)
+    sweeps = rng.integers(0, 9, Ls.size)
+    chains = rng.choice([1, 2, 3, 5], Ls.size)
+    temps = rng.choice([1, 2, 4], Ls.size)
+    burns = rng.integers(0, 3, Ls.size)
+    items, syns, flat = make_batch(Ls, ps, sweeps, 12, chains=chains, n_temps=temps,
+                                   burns=burns, noise=np.full(Ls.size, noise))
+    plan = mc.MixedPlan(items, seed=0xBEEF)
+    t = plan.tuning
+    assert t["pair_small"] == 1           # the default
+    t["pair_small"] = 0
+    plan.tuning = t
+    ref = plan.execute(flat, want_sums=True)
+    torch.cuda.synchronize()
+    ref = {k: v.clone() for k, v in ref.items()}
+    for wg, occ in ((256, 0), (64, -2), (128, 2)):
+        t.update(pair_small=1, wg_narrow=wg, occ_narrow=occ)
+        plan.tuning = t
+        out = plan.execute(flat, want_sums=True)
+        torch.cuda.synchronize()
+        for k in ref:
+            assert torch.equal(ref[k], out[k]), (wg, occ, k)
+    for i in (0, 3, 6, Ls.size - 5):
+        same(per_item(plan, out, i), uniform(items[i], syns[i], 0xBEEF))
+    with pytest.raises(mc.McmcError):
+        plan.tuning = dict(t, pair_small=2)
+    # a graph recorded under the pair mapping replays it
+    g = plan._outputs(flat.device, True, True)
+    for _ in range(2):
+        plan.execute(flat, want_sums=True, graph=True, out=g)
+        torch.cuda.synchronize()
+        for k in ref:
+            assert torch.equal(ref[k], g[k]), k
+    plan.close()
