@@ -47,34 +47,43 @@ struct Wave64 {
     const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(x >> 32));
     return (int64_t)(((uint64_t)hi << 32) | lo);
   }
-  // one step of the (key, idx) minimum: combine with the value DPP control
-  // CTRL brings in (lanes it does not reach keep the identity)
+  // one step of an unsigned minimum over the wave: combine with the value DPP
+  // control CTRL brings in (lanes it does not reach keep the identity)
   template <int CTRL, int ROWS>
-  MW_FN static void min_step(uint32_t& lo, int& hi, int& id) {
-    const uint32_t lo2 = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)lo, CTRL, ROWS, 0xf, false);
-    const int hi2 = __builtin_amdgcn_update_dpp(0x40000000, hi, CTRL, ROWS, 0xf, false);
-    const int id2 = __builtin_amdgcn_update_dpp(0x7fff, id, CTRL, ROWS, 0xf, false);
-    const bool take = hi2 < hi || (hi2 == hi && (lo2 < lo || (lo2 == lo && id2 < id)));
-    if (take) { lo = lo2; hi = hi2; id = id2; }
+  MW_FN static uint32_t min_step(uint32_t v) {
+    const uint32_t o = (uint32_t)__builtin_amdgcn_update_dpp(-1, (int)v, CTRL, ROWS, 0xf, false);
+    return o < v ? o : v;
   }
-  // smallest (key, idx) over the wave: prefix minima within each row of 16
+  // unsigned minimum of v over the wave: prefix minima within each row of 16
   // lanes (row_shr 1, 2, 4, 8), then row 0's result into row 1 and row 2's
   // into row 3 (row_bcast:15), then row 1's into rows 2 and 3
-  // (row_bcast:31); lane 63 holds the minimum.  Keys are below 2^62.
+  // (row_bcast:31); lane 63 holds the minimum.
+  MW_FN static uint32_t wave_min(uint32_t v) {
+    v = min_step<0x111, 0xf>(v);
+    v = min_step<0x112, 0xf>(v);
+    v = min_step<0x114, 0xf>(v);
+    v = min_step<0x118, 0xf>(v);
+    v = min_step<0x142, 0xa>(v);
+    v = min_step<0x143, 0xc>(v);
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
+  }
+  // smallest (signed) key over the wave and the idx of the lowest lane
+  // holding it: the minimum of the high words (sign bit flipped, so that the
+  // unsigned order is the signed one), then, only when several lanes share
+  // it, the minimum of their low words
   MW_FN void argmin(int64_t& key, int& idx) const {
-    uint32_t lo = (uint32_t)key;
-    int hi = (int)(key >> 32);
-    int id = idx;
-    min_step<0x111, 0xf>(lo, hi, id);
-    min_step<0x112, 0xf>(lo, hi, id);
-    min_step<0x114, 0xf>(lo, hi, id);
-    min_step<0x118, 0xf>(lo, hi, id);
-    min_step<0x142, 0xa>(lo, hi, id);
-    min_step<0x143, 0xc>(lo, hi, id);
-    lo = (uint32_t)__builtin_amdgcn_readlane((int)lo, 63);
-    hi = __builtin_amdgcn_readlane(hi, 63);
-    idx = __builtin_amdgcn_readlane(id, 63);
-    key = (int64_t)(((uint64_t)(uint32_t)hi << 32) | lo);
+    const uint32_t lo = (uint32_t)key, hi = (uint32_t)((uint64_t)key >> 32) ^ 0x80000000u;
+    const uint32_t mh = wave_min(hi);
+    uint64_t at = __ballot(hi == mh);
+    uint32_t ml;
+    if (__popcll(at) > 1) {
+      ml = wave_min(hi == mh ? lo : 0xFFFFFFFFu);
+      at = __ballot(hi == mh && lo == ml);
+    } else {
+      ml = (uint32_t)__builtin_amdgcn_readlane((int)lo, __builtin_ctzll(at));
+    }
+    idx = __builtin_amdgcn_readlane(idx, __builtin_ctzll(at));
+    key = (int64_t)(((uint64_t)(mh ^ 0x80000000u) << 32) | ml);
   }
   MW_FN bool any(bool p) const { return __ballot(p) != 0ull; }
   MW_FN int compact(bool take, int& count) const {
@@ -95,13 +104,13 @@ size_t mwpm_lds(int cap) {
 }
 
 // Capacity of the first launch: the problems of typical syndromes (lit sites
-// of one type up to about 2/5 of them, at least 94), so that more waves fit
+// of one type up to about 2/5 of them, at least 85), so that more waves fit
 // per compute unit; the rare larger syndromes go to a second launch sized for
 // a fully lit code.
 int mwpm_small_capacity(int L) {
   const int full = mw::capacity(L);
   int c = 2 * L * (L - 1) / 5 + 8;
-  if (c < 96) c = 96;
+  if (c < 88) c = 88;
   c = (c + 3) & ~3;
   return c < full ? c : full;
 }
@@ -114,10 +123,13 @@ __device__ __forceinline__ int max_vertices(int k) { return (k & 1) ? k + 3 : k 
 
 // Wave w solves anyon types w, w + waves (0 plaquettes / x parts, 1 stars /
 // z parts): parity 0 from the start, then parity 1 from parity 0's solution;
-// problem p = 2 type + parity paints plane p.  The small launch (big = 0) takes the syndromes whose problems fit `cap`
-// vertices, the big launch (big = 1) the others.
-__global__ void __launch_bounds__(128) init_mwpm_kernel(const StartArgs a, int cap, int waves,
-                                                        int small_cap, int big) {
+// problem p = 2 type + parity paints plane p.  The small launch (big = 0)
+// takes the syndromes whose problems fit `cap` vertices, the big launch
+// (big = 1) the others.  Register budget: 5 waves per SIMD (96 VGPRs, a few
+// spills), which the small launch's LDS also allows; at 4 waves (117 VGPRs,
+// none) the kernel is 15% slower.
+__global__ void __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(5)))
+init_mwpm_kernel(const StartArgs a, int cap, int waves, int small_cap, int big) {
   extern __shared__ __align__(16) uint8_t mw_lds[];
   __shared__ int lit[2];
   const int64_t s = blockIdx.x;

@@ -8,7 +8,8 @@
 // The policy WV provides:
 //   int lane; static constexpr int N (lanes);
 //   sync()                 order LDS writes of all lanes before later reads
-//   argmin(key, idx)       smallest (key, idx) over the lanes, to every lane
+//   argmin(key, idx)       smallest key over the lanes and the idx of a lane
+//                          holding it, to every lane
 //   any(p)                 p in some lane
 //   compact(take, &count)  slot of this lane among the takers; count += takers
 //   xor_word(p, v)         *p ^= v (atomically across lanes)
@@ -78,10 +79,10 @@ MW_HD int capacity(int L) { return ((L * (L - 1) + 2) + 3) & ~3; }
 // bytes of one problem's state (nodes: nn = cap + cap / 2)
 MW_HD size_t region_bytes(int cap) {
   // int64: u, best, key [cap], z [cap/2] (blossom b at z[b - cap])
-  // int16: crd, mate, top, bestS, list [cap], freel [cap/2]
+  // int16: crd, mate, top, bestS, list, slist [cap], freel [cap/2]
   //        par, lab, tS, tT, base, bfirst, cnext, cprev, cex, cey, mark [nn]
   //        stack [2 nn] ((node, vertex) pairs)
-  return (size_t)cap * 78;
+  return (size_t)cap * 80;
 }
 
 template <class WV>
@@ -90,7 +91,7 @@ struct Solver {
   int64_t *u, *best, *z;
   uint64_t* key;
   uint16_t* crd;
-  int16_t *mate, *top, *bestS, *freel, *list;
+  int16_t *mate, *top, *bestS, *freel, *list, *slist;
   int16_t *par, *lab, *tS, *tT, *base, *bfirst, *cnext, *cprev, *cex, *cey, *mark;
   int16_t* stk;
   int nv, cap, nn, L, nfree, k_lit;
@@ -110,6 +111,7 @@ struct Solver {
     top = p16; p16 += cap;
     bestS = p16; p16 += cap;
     list = p16; p16 += cap;
+    slist = p16; p16 += cap;
     freel = p16; p16 += cap / 2;
     int16_t** node[11] = {&par, &lab, &tS, &tT, &base, &bfirst, &cnext, &cprev, &cex, &cey,
                           &mark};
@@ -389,15 +391,23 @@ struct Solver {
   // vertex outside its outermost node
   MW_FN void recompute(int cnt) {
     for (int k = 0; k < cnt; ++k) MW_COUNT(recompute_vertex);
-    if (cnt >= WV::N / 4) {  // many: one vertex per lane
+    if (cnt >= WV::N / 4) {  // many: one vertex per lane, over the list of S vertices
+      int ns = 0;
+      for (int x0 = 0; x0 < nv; x0 += WV::N) {
+        const int x = x0 + wv.lane;
+        const bool take = x < nv && lab[top[x]] == S;
+        const int slot = wv.compact(take, ns);
+        if (take) slist[slot] = (int16_t)x;
+      }
+      wv.sync();
       for (int k = wv.lane; k < cnt; k += WV::N) {
         const int y = list[k];
         const int ty = top[y];
         int64_t b = INF;
         int bs = -1;
-        for (int x = 0; x < nv; ++x) {
-          const int tx = top[x];
-          if (tx == ty || lab[tx] != S) continue;
+        for (int m = 0; m < ns; ++m) {
+          const int x = slist[m];
+          if (top[x] == ty) continue;
           const int64_t sl = slack(x, y);
           if (sl < b) { b = sl; bs = x; }
         }
