@@ -80,9 +80,10 @@ MW_HD int capacity(int L) { return ((L * (L - 1) + 2) + 3) & ~3; }
 MW_HD size_t region_bytes(int cap) {
   // int64: u, best, key [cap], z [cap/2] (blossom b at z[b - cap])
   // int16: crd, mate, top, bestS, list, slist [cap], freel [cap/2]
-  //        par, lab, tS, tT, base, bfirst, cnext, cprev, cex, cey, mark [nn]
+  //        par, lab, tS, tT, base, bfirst, cnext, cprev, cex, cey, mark,
+  //        tid [nn]
   //        stack [2 nn] ((node, vertex) pairs)
-  return (size_t)cap * 80;
+  return (size_t)cap * 83;
 }
 
 template <class WV>
@@ -92,7 +93,7 @@ struct Solver {
   uint64_t* key;
   uint16_t* crd;
   int16_t *mate, *top, *bestS, *freel, *list, *slist;
-  int16_t *par, *lab, *tS, *tT, *base, *bfirst, *cnext, *cprev, *cex, *cey, *mark;
+  int16_t *par, *lab, *tS, *tT, *base, *bfirst, *cnext, *cprev, *cex, *cey, *mark, *tid;
   int16_t* stk;
   int nv, cap, nn, L, nfree, k_lit;
   bool star, fail;
@@ -113,9 +114,9 @@ struct Solver {
     list = p16; p16 += cap;
     slist = p16; p16 += cap;
     freel = p16; p16 += cap / 2;
-    int16_t** node[11] = {&par, &lab, &tS, &tT, &base, &bfirst, &cnext, &cprev, &cex, &cey,
-                          &mark};
-    for (int k = 0; k < 11; ++k) { *node[k] = p16; p16 += nn; }
+    int16_t** node[12] = {&par, &lab, &tS, &tT, &base, &bfirst, &cnext, &cprev, &cex, &cey,
+                          &mark, &tid};
+    for (int k = 0; k < 12; ++k) { *node[k] = p16; p16 += nn; }
     stk = p16;
   }
   MW_FN bool is_boundary(int v) const { return crd[v] >= CRD_NEAR; }
@@ -201,10 +202,15 @@ struct Solver {
     return cnt;
   }
 
-  // Each vertex x in list[0..cnt) is S: recompute its least slack to S
-  // vertices outside its outermost node, and offer x to every vertex outside
-  // that node.
-  MW_FN void refresh(int cnt) {
+  // Each vertex x in list[0..cnt) has just become S: offer x to every vertex
+  // outside its outermost node, and, with `own`, recompute x's least slack to
+  // S vertices outside that node.  Without `own` x keeps the least slack it
+  // had as a free or T vertex, which is the same quantity: that holds when x
+  // had no S vertex in its outermost node before (a grow, or the children of
+  // an expanded T blossom), since every S vertex was offered to it and every
+  // dual change updated it; the new S vertices among themselves are covered
+  // by the offers.
+  MW_FN void refresh(int cnt, bool own) {
     for (int k = 0; k < cnt; ++k) MW_COUNT(refresh_vertex);
     for (int k = 0; k < cnt; ++k) {
       const int x = rd(list, k);
@@ -216,12 +222,14 @@ struct Solver {
         if (ty == tx) continue;
         const int64_t sl = slack(x, y);
         if (sl < best[y]) { best[y] = sl; bestS[y] = (int16_t)x; }
-        if (lab[ty] == S && sl < bk) { bk = sl; bi = y; }
+        if (own && lab[ty] == S && sl < bk) { bk = sl; bi = y; }
       }
-      wv.argmin(bk, bi);
-      wv.sync();
-      best[x] = bk;
-      bestS[x] = (int16_t)(bk < INF ? bi : -1);
+      if (own) {
+        wv.argmin(bk, bi);
+        wv.sync();
+        best[x] = bk;
+        bestS[x] = (int16_t)(bk < INF ? bi : -1);
+      }
       wv.sync();
     }
   }
@@ -325,13 +333,14 @@ struct Solver {
     base[b] = (int16_t)rd(base, A);
     z[b - cap] = 0;
     lab[b] = S;
+    tid[b] = (int16_t)rd(tid, A);
     par[b] = -1;
     wv.sync();
     for (int v = wv.lane; v < nv; v += WV::N)
       if (par[top[v]] == b) top[v] = (int16_t)b;
     wv.sync();
     const int cnt = collect([&](int y) { return top[y] == b; });
-    refresh(cnt);
+    refresh(cnt, true);   // S vertices inside b may have kept a partner now inside b
   }
 
   // dissolve the outermost T blossom B (dual zero): its children on the even
@@ -350,7 +359,8 @@ struct Solver {
       x = rd(cnext, x);
       if (++g > 2 * cap) { fail = true; return; }
     } while (x != first);
-    lab[c] = T; tS[c] = (int16_t)s; tT[c] = (int16_t)t;
+    const int16_t tree = (int16_t)rd(tid, B);
+    lab[c] = T; tS[c] = (int16_t)s; tT[c] = (int16_t)t; tid[c] = tree;
     const bool fwd = (k & 1) != 0;
     int pos = c;
     for (g = 0; pos != first; ++g) {
@@ -362,6 +372,7 @@ struct Solver {
       lab[a] = S;
       mark[a] = 1;
       lab[b] = T; tS[b] = (int16_t)ex; tT[b] = (int16_t)ey;
+      tid[a] = tid[b] = tree;
       pos = b;
     }
     base[B] = -1;
@@ -383,7 +394,7 @@ struct Solver {
       x = rd(cnext, x);
     } while (x != first && ++g <= 2 * cap);
     wv.sync();
-    refresh(cnt);
+    refresh(cnt, false);
   }
 
   // ---------------------------------------------------------------- solve
@@ -391,15 +402,18 @@ struct Solver {
   // vertex outside its outermost node
   MW_FN void recompute(int cnt) {
     for (int k = 0; k < cnt; ++k) MW_COUNT(recompute_vertex);
-    if (cnt >= WV::N / 4) {  // many: one vertex per lane, over the list of S vertices
-      int ns = 0;
-      for (int x0 = 0; x0 < nv; x0 += WV::N) {
-        const int x = x0 + wv.lane;
-        const bool take = x < nv && lab[top[x]] == S;
-        const int slot = wv.compact(take, ns);
-        if (take) slist[slot] = (int16_t)x;
-      }
-      wv.sync();
+    // the S vertices, in ascending order
+    int ns = 0;
+    for (int x0 = 0; x0 < nv; x0 += WV::N) {
+      const int x = x0 + wv.lane;
+      const bool take = x < nv && lab[top[x]] == S;
+      const int slot = wv.compact(take, ns);
+      if (take) slist[slot] = (int16_t)x;
+    }
+    wv.sync();
+    // many vertices, or few S vertices: one vertex per lane, each scanning
+    // the S list (a pass costs about as much as 1.5 wave minima)
+    if (2 * ns <= 3 * cnt || cnt >= WV::N / 4) {
       for (int k = wv.lane; k < cnt; k += WV::N) {
         const int y = list[k];
         const int ty = top[y];
@@ -436,34 +450,10 @@ struct Solver {
     }
   }
 
-  // root of the tree holding outermost node x (S or T), for a different x in
-  // every lane (plain reads)
-  MW_FN int root_of_lane(int x) const {
-    for (int g = 0; g < 2 * cap; ++g) {
-      if (lab[x] == T) {
-        x = top[tS[x]];
-      } else {
-        const int m = mate[base[x]];
-        if (m < 0) return x;
-        x = top[tS[top[m]]];
-      }
-    }
-    return -1;
-  }
-
-  // the same for one x shared by every lane
-  MW_FN int root_of(int x) const {
-    for (int g = 0; g < 2 * cap; ++g) {
-      if (rd(lab, x) == T) {
-        x = rd(top, rd(tS, x));
-      } else {
-        const int p = s_parent(x);
-        if (p < 0) return x;
-        x = p;
-      }
-    }
-    return -1;
-  }
+  // The tree of a labelled outermost node is identified by its exposed
+  // vertex (tid), set when the node is labelled: exposed vertices at the
+  // start, the tree of the edge's S end on a grow, the tree of the shrunk
+  // cycle on a shrink, the expanded blossom's tree on an expand.
 
   MW_FN void solve() {
     for (int x = wv.lane; x < nn; x += WV::N) {
@@ -514,7 +504,7 @@ struct Solver {
     }
     wv.sync();
     for (int v = wv.lane; v < nv; v += WV::N)
-      if (mate[v] < 0) lab[v] = S;
+      if (mate[v] < 0) { lab[v] = S; tid[v] = (int16_t)v; }
     wv.sync();
     {
       const int cnt = collect([&](int y) { (void)y; return true; });
@@ -558,7 +548,7 @@ struct Solver {
     for (int x = wv.lane; x < nn; x += WV::N) lab[x] = FREE;
     wv.sync();
     for (int v = wv.lane; v < nv; v += WV::N)
-      if (mate[v] < 0) lab[top[v]] = S;
+      if (mate[v] < 0) { lab[top[v]] = S; tid[top[v]] = (int16_t)v; }
     wv.sync();
     const int cnt = collect([&](int y) { (void)y; return true; });
     recompute(cnt);
@@ -623,17 +613,19 @@ struct Solver {
           MW_COUNT(grow);
           const int mb = rd(mate, rd(base, Bj));
           if (mb < 0) { fail = true; break; }
+          const int16_t tree = (int16_t)rd(tid, rd(top, i));
           lab[Bj] = T;
           tS[Bj] = (int16_t)i;
           tT[Bj] = (int16_t)j;
+          tid[Bj] = tree;
           const int Bm = rd(top, mb);
           lab[Bm] = S;
+          tid[Bm] = tree;
           wv.sync();
           const int cnt = collect([&](int y) { return top[y] == Bm; });
-          refresh(cnt);
+          refresh(cnt, false);
         } else {
-          const int ri = root_of(rd(top, i)), rj = root_of(Bj);
-          if (ri < 0 || rj < 0) { fail = true; break; }
+          const int ri = rd(tid, rd(top, i)), rj = rd(tid, Bj);
           if (ri != rj) {
             MW_COUNT(augment);
             // the two trees dissolve after the augmentation; the others stay
@@ -641,7 +633,7 @@ struct Solver {
               if (par[x] >= 0 || lab[x] == FREE || (x >= cap && base[x] < 0) ||
                   (x < cap && x >= nv))
                 continue;
-              const int r = root_of_lane(x);
+              const int r = tid[x];
               mark[x] = (int16_t)(r == ri || r == rj);
             }
             wv.sync();
