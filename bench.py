@@ -79,6 +79,12 @@ def main():
     ap.add_argument("--gate-epochs", type=int, default=4)
     ap.add_argument("--gate-eval", type=int, default=100_000)
     ap.add_argument("--mixed-n", type=int, default=100000)
+    ap.add_argument("--st-L", type=int, default=0,
+                    help="space-time workload: code distance (default 7)")
+    ap.add_argument("--st-rounds", type=int, default=0,
+                    help="space-time workload: measurement rounds (default = L)")
+    ap.add_argument("--st-sweeps", type=int, default=0,
+                    help="space-time workload: sweeps (default 16 L^2)")
     ap.add_argument("--init", choices=["greedy", "mwpm"], default="mwpm",
                     help="class starts: Sec. III's exact enhanced matching (default), or the "
                          "greedy matching")
@@ -105,7 +111,7 @@ def main():
         elif args.workload == "randomscan":
             args.cpu = cpu_baseline(min(args.cpu_sample, 64), ns, random_scan=True,
                                     workers=host_cores())
-        else:
+        elif not args.st_L:   # the oracle baseline is for the default space-time workload
             args.cpu = cpu_baseline_spacetime(host_cores())
 
     import torch
@@ -274,11 +280,7 @@ def main():
                    "probabilities and corrections copied back, on the decode stream, "
                    "synchronised per batch"}
 
-    if args.copy_probe_mb:
-        src = torch.ones((args.copy_probe_mb << 20,), dtype=torch.uint8, device=dev)
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
+    copy_probe(args, torch, dev)
 
     cpu = args.cpu
 
@@ -359,6 +361,16 @@ def chain_traffic(n):
     if h.hexdigest()[:16] != CHAIN_TRAFFIC_SHA:
         return None
     return CHAIN_TRAFFIC_PER_SYNDROME * n
+
+
+def copy_probe(args, torch, dev):
+    """A plain device-to-device copy of --copy-probe-mb MiB, for scaling the
+    HBM byte counters of a profiled run."""
+    if args.copy_probe_mb:
+        src = torch.ones((args.copy_probe_mb << 20,), dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
 
 
 def bench_mixed(args, mc, torch, dev):
@@ -657,6 +669,10 @@ def bench_spacetime(args, mc, torch, dev):
     Also the logical error of decoding the last round alone with the
     single-round decoder (L^2 sweeps), on the same histories."""
     Ls, T, p, pm, chains, sweeps = ST_L, ST_T, ST_P, ST_PM, ST_CHAINS, ST_SWEEPS
+    if args.st_L:
+        Ls = args.st_L
+        T = args.st_rounds or Ls
+        sweeps = args.st_sweeps or 16 * Ls * Ls
     n = 32768
     steps, warm = args.steps, args.warmup
     nq, ns = mc.geometry(Ls)
@@ -700,6 +716,7 @@ def bench_spacetime(args, mc, torch, dev):
     z1.record(stream)
     torch.cuda.synchronize()
     chain_ms = step_ms - z0.elapsed_time(z1) / steps
+    copy_probe(args, torch, dev)
     moves_per_history = 4 * chains * sweeps * (T * ns + 2 * (T - 1) * nq)
     achieved = n * moves_per_history * OPS_PER_UPDATE / (chain_ms * 1e-3) / 1e12
     fails = sum(int((c != t).sum().item()) for c, t in zip(chosen, truth[warm:]))
@@ -711,21 +728,23 @@ def bench_spacetime(args, mc, torch, dev):
                               chains=chains, want_correction=False)
         last_fail += int((out["chosen"] != truth[warm + i]).sum().item())
     line = {
-        "metric": "decoded measurement histories/sec, imperfect measurements (L=7, 7 rounds)",
+        "metric": f"decoded measurement histories/sec, imperfect measurements (L={Ls}, {T} rounds)",
         "value": total / wall, "unit": "histories/s",
         "moves_per_s": total / wall * moves_per_history,
         "n_gpus": 1, "steps": steps, "warmup": warm, "ms_per_step": wall * 1e3 / steps,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32+f64",
         "data": "synthetic: depolarizing data errors and wrong outcomes from the library's "
                 "Philox sampler",
-        "config": {"workload": "planar code L=7, T=7 measurement rounds (last perfect), "
-                               "p = p_M = 0.02, 4 classes x 4 chains, 784 sweeps of all "
+        "config": {"workload": f"planar code L={Ls}, T={T} measurement rounds (last perfect), "
+                               f"p = p_M = 0.02, 4 classes x 4 chains, {sweeps} sweeps of all "
                                f"spatial and time moves, {n} histories per step",
                    "L": Ls, "rounds": T, "p": p, "p_m": pm, "chains_per_class": chains,
                    "sweeps": sweeps, "batch": n, "moves_per_history": moves_per_history},
         "logical_error": {"rate": fails / total, "samples": total,
                           "last_round_only": last_fail / total},
-        "roofline": {"bound": "alu", "kernel": "st_chain_fast_kernel<7> (space-time chains)",
+        "roofline": {"bound": "alu",
+                     "kernel": (f"st_chain_fast_kernel<{Ls}>" if Ls <= 12 else
+                                f"st_chain_win_kernel<{Ls}>") + " (space-time chains)",
                      "achieved": achieved, "peak": PEAK_INT_OPS / 1e12, "unit": "Tops/s",
                      "frac": achieved / (PEAK_INT_OPS / 1e12), "traffic": None,
                      "chain_ms_per_launch": chain_ms, "ops_per_update": OPS_PER_UPDATE,

@@ -212,11 +212,11 @@ hipError_t launch_sample_items(const ItemDesc* items, const GroupDesc* groups, i
 // ---- imperfect measurements (space-time hypotheses) ---------------------------
 // LDS of one 64-chain workgroup of the space-time kernel (lattice tables)
 // must stay within this.
-constexpr size_t SPACETIME_LDS_MAX = 160 * 1024;
-// Codes up to this L run the register-resident kernel; larger ones the
-// kernel that reads and writes the hypothesis buffer per move.
-constexpr int SPACETIME_FAST_L_MAX = 13;
-size_t spacetime_lds_bytes(int L, int T);
+// Codes up to this L run the register-interval kernel, larger ones the
+// streaming-window kernel (spacetime_win.h, one translation unit per L).
+constexpr int SPACETIME_FAST_L_MAX = 12;
+constexpr int SPACETIME_WIN_L_MIN = SPACETIME_FAST_L_MAX + 1;
+constexpr int SPACETIME_WIN_L_MAX = MCMC_L_MAX;
 struct SpaceTimeArgs {
   int32_t L, T, chains, burn, sweep_end;
   int64_t n;                    // observation histories

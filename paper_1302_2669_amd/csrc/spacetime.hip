@@ -29,19 +29,17 @@
 // current interval (spatial half) or of intervals t, t+1 and round t's
 // outcomes (time half) in registers, where every qubit, site and stabilizer
 // index is a compile-time constant; the buffer is then read and written once
-// per interval.  Above, st_chain_kernel reads and writes the buffer per move,
-// with per-site qubit lists and per-qubit stabilizer lists in LDS.  Neither
+// per interval.  Larger codes run a templated kernel that keeps only a
+// streaming window of those words in registers (spacetime_win.h).  Neither
 // holds hypotheses in LDS, so occupancy is set by registers alone.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-#include "device_common.h"
-#include "internal.h"
+#include "spacetime_common.h"
 
 namespace mcmc {
 namespace {
 
-constexpr int ST_LANES = 64;
 constexpr uint32_t ST_NONE = 0xFFFFu;
 constexpr int ST_SAMPLE_NQ = 2048;   // accumulated-error bytes of the sampler
 constexpr int ST_FAST_L_MAX = SPACETIME_FAST_L_MAX;
@@ -127,285 +125,7 @@ __global__ void __launch_bounds__(256) st_last_kernel(int64_t n, int T, int nsta
   last[i] = obs[(h * T + (T - 1)) * nstab + (i - h * nstab)] != 0;
 }
 
-// ---- chains -----------------------------------------------------------------
-__global__ void __launch_bounds__(ST_LANES) st_chain_kernel(const SpaceTimeArgs a) {
-  extern __shared__ uint32_t st_lds[];
-  const int L = a.L, T = a.T;
-  const int nq = 2 * L * L - 2 * L + 1;
-  const int nstab = 2 * L * (L - 1);
-  const int nstar = L * (L - 1);
-  const int WQ = (nq + 15) / 16;       // data words per interval
-  const int WM = (nstab + 31) / 32;    // outcome words per round
-  const int lane = threadIdx.x;
-  uint32_t* site_q = st_lds;                       // [nstab][2]: 4 qubits (16 bit each)
-  uint32_t* qubit_s = site_q + 2 * nstab;          // [nq][2]: plaquettes, stars of q
-  uint32_t* tthr = qubit_s + 2 * nq;               // [25] time-move thresholds
-
-  const int side = 2 * L - 1;
-  for (int s = lane; s < nstab; s += ST_LANES) {
-    uint32_t q[4] = {ST_NONE, ST_NONE, ST_NONE, ST_NONE};
-    int r, c;
-    if (s < nstar) { r = 2 * (s / L) + 1; c = 2 * (s % L); }
-    else { const int k = s - nstar; r = 2 * (k / (L - 1)); c = 2 * (k % (L - 1)) + 1; }
-    int k = 0;
-    if (r > 0) q[k++] = (uint32_t)(((r - 1) * side + c) >> 1);
-    if (r < side - 1) q[k++] = (uint32_t)(((r + 1) * side + c) >> 1);
-    if (c > 0) q[k++] = (uint32_t)((r * side + c - 1) >> 1);
-    if (c < side - 1) q[k++] = (uint32_t)((r * side + c + 1) >> 1);
-    site_q[2 * s] = pack2(q[0], q[1]);
-    site_q[2 * s + 1] = pack2(q[2], q[3]);
-  }
-  for (int qi = lane; qi < nq; qi += ST_LANES) {
-    // grid cell of qubit qi: index = (r * side + c) / 2 with r + c even
-    const int r = (2 * qi) / side;
-    const int c = 2 * qi - r * side;
-    uint32_t pl[2] = {ST_NONE, ST_NONE}, sr[2] = {ST_NONE, ST_NONE};
-    int np = 0, ns = 0;
-    const int dr[4] = {-1, 1, 0, 0}, dc[4] = {0, 0, -1, 1};
-    for (int d = 0; d < 4; ++d) {
-      const int rr = r + dr[d], cc = c + dc[d];
-      if (rr < 0 || rr >= side || cc < 0 || cc >= side) continue;
-      if (rr & 1) {  // star at (odd, even)
-        sr[ns++] = (uint32_t)(((rr - 1) / 2) * L + cc / 2);
-      } else {       // plaquette at (even, odd)
-        pl[np++] = (uint32_t)(nstar + (rr / 2) * (L - 1) + (cc - 1) / 2);
-      }
-    }
-    qubit_s[2 * qi] = pack2(pl[0], pl[1]);
-    qubit_s[2 * qi + 1] = pack2(sr[0], sr[1]);
-  }
-  if (lane < 25) tthr[lane] = a.t_thr[lane];
-  __syncthreads();
-  const uint32_t sp1 = a.sp_thr[0], sp2 = a.sp_thr[1], sp3 = a.sp_thr[2], sp4 = a.sp_thr[3];
-  const uint32_t t_always = a.t_always;
-
-  const int64_t task = (int64_t)blockIdx.x * ST_LANES + lane;
-  if (task >= a.n_tasks) return;
-  // the hypothesis in global memory, word-major over all chains (a wave's
-  // accesses to one word are one coalesced 256-byte line)
-  const int64_t stride = a.n_tasks;
-  uint32_t* Ew = a.state + task;                        // [T*WQ][stride]
-  uint32_t* Mw = Ew + (int64_t)T * WQ * stride;         // [(T-1)*WM][stride]
-  const int C = a.chains;
-  const int64_t item = task / (4 * C);
-  const int rem = (int)(task - item * 4 * C);
-  const int cls = rem / C, chain = rem % C;
-  const uint32_t sid = a.ids ? a.ids[item] : (uint32_t)item;
-
-  // class start: every flipped outcome before the last round blamed on the
-  // measurement (M_t = s_t), no data error before the last interval, and the
-  // class-cls matching start of the last round's syndrome in interval T-1
-  int32_t n = 0, m = 0;
-  for (int k = 0; k < (T - 1) * WQ; ++k) Ew[k * stride] = 0u;
-  {
-    const uint8_t* b = a.reps + (item * 4 + cls) * nq;
-    for (int w = 0; w < WQ; ++w) {
-      uint32_t word = 0;
-      for (int f = 0; f < 16; ++f) {
-        const int q = 16 * w + f;
-        if (q < nq) word |= (uint32_t)(b[q] & 3u) << (2 * f);
-      }
-      Ew[(int64_t)((T - 1) * WQ + w) * stride] = word;
-    }
-    n = a.rep_weight[item * 4 + cls];
-  }
-  for (int t = 0; t + 1 < T; ++t) {
-    const uint8_t* o = a.obs + (item * T + t) * nstab;
-    for (int w = 0; w < WM; ++w) {
-      uint32_t word = 0;
-      for (int b = 0; b < 32; ++b) {
-        const int k = 32 * w + b;
-        if (k < nstab && o[k] != 0) word |= 1u << b;
-      }
-      Mw[(int64_t)(t * WM + w) * stride] = word;
-      m += __builtin_popcount(word);
-    }
-  }
-
-  const uint32_t ctr3 = (3u << 30) | ((uint32_t)cls << 28) | (1u << 20) | (uint32_t)chain;
-  int64_t Sn = 0, Sm = 0, Acnt = 0;
-  for (int sweep = 0; sweep < a.sweep_end; ++sweep) {
-    const bool counted = sweep >= a.burn;
-    uint4 blk = make_uint4(0, 0, 0, 0);
-    uint32_t d = 0;
-    auto draw = [&]() -> uint32_t {
-      if ((d & 3u) == 0)
-        blk = philox4x32_10(make_uint4(d >> 2, (uint32_t)sweep, sid, ctr3), a.k0, a.k1);
-      const uint32_t u = word_of(blk, (int)(d & 3u));
-      ++d;
-      return u;
-    };
-    // spatial moves: the site's four words are read at once (a missing
-    // neighbour reads word 0 of the interval and flips nothing), the weight
-    // change of each code comes from a 2-bit-field constant, and an accepted
-    // move writes each word back once with the flips of every qubit of the
-    // site in that word (two qubits of a site may share a word)
-    for (int t = 0; t < T; ++t) {
-      uint32_t* E = Ew + (int64_t)t * WQ * stride;
-      for (int s = 0; s < nstab; ++s) {
-        const uint32_t u = draw();
-        const bool star = s < nstar;
-        const uint32_t qq[4] = {site_q[2 * s] & 0xFFFFu, site_q[2 * s] >> 16,
-                                site_q[2 * s + 1] & 0xFFFFu, site_q[2 * s + 1] >> 16};
-        int64_t widx[4];
-        uint32_t sh[4];
-        bool valid[4];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          valid[k] = qq[k] != ST_NONE;
-          widx[k] = valid[k] ? (int64_t)(qq[k] >> 4) * stride : 0;
-          sh[k] = 2u * (qq[k] & 15u);
-        }
-        uint32_t w[4];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) w[k] = E[widx[k]];
-        // (1 - other)(1 - 2 own) + 1 by code x + 2z, own = x for a star
-        const uint32_t lut = star ? 0x52u : 0x46u;
-        int delta = 0;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          const uint32_t code = (w[k] >> sh[k]) & 3u;
-          delta += valid[k] ? (int)((lut >> (2u * code)) & 3u) - 1 : 0;
-        }
-        const uint32_t t12 = delta == 1 ? sp1 : sp2;
-        const uint32_t t34 = delta == 3 ? sp3 : sp4;
-        const uint32_t thr = delta <= 2 ? t12 : t34;
-        if ((delta <= 0) | (u < thr)) {
-          const uint32_t bit = star ? 1u : 2u;
-          uint32_t mask[4];
-#pragma unroll
-          for (int k = 0; k < 4; ++k) mask[k] = valid[k] ? bit << sh[k] : 0u;
-#pragma unroll
-          for (int k = 0; k < 4; ++k) {
-            uint32_t v = w[k];
-#pragma unroll
-            for (int j = 0; j < 4; ++j) v ^= widx[j] == widx[k] ? mask[j] : 0u;
-            E[widx[k]] = v;   // words read twice get the same value twice
-          }
-          n += delta;
-          ++Acnt;
-        }
-      }
-    }
-    if (counted) { Sn += n; Sm += m; }
-    // time moves (two unused draws close every round), branch-free as above:
-    // a missing stabilizer reads word 0 of the round and flips nothing
-    for (int t = 0; t + 1 < T; ++t, d += 2) {
-      uint32_t* E0 = Ew + (int64_t)t * WQ * stride;
-      uint32_t* E1 = E0 + (int64_t)WQ * stride;
-      uint32_t* Mt = Mw + (int64_t)t * WM * stride;
-      for (int q = 0; q < nq; ++q) {
-        const int64_t wq = (int64_t)(q >> 4) * stride;
-        const uint32_t sh = 2u * (uint32_t)(q & 15);
-        for (int kind = 0; kind < 2; ++kind) {
-          const uint32_t u = draw();
-          const uint32_t ss = qubit_s[2 * q + kind];
-          const uint32_t sa = ss & 0xFFFFu, sb = ss >> 16;
-          const bool va = sa != ST_NONE, vb = sb != ST_NONE;
-          const int64_t ia = va ? (int64_t)(sa >> 5) * stride : 0;
-          const int64_t ib = vb ? (int64_t)(sb >> 5) * stride : 0;
-          const uint32_t w0 = E0[wq], w1 = E1[wq];
-          const uint32_t c0 = (w0 >> sh) & 3u, c1 = (w1 >> sh) & 3u;
-          const uint32_t ma = Mt[ia], mb = Mt[ib];
-          // X on the qubit changes the weight by (1 - z)(1 - 2x), Z by
-          // (1 - x)(1 - 2z): plus one, by code x + 2z
-          const uint32_t lut = kind == 0 ? 0x52u : 0x46u;
-          const int dn = (int)((lut >> (2u * c0)) & 3u) + (int)((lut >> (2u * c1)) & 3u) - 2;
-          const int dm = (va ? 1 - 2 * (int)((ma >> (sa & 31u)) & 1u) : 0) +
-                         (vb ? 1 - 2 * (int)((mb >> (sb & 31u)) & 1u) : 0);
-          const int e = (dn + 2) * 5 + (dm + 2);
-          if (((t_always >> e) & 1u) | (u < tthr[e])) {
-            const uint32_t bit = (kind == 0 ? 1u : 2u) << sh;
-            const uint32_t fa = va ? 1u << (sa & 31u) : 0u;
-            const uint32_t fb = vb ? 1u << (sb & 31u) : 0u;
-            E0[wq] = w0 ^ bit;
-            E1[wq] = w1 ^ bit;
-            // the two stabilizers' outcomes may share a word
-            Mt[ia] = ma ^ fa ^ (ia == ib ? fb : 0u);
-            Mt[ib] = mb ^ fb ^ (ia == ib ? fa : 0u);
-            n += dn;
-            m += dm;
-            ++Acnt;
-          }
-        }
-      }
-    }
-    if (counted) { Sn += n; Sm += m; }
-  }
-
-  const int64_t out = item * 4 * C + rem;
-  a.Sn[out] = Sn;
-  a.Sm[out] = Sm;
-  a.A[out] = Acnt;
-  a.n_final[out] = n;
-  a.m_final[out] = m;
-  if (a.final_c && chain == 0) {  // accumulated data error of this hypothesis
-    uint8_t* o = a.final_c + (item * 4 + cls) * nq;
-    for (int w = 0; w < WQ; ++w) {
-      uint32_t word = 0;
-      for (int t = 0; t < T; ++t) word ^= Ew[(int64_t)(t * WQ + w) * stride];
-      for (int f = 0; f < 16; ++f) {
-        const int q = 16 * w + f;
-        if (q < nq) o[q] = (uint8_t)((word >> (2 * f)) & 3u);
-      }
-    }
-  }
-}
-
 // ---- chains, register-resident intervals (small codes) -----------------------
-template <int L>
-struct StGeo {
-  static constexpr int SIDE = 2 * L - 1;
-  static constexpr int NQ = 2 * L * L - 2 * L + 1;
-  static constexpr int NSTAB = 2 * L * (L - 1);
-  static constexpr int NSTAR = L * (L - 1);
-  static constexpr int WQ = (NQ + 15) / 16;
-  static constexpr int WM = (NSTAB + 31) / 32;
-  // qubit k (0..3) of site s in the generic kernel's order, -1 if missing
-  static constexpr int site_qubit(int s, int k) {
-    int r = 0, c = 0;
-    if (s < NSTAR) { r = 2 * (s / L) + 1; c = 2 * (s % L); }
-    else { r = 2 * ((s - NSTAR) / (L - 1)); c = 2 * ((s - NSTAR) % (L - 1)) + 1; }
-    int q[4] = {-1, -1, -1, -1};
-    int n = 0;
-    if (r > 0) q[n++] = ((r - 1) * SIDE + c) / 2;
-    if (r < SIDE - 1) q[n++] = ((r + 1) * SIDE + c) / 2;
-    if (c > 0) q[n++] = (r * SIDE + c - 1) / 2;
-    if (c < SIDE - 1) q[n++] = (r * SIDE + c + 1) / 2;
-    return q[k];
-  }
-  // stabilizer k (0..1) anticommuting with X (kind 0: plaquettes) or Z
-  // (kind 1: stars) on qubit q, -1 if missing
-  static constexpr int qubit_stab(int q, int kind, int k) {
-    const int r = (2 * q) / SIDE, c = 2 * q - r * SIDE;
-    int pl[2] = {-1, -1}, st[2] = {-1, -1};
-    int np = 0, ns = 0;
-    const int dr[4] = {-1, 1, 0, 0}, dc[4] = {0, 0, -1, 1};
-    for (int d = 0; d < 4; ++d) {
-      const int rr = r + dr[d], cc = c + dc[d];
-      if (rr < 0 || rr >= SIDE || cc < 0 || cc >= SIDE) continue;
-      if (rr & 1) st[ns++] = ((rr - 1) / 2) * L + cc / 2;
-      else pl[np++] = NSTAR + (rr / 2) * (L - 1) + (cc - 1) / 2;
-    }
-    return kind == 0 ? pl[k] : st[k];
-  }
-};
-
-// After every move the state words pass through an empty asm statement, and
-// each Philox block index is made opaque: a flip only touches bits that the
-// compiler can prove other moves do not read, so without the fences it
-// extracts every move's fields from the words as loaded and keeps them all
-// live (hundreds of registers, then scratch).
-template <int N>
-__device__ __forceinline__ void st_fence(uint32_t (&x)[N]) {
-#pragma unroll
-  for (int i = 0; i < N; ++i) asm volatile("" : "+v"(x[i]));
-}
-__device__ __forceinline__ uint32_t st_opaque(uint32_t v) {
-  asm volatile("" : "+v"(v));
-  return v;
-}
-
 template <int L>
 // 8 waves per SIMD (64 registers), the most a SIMD holds: the move sequence is
 // latency-bound (Philox chains, table loads), and more resident waves hide
@@ -431,40 +151,12 @@ st_chain_fast_kernel(const SpaceTimeArgs a) {
   const int64_t stride = a.n_tasks;
   uint32_t* Ew = a.state + task;                        // [T*WQ][stride]
   uint32_t* Mw = Ew + (int64_t)T * WQ * stride;         // [(T-1)*WM][stride]
-  const int C = a.chains;
-  const int64_t item = task / (4 * C);
-  const int rem = (int)(task - item * 4 * C);
-  const int cls = rem / C, chain = rem % C;
-  const uint32_t sid = a.ids ? a.ids[item] : (uint32_t)item;
-
+  const StTask tk = st_task(a, task);
+  const uint32_t sid = tk.sid;
   int32_t n = 0, m = 0;
-  for (int k = 0; k < (T - 1) * WQ; ++k) Ew[k * stride] = 0u;
-  {
-    const uint8_t* b = a.reps + (item * 4 + cls) * NQ;
-    for (int w = 0; w < WQ; ++w) {
-      uint32_t word = 0;
-      for (int f = 0; f < 16; ++f) {
-        const int q = 16 * w + f;
-        if (q < NQ) word |= (uint32_t)(b[q] & 3u) << (2 * f);
-      }
-      Ew[((T - 1) * WQ + w) * stride] = word;
-    }
-    n = a.rep_weight[item * 4 + cls];
-  }
-  for (int t = 0; t + 1 < T; ++t) {
-    const uint8_t* o = a.obs + (item * T + t) * NSTAB;
-    for (int w = 0; w < WM; ++w) {
-      uint32_t word = 0;
-      for (int b = 0; b < 32; ++b) {
-        const int k = 32 * w + b;
-        if (k < NSTAB && o[k] != 0) word |= 1u << b;
-      }
-      Mw[(t * WM + w) * stride] = word;
-      m += __builtin_popcount(word);
-    }
-  }
+  st_start(a, tk, NQ, NSTAB, WQ, WM, Ew, Mw, stride, n, m);
 
-  const uint32_t ctr3 = (3u << 30) | ((uint32_t)cls << 28) | (1u << 20) | (uint32_t)chain;
+  const uint32_t ctr3 = (3u << 30) | ((uint32_t)tk.cls << 28) | (1u << 20) | (uint32_t)tk.chain;
   const uint32_t always = a.t_always;
   int64_t Sn = 0, Sm = 0, Acnt = 0;
   for (int sweep = 0; sweep < a.sweep_end; ++sweep) {
@@ -578,24 +270,7 @@ st_chain_fast_kernel(const SpaceTimeArgs a) {
     }
     if (counted) { Sn += n; Sm += m; }
   }
-
-  const int64_t out = item * 4 * C + rem;
-  a.Sn[out] = Sn;
-  a.Sm[out] = Sm;
-  a.A[out] = Acnt;
-  a.n_final[out] = n;
-  a.m_final[out] = m;
-  if (a.final_c && chain == 0) {
-    uint8_t* o = a.final_c + (item * 4 + cls) * NQ;
-    for (int w = 0; w < WQ; ++w) {
-      uint32_t word = 0;
-      for (int t = 0; t < T; ++t) word ^= Ew[(t * WQ + w) * stride];
-      for (int f = 0; f < 16; ++f) {
-        const int q = 16 * w + f;
-        if (q < NQ) o[q] = (uint8_t)((word >> (2 * f)) & 3u);
-      }
-    }
-  }
+  st_finish(a, tk, NQ, WQ, Ew, stride, Sn, Sm, Acnt, n, m);
 }
 
 // ---- estimator --------------------------------------------------------------
@@ -643,13 +318,6 @@ unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1) / per)
 
 }  // namespace
 
-size_t spacetime_lds_bytes(int L, int T) {
-  (void)T;  // the hypotheses live in the workspace; LDS holds the lattice tables
-  const int nq = 2 * L * L - 2 * L + 1, nstab = 2 * L * (L - 1);
-  const size_t words = (size_t)2 * nstab + (size_t)2 * nq + 25;
-  return words * sizeof(uint32_t);
-}
-
 hipError_t launch_spacetime_sample(int L, int T, uint32_t thr_d, uint32_t thr_m, uint32_t k0,
                                    uint32_t k1, uint32_t id_base, int64_t n, uint8_t* obs,
                                    uint8_t* true_class, hipStream_t s) {
@@ -679,6 +347,16 @@ hipError_t launch_fast(const SpaceTimeArgs& a, hipStream_t s) {
 }
 
 template <int LL>
+hipError_t dispatch_window(const SpaceTimeArgs& a, hipStream_t s) {
+  if constexpr (LL > SPACETIME_WIN_L_MAX) {
+    return hipErrorInvalidValue;
+  } else {
+    if (a.L == LL) return launch_spacetime_win_L<LL>(a, s);
+    return dispatch_window<LL + 1>(a, s);
+  }
+}
+
+template <int LL>
 hipError_t dispatch_fast(const SpaceTimeArgs& a, hipStream_t s) {
   if constexpr (LL > ST_FAST_L_MAX) {
     return hipErrorInvalidValue;
@@ -693,12 +371,7 @@ hipError_t dispatch_fast(const SpaceTimeArgs& a, hipStream_t s) {
 hipError_t launch_spacetime_chains(const SpaceTimeArgs& a, hipStream_t s) {
   if (a.n_tasks == 0) return hipSuccess;
   if (a.L <= ST_FAST_L_MAX) return dispatch_fast<2>(a, s);
-  if (!a.state) return hipErrorInvalidValue;
-  const size_t lds = spacetime_lds_bytes(a.L, a.T);
-  if (lds > SPACETIME_LDS_MAX) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(st_chain_kernel, dim3(blocks_for(a.n_tasks, ST_LANES)), dim3(ST_LANES), lds,
-                     s, a);
-  return hipGetLastError();
+  return dispatch_window<SPACETIME_WIN_L_MIN>(a, s);
 }
 
 hipError_t launch_spacetime_decide(const SpaceTimeArgs& a, hipStream_t s) {

@@ -23,7 +23,6 @@ int check_st(const mcmc_spacetime_params* prm, int64_t n) {
   if (prm->chains < 1 || prm->chains > MCMC_CHAINS_MAX) return MCMC_ERANGE;
   if (prm->burn < 0 || prm->sweeps < 0) return MCMC_ERANGE;
   if ((int64_t)prm->burn + prm->sweeps > MCMC_SWEEPS_MAX) return MCMC_ERANGE;
-  if (spacetime_lds_bytes(prm->L, prm->rounds) > SPACETIME_LDS_MAX) return MCMC_ERANGE;
   const int64_t T = n * 4 * (int64_t)prm->chains;
   if (n > 0 && (T / n / 4 != prm->chains || T > ((int64_t)1 << 36))) return MCMC_ERANGE;
   return MCMC_OK;

@@ -1,0 +1,6 @@
+// Space-time chains at L = 22 with the streaming register window.
+#include "spacetime_win.h"
+
+namespace mcmc {
+template hipError_t launch_spacetime_win_L<22>(const SpaceTimeArgs& a, hipStream_t s);
+}  // namespace mcmc

@@ -53,11 +53,16 @@ CASES = [
     (11, 3, 0.04, 0.06, 1, 0, 2, 2),
     (12, 2, 0.05, 0.05, 1, 0, 1, 1),
     (13, 2, 0.04, 0.04, 1, 1, 1, 2),
-    (14, 2, 0.05, 0.05, 1, 0, 1, 1),
+    (14, 2, 0.05, 0.05, 1, 0, 1, 1),     # L >= 13: streaming-window kernel
+    (15, 3, 0.04, 0.04, 2, 1, 2, 2),
+    (16, 2, 0.05, 0.05, 2, 0, 1, 1),
     (17, 2, 0.05, 0.05, 1, 0, 1, 1),
+    (17, 4, 0.03, 0.03, 2, 1, 1, 1),
+    (18, 2, 0.04, 0.04, 1, 0, 1, 1),
     (25, 2, 0.03, 0.03, 1, 0, 1, 1),
     (3, 64, 0.05, 0.05, 1, 0, 1, 2),     # the most rounds, register kernel
-    (14, 24, 0.02, 0.02, 1, 0, 1, 1),    # many rounds, buffer kernel
+    (14, 24, 0.02, 0.02, 1, 0, 1, 1),    # many rounds, streaming-window kernel
+    (21, 12, 0.02, 0.02, 1, 0, 1, 1),    # many rounds, a large code
 ]
 
 
