@@ -92,6 +92,59 @@ struct StWindow {
 
   static constexpr Spatial SP = spatial();
   static constexpr Time TM = time();
+
+  // The plans are sound: replaying them, every word a move reads or writes
+  // is loaded and not yet stored, every word is loaded and stored once per
+  // pass, and none is left loaded at a pass's end.
+  static constexpr bool any(const uint64_t (&m)[2]) { return (m[0] | m[1]) != 0; }
+  static constexpr bool has(const uint64_t (&m)[2], int w) { return (m[w >> 6] >> (w & 63)) & 1ull; }
+  static constexpr bool spatial_sound() {
+    for (int pass = 0; pass < 2; ++pass) {
+      const int s0 = pass == 0 ? 0 : NSTAR, s1 = pass == 0 ? NSTAR : NSTAB;
+      bool live[128] = {};
+      int loads[128] = {}, stores[128] = {};
+      for (int s = s0; s < s1; ++s) {
+        if (any(SP.load[s]))
+          for (int w = 0; w < WQ; ++w)
+            if (has(SP.load[s], w)) { if (live[w]) return false; live[w] = true; ++loads[w]; }
+        for (int k = 0; k < 4; ++k) {
+          const int q = G::site_qubit(s, k);
+          if (q >= 0 && !live[q >> 4]) return false;
+        }
+        if (any(SP.store[s]))
+          for (int w = 0; w < WQ; ++w)
+            if (has(SP.store[s], w)) { if (!live[w]) return false; live[w] = false; ++stores[w]; }
+      }
+      for (int w = 0; w < WQ; ++w)
+        if (live[w] || loads[w] != stores[w] || loads[w] > 1) return false;
+    }
+    return true;
+  }
+  static constexpr bool time_sound() {
+    bool le[128] = {}, lm[128] = {};
+    for (int r = 0; r < 2 * NQ; ++r) {
+      if (any(TM.load_e[r]))
+        for (int w = 0; w < WQ; ++w)
+          if (has(TM.load_e[r], w)) { if (le[w]) return false; le[w] = true; }
+      if (any(TM.load_m[r]))
+        for (int w = 0; w < WM; ++w)
+          if (has(TM.load_m[r], w)) { if (lm[w]) return false; lm[w] = true; }
+      if (!le[(r >> 1) >> 4]) return false;
+      for (int k = 0; k < 2; ++k) {
+        const int st = G::qubit_stab(r >> 1, r & 1, k);
+        if (st >= 0 && !lm[st >> 5]) return false;
+      }
+      if (any(TM.store_e[r]))
+        for (int w = 0; w < WQ; ++w)
+          if (has(TM.store_e[r], w)) { if (!le[w]) return false; le[w] = false; }
+      if (any(TM.store_m[r]))
+        for (int w = 0; w < WM; ++w)
+          if (has(TM.store_m[r], w)) { if (!lm[w]) return false; lm[w] = false; }
+    }
+    for (int w = 0; w < 128; ++w)
+      if (le[w] || lm[w]) return false;
+    return true;
+  }
 };
 
 // address of word W of a plane: the index passes through a register first,
@@ -130,6 +183,8 @@ __global__ void __launch_bounds__(ST_LANES) __attribute__((amdgpu_waves_per_eu(8
 st_chain_win_kernel(const SpaceTimeArgs a) {
   using G = StGeo<L>;
   using P = StWindow<L>;
+  static_assert(P::spatial_sound(), "spatial load/store plan");
+  static_assert(P::time_sound(), "time load/store plan");
   constexpr int NQ = G::NQ, NSTAB = G::NSTAB, NSTAR = G::NSTAR, WQ = G::WQ, WM = G::WM;
   __shared__ uint32_t tthr[32];                     // [25] time-move thresholds
   __shared__ uint32_t sthr[4];                      // spatial thresholds
