@@ -48,12 +48,26 @@ def _compile(src, obj):
     return obj
 
 
+def _includes(path, seen):
+    """The project files `path` includes (quoted includes, transitively)."""
+    if path in seen or not os.path.exists(path):
+        return
+    seen.add(path)
+    with open(path, "r") as fh:
+        for line in fh:
+            line = line.strip()
+            if line.startswith("#include \""):
+                name = line.split('"')[1]
+                _includes(os.path.normpath(os.path.join(os.path.dirname(path), name)), seen)
+
+
 def _key(src):
-    """Hash of a source, every header it may include and the flags."""
+    """Hash of a source, every project header it includes and the flags."""
     h = hashlib.sha256()
     h.update(" ".join(COMMON).encode())
-    hdrs = sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".h"))
-    for f in [src] + hdrs + [os.path.join(HERE, "..", "include", "mcmcdec.h")]:
+    files = set()
+    _includes(os.path.normpath(src), files)
+    for f in sorted(files):
         with open(f, "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:24]
