@@ -73,6 +73,17 @@ def _key(src):
     return h.hexdigest()[:24]
 
 
+def _cost(src):
+    """Rough compile cost of a source, for ordering the builds."""
+    name = os.path.basename(src)
+    if name.startswith("spacetime_win_"):
+        L = int(name[len("spacetime_win_"):-len(".hip")])
+        return 1000 + L * L
+    if name.startswith(("chain_", "spacetime", "mwpm", "cnn")):
+        return 500 + os.path.getsize(src) / 1000
+    return os.path.getsize(src) / 1000
+
+
 def build(jobs=None, verbose=True, cache=False):
     """Compile every source and link the library.  With cache=True (for
     development) an object whose source, headers and flags are unchanged is
@@ -92,8 +103,11 @@ def build(jobs=None, verbose=True, cache=False):
                 o = os.path.join(tmp, os.path.basename(s) + ".o")
                 todo.append((s, o))
             objs.append(o)
+        # longest compiles first (the unrolled space-time kernels, largest
+        # code first, then the chain kernels), so that the pool ends together
         with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
-            futs = [ex.submit(_compile, s, o + ".part") for s, o in todo]
+            futs = [ex.submit(_compile, s, o + ".part")
+                    for s, o in sorted(todo, key=lambda t: _cost(t[0]), reverse=True)]
             for f in futs:
                 f.result()
         for s, o in todo:
