@@ -203,32 +203,20 @@ struct Solver {
   }
 
   // Each vertex x in list[0..cnt) has just become S: offer x to every vertex
-  // outside its outermost node, and, with `own`, recompute x's least slack to
-  // S vertices outside that node.  Without `own` x keeps the least slack it
-  // had as a free or T vertex, which is the same quantity: that holds when x
-  // had no S vertex in its outermost node before (a grow, or the children of
-  // an expanded T blossom), since every S vertex was offered to it and every
-  // dual change updated it; the new S vertices among themselves are covered
-  // by the offers.
-  MW_FN void refresh(int cnt, bool own) {
+  // outside its outermost node.  x keeps the least slack it had as a free or
+  // T vertex, which is the same quantity when x had no S vertex in its
+  // outermost node before (a grow, or the children of an expanded T
+  // blossom): every S vertex was offered to it and every dual change updated
+  // it; the new S vertices among themselves are covered by the offers.
+  MW_FN void refresh(int cnt) {
     for (int k = 0; k < cnt; ++k) MW_COUNT(refresh_vertex);
     for (int k = 0; k < cnt; ++k) {
       const int x = rd(list, k);
       const int tx = rd(top, x);
-      int64_t bk = INF;
-      int bi = 0x7fff;
       for (int y = wv.lane; y < nv; y += WV::N) {
-        const int ty = top[y];
-        if (ty == tx) continue;
+        if (top[y] == tx) continue;
         const int64_t sl = slack(x, y);
         if (sl < best[y]) { best[y] = sl; bestS[y] = (int16_t)x; }
-        if (own && lab[ty] == S && sl < bk) { bk = sl; bi = y; }
-      }
-      if (own) {
-        wv.argmin(bk, bi);
-        wv.sync();
-        best[x] = bk;
-        bestS[x] = (int16_t)(bk < INF ? bi : -1);
       }
       wv.sync();
     }
@@ -336,11 +324,25 @@ struct Solver {
     tid[b] = (int16_t)rd(tid, A);
     par[b] = -1;
     wv.sync();
+    // The vertices of b's T children become S: offer them to every vertex
+    // outside b (as T vertices they already hold their least slack to the S
+    // vertices outside their node).
+    const int cnt = collect([&](int y) {
+      const int ty = top[y];
+      return par[ty] == b && lab[ty] == T;
+    });
     for (int v = wv.lane; v < nv; v += WV::N)
       if (par[top[v]] == b) top[v] = (int16_t)b;
     wv.sync();
-    const int cnt = collect([&](int y) { return top[y] == b; });
-    refresh(cnt, true);   // S vertices inside b may have kept a partner now inside b
+    refresh(cnt);
+    // The S vertices outside b are those outside the old nodes minus b's
+    // own, so a vertex of b keeps its least slack unless its partner is now
+    // inside b.
+    const int cnt2 = collect([&](int y) {
+      const int s = bestS[y];
+      return top[y] == b && s >= 0 && top[s] == b;
+    });
+    recompute(cnt2);
   }
 
   // dissolve the outermost T blossom B (dual zero): its children on the even
@@ -394,13 +396,14 @@ struct Solver {
       x = rd(cnext, x);
     } while (x != first && ++g <= 2 * cap);
     wv.sync();
-    refresh(cnt, false);
+    refresh(cnt);
   }
 
   // ---------------------------------------------------------------- solve
   // best / bestS of every vertex in list[0..cnt): its least slack to an S
   // vertex outside its outermost node
   MW_FN void recompute(int cnt) {
+    if (cnt == 0) return;
     for (int k = 0; k < cnt; ++k) MW_COUNT(recompute_vertex);
     // the S vertices, in ascending order
     int ns = 0;
@@ -623,7 +626,7 @@ struct Solver {
           tid[Bm] = tree;
           wv.sync();
           const int cnt = collect([&](int y) { return top[y] == Bm; });
-          refresh(cnt, false);
+          refresh(cnt);
         } else {
           const int ri = rd(tid, rd(top, i)), rj = rd(tid, Bj);
           if (ri != rj) {
