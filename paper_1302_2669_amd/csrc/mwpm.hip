@@ -85,6 +85,34 @@ struct Wave64 {
     idx = __builtin_amdgcn_readlane(idx, __builtin_ctzll(at));
     key = (int64_t)(((uint64_t)(mh ^ 0x80000000u) << 32) | ml);
   }
+  // one step of the grouped minimum: (hi, lo, ix) from the lane DPP control
+  // CTRL names, lexicographically unsigned (unreached lanes bring all ones)
+  template <int CTRL, int ROWS>
+  MW_FN static void seg_step(uint32_t& hi, uint32_t& lo, uint32_t& ix) {
+    const uint32_t oh = (uint32_t)__builtin_amdgcn_update_dpp(-1, (int)hi, CTRL, ROWS, 0xf, false);
+    const uint32_t ol = (uint32_t)__builtin_amdgcn_update_dpp(-1, (int)lo, CTRL, ROWS, 0xf, false);
+    const uint32_t oi = (uint32_t)__builtin_amdgcn_update_dpp(-1, (int)ix, CTRL, ROWS, 0xf, false);
+    const bool take = oh < hi || (oh == hi && (ol < lo || (ol == lo && oi < ix)));
+    hi = take ? oh : hi;
+    lo = take ? ol : lo;
+    ix = take ? oi : ix;
+  }
+  // smallest (signed key, idx >= 0) within each aligned group of 2^lg lanes
+  // (lg wave-uniform, 0..6), left in the group's last lane: the prefix
+  // minima of wave_min stopped after lg steps, each lane then holding the
+  // minimum over the 2^lg lanes ending at it
+  MW_FN void seg_argmin(int64_t& key, int& idx, int lg) const {
+    uint32_t lo = (uint32_t)key, hi = (uint32_t)((uint64_t)key >> 32) ^ 0x80000000u;
+    uint32_t ix = (uint32_t)idx;
+    if (lg >= 1) seg_step<0x111, 0xf>(hi, lo, ix);
+    if (lg >= 2) seg_step<0x112, 0xf>(hi, lo, ix);
+    if (lg >= 3) seg_step<0x114, 0xf>(hi, lo, ix);
+    if (lg >= 4) seg_step<0x118, 0xf>(hi, lo, ix);
+    if (lg >= 5) seg_step<0x142, 0xa>(hi, lo, ix);
+    if (lg >= 6) seg_step<0x143, 0xc>(hi, lo, ix);
+    key = (int64_t)(((uint64_t)(hi ^ 0x80000000u) << 32) | lo);
+    idx = (int)ix;
+  }
   MW_FN bool any(bool p) const { return __ballot(p) != 0ull; }
   MW_FN int compact(bool take, int& count) const {
     const uint64_t bal = __ballot(take);

@@ -414,43 +414,39 @@ struct Solver {
       if (take) slist[slot] = (int16_t)x;
     }
     wv.sync();
-    // many vertices, or few S vertices: one vertex per lane, each scanning
-    // the S list (a pass costs about as much as 1.5 wave minima)
-    if (2 * ns <= 3 * cnt || cnt >= WV::N / 4) {
-      for (int k = wv.lane; k < cnt; k += WV::N) {
-        const int y = list[k];
+    // Each vertex takes an aligned group of 2^lg lanes, lane r of the group
+    // scanning S list entries r, r + 2^lg, ..., then a (slack, S vertex)
+    // minimum within the group.  lg from a cost estimate: a slack counts 4, a
+    // reduction step 1 and a pass over N >> lg vertices 4 on its own.
+    int lg = 0, cost = 0x7fffffff;
+    for (int l = 0; (1 << l) <= WV::N; ++l) {
+      const int per = (ns + (1 << l) - 1) >> l, grp = WV::N >> l;
+      const int c = (cnt + grp - 1) / grp * (4 * per + l + 4);
+      if (c < cost) { cost = c; lg = l; }
+    }
+    const int P = 1 << lg, grp = WV::N >> lg, r = wv.lane & (P - 1);
+    for (int k0 = 0; k0 < cnt; k0 += grp) {
+      const int k = k0 + (wv.lane >> lg);
+      int y = 0;
+      int64_t b = INF;
+      int bs = 0x7fff;
+      if (k < cnt) {
+        y = list[k];
         const int ty = top[y];
-        int64_t b = INF;
-        int bs = -1;
-        for (int m = 0; m < ns; ++m) {
+        for (int m = r; m < ns; m += P) {  // ascending x: ties keep the smaller
           const int x = slist[m];
           if (top[x] == ty) continue;
           const int64_t sl = slack(x, y);
           if (sl < b) { b = sl; bs = x; }
         }
+      }
+      wv.seg_argmin(b, bs, lg);
+      if (k < cnt && r == P - 1) {
         best[y] = b;
-        bestS[y] = (int16_t)bs;
+        bestS[y] = (int16_t)(b < INF ? bs : -1);
       }
-      wv.sync();
-      return;
     }
-    for (int k = 0; k < cnt; ++k) {  // few: one vertex at a time across the lanes
-      const int y = rd(list, k);
-      const int ty = rd(top, y);
-      int64_t b = INF;
-      int bs = 0x7fff;
-      for (int x = wv.lane; x < nv; x += WV::N) {
-        const int tx = top[x];
-        if (tx == ty || lab[tx] != S) continue;
-        const int64_t sl = slack(x, y);
-        if (sl < b) { b = sl; bs = x; }
-      }
-      wv.argmin(b, bs);
-      wv.sync();
-      best[y] = b;
-      bestS[y] = (int16_t)(b < INF ? bs : -1);
-      wv.sync();
-    }
+    wv.sync();
   }
 
   // The tree of a labelled outermost node is identified by its exposed

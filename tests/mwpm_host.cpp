@@ -25,6 +25,7 @@ struct Wave1 {
   int lane = 0;
   void sync() const {}
   void argmin(int64_t&, int&) const {}
+  void seg_argmin(int64_t&, int&, int) const {}
   bool any(bool p) const { return p; }
   int compact(bool take, int& count) const {
     const int slot = count;
