@@ -210,16 +210,20 @@ struct Solver {
   // it; the new S vertices among themselves are covered by the offers.
   MW_FN void refresh(int cnt) {
     for (int k = 0; k < cnt; ++k) MW_COUNT(refresh_vertex);
-    for (int k = 0; k < cnt; ++k) {
-      const int x = rd(list, k);
-      const int tx = rd(top, x);
-      for (int y = wv.lane; y < nv; y += WV::N) {
-        if (top[y] == tx) continue;
+    if (cnt == 0) return;
+    for (int y = wv.lane; y < nv; y += WV::N) {  // in list order, as one offer after another
+      const int ty = top[y];
+      int64_t b = best[y];
+      int bs = -1;
+      for (int k = 0; k < cnt; ++k) {
+        const int x = list[k];
+        if (top[x] == ty) continue;
         const int64_t sl = slack(x, y);
-        if (sl < best[y]) { best[y] = sl; bestS[y] = (int16_t)x; }
+        if (sl < b) { b = sl; bs = x; }
       }
-      wv.sync();
+      if (bs >= 0) { best[y] = b; bestS[y] = (int16_t)bs; }
     }
+    wv.sync();
   }
 
   // Make vertex v the base of node B: at every blossom level, flip the even
@@ -572,35 +576,55 @@ struct Solver {
     return down;
   }
 
+  // The least key over the candidates (a free vertex's best, half an S
+  // vertex's best, half the dual of an outermost T blossom) and the index
+  // holding it, ties to the lowest index; false if an S vertex holds an odd
+  // best, which a correct dual state never has.
+  MW_FN bool scan(int64_t& key, int& idx) {
+    MW_COUNT(event);
+    key = INF;
+    idx = 0x7fff;
+    bool odd = false;
+    for (int j = wv.lane; j < nv; j += WV::N) {
+      const int16_t l = lab[top[j]];
+      const int64_t b = best[j];
+      if (b >= INF || l == T) continue;
+      int64_t kk = b;
+      if (l == S) {
+        odd |= (b & 1) != 0;  // the slack between two S vertices is even
+        kk = b >> 1;
+      }
+      if (kk < key || (kk == key && j < idx)) { key = kk; idx = j; }
+    }
+    if (nfree < cap / 2) {  // blossoms exist (indices >= cap)
+      for (int b = cap + wv.lane; b < nn; b += WV::N) {
+        if (base[b] < 0 || par[b] >= 0 || lab[b] != T) continue;
+        const int64_t kk = z[b - cap] >> 1;
+        if (kk < key || (kk == key && b < idx)) { key = kk; idx = b; }
+      }
+    }
+    wv.argmin(key, idx);
+    return !wv.any(odd);
+  }
+
   // the event loop, from `matched` matched vertices and a labelled forest
   MW_FN void run(int matched) {
     const int ev_max = 16 * nv * (nv / 2 + 2) + 64;
+    // A dual change by the least key lowers every candidate's key by that
+    // amount (both ends of an S-S slack move), so the step after it acts on
+    // the same candidate at key 0 without a scan.
+    bool rescan = true;
+    int64_t key = INF;
+    int idx = 0x7fff;
     for (int ev = 0; matched < nv && !fail; ++ev) {
       if (ev > ev_max) { fail = true; break; }
-      MW_COUNT(event);
-      int64_t key = INF;
-      int idx = 0x7fff;
-      bool odd = false;
-      for (int j = wv.lane; j < nv; j += WV::N) {
-        const int16_t l = lab[top[j]];
-        const int64_t b = best[j];
-        if (b >= INF || l == T) continue;
-        int64_t kk = b;
-        if (l == S) {
-          odd |= (b & 1) != 0;  // the slack between two S vertices is even
-          kk = b >> 1;
-        }
-        if (kk < key || (kk == key && j < idx)) { key = kk; idx = j; }
+      if (!rescan) {
+        key = 0;
+      } else if (!scan(key, idx)) {
+        fail = true;
+        break;
       }
-      if (nfree < cap / 2) {  // half the dual of an outermost T blossom (index >= cap)
-        for (int b = cap + wv.lane; b < nn; b += WV::N) {
-          if (base[b] < 0 || par[b] >= 0 || lab[b] != T) continue;
-          const int64_t kk = z[b - cap] >> 1;
-          if (kk < key || (kk == key && b < idx)) { key = kk; idx = b; }
-        }
-      }
-      wv.argmin(key, idx);
-      if (wv.any(odd)) { fail = true; break; }
+      rescan = true;
       if (key == 0 && idx >= cap) {
         MW_COUNT(expand);
         expand_t(idx);
@@ -678,6 +702,7 @@ struct Solver {
           }
         }
         wv.sync();
+        rescan = false;
       }
     }
     if (matched < nv) fail = true;
