@@ -131,10 +131,16 @@ size_t mwpm_lds(int cap) {
   return mwpm_waves(cap) * mw::region_bytes(cap) + (4 * mw::ROWS + 4) * sizeof(uint32_t);
 }
 
-// Capacity of the first launch: the problems of typical syndromes (lit sites
-// of one type up to about 2/5 of them, at least 85), so that more waves fit
-// per compute unit; the rare larger syndromes go to a second launch sized for
-// a fully lit code.
+// Capacity of the first launch: two 64-vertex states and the planes take
+// 11.4 KB of LDS, so 14 two-wave workgroups (7 waves per SIMD) fit in a
+// compute unit's 160 KB; at L = 13, p = 0.15 this holds 99% of the
+// syndromes.
+constexpr int MWPM_FAST_CAP = 64;
+
+// Capacity of the launch after it (5 waves per SIMD at most): the problems
+// of the typical syndromes of the larger codes (lit sites of one type up to
+// about 2/5 of them, at least 85); the rare larger syndromes go to a last
+// launch sized for a fully lit code.
 int mwpm_small_capacity(int L) {
   const int full = mw::capacity(L);
   int c = 2 * L * (L - 1) / 5 + 8;
@@ -151,13 +157,16 @@ __device__ __forceinline__ int max_vertices(int k) { return (k & 1) ? k + 3 : k 
 
 // Wave w solves anyon types w, w + waves (0 plaquettes / x parts, 1 stars /
 // z parts): parity 0 from the start, then parity 1 from parity 0's solution;
-// problem p = 2 type + parity paints plane p.  The small launch (big = 0)
-// takes the syndromes whose problems fit `cap` vertices, the big launch
-// (big = 1) the others.  Register budget: 5 waves per SIMD (96 VGPRs, a few
-// spills), which the small launch's LDS also allows; at 4 waves (117 VGPRs,
-// none) the kernel is 15% slower.
-__global__ void __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(5)))
-init_mwpm_kernel(const StartArgs a, int cap, int waves, int small_cap, int big) {
+// problem p = 2 type + parity paints plane p.  A launch takes the syndromes
+// whose larger problem needs more than `lo` and at most `hi` vertices, in a
+// state sized for `cap`.  WPE is the register budget in waves per SIMD: 7
+// (72 VGPRs, some spills) for the launch of capacity MWPM_FAST_CAP, whose
+// LDS allows 7; 5 (96 VGPRs, a few spills) for the larger capacities, whose
+// LDS allows at most 5 (at 4 waves, 117 VGPRs and none, the kernel is 15%
+// slower; at 8, 64 VGPRs, the scalar spills make it 28% slower than at 7).
+template <int WPE>
+__global__ void __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(WPE)))
+init_mwpm_kernel(const StartArgs a, int cap, int waves, int lo, int hi) {
   extern __shared__ __align__(16) uint8_t mw_lds[];
   __shared__ int lit[2];
   const int64_t s = blockIdx.x;
@@ -176,7 +185,7 @@ init_mwpm_kernel(const StartArgs a, int cap, int waves, int small_cap, int big) 
   if (cp) atomicAdd(&lit[0], cp);
   __syncthreads();
   const int need = max(max_vertices(lit[0]), max_vertices(lit[1]));
-  if ((need <= small_cap) == (big != 0)) return;  // the other launch takes it
+  if (need <= lo || need > hi) return;  // another launch takes it
   const int wave = threadIdx.x >> 6;
   const size_t region = mw::region_bytes(cap);
   uint32_t* planes = reinterpret_cast<uint32_t*>(mw_lds + waves * region);  // [4][ROWS]
@@ -238,20 +247,33 @@ hipError_t launch_init_mwpm(const StartArgs& a, hipStream_t s) {
   if (a.n == 0) return hipSuccess;
   const int L = a.items ? a.max_L : a.L;
   if (L < MCMC_L_MIN || L > MCMC_L_MAX) return hipErrorInvalidValue;
-  const int full = mw::capacity(L), small = mwpm_small_capacity(L);
-  for (int big = 0; big <= (full > small ? 1 : 0); ++big) {
-    const int cap = big ? full : small;
+  // capacity tiers: the 7-wave launch, the typical syndromes of the larger
+  // codes, a fully lit code
+  const int full = mw::capacity(L), mid = mwpm_small_capacity(L);
+  int caps[3], nt = 0;
+  if (mid > MWPM_FAST_CAP) caps[nt++] = MWPM_FAST_CAP;
+  caps[nt++] = mid;
+  if (full > mid) caps[nt++] = full;
+  int lo = 0;
+  for (int t = 0; t < nt; ++t) {
+    const int cap = caps[t], hi = t + 1 < nt ? cap : 0x7fffffff;
     const size_t lds = mwpm_lds(cap);
+    const void* fn = cap <= MWPM_FAST_CAP ? reinterpret_cast<const void*>(init_mwpm_kernel<7>)
+                                          : reinterpret_cast<const void*>(init_mwpm_kernel<5>);
     if (lds > 64 * 1024) {
-      const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(init_mwpm_kernel),
-                                               hipFuncAttributeMaxDynamicSharedMemorySize,
+      const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
                                                (int)lds);
       if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(init_mwpm_kernel, dim3((unsigned)a.n), dim3(128), lds, s, a, cap,
-                       mwpm_waves(cap), small, big);
+    if (cap <= MWPM_FAST_CAP)
+      hipLaunchKernelGGL(init_mwpm_kernel<7>, dim3((unsigned)a.n), dim3(128), lds, s, a, cap,
+                         mwpm_waves(cap), lo, hi);
+    else
+      hipLaunchKernelGGL(init_mwpm_kernel<5>, dim3((unsigned)a.n), dim3(128), lds, s, a, cap,
+                         mwpm_waves(cap), lo, hi);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+    lo = cap;
   }
   return hipSuccess;
 }
