@@ -239,10 +239,13 @@ int mcmc_chain_state_size(const mcmc_params* prm, int64_t n, size_t* bytes) {
   return MCMC_OK;
 }
 
-int mcmc_decode_batch(const uint8_t* syndromes, const uint32_t* syndrome_ids, int64_t n,
-                      const mcmc_params* prm, double* class_prob, double* mean_n, int64_t* sum_n,
-                      int64_t* accepts, uint8_t* chosen, uint8_t* correction, void* chain_state,
-                      int16_t* trace, void* workspace, size_t workspace_bytes, void* stream) {
+// mcmc_decode_batch; may_create: the matching starts may create their side
+// stream (not for the entry point that allocates nothing)
+static int decode_batch(const uint8_t* syndromes, const uint32_t* syndrome_ids, int64_t n,
+                        const mcmc_params* prm, double* class_prob, double* mean_n,
+                        int64_t* sum_n, int64_t* accepts, uint8_t* chosen, uint8_t* correction,
+                        void* chain_state, int16_t* trace, void* workspace,
+                        size_t workspace_bytes, void* stream, bool may_create) {
   int st = check_params(prm, n);
   if (st != MCMC_OK) return st;
   if (n == 0) return MCMC_OK;
@@ -280,7 +283,7 @@ int mcmc_decode_batch(const uint8_t* syndromes, const uint32_t* syndrome_ids, in
     sa.rows = init_rows;
     sa.weights = init_n;
     sa.noise = (int32_t)prm->noise;
-    st = hip_status(launch_init_mode(prm->init, sa, s));
+    st = hip_status(launch_init_mode(prm->init, sa, s, may_create));
     if (st != MCMC_OK) return st;
   }
 
@@ -364,6 +367,14 @@ int mcmc_decode_batch(const uint8_t* syndromes, const uint32_t* syndrome_ids, in
   return hip_status(launch_decide(d, s));
 }
 
+int mcmc_decode_batch(const uint8_t* syndromes, const uint32_t* syndrome_ids, int64_t n,
+                      const mcmc_params* prm, double* class_prob, double* mean_n, int64_t* sum_n,
+                      int64_t* accepts, uint8_t* chosen, uint8_t* correction, void* chain_state,
+                      int16_t* trace, void* workspace, size_t workspace_bytes, void* stream) {
+  return decode_batch(syndromes, syndrome_ids, n, prm, class_prob, mean_n, sum_n, accepts, chosen,
+                      correction, chain_state, trace, workspace, workspace_bytes, stream, true);
+}
+
 int mcmc_decode_batch_noalloc(const uint8_t* syndromes, const uint32_t* syndrome_ids, int64_t n,
                               const mcmc_params* prm, double* class_prob, double* mean_n,
                               int64_t* sum_n, int64_t* accepts, uint8_t* chosen,
@@ -378,9 +389,8 @@ int mcmc_decode_batch_noalloc(const uint8_t* syndromes, const uint32_t* syndrome
   if (sst != MCMC_OK) return sst;
   // the same kernels as mcmc_decode_batch, with the device's scratch as the
   // workspace (its tile counter is zeroed by a kernel at the start of every call)
-  return mcmc_decode_batch(syndromes, syndrome_ids, n, prm, class_prob, mean_n, sum_n, accepts,
-                           chosen, correction, chain_state, trace, ws,
-                           MCMC_NOALLOC_SCRATCH_BYTES, stream);
+  return decode_batch(syndromes, syndrome_ids, n, prm, class_prob, mean_n, sum_n, accepts, chosen,
+                      correction, chain_state, trace, ws, MCMC_NOALLOC_SCRATCH_BYTES, stream, false);
 }
 
 int mcmc_init_representatives(int32_t L, uint32_t init, const uint8_t* syndromes, int64_t n,

@@ -449,6 +449,7 @@ int mcmc_gated_create(const mcmc_gate_config* h_cfg, mcmc_gated** out) {
     free_gated(g);
     return st != MCMC_OK ? st : MCMC_EDEVICE;
   }
+  if (c.init == MCMC_INIT_MWPM) (void)mwpm_prepare_overlap();
   *out = g;
   return MCMC_OK;
 }

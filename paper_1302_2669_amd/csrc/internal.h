@@ -142,10 +142,18 @@ struct StartArgs {
 hipError_t launch_init(const StartArgs& a, hipStream_t s);
 hipError_t launch_init_matching(const StartArgs& a, hipStream_t s);
 // Exact minimum-weight matching starts (MCMC_INIT_MWPM): one workgroup per
-// syndrome, dynamic LDS sized for the largest L.
-hipError_t launch_init_mwpm(const StartArgs& a, hipStream_t s);
+// syndrome, dynamic LDS sized for the largest L.  The launches of the larger
+// capacities go to a per-device side stream forked from and joined to s; the
+// first call on a device that is not capturing creates it when may_create
+// (callers that must not create runtime objects pass false: then, as under a
+// capture before the stream exists, every launch goes to s in order).
+hipError_t launch_init_mwpm(const StartArgs& a, hipStream_t s, bool may_create = true);
+// Creates the current device's side stream of launch_init_mwpm now (for
+// callers that capture the starts into a graph later).
+hipError_t mwpm_prepare_overlap();
 // The start kernel of an MCMC_INIT_* mode.
-hipError_t launch_init_mode(uint32_t init, const StartArgs& a, hipStream_t s);
+hipError_t launch_init_mode(uint32_t init, const StartArgs& a, hipStream_t s,
+                            bool may_create = true);
 
 #ifdef __HIPCC__
 // Syndrome s of a start launch: its L, input bytes, start block and caller index.

@@ -570,8 +570,8 @@ hipError_t launch_init_matching(const StartArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_init_mode(uint32_t init, const StartArgs& a, hipStream_t s) {
-  if (init == MCMC_INIT_MWPM) return launch_init_mwpm(a, s);
+hipError_t launch_init_mode(uint32_t init, const StartArgs& a, hipStream_t s, bool may_create) {
+  if (init == MCMC_INIT_MWPM) return launch_init_mwpm(a, s, may_create);
   if (init == MCMC_INIT_MATCHING) return launch_init_matching(a, s);
   return launch_init(a, s);
 }

@@ -20,8 +20,11 @@
 // One workgroup per syndrome.  Its two waves each solve one anyon type (both
 // parities, the second from the first's solution) with the whole solver state
 // in LDS (at large L one wave takes both types in turn), XOR their parts into
-// bit planes, and the workgroup packs the four class starts.  Two launches: one sized for typical
-// syndromes (more resident waves), one for the rest.
+// bit planes, and the workgroup packs the four class starts.  Up to three
+// launches by problem size (capacity tiers); the larger two, which hold few
+// syndromes but long solves, run on a side stream beside the first.
+#include <mutex>
+
 #include "device_common.h"
 #include "internal.h"
 
@@ -243,7 +246,66 @@ init_mwpm_kernel(const StartArgs a, int cap, int waves, int lo, int hi) {
   if (a.weights && threadIdx.x < 4) a.weights[si.orig * 4 + threadIdx.x] = wsum[threadIdx.x];
 }
 
-hipError_t launch_init_mwpm(const StartArgs& a, hipStream_t s) {
+namespace {
+
+// Per device: the side stream of the larger tiers and the events that fork
+// it from and join it to the caller's stream.  Created on first use outside
+// a stream capture (or by mwpm_prepare_overlap) and kept until the process
+// ends; the mutex orders concurrent callers' fork-launch-join sequences.
+struct Overlap {
+  hipStream_t side = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
+};
+constexpr int kOverlapDevices = 64;
+std::mutex g_overlap_mu;
+Overlap g_overlap[kOverlapDevices];
+
+// the current device's entry, created if `create`; null if it does not exist
+// (or cannot be made)
+Overlap* overlap_entry(bool create) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kOverlapDevices) return nullptr;
+  Overlap& o = g_overlap[dev];
+  if (o.side || !create) return o.side ? &o : nullptr;
+  Overlap n;
+  if (hipStreamCreateWithFlags(&n.side, hipStreamNonBlocking) != hipSuccess) return nullptr;
+  if (hipEventCreateWithFlags(&n.fork, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&n.join, hipEventDisableTiming) != hipSuccess) {
+    if (n.fork) (void)hipEventDestroy(n.fork);
+    (void)hipStreamDestroy(n.side);
+    return nullptr;
+  }
+  o = n;
+  return &o;
+}
+
+hipError_t launch_tier(const StartArgs& a, int cap, int lo, int hi, hipStream_t s) {
+  const size_t lds = mwpm_lds(cap);
+  const bool fast = cap <= MWPM_FAST_CAP;
+  const void* fn = fast ? reinterpret_cast<const void*>(init_mwpm_kernel<7>)
+                        : reinterpret_cast<const void*>(init_mwpm_kernel<5>);
+  if (lds > 64 * 1024) {
+    const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                             (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  if (fast)
+    hipLaunchKernelGGL(init_mwpm_kernel<7>, dim3((unsigned)a.n), dim3(128), lds, s, a, cap,
+                       mwpm_waves(cap), lo, hi);
+  else
+    hipLaunchKernelGGL(init_mwpm_kernel<5>, dim3((unsigned)a.n), dim3(128), lds, s, a, cap,
+                       mwpm_waves(cap), lo, hi);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t mwpm_prepare_overlap() {
+  std::lock_guard<std::mutex> lock(g_overlap_mu);
+  return overlap_entry(true) ? hipSuccess : hipErrorOutOfMemory;
+}
+
+hipError_t launch_init_mwpm(const StartArgs& a, hipStream_t s, bool may_create) {
   if (a.n == 0) return hipSuccess;
   const int L = a.items ? a.max_L : a.L;
   if (L < MCMC_L_MIN || L > MCMC_L_MAX) return hipErrorInvalidValue;
@@ -254,27 +316,30 @@ hipError_t launch_init_mwpm(const StartArgs& a, hipStream_t s) {
   if (mid > MWPM_FAST_CAP) caps[nt++] = MWPM_FAST_CAP;
   caps[nt++] = mid;
   if (full > mid) caps[nt++] = full;
-  int lo = 0;
+  int lo[3], hi[3];
   for (int t = 0; t < nt; ++t) {
-    const int cap = caps[t], hi = t + 1 < nt ? cap : 0x7fffffff;
-    const size_t lds = mwpm_lds(cap);
-    const void* fn = cap <= MWPM_FAST_CAP ? reinterpret_cast<const void*>(init_mwpm_kernel<7>)
-                                          : reinterpret_cast<const void*>(init_mwpm_kernel<5>);
-    if (lds > 64 * 1024) {
-      const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                               (int)lds);
-      if (e != hipSuccess) return e;
-    }
-    if (cap <= MWPM_FAST_CAP)
-      hipLaunchKernelGGL(init_mwpm_kernel<7>, dim3((unsigned)a.n), dim3(128), lds, s, a, cap,
-                         mwpm_waves(cap), lo, hi);
-    else
-      hipLaunchKernelGGL(init_mwpm_kernel<5>, dim3((unsigned)a.n), dim3(128), lds, s, a, cap,
-                         mwpm_waves(cap), lo, hi);
-    const hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    lo = cap;
+    lo[t] = t ? caps[t - 1] : 0;
+    hi[t] = t + 1 < nt ? caps[t] : 0x7fffffff;
   }
+  if (nt == 1) return launch_tier(a, caps[0], lo[0], hi[0], s);
+  // the later tiers on the side stream, launched first so that their few long
+  // workgroups start at once; without a side stream, in order on s
+  std::lock_guard<std::mutex> lock(g_overlap_mu);
+  hipStreamCaptureStatus cap_status = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &cap_status) != hipSuccess) cap_status = hipStreamCaptureStatusNone;
+  const Overlap* o = overlap_entry(may_create && cap_status == hipStreamCaptureStatusNone);
+  hipError_t e = hipSuccess;
+  if (o) {
+    if ((e = hipEventRecord(o->fork, s)) != hipSuccess) return e;
+    if ((e = hipStreamWaitEvent(o->side, o->fork, 0)) != hipSuccess) return e;
+    for (int t = 1; t < nt; ++t)
+      if ((e = launch_tier(a, caps[t], lo[t], hi[t], o->side)) != hipSuccess) return e;
+    if ((e = launch_tier(a, caps[0], lo[0], hi[0], s)) != hipSuccess) return e;
+    if ((e = hipEventRecord(o->join, o->side)) != hipSuccess) return e;
+    return hipStreamWaitEvent(s, o->join, 0);
+  }
+  for (int t = 0; t < nt; ++t)
+    if ((e = launch_tier(a, caps[t], lo[t], hi[t], s)) != hipSuccess) return e;
   return hipSuccess;
 }
 

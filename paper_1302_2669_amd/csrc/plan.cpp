@@ -613,6 +613,9 @@ int mcmc_plan_create(const mcmc_item* items, int64_t n, uint64_t seed, uint32_t 
   p->tuning.occ_wide = 0;
   p->tuning.pair_small = 1;   // measured faster at every L <= 8 (1.02-1.7x)
   p->tuning.concurrent = 2;
+  // the matching starts' side stream exists before any capture of the plan
+  // (without it the starts run their launches in order)
+  if (init == MCMC_INIT_MWPM) (void)mwpm_prepare_overlap();
   *out = p;
   return MCMC_OK;
 }
