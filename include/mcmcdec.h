@@ -115,7 +115,8 @@ enum mcmc_status {
                                   class c = x part of parity c&1 + z part of
                                   parity c>>1.  Ties between equal-weight
                                   matchings go to the smallest sum of a per-pair
-                                  splitmix64 key; paths are fixed per pair (see
+                                  key (from the ends' splitmix64 keys); paths
+                                  are fixed per pair (see
                                   mcmc_init_representatives).  With no counted
                                   sweep the decision is the enhanced-matching
                                   decoder (fewest errors, Y counting once). */
@@ -249,15 +250,25 @@ int mcmc_decode_batch_noalloc(const uint8_t* d_syndromes, const uint32_t* d_synd
  *   d(a, a') = min(|di| + |dj|, near(a) + near(a'), far(a) + far(a')),
  *   d(a, NEAR) = near(a), d(a, FAR) = far(a), d(NEAR, FAR) = L,
  * near/far = j+1 / L-1-j (plaquettes), i+1 / L-1-i (stars).  The matching
- * minimises the sum of W = d 2^53 + 2 t over its pairs, t = splitmix64 at
- * state (min(id) << 12) | max(id) shifted right by 21 (id = site index,
- * NEAR 4094, FAR 4095), so the total distance is the minimum and ties go to
- * the smallest t sum.  Pair a < a' (site order): direct path if the
+ * minimises the sum of W = d 2^53 + 2 t over its pairs, t = the top 43 bits
+ * of the 64-bit product K(a) K(a') of the ends' keys, K = splitmix64 at the
+ * vertex id (id = site index, NEAR 4094, FAR 4095), so the total distance is
+ * the minimum and ties go to the smallest t sum.  Pair a < a' (site order): direct path if the
  * Manhattan distance is d (plaquettes along a's grid row to the column of
  * a', then along that column; stars along a's grid column to the row of a',
  * then along that row), else both strings to the nearer boundary (NEAR on a
  * tie); boundary matches are straight strings and NEAR-FAR is the logical
- * string (X on grid row 0, Z on grid column 0). */
+ * string (X on grid row 0, Z on grid column 0).
+ *
+ * Resources: the syndromes too large for the first launch of the matching
+ * starts are solved on a non-blocking stream of the library's, forked from
+ * `stream` and joined back to it with two events.  That stream and the two
+ * events are created once per device, on the first MCMC_INIT_MWPM call that
+ * is not under a stream capture (or by mcmc_plan_create / mcmc_gated_create
+ * with MCMC_INIT_MWPM), and kept until the process ends; until then, and
+ * always for mcmc_decode_batch_noalloc, every launch goes to `stream` in
+ * order.  The same holds for mcmc_decode_batch, plans and the gated decoder
+ * with MCMC_INIT_MWPM starts. */
 int mcmc_init_representatives(int32_t L, uint32_t init, const uint8_t* d_syndromes, int64_t n,
                               uint8_t* d_reps, void* stream);
 
