@@ -167,3 +167,64 @@ def test_plan_with_mwpm_starts_equals_uniform_decodes():
                               u["correction"][0].cpu().numpy())
         assert int(out["chosen"][i]) == int(u["chosen"][0])
     plan.close()
+
+
+def boundary_syndromes(L, counts, seed):
+    """Syndromes whose busier anyon type has exactly k lit sites, for each k
+    in `counts`, both ways round (the other type: a random count up to k)."""
+    lat = geometry.Lattice(L)
+    ns = L * (L - 1)
+    rng = np.random.default_rng(seed)
+    out = []
+    for k in counts:
+        for busy_first in (True, False):
+            s = np.zeros(lat.n_stab, np.uint8)
+            other = int(rng.integers(0, k + 1))
+            kb, ko = (k, other) if busy_first else (other, k)
+            s[rng.choice(ns, kb, replace=False)] = 1
+            s[ns + rng.choice(ns, ko, replace=False)] = 1
+            out.append(s)
+    return np.stack(out)
+
+
+# lit counts k whose larger problem (k + 2 vertices for even k, k + 3 for
+# odd) falls on either side of the launch capacities 64 and 88 at L = 13
+TIER_COUNTS = [20, 60, 61, 62, 63, 64, 84, 85, 86, 87, 88, 120]
+
+
+def test_starts_parity_at_capacity_tiers():
+    """One batch spanning the three capacity tiers (the larger two on the
+    library's side stream), every start bit-exact with the oracle."""
+    L = 13
+    say(f"mwpm starts at the capacity tiers, L={L}")
+    lat = geometry.Lattice(L)
+    syn = boundary_syndromes(L, TIER_COUNTS, 0x7135)
+    reps = gpu_starts(syn, L)
+    for i in range(syn.shape[0]):
+        assert np.array_equal(reps[i], mm.mwpm_representatives(lat, syn[i])), i
+
+
+def test_plan_graph_with_mwpm_starts_replays():
+    """A plan's graph holds the side-stream fork and join of the starts:
+    three replays, with eager decodes and synchronisations between them, all
+    equal to the eager execution."""
+    L = 13
+    say("mwpm plan graph replays")
+    syn = boundary_syndromes(L, TIER_COUNTS, 0x7136)
+    items = [dict(L=L, p=0.15, sweeps=2, chains=2, syndrome_id=100 + i)
+             for i in range(syn.shape[0])]
+    flat = torch.from_numpy(syn.reshape(-1)).to(DEV)
+    plan = mc.MixedPlan(items, seed=0x5EED, init=MWPM)
+    ref = plan.execute(flat, want_sums=True)
+    torch.cuda.synchronize()
+    ref = {k: v.clone() for k, v in ref.items()}
+    out = None
+    for r in range(3):
+        out = plan.execute(flat, want_sums=True, graph=True, out=out)
+        torch.cuda.synchronize()
+        for k in ("sum_n", "chosen", "correction"):
+            assert torch.equal(out[k], ref[k]), (r, k)
+        # eager work of the program's own between replays
+        mc.init_representatives(flat.view(len(items), -1), L, init=MWPM)
+        torch.cuda.synchronize()
+    plan.close()
