@@ -506,6 +506,30 @@ struct Solver {
       matched += 2 * dummy;
     }
     wv.sync();
+    // then each exposed vertex in turn raises its dual by its least slack
+    // (every slack stays >= 0; slacks are even, so u stays even) and is
+    // matched along the edge that became tight when that edge's other end is
+    // still exposed (exposed ends first among equal slacks)
+    for (int v = 0; v < nv; ++v) {
+      if (rd(mate, v) >= 0) continue;
+      int64_t key = INF;
+      int idx = 0x7fff;
+      for (int w = wv.lane; w < nv; w += WV::N) {
+        if (w == v) continue;
+        const int64_t k = (slack(v, w) << 1) | (mate[w] >= 0 ? 1 : 0);
+        if (k < key) { key = k; idx = w; }
+      }
+      wv.argmin(key, idx);
+      wv.sync();
+      if (key >= INF) continue;
+      u[v] += key >> 1;
+      if ((key & 1) == 0) {
+        mate[v] = (int16_t)idx;
+        mate[idx] = (int16_t)v;
+        matched += 2;
+      }
+      wv.sync();
+    }
     for (int v = wv.lane; v < nv; v += WV::N)
       if (mate[v] < 0) { lab[v] = S; tid[v] = (int16_t)v; }
     wv.sync();
