@@ -149,7 +149,7 @@ typedef struct mcmc_params {
 /* Human-readable name of a status code (static string). */
 const char* mcmc_strerror(int status);
 
-/* ABI version of this header: 0x00010400 for 1.4. */
+/* ABI version of this header: 0x00010500 for 1.5. */
 int32_t mcmc_abi_version(void);
 
 /* n_q and n_stab of a distance-L code (Sec. II: n_stab = 2L(L-1),
@@ -271,6 +271,14 @@ int mcmc_decode_batch_noalloc(const uint8_t* d_syndromes, const uint32_t* d_synd
  * with MCMC_INIT_MWPM starts. */
 int mcmc_init_representatives(int32_t L, uint32_t init, const uint8_t* d_syndromes, int64_t n,
                               uint8_t* d_reps, void* stream);
+
+/* The weights of the four class starts of n syndromes (the same starts as
+ * mcmc_init_representatives): d_weights [n][4] int32, entry k the number of
+ * qubits on which class k's start is not the identity (depolarizing weight).
+ * Asynchronous; needs no workspace.  ERANGE / EINVAL as
+ * mcmc_init_representatives. */
+int mcmc_start_weights(int32_t L, uint32_t init, const uint8_t* d_syndromes, int64_t n,
+                       int32_t* d_weights, void* stream);
 
 /* Unpack a chain-state buffer into d_states [n][4][K][chains][n_q] uint8 and
  * d_weights [n][4][K][chains] int32, each chain's energy n under the noise
@@ -589,6 +597,32 @@ int mcmc_cnn_gate(int64_t batch, const float* d_logits, float threshold, int32_t
  * sqrt((v_b + v_s) / C) (infinite if the spread is zero and m_s > m_b, zero
  * if m_s = m_b).  Needs chains >= 2.
  */
+/*
+ * The start-weight gap route (not in the paper; a rule beside the network).
+ * The gap of a syndrome is the second-smallest minus the smallest of its
+ * four class start weights (mcmc_start_weights); its rate bin is
+ * floor(p * 100) computed in fp32 (p rounded to fp32, the product rounded to
+ * fp32), capped at MCMC_GAP_BINS - 1.  With a table set, a syndrome the
+ * network does not send to route 0 takes route 0 (the no-sweep decision,
+ * class unchanged) when its gap is at least its bin's entry; an entry of
+ * MCMC_GAP_NEVER never does.
+ */
+#define MCMC_GAP_BINS 50
+#define MCMC_GAP_NEVER 255u
+
+/* Fit of the gap table from labelled samples: h_table [MCMC_GAP_BINS]
+ * receives, per rate bin, the smallest G < MCMC_GAP_NEVER such that among
+ * the bin's samples with gap >= G at least min_count remain and the number
+ * whose budget label (mcmc_gate_budget_labels) is not 0 is at most
+ * max_miss times their count (compared in double); MCMC_GAP_NEVER if none.
+ * h_p [n] host rates, d_weights [n][4] and d_budget [n] device arrays.
+ * Copies them to the host and waits on the stream.  EINVAL on null pointers,
+ * ERANGE on n < 0, max_miss outside [0, 1], min_count < 1 or a rate that
+ * mcmc_gated_decode would reject. */
+int mcmc_gate_fit_gap_table(int64_t n, const double* h_p, const int32_t* d_weights,
+                            const int32_t* d_budget, double max_miss, int32_t min_count,
+                            uint8_t* h_table, void* stream);
+
 typedef struct mcmc_gate_config {
   int32_t L;            /* code distance                                           */
   int32_t n_temps;      /* K of the Metropolis routes (1 or even)                  */
@@ -617,6 +651,12 @@ int mcmc_gated_destroy(mcmc_gated* gated);
 int mcmc_gated_workspace_size(const mcmc_gated* gated, size_t* h_bytes);
 /* The decoder's internal plan (for mcmc_plan_set_tuning / get_tuning). */
 int mcmc_gated_plan(mcmc_gated* gated, mcmc_plan** h_plan);
+/* The gap route's table of the decoder: h_table [MCMC_GAP_BINS] (copied,
+ * the call waits for the copy), or NULL to switch the route off (the
+ * default).  The decoder then computes every syndrome's class starts before
+ * the gate (with escalation, in a launch of their own that only counts the
+ * weights, before the plan's). */
+int mcmc_gated_set_gap_table(mcmc_gated* gated, const uint8_t* h_table);
 
 /*
  * Decode n <= max_batch syndromes d_syndromes [n][n_stab] with network

@@ -215,6 +215,61 @@ def budget_labels(d_zero, d_short, d_full):
     return np.where(d_zero == d_full, 0, np.where(d_short == d_full, 1, 2)).astype(np.int32)
 
 
+# The start-weight gap route (a rule beside the network, not in the paper):
+# the decision from the class starts alone is taken when the gap between the
+# lightest and the second-lightest class start reaches a threshold that
+# depends on the error rate.  The rate axis is cut into GAP_BINS bins of
+# GAP_BIN_WIDTH; GAP_NEVER marks a bin whose threshold no gap reaches.
+GAP_BINS = 50
+GAP_BIN_WIDTH = 0.01
+GAP_NEVER = 255
+
+
+def start_weight_gap(weights):
+    """int64 [n]: second-smallest minus smallest of each row of the [n][4]
+    class start weights."""
+    w = np.sort(np.asarray(weights, dtype=np.int64), axis=1)
+    return w[:, 1] - w[:, 0]
+
+
+def gap_bin(p):
+    """int64 [n]: the rate bin floor(p * 100), computed in fp32 as the gate
+    kernel does (p as fp32, the product rounded to fp32), capped at
+    GAP_BINS - 1."""
+    q = np.asarray(p, dtype=np.float32) * np.float32(1.0 / GAP_BIN_WIDTH)
+    return np.minimum(np.floor(q).astype(np.int64), GAP_BINS - 1)
+
+
+def fit_gap_table(p, weights, budget, max_miss, min_count):
+    """uint8 [GAP_BINS]: per rate bin, the smallest gap threshold G such that
+    among the bin's samples with gap >= G at least min_count remain and the
+    fraction whose budget label is not 0 (the no-sweep decision differs from
+    the full-budget one) is at most max_miss; GAP_NEVER if no G < GAP_NEVER
+    qualifies.  Written out by the definition, G by G."""
+    gap = start_weight_gap(weights)
+    b = gap_bin(p)
+    miss = np.asarray(budget) != 0
+    table = np.full(GAP_BINS, GAP_NEVER, dtype=np.uint8)
+    for k in range(GAP_BINS):
+        gk, mk = gap[b == k], miss[b == k]
+        for G in range(GAP_NEVER):
+            sel = gk >= G
+            cnt = int(sel.sum())
+            if cnt < min_count:
+                break
+            if int(mk[sel].sum()) <= max_miss * cnt:
+                table[k] = G
+                break
+    return table
+
+
+def gap_route(p, weights, table):
+    """bool [n]: the gap route takes the syndrome (gap >= its bin's
+    threshold, a GAP_NEVER threshold never)."""
+    t = np.asarray(table, dtype=np.int64)[gap_bin(p)]
+    return (t != GAP_NEVER) & (start_weight_gap(weights) >= t)
+
+
 def relative_targets(class_prob, start_class):
     """Class targets read relative to the start decision: out[i][k] =
     class_prob[i][k ^ start_class[i]].  A class is bx + 2 bz with bx, bz the

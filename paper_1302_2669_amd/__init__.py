@@ -17,8 +17,8 @@ from ._lib import (MCMC_INIT_CANONICAL, MCMC_INIT_MATCHING, MCMC_INIT_MWPM, MCMC
 
 __all__ = ["Params", "McmcError", "geometry", "lattice", "acceptance_table", "workspace_size",
            "chain_state_size", "decode_batch", "sample_errors", "init_representatives",
-           "unpack_chain_state", "MCMC_TRACE", "MCMC_RESUME", "MCMC_RANDOM_SCAN", "MCMC_L_MIN",
-           "MCMC_L_MAX",
+           "start_weights", "unpack_chain_state", "MCMC_TRACE", "MCMC_RESUME",
+           "MCMC_RANDOM_SCAN", "MCMC_L_MIN", "MCMC_L_MAX",
            "MCMC_INIT_CANONICAL", "MCMC_INIT_MATCHING", "MCMC_INIT_MWPM", "MCMC_NOISE_DEPOLARIZING",
            "MCMC_NOISE_BITPHASE", "params_table", "MixedPlan", "spacetime_params",
            "spacetime_tables", "sample_spacetime", "decode_spacetime"]
@@ -190,6 +190,17 @@ def init_representatives(syndromes, L, init=MCMC_INIT_MATCHING):
                                                _ptr(reps), _stream(syndromes.device))
     _lib.check(st, "mcmc_init_representatives")
     return reps
+
+
+def start_weights(syndromes, L, init=MCMC_INIT_MATCHING):
+    """int32 [n][4]: the weights of the four class starts (mcmc_start_weights)."""
+    torch = _torch()
+    n = int(syndromes.shape[0])
+    w = torch.empty((n, 4), dtype=torch.int32, device=syndromes.device)
+    st = _lib._lib().mcmc_start_weights(int(L), int(init), _ptr(syndromes.contiguous()), n,
+                                        _ptr(w), _stream(syndromes.device))
+    _lib.check(st, "mcmc_start_weights")
+    return w
 
 
 def unpack_chain_state(chain_state, n, L, p, sweeps, seed, chains=1, n_temps=1, burn=0,

@@ -142,6 +142,7 @@ _SIGNATURES = {
     "mcmc_decode_batch_noalloc": (ctypes.c_int, [_P, _P, _I64, _PPRM, _P, _P, _P, _P, _P, _P,
                                                  _P, _P, _P]),
     "mcmc_init_representatives": (ctypes.c_int, [_I32, _U32, _P, _I64, _P, _P]),
+    "mcmc_start_weights": (ctypes.c_int, [_I32, _U32, _P, _I64, _P, _P]),
     "mcmc_unpack_chain_state": (ctypes.c_int, [_PPRM, _I64, _P, _P, _P, _P]),
     "mcmc_sample_errors": (ctypes.c_int, [_I32, _D, _U64, _P, _U32, _I64, _P, _P, _P, _P]),
     "mcmc_sample_errors_model": (ctypes.c_int,
@@ -171,6 +172,7 @@ _SIGNATURES = {
     "mcmc_cnn_gate": (ctypes.c_int, [_I64, _P, ctypes.c_float, _I32, _P, _P, _P, _P]),
     "mcmc_cnn_init": (ctypes.c_int, [_I32, _U64, _P, _P]),
     "mcmc_gate_budget_labels": (ctypes.c_int, [_I64, _P, _P, _P, _P, _P]),
+    "mcmc_gate_fit_gap_table": (ctypes.c_int, [_I64, _P, _P, _P, ctypes.c_double, _I32, _P, _P]),
     "mcmc_gate_relative_targets": (ctypes.c_int, [_I64, _P, _P, _P, _P]),
     "mcmc_cnn_permutation": (ctypes.c_int, [_I64, _U64, _U32, _P, _P]),
     "mcmc_cnn_train_workspace_size": (ctypes.c_int, [_I32, _I64, _I64, _PSZ]),
@@ -181,6 +183,7 @@ _SIGNATURES = {
     "mcmc_gated_destroy": (ctypes.c_int, [_P]),
     "mcmc_gated_workspace_size": (ctypes.c_int, [_P, _PSZ]),
     "mcmc_gated_plan": (ctypes.c_int, [_P, ctypes.POINTER(_P)]),
+    "mcmc_gated_set_gap_table": (ctypes.c_int, [_P, _P]),
     "mcmc_gated_decode": (ctypes.c_int, [_P, _P, _P, _P, _P, _I64, _P, _P, _P, _P,
                                          ctypes.POINTER(_I64), _P, _SZ, _P]),
     "mcmc_spacetime_workspace_size": (ctypes.c_int, [ctypes.POINTER(SpaceTimeParams), _I64, _PSZ]),
@@ -194,7 +197,7 @@ _handle = None
 
 
 # layout of the structures below (mcmc_params, mcmc_item, ...)
-ABI_VERSION = 0x00010400
+ABI_VERSION = 0x00010500
 
 
 def _lib():

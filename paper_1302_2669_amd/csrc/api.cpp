@@ -166,7 +166,7 @@ const char* mcmc_strerror(int status) {
   }
 }
 
-int32_t mcmc_abi_version(void) { return 0x00010400; }
+int32_t mcmc_abi_version(void) { return 0x00010500; }
 
 int mcmc_geometry(int32_t L, int32_t* n_qubits, int32_t* n_stab) {
   if (!valid_L(L)) return MCMC_ERANGE;
@@ -408,6 +408,22 @@ int mcmc_init_representatives(int32_t L, uint32_t init, const uint8_t* syndromes
   sa.L = L;
   sa.bytes = reps;
   return hip_status(launch_init_mode(init, sa, s));
+}
+
+int mcmc_start_weights(int32_t L, uint32_t init, const uint8_t* syndromes, int64_t n,
+                       int32_t* weights, void* stream) {
+  if (!valid_L(L)) return MCMC_ERANGE;
+  if (init != MCMC_INIT_CANONICAL && init != MCMC_INIT_MATCHING && init != MCMC_INIT_MWPM)
+    return MCMC_EINVAL;
+  if (n < 0) return MCMC_ERANGE;
+  if (n == 0) return MCMC_OK;
+  if (!syndromes || !weights) return MCMC_EINVAL;
+  StartArgs sa{};
+  sa.syn = syndromes;
+  sa.n = n;
+  sa.L = L;
+  sa.weights = weights;
+  return hip_status(launch_init_mode(init, sa, (hipStream_t)stream));
 }
 
 int mcmc_unpack_chain_state(const mcmc_params* prm, int64_t n, const void* chain_state,

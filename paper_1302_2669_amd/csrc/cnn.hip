@@ -671,7 +671,7 @@ __global__ void adam_kernel(int64_t n, float* __restrict__ prm, const float* __r
 __global__ void gate_kernel(int64_t B, const float* __restrict__ logits, float thr,
                             int class_route, uint8_t* __restrict__ route,
                             uint8_t* __restrict__ cls, float* __restrict__ conf,
-                            uint8_t* __restrict__ flip) {
+                            uint8_t* __restrict__ flip, const GapRoute gap) {
   const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= B) return;
   const float* z = logits + b * 8;
@@ -690,6 +690,10 @@ __global__ void gate_kernel(int64_t B, const float* __restrict__ logits, float t
   if (class_route && cmax >= thr) {
     r = 0;
     f = (uint8_t)best;
+  }
+  if (gap.table && r != 0) {  // the start-weight gap route: the no-sweep decision
+    const int t = gap.table[gap_bin(gap.p[b])];
+    if (t != (int)MCMC_GAP_NEVER && start_weight_gap(gap.weights + 4 * b) >= t) r = 0;
   }
   route[b] = r;
   cls[b] = (uint8_t)best;
@@ -980,9 +984,10 @@ hipError_t cnn_adam(int64_t n, float* prm, const float* g, float* m, float* v, f
 }
 
 hipError_t cnn_gate(int64_t B, const float* logits, float thr, bool class_route, uint8_t* route,
-                    uint8_t* cls, float* conf, uint8_t* flip, hipStream_t s) {
+                    uint8_t* cls, float* conf, uint8_t* flip, const GapRoute& gap,
+                    hipStream_t s) {
   hipLaunchKernelGGL(gate_kernel, dim3(blocks_for(B, 256)), dim3(256), 0, s, B, logits, thr,
-                     class_route ? 1 : 0, route, cls, conf, flip);
+                     class_route ? 1 : 0, route, cls, conf, flip, gap);
   return hipGetLastError();
 }
 

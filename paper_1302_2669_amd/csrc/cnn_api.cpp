@@ -259,7 +259,7 @@ int mcmc_cnn_gate(int64_t batch, const float* d_logits, float threshold, int32_t
   if (!d_logits || !d_route || !d_class) return MCMC_EINVAL;
   return hip_status(
       cnn_gate(batch, d_logits, threshold, class_route != 0, d_route, d_class, d_confidence,
-               nullptr, (hipStream_t)stream));
+               nullptr, GapRoute{}, (hipStream_t)stream));
 }
 
 }  // extern "C"
@@ -288,6 +288,8 @@ struct mcmc_gated {
   uint32_t* d_ids = nullptr;
   uint32_t* d_counts = nullptr;
   uint32_t* d_tile_cum = nullptr;
+  uint8_t* d_gap = nullptr;          // gap route thresholds [MCMC_GAP_BINS]
+  bool gap_on = false;
   uint32_t* h_ids = nullptr;
   uint32_t* h_tab = nullptr;
   double* h_beta = nullptr;
@@ -422,8 +424,9 @@ int mcmc_gated_create(const mcmc_gate_config* h_cfg, mcmc_gated** out) {
   const size_t sz_g = align_up(3 * sizeof(GroupDesc)), sz_i = align_up(n * sizeof(ItemDesc));
   // tables: one per syndrome, then the configured rate's at slot N
   const size_t sz_t = align_up((n + 1) * K4 * 4), sz_b = align_up(n * 8), sz_id = align_up(n * 4);
-  const size_t sz_c = align_up(8 * 4), sz_tc = align_up(4 * 4);
-  ok = ok && hipMalloc(&g->dblock, sz_g + sz_i + sz_t + sz_b + sz_id + sz_c + sz_tc) == hipSuccess;
+  const size_t sz_c = align_up(8 * 4), sz_tc = align_up(4 * 4), sz_gap = align_up(MCMC_GAP_BINS);
+  ok = ok && hipMalloc(&g->dblock, sz_g + sz_i + sz_t + sz_b + sz_id + sz_c + sz_tc + sz_gap) ==
+                 hipSuccess;
   if (ok) {
     char* b = (char*)g->dblock;
     g->d_groups = (GroupDesc*)b;
@@ -433,6 +436,7 @@ int mcmc_gated_create(const mcmc_gate_config* h_cfg, mcmc_gated** out) {
     g->d_ids = (uint32_t*)(b + sz_g + sz_i + sz_t + sz_b);
     g->d_counts = (uint32_t*)(b + sz_g + sz_i + sz_t + sz_b + sz_id);
     g->d_tile_cum = (uint32_t*)(b + sz_g + sz_i + sz_t + sz_b + sz_id + sz_c);
+    g->d_gap = (uint8_t*)(b + sz_g + sz_i + sz_t + sz_b + sz_id + sz_c + sz_tc);
   }
   ok = ok && hipHostMalloc((void**)&g->h_ids, n * 4, hipHostMallocDefault) == hipSuccess;
   ok = ok && hipHostMalloc((void**)&g->h_tab, n * K4 * 4, hipHostMallocDefault) == hipSuccess;
@@ -471,6 +475,70 @@ int mcmc_gated_plan(mcmc_gated* g, mcmc_plan** h_plan) {
   return MCMC_OK;
 }
 
+int mcmc_gated_set_gap_table(mcmc_gated* g, const uint8_t* h_table) {
+  if (!g) return MCMC_EINVAL;
+  if (!h_table) {
+    g->gap_on = false;
+    return MCMC_OK;
+  }
+  if (hipMemcpy(g->d_gap, h_table, MCMC_GAP_BINS, hipMemcpyHostToDevice) != hipSuccess)
+    return MCMC_EDEVICE;
+  g->gap_on = true;
+  return MCMC_OK;
+}
+
+int mcmc_gate_fit_gap_table(int64_t n, const double* h_p, const int32_t* d_weights,
+                            const int32_t* d_budget, double max_miss, int32_t min_count,
+                            uint8_t* h_table, void* stream) {
+  if (!h_table || (n > 0 && (!h_p || !d_weights || !d_budget))) return MCMC_EINVAL;
+  if (n < 0 || !(max_miss >= 0.0 && max_miss <= 1.0) || min_count < 1) return MCMC_ERANGE;
+  for (int64_t i = 0; i < n; ++i)
+    if (!valid_p(h_p[i])) return MCMC_ERANGE;
+  std::vector<int32_t> w, bud;
+  try {
+    w.resize((size_t)n * 4);
+    bud.resize((size_t)n);
+  } catch (...) {
+    return MCMC_ENOMEM;
+  }
+  const hipStream_t s = (hipStream_t)stream;
+  if (n > 0 &&
+      (hipMemcpyAsync(w.data(), d_weights, (size_t)n * 16, hipMemcpyDeviceToHost, s) !=
+           hipSuccess ||
+       hipMemcpyAsync(bud.data(), d_budget, (size_t)n * 4, hipMemcpyDeviceToHost, s) !=
+           hipSuccess ||
+       hipStreamSynchronize(s) != hipSuccess))
+    return MCMC_EDEVICE;
+  // per bin and gap value: samples and misses (budget label != 0); gaps at
+  // or above MCMC_GAP_NEVER are counted in the last slot
+  constexpr int NG = (int)MCMC_GAP_NEVER + 1;
+  std::vector<int64_t> cnt((size_t)MCMC_GAP_BINS * NG, 0), miss((size_t)MCMC_GAP_BINS * NG, 0);
+  for (int64_t i = 0; i < n; ++i) {
+    const int32_t gap = start_weight_gap(&w[(size_t)i * 4]);
+    const int k = gap_bin((float)h_p[i]);
+    const size_t at = (size_t)k * NG + (size_t)std::min<int32_t>(gap, NG - 1);
+    ++cnt[at];
+    miss[at] += bud[(size_t)i] != 0;
+  }
+  for (int k = 0; k < MCMC_GAP_BINS; ++k) {
+    // counts of gap >= G from the top down, then the smallest qualifying G
+    int64_t c_ge[NG + 1], m_ge[NG + 1];
+    c_ge[NG] = m_ge[NG] = 0;
+    for (int G = NG - 1; G >= 0; --G) {
+      c_ge[G] = c_ge[G + 1] + cnt[(size_t)k * NG + G];
+      m_ge[G] = m_ge[G + 1] + miss[(size_t)k * NG + G];
+    }
+    h_table[k] = (uint8_t)MCMC_GAP_NEVER;
+    for (int G = 0; G < (int)MCMC_GAP_NEVER && c_ge[G] >= min_count; ++G) {
+      if ((double)m_ge[G] <= max_miss * (double)c_ge[G]) {
+        h_table[k] = (uint8_t)G;
+        break;
+      }
+    }
+  }
+  return MCMC_OK;
+}
+
 }  // extern "C"
 
 namespace {
@@ -504,11 +572,29 @@ int gated_decode_device(mcmc_gated* g, const float* d_params, const uint8_t* d_s
   if (!ok) return MCMC_EDEVICE;
   g->staged_pending = true;
 
-  int st = hip_status(cnn_infer(c.L, n, d_params, d_syndromes, pf, logits, ws + wl.cnn, s));
+  // the class starts, in syndrome order (the plan's items keep each
+  // syndrome's start rows and weights at its own offsets), before the gate,
+  // which may read their weights
+  uint32_t* queue = (uint32_t*)(ws + wl.q);
+  uint32_t* irows = (uint32_t*)(ws + wl.irows);
+  int32_t* in_n = (int32_t*)(ws + wl.in_n);
+  StartArgs sa{};
+  sa.syn = d_syndromes;
+  sa.n = n;
+  sa.L = c.L;
+  sa.rows = irows;
+  sa.weights = in_n;
+  sa.max_L = c.L;
+  int st = hip_status(launch_init_mode(c.init, sa, s));
+  if (st != MCMC_OK) return st;
+
+  st = hip_status(cnn_infer(c.L, n, d_params, d_syndromes, pf, logits, ws + wl.cnn, s));
   if (st != MCMC_OK) return st;
   uint8_t* flip = c.class_route ? (uint8_t*)(ws + wl.flip) : nullptr;
+  GapRoute gap{};
+  if (g->gap_on) gap = GapRoute{in_n, pf, g->d_gap};
   st = hip_status(cnn_gate(n, logits, c.threshold, c.class_route != 0, route,
-                           (uint8_t*)(ws + wl.cls), (float*)(ws + wl.conf), flip, s));
+                           (uint8_t*)(ws + wl.cls), (float*)(ws + wl.conf), flip, gap, s));
   if (st != MCMC_OK) return st;
 
   BudgetArgs ba{};
@@ -532,23 +618,10 @@ int gated_decode_device(mcmc_gated* g, const float* d_params, const uint8_t* d_s
   st = hip_status(launch_budget_plan(ba, s));
   if (st != MCMC_OK) return st;
 
-  uint32_t* queue = (uint32_t*)(ws + wl.q);
-  uint32_t* irows = (uint32_t*)(ws + wl.irows);
-  int32_t* in_n = (int32_t*)(ws + wl.in_n);
   int64_t* S = (int64_t*)(ws + wl.S);
   int32_t* nf = (int32_t*)(ws + wl.nf);
   uint32_t* frows = d_correction ? (uint32_t*)(ws + wl.frows) : nullptr;
   st = hip_status(launch_zero(queue, kQueueSlots, s));
-  if (st != MCMC_OK) return st;
-  StartArgs sa{};
-  sa.syn = d_syndromes;
-  sa.items = g->d_items;
-  sa.groups = g->d_groups;
-  sa.n = n;
-  sa.rows = irows;
-  sa.weights = in_n;
-  sa.max_L = c.L;
-  st = hip_status(launch_init_mode(c.init, sa, s));
   if (st != MCMC_OK) return st;
 
   const int r = range_of(c.L);
@@ -646,8 +719,21 @@ int mcmc_gated_decode(mcmc_gated* g, const float* d_params, const uint8_t* d_syn
     return MCMC_EDEVICE;
   st = hip_status(cnn_infer(c.L, n, d_params, d_syndromes, pf, logits, ws + wl.cnn, s));
   if (st != MCMC_OK) return st;
+  GapRoute gap{};
+  if (g->gap_on) {  // the start weights alone (the plan makes its own starts)
+    int32_t* in_n = (int32_t*)(ws + wl.in_n);
+    StartArgs sa{};
+    sa.syn = d_syndromes;
+    sa.n = n;
+    sa.L = c.L;
+    sa.weights = in_n;
+    sa.max_L = c.L;
+    st = hip_status(launch_init_mode(c.init, sa, s));
+    if (st != MCMC_OK) return st;
+    gap = GapRoute{in_n, pf, g->d_gap};
+  }
   st = hip_status(cnn_gate(n, logits, c.threshold, false, route, (uint8_t*)(ws + wl.cls),
-                           (float*)(ws + wl.conf), nullptr, s));
+                           (float*)(ws + wl.conf), nullptr, gap, s));
   if (st != MCMC_OK) return st;
   if (hipMemcpyAsync(g->h_route, route, (size_t)n, hipMemcpyDeviceToHost, s) != hipSuccess)
     return MCMC_EDEVICE;

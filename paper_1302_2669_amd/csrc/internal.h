@@ -2,6 +2,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <math.h>
 #include <stdint.h>
 
 #include "../../include/mcmcdec.h"
@@ -154,6 +155,22 @@ hipError_t mwpm_prepare_overlap();
 // The start kernel of an MCMC_INIT_* mode.
 hipError_t launch_init_mode(uint32_t init, const StartArgs& a, hipStream_t s,
                             bool may_create = true);
+
+// Rate bin of the gap route: floor(p * 100) in fp32 (p already fp32), capped
+// to [0, MCMC_GAP_BINS - 1]; the gate kernel and the host fit share it.
+__host__ __device__ inline int gap_bin(float p) {
+  const float q = p * 100.0f;
+  const int k = (int)floorf(q);
+  return k < 0 ? 0 : (k > MCMC_GAP_BINS - 1 ? MCMC_GAP_BINS - 1 : k);
+}
+
+// Second-smallest minus smallest of four class start weights.
+__host__ __device__ inline int32_t start_weight_gap(const int32_t* x) {
+  const int32_t a = x[0] < x[1] ? x[0] : x[1], b = x[0] < x[1] ? x[1] : x[0];
+  const int32_t c = x[2] < x[3] ? x[2] : x[3], d = x[2] < x[3] ? x[3] : x[2];
+  const int32_t lo = a < c ? a : c, hi_lo = a < c ? c : a, lo_hi = b < d ? b : d;
+  return (hi_lo < lo_hi ? hi_lo : lo_hi) - lo;
+}
 
 #ifdef __HIPCC__
 // Syndrome s of a start launch: its L, input bytes, start block and caller index.
@@ -308,8 +325,16 @@ hipError_t cnn_adam(int64_t n, float* prm, const float* g, float* m, float* v, f
                     float b2, float eps, float c1, float c2, hipStream_t s);
 // route, argmax class, confidences [B][3] (or nullptr) and, when flip is
 // not nullptr, the class to compose with the start decision (class route)
+// The start-weight gap route of the gate (table == nullptr: off): weights
+// [B][4] class start weights, p [B] fp32 rates, table [MCMC_GAP_BINS].
+struct GapRoute {
+  const int32_t* weights = nullptr;
+  const float* p = nullptr;
+  const uint8_t* table = nullptr;
+};
 hipError_t cnn_gate(int64_t B, const float* logits, float thr, bool class_route, uint8_t* route,
-                    uint8_t* cls, float* conf, uint8_t* flip, hipStream_t s);
+                    uint8_t* cls, float* conf, uint8_t* flip, const GapRoute& gap,
+                    hipStream_t s);
 // flag[i] = route[i] == 1 && the replica margin z of the short run's decision
 // (per-chain sums sum_n, [4][K][C] per syndrome) is below thr
 hipError_t cnn_escalate_flags(int64_t n, const uint8_t* route, const int64_t* sum_n, int K, int C,

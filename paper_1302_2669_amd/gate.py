@@ -118,6 +118,26 @@ def gate(logits, threshold=0.99, class_route=False):
     return route, cls, conf
 
 
+GAP_BINS = 50
+GAP_NEVER = 255
+
+
+def fit_gap_table(p, weights, budget, max_miss, min_count=50):
+    """uint8 [GAP_BINS] host array: the start-weight gap route's thresholds
+    per rate bin (mcmc_gate_fit_gap_table), from host rates p [n], device
+    class start weights [n][4] (start_weights) and budget labels [n]."""
+    torch = _torch()
+    n = len(p)
+    h_p = np.ascontiguousarray(p, dtype=np.float64)
+    table = np.zeros(GAP_BINS, dtype=np.uint8)
+    w = weights.contiguous()
+    b = budget.to(torch.int32).contiguous()
+    _lib.check(_lib._lib().mcmc_gate_fit_gap_table(
+        int(n), h_p.ctypes.data, _ptr(w), _ptr(b), float(max_miss), int(min_count),
+        table.ctypes.data, _stream(w.device)), "mcmc_gate_fit_gap_table")
+    return table
+
+
 def init_params(L, seed, device="cuda"):
     """Initial parameters [param_count] fp32 on the device (mcmc_cnn_init:
     He-normal weights from the library's Philox stream, zero biases)."""
@@ -310,7 +330,7 @@ class GatedDecoder:
 
     def __init__(self, L, p, seed, max_batch, sweeps_short=None, sweeps_full=None, chains=4,
                  n_temps=1, burn=0, threshold=0.99, escalate=0.0, init=MCMC_INIT_MATCHING,
-                 class_route=False, device="cuda"):
+                 class_route=False, gap_table=None, device="cuda"):
         torch = _torch()
         cfg = _lib.GateConfig()
         cfg.L = int(L)
@@ -337,6 +357,22 @@ class GatedDecoder:
         _lib.check(_lib._lib().mcmc_gated_workspace_size(h, ctypes.byref(b)),
                    "mcmc_gated_workspace_size")
         self.workspace = torch.empty((max(b.value, 1),), dtype=torch.uint8, device=device)
+        self.set_gap_table(gap_table)
+
+    def set_gap_table(self, table):
+        """The start-weight gap route's thresholds (uint8 [GAP_BINS]), or None
+        to switch the route off (mcmc_gated_set_gap_table)."""
+        if table is None:
+            _lib.check(_lib._lib().mcmc_gated_set_gap_table(self._h, None),
+                       "mcmc_gated_set_gap_table")
+            self.gap_table = None
+            return
+        t = np.ascontiguousarray(table, dtype=np.uint8)
+        if t.shape != (GAP_BINS,):
+            raise ValueError(f"gap table needs {GAP_BINS} entries")
+        _lib.check(_lib._lib().mcmc_gated_set_gap_table(self._h, t.ctypes.data),
+                   "mcmc_gated_set_gap_table")
+        self.gap_table = t
 
     def close(self):
         if getattr(self, "_h", None):

@@ -27,7 +27,7 @@ def test_exports_every_declared_symbol():
     assert decl == _lib.exported_symbols()
     for name in decl:
         assert hasattr(lib, name), name
-    assert lib.mcmc_abi_version() == 0x00010400
+    assert lib.mcmc_abi_version() == 0x00010500
 
 
 @pytest.mark.parametrize("L", list(range(2, 26)))
@@ -232,6 +232,30 @@ def test_gated_config_rejected_before_allocating():
         assert lib.mcmc_gated_create(ctypes.byref(cfg(**bad)), ctypes.byref(h)) == status, bad
     assert lib.mcmc_gated_create(None, ctypes.byref(h)) == -1
     assert lib.mcmc_gated_destroy(None) == 0
+
+
+def test_gap_route_entry_points_reject_before_launch():
+    lib = _lib._lib()
+    d = ctypes.c_void_p(0x1000)
+    sw = lib.mcmc_start_weights
+    assert sw(1, 2, d, 4, d, None) == -2                 # bad L
+    assert sw(13, 7, d, 4, d, None) == -1                # bad start mode
+    assert sw(13, 2, d, -1, d, None) == -2
+    assert sw(13, 2, None, 4, d, None) == -1
+    assert sw(13, 2, None, 0, None, None) == 0           # empty batch
+    fit = lib.mcmc_gate_fit_gap_table
+    table = (ctypes.c_uint8 * 50)()
+    p_ok = (ctypes.c_double * 2)(0.1, 0.2)
+    p_bad = (ctypes.c_double * 2)(0.1, 0.8)
+    assert fit(2, p_ok, d, d, 0.01, 10, None, None) == -1             # no table
+    assert fit(2, None, d, d, 0.01, 10, table, None) == -1            # no rates
+    assert fit(-1, p_ok, d, d, 0.01, 10, table, None) == -2
+    assert fit(2, p_ok, d, d, 1.5, 10, table, None) == -2             # max_miss > 1
+    assert fit(2, p_ok, d, d, 0.01, 0, table, None) == -2             # min_count < 1
+    assert fit(2, p_bad, d, d, 0.01, 10, table, None) == -2           # rate out of range
+    assert fit(0, None, None, None, 0.01, 10, table, None) == 0       # no samples: all NEVER
+    assert list(table) == [255] * 50
+    assert lib.mcmc_gated_set_gap_table(None, table) == -1
 
 
 @pytest.mark.parametrize("p,pm", [(0.05, 0.05), (0.1, 0.02), (0.15, 0.3), (0.03, 0.45)])

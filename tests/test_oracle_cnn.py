@@ -172,3 +172,62 @@ def test_relative_targets_by_enumeration():
         np.testing.assert_allclose(rel, direct, rtol=1e-12, atol=1e-15)
         assert rel[0] == prob[start]
     assert len(seen) >= 2      # some syndromes decide a class other than the identity
+
+
+def test_start_weight_gap_hand_cases():
+    w = np.array([[3, 5, 4, 9], [2, 2, 7, 7], [10, 3, 8, 8], [0, 0, 0, 0], [9, 8, 7, 6]])
+    assert cnn.start_weight_gap(w).tolist() == [1, 0, 5, 0, 1]
+
+
+def test_gap_bin_edges():
+    """floor(p * 100) in fp32, capped: bin edges of decimal rates land where
+    the fp32 product does."""
+    p = np.array([0.0, 0.009, 0.01, 0.05, 0.0999, 0.1, 0.15, 0.289, 0.49, 0.5, 0.74])
+    want = [int(np.floor(np.float32(x) * np.float32(100.0))) for x in p]
+    want = [min(k, cnn.GAP_BINS - 1) for k in want]
+    assert cnn.gap_bin(p).tolist() == want
+    assert cnn.gap_bin(p).tolist() == [0, 0, 1, 5, 9, 10, 15, 28, 49, 49, 49]
+
+
+def test_fit_gap_table_hand_case():
+    """Bin 5: gaps 0..3 twice each, labels missing at gaps 0 and 1."""
+    gaps = np.array([0, 0, 1, 1, 2, 2, 3, 3])
+    w = np.stack([np.zeros(8, int), gaps, gaps + 5, gaps + 9], axis=1)
+    p = np.full(8, 0.055)
+    budget = np.array([1, 0, 2, 0, 0, 0, 0, 0])
+    t = cnn.fit_gap_table(p, w, budget, 0.0, 2)
+    assert t[5] == 2 and (np.delete(t, 5) == cnn.GAP_NEVER).all()
+    assert cnn.fit_gap_table(p, w, budget, 0.25, 2)[5] == 0       # 2 of 8 at G = 0
+    assert cnn.fit_gap_table(p, w, budget, 0.2, 2)[5] == 1        # 1 of 6 at G = 1
+    assert cnn.fit_gap_table(p, w, budget, 0.0, 5)[5] == cnn.GAP_NEVER   # 4 < 5 left at G = 2
+    route = cnn.gap_route(np.array([0.055, 0.055, 0.3]),
+                          np.array([[0, 1, 5, 9], [0, 2, 5, 9], [0, 40, 50, 60]]), t)
+    assert route.tolist() == [False, True, False]                # bin 30 is NEVER
+
+
+def test_fit_gap_table_meets_its_definition():
+    """On random labelled samples: every fitted threshold satisfies the
+    miss bound with at least min_count samples, every smaller one does not,
+    and a NEVER bin has no qualifying threshold with enough samples."""
+    rng = np.random.default_rng(0x6A9)
+    n = 4000
+    p = rng.uniform(0.03, 0.2, n)
+    w = np.sort(rng.integers(0, 30, size=(n, 4)), axis=1)[:, rng.permutation(4)]
+    gap = cnn.start_weight_gap(w)
+    # misses likelier at small gaps and high rates
+    budget = (rng.random(n) < np.exp(-gap / 3.0) * p * 4).astype(np.int32)
+    for max_miss, min_count in ((0.0, 1), (0.01, 20), (0.05, 40)):
+        t = cnn.fit_gap_table(p, w, budget, max_miss, min_count)
+        b = cnn.gap_bin(p)
+        for k in range(cnn.GAP_BINS):
+            gk, mk = gap[b == k], budget[b == k] != 0
+
+            def ok(G):
+                sel = gk >= G
+                return sel.sum() >= min_count and mk[sel].sum() <= max_miss * sel.sum()
+
+            if t[k] == cnn.GAP_NEVER:
+                assert not any(ok(G) for G in range(cnn.GAP_NEVER))
+            else:
+                assert ok(int(t[k])) and not any(ok(G) for G in range(int(t[k])))
+        assert (t != cnn.GAP_NEVER).sum() >= 5
