@@ -78,6 +78,9 @@ def main():
     ap.add_argument("--gate-train", type=int, default=1_000_000)
     ap.add_argument("--gate-epochs", type=int, default=4)
     ap.add_argument("--gate-eval", type=int, default=100_000)
+    ap.add_argument("--gap-max-miss", type=float, default=0.003,
+                    help="gated workload: bound on the fraction of gap-routed training "
+                         "samples whose decision needs sweeps, per rate bin")
     ap.add_argument("--mixed-n", type=int, default=100000)
     ap.add_argument("--st-L", type=int, default=0,
                     help="space-time workload: code distance (default 7)")
@@ -448,6 +451,9 @@ def bench_gated(args, mc, torch, dev):
     soft, bud, _ = gate.mcmc_labels(L, syn, p_tr, ids, seed, init=init, relative=True)
     start_right = float(soft[:, 0].mean())
     label_mix = [float((bud == k).float().mean()) for k in range(3)]
+    # the start-weight gap route's thresholds, fitted on the same labels
+    gap_table = gate.fit_gap_table(p_tr, mc.start_weights(syn, L, init=init), bud,
+                                   args.gap_max_miss, 50)
     t1 = now()
     net = gate.GateNet(L, gate.init_params(L, seed, device=dev), device=dev)
     hist = gate.train(net, syn, torch.from_numpy(p_tr.astype(np.float32)).to(dev), soft, bud,
@@ -474,12 +480,17 @@ def bench_gated(args, mc, torch, dev):
         pr = out["chosen"] == cls_e
         err_plain = float((~pr).float().mean())
         points = []
-        # (threshold, escalation margin, class route)
-        for thr, esc, cr in ((0.99, 0.0, True), (0.99, 0.0, False), (0.99, 3.0, False),
-                             (0.95, 0.0, True), (0.95, 3.0, False), (0.9, 3.0, False),
-                             (0.9, 0.0, True)):
+        # (threshold, escalation margin, class route, gap route); threshold 1
+        # leaves the network no route 0 or 1: the gap route alone
+        for thr, esc, cr, gp in ((0.99, 0.0, True, False), (0.99, 0.0, False, False),
+                                 (0.99, 3.0, False, False), (0.95, 0.0, True, False),
+                                 (0.95, 3.0, False, False), (0.9, 3.0, False, False),
+                                 (0.9, 0.0, True, False), (1.0, 0.0, False, True),
+                                 (0.995, 0.0, True, True), (0.99, 0.0, True, True),
+                                 (0.99, 3.0, False, True), (0.95, 3.0, False, True)):
             g = gate.GatedDecoder(L, P, seed, max_batch=n_ev, chains=CHAINS, threshold=thr,
-                                  escalate=esc, init=init, class_route=cr)
+                                  escalate=esc, init=init, class_route=cr,
+                                  gap_table=gap_table if gp else None)
             res = g.decode(net.params, syn_e, p=p_ev, ids=ids_e, want_correction=True)
             ta = now()
             for _ in range(reps):
@@ -498,6 +509,7 @@ def bench_gated(args, mc, torch, dev):
             conf = torch.softmax(zc, dim=1).max(dim=1).values
             moved = int(((conf >= thr) & (zc.argmax(dim=1) != 0)).sum()) if cr else 0
             points.append({"threshold": thr, "escalate": esc, "class_route": cr,
+                           "gap_route": gp,
                            "class_head_other_class": moved, "syndromes_per_s": n_ev / t_g,
                            "speedup": t_plain / t_g, "work_saving": n_ev * SWEEPS / max(1, work),
                            "logical_error": err, "rel_error_change": (err - err_plain) / err_plain,
@@ -537,7 +549,8 @@ def bench_gated(args, mc, torch, dev):
     # the matched-error operating point: the fastest decoder, the plain one
     # included (the gate is switched off when it does not pay), whose logical
     # error is within 2% relative of the plain decoder's on the same syndromes
-    plain_point = {"threshold": None, "escalate": None, "class_route": None, "gate": "off",
+    plain_point = {"threshold": None, "escalate": None, "class_route": None, "gap_route": None,
+                   "gate": "off",
                    "syndromes_per_s": uni["plain_syndromes_per_s"], "speedup": 1.0,
                    "rel_error_change": 0.0}
     matched = [q for q in uni["points"] if q["rel_error_change"] <= 0.02] + [plain_point]
@@ -558,10 +571,13 @@ def bench_gated(args, mc, torch, dev):
                    "start": args.init, "train_budget_label_mix": label_mix,
                    "train_mean_p_start_decision_right": start_right,
                    "class_targets": "relative to the start decision",
-                   "escalate": "replica margin z of the short run's decision"},
+                   "escalate": "replica margin z of the short run's decision",
+                   "gap_table": {"max_miss": args.gap_max_miss, "min_count": 50,
+                                 "thresholds_by_rate_bin": [int(v) for v in gap_table]}},
         "speedup_vs_plain": head["speedup"],
         "operating_point": {"threshold": head["threshold"], "escalate": head["escalate"],
-                            "class_route": head["class_route"], "gate": head.get("gate", "on"),
+                            "class_route": head["class_route"], "gap_route": head["gap_route"],
+                            "gate": head.get("gate", "on"),
                             "rel_error_change": head["rel_error_change"],
                             "rule": "fastest decoder (plain included) within 2% relative "
                                     "logical error of plain"},
