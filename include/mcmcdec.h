@@ -653,7 +653,8 @@ int mcmc_gated_workspace_size(const mcmc_gated* gated, size_t* h_bytes);
 int mcmc_gated_plan(mcmc_gated* gated, mcmc_plan** h_plan);
 /* The gap route's table of the decoder: h_table [MCMC_GAP_BINS] (copied,
  * the call waits for the copy), or NULL to switch the route off (the
- * default).  The decoder then computes every syndrome's class starts before
+ * default).  Not while a decode of this decoder is in flight (the device
+ * copy of the table is shared by its calls).  The decoder then computes every syndrome's class starts before
  * the gate (with escalation, in a launch of their own that only counts the
  * weights, before the plan's). */
 int mcmc_gated_set_gap_table(mcmc_gated* gated, const uint8_t* h_table);
