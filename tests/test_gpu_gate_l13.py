@@ -100,6 +100,9 @@ def test_trained_gate_at_l13():
     hist = gate.train(net, syn, torch.from_numpy(p_tr.astype(np.float32)).to(DEV), soft, bud,
                       epochs=3, batch=512, lr=3e-3, seed=SEED, log=say)
     assert hist[-1] < hist[0]
+    # the start-weight gap route's table from the same labels
+    table = gate.fit_gap_table(p_tr, mc.start_weights(syn, L, init=MWPM), bud, 0.003, 50)
+    say(f"gap table {table.tolist()}")
 
     def evaluate(p_ev, tag):
         syn_e, cls_e, ids_e = gate.sample_dataset(L, p_ev, SEED + 3, id_base=1 << 30)
@@ -109,18 +112,22 @@ def test_trained_gate_at_l13():
         plan.close()
         pr = (plain == cls_e).cpu().numpy()
         res = {}
-        for class_route in (False, True):
-            g = gate.GatedDecoder(L, 0.15, SEED, max_batch=n_eval, chains=4, threshold=0.99,
-                                  init=MWPM, class_route=class_route)
+        # (class route, gap route): the network alone, with its class head,
+        # and the gap route alone (threshold 1 leaves the network no route
+        # 0 or 1)
+        for class_route, gap in ((False, False), (True, False), (False, True)):
+            g = gate.GatedDecoder(L, 0.15, SEED, max_batch=n_eval, chains=4,
+                                  threshold=1.0 if gap else 0.99, init=MWPM,
+                                  class_route=class_route, gap_table=table if gap else None)
             out = g.decode(net.params, syn_e, p=p_ev, ids=ids_e)
             g.close()
             gr = (out["chosen"] == cls_e).cpu().numpy()
             worse, better = int((pr & ~gr).sum()), int((~pr & gr).sum())
             gain = n_eval * L * L / max(1, work(out["counts"]))
-            say(f"{tag} class_route={class_route}: routes {out['counts']} work gain "
+            say(f"{tag} class_route={class_route} gap={gap}: routes {out['counts']} work gain "
                 f"{gain:.3f}; logical error plain {1 - pr.mean():.4f} gated "
                 f"{1 - gr.mean():.4f}; plain-right/gated-wrong {worse}, reverse {better}")
-            res[class_route] = (gain, worse, better, 1 - pr.mean(), 1 - gr.mean())
+            res[(class_route, gap)] = (gain, worse, better, 1 - pr.mean(), 1 - gr.mean())
         return res
 
     uni = evaluate(uniform_rates(n_eval, SEED + 4).astype(np.float64), "p uniform")
@@ -128,6 +135,11 @@ def test_trained_gate_at_l13():
         assert gain >= 1.5
         assert worse - better <= 0.003 * n_eval
         assert e_gated <= 1.02 * e_plain
+    # the gap route alone: more work saved than the network, at a smaller
+    # error cost
+    gain, worse, better, e_plain, e_gated = uni[(False, True)]
+    assert gain >= 1.8 and gain > uni[(False, False)][0]
+    assert worse - better <= 0.002 * n_eval
     fixed = evaluate(np.full(n_eval, 0.15), "p 0.15")
     for gain, worse, better, e_plain, e_gated in fixed.values():
         assert gain >= 1.0
