@@ -228,3 +228,47 @@ def test_plan_graph_with_mwpm_starts_replays():
         mc.init_representatives(flat.view(len(items), -1), L, init=MWPM)
         torch.cuda.synchronize()
     plan.close()
+
+
+def test_concurrent_decodes_on_two_streams():
+    """Two host threads decoding with the exact starts on streams of their
+    own share the library's side stream (and its lock): every output equals
+    the same decode run alone."""
+    import threading
+    L, p, n = 13, 0.18, 4096          # at p = 0.18 about 8% of syndromes take the later tiers
+    say("concurrent mwpm decodes")
+    batches = [mc.sample_errors(L, p, 0x51DE + k, n, device=DEV)[0] for k in range(2)]
+    ids = [torch.arange(k * n, (k + 1) * n, dtype=torch.int32, device=DEV) for k in range(2)]
+
+    def run(k):
+        return mc.decode_batch(batches[k], L, p, 4, 0xC0DE, chains=2, syndrome_ids=ids[k],
+                               want_correction=True, want_sums=True, init=MWPM)
+
+    alone = []
+    for k in range(2):
+        o = run(k)
+        torch.cuda.synchronize()
+        alone.append({key: v.clone() for key, v in o.items() if torch.is_tensor(v)})
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    got, errors = [None, None], []
+
+    def worker(k):
+        try:
+            with torch.cuda.stream(streams[k]):
+                for _ in range(3):
+                    o = run(k)
+                streams[k].synchronize()
+                got[k] = o
+        except Exception as e:  # noqa: BLE001 - reported below
+            errors.append(e)
+
+    threads = [threading.Thread(target=worker, args=(k,)) for k in range(2)]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join()
+    assert not errors, errors
+    torch.cuda.synchronize()
+    for k in range(2):
+        for key in ("chosen", "correction", "sum_n"):
+            assert torch.equal(got[k][key], alone[k][key]), (k, key)
