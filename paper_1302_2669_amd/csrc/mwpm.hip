@@ -167,9 +167,12 @@ __device__ __forceinline__ int max_vertices(int k) { return (k & 1) ? k + 3 : k 
 // LDS allows 7; 5 (96 VGPRs, a few spills) for the larger capacities, whose
 // LDS allows at most 5 (at 4 waves, 117 VGPRs and none, the kernel is 15%
 // slower; at 8, 64 VGPRs, the scalar spills make it 28% slower than at 7).
-template <int WPE>
+template <int WPE, int CAP>
 __global__ void __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(WPE)))
-init_mwpm_kernel(const StartArgs a, int cap, int waves, int lo, int hi) {
+init_mwpm_kernel(const StartArgs a, int cap_arg, int waves, int lo, int hi) {
+  // CAP != 0: the capacity as a compile-time constant, so that every solver
+  // array sits at a constant offset from the wave's region
+  const int cap = CAP ? CAP : cap_arg;
   extern __shared__ __align__(16) uint8_t mw_lds[];
   __shared__ int lit[2];
   const int64_t s = blockIdx.x;
@@ -281,19 +284,25 @@ Overlap* overlap_entry(bool create) {
 
 hipError_t launch_tier(const StartArgs& a, int cap, int lo, int hi, hipStream_t s) {
   const size_t lds = mwpm_lds(cap);
-  const bool fast = cap <= MWPM_FAST_CAP;
-  const void* fn = fast ? reinterpret_cast<const void*>(init_mwpm_kernel<7>)
-                        : reinterpret_cast<const void*>(init_mwpm_kernel<5>);
+  // the capacity compiled in only where the launch's is exactly that one
+  // (smaller codes have smaller single-tier capacities)
+  const bool fast = cap <= MWPM_FAST_CAP, fixed = cap == MWPM_FAST_CAP;
+  const void* fn = fixed  ? reinterpret_cast<const void*>(init_mwpm_kernel<7, MWPM_FAST_CAP>)
+                   : fast ? reinterpret_cast<const void*>(init_mwpm_kernel<7, 0>)
+                          : reinterpret_cast<const void*>(init_mwpm_kernel<5, 0>);
   if (lds > 64 * 1024) {
     const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
                                              (int)lds);
     if (e != hipSuccess) return e;
   }
-  if (fast)
-    hipLaunchKernelGGL(init_mwpm_kernel<7>, dim3((unsigned)a.n), dim3(128), lds, s, a, cap,
+  if (fixed)
+    hipLaunchKernelGGL((init_mwpm_kernel<7, MWPM_FAST_CAP>), dim3((unsigned)a.n), dim3(128), lds,
+                       s, a, cap, mwpm_waves(cap), lo, hi);
+  else if (fast)
+    hipLaunchKernelGGL((init_mwpm_kernel<7, 0>), dim3((unsigned)a.n), dim3(128), lds, s, a, cap,
                        mwpm_waves(cap), lo, hi);
   else
-    hipLaunchKernelGGL(init_mwpm_kernel<5>, dim3((unsigned)a.n), dim3(128), lds, s, a, cap,
+    hipLaunchKernelGGL((init_mwpm_kernel<5, 0>), dim3((unsigned)a.n), dim3(128), lds, s, a, cap,
                        mwpm_waves(cap), lo, hi);
   return hipGetLastError();
 }
