@@ -54,6 +54,17 @@
 #define MW_COUNT(what) ((void)0)
 #endif
 
+// A fact the compiler may rely on (the vertex count never exceeds the
+// capacity, which the caller guarantees by sizing the state for the larger
+// of a type's two problems: with a compile-time capacity of at most one
+// wave, every pass over the vertices is a single guarded step); nothing on
+// other compilers.
+#ifdef __clang__
+#define MW_ASSUME(cond) __builtin_assume(cond)
+#else
+#define MW_ASSUME(cond) ((void)0)
+#endif
+
 namespace mcmc {
 namespace mw {
 
@@ -641,6 +652,7 @@ struct Solver {
     int64_t key = INF;
     int idx = 0x7fff;
     for (int ev = 0; matched < nv && !fail; ++ev) {
+      MW_ASSUME(nv >= 0 && nv <= cap);
       if (ev > ev_max) { fail = true; break; }
       if (!rescan) {
         key = 0;
