@@ -696,8 +696,12 @@ struct Solver {
               mark[x] = (int16_t)(r == ri || r == rj);
             }
             wv.sync();
+            // A least slack to the S vertices outside a node can only rise
+            // when some of them stop being S, and then only where it was
+            // held by one of them: the others keep theirs, whatever their
+            // own label becomes.
             const int cnt = collect([&](int y) {
-              return mark[top[y]] != 0 || (bestS[y] >= 0 && mark[top[bestS[y]]] != 0);
+              return bestS[y] >= 0 && mark[top[bestS[y]]] != 0;
             });
             augment_path(i, j);
             augment_path(j, i);
